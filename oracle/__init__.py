@@ -16,6 +16,7 @@ from .hs_oracle import (  # noqa: F401
     simulate_level_pattern,
     symbolic_analysis,
     qrcp_truncated,
+    compress_fill,
     householder_complement,
     lu_nopiv,
     factor,

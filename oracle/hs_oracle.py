@@ -40,13 +40,14 @@ R2  neighbours: structural pattern of the level's starting matrix,
     already processed take part through their coarse DOFs.
 R3  order: greedy distance-2 colouring by ascending cluster index; clusters
     processed by (colour, index).
-R4  compression: truncated Householder QR with column pivoting of
-    F = [A_s,w1 ... A_s,wp] (followed by [A_w1,s^T ... A_wp,s^T] for a
-    nonsymmetric matrix), pivot = largest recomputed remaining column norm
-    (ties within a relative 1e-10 of the squared maximum go to the lowest
-    column index), stop at the first |R_jj| <= eps |R_11|; U = Q[:, :k] with
-    columns signed so that R_jj > 0, Z = U^T F.  Columns of F are ordered by
-    the processing position of the partner cluster.
+R4  compression: truncated Householder QR with column pivoting of F^T, i.e.
+    pivoting over the unknowns of s, where F = [A_s,w1 ... A_s,wp]
+    (followed by [A_w1,s^T ... A_wp,s^T] for a nonsymmetric matrix); pivot =
+    largest recomputed remaining norm, ties within a relative 1e-10 of the
+    squared maximum go to the lowest position in the current (exchanged)
+    order; stop at the first |R_jj| <= eps |R_11|; rows of R signed so that
+    R_jj > 0; U = orthonormal factor (positive diagonal) of P R_k^T, the
+    first k columns of R^T put back in the unknowns' order; Z = U^T F.
 R5  V: trailing m-k columns of the Householder Q of X = A_ss^{-1} U (LAPACK
     larfg convention); nonsymmetric: V_L from X, V_R from A_ss^{-T} U.
 R6  coarse-fill blocks use (U^T A_ss^{-1} U) Z as printed in Eq. (scaling).
@@ -271,21 +272,19 @@ def _house(x: np.ndarray) -> Tuple[np.ndarray, float, float]:
 PIVOT_TIE_RTOL = 1e-10
 
 
-def qrcp_truncated(F: np.ndarray, eps: float, fixed_rank: int = 0):
-    """Reading R4 of Eq. (lra): truncated QR with column pivoting.
-
-    Returns (k, U, Z, rdiag, piv): U (m x k) orthonormal, Z = U^T F (k x n),
-    rdiag the |R_jj| of the accepted pivots, piv their original column ids.
-    """
-    m, n = F.shape
-    R = np.array(F, dtype=np.float64, copy=True)
-    Q = np.eye(m)
+def qrcp_truncated(M: np.ndarray, eps: float, fixed_rank: int = 0):
+    """Truncated QR with column pivoting of M (rows x cols):
+    M[:, piv] = Q R.  Returns (k, R_k, rdiag, piv) with R_k the first k rows of
+    R (k x cols, columns in pivot order, rows signed so that R_jj > 0),
+    rdiag = |R_jj| of the accepted pivots and piv the full column exchange
+    order (accepted pivots first)."""
+    rows, n = M.shape
+    R = np.array(M, dtype=np.float64, copy=True)
     cols = np.arange(n)
     rdiag: List[float] = []
-    betas: List[float] = []
     r11 = 0.0
     k = 0
-    for j in range(min(m, n)):
+    for j in range(min(rows, n)):
         norms2 = np.sum(R[j:, j:] ** 2, axis=0)  # recomputed, not downdated
         mx = float(norms2.max())
         if mx == 0.0:
@@ -302,13 +301,27 @@ def qrcp_truncated(F: np.ndarray, eps: float, fixed_rank: int = 0):
         cols[[j, p]] = cols[[p, j]]
         v, tau, beta = _house(R[j:, j])
         R[j:, j:] -= tau * np.outer(v, v @ R[j:, j:])
-        Q[:, j:] -= tau * np.outer(Q[:, j:] @ v, v)
+        if beta < 0.0:
+            R[j, :] = -R[j, :]
         rdiag.append(rjj)
-        betas.append(beta)
         k = j + 1
-    U = Q[:, :k] * np.where(np.asarray(betas) < 0.0, -1.0, 1.0)[None, :] if k else np.zeros((m, 0))
-    Z = U.T @ F
-    return k, U, Z, np.asarray(rdiag), cols[:k].copy()
+    return k, np.triu(R[:k, :]), np.asarray(rdiag), cols
+
+
+def compress_fill(F: np.ndarray, eps: float, fixed_rank: int = 0):
+    """Reading R4 of Eq. (lra): F ~ U Z with U (m x k) orthonormal.
+
+    Returns (k, U, Z, rdiag, piv) with rdiag the |R_jj| of the accepted
+    pivots and piv the unknowns of s chosen as pivots."""
+    m = F.shape[0]
+    k, Rk, rdiag, cols = qrcp_truncated(F.T, eps, fixed_rank)
+    if k == 0:
+        return 0, np.zeros((m, 0)), np.zeros((0, F.shape[1])), rdiag, cols[:0].copy()
+    Mk = np.zeros((m, k))
+    Mk[cols, :] = Rk.T  # P R_k^T: row i of R_k^T belongs to unknown cols[i]
+    Q, Rq = np.linalg.qr(Mk)
+    U = Q * np.where(np.diag(Rq) < 0.0, -1.0, 1.0)[None, :]
+    return k, U, U.T @ F, rdiag, cols[:k].copy()
 
 
 def householder_complement(X: np.ndarray) -> np.ndarray:
@@ -470,7 +483,7 @@ def _low_rank_elimination(s, sym: LevelSymbolic, blocks, cur, eps, symmetric, fi
     elif eps == 0.0:
         k, U, Z = m, None, None  # exact mode (reading R8)
     else:
-        k, U, Z, rdiag, _ = qrcp_truncated(F, eps, fixed_rank)
+        k, U, Z, rdiag, _ = compress_fill(F, eps, fixed_rank)
         rec.rdiag = rdiag
     rec.k = k
     nt = A_sn.shape[1]

@@ -147,56 +147,55 @@ def test_householder_complement_matches_lapack_q():
 
 
 def test_qrcp_matches_lapack_geqp3_on_generic_matrix():
-    """On a matrix with well-separated column norms QRCP pivots, |R_jj| and
-    the Q factor are the LAPACK geqp3 ones (scipy.linalg.qr pivoting=True)."""
+    """On a matrix with well-separated column norms the pivots, |R_jj| and R
+    (up to the sign of each row) are those of LAPACK geqp3
+    (scipy.linalg.qr with pivoting=True)."""
     rng = np.random.default_rng(1)
-    m, n = 12, 30
-    F = rng.standard_normal((m, n)) * np.logspace(0, -3, n)[rng.permutation(n)]
-    k, U, Z, rdiag, piv = O.qrcp_truncated(F, 0.0)
-    Q, R, P = sla.qr(F, pivoting=True, mode="economic")
-    assert k == m
-    assert np.array_equal(piv, P[:k])
-    assert np.allclose(rdiag, np.abs(np.diag(R))[:k], rtol=1e-12)
-    sgn = np.sign(np.diag(R))[:k]
-    assert np.allclose(U, Q[:, :k] * sgn, atol=1e-12)
-    assert np.allclose(Z, U.T @ F)
+    for rows, n in [(30, 12), (12, 30)]:
+        M = rng.standard_normal((rows, n)) * np.logspace(0, -3, n)[rng.permutation(n)]
+        k, Rk, rdiag, piv = O.qrcp_truncated(M, 0.0)
+        Q, R, P = sla.qr(M, pivoting=True, mode="economic")
+        assert k == min(rows, n)
+        assert np.array_equal(piv[:k], P[:k])
+        assert np.allclose(rdiag, np.abs(np.diag(R))[:k], rtol=1e-12)
+        sgn = np.sign(np.diag(R))[:k]
+        assert np.allclose(Rk, R[:k, :] * sgn[:, None], atol=1e-12)
 
 
 @pytest.mark.parametrize("eps", [1e-1, 1e-3, 1e-6, 1e-10])
-def test_qrcp_truncation_error_bound_vs_svd(eps):
-    """Eq. (lra): ||F - U Z||_2 <= sqrt(n-k) eps |R_11| (every column left
-    after k pivots has norm <= the rejected pivot <= eps |R_11|); and by
-    Eckart-Young sigma_{k+1}(F) can be no larger (brute-force SVD)."""
+def test_compression_error_bound_vs_svd(eps):
+    """Eq. (lra) with the row-pivoted QR of F^T: every row residual left after
+    k pivots is no larger than the rejected pivot, so
+    ||F - U Z||_2 <= ||R_22||_F <= sqrt(m-k) eps |R_11|, |R_11| = largest row
+    norm of F; by Eckart-Young sigma_{k+1}(F) is no larger (brute-force SVD)."""
     rng = np.random.default_rng(2)
     m, n = 24, 60
     F = (rng.standard_normal((m, 10)) * np.logspace(0, -12, 10)) @ rng.standard_normal((10, n))
     F += 1e-14 * rng.standard_normal((m, n))
-    k, U, Z, rdiag, piv = O.qrcp_truncated(F, eps)
+    k, U, Z, rdiag, piv = O.compress_fill(F, eps)
     assert np.allclose(U.T @ U, np.eye(k), atol=1e-13)
+    assert np.allclose(Z, U.T @ F)
     err = np.linalg.norm(F - U @ Z, 2)
-    r11 = np.linalg.norm(F, axis=0).max()
-    assert err <= np.sqrt(n - k) * eps * r11 * (1 + 1e-10) + 1e-13 * r11
+    r11 = np.linalg.norm(F, axis=1).max()
+    assert abs(rdiag[0] - r11) <= 1e-14 * r11
+    assert err <= np.sqrt(m - k) * eps * r11 * (1 + 1e-10) + 1e-13 * r11
     sv = np.linalg.svd(F, compute_uv=False)
     if k < sv.size:
         assert sv[k] <= err * (1 + 1e-10) + 1e-14 * r11
-    # accepted pivots all pass the relative threshold
     assert np.all(rdiag > eps * rdiag[0])
-    # pivoted columns are reproduced: F[:, piv] = U R with R upper triangular, R_jj > 0
-    Rk = U.T @ F[:, piv]
-    assert np.allclose(np.tril(Rk, -1), 0, atol=1e-12 * r11)
-    assert np.all(np.diag(Rk) > 0)
 
 
-def test_qrcp_ties_go_to_lowest_index_and_fixed_rank():
-    F = np.zeros((4, 6))
-    F[0, 1] = 3.0
-    F[1, 4] = 3.0  # same norm as column 1: tie -> column 1 first
-    F[2, 5] = 1.0
-    k, U, Z, rdiag, piv = O.qrcp_truncated(F, 1e-3)
+def test_compression_ties_go_to_lowest_position_and_fixed_rank():
+    F = np.zeros((6, 4))
+    F[1, 0] = 3.0
+    F[4, 1] = 3.0  # same norm as row 1: tie -> row 1 first
+    F[5, 2] = 1.0
+    k, U, Z, rdiag, piv = O.compress_fill(F, 1e-3)
     assert k == 3 and list(piv) == [1, 4, 5]
-    k2, *_ = O.qrcp_truncated(F, 1e-3, fixed_rank=2)
+    assert np.allclose(U @ Z, F)
+    k2, *_ = O.compress_fill(F, 1e-3, fixed_rank=2)
     assert k2 == 2
-    k0, *_ = O.qrcp_truncated(np.zeros((3, 5)), 1e-3)
+    k0, *_ = O.compress_fill(np.zeros((3, 5)), 1e-3)
     assert k0 == 0
 
 
