@@ -59,6 +59,9 @@ R9  pivot blocks and F_ff are factored by LU without pivoting (Doolittle), the
 R10 the recursion stops at the single root cluster, factored densely.
 R11 structural fill a-b for every pair of neighbours of a processed cluster
     is recorded whatever the rank, so patterns do not depend on numbers.
+R12 fill whose largest row norm is at most 1e-12 ||A_ss||_F is rounding noise
+    of earlier Schur updates (the relative rule of Eq. lra would compress
+    noise): it is treated as zero, k = 0 (eps > 0 only).
 """
 
 from __future__ import annotations
@@ -270,6 +273,7 @@ def _house(x: np.ndarray) -> Tuple[np.ndarray, float, float]:
 
 
 PIVOT_TIE_RTOL = 1e-10
+FILL_NOISE_FLOOR = 1e-12
 
 
 def qrcp_truncated(M: np.ndarray, eps: float, fixed_rank: int = 0):
@@ -482,6 +486,8 @@ def _low_rank_elimination(s, sym: LevelSymbolic, blocks, cur, eps, symmetric, fi
         k, U, Z = 0, None, None
     elif eps == 0.0:
         k, U, Z = m, None, None  # exact mode (reading R8)
+    elif np.linalg.norm(F, axis=1).max() <= FILL_NOISE_FLOOR * np.linalg.norm(A_ss):
+        k, U, Z = 0, None, None  # reading R12: the fill is rounding noise
     else:
         k, U, Z, rdiag, _ = compress_fill(F, eps, fixed_rank)
         rec.rdiag = rdiag
