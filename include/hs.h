@@ -1,0 +1,243 @@
+/*
+ * hs.h -- C ABI of the hierarchical low-rank elimination solver for one AMD
+ * MI355X (gfx950).
+ *
+ * The method is the sparse hierarchical factorization of Chen, Pouransari,
+ * Rajamanickam, Boman and Darve, "A distributed-memory hierarchical solver for
+ * general sparse linear systems" (arXiv 1712.07297):
+ *   - Sec. 2.1: for every cluster s of unknowns, the fill blocks A_sw are
+ *     compressed to tolerance eps (Eq. lra), the sparsification operator E_s
+ *     (Eq. scaling) splits s into fine and coarse unknowns, the elimination
+ *     operator G_s (Eq. elim) eliminates the fine unknowns with a Schur
+ *     complement update of the neighbour blocks, and P_s (Eq. perm) moves the
+ *     coarse unknowns last;
+ *   - Alg. 1: all clusters of a level are processed, the coarse unknowns of
+ *     sibling clusters form the next level, recursively;
+ *   - Alg. 2: the factorization is applied by forward and backward
+ *     substitution;
+ *   - Sec. 5: it is used as a direct solver (small eps) or as a preconditioner
+ *     for CG (symmetric positive definite A) or GMRES (general A).
+ *
+ * Conventions shared by every entry point:
+ *   - Matrices are square, CSR with int64 row pointers, int32 column indices
+ *     (sorted, unique within a row, in range) and float64 values.
+ *   - Unknowns are the points of an nx*ny*nz grid, index x + nx*(y + ny*z);
+ *     the geometry is used to build the cluster tree (recursive bisection).
+ *   - Dense right-hand sides and solutions are column major, n rows, leading
+ *     dimension >= n, float64.
+ *   - Every function returns 0 on success, a negative HS_ERR_* code on error,
+ *     or a positive HS_WARN_* code when the result is usable but incomplete.
+ *     No function throws.  hs_last_error() returns a message for the calling
+ *     thread's last failure.
+ *   - "Device pointer" means memory allocated on the current HIP device;
+ *     "host pointer" means ordinary host memory.  All work is ordered on the
+ *     HIP stream passed in (NULL = the default stream); functions that return
+ *     host-visible results (ranks, iteration counts) synchronise that stream.
+ *   - The library allocates its own device memory (factor storage,
+ *     workspaces) with hipMalloc unless hs_set_allocator() installs another
+ *     allocator.  It never frees or writes caller buffers other than the
+ *     documented outputs.
+ */
+#ifndef HS_H_
+#define HS_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define HS_OK 0
+#define HS_ERR_ARG (-1)         /* null pointer, negative size, bad option */
+#define HS_ERR_PATTERN (-2)     /* unsorted / duplicate / out-of-range CSR index */
+#define HS_ERR_GEOMETRY (-3)    /* n != nx*ny*nz, or a non-grid coupling */
+#define HS_ERR_BREAKDOWN (-4)   /* zero or non-finite pivot in an unpivoted LU */
+#define HS_ERR_NOMEM (-5)       /* device allocation failed or above the cap */
+#define HS_ERR_HIP (-6)         /* a HIP runtime call failed */
+#define HS_ERR_UNSUPPORTED (-7) /* a cluster larger than the kernels support */
+#define HS_ERR_NODEVICE (-8)    /* no gfx950 device visible */
+#define HS_WARN_NOT_CONVERGED 1 /* Krylov solver hit maxit; X holds the last iterate */
+
+/* ---- inputs ----------------------------------------------------------- */
+
+/* Sparse matrix in CSR form.  All arrays are owned by the caller and only
+ * read.  on_device = 0: host pointers; 1: device pointers. */
+typedef struct hs_csr {
+    int64_t n;
+    int64_t nnz;
+    const int64_t* row_ptr; /* n + 1 entries, row_ptr[0] = 0, row_ptr[n] = nnz */
+    const int32_t* col_idx; /* nnz entries */
+    const double* val;      /* nnz entries */
+    int32_t on_device;
+} hs_csr;
+
+/* Grid of the unknowns (lexicographic, x fastest). dim = 1, 2 or 3. */
+typedef struct hs_geometry {
+    int32_t dim;
+    int32_t nx, ny, nz;
+} hs_geometry;
+
+#define HS_FP64 0  /* everything in float64 */
+#define HS_MIXED 1 /* float32 factor with float64 on the two coarsest levels */
+
+/* Options of the factorization.
+ *   eps         relative truncation tolerance of the fill compression
+ *               (Eq. lra): a pivot R_jj of the rank-revealing QR is kept while
+ *               |R_jj| > eps |R_11|.  eps = 0 selects the exact mode, in which
+ *               a cluster with fill is passed whole to the next level.
+ *   fixed_rank  if > 0, additionally cap every rank at this value (the fixed
+ *               rank K of Sec. 5.1).
+ *   leaf_size   target number of unknowns per leaf cluster (> 0).
+ *   precision   HS_FP64 or HS_MIXED.
+ *   symmetric   1: A is symmetric (one-sided compression, V_R = V_L);
+ *               0: general A (row and column fill compressed together);
+ *               -1: detect from the values. */
+typedef struct hs_opts {
+    double eps;
+    int32_t fixed_rank;
+    int32_t leaf_size;
+    int32_t precision;
+    int32_t symmetric;
+    int32_t keep_levels; /* 1: keep a host copy of every level's starting matrix
+                            (test hook, see hs_factor_level_matrix); 0: off */
+} hs_opts;
+
+/* Opaque factorization; device resident; owned by the library until hs_free. */
+typedef struct hs_factor_s* hs_factor_t;
+
+/* Summary of a factorization (host struct filled by hs_factor_info). */
+typedef struct hs_info {
+    int32_t nlevels;
+    int32_t ncolors_total;     /* colour batches over all levels */
+    int64_t n;
+    int64_t coarse_dofs[64];   /* unknowns left after each level (sum of ranks) */
+    int32_t level_clusters[64];
+    int32_t level_colors[64];
+    int32_t max_cluster;       /* largest cluster size met */
+    int32_t breakdown_level;   /* -1, or the level / cluster of a breakdown */
+    int32_t breakdown_cluster;
+    double factor_flops;       /* algorithmic flops of the factorization */
+    double apply_flops_per_rhs;/* algorithmic flops of one forward+backward solve */
+    double factor_bytes;       /* bytes of the stored factor records */
+    double symbolic_seconds;   /* host time of the symbolic analysis */
+    double numeric_seconds;    /* wall time of the numeric factorization */
+} hs_info;
+
+/* ---- entry points -------------------------------------------------------- */
+
+/* Factor A (Alg. 1 with the low-rank elimination of Sec. 2.1).
+ * A: host or device CSR (see hs_csr); geom: grid of the unknowns; opts: see
+ * hs_opts.  On success *F_out receives a new factorization that keeps its own
+ * device copy of A (for the Krylov solvers).  Synchronises the stream once per
+ * level to size the next level (ranks decide the sizes).
+ * Errors: HS_ERR_ARG, HS_ERR_PATTERN, HS_ERR_GEOMETRY, HS_ERR_BREAKDOWN (the
+ * failing level and cluster are in hs_factor_info of the partial factor,
+ * which is then freed; *F_out is set to NULL), HS_ERR_NOMEM, HS_ERR_HIP,
+ * HS_ERR_UNSUPPORTED (a cluster above the supported size). */
+int hs_factor(const hs_csr* A, const hs_geometry* geom, const hs_opts* opts, void* hip_stream,
+              hs_factor_t* F_out);
+
+/* Apply the factorization once (Alg. 2): X = A_fac^{-1} B.
+ * B, X: device pointers, n x nrhs column major with leading dimensions ldb,
+ * ldx >= n; B is not modified; X may alias B only if ldx == ldb.  Stream
+ * ordered, no synchronisation. */
+int hs_solve(hs_factor_t F, int64_t nrhs, const double* B, int64_t ldb, double* X, int64_t ldx,
+             void* hip_stream);
+
+/* Preconditioned conjugate gradients (symmetric positive definite A), one
+ * recurrence per right-hand side, x0 = 0, float64, preconditioner = the
+ * factorization (Sec. 5.1).  Iterates until ||b - A x||_2 <= tol ||b||_2 for
+ * every column or maxit iterations.  B, X device pointers as in hs_solve.
+ * iters_out (host, may be NULL): iterations taken; relres_out (host, nrhs
+ * entries, may be NULL): final true relative residual of every column.
+ * Returns HS_WARN_NOT_CONVERGED if some column missed tol. */
+int hs_pcg(hs_factor_t F, int64_t nrhs, const double* B, int64_t ldb, double* X, int64_t ldx,
+           double tol, int32_t maxit, int32_t* iters_out, double* relres_out, void* hip_stream);
+
+/* Right-preconditioned restarted GMRES(restart) with modified Gram-Schmidt,
+ * x0 = 0, float64, for general A; each column solved independently; same
+ * arguments and stopping rule as hs_pcg. */
+int hs_gmres(hs_factor_t F, int64_t nrhs, const double* B, int64_t ldb, double* X, int64_t ldx,
+             double tol, int32_t maxit, int32_t restart, int32_t* iters_out, double* relres_out,
+             void* hip_stream);
+
+/* Fill *out (host) with a summary of F. */
+int hs_factor_info(hs_factor_t F, hs_info* out);
+
+/* Copy the ranks (coarse sizes after elimination) of the clusters of one level
+ * into ranks (host, room for hs_info.level_clusters[level] entries). */
+int hs_factor_ranks(hs_factor_t F, int32_t level, int32_t* ranks);
+
+/* Copy the cluster sizes at the start of a level (host array, as above). */
+int hs_factor_sizes(hs_factor_t F, int32_t level, int32_t* sizes);
+
+/* Copy one level's starting matrix, assembled densely in cluster order, to
+ * out (host, column major, dim x dim with dim = sum of the level's sizes).
+ * Needs opts.keep_levels = 1 at hs_factor time; HS_ERR_ARG otherwise. */
+int hs_factor_level_matrix(hs_factor_t F, int32_t level, double* out, int64_t dim);
+
+/* Copy one stored operator of cluster `cluster` at `level` to out (host,
+ * column major, cap doubles available); *rows / *cols receive its shape.
+ *   which = 0: T_L' = diag(L_f^{-1}, I) [V_L U]^T A_ss^{-1}      (m x m)
+ *   which = 1: T_R' = A_ss^{-1} [V_R U] diag(U_f^{-1}, I)         (m x m)
+ *   which = 2: E_R  = L_f^{-1} V_L^T A_ss^{-1} A_sn                (f x n_tot)
+ *   which = 3: E_L  = A_ns A_ss^{-1} V_R U_f^{-1}                  (n_tot x f)
+ * (Sec. 2.1: E_s of Eq. scaling folded with G_s of Eq. elim; a cluster
+ * without fill has V = I, U empty, so T_L' = L^{-1}, T_R' = U^{-1}.)  A
+ * cluster that kept all its unknowns (k = m) has no operator: shape 0 x 0.
+ * Synchronises the device. */
+int hs_factor_record(hs_factor_t F, int32_t level, int32_t cluster, int32_t which, double* out, int64_t cap,
+                     int64_t* rows, int64_t* cols);
+
+/* ---- symbolic analysis (host only, no device needed) ------------------ */
+
+/* The integer part of the method: cluster tree by recursive bisection of the
+ * grid (Alg. 1 "Partition the graph of A"), block pattern A_B per level
+ * (Eq. quotient), distance-2 colouring and processing order (Sec. 3.4), and
+ * the fill partners w(s) of every cluster (Sec. 2.3).  A must be a host CSR. */
+typedef struct hs_symbolic_s* hs_symbolic_t;
+
+int hs_symbolic_create(const hs_csr* A_host, const hs_geometry* geom, int32_t leaf_size,
+                       hs_symbolic_t* S_out);
+/* Number of levels and of clusters / colours of one level. */
+int hs_symbolic_levels(hs_symbolic_t S, int32_t* nlevels);
+int hs_symbolic_level(hs_symbolic_t S, int32_t level, int32_t* nclusters, int32_t* ncolors,
+                      int64_t* nadj, int64_t* nfill, int64_t* npattern);
+/* Leaf (level-0 cluster) of every unknown and position inside it (n each). */
+int hs_symbolic_leaves(hs_symbolic_t S, int32_t* leaf_of_dof, int32_t* local_of_dof);
+/* Per-level arrays (host, sized from hs_symbolic_level):
+ *   colors[nclusters], order[nclusters] (processing order),
+ *   adj_ptr[nclusters+1], adj[nadj]       neighbours at the level start,
+ *   fill_ptr[nclusters+1], fill[nfill]    fill partners w(s) when s is processed,
+ *   pat_ptr[nclusters+1], pat[npattern]   block pattern after the level (A_B^2).
+ * Any pointer may be NULL. */
+int hs_symbolic_arrays(hs_symbolic_t S, int32_t level, int32_t* colors, int32_t* order,
+                       int32_t* adj_ptr, int32_t* adj, int32_t* fill_ptr, int32_t* fill,
+                       int32_t* pat_ptr, int32_t* pat);
+void hs_symbolic_free(hs_symbolic_t S);
+
+/* Release F and all its device memory.  NULL is ignored. */
+void hs_free(hs_factor_t F);
+
+/* Install the device allocator used for all library-owned memory.
+ * alloc(bytes, ctx) returns a device pointer or NULL; free(ptr, ctx).  Pass
+ * NULLs to go back to hipMalloc / hipFree.  Must not be called while a
+ * factorization exists. */
+int hs_set_allocator(void* (*alloc_fn)(size_t, void*), void (*free_fn)(void*, void*), void* ctx);
+
+/* Message describing the calling thread's last failure ("" if none). */
+const char* hs_last_error(void);
+
+/* Human-readable name of a status code. */
+const char* hs_strerror(int code);
+
+/* Library version string. */
+const char* hs_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HS_H_ */

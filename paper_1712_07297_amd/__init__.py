@@ -1,0 +1,17 @@
+"""Hierarchical low-rank elimination solver for sparse systems on one AMD
+MI355X (gfx950): HIP kernels behind the C ABI of include/hs.h, with a thin
+ctypes binding.  The factorization is the one of Chen, Pouransari,
+Rajamanickam, Boman and Darve (arXiv 1712.07297), Sec. 2 (Algs. 1 and 2),
+used as a direct solver or as a CG / GMRES preconditioner (Sec. 5)."""
+
+from ._lib import (  # noqa: F401
+    HS_FP64,
+    HS_MIXED,
+    Factor,
+    HsError,
+    Symbolic,
+    header_functions,
+    lib,
+    strerror,
+    version,
+)

@@ -1,0 +1,337 @@
+"""ctypes binding of libhs.so (include/hs.h).  Argument marshalling only: every
+step of the method runs in the HIP kernels of the library.
+
+Dense right-hand sides / solutions are torch float64 CUDA tensors of shape
+(nrhs, n) (row-major, i.e. the column-major n x nrhs layout of the C ABI) or
+(n,); the CSR matrix may be numpy arrays (host) or torch CUDA tensors.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhs.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "hs.h")
+
+HS_OK = 0
+HS_ERR_ARG = -1
+HS_ERR_PATTERN = -2
+HS_ERR_GEOMETRY = -3
+HS_ERR_BREAKDOWN = -4
+HS_ERR_NOMEM = -5
+HS_ERR_HIP = -6
+HS_ERR_UNSUPPORTED = -7
+HS_ERR_NODEVICE = -8
+HS_WARN_NOT_CONVERGED = 1
+HS_FP64 = 0
+HS_MIXED = 1
+
+
+class HsError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{msg} (code {code})")
+        self.code = code
+
+
+class hs_csr(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int64),
+        ("nnz", ctypes.c_int64),
+        ("row_ptr", ctypes.c_void_p),
+        ("col_idx", ctypes.c_void_p),
+        ("val", ctypes.c_void_p),
+        ("on_device", ctypes.c_int32),
+    ]
+
+
+class hs_geometry(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32)]
+
+
+class hs_opts(ctypes.Structure):
+    _fields_ = [
+        ("eps", ctypes.c_double),
+        ("fixed_rank", ctypes.c_int32),
+        ("leaf_size", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("symmetric", ctypes.c_int32),
+        ("keep_levels", ctypes.c_int32),
+    ]
+
+
+class hs_info(ctypes.Structure):
+    _fields_ = [
+        ("nlevels", ctypes.c_int32),
+        ("ncolors_total", ctypes.c_int32),
+        ("n", ctypes.c_int64),
+        ("coarse_dofs", ctypes.c_int64 * 64),
+        ("level_clusters", ctypes.c_int32 * 64),
+        ("level_colors", ctypes.c_int32 * 64),
+        ("max_cluster", ctypes.c_int32),
+        ("breakdown_level", ctypes.c_int32),
+        ("breakdown_cluster", ctypes.c_int32),
+        ("factor_flops", ctypes.c_double),
+        ("apply_flops_per_rhs", ctypes.c_double),
+        ("factor_bytes", ctypes.c_double),
+        ("symbolic_seconds", ctypes.c_double),
+        ("numeric_seconds", ctypes.c_double),
+    ]
+
+
+_lib = None
+
+_P = ctypes.c_void_p
+_I32 = ctypes.c_int32
+_I64 = ctypes.c_int64
+_D = ctypes.c_double
+_PI32 = ctypes.POINTER(ctypes.c_int32)
+_PD = ctypes.POINTER(ctypes.c_double)
+
+_SIGS = {
+    "hs_factor": (ctypes.c_int, [ctypes.POINTER(hs_csr), ctypes.POINTER(hs_geometry), ctypes.POINTER(hs_opts), _P, ctypes.POINTER(_P)]),
+    "hs_solve": (ctypes.c_int, [_P, _I64, _P, _I64, _P, _I64, _P]),
+    "hs_pcg": (ctypes.c_int, [_P, _I64, _P, _I64, _P, _I64, _D, _I32, _PI32, _PD, _P]),
+    "hs_gmres": (ctypes.c_int, [_P, _I64, _P, _I64, _P, _I64, _D, _I32, _I32, _PI32, _PD, _P]),
+    "hs_factor_info": (ctypes.c_int, [_P, ctypes.POINTER(hs_info)]),
+    "hs_factor_ranks": (ctypes.c_int, [_P, _I32, _PI32]),
+    "hs_factor_sizes": (ctypes.c_int, [_P, _I32, _PI32]),
+    "hs_factor_level_matrix": (ctypes.c_int, [_P, _I32, _PD, _I64]),
+    "hs_factor_record": (ctypes.c_int, [_P, _I32, _I32, _I32, _PD, _I64, ctypes.POINTER(_I64), ctypes.POINTER(_I64)]),
+    "hs_free": (None, [_P]),
+    "hs_symbolic_create": (ctypes.c_int, [ctypes.POINTER(hs_csr), ctypes.POINTER(hs_geometry), _I32, ctypes.POINTER(_P)]),
+    "hs_symbolic_levels": (ctypes.c_int, [_P, _PI32]),
+    "hs_symbolic_level": (ctypes.c_int, [_P, _I32, _PI32, _PI32, ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(_I64)]),
+    "hs_symbolic_leaves": (ctypes.c_int, [_P, _PI32, _PI32]),
+    "hs_symbolic_arrays": (ctypes.c_int, [_P, _I32, _PI32, _PI32, _PI32, _PI32, _PI32, _PI32, _PI32, _PI32]),
+    "hs_symbolic_free": (None, [_P]),
+    "hs_set_allocator": (ctypes.c_int, [_P, _P, _P]),
+    "hs_last_error": (ctypes.c_char_p, []),
+    "hs_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "hs_version": (ctypes.c_char_p, []),
+}
+
+
+def header_functions() -> list:
+    """Names of the functions declared in include/hs.h."""
+    with open(HEADER) as f:
+        txt = f.read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(hs_[a-z_0-9]+)\s*\(", txt)))
+
+
+def lib() -> ctypes.CDLL:
+    """Load libhs.so (built by paper_1712_07297_amd.build); raises if absent."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1712_07297_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(code: int, what: str) -> int:
+    if code < 0:
+        msg = lib().hs_last_error().decode()
+        raise HsError(code, f"{what}: {lib().hs_strerror(code).decode()}: {msg}")
+    return code
+
+
+def _ptr(x) -> int:
+    if x is None:
+        return 0
+    if isinstance(x, np.ndarray):
+        return x.ctypes.data
+    return x.data_ptr()  # torch tensor
+
+
+def _csr_struct(row_ptr, col_idx, val, keep: list) -> hs_csr:
+    """Host numpy arrays or torch CUDA tensors."""
+    on_dev = not isinstance(row_ptr, np.ndarray)
+    if not on_dev:
+        row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
+        col_idx = np.ascontiguousarray(col_idx, dtype=np.int32)
+        val = np.ascontiguousarray(val, dtype=np.float64)
+    else:
+        import torch
+
+        assert row_ptr.dtype == torch.int64 and col_idx.dtype == torch.int32 and val.dtype == torch.float64
+        row_ptr, col_idx, val = row_ptr.contiguous(), col_idx.contiguous(), val.contiguous()
+    keep += [row_ptr, col_idx, val]
+    n = int(row_ptr.shape[0]) - 1
+    nnz = int(col_idx.shape[0])
+    return hs_csr(n, nnz, _ptr(row_ptr), _ptr(col_idx), _ptr(val), 1 if on_dev else 0)
+
+
+def _stream(stream) -> int:
+    if stream is not None:
+        return int(stream)
+    import torch
+
+    return int(torch.cuda.current_stream().cuda_stream)
+
+
+def _geom(dims: Sequence[int]) -> hs_geometry:
+    nx, ny, nz = (list(dims) + [1, 1])[:3]
+    dim = 3 if nz > 1 else (2 if ny > 1 else 1)
+    return hs_geometry(dim, int(nx), int(ny), int(nz))
+
+
+def _rhs(B):
+    """(nrhs, n) or (n,) CUDA float64 tensor -> (tensor (nrhs, n), nrhs, ld, squeeze)."""
+    import torch
+
+    if not isinstance(B, torch.Tensor) or not B.is_cuda or B.dtype != torch.float64:
+        raise TypeError("right-hand sides must be CUDA float64 torch tensors")
+    sq = B.dim() == 1
+    B2 = B.reshape(1, -1) if sq else B
+    if B2.stride(1) != 1:
+        B2 = B2.contiguous()
+    return B2, B2.shape[0], B2.stride(0), sq
+
+
+class Factor:
+    """A device-resident factorization (hs_factor)."""
+
+    def __init__(self, row_ptr, col_idx, val, dims, eps: float, leaf: int = 64, symmetric: int = -1,
+                 precision: int = HS_FP64, fixed_rank: int = 0, keep_levels: bool = False, stream=None):
+        keep: list = []
+        A = _csr_struct(row_ptr, col_idx, val, keep)
+        self.n = A.n
+        opts = hs_opts(float(eps), int(fixed_rank), int(leaf), int(precision), int(symmetric), 1 if keep_levels else 0)
+        geom = _geom(dims)
+        h = _P()
+        _check(lib().hs_factor(ctypes.byref(A), ctypes.byref(geom), ctypes.byref(opts), _stream(stream), ctypes.byref(h)), "hs_factor")
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.hs_free(h)
+            self._h = None
+
+    def free(self):
+        self.__del__()
+
+    def solve(self, B, X=None, stream=None):
+        import torch
+
+        B2, nrhs, ldb, sq = _rhs(B)
+        if X is None:
+            X = torch.empty_like(B2)
+        _check(lib().hs_solve(self._h, nrhs, _ptr(B2), ldb, _ptr(X), X.stride(0), _stream(stream)), "hs_solve")
+        return X.reshape(-1) if sq else X
+
+    def pcg(self, B, tol: float = 1e-10, maxit: int = 500, X=None, stream=None):
+        import torch
+
+        B2, nrhs, ldb, sq = _rhs(B)
+        if X is None:
+            X = torch.empty_like(B2)
+        it = _I32(0)
+        rel = (ctypes.c_double * nrhs)()
+        rc = _check(lib().hs_pcg(self._h, nrhs, _ptr(B2), ldb, _ptr(X), X.stride(0), float(tol), int(maxit), ctypes.byref(it), rel, _stream(stream)), "hs_pcg")
+        return (X.reshape(-1) if sq else X), int(it.value), np.array(rel[:]), rc == HS_OK
+
+    def gmres(self, B, tol: float = 1e-10, maxit: int = 500, restart: int = 30, X=None, stream=None):
+        import torch
+
+        B2, nrhs, ldb, sq = _rhs(B)
+        if X is None:
+            X = torch.empty_like(B2)
+        it = _I32(0)
+        rel = (ctypes.c_double * nrhs)()
+        rc = _check(lib().hs_gmres(self._h, nrhs, _ptr(B2), ldb, _ptr(X), X.stride(0), float(tol), int(maxit), int(restart), ctypes.byref(it), rel, _stream(stream)), "hs_gmres")
+        return (X.reshape(-1) if sq else X), int(it.value), np.array(rel[:]), rc == HS_OK
+
+    def info(self) -> hs_info:
+        out = hs_info()
+        _check(lib().hs_factor_info(self._h, ctypes.byref(out)), "hs_factor_info")
+        return out
+
+    def ranks(self, level: int) -> np.ndarray:
+        nc = self.info().level_clusters[level]
+        out = np.zeros(nc, dtype=np.int32)
+        _check(lib().hs_factor_ranks(self._h, level, out.ctypes.data_as(_PI32)), "hs_factor_ranks")
+        return out
+
+    def sizes(self, level: int) -> np.ndarray:
+        nc = self.info().level_clusters[level]
+        out = np.zeros(nc, dtype=np.int32)
+        _check(lib().hs_factor_sizes(self._h, level, out.ctypes.data_as(_PI32)), "hs_factor_sizes")
+        return out
+
+    def record(self, level: int, cluster: int, which: str) -> np.ndarray:
+        """Stored operator of a cluster: 'TL', 'TR', 'ER' or 'EL'."""
+        w = {"TL": 0, "TR": 1, "ER": 2, "EL": 3}[which]
+        r, c = _I64(0), _I64(0)
+        _check(lib().hs_factor_record(self._h, level, cluster, w, None, 0, ctypes.byref(r), ctypes.byref(c)), "hs_factor_record")
+        out = np.zeros((r.value, c.value), order="F")
+        if out.size:
+            _check(lib().hs_factor_record(self._h, level, cluster, w, out.ctypes.data_as(_PD), out.size, ctypes.byref(r), ctypes.byref(c)), "hs_factor_record")
+        return out
+
+    def level_matrix(self, level: int) -> np.ndarray:
+        dim = int(self.sizes(level).sum())
+        out = np.zeros((dim, dim), order="F")
+        _check(lib().hs_factor_level_matrix(self._h, level, out.ctypes.data_as(_PD), dim), "hs_factor_level_matrix")
+        return out
+
+
+class Symbolic:
+    """The integer part of the method (host only)."""
+
+    def __init__(self, row_ptr, col_idx, dims, leaf: int):
+        keep: list = []
+        row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
+        col_idx = np.ascontiguousarray(col_idx, dtype=np.int32)
+        A = _csr_struct(row_ptr, col_idx, np.zeros(col_idx.size), keep)
+        geom = _geom(dims)
+        h = _P()
+        _check(lib().hs_symbolic_create(ctypes.byref(A), ctypes.byref(geom), int(leaf), ctypes.byref(h)), "hs_symbolic_create")
+        self._h = h
+        self.n = A.n
+        nl = _I32(0)
+        _check(lib().hs_symbolic_levels(h, ctypes.byref(nl)), "hs_symbolic_levels")
+        self.nlevels = int(nl.value)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.hs_symbolic_free(h)
+            self._h = None
+
+    def leaves(self) -> Tuple[np.ndarray, np.ndarray]:
+        a = np.zeros(self.n, dtype=np.int32)
+        b = np.zeros(self.n, dtype=np.int32)
+        _check(lib().hs_symbolic_leaves(self._h, a.ctypes.data_as(_PI32), b.ctypes.data_as(_PI32)), "hs_symbolic_leaves")
+        return a, b
+
+    def level(self, level: int) -> dict:
+        ncl, nco = _I32(0), _I32(0)
+        nadj, nfill, npat = _I64(0), _I64(0), _I64(0)
+        _check(lib().hs_symbolic_level(self._h, level, ctypes.byref(ncl), ctypes.byref(nco), ctypes.byref(nadj), ctypes.byref(nfill), ctypes.byref(npat)), "hs_symbolic_level")
+        c = int(ncl.value)
+        arr = {k: np.zeros(sz, dtype=np.int32) for k, sz in [("colors", c), ("order", c), ("adj_ptr", c + 1), ("adj", nadj.value), ("fill_ptr", c + 1), ("fill", nfill.value), ("pat_ptr", c + 1), ("pat", npat.value)]}
+        _check(lib().hs_symbolic_arrays(self._h, level, *[arr[k].ctypes.data_as(_PI32) for k in ["colors", "order", "adj_ptr", "adj", "fill_ptr", "fill", "pat_ptr", "pat"]]), "hs_symbolic_arrays")
+        arr["ncolors"] = int(nco.value)
+        arr["nclusters"] = c
+        return arr
+
+
+def strerror(code: int) -> str:
+    return lib().hs_strerror(code).decode()
+
+
+def version() -> str:
+    return lib().hs_version().decode()

@@ -1,0 +1,646 @@
+// Factorization kernels: one level of the hierarchical solver, one colour at a
+// time (clusters of one colour are more than two apart in A_B, Sec. 2.3, so
+// every kernel below runs all of them at once without write conflicts).
+//
+// Per cluster s with m unknowns, k coarse unknowns and f = m - k fine ones:
+//   gram      G = F F^T, F = [A_s,w ...] (+ [A_w,s^T ...] when A is
+//             nonsymmetric): the fill blocks of s (Eq. lra), partial sums over
+//             slices of the fill partners;
+//   pivot     LU of A_ss with explicit L^{-1}, U^{-1}, A_ss^{-1}; the
+//             row-pivoted truncated QR of F^T computed as a pivoted Cholesky
+//             of G; U; V_L (V_R) = complement of A_ss^{-1} U (A_ss^{-T} U);
+//             T_L = [V_L U]^T A_ss^{-1}, T_R = A_ss^{-1} [V_R U] (the two
+//             halves of E_s, Eq. scaling); F_ff = V_L^T A_ss^{-1} V_R = L_f U_f
+//             (Eq. elim); folded operators T_L' = diag(L_f^{-1}, I) T_L,
+//             T_R' = T_R diag(U_f^{-1}, I); C = U^T A_ss^{-1} U;
+//   fill      coarse fill blocks C Z (Eq. scaling), Z = U^T F;
+//   nbr       [E_R; B_cn] = T_L' A_sn and [E_L, B_nc] = A_ns T_R';
+//   schur     A_ab -= E_L[a] E_R[b] for every ordered neighbour pair (Eq. elim).
+// A cluster without fill keeps E_s = I (Sec. 2.2): T_L' = L^{-1}, T_R' = U^{-1}.
+// Blocks of a processed cluster keep its coarse rows / columns first.
+#include "device_common.h"
+#include "kernels.h"
+
+namespace hs {
+
+__device__ inline int find_cluster(const int* pre, int n, int q) {
+    // largest ci with pre[ci] <= q (pre ascending, pre[0] = 0)
+    int lo = 0, hi = n;  // answer in [lo, hi)
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (pre[mid] <= q)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+__device__ inline int find_cluster64(const int64_t* pre, int n, int64_t q) {
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (pre[mid] <= q)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// ============================================================== Gram partials
+
+__global__ void __launch_bounds__(WG) k_gram(LevelDev L, const int* __restrict__ clist) {
+    __shared__ GemmSmem sm;
+    const int s = clist[blockIdx.y];
+    const int split = blockIdx.x;
+    const int M = L.m[s];
+    if (M == 0) return;
+    double* Gp = L.ws + L.ws_off[s] + (int64_t)(WS_GP + split) * M * M;
+    wg_zero(M, M, Gp, M);
+    __syncthreads();
+    const int f0 = L.fill_ptr[s], nf = L.fill_ptr[s + 1] - f0;
+    const int chunk = (nf + L.gram_splits - 1) / L.gram_splits;
+    const int e0 = f0 + split * chunk, e1 = min(f0 + nf, e0 + chunk);
+    for (int e = e0; e < e1; ++e) {
+        const int t = L.fill_id[e];
+        const int ct = cur_size(L, t, L.fill_before[e]);
+        if (ct == 0) continue;
+        const double* Bst = blk_ptr(L, L.fill_bst[e]);
+        wg_gemm<false, true>(M, M, ct, 1.0, Bst, M, Bst, M, 1.0, Gp, M, &sm);
+        if (!L.symmetric) {
+            const double* Bts = blk_ptr(L, L.fill_bts[e]);
+            wg_gemm<true, false>(M, M, ct, 1.0, Bts, L.m[t], Bts, L.m[t], 1.0, Gp, M, &sm);
+        }
+    }
+}
+
+void launch_gram(const LevelDev& L, const ColourDev& C, hipStream_t st) {
+    if (C.n == 0) return;
+    hipLaunchKernelGGL(k_gram, dim3(L.gram_splits, C.n), dim3(WG), 0, st, L, C.clist);
+}
+
+// ============================================================== pivot kernel
+
+// Pivoted Cholesky of the Gram matrix W (M x M, symmetric, ld M), i.e. the
+// column-pivoted QR of F^T: pivot = largest remaining diagonal, ties within a
+// relative 1e-10 go to the lowest current position, rows / columns exchanged
+// physically; stop at the first chosen pivot d_j <= eps^2 d_0 (that is
+// |R_jj| <= eps |R_11|) or at fixed_rank.  On return the first k columns of W
+// hold the factor in the exchanged order and perm[i] is the unknown at
+// position i.
+__device__ int wg_pivoted_cholesky(double* W, int M, double eps, int fixed_rank, int* perm, double* d, double* red,
+                                   int* ired) {
+    const int tid = threadIdx.x;
+    for (int i = tid; i < M; i += blockDim.x) {
+        perm[i] = i;
+        d[i] = W[i + (int64_t)i * M];
+    }
+    __syncthreads();
+    double d0 = 0.0;
+    int kk = 0;
+    for (int j = 0; j < M; ++j) {
+        double mx = -1.0;
+        for (int i = j + tid; i < M; i += blockDim.x) mx = fmax(mx, d[i]);
+        mx = block_max(mx, red);
+        if (!(mx > 0.0)) break;
+        const double thr = (1.0 - 1e-10) * mx;
+        int cand = M;
+        for (int i = j + tid; i < M; i += blockDim.x)
+            if (d[i] >= thr) {
+                cand = i;
+                break;
+            }
+        const int p = block_min_int(cand, ired);
+        const double dj = d[p];
+        if (j == 0) d0 = dj;
+        if (dj <= eps * eps * d0) break;
+        if (fixed_rank > 0 && j >= fixed_rank) break;
+        if (p != j) {
+            for (int c = tid; c < M; c += blockDim.x) {
+                double t = W[j + (int64_t)c * M];
+                W[j + (int64_t)c * M] = W[p + (int64_t)c * M];
+                W[p + (int64_t)c * M] = t;
+            }
+            __syncthreads();
+            for (int r = tid; r < M; r += blockDim.x) {
+                double t = W[r + (int64_t)j * M];
+                W[r + (int64_t)j * M] = W[r + (int64_t)p * M];
+                W[r + (int64_t)p * M] = t;
+            }
+            if (tid == 0) {
+                int ti = perm[j];
+                perm[j] = perm[p];
+                perm[p] = ti;
+                double td = d[j];
+                d[j] = d[p];
+                d[p] = td;
+            }
+            __syncthreads();
+        }
+        const double ljj = sqrt(W[j + (int64_t)j * M]);
+        const double inv = 1.0 / ljj;
+        for (int i = j + 1 + tid; i < M; i += blockDim.x) W[i + (int64_t)j * M] *= inv;
+        __syncthreads();
+        if (tid == 0) W[j + (int64_t)j * M] = ljj;
+        const int n = M - j - 1;
+        for (int64_t e = tid; e < (int64_t)n * n; e += blockDim.x) {
+            int i = j + 1 + (int)(e % n), c = j + 1 + (int)(e / n);
+            W[i + (int64_t)c * M] -= W[i + (int64_t)j * M] * W[c + (int64_t)j * M];
+        }
+        __syncthreads();
+        for (int i = j + 1 + tid; i < M; i += blockDim.x) d[i] = W[i + (int64_t)i * M];
+        kk = j + 1;
+        __syncthreads();
+    }
+    __syncthreads();
+    return kk;
+}
+
+// Householder complement: Q columns [K, M) of the QR of X (M x K) into V
+// (ld ldv).  A is an M x K scratch copy destroyed here.
+__device__ void wg_complement(double* A, int M, int K, double* V, int ldv, double* tau_sh, double* red) {
+    wg_house_qr(A, M, K, M, tau_sh, red);
+    wg_house_form_q(A, M, K, M, tau_sh, K, M - K, V, ldv);
+}
+
+__global__ void __launch_bounds__(WG) k_pivot(LevelDev L, const int* __restrict__ clist, int lds_m) {
+    extern __shared__ double dyn[];  // lds_m * lds_m doubles
+    __shared__ GemmSmem sm;
+    __shared__ double red[16];
+    __shared__ int ired[16];
+    __shared__ int flag_sh;
+    __shared__ int perm[MAX_M];
+    __shared__ double dsh[MAX_M];
+
+    const int s = clist[blockIdx.x];
+    const int tid = threadIdx.x;
+    const int M = L.m[s];
+
+    // packed offsets of the current neighbour sizes inside E_L / E_R, and the
+    // number of fill columns
+    __shared__ int fcols_sh;
+    if (tid == 0) {
+        int off = 0;
+        for (int e = L.nbr_ptr[s]; e < L.nbr_ptr[s + 1]; ++e) {
+            L.nbr_noff[e] = off;
+            off += cur_size(L, L.nbr_id[e], L.nbr_before[e]);
+        }
+        L.ntot[s] = off;
+        int fc = 0;
+        for (int e = L.fill_ptr[s]; e < L.fill_ptr[s + 1]; ++e) fc += cur_size(L, L.fill_id[e], L.fill_before[e]);
+        fcols_sh = fc;
+    }
+    __syncthreads();
+    if (M == 0) {
+        if (tid == 0) L.k[s] = 0;
+        return;
+    }
+    const int64_t MM = (int64_t)M * M;
+    double* ws = L.ws + L.ws_off[s];
+    double* Ainv = ws + WS_AINV * MM;
+    double* Linv = ws + WS_LINV * MM;
+    double* Uinv = ws + WS_UINV * MM;
+    double* Umat = ws + WS_U * MM;
+    double* X = ws + WS_X * MM;
+    double* SL = ws + WS_SL * MM;
+    double* SR = ws + WS_SR * MM;
+    double* TL = ws + WS_TL * MM;
+    double* TR = ws + WS_TR * MM;
+    double* CU = ws + WS_CU * MM;
+    double* UC = ws + WS_UC * MM;
+    double* W = (M <= lds_m) ? dyn : ws + WS_SCR * MM;
+    double* TLp = L.rec + L.rec_off[s];
+    double* TRp = TLp + MM;
+    double* Bss = blk_ptr(L, L.diag_blk[s]);
+
+    // ---- 1. A_ss = L U (no pivoting), explicit inverses
+    wg_copy(M, M, Bss, M, W, M);
+    __syncthreads();
+    double ass2 = 0.0;  // ||A_ss||_F^2 (noise floor of the fill)
+    for (int64_t e = tid; e < MM; e += blockDim.x) ass2 = fma(W[e], W[e], ass2);
+    ass2 = block_sum(ass2, red);
+    if (!wg_lu_nopiv(W, M, M, &flag_sh)) {
+        if (tid == 0) {
+            L.flag[s] = 1;
+            L.k[s] = M;  // leave the cluster untouched
+        }
+        return;
+    }
+    wg_trinv_lower_unit(W, M, M, Linv, M);
+    wg_trinv_upper(W, M, M, Uinv, M);
+    wg_gemm<false, false>(M, M, M, 1.0, Uinv, M, Linv, M, 0.0, Ainv, M, &sm);
+
+    // ---- 2. rank of the fill (Eq. lra)
+    int kk;
+    if (fcols_sh == 0) {
+        kk = 0;
+    } else if (L.eps == 0.0) {
+        kk = M;  // exact mode
+    } else {
+        // W = sum of the Gram partials
+        for (int64_t e = tid; e < MM; e += blockDim.x) {
+            double g = 0.0;
+            for (int sp = 0; sp < L.gram_splits; ++sp) g += ws[(WS_GP + sp) * MM + e];
+            W[e] = g;
+        }
+        __syncthreads();
+        // fill at the rounding level of A_ss is noise: treat it as zero
+        double dmax = 0.0;
+        for (int i = tid; i < M; i += blockDim.x) dmax = fmax(dmax, W[i + (int64_t)i * M]);
+        dmax = block_max(dmax, red);
+        if (dmax <= FILL_NOISE_FLOOR * FILL_NOISE_FLOOR * ass2)
+            kk = 0;
+        else
+            kk = wg_pivoted_cholesky(W, M, L.eps, L.fixed_rank, perm, dsh, red, ired);
+        if (kk > 0 && kk < M) {
+            // P R_k^T in the unknowns' order, then its orthonormal factor U
+            for (int64_t e = tid; e < (int64_t)M * kk; e += blockDim.x) {
+                int i = (int)(e % M), j = (int)(e / M);
+                X[perm[i] + (int64_t)j * M] = (i >= j) ? W[i + (int64_t)j * M] : 0.0;
+            }
+            __syncthreads();
+            wg_house_qr(X, M, kk, M, dsh, red);
+            wg_house_form_q(X, M, kk, M, dsh, 0, kk, Umat, M);
+            for (int j = tid; j < kk; j += blockDim.x)
+                if (X[j + (int64_t)j * M] < 0.0)
+                    for (int i = 0; i < M; ++i) Umat[i + (int64_t)j * M] = -Umat[i + (int64_t)j * M];
+            __syncthreads();
+        }
+    }
+    if (tid == 0) L.k[s] = kk;
+    if (kk == M) return;  // nothing eliminated
+    if (kk == 0) {
+        wg_copy(M, M, Linv, M, TLp, M);
+        wg_copy(M, M, Uinv, M, TRp, M);
+        return;
+    }
+    const int f = M - kk;
+
+    // ---- 3. sparsification operator E_s (Eq. scaling)
+    // X = A^{-1} U; S_L = [V_L U] with V_L the complement of X
+    wg_gemm<false, false>(M, kk, M, 1.0, Ainv, M, Umat, M, 0.0, X, M, &sm);
+    wg_complement(X, M, kk, SL, M, dsh, red);
+    wg_copy(M, kk, Umat, M, SL + (int64_t)f * M, M);
+    __syncthreads();
+    if (L.symmetric) {
+        wg_copy(M, M, SL, M, SR, M);
+    } else {
+        wg_gemm<true, false>(M, kk, M, 1.0, Ainv, M, Umat, M, 0.0, X, M, &sm);  // A^{-T} U
+        wg_complement(X, M, kk, SR, M, dsh, red);
+        wg_copy(M, kk, Umat, M, SR + (int64_t)f * M, M);
+    }
+    __syncthreads();
+    wg_gemm<true, false>(M, M, M, 1.0, SL, M, Ainv, M, 0.0, TL, M, &sm);   // T_L = S_L^T A^{-1}
+    wg_gemm<false, false>(M, M, M, 1.0, Ainv, M, SR, M, 0.0, TR, M, &sm);  // T_R = A^{-1} S_R
+
+    // ---- 4. elimination operator G_s (Eq. elim): F_ff = T_L[:f] S_R[:, :f] = L_f U_f
+    wg_gemm<false, false>(f, f, M, 1.0, TL, M, SR, M, 0.0, W, M, &sm);
+    if (!wg_lu_nopiv(W, f, M, &flag_sh)) {
+        if (tid == 0) {
+            L.flag[s] = 2;
+            L.k[s] = M;
+        }
+        return;
+    }
+    wg_trinv_lower_unit(W, f, M, Linv, M);
+    wg_trinv_upper(W, f, M, Uinv, M);
+    // T_L' = [L_f^{-1} T_L[:f, :]; T_L[f:, :]],  T_R' = [T_R[:, :f] U_f^{-1}, T_R[:, f:]]
+    wg_gemm<false, false>(f, M, f, 1.0, Linv, M, TL, M, 0.0, TLp, M, &sm);
+    wg_copy(kk, M, TL + f, M, TLp + f, M);
+    wg_gemm<false, false>(M, f, f, 1.0, TR, M, Uinv, M, 0.0, TRp, M, &sm);
+    wg_copy(M, kk, TR + (int64_t)f * M, M, TRp + (int64_t)f * M, M);
+
+    // ---- 5. coarse block C = U^T A^{-1} U = T_L[f:] S_R[:, f:] into (s, s); C U^T and U C
+    wg_gemm<false, false>(kk, kk, M, 1.0, TL + f, M, SR + (int64_t)f * M, M, 0.0, W, M, &sm);
+    wg_copy(kk, kk, W, M, Bss, M);
+    wg_gemm<false, true>(kk, M, kk, 1.0, W, M, Umat, M, 0.0, CU, M, &sm);   // C U^T (k x m)
+    wg_gemm<false, false>(M, kk, kk, 1.0, Umat, M, W, M, 0.0, UC, M, &sm);  // U C (m x k)
+}
+
+void launch_pivot(const LevelDev& L, const ColourDev& C, hipStream_t st) {
+    if (C.n == 0) return;
+    const int lds_m = C.max_m <= LDS_M ? C.max_m : 0;
+    const size_t shmem = (size_t)lds_m * lds_m * sizeof(double);
+    hipLaunchKernelGGL(k_pivot, dim3(C.n), dim3(WG), shmem, st, L, C.clist, lds_m);
+}
+
+// ============================================================ fill update
+// Coarse fill blocks (Eq. scaling): B(s^c, t) = C U^T B(s, t) and
+// B(t, s^c) = B(s, t)^T U C (symmetric) or B(t, s) U C (general); one column
+// panel of one partner block per workgroup, read before written (in place).
+int panel_width(int max_m) {
+    int pw = max_m > 0 ? 4096 / max_m : PANEL;
+    return pw < 1 ? 1 : (pw > PANEL ? PANEL : pw);
+}
+
+__global__ void __launch_bounds__(WG) k_fill_update(LevelDev L, ColourDev C, int pw) {
+    extern __shared__ double dyn[];
+    const int q = blockIdx.y;
+    const int ci = find_cluster(C.fill_pre, C.n, q);
+    const int s = C.clist[ci];
+    const int e = L.fill_ptr[s] + (q - C.fill_pre[ci]);
+    const int M = L.m[s];
+    const int kk = L.k[s];
+    if (kk == 0 || kk == M) return;
+    const int t = L.fill_id[e];
+    const int ct = cur_size(L, t, L.fill_before[e]);
+    const int c0 = blockIdx.x * pw;
+    const int w = min(pw, ct - c0);
+    if (w <= 0) return;
+    const int64_t MM = (int64_t)M * M;
+    const double* ws = L.ws + L.ws_off[s];
+    const double* CU = ws + WS_CU * MM;
+    const double* UC = ws + WS_UC * MM;
+    double* Bst = blk_ptr(L, L.fill_bst[e]);
+    double* Bts = blk_ptr(L, L.fill_bts[e]);
+    const int mt = L.m[t];
+    double* P1 = dyn;                    // M x w (ld M): B(s, t)[:, panel]
+    double* P2 = dyn + (int64_t)M * pw;  // w x M (ld pw): B(t, s)[panel, :]
+    for (int x = threadIdx.x; x < M * w; x += blockDim.x) {
+        int i = x % M, j = x / M;
+        P1[i + j * M] = Bst[i + (int64_t)(c0 + j) * M];
+    }
+    if (!L.symmetric)
+        for (int x = threadIdx.x; x < M * w; x += blockDim.x) {
+            int j = x % w, i = x / w;
+            P2[j + i * pw] = Bts[(c0 + j) + (int64_t)i * mt];
+        }
+    __syncthreads();
+    for (int x = threadIdx.x; x < kk * w; x += blockDim.x) {
+        int i = x % kk, j = x / kk;
+        double a = 0.0, b = 0.0;
+        for (int l = 0; l < M; ++l) {
+            a = fma(CU[i + (int64_t)l * M], P1[l + j * M], a);
+            const double src = L.symmetric ? P1[l + j * M] : P2[j + l * pw];
+            b = fma(src, UC[l + (int64_t)i * M], b);
+        }
+        Bst[i + (int64_t)(c0 + j) * M] = a;
+        Bts[(c0 + j) + (int64_t)i * mt] = b;
+    }
+}
+
+void launch_fill_update(const LevelDev& L, const ColourDev& C, hipStream_t st) {
+    if (C.fill_total == 0 || C.panels == 0) return;
+    const int pw = panel_width(C.max_m);
+    const size_t shmem = (size_t)2 * C.max_m * pw * sizeof(double);
+    hipLaunchKernelGGL(k_fill_update, dim3(C.panels, C.fill_total), dim3(WG), shmem, st, L, C, pw);
+}
+
+// ======================================================== neighbour update
+// [E_R; B(s^c, a)] = T_L' B(s, a) and [E_L[a], B(a, s^c)] = B(a, s) T_R',
+// one column panel of one neighbour per workgroup (in place on the blocks).
+__global__ void __launch_bounds__(WG) k_nbr_update(LevelDev L, ColourDev C, int pw) {
+    extern __shared__ double dyn[];
+    const int q = blockIdx.y;
+    const int ci = find_cluster(C.nbr_pre, C.n, q);
+    const int s = C.clist[ci];
+    const int e = L.nbr_ptr[s] + (q - C.nbr_pre[ci]);
+    const int M = L.m[s];
+    const int kk = L.k[s];
+    if (M == 0 || kk == M) return;
+    const int f = M - kk;
+    const int a = L.nbr_id[e];
+    const int ca = cur_size(L, a, L.nbr_before[e]);
+    const int c0 = blockIdx.x * pw;
+    const int w = min(pw, ca - c0);
+    if (w <= 0) return;
+    const int64_t MM = (int64_t)M * M;
+    const int ncap = L.ncap[s];
+    const double* TLp = L.rec + L.rec_off[s];
+    const double* TRp = TLp + MM;
+    double* ER = L.rec + L.rec_off[s] + 2 * MM;     // f x ntot, ld M
+    double* EL = ER + (int64_t)M * ncap;            // ntot x f, ld ncap
+    const int off = L.nbr_noff[e];
+    double* Bsa = blk_ptr(L, L.nbr_bsa[e]);
+    double* Bas = blk_ptr(L, L.nbr_bas[e]);
+    const int ma = L.m[a];
+    double* P1 = dyn;                     // M x w
+    double* P2 = dyn + (int64_t)M * pw;   // w x M (ld pw)
+    for (int x = threadIdx.x; x < M * w; x += blockDim.x) {
+        int i = x % M, j = x / M;
+        P1[i + j * M] = Bsa[i + (int64_t)(c0 + j) * M];
+    }
+    for (int x = threadIdx.x; x < M * w; x += blockDim.x) {
+        int j = x % w, i = x / w;
+        P2[j + i * pw] = Bas[(c0 + j) + (int64_t)i * ma];
+    }
+    __syncthreads();
+    for (int x = threadIdx.x; x < M * w; x += blockDim.x) {
+        int i = x % M, j = x / M;
+        double acc = 0.0;
+        for (int l = 0; l < M; ++l) acc = fma(TLp[i + (int64_t)l * M], P1[l + j * M], acc);
+        if (i < f)
+            ER[i + (int64_t)(off + c0 + j) * M] = acc;
+        else
+            Bsa[(i - f) + (int64_t)(c0 + j) * M] = acc;
+    }
+    for (int x = threadIdx.x; x < M * w; x += blockDim.x) {
+        int j = x % w, c = x / w;
+        double acc = 0.0;
+        for (int l = 0; l < M; ++l) acc = fma(P2[j + l * pw], TRp[l + (int64_t)c * M], acc);
+        if (c < f)
+            EL[(off + c0 + j) + (int64_t)c * ncap] = acc;
+        else
+            Bas[(c0 + j) + (int64_t)(c - f) * ma] = acc;
+    }
+}
+
+void launch_nbr_update(const LevelDev& L, const ColourDev& C, hipStream_t st) {
+    if (C.nbr_total == 0 || C.panels == 0) return;
+    const int pw = panel_width(C.max_m);
+    const size_t shmem = (size_t)2 * C.max_m * pw * sizeof(double);
+    hipLaunchKernelGGL(k_nbr_update, dim3(C.panels, C.nbr_total), dim3(WG), shmem, st, L, C, pw);
+}
+
+// ============================================================ Schur update
+// A_ab -= E_L[a] E_R[b] for all neighbour pairs of s, computed as the single
+// product E_L E_R (ntot x ntot, inner dimension f) in 64 x 64 tiles whose
+// epilogue scatters every entry into its block (Eq. elim).
+struct SchurSmem {
+    double a[GK][SCHUR_T + 1];
+    double b[GK][SCHUR_T + 1];
+    int rblk[SCHUR_T];   // neighbour index of every tile row (-1 = none)
+    int rloc[SCHUR_T];
+    int cblk[SCHUR_T];
+    int cloc[SCHUR_T];
+};
+
+__device__ inline void map_rows(const LevelDev& L, int s, int r0, int nt, int* nbr_of, int* loc_of) {
+    const int e0 = L.nbr_ptr[s], nb = L.nbr_ptr[s + 1] - e0;
+    for (int r = threadIdx.x; r < SCHUR_T; r += blockDim.x) {
+        const int g = r0 + r;
+        int idx = -1, loc = 0;
+        if (g < nt) {
+            // last neighbour whose packed offset is <= g
+            int lo = 0, hi = nb;
+            while (hi - lo > 1) {
+                int mid = (lo + hi) >> 1;
+                if (L.nbr_noff[e0 + mid] <= g)
+                    lo = mid;
+                else
+                    hi = mid;
+            }
+            idx = lo;
+            loc = g - L.nbr_noff[e0 + lo];
+        }
+        nbr_of[r] = idx;
+        loc_of[r] = loc;
+    }
+}
+
+__global__ void __launch_bounds__(WG) k_schur(LevelDev L, ColourDev C) {
+    __shared__ SchurSmem sm;
+    const int64_t q = blockIdx.x;
+    const int ci = find_cluster64(C.tile_pre, C.n, q);
+    const int s = C.clist[ci];
+    const int M = L.m[s];
+    const int kk = L.k[s];
+    const int f = M - kk;
+    if (M == 0 || f == 0) return;
+    const int ncap = L.ncap[s];
+    const int nt = L.ntot[s];
+    const int tpr = (ncap + SCHUR_T - 1) / SCHUR_T;
+    const int64_t t = q - C.tile_pre[ci];
+    const int r0 = (int)(t / tpr) * SCHUR_T, c0 = (int)(t % tpr) * SCHUR_T;
+    if (r0 >= nt || c0 >= nt) return;
+    const int64_t MM = (int64_t)M * M;
+    const double* ER = L.rec + L.rec_off[s] + 2 * MM;  // ld M
+    const double* EL = ER + (int64_t)M * ncap;          // ld ncap
+    map_rows(L, s, r0, nt, sm.rblk, sm.rloc);
+    map_rows(L, s, c0, nt, sm.cblk, sm.cloc);
+
+    const int tid = threadIdx.x;
+    const int tx = tid & 15, ty = tid >> 4;
+    double acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+    for (int k0 = 0; k0 < f; k0 += GK) {
+        __syncthreads();
+        for (int e = tid; e < SCHUR_T * GK; e += WG) {
+            const int rr = e % SCHUR_T, kx = e / SCHUR_T;
+            const int gk = k0 + kx;
+            sm.a[kx][rr] = (r0 + rr < nt && gk < f) ? EL[(r0 + rr) + (int64_t)gk * ncap] : 0.0;
+            const int kb = e % GK, cc = e / GK;
+            const int gkb = k0 + kb;
+            sm.b[kb][cc] = (c0 + cc < nt && gkb < f) ? ER[gkb + (int64_t)(c0 + cc) * M] : 0.0;
+        }
+        __syncthreads();
+        const int kmax = min(GK, f - k0);
+        for (int kx = 0; kx < kmax; ++kx) {
+            double av[4], bv[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) av[i] = sm.a[kx][tx + 16 * i];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) bv[j] = sm.b[kx][ty + 16 * j];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = fma(av[i], bv[j], acc[i][j]);
+        }
+    }
+    __syncthreads();
+    const int e0 = L.nbr_ptr[s], nb = L.nbr_ptr[s + 1] - e0;
+    const int64_t pb = L.pair_base[s];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int r = tx + 16 * i, c = ty + 16 * j;
+            const int bi = sm.rblk[r], bj = sm.cblk[c];
+            if (bi < 0 || bj < 0) continue;
+            const int a = L.nbr_id[e0 + bi];
+            double* Cb = blk_ptr(L, L.pair_blk[pb + (int64_t)bi * nb + bj]);
+            Cb[sm.rloc[r] + (int64_t)sm.cloc[c] * L.m[a]] -= acc[i][j];
+        }
+}
+
+void launch_schur(const LevelDev& L, const ColourDev& C, hipStream_t st) {
+    if (C.tile_total == 0) return;
+    hipLaunchKernelGGL(k_schur, dim3((unsigned)C.tile_total), dim3(WG), 0, st, L, C);
+}
+
+// ================================================================ assembly
+
+__global__ void k_assemble0(int64_t n, const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx,
+                            const double* __restrict__ val, const int* __restrict__ cluster_of,
+                            const int* __restrict__ local_of, const int* __restrict__ m,
+                            const int* __restrict__ pat_ptr, const int* __restrict__ pat,
+                            const int64_t* __restrict__ blk_off, double* __restrict__ blocks) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int ci = cluster_of[i], li = local_of[i];
+    const int lo0 = pat_ptr[ci], hi0 = pat_ptr[ci + 1];
+    for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+        const int j = col_idx[e];
+        const int cj = cluster_of[j], lj = local_of[j];
+        int lo = lo0, hi = hi0;
+        while (lo < hi) {
+            int mid = (lo + hi) >> 1;
+            if (pat[mid] < cj)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        blocks[blk_off[lo] + li + (int64_t)lj * m[ci]] = val[e];
+    }
+}
+
+void launch_assemble0(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, const double* val,
+                      const int* cluster_of, const int* local_of, const int* m, const int* pat_ptr, const int* pat,
+                      const int64_t* blk_off, double* blocks, hipStream_t st) {
+    const int bs = 256;
+    hipLaunchKernelGGL(k_assemble0, dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, st, n, row_ptr, col_idx, val,
+                       cluster_of, local_of, m, pat_ptr, pat, blk_off, blocks);
+}
+
+// Parent block (P, Q) = [[B(l_P, l_Q), B(l_P, r_Q)], [B(r_P, l_Q), B(r_P, r_Q)]]
+// of the children's coarse blocks (Alg. 1 "Extract A_c").
+__global__ void k_merge(const int* __restrict__ nb_row, const int* __restrict__ nb_col, const int* __restrict__ src4,
+                        const int* __restrict__ k_prev, const int* __restrict__ m_prev,
+                        const int64_t* __restrict__ blk_off_prev, const double* __restrict__ blocks_prev,
+                        const int* __restrict__ m_next, const int64_t* __restrict__ blk_off_next,
+                        double* __restrict__ blocks_next, int ncl_prev) {
+    const int b = blockIdx.x;
+    const int P = nb_row[b], Q = nb_col[b];
+    const int ldn = m_next[P];
+    double* dst = blocks_next + blk_off_next[b];
+    for (int h = 0; h < 4; ++h) {
+        const int src = src4[4 * b + h];
+        if (src < 0) continue;
+        const int a = 2 * P + (h >> 1), c = 2 * Q + (h & 1);
+        const int roff = (h >> 1) ? k_prev[2 * P] : 0;
+        const int coff = (h & 1) ? k_prev[2 * Q] : 0;
+        const int ka = k_prev[a], kc = k_prev[c];
+        const double* sp = blocks_prev + blk_off_prev[src];
+        const int lds = m_prev[a];
+        for (int x = threadIdx.x; x < ka * kc; x += blockDim.x) {
+            int i = x % ka, j = x / ka;
+            dst[(roff + i) + (int64_t)(coff + j) * ldn] = sp[i + (int64_t)j * lds];
+        }
+    }
+    (void)ncl_prev;
+}
+
+void launch_merge(int nblk_next, const int* nb_row, const int* nb_col, const int* src4, const int* k_prev,
+                  const int* m_prev, const int64_t* blk_off_prev, const double* blocks_prev, const int* m_next,
+                  const int64_t* blk_off_next, double* blocks_next, int ncl_prev, hipStream_t st) {
+    if (nblk_next == 0) return;
+    hipLaunchKernelGGL(k_merge, dim3(nblk_next), dim3(256), 0, st, nb_row, nb_col, src4, k_prev, m_prev, blk_off_prev,
+                       blocks_prev, m_next, blk_off_next, blocks_next, ncl_prev);
+}
+
+__global__ void k_fill_zero(double* p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0.0;
+}
+
+void launch_fill_zero(double* p, int64_t n, hipStream_t st) {
+    if (n <= 0) return;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)blocks), dim3(256), 0, st, p, n);
+}
+
+}  // namespace hs

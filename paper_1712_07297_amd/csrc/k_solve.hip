@@ -1,0 +1,341 @@
+// Solve kernels (Alg. 2) and float64 Krylov building blocks.
+//
+// Level vectors hold one segment per cluster, the segment of cluster s being
+// an m_s x nrhs column-major block at offset seg[s] * nrhs.  Forward
+// substitution applies W_s = P_s G_s E_s cluster by cluster in processing
+// order: z_s = T_L' y_s (fine unknowns first, coarse last) and every
+// neighbour's current unknowns lose E_L[a] z_s[:f].  Backward substitution
+// runs in reverse: out_s = T_R' [z_f - sum_a E_R[:, a] x_a ; x_c].  A
+// neighbour processed before s is represented by its coarse part.
+#include "device_common.h"
+#include "kernels.h"
+
+namespace hs {
+
+__device__ inline int find_pre(const int* pre, int n, int q) {
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (pre[mid] <= q)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// ---------------------------------------------------------------- forward
+
+__global__ void __launch_bounds__(WG) k_apply_fwd_t(SolveLevelDev S, ColourDev C, const double* __restrict__ y,
+                                                    double* __restrict__ z, int nrhs) {
+    extern __shared__ double ys[];
+    const int s = C.clist[blockIdx.x];
+    const int M = S.m[s];
+    if (M == 0) return;
+    const int kk = S.k[s];
+    const double* ysrc = y + S.seg[s] * nrhs;
+    double* zdst = z + S.seg[s] * nrhs;
+    const int tot = M * nrhs;
+    if (kk == M) {
+        for (int x = threadIdx.x; x < tot; x += blockDim.x) zdst[x] = ysrc[x];
+        return;
+    }
+    for (int x = threadIdx.x; x < tot; x += blockDim.x) ys[x] = ysrc[x];
+    __syncthreads();
+    const double* T = S.rec + S.rec_off[s];
+    for (int x = threadIdx.x; x < tot; x += blockDim.x) {
+        const int i = x % M, r = x / M;
+        double acc = 0.0;
+        for (int l = 0; l < M; ++l) acc = fma(T[i + (int64_t)l * M], ys[l + r * M], acc);
+        zdst[x] = acc;
+    }
+}
+
+void launch_apply_fwd_t(const SolveLevelDev& S, const ColourDev& C, const double* y, double* z, int nrhs,
+                        hipStream_t st) {
+    if (C.n == 0) return;
+    hipLaunchKernelGGL(k_apply_fwd_t, dim3(C.n), dim3(WG), (size_t)C.max_m * nrhs * sizeof(double), st, S, C, y, z,
+                       nrhs);
+}
+
+constexpr int UROWS = 64;
+
+__global__ void __launch_bounds__(WG) k_apply_fwd_u(SolveLevelDev S, ColourDev C, double* __restrict__ y,
+                                                    double* __restrict__ z, int nrhs) {
+    extern __shared__ double zf[];
+    const int q = blockIdx.y;
+    const int ci = find_pre(C.nbr_pre, C.n, q);
+    const int s = C.clist[ci];
+    const int e = S.nbr_ptr[s] + (q - C.nbr_pre[ci]);
+    const int M = S.m[s];
+    const int kk = S.k[s];
+    const int f = M - kk;
+    if (M == 0 || f == 0) return;
+    const int a = S.nbr_id[e];
+    const int before = S.nbr_before[e];
+    const int ma = S.m[a];
+    const int ca = before ? S.k[a] : ma;
+    const int r0 = blockIdx.x * UROWS;
+    if (r0 >= ca) return;
+    const int nr = min(UROWS, ca - r0);
+    const double* zs = z + S.seg[s] * nrhs;
+    for (int x = threadIdx.x; x < f * nrhs; x += blockDim.x) {
+        const int j = x % f, r = x / f;
+        zf[x] = zs[j + r * M];
+    }
+    __syncthreads();
+    const int ncap = S.ncap[s];
+    const double* EL = S.rec + S.rec_off[s] + 2 * (int64_t)M * M + (int64_t)M * ncap;  // ld ncap
+    const int off = S.nbr_noff[e];
+    double* tgt = before ? z + S.seg[a] * nrhs + (ma - ca) : y + S.seg[a] * nrhs;  // ld ma
+    for (int x = threadIdx.x; x < nr * nrhs; x += blockDim.x) {
+        const int i = x % nr, r = x / nr;
+        double acc = 0.0;
+        const double* row = EL + off + r0 + i;
+        for (int j = 0; j < f; ++j) acc = fma(row[(int64_t)j * ncap], zf[j + r * f], acc);
+        tgt[r0 + i + (int64_t)r * ma] -= acc;
+    }
+}
+
+void launch_apply_fwd_u(const SolveLevelDev& S, const ColourDev& C, double* y, double* z, int nrhs, int max_m,
+                        hipStream_t st) {
+    if (C.nbr_total == 0) return;
+    const int chunks = (C.max_nbr_m + UROWS - 1) / UROWS;
+    if (chunks == 0) return;
+    (void)max_m;
+    hipLaunchKernelGGL(k_apply_fwd_u, dim3(chunks, C.nbr_total), dim3(WG), (size_t)C.max_m * nrhs * sizeof(double), st,
+                       S, C, y, z, nrhs);
+}
+
+// --------------------------------------------------------------- backward
+
+__global__ void __launch_bounds__(WG) k_apply_bwd_acc(SolveLevelDev S, ColourDev C, const double* __restrict__ z,
+                                                      const double* __restrict__ out, double* __restrict__ part,
+                                                      const int64_t* __restrict__ part_off, int nrhs) {
+    extern __shared__ double xs[];
+    const int q = blockIdx.x;
+    const int ci = find_pre(C.nbr_pre, C.n, q);
+    const int s = C.clist[ci];
+    const int e = S.nbr_ptr[s] + (q - C.nbr_pre[ci]);
+    const int M = S.m[s];
+    const int kk = S.k[s];
+    const int f = M - kk;
+    if (M == 0 || f == 0) return;
+    const int a = S.nbr_id[e];
+    const int before = S.nbr_before[e];
+    const int ma = S.m[a];
+    const int ca = before ? S.k[a] : ma;
+    double* dst = part + part_off[q] * nrhs;  // f x nrhs
+    const double* src = before ? z + S.seg[a] * nrhs + (ma - ca) : out + S.seg[a] * nrhs;  // ld ma
+    for (int x = threadIdx.x; x < ca * nrhs; x += blockDim.x) {
+        const int i = x % ca, r = x / ca;
+        xs[x] = src[i + (int64_t)r * ma];
+    }
+    __syncthreads();
+    const double* ER = S.rec + S.rec_off[s] + 2 * (int64_t)M * M;  // ld M
+    const int off = S.nbr_noff[e];
+    for (int x = threadIdx.x; x < f * nrhs; x += blockDim.x) {
+        const int j = x % f, r = x / f;
+        double acc = 0.0;
+        for (int i = 0; i < ca; ++i) acc = fma(ER[j + (int64_t)(off + i) * M], xs[i + r * ca], acc);
+        dst[x] = acc;
+    }
+}
+
+void launch_apply_bwd_acc(const SolveLevelDev& S, const ColourDev& C, const double* z, const double* out,
+                          double* part, const int64_t* part_off, int nrhs, hipStream_t st) {
+    if (C.nbr_total == 0) return;
+    hipLaunchKernelGGL(k_apply_bwd_acc, dim3(C.nbr_total), dim3(WG), (size_t)C.max_nbr_m * nrhs * sizeof(double), st,
+                       S, C, z, out, part, part_off, nrhs);
+}
+
+__global__ void __launch_bounds__(WG) k_apply_bwd_t(SolveLevelDev S, ColourDev C, const double* __restrict__ z,
+                                                    double* __restrict__ out, const double* __restrict__ part,
+                                                    const int64_t* __restrict__ part_off, int nrhs) {
+    extern __shared__ double vs[];
+    const int ci = blockIdx.x;
+    const int s = C.clist[ci];
+    const int M = S.m[s];
+    if (M == 0) return;
+    const int kk = S.k[s];
+    const int f = M - kk;
+    const double* zs = z + S.seg[s] * nrhs;
+    double* os = out + S.seg[s] * nrhs;
+    const int tot = M * nrhs;
+    if (f == 0) {
+        for (int x = threadIdx.x; x < tot; x += blockDim.x) os[x] = zs[x];
+        return;
+    }
+    const int q0 = C.nbr_pre[ci], q1 = C.nbr_pre[ci + 1];
+    for (int x = threadIdx.x; x < tot; x += blockDim.x) {
+        const int i = x % M, r = x / M;
+        double v = zs[x];
+        if (i < f)
+            for (int q = q0; q < q1; ++q) v -= part[part_off[q] * nrhs + i + r * f];
+        vs[x] = v;
+    }
+    __syncthreads();
+    const double* T = S.rec + S.rec_off[s] + (int64_t)M * M;  // T_R'
+    for (int x = threadIdx.x; x < tot; x += blockDim.x) {
+        const int i = x % M, r = x / M;
+        double acc = 0.0;
+        for (int l = 0; l < M; ++l) acc = fma(T[i + (int64_t)l * M], vs[l + r * M], acc);
+        os[x] = acc;
+    }
+}
+
+void launch_apply_bwd_t(const SolveLevelDev& S, const ColourDev& C, const double* z, double* out,
+                        const double* part, const int64_t* part_off, int nrhs, hipStream_t st) {
+    if (C.n == 0) return;
+    hipLaunchKernelGGL(k_apply_bwd_t, dim3(C.n), dim3(WG), (size_t)C.max_m * nrhs * sizeof(double), st, S, C, z, out,
+                       part, part_off, nrhs);
+}
+
+// ---------------------------------------------------------- level transfer
+
+__global__ void k_to_coarse(SolveLevelDev S, const int64_t* __restrict__ seg_next, int ncl_next,
+                            const double* __restrict__ z, double* __restrict__ ynext, int nrhs, int from) {
+    const int P = blockIdx.x;
+    const int l = 2 * P, r = 2 * P + 1;
+    const int kl = S.k[l], kr = (r < S.ncl) ? S.k[r] : 0;
+    const int mp = kl + kr;
+    double* yp = ynext + seg_next[P] * nrhs;
+    for (int x = threadIdx.x; x < mp * nrhs; x += blockDim.x) {
+        const int i = x % mp, c = x / mp;
+        int cl = l, ii = i;
+        if (i >= kl) {
+            cl = r;
+            ii = i - kl;
+        }
+        const int mc = S.m[cl];
+        double* zc = const_cast<double*>(z) + S.seg[cl] * nrhs + (mc - S.k[cl]) + ii + (int64_t)c * mc;
+        if (from)
+            *zc = yp[x];
+        else
+            yp[x] = *zc;
+    }
+}
+
+void launch_to_coarse(const SolveLevelDev& S, const int64_t* seg_next, int ncl_next, const double* z, double* ynext,
+                      int nrhs, hipStream_t st) {
+    if (ncl_next == 0) return;
+    hipLaunchKernelGGL(k_to_coarse, dim3(ncl_next), dim3(256), 0, st, S, seg_next, ncl_next, z, ynext, nrhs, 0);
+}
+
+void launch_from_coarse(const SolveLevelDev& S, const int64_t* seg_next, int ncl_next, const double* outnext,
+                        double* z, int nrhs, hipStream_t st) {
+    if (ncl_next == 0) return;
+    hipLaunchKernelGGL(k_to_coarse, dim3(ncl_next), dim3(256), 0, st, S, seg_next, ncl_next, z,
+                       const_cast<double*>(outnext), nrhs, 1);
+}
+
+__global__ void k_scatter_gather(int64_t n, const int* __restrict__ cluster_of, const int* __restrict__ local_of,
+                                 const int64_t* __restrict__ seg, const int* __restrict__ m, double* g, int64_t ldg,
+                                 double* v, int nrhs, int to_level) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int c = cluster_of[i], li = local_of[i], mc = m[c];
+    double* base = v + seg[c] * nrhs + li;
+    for (int r = 0; r < nrhs; ++r) {
+        if (to_level)
+            base[(int64_t)r * mc] = g[i + r * ldg];
+        else
+            g[i + r * ldg] = base[(int64_t)r * mc];
+    }
+}
+
+void launch_scatter_rhs(int64_t n, const int* cluster_of, const int* local_of, const int64_t* seg, const int* m,
+                        const double* B, int64_t ldb, double* y, int nrhs, hipStream_t st) {
+    hipLaunchKernelGGL(k_scatter_gather, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, cluster_of, local_of,
+                       seg, m, const_cast<double*>(B), ldb, y, nrhs, 1);
+}
+
+void launch_gather_sol(int64_t n, const int* cluster_of, const int* local_of, const int64_t* seg, const int* m,
+                       const double* out, double* X, int64_t ldx, int nrhs, hipStream_t st) {
+    hipLaunchKernelGGL(k_scatter_gather, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, cluster_of, local_of,
+                       seg, m, X, ldx, const_cast<double*>(out), nrhs, 0);
+}
+
+// ------------------------------------------------------------------ Krylov
+
+__global__ void k_spmv(int64_t n, const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx,
+                       const double* __restrict__ val, const double* __restrict__ X, int64_t ldx,
+                       double* __restrict__ Y, int64_t ldy, int nrhs) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t e0 = row_ptr[i], e1 = row_ptr[i + 1];
+    for (int r = 0; r < nrhs; ++r) {
+        const double* x = X + r * ldx;
+        double acc = 0.0;
+        for (int64_t e = e0; e < e1; ++e) acc = fma(val[e], x[col_idx[e]], acc);
+        Y[i + r * ldy] = acc;
+    }
+}
+
+void launch_spmv(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, const double* val, const double* X,
+                 int64_t ldx, double* Y, int64_t ldy, int nrhs, hipStream_t st) {
+    hipLaunchKernelGGL(k_spmv, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, row_ptr, col_idx, val, X, ldx,
+                       Y, ldy, nrhs);
+}
+
+__global__ void k_dots_part(int64_t n, const double* __restrict__ a, int64_t lda, const double* __restrict__ b,
+                            int64_t ldb, double* __restrict__ part) {
+    __shared__ double red[16];
+    const int r = blockIdx.y;
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        acc = fma(a[i + r * lda], b[i + r * ldb], acc);
+    acc = block_sum(acc, red);
+    if (threadIdx.x == 0) part[r * gridDim.x + blockIdx.x] = acc;
+}
+
+__global__ void k_dots_final(const double* __restrict__ part, int nb, double* __restrict__ out) {
+    __shared__ double red[16];
+    const int r = blockIdx.x;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) acc += part[r * nb + i];
+    acc = block_sum(acc, red);
+    if (threadIdx.x == 0) out[r] = acc;
+}
+
+void launch_dots(int64_t n, const double* a, int64_t lda, const double* b, int64_t ldb, int nrhs, double* part,
+                 double* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_dots_part, dim3(KRYLOV_BLOCKS, nrhs), dim3(256), 0, st, n, a, lda, b, ldb, part);
+    hipLaunchKernelGGL(k_dots_final, dim3(nrhs), dim3(256), 0, st, part, KRYLOV_BLOCKS, out);
+}
+
+__global__ void k_axpby(int64_t n, const double* __restrict__ alpha, const double* __restrict__ x, int64_t ldx,
+                        const double* __restrict__ beta, double* __restrict__ y, int64_t ldy, int nrhs) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int r = 0; r < nrhs; ++r) {
+        // a zero coefficient never reads its operand (uninitialised memory may hold NaN)
+        double v = 0.0;
+        if (alpha[r] != 0.0) v = alpha[r] * x[i + r * ldx];
+        if (beta[r] != 0.0) v = fma(beta[r], y[i + r * ldy], v);
+        y[i + r * ldy] = v;
+    }
+}
+
+void launch_axpby(int64_t n, const double* alpha, const double* x, int64_t ldx, const double* beta, double* y,
+                  int64_t ldy, int nrhs, hipStream_t st) {
+    hipLaunchKernelGGL(k_axpby, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, alpha, x, ldx, beta, y, ldy,
+                       nrhs);
+}
+
+__global__ void k_xmy(int64_t n, const double* __restrict__ x, int64_t ldx, double* __restrict__ y, int64_t ldy,
+                      int nrhs, int copy) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int r = 0; r < nrhs; ++r) y[i + r * ldy] = copy ? x[i + r * ldx] : x[i + r * ldx] - y[i + r * ldy];
+}
+
+void launch_xmy(int64_t n, const double* x, int64_t ldx, double* y, int64_t ldy, int nrhs, hipStream_t st) {
+    hipLaunchKernelGGL(k_xmy, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, x, ldx, y, ldy, nrhs, 0);
+}
+
+void launch_copy(int64_t n, const double* x, int64_t ldx, double* y, int64_t ldy, int nrhs, hipStream_t st) {
+    hipLaunchKernelGGL(k_xmy, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, x, ldx, y, ldy, nrhs, 1);
+}
+
+}  // namespace hs

@@ -1,0 +1,104 @@
+// Host-side launch interface of the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "device_common.h"
+
+namespace hs {
+
+// Work lists of one colour (device pointers).  Every cluster of the colour
+// contributes its neighbour entries, fill entries and Schur output tiles; the
+// kernels find their cluster by binary search over the prefix arrays.
+struct ColourDev {
+    int n = 0;                        // clusters in the colour
+    const int* clist = nullptr;       // [n] clusters, processing order
+    const int* nbr_pre = nullptr;     // [n+1] prefix of neighbour counts
+    const int* fill_pre = nullptr;    // [n+1] prefix of fill-partner counts
+    const int64_t* tile_pre = nullptr;// [n+1] prefix of Schur output tiles (capacity)
+    int nbr_total = 0;
+    int fill_total = 0;
+    int64_t tile_total = 0;
+    int panels = 0;                   // column panels per neighbour / partner block (capacity)
+    int max_m = 0;                    // largest cluster of the colour
+    int max_nbr_m = 0;                // largest neighbour or fill partner of a cluster of the colour
+};
+
+// ---- factorization, one colour at a time
+void launch_gram(const LevelDev& L, const ColourDev& C, hipStream_t st);
+void launch_pivot(const LevelDev& L, const ColourDev& C, hipStream_t st);
+void launch_fill_update(const LevelDev& L, const ColourDev& C, hipStream_t st);
+void launch_nbr_update(const LevelDev& L, const ColourDev& C, hipStream_t st);
+// column panel width used by the fill / neighbour updates for clusters up to max_m
+int panel_width(int max_m);
+void launch_schur(const LevelDev& L, const ColourDev& C, hipStream_t st);
+
+// ---- level set-up
+// Scatter the CSR values into the level-0 block store.
+void launch_assemble0(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, const double* val,
+                      const int* cluster_of, const int* local_of, const int* m, const int* pat_ptr, const int* pat,
+                      const int64_t* blk_off, double* blocks, hipStream_t st);
+// Gather the coarse blocks of the children into the parent level.  For every
+// parent block: src[4] child block ids (-1 = absent) for (l,l),(l,r),(r,l),(r,r).
+void launch_merge(int nblk_next, const int* nb_row, const int* nb_col, const int* src4, const int* k_prev,
+                  const int* m_prev, const int64_t* blk_off_prev, const double* blocks_prev, const int* m_next,
+                  const int64_t* blk_off_next, double* blocks_next, int ncl_prev, hipStream_t st);
+void launch_fill_zero(double* p, int64_t n, hipStream_t st);
+
+// ---- solve (Alg. 2)
+struct SolveLevelDev {
+    int ncl;
+    const int* m;
+    const int* k;
+    const int* nbr_ptr;
+    const int* nbr_id;
+    const int* nbr_before;
+    const int* nbr_noff;
+    const int* ntot;
+    const int* ncap;
+    const int64_t* rec_off;
+    const double* rec;
+    const int64_t* seg;  // [ncl+1] offset of every cluster segment (units of unknowns)
+};
+// z_s = T_L' y_s for the clusters of a colour (deferred: z_s = y_s)
+void launch_apply_fwd_t(const SolveLevelDev& S, const ColourDev& C, const double* y, double* z, int nrhs,
+                        hipStream_t st);
+// neighbours: y_a (or z_a's coarse part) -= E_L[a] z_s[:f]
+void launch_apply_fwd_u(const SolveLevelDev& S, const ColourDev& C, double* y, double* z, int nrhs, int max_m,
+                        hipStream_t st);
+// part[s][i] = E_R[:, a_i] x_a (current values); part_off in units of f (times nrhs)
+void launch_apply_bwd_acc(const SolveLevelDev& S, const ColourDev& C, const double* z, const double* out,
+                          double* part, const int64_t* part_off, int nrhs, hipStream_t st);
+// out_s = T_R' [z_f - sum_i part[s][i]; z_c]
+void launch_apply_bwd_t(const SolveLevelDev& S, const ColourDev& C, const double* z, double* out,
+                        const double* part, const int64_t* part_off, int nrhs, hipStream_t st);
+// next-level y = coarse parts of z (parent = left child then right child)
+void launch_to_coarse(const SolveLevelDev& S, const int64_t* seg_next, int ncl_next, const double* z, double* ynext,
+                      int nrhs, hipStream_t st);
+// coarse parts of z = next-level out
+void launch_from_coarse(const SolveLevelDev& S, const int64_t* seg_next, int ncl_next, const double* outnext,
+                        double* z, int nrhs, hipStream_t st);
+// level-0 vector <-> global vector (cluster_of / local_of: leaf and position of every unknown)
+void launch_scatter_rhs(int64_t n, const int* cluster_of, const int* local_of, const int64_t* seg, const int* m,
+                        const double* B, int64_t ldb, double* y, int nrhs, hipStream_t st);
+void launch_gather_sol(int64_t n, const int* cluster_of, const int* local_of, const int64_t* seg, const int* m,
+                       const double* out, double* X, int64_t ldx, int nrhs, hipStream_t st);
+
+// ---- Krylov building blocks (float64, n x nrhs column major)
+void launch_spmv(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, const double* val, const double* X,
+                 int64_t ldx, double* Y, int64_t ldy, int nrhs, hipStream_t st);
+// out[j] = sum_i a[i,j] * b[i,j] for every column (deterministic two-pass); part has room for
+// nrhs * KRYLOV_BLOCKS doubles.
+constexpr int KRYLOV_BLOCKS = 256;
+void launch_dots(int64_t n, const double* a, int64_t lda, const double* b, int64_t ldb, int nrhs, double* part,
+                 double* out, hipStream_t st);
+// y[:, j] = alpha[j] * x[:, j] + beta[j] * y[:, j] (alpha / beta device arrays, may be per column)
+void launch_axpby(int64_t n, const double* alpha, const double* x, int64_t ldx, const double* beta, double* y,
+                  int64_t ldy, int nrhs, hipStream_t st);
+// y = x - y (elementwise, n x nrhs)
+void launch_xmy(int64_t n, const double* x, int64_t ldx, double* y, int64_t ldy, int nrhs, hipStream_t st);
+void launch_copy(int64_t n, const double* x, int64_t ldx, double* y, int64_t ldy, int nrhs, hipStream_t st);
+
+}  // namespace hs

@@ -1,0 +1,259 @@
+// Symbolic analysis: the cluster tree from recursive bisection of the grid
+// box (Alg. 1 "Partition the graph of A"; the recursive-bisection case of the
+// relation to LoRaSp in Sec. 2.2), the block pattern A_B of Eq. (quotient),
+// the distance-2 colouring of Sec. 3.4 that lets clusters more than two apart
+// run together (Sec. 2.3), and the structural fill of Sec. 2.3: eliminating a
+// cluster couples every pair of its neighbours, so after a level the pattern
+// is that of A_B^2, and the fill partners of a cluster are the clusters two
+// steps away that an earlier cluster has already coupled to it.
+#include "symbolic.h"
+
+#include <algorithm>
+#include <array>
+#include <cstring>
+
+#include "../../include/hs.h"
+
+namespace hs {
+
+int LevelSymbolic::block_id(int a, int b) const {
+    const int* lo = pat.data() + pat_ptr[a];
+    const int* hi = pat.data() + pat_ptr[a + 1];
+    const int* it = std::lower_bound(lo, hi, b);
+    if (it == hi || *it != b) return -1;
+    return static_cast<int>(it - pat.data());
+}
+
+namespace {
+
+struct Box {
+    std::array<int, 3> lo, hi;
+};
+
+// Greedy distance-2 colouring by ascending index; returns the colour count.
+int colour_distance2(int ncl, const std::vector<int>& ptr, const std::vector<int>& adj,
+                     std::vector<int>& color) {
+    color.assign(ncl, -1);
+    std::vector<int> mark;  // mark[c] == i  <=> colour c used near i
+    int ncolors = 0;
+    for (int i = 0; i < ncl; ++i) {
+        for (int e = ptr[i]; e < ptr[i + 1]; ++e) {
+            int j = adj[e];
+            if (color[j] >= 0) {
+                if ((int)mark.size() <= color[j]) mark.resize(color[j] + 1, -1);
+                mark[color[j]] = i;
+            }
+            for (int f = ptr[j]; f < ptr[j + 1]; ++f) {
+                int l = adj[f];
+                if (l != i && color[l] >= 0) {
+                    if ((int)mark.size() <= color[l]) mark.resize(color[l] + 1, -1);
+                    mark[color[l]] = i;
+                }
+            }
+        }
+        int c = 0;
+        while (c < (int)mark.size() && mark[c] == i) ++c;
+        color[i] = c;
+        ncolors = std::max(ncolors, c + 1);
+    }
+    return ncolors;
+}
+
+// Sorted-row set with membership test; dense bit rows for small levels.
+class Pattern {
+   public:
+    explicit Pattern(int n) : n_(n), dense_((int64_t)n * n <= (int64_t)1 << 26) {
+        if (dense_)
+            bits_.assign((size_t)n * n, 0);
+        else
+            rows_.assign(n, {});
+    }
+    bool has(int a, int b) const {
+        if (dense_) return bits_[(size_t)a * n_ + b] != 0;
+        const auto& r = rows_[a];
+        return std::binary_search(r.begin(), r.end(), b);
+    }
+    void add(int a, int b) {
+        if (dense_) {
+            bits_[(size_t)a * n_ + b] = 1;
+            return;
+        }
+        auto& r = rows_[a];
+        auto it = std::lower_bound(r.begin(), r.end(), b);
+        if (it == r.end() || *it != b) r.insert(it, b);
+    }
+    void row(int a, std::vector<int>& out) const {
+        out.clear();
+        if (dense_) {
+            const uint8_t* p = bits_.data() + (size_t)a * n_;
+            for (int b = 0; b < n_; ++b)
+                if (p[b]) out.push_back(b);
+        } else {
+            out = rows_[a];
+        }
+    }
+
+   private:
+    int n_;
+    bool dense_;
+    std::vector<uint8_t> bits_;
+    std::vector<std::vector<int>> rows_;
+};
+
+void simulate_level(LevelSymbolic& L, std::vector<int>& next_ptr, std::vector<int>& next_adj) {
+    const int ncl = L.ncl;
+    L.ncolors = colour_distance2(ncl, L.adj_ptr, L.adj, L.color);
+    L.order.resize(ncl);
+    for (int i = 0; i < ncl; ++i) L.order[i] = i;
+    std::stable_sort(L.order.begin(), L.order.end(), [&](int a, int b) { return L.color[a] < L.color[b]; });
+    L.pos.assign(ncl, 0);
+    for (int p = 0; p < ncl; ++p) L.pos[L.order[p]] = p;
+    L.color_ptr.assign(L.ncolors + 1, 0);
+    for (int i = 0; i < ncl; ++i) L.color_ptr[L.color[i] + 1]++;
+    for (int c = 0; c < L.ncolors; ++c) L.color_ptr[c + 1] += L.color_ptr[c];
+
+    Pattern P(ncl);
+    for (int a = 0; a < ncl; ++a) {
+        P.add(a, a);
+        for (int e = L.adj_ptr[a]; e < L.adj_ptr[a + 1]; ++e) P.add(a, L.adj[e]);
+    }
+    std::vector<std::vector<int>> fill(ncl);
+    std::vector<int> row;
+    std::vector<char> isnbr(ncl, 0);
+    for (int s : L.order) {
+        for (int e = L.adj_ptr[s]; e < L.adj_ptr[s + 1]; ++e) isnbr[L.adj[e]] = 1;
+        P.row(s, row);
+        for (int t : row)
+            if (t != s && !isnbr[t]) fill[s].push_back(t);
+        std::sort(fill[s].begin(), fill[s].end(), [&](int a, int b) { return L.pos[a] < L.pos[b]; });
+        for (int e = L.adj_ptr[s]; e < L.adj_ptr[s + 1]; ++e) isnbr[L.adj[e]] = 0;
+        for (int e = L.adj_ptr[s]; e < L.adj_ptr[s + 1]; ++e)
+            for (int f = L.adj_ptr[s]; f < L.adj_ptr[s + 1]; ++f) P.add(L.adj[e], L.adj[f]);
+    }
+    L.fill_ptr.assign(ncl + 1, 0);
+    L.fill.clear();
+    for (int s = 0; s < ncl; ++s) {
+        L.fill.insert(L.fill.end(), fill[s].begin(), fill[s].end());
+        L.fill_ptr[s + 1] = (int)L.fill.size();
+    }
+    L.pat_ptr.assign(ncl + 1, 0);
+    L.pat.clear();
+    for (int a = 0; a < ncl; ++a) {
+        P.row(a, row);
+        L.pat.insert(L.pat.end(), row.begin(), row.end());
+        L.pat_ptr[a + 1] = (int)L.pat.size();
+    }
+    // quotient of the final pattern over parent clusters
+    const int npar = (ncl + 1) / 2;
+    std::vector<std::vector<int>> nadj(npar);
+    for (int a = 0; a < ncl; ++a)
+        for (int e = L.pat_ptr[a]; e < L.pat_ptr[a + 1]; ++e) {
+            int pa = a / 2, pb = L.pat[e] / 2;
+            if (pa != pb) nadj[pa].push_back(pb);
+        }
+    next_ptr.assign(npar + 1, 0);
+    next_adj.clear();
+    for (int p = 0; p < npar; ++p) {
+        auto& v = nadj[p];
+        std::sort(v.begin(), v.end());
+        v.erase(std::unique(v.begin(), v.end()), v.end());
+        next_adj.insert(next_adj.end(), v.begin(), v.end());
+        next_ptr[p + 1] = (int)next_adj.size();
+    }
+}
+
+}  // namespace
+
+int build_symbolic(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, int nx, int ny, int nz, int leaf,
+                   Symbolic& S) {
+    if (n <= 0 || leaf <= 0 || nx <= 0 || ny <= 0 || nz <= 0) return HS_ERR_ARG;
+    if ((int64_t)nx * ny * nz != n) return HS_ERR_GEOMETRY;
+    S = Symbolic();
+    S.n = n;
+    int depth = 0;
+    while ((int64_t)leaf << depth < n) ++depth;
+    if (depth > 30) return HS_ERR_ARG;
+    S.depth = depth;
+    S.nlevels = depth + 1;
+
+    std::vector<Box> boxes{Box{{0, 0, 0}, {nx, ny, nz}}};
+    for (int d = 0; d < depth; ++d) {
+        std::vector<Box> nxt;
+        nxt.reserve(boxes.size() * 2);
+        for (const Box& b : boxes) {
+            int axis = 0;
+            int best = b.hi[0] - b.lo[0];
+            for (int a = 1; a < 3; ++a)
+                if (b.hi[a] - b.lo[a] > best) {
+                    best = b.hi[a] - b.lo[a];
+                    axis = a;
+                }
+            int cut = b.lo[axis] + best / 2;
+            Box l = b, r = b;
+            l.hi[axis] = cut;
+            r.lo[axis] = cut;
+            nxt.push_back(l);
+            nxt.push_back(r);
+        }
+        boxes.swap(nxt);
+    }
+    const int nleaf = (int)boxes.size();
+    S.leaf_ptr.assign(nleaf + 1, 0);
+    S.leaf_dofs.resize(n);
+    S.cluster_of.assign(n, -1);
+    S.local_of.assign(n, -1);
+    int64_t w = 0;
+    for (int c = 0; c < nleaf; ++c) {
+        const Box& b = boxes[c];
+        int loc = 0;
+        // ids x + nx*(y + ny*z) ascending: z outermost, x innermost
+        for (int z = b.lo[2]; z < b.hi[2]; ++z)
+            for (int y = b.lo[1]; y < b.hi[1]; ++y)
+                for (int x = b.lo[0]; x < b.hi[0]; ++x) {
+                    int64_t id = x + (int64_t)nx * (y + (int64_t)ny * z);
+                    S.leaf_dofs[w++] = id;
+                    S.cluster_of[id] = c;
+                    S.local_of[id] = loc++;
+                }
+        S.leaf_ptr[c + 1] = (int)w;
+    }
+
+    // level-0 block graph from the stored entries, symmetrised
+    std::vector<std::vector<int>> adj(nleaf);
+    for (int64_t i = 0; i < n; ++i) {
+        int ci = S.cluster_of[i];
+        for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+            int cj = S.cluster_of[col_idx[e]];
+            if (ci != cj) {
+                adj[ci].push_back(cj);
+                adj[cj].push_back(ci);
+            }
+        }
+    }
+    LevelSymbolic L0;
+    L0.ncl = nleaf;
+    L0.adj_ptr.assign(nleaf + 1, 0);
+    for (int c = 0; c < nleaf; ++c) {
+        auto& v = adj[c];
+        std::sort(v.begin(), v.end());
+        v.erase(std::unique(v.begin(), v.end()), v.end());
+        L0.adj.insert(L0.adj.end(), v.begin(), v.end());
+        L0.adj_ptr[c + 1] = (int)L0.adj.size();
+    }
+    S.levels.clear();
+    S.levels.push_back(std::move(L0));
+    for (int lvl = 0; lvl < S.nlevels; ++lvl) {
+        std::vector<int> nptr, nadj;
+        simulate_level(S.levels[lvl], nptr, nadj);
+        if (lvl + 1 < S.nlevels) {
+            LevelSymbolic N;
+            N.ncl = (int)nptr.size() - 1;
+            N.adj_ptr = std::move(nptr);
+            N.adj = std::move(nadj);
+            S.levels.push_back(std::move(N));
+        }
+    }
+    return HS_OK;
+}
+
+}  // namespace hs
