@@ -218,6 +218,21 @@ int hs_symbolic_arrays(hs_symbolic_t S, int32_t level, int32_t* colors, int32_t*
                        int32_t* pat_ptr, int32_t* pat);
 void hs_symbolic_free(hs_symbolic_t S);
 
+/* ---- tracing ----------------------------------------------------------- */
+
+/* Per-kernel-family timing with HIP events recorded on the stream of each
+ * call (a tracing aid; off by default).  Families: "gram", "pivot", "fill",
+ * "nbr", "schur", "merge", "apply", "spmv".  While enabled, every launch of a
+ * family is bracketed by two events; intervals are read back at the next
+ * synchronisation of the library.  hs_profile_read returns, for one family
+ * since the last reset: launches, summed seconds, and the algorithmic bytes
+ * and flops of those launches (counted from the sizes the kernels worked on:
+ * for "schur", per cluster 2 f n_tot^2 flops and 8 (2 f n_tot + 2 n_tot^2)
+ * bytes in float64).  Unknown family: HS_ERR_ARG. */
+int hs_profile_enable(int32_t enable);
+int hs_profile_reset(void);
+int hs_profile_read(const char* family, int64_t* launches, double* seconds, double* bytes, double* flops);
+
 /* Release F and all its device memory.  NULL is ignored. */
 void hs_free(hs_factor_t F);
 

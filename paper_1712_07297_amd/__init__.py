@@ -12,6 +12,9 @@ from ._lib import (  # noqa: F401
     Symbolic,
     header_functions,
     lib,
+    profile_enable,
+    profile_read,
+    profile_reset,
     strerror,
     version,
 )

@@ -111,6 +111,9 @@ _SIGS = {
     "hs_symbolic_arrays": (ctypes.c_int, [_P, _I32, _PI32, _PI32, _PI32, _PI32, _PI32, _PI32, _PI32, _PI32]),
     "hs_symbolic_free": (None, [_P]),
     "hs_set_allocator": (ctypes.c_int, [_P, _P, _P]),
+    "hs_profile_enable": (ctypes.c_int, [_I32]),
+    "hs_profile_reset": (ctypes.c_int, []),
+    "hs_profile_read": (ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(_I64), _PD, _PD, _PD]),
     "hs_last_error": (ctypes.c_char_p, []),
     "hs_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "hs_version": (ctypes.c_char_p, []),
@@ -327,6 +330,21 @@ class Symbolic:
         arr["ncolors"] = int(nco.value)
         arr["nclusters"] = c
         return arr
+
+
+def profile_enable(on: bool = True) -> None:
+    _check(lib().hs_profile_enable(1 if on else 0), "hs_profile_enable")
+
+
+def profile_reset() -> None:
+    _check(lib().hs_profile_reset(), "hs_profile_reset")
+
+
+def profile_read(family: str) -> dict:
+    n = _I64(0)
+    sec, by, fl = ctypes.c_double(0), ctypes.c_double(0), ctypes.c_double(0)
+    _check(lib().hs_profile_read(family.encode(), ctypes.byref(n), ctypes.byref(sec), ctypes.byref(by), ctypes.byref(fl)), "hs_profile_read")
+    return {"launches": int(n.value), "seconds": sec.value, "bytes": by.value, "flops": fl.value}
 
 
 def strerror(code: int) -> str:

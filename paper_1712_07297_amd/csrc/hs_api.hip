@@ -120,6 +120,70 @@ struct Blob {
     }
 };
 
+// ---------------------------------------------------------------- tracing
+
+struct ProfFamily {
+    const char* name;
+    int64_t launches = 0;
+    double seconds = 0.0, bytes = 0.0, flops = 0.0;
+};
+enum ProfId { PF_GRAM = 0, PF_PIVOT, PF_FILL, PF_NBR, PF_SCHUR, PF_MERGE, PF_APPLY, PF_SPMV, PF_COUNT };
+static ProfFamily g_prof[PF_COUNT] = {{"gram"}, {"pivot"}, {"fill"}, {"nbr"}, {"schur"}, {"merge"}, {"apply"}, {"spmv"}};
+static bool g_prof_on = false;
+struct ProfPending {
+    int fam;
+    hipEvent_t a, b;
+};
+static std::vector<ProfPending> g_prof_pending;
+static std::vector<hipEvent_t> g_prof_pool;
+
+static hipEvent_t prof_event() {
+    if (!g_prof_pool.empty()) {
+        hipEvent_t e = g_prof_pool.back();
+        g_prof_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+}
+
+// Bracket one launch: call with begin=true before, begin=false after.
+struct ProfScope {
+    int fam;
+    hipStream_t st;
+    hipEvent_t a = nullptr;
+    ProfScope(int f, hipStream_t s) : fam(f), st(s) {
+        if (g_prof_on) {
+            a = prof_event();
+            (void)hipEventRecord(a, st);
+        }
+    }
+    ~ProfScope() {
+        if (g_prof_on && a) {
+            hipEvent_t b = prof_event();
+            (void)hipEventRecord(b, st);
+            g_prof_pending.push_back({fam, a, b});
+        }
+    }
+};
+
+// Read back finished intervals (the caller has synchronised the stream).
+static void prof_flush() {
+    for (auto& p : g_prof_pending) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+            g_prof[p.fam].seconds += ms * 1e-3;
+            g_prof[p.fam].launches += 1;
+        } else {
+            (void)hipGetLastError();
+        }
+        g_prof_pool.push_back(p.a);
+        g_prof_pool.push_back(p.b);
+    }
+    g_prof_pending.clear();
+}
+
 // ------------------------------------------------------------- level state
 
 struct ColourHost {
@@ -572,9 +636,12 @@ static int factor_impl(hs_factor_s* F, const hs_csr* A, const hs_geometry* G, hi
             DevBuf mbuf;
             if (!mbuf.alloc(mb.data.size())) return fail(HS_ERR_NOMEM, "merge metadata");
             HIP_TRY(hipMemcpyAsync(mbuf.p, mb.data.data(), mb.data.size(), hipMemcpyHostToDevice, st));
-            launch_merge(LD.nblk, (const int*)(mbuf.as<char>() + o_r), (const int*)(mbuf.as<char>() + o_c),
-                         (const int*)(mbuf.as<char>() + o_s), prev->dev.k, prev->dev.m, prev->dev.blk_off,
-                         prev->dev.blocks, LD.dev.m, LD.dev.blk_off, LD.dev.blocks, prev->ncl, st);
+            {
+                ProfScope ps(PF_MERGE, st);
+                launch_merge(LD.nblk, (const int*)(mbuf.as<char>() + o_r), (const int*)(mbuf.as<char>() + o_c),
+                             (const int*)(mbuf.as<char>() + o_s), prev->dev.k, prev->dev.m, prev->dev.blk_off,
+                             prev->dev.blocks, LD.dev.m, LD.dev.blk_off, LD.dev.blocks, prev->ncl, st);
+            }
             HIP_TRY(hipStreamSynchronize(st));  // merge metadata and the children's blocks are freed below
             prev->blocks.release();
             prev->dev.blocks = nullptr;
@@ -584,11 +651,26 @@ static int factor_impl(hs_factor_s* F, const hs_csr* A, const hs_geometry* G, hi
             if (rc) return rc;
         }
         for (auto& CH : LD.colours) {
-            if (F->opts.eps > 0.0 && CH.dev.fill_total > 0) launch_gram(LD.dev, CH.dev, st);
-            launch_pivot(LD.dev, CH.dev, st);
-            launch_fill_update(LD.dev, CH.dev, st);
-            launch_nbr_update(LD.dev, CH.dev, st);
-            launch_schur(LD.dev, CH.dev, st);
+            if (F->opts.eps > 0.0 && CH.dev.fill_total > 0) {
+                ProfScope ps(PF_GRAM, st);
+                launch_gram(LD.dev, CH.dev, st);
+            }
+            {
+                ProfScope ps(PF_PIVOT, st);
+                launch_pivot(LD.dev, CH.dev, st);
+            }
+            if (CH.dev.fill_total > 0) {
+                ProfScope ps(PF_FILL, st);
+                launch_fill_update(LD.dev, CH.dev, st);
+            }
+            if (CH.dev.nbr_total > 0) {
+                ProfScope ps(PF_NBR, st);
+                launch_nbr_update(LD.dev, CH.dev, st);
+            }
+            if (CH.dev.tile_total > 0) {
+                ProfScope ps(PF_SCHUR, st);
+                launch_schur(LD.dev, CH.dev, st);
+            }
         }
         HIP_TRY(hipGetLastError());
         // ranks decide the next level's sizes: one synchronisation per level
@@ -606,6 +688,15 @@ static int factor_impl(hs_factor_s* F, const hs_csr* A, const hs_geometry* G, hi
                                                   ", cluster " + std::to_string(c) +
                                                   (flag[c] == 2 ? " (fine block)" : " (pivot block)"));
             }
+        if (g_prof_on) {
+            prof_flush();
+            for (int c = 0; c < LD.ncl; ++c) {
+                const double f = LD.m[c] - LD.k[c], nt = ntot[c];
+                if (LD.m[c] == 0 || f == 0 || nt == 0) continue;
+                g_prof[PF_SCHUR].flops += 2.0 * f * nt * nt;
+                g_prof[PF_SCHUR].bytes += 8.0 * (2.0 * f * nt + 2.0 * nt * nt);
+            }
+        }
         for (int c = 0; c < LD.ncl; ++c) {
             int wt = 0;
             for (int e = S.fill_ptr[c]; e < S.fill_ptr[c + 1]; ++e) {
@@ -681,6 +772,7 @@ static int factor_impl(hs_factor_s* F, const hs_csr* A, const hs_geometry* G, hi
         }
     }
     HIP_TRY(hipStreamSynchronize(st));
+    if (g_prof_on) prof_flush();
     F->info.factor_flops = flops;
     F->info.apply_flops_per_rhs = apply_flops;
     F->info.factor_bytes = rec_bytes;
@@ -737,6 +829,7 @@ static int solve_chunk(hs_factor_s* F, int nrhs, const double* B, int64_t ldb, d
     for (int l = 0; l < nlev; ++l) {
         LevelData& LD = F->levels[l];
         for (auto& CH : LD.colours) {
+            ProfScope ps(PF_APPLY, st);
             launch_apply_fwd_t(LD.sdev, CH.dev, Y(l), Z(l), nrhs, st);
             launch_apply_fwd_u(LD.sdev, CH.dev, Y(l), Z(l), nrhs, CH.dev.max_nbr_m, st);
         }
@@ -749,6 +842,7 @@ static int solve_chunk(hs_factor_s* F, int nrhs, const double* B, int64_t ldb, d
             launch_from_coarse(LD.sdev, F->levels[l + 1].sdev.seg, F->levels[l + 1].ncl, O(l + 1), Z(l), nrhs, st);
         for (int c = (int)LD.colours.size() - 1; c >= 0; --c) {
             auto& CH = LD.colours[c];
+            ProfScope ps(PF_APPLY, st);
             launch_apply_bwd_acc(LD.sdev, CH.dev, Z(l), O(l), part, CH.part_off, nrhs, st);
             launch_apply_bwd_t(LD.sdev, CH.dev, Z(l), O(l), part, CH.part_off, nrhs, st);
         }
@@ -776,6 +870,7 @@ static int dots_host(hs_factor_s* F, int64_t n, const double* a, int64_t lda, co
     launch_dots(n, a, lda, b, ldb, nrhs, part, dout, st);
     HIP_TRY(hipMemcpyAsync(hout, dout, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
+    if (g_prof_on) prof_flush();
     (void)F;
     return HS_OK;
 }
@@ -1187,6 +1282,33 @@ int hs_set_allocator(void* (*alloc_fn)(size_t, void*), void (*free_fn)(void*, vo
     g_free_fn = free_fn;
     g_alloc_ctx = ctx;
     return HS_OK;
+}
+
+int hs_profile_enable(int32_t enable) {
+    g_prof_on = enable != 0;
+    return HS_OK;
+}
+
+int hs_profile_reset(void) {
+    for (auto& f : g_prof) {
+        f.launches = 0;
+        f.seconds = f.bytes = f.flops = 0.0;
+    }
+    g_prof_pending.clear();
+    return HS_OK;
+}
+
+int hs_profile_read(const char* family, int64_t* launches, double* seconds, double* bytes, double* flops) {
+    if (!family) return fail(HS_ERR_ARG, "null family");
+    for (auto& f : g_prof)
+        if (std::strcmp(f.name, family) == 0) {
+            if (launches) *launches = f.launches;
+            if (seconds) *seconds = f.seconds;
+            if (bytes) *bytes = f.bytes;
+            if (flops) *flops = f.flops;
+            return HS_OK;
+        }
+    return fail(HS_ERR_ARG, std::string("unknown family ") + family);
 }
 
 const char* hs_last_error(void) { return g_err.c_str(); }

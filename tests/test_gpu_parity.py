@@ -1,0 +1,247 @@
+"""Parity of the HIP library with the CPU oracle, through the C ABI.
+
+Bars (from the method's accuracy requirements):
+  * integer work (tree, colours, ranks, sizes): bit-exact;
+  * factor entries at eps = 0 (every level's matrix, every stored operator):
+    within 1e-10 relative;
+  * at eps > 0 with no pivot near-tie: ranks bit-exact, level matrices and
+    stored operators within TOL_EPS(eps) = max(1e-9, 1e-13 / eps^2) relative
+    (the Gram-matrix form of the rank-revealing QR resolves the weakest kept
+    direction to about u / eps^2);
+  * solves within 1e-8 relative of the oracle's.
+"""
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+import oracle as O
+from workloads import (
+    chain1d,
+    config1,
+    config2,
+    convdiff2d_upwind,
+    poisson2d,
+    poisson3d,
+    random_nonsym_dd,
+    random_spd_blocks,
+)
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1712_07297_amd as P
+
+    P.lib()
+    return P
+
+
+def _tol_eps(eps):
+    return 1e-10 if eps == 0 else max(1e-9, 1e-13 / eps**2)
+
+
+def _oracle_ops(rec):
+    """T_L', T_R', E_R, E_L of an oracle record, as the library stores them."""
+    if rec.kind == "full":
+        return np.linalg.inv(rec.L), np.linalg.inv(rec.Uu), rec.ER, rec.EL
+    Ainv = np.linalg.inv(rec.L @ rec.Uu)
+    TL = np.vstack([np.linalg.solve(rec.Lf, rec.VL.T @ Ainv), rec.U.T @ Ainv])
+    TR = np.hstack([Ainv @ rec.VR @ np.linalg.inv(rec.Uf), Ainv @ rec.U])
+    return TL, TR, rec.ER, rec.EL
+
+
+def _rel(a, b, scale):
+    return np.abs(a - b).max() / scale if a.size else 0.0
+
+
+def _compare_factor(P, A, dims, leaf, eps, sym, check_records=True, max_level_check=99):
+    fo = O.factor(A.row_ptr, A.col_idx, A.val, dims, leaf, eps, sym, keep_blocks=True)
+    F = P.Factor(A.row_ptr, A.col_idx, A.val, dims, eps, leaf, symmetric=1 if sym else 0, keep_levels=True)
+    tol = _tol_eps(eps)
+    info = F.info()
+    assert info.nlevels == len(fo.levels)
+    for l, lev in enumerate(fo.levels):
+        assert np.array_equal(F.sizes(l), lev.m), f"sizes level {l}"
+        assert np.array_equal(F.ranks(l), lev.k), f"ranks level {l}"
+        if sum(lev.m) == 0 or l > max_level_check:
+            continue
+        Mo, _ = O.assemble_level_dense(lev)
+        Mg = F.level_matrix(l)
+        scale = np.abs(Mo).max()
+        assert _rel(Mg, Mo, scale) <= tol, f"level {l} matrix"
+        if not check_records:
+            continue
+        for s, rec in enumerate(lev.records):
+            if rec.kind not in ("full", "lowrank"):
+                continue
+            ops = _oracle_ops(rec)
+            base = max(1.0, np.abs(ops[0]).max())
+            for name, o in zip(("TL", "TR", "ER", "EL"), ops):
+                g = F.record(l, s, name)
+                assert g.shape == o.shape, (l, s, name)
+                if o.size == 0:
+                    continue
+                sc = max(np.abs(o).max(), 1e-8 * base)
+                assert _rel(g, o, sc) <= max(tol * 100, 1e-9), (l, s, name, _rel(g, o, sc))
+    return fo, F
+
+
+def _solve_both(P, fo, F, n, nrhs=3, seed=0):
+    B = np.random.default_rng(seed).uniform(-1, 1, (n, nrhs))
+    Xo = O.solve(fo, B)
+    Xg = F.solve(torch.tensor(B.T.copy(), device="cuda")).cpu().numpy().T
+    return B, Xo, Xg
+
+
+EXACT = [
+    ("poisson2d", lambda r: (poisson2d(16, 12), (16, 12, 1), 8, True)),
+    ("poisson3d", lambda r: (poisson3d(6, 6, 5), (6, 6, 5), 8, True)),
+    ("spd_random", lambda r: (random_spd_blocks(r, 14, 9), (14, 9, 1), 6, True)),
+    ("spd_random3d", lambda r: (random_spd_blocks(r, 5, 6, 4), (5, 6, 4), 7, True)),
+    ("nonsym", lambda r: (random_nonsym_dd(r, 13, 11), (13, 11, 1), 6, False)),
+    ("convdiff", lambda r: (convdiff2d_upwind(15, 80.0, 2.0), (15, 15, 1), 8, False)),
+    ("ragged", lambda r: (poisson2d(23, 7), (23, 7, 1), 5, True)),
+]
+
+
+@pytest.mark.parametrize("name,mk", EXACT)
+def test_exact_mode_factor_entries_and_solve(P, name, mk):
+    A, dims, leaf, sym = mk(np.random.default_rng(7))
+    fo, F = _compare_factor(P, A, dims, leaf, 0.0, sym)
+    B, Xo, Xg = _solve_both(P, fo, F, A.n)
+    Xd = sla.lu_solve(sla.lu_factor(A.to_dense()), B)
+    assert np.linalg.norm(Xg - Xd) / np.linalg.norm(Xd) < 1e-12
+    assert np.linalg.norm(Xg - Xo) / np.linalg.norm(Xo) < 1e-12
+
+
+EPS_CASES = [
+    ("spd_1e-2", lambda: (random_spd_blocks(np.random.default_rng(11), 20, 16), (20, 16, 1), 10, 1e-2, True)),
+    ("spd_1e-3", lambda: (random_spd_blocks(np.random.default_rng(11), 20, 16), (20, 16, 1), 10, 1e-3, True)),
+    ("spd_as_general", lambda: (random_spd_blocks(np.random.default_rng(11), 20, 16), (20, 16, 1), 10, 1e-3, False)),
+    ("nonsym_1e-3", lambda: (random_nonsym_dd(np.random.default_rng(12), 20, 16), (20, 16, 1), 10, 1e-3, False)),
+    ("poisson2d_1e-3", lambda: (poisson2d(24, 20), (24, 20, 1), 10, 1e-3, True)),
+    ("poisson3d_1e-4", lambda: (poisson3d(10, 9, 8), (10, 9, 8), 32, 1e-4, True)),
+]
+
+
+@pytest.mark.parametrize("name,mk", EPS_CASES)
+def test_compressed_factor_parity(P, name, mk):
+    A, dims, leaf, eps, sym = mk()
+    fo, F = _compare_factor(P, A, dims, leaf, eps, sym)
+    B, Xo, Xg = _solve_both(P, fo, F, A.n)
+    assert np.linalg.norm(Xg - Xo) / np.linalg.norm(Xo) < 1e-8
+
+
+def test_config1_direct_solve(P):
+    """Config 1: 2D Poisson 32x32, leaves of 16, eps 1e-6, direct solve.
+    Ranks on all 7 levels bit-exact, solve within 1e-8 of the oracle's."""
+    p = config1()
+    fo, F = _compare_factor(P, p.A, p.dims, p.leaf, p.eps, True, check_records=False, max_level_check=1)
+    Xo = O.solve(fo, p.B)
+    Xg = F.solve(torch.tensor(p.B.T.copy(), device="cuda")).cpu().numpy().T
+    assert np.linalg.norm(Xg - Xo) / np.linalg.norm(Xo) < 1e-8
+    r = np.linalg.norm(p.B - p.A.to_dense() @ Xg) / np.linalg.norm(p.B)
+    assert r < 1e-6
+
+
+def test_pcg_poisson3d(P):
+    """Config-2 shape at 16^3: the factor as CG preconditioner, 8 RHS to 1e-10."""
+    p = config2(side=16, nrhs=8)
+    F = P.Factor(p.A.row_ptr, p.A.col_idx, p.A.val, p.dims, p.eps, p.leaf, symmetric=1)
+    Bt = torch.tensor(p.B.T.copy(), device="cuda")
+    X, it, rel, ok = F.pcg(Bt, 1e-10, 100)
+    assert ok and np.all(rel <= 1e-10) and it <= 10
+    Xh = X.cpu().numpy().T
+    Asp = sp.csr_matrix((p.A.val, p.A.col_idx, p.A.row_ptr), shape=(p.A.n, p.A.n))
+    R = p.B - Asp @ Xh
+    assert np.all(np.linalg.norm(R, axis=0) <= 1e-10 * np.linalg.norm(p.B, axis=0) * 1.01)
+    Xd = spla.spsolve(Asp.tocsc(), p.B)
+    assert np.linalg.norm(Xh - Xd) / np.linalg.norm(Xd) < 1e-8
+    # the oracle's PCG with its own factor agrees as well
+    fo = O.factor(p.A.row_ptr, p.A.col_idx, p.A.val, p.dims, p.leaf, p.eps, True)
+    Xo, ito, relo = O.pcg(p.A.row_ptr, p.A.col_idx, p.A.val, p.B, lambda R_: O.solve(fo, R_), 1e-10, 100)
+    assert ito == it
+    assert np.linalg.norm(Xh - Xo) / np.linalg.norm(Xo) < 1e-8
+
+
+def test_gmres_convdiff(P):
+    """Nonsymmetric upwind convection-diffusion, right-preconditioned GMRES(30)."""
+    A = convdiff2d_upwind(48, 60.0, 0.7)
+    F = P.Factor(A.row_ptr, A.col_idx, A.val, (48, 48, 1), 1e-3, 64, symmetric=0)
+    b = np.random.default_rng(3).uniform(-1, 1, A.n)
+    x, it, rel, ok = F.gmres(torch.tensor(b, device="cuda"), 1e-10, 200, 30)
+    assert ok and rel[0] <= 1e-10
+    Asp = sp.csr_matrix((A.val, A.col_idx, A.row_ptr), shape=(A.n, A.n))
+    xd = spla.spsolve(Asp.tocsc(), b)
+    assert np.linalg.norm(x.cpu().numpy() - xd) / np.linalg.norm(xd) < 1e-8
+
+
+def test_single_cluster_is_dense_lu(P):
+    A = random_spd_blocks(np.random.default_rng(3), 5, 4)
+    fo, F = _compare_factor(P, A, (5, 4, 1), 64, 1e-6, True)
+    assert F.info().nlevels == 1
+    B, Xo, Xg = _solve_both(P, fo, F, A.n)
+    assert np.linalg.norm(Xg - np.linalg.solve(A.to_dense(), B)) < 1e-12 * np.linalg.norm(Xg)
+
+
+def test_chain_and_empty_leaves(P):
+    """1D chain with leaf 1 on 3 unknowns has an empty leaf; a longer chain is
+    exact for any eps (rank-1 fill)."""
+    A = chain1d(3)
+    fo, F = _compare_factor(P, A, (3, 1, 1), 1, 1e-6, True)
+    assert 0 in F.sizes(0)
+    A = chain1d(200)
+    fo, F = _compare_factor(P, A, (200, 1, 1), 4, 1e-3, True)
+    B, Xo, Xg = _solve_both(P, fo, F, A.n)
+    assert np.linalg.norm(A.to_dense() @ Xg - B) / np.linalg.norm(B) < 1e-12
+
+
+def test_fixed_rank_mode(P):
+    A = random_spd_blocks(np.random.default_rng(5), 24, 18)
+    fo = O.factor(A.row_ptr, A.col_idx, A.val, (24, 18, 1), 12, 1e-8, True, fixed_rank=3)
+    F = P.Factor(A.row_ptr, A.col_idx, A.val, (24, 18, 1), 1e-8, 12, symmetric=1, fixed_rank=3)
+    for l, lev in enumerate(fo.levels):
+        assert np.array_equal(F.ranks(l), lev.k)
+        assert max(lev.k) <= max(lev.m)
+    B, Xo, Xg = _solve_both(P, fo, F, A.n)
+    assert np.linalg.norm(Xg - Xo) / np.linalg.norm(Xo) < 1e-8
+
+
+def test_breakdown_is_reported(P):
+    """A zero pivot in an unpivoted LU is an error naming level and cluster."""
+    A = poisson2d(8, 8)
+    val = A.val.copy()
+    rows = np.repeat(np.arange(A.n), np.diff(A.row_ptr))
+    val[(rows == 0) & (A.col_idx == 0)] = 0.0  # first pivot of the first leaf
+    with pytest.raises(P.HsError) as e:
+        P.Factor(A.row_ptr, A.col_idx, val, (8, 8, 1), 1e-6, 16, symmetric=1)
+    assert e.value.code == -4 and "level 0" in str(e.value)
+
+
+def test_device_csr_and_determinism(P):
+    """A CSR handed over in device memory gives the same factor; two runs are
+    bitwise identical."""
+    A = random_spd_blocks(np.random.default_rng(9), 30, 20)
+    F1 = P.Factor(A.row_ptr, A.col_idx, A.val, (30, 20, 1), 1e-4, 16, symmetric=1)
+    d = lambda x: torch.tensor(x, device="cuda")
+    F2 = P.Factor(d(A.row_ptr), d(A.col_idx), d(A.val), (30, 20, 1), 1e-4, 16, symmetric=1)
+    B = torch.tensor(np.random.default_rng(1).uniform(-1, 1, (2, A.n)), device="cuda")
+    x1 = F1.solve(B)
+    x2 = F2.solve(B)
+    assert torch.equal(x1, x2)
+
+
+def test_symmetric_detection(P):
+    A = random_spd_blocks(np.random.default_rng(9), 12, 12)
+    F = P.Factor(A.row_ptr, A.col_idx, A.val, (12, 12, 1), 1e-4, 16, symmetric=-1)
+    G = P.Factor(A.row_ptr, A.col_idx, A.val, (12, 12, 1), 1e-4, 16, symmetric=1)
+    for l in range(F.info().nlevels):
+        assert np.array_equal(F.ranks(l), G.ranks(l))
