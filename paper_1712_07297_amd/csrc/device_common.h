@@ -128,80 +128,99 @@ __device__ inline void wg_zero(int M, int N, double* dst, int ldd) {
     }
 }
 
-// ------------------------------------------------------------ cooperative GEMM
-// C (M x N) = alpha op(A) op(B) + beta C; op(A) is M x K, op(B) is K x N.
-// 64 x 64 output tiles, K staged through LDS in chunks of 16; each of the 256
-// threads owns a 4 x 4 register micro-tile.  beta == 0 never reads C.
-constexpr int GT = 64, GK = 16;
-struct GemmSmem {
-    double a[GK][GT + 1];
-    double b[GK][GT + 1];
+// ------------------------------------------------------------ MFMA tile core
+// One 64 x 64 tile of D = Left (64 x K) * Right (K x 64) on the FP64 matrix
+// cores (v_mfma_f64_16x16x4f64): 4 waves as 2 x 2 quarters of 32 x 32, each
+// quarter 2 x 2 blocks of 16 x 16.  The MFMA computes the transposed block
+// (Right^T Left^T) so that lane l % 16 indexes rows of D: the epilogue then
+// touches 16 consecutive rows of a column per group of lanes (coalesced for
+// column-major outputs).  Lane layout of the instruction: operand a of lane l
+// is row l%16, k l/16; operand b of lane l is k l/16, column l%16; result
+// element r of lane l is row l/16 + 4r, column l%16.
+typedef double v4d __attribute__((ext_vector_type(4)));
+constexpr int MT = 64, MKC = 16;
+struct MfmaSmem {
+    double a[MKC][MT + 1];  // a[k][row] = Left(row, k)
+    double b[MKC][MT + 1];  // b[k][col] = Right(k, col)
 };
+
+// la(r, k) / lb(k, c) return the operand element or 0 outside the matrix.
+template <class LoadL, class LoadR>
+__device__ inline void mfma_tile64(int K, const LoadL& la, const LoadR& lb, MfmaSmem* sm, v4d acc[2][2]) {
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wm = (w & 1) * 32, wn = (w >> 1) * 32;
+    const int lr = lane & 15, lk = lane >> 4;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < K; k0 += MKC) {
+        __syncthreads();
+        for (int e = tid; e < MT * MKC; e += WG) {
+            const int r = e % MT, kk = e / MT;
+            sm->a[kk][r] = (k0 + kk < K) ? la(r, k0 + kk) : 0.0;
+            const int kb = e % MKC, c = e / MKC;
+            sm->b[kb][c] = (k0 + kb < K) ? lb(k0 + kb, c) : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < MKC; ks += 4) {
+            double av[2], bv[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) av[i] = sm->a[ks + lk][wm + 16 * i + lr];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) bv[j] = sm->b[ks + lk][wn + 16 * j + lr];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[j], av[i], acc[i][j], 0, 0, 0);
+        }
+    }
+}
+
+// Visit the tile's results: f(row, col, value), row/col within the 64 x 64 tile.
+template <class Fn>
+__device__ inline void mfma_tile64_store(const v4d acc[2][2], const Fn& f) {
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wm = (w & 1) * 32, wn = (w >> 1) * 32;
+    const int lr = lane & 15, lk = lane >> 4;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) f(wm + 16 * i + lr, wn + 16 * j + lk + 4 * r, acc[i][j][r]);
+}
+
+// ------------------------------------------------------------ cooperative GEMM
+// C (M x N) = alpha op(A) op(B) + beta C; op(A) is M x K, op(B) is K x N, on
+// the FP64 matrix cores, 64 x 64 tiles.  beta == 0 never reads C.
+typedef MfmaSmem GemmSmem;
 
 template <bool TA, bool TB>
 __device__ void wg_gemm(int M, int N, int K, double alpha, const double* A, int lda, const double* B, int ldb,
                         double beta, double* C, int ldc, GemmSmem* sm) {
-    const int tid = threadIdx.x;
-    const int tx = tid & 15, ty = tid >> 4;  // 16 x 16 threads
-    for (int r0 = 0; r0 < M; r0 += GT)
-        for (int c0 = 0; c0 < N; c0 += GT) {
-            double acc[4][4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
-            for (int k0 = 0; k0 < K; k0 += GK) {
-                __syncthreads();
-                for (int e = tid; e < GT * GK; e += WG) {
-                    int kk, rr;
-                    if (TA) {
-                        kk = e % GK;
-                        rr = e / GK;
-                    } else {
-                        rr = e % GT;
-                        kk = e / GT;
-                    }
-                    int gr = r0 + rr, gk = k0 + kk;
-                    double va = 0.0;
-                    if (gr < M && gk < K) va = TA ? A[gk + (int64_t)gr * lda] : A[gr + (int64_t)gk * lda];
-                    sm->a[kk][rr] = va;
-                    int cc, kb;
-                    if (TB) {
-                        cc = e % GT;
-                        kb = e / GT;
-                    } else {
-                        kb = e % GK;
-                        cc = e / GK;
-                    }
-                    int gc = c0 + cc, gkb = k0 + kb;
-                    double vb = 0.0;
-                    if (gc < N && gkb < K) vb = TB ? B[gc + (int64_t)gkb * ldb] : B[gkb + (int64_t)gc * ldb];
-                    sm->b[kb][cc] = vb;
+    for (int r0 = 0; r0 < M; r0 += MT)
+        for (int c0 = 0; c0 < N; c0 += MT) {
+            v4d acc[2][2];
+            mfma_tile64(
+                K,
+                [&](int r, int k) {
+                    const int gr = r0 + r;
+                    return gr < M ? (TA ? A[k + (int64_t)gr * lda] : A[gr + (int64_t)k * lda]) : 0.0;
+                },
+                [&](int k, int c) {
+                    const int gc = c0 + c;
+                    return gc < N ? (TB ? B[gc + (int64_t)k * ldb] : B[k + (int64_t)gc * ldb]) : 0.0;
+                },
+                sm, acc);
+            mfma_tile64_store(acc, [&](int r, int c, double v) {
+                const int gr = r0 + r, gc = c0 + c;
+                if (gr < M && gc < N) {
+                    double* p = C + gr + (int64_t)gc * ldc;
+                    *p = (beta == 0.0) ? alpha * v : fma(alpha, v, beta * *p);
                 }
-                __syncthreads();
-                const int kmax = min(GK, K - k0);
-                for (int kk = 0; kk < kmax; ++kk) {
-                    double av[4], bv[4];
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) av[i] = sm->a[kk][tx + 16 * i];
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) bv[j] = sm->b[kk][ty + 16 * j];
-#pragma unroll
-                    for (int i = 0; i < 4; ++i)
-#pragma unroll
-                        for (int j = 0; j < 4; ++j) acc[i][j] = fma(av[i], bv[j], acc[i][j]);
-                }
-            }
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    int gr = r0 + tx + 16 * i, gc = c0 + ty + 16 * j;
-                    if (gr < M && gc < N) {
-                        double* p = C + gr + (int64_t)gc * ldc;
-                        *p = (beta == 0.0) ? alpha * acc[i][j] : fma(alpha, acc[i][j], beta * *p);
-                    }
-                }
+            });
         }
     __syncthreads();
 }

@@ -18,7 +18,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/hs.h"
+#include "hs.h"
 #include "kernels.h"
 #include "symbolic.h"
 
@@ -127,8 +127,9 @@ struct ProfFamily {
     int64_t launches = 0;
     double seconds = 0.0, bytes = 0.0, flops = 0.0;
 };
-enum ProfId { PF_GRAM = 0, PF_PIVOT, PF_FILL, PF_NBR, PF_SCHUR, PF_MERGE, PF_APPLY, PF_SPMV, PF_COUNT };
-static ProfFamily g_prof[PF_COUNT] = {{"gram"}, {"pivot"}, {"fill"}, {"nbr"}, {"schur"}, {"merge"}, {"apply"}, {"spmv"}};
+enum ProfId { PF_GRAM = 0, PF_PIVOT, PF_FILL, PF_NBR, PF_SCHUR, PF_MERGE, PF_APPLY, PF_SPMV, PF_DENSE, PF_COUNT };
+static ProfFamily g_prof[PF_COUNT] = {{"gram"}, {"pivot"}, {"fill"}, {"nbr"},   {"schur"},
+                                      {"merge"}, {"apply"}, {"spmv"}, {"dense"}};
 static bool g_prof_on = false;
 struct ProfPending {
     int fam;
@@ -209,6 +210,8 @@ struct LevelData {
     DevBuf rec;
     LevelDev dev{};
     SolveLevelDev sdev{};
+    const int* dev_pat_ptr = nullptr;  // final pattern on the device
+    const int* dev_pat = nullptr;
     std::vector<ColourHost> colours;
     std::vector<int64_t> seg;                      // [ncl+1] segment offsets
     int64_t nseg = 0;
@@ -455,6 +458,8 @@ static void bind_level(LevelData& LD, const std::vector<size_t>& offs, const hs_
     D.rec = LD.rec.as<double>();
     D.ws_off = (const int64_t*)P(21);
     D.ws = F->ws.as<double>();
+    LD.dev_pat_ptr = (const int*)P(22);
+    LD.dev_pat = (const int*)P(23);
     const int* order = (const int*)P(24);
     for (auto& CH : LD.colours) {
         CH.dev.clist = order + CH.first;
@@ -519,6 +524,59 @@ static int keep_level_matrix(hs_factor_s* F, LevelData& LD, hipStream_t st) {
                 for (int i = 0; i < LD.m[a]; ++i)
                     LD.kept[(off[a] + i) + (off[b] + j) * dim] = blk[LD.blk_off[e] + i + (int64_t)j * LD.m[a]];
         }
+    return HS_OK;
+}
+
+// Dense factorization of a complete level; ranks become 0 and the solve
+// metadata (packed neighbour offsets, n_tot) is written for every cluster.
+static int factor_dense_level(hs_factor_s* F, int lvl, hipStream_t st) {
+    LevelData& LD = F->levels[lvl];
+    const LevelSymbolic& S = F->sym.levels[lvl];
+    std::vector<int64_t> off(LD.ncl + 1, 0);
+    for (int c = 0; c < LD.ncl; ++c) off[c + 1] = off[c] + LD.m[c];
+    const int64_t N = off[LD.ncl];
+    // packed offsets: neighbours before s are eliminated (size 0)
+    std::vector<int> noff(S.adj.size()), ntot(LD.ncl), zeros(LD.ncl, 0);
+    for (int s = 0; s < LD.ncl; ++s) {
+        int acc = 0;
+        for (int e = S.adj_ptr[s]; e < S.adj_ptr[s + 1]; ++e) {
+            noff[e] = acc;
+            const int a = S.adj[e];
+            acc += a < s ? 0 : LD.m[a];
+        }
+        ntot[s] = acc;
+    }
+    HIP_TRY(hipMemcpyAsync(LD.dev.nbr_noff, noff.data(), noff.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(LD.dev.ntot, ntot.data(), ntot.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(LD.dev.k, zeros.data(), zeros.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    if (N == 0) return HS_OK;
+    Blob b;
+    const size_t o_off = b.add(off);
+    DevBuf aux, dense;
+    if (!aux.alloc(b.data.size() + (2 * 128 * 128 + 64) * sizeof(double))) return fail(HS_ERR_NOMEM, "dense level");
+    if (!dense.alloc((size_t)N * N * sizeof(double))) return fail(HS_ERR_NOMEM, "dense level matrix");
+    HIP_TRY(hipMemcpyAsync(aux.p, b.data.data(), b.data.size(), hipMemcpyHostToDevice, st));
+    char* base = aux.as<char>();
+    const size_t o_inv = (b.data.size() + 255) & ~size_t(255);
+    double* inv = (double*)(base + o_inv);
+    int* flag = (int*)(inv + 2 * 128 * 128);
+    HIP_TRY(hipMemsetAsync(flag, 0, sizeof(int), st));
+    int rc;
+    {
+        ProfScope ps(PF_DENSE, st);
+        rc = dense_level_factor(dense.as<double>(), N, LD.dev_pat_ptr, LD.dev_pat, LD.dev.m,
+                                (const int64_t*)(base + o_off), LD.dev.blk_off, LD.dev.blocks, LD.ncl, LD.nblk, inv,
+                                flag, LD.dev.ncap, LD.dev.rec_off, LD.dev.rec, LD.m, off, st);
+    }
+    if (rc) return fail(HS_ERR_HIP, "dense level launch failed");
+    int hflag = 0;
+    HIP_TRY(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (hflag) {
+        F->info.breakdown_level = lvl;
+        F->info.breakdown_cluster = -1;
+        return fail(HS_ERR_BREAKDOWN, "zero or non-finite pivot at level " + std::to_string(lvl) + " (dense level)");
+    }
     return HS_OK;
 }
 
@@ -650,7 +708,17 @@ static int factor_impl(hs_factor_s* F, const hs_csr* A, const hs_geometry* G, hi
             rc = keep_level_matrix(F, LD, st);
             if (rc) return rc;
         }
+        // A level whose clusters all neighbour each other has no fill: it is
+        // factored densely (Alg. 1, conventional factorization).
+        bool complete = true;
+        for (int c = 0; c < S.ncl && complete; ++c)
+            if (S.adj_ptr[c + 1] - S.adj_ptr[c] != S.ncl - 1 || S.order[c] != c) complete = false;
+        if (complete) {
+            rc = factor_dense_level(F, lvl, st);
+            if (rc) return rc;
+        }
         for (auto& CH : LD.colours) {
+            if (complete) break;
             if (F->opts.eps > 0.0 && CH.dev.fill_total > 0) {
                 ProfScope ps(PF_GRAM, st);
                 launch_gram(LD.dev, CH.dev, st);

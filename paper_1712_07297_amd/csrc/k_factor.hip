@@ -456,13 +456,14 @@ void launch_nbr_update(const LevelDev& L, const ColourDev& C, hipStream_t st) {
 // A_ab -= E_L[a] E_R[b] for all neighbour pairs of s, computed as the single
 // product E_L E_R (ntot x ntot, inner dimension f) in 64 x 64 tiles whose
 // epilogue scatters every entry into its block (Eq. elim).
-struct SchurSmem {
-    double a[GK][SCHUR_T + 1];
-    double b[GK][SCHUR_T + 1];
+constexpr int PTAB = 256;  // block-pointer table of a Schur tile (row x column neighbours)
+struct SchurMaps {
     int rblk[SCHUR_T];   // neighbour index of every tile row (-1 = none)
     int rloc[SCHUR_T];
     int cblk[SCHUR_T];
     int cloc[SCHUR_T];
+    double* ptab[PTAB];  // block (bi0 + i, bj0 + j) at ptab[i * nbj + j]
+    int ldtab[SCHUR_T];  // leading dimension of row neighbour bi0 + i
 };
 
 __device__ inline void map_rows(const LevelDev& L, int s, int r0, int nt, int* nbr_of, int* loc_of) {
@@ -489,7 +490,8 @@ __device__ inline void map_rows(const LevelDev& L, int s, int r0, int nt, int* n
 }
 
 __global__ void __launch_bounds__(WG) k_schur(LevelDev L, ColourDev C) {
-    __shared__ SchurSmem sm;
+    __shared__ MfmaSmem sm;
+    __shared__ SchurMaps mp;
     const int64_t q = blockIdx.x;
     const int ci = find_cluster64(C.tile_pre, C.n, q);
     const int s = C.clist[ci];
@@ -504,56 +506,43 @@ __global__ void __launch_bounds__(WG) k_schur(LevelDev L, ColourDev C) {
     const int r0 = (int)(t / tpr) * SCHUR_T, c0 = (int)(t % tpr) * SCHUR_T;
     if (r0 >= nt || c0 >= nt) return;
     const int64_t MM = (int64_t)M * M;
-    const double* ER = L.rec + L.rec_off[s] + 2 * MM;  // ld M
-    const double* EL = ER + (int64_t)M * ncap;          // ld ncap
-    map_rows(L, s, r0, nt, sm.rblk, sm.rloc);
-    map_rows(L, s, c0, nt, sm.cblk, sm.cloc);
-
-    const int tid = threadIdx.x;
-    const int tx = tid & 15, ty = tid >> 4;
-    double acc[4][4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
-    for (int k0 = 0; k0 < f; k0 += GK) {
-        __syncthreads();
-        for (int e = tid; e < SCHUR_T * GK; e += WG) {
-            const int rr = e % SCHUR_T, kx = e / SCHUR_T;
-            const int gk = k0 + kx;
-            sm.a[kx][rr] = (r0 + rr < nt && gk < f) ? EL[(r0 + rr) + (int64_t)gk * ncap] : 0.0;
-            const int kb = e % GK, cc = e / GK;
-            const int gkb = k0 + kb;
-            sm.b[kb][cc] = (c0 + cc < nt && gkb < f) ? ER[gkb + (int64_t)(c0 + cc) * M] : 0.0;
-        }
-        __syncthreads();
-        const int kmax = min(GK, f - k0);
-        for (int kx = 0; kx < kmax; ++kx) {
-            double av[4], bv[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) av[i] = sm.a[kx][tx + 16 * i];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) bv[j] = sm.b[kx][ty + 16 * j];
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = fma(av[i], bv[j], acc[i][j]);
-        }
-    }
+    const double* ER = L.rec + L.rec_off[s] + 2 * MM;  // f x ntot, ld M
+    const double* EL = ER + (int64_t)M * ncap;          // ntot x f, ld ncap
+    map_rows(L, s, r0, nt, mp.rblk, mp.rloc);
+    map_rows(L, s, c0, nt, mp.cblk, mp.cloc);
+    v4d acc[2][2];
+    mfma_tile64(
+        f, [&](int r, int k) { return (r0 + r < nt && k < f) ? EL[(r0 + r) + (int64_t)k * ncap] : 0.0; },
+        [&](int k, int c) { return (c0 + c < nt && k < f) ? ER[k + (int64_t)(c0 + c) * M] : 0.0; }, &sm, acc);
     __syncthreads();
     const int e0 = L.nbr_ptr[s], nb = L.nbr_ptr[s + 1] - e0;
     const int64_t pb = L.pair_base[s];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int r = tx + 16 * i, c = ty + 16 * j;
-            const int bi = sm.rblk[r], bj = sm.cblk[c];
-            if (bi < 0 || bj < 0) continue;
+    // neighbour ranges covered by the tile; the block pointers of every
+    // (row neighbour, column neighbour) pair go to LDS once
+    const int nr = min(SCHUR_T, nt - r0), nc = min(SCHUR_T, nt - c0);
+    const int bi0 = mp.rblk[0], bj0 = mp.cblk[0];
+    const int nbi = mp.rblk[nr - 1] - bi0 + 1, nbj = mp.cblk[nc - 1] - bj0 + 1;
+    const bool table = nbi * nbj <= PTAB;
+    if (table) {
+        for (int x = threadIdx.x; x < nbi * nbj; x += blockDim.x) {
+            const int i = x / nbj, j = x % nbj;
+            mp.ptab[x] = blk_ptr(L, L.pair_blk[pb + (int64_t)(bi0 + i) * nb + (bj0 + j)]);
+        }
+        for (int i = threadIdx.x; i < nbi; i += blockDim.x) mp.ldtab[i] = L.m[L.nbr_id[e0 + bi0 + i]];
+    }
+    __syncthreads();
+    mfma_tile64_store(acc, [&](int r, int c, double v) {
+        const int bi = mp.rblk[r], bj = mp.cblk[c];
+        if (bi < 0 || bj < 0) return;
+        if (table) {
+            const int i = bi - bi0;
+            mp.ptab[i * nbj + (bj - bj0)][mp.rloc[r] + (int64_t)mp.cloc[c] * mp.ldtab[i]] -= v;
+        } else {
             const int a = L.nbr_id[e0 + bi];
             double* Cb = blk_ptr(L, L.pair_blk[pb + (int64_t)bi * nb + bj]);
-            Cb[sm.rloc[r] + (int64_t)sm.cloc[c] * L.m[a]] -= acc[i][j];
+            Cb[mp.rloc[r] + (int64_t)mp.cloc[c] * L.m[a]] -= v;
         }
+    });
 }
 
 void launch_schur(const LevelDev& L, const ColourDev& C, hipStream_t st) {

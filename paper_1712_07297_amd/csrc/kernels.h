@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <vector>
 
 #include "device_common.h"
 
@@ -46,6 +47,14 @@ void launch_merge(int nblk_next, const int* nb_row, const int* nb_col, const int
                   const int* m_prev, const int64_t* blk_off_prev, const double* blocks_prev, const int* m_next,
                   const int64_t* blk_off_next, double* blocks_next, int ncl_prev, hipStream_t st);
 void launch_fill_zero(double* p, int64_t n, hipStream_t st);
+// Dense level (complete cluster graph): assemble D (N x N, ld N) from the
+// block store, unpivoted blocked LU in place, per-cluster operators into the
+// records.  inv: 2 * 128 * 128 doubles of workspace; flag: device int, set to
+// 1 on a zero or non-finite pivot.
+int dense_level_factor(double* D, int64_t N, const int* pat_ptr, const int* pat, const int* m, const int64_t* off,
+                       const int64_t* blk_off, const double* blocks, int ncl, int nblk, double* inv, int* flag,
+                       const int* ncap, const int64_t* rec_off, double* rec, const std::vector<int>& m_host,
+                       const std::vector<int64_t>& off_host, hipStream_t st);
 
 // ---- solve (Alg. 2)
 struct SolveLevelDev {

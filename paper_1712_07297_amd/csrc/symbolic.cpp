@@ -12,7 +12,7 @@
 #include <array>
 #include <cstring>
 
-#include "../../include/hs.h"
+#include "hs.h"
 
 namespace hs {
 
