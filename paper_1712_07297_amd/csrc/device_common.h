@@ -22,6 +22,14 @@ constexpr int MAX_M = 512;    // largest cluster the kernels accept
 // rounding noise of earlier Schur updates and is treated as zero.
 constexpr double FILL_NOISE_FLOOR = 1e-12;
 
+// Pointers into LDS carry their address space: routines instantiated for
+// them compile to ds_* instructions rather than generic (flat) accesses.
+typedef __attribute__((address_space(3))) double lds_f64;
+typedef __attribute__((address_space(3))) int lds_i32;
+typedef __attribute__((address_space(1))) double glb_f64;  // global memory
+__device__ inline lds_f64* to_lds(double* p) { return (lds_f64*)p; }
+__device__ inline lds_i32* to_lds(int* p) { return (lds_i32*)p; }
+
 // Per-level view of the factorization state (device pointers).
 struct LevelDev {
     int ncl;
@@ -65,21 +73,51 @@ __device__ inline double* blk_ptr(const LevelDev& L, int id) { return L.blocks +
 
 // ---------------------------------------------------------------- reductions
 
+// Wave-wide reductions over DPP lane permutations (every lane active): swaps
+// inside quads, then the half-row and row mirrors leave each row of 16 lanes
+// with its row total; the four row totals are combined from lanes 0, 16, 32
+// and 48.  Every lane gets the same result.
+template <int CTRL>
+__device__ inline double dpp_d(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ inline double readlane_d(double v, int l) {  // value of v in lane l (l uniform)
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+constexpr int DPP_QUAD_1032 = 0xB1, DPP_QUAD_2301 = 0x4E, DPP_ROW_MIRROR = 0x140, DPP_ROW_HALF_MIRROR = 0x141;
+
 __device__ inline double wave_sum(double v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    v += dpp_d<DPP_QUAD_1032>(v);
+    v += dpp_d<DPP_QUAD_2301>(v);
+    v += dpp_d<DPP_ROW_HALF_MIRROR>(v);
+    v += dpp_d<DPP_ROW_MIRROR>(v);
+    return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
 }
 __device__ inline double wave_max(double v) {
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-    return v;
+    v = fmax(v, dpp_d<DPP_QUAD_1032>(v));
+    v = fmax(v, dpp_d<DPP_QUAD_2301>(v));
+    v = fmax(v, dpp_d<DPP_ROW_HALF_MIRROR>(v));
+    v = fmax(v, dpp_d<DPP_ROW_MIRROR>(v));
+    return fmax(fmax(readlane_d(v, 0), readlane_d(v, 16)), fmax(readlane_d(v, 32), readlane_d(v, 48)));
 }
 __device__ inline int wave_min_int(int v) {
-    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
-    return v;
+    v = min(v, __builtin_amdgcn_update_dpp(0, v, DPP_QUAD_1032, 0xF, 0xF, false));
+    v = min(v, __builtin_amdgcn_update_dpp(0, v, DPP_QUAD_2301, 0xF, 0xF, false));
+    v = min(v, __builtin_amdgcn_update_dpp(0, v, DPP_ROW_HALF_MIRROR, 0xF, 0xF, false));
+    v = min(v, __builtin_amdgcn_update_dpp(0, v, DPP_ROW_MIRROR, 0xF, 0xF, false));
+    return min(min(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
+               min(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
 }
 
 // Block-wide reductions (blockDim.x a multiple of 64, <= 1024); red has >= 16 slots.
-__device__ inline double block_sum(double v, double* red) {
+template <class PR>
+__device__ inline double block_sum(double v, PR red) {
     v = wave_sum(v);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
     __syncthreads();
@@ -90,7 +128,8 @@ __device__ inline double block_sum(double v, double* red) {
     __syncthreads();
     return r;
 }
-__device__ inline double block_max(double v, double* red) {
+template <class PR>
+__device__ inline double block_max(double v, PR red) {
     v = wave_max(v);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
     __syncthreads();
@@ -101,7 +140,8 @@ __device__ inline double block_max(double v, double* red) {
     __syncthreads();
     return r;
 }
-__device__ inline int block_min_int(int v, int* red) {
+template <class PR>
+__device__ inline int block_min_int(int v, PR red) {
     v = wave_min_int(v);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
     __syncthreads();
@@ -114,18 +154,19 @@ __device__ inline int block_min_int(int v, int* red) {
 }
 
 // ------------------------------------------------------------ cooperative copy
+// Columns over waves, rows over lanes (no integer division in the loops).
 
-__device__ inline void wg_copy(int M, int N, const double* src, int lds, double* dst, int ldd) {
-    for (int64_t e = threadIdx.x; e < (int64_t)M * N; e += blockDim.x) {
-        int i = (int)(e % M), j = (int)(e / M);
-        dst[i + (int64_t)j * ldd] = src[i + (int64_t)j * lds];
-    }
+template <class PS, class PD>
+__device__ inline void wg_copy(int M, int N, PS src, int lds, PD dst, int ldd) {
+    const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+    for (int j = threadIdx.x >> 6; j < N; j += nw)
+        for (int i = lane; i < M; i += 64) dst[i + (int64_t)j * ldd] = src[i + (int64_t)j * lds];
 }
-__device__ inline void wg_zero(int M, int N, double* dst, int ldd) {
-    for (int64_t e = threadIdx.x; e < (int64_t)M * N; e += blockDim.x) {
-        int i = (int)(e % M), j = (int)(e / M);
-        dst[i + (int64_t)j * ldd] = 0.0;
-    }
+template <class PD>
+__device__ inline void wg_zero(int M, int N, PD dst, int ldd) {
+    const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+    for (int j = threadIdx.x >> 6; j < N; j += nw)
+        for (int i = lane; i < M; i += 64) dst[i + (int64_t)j * ldd] = 0.0;
 }
 
 // ------------------------------------------------------------ MFMA tile core
@@ -143,26 +184,41 @@ struct MfmaSmem {
     double a[MKC][MT + 1];  // a[k][row] = Left(row, k)
     double b[MKC][MT + 1];  // b[k][col] = Right(k, col)
 };
+typedef __attribute__((address_space(3))) MfmaSmem lds_smem;
+__device__ inline lds_smem* to_lds(MfmaSmem* p) { return (lds_smem*)p; }
 
 // la(r, k) / lb(k, c) return the operand element or 0 outside the matrix.
+// Accumulates into acc (acc += Left * Right).
 template <class LoadL, class LoadR>
-__device__ inline void mfma_tile64(int K, const LoadL& la, const LoadR& lb, MfmaSmem* sm, v4d acc[2][2]) {
+__device__ inline void mfma_tile64_acc(int K, const LoadL& la, const LoadR& lb, lds_smem* sm, v4d acc[2][2]) {
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wm = (w & 1) * 32, wn = (w >> 1) * 32;
     const int lr = lane & 15, lk = lane >> 4;
+    // each thread stages 4 elements of each operand per K chunk; the next
+    // chunk is fetched into registers while the matrix cores work on this one
+    constexpr int PER = MT * MKC / WG;
+    double ra[PER], rb[PER];
+    auto fetch = [&](int k0) {
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+        for (int t = 0; t < PER; ++t) {
+            const int e = tid + t * WG;
+            const int r = e % MT, kk = e / MT;
+            ra[t] = (k0 + kk < K) ? la(r, k0 + kk) : 0.0;
+            const int kb = e % MKC, c = e / MKC;
+            rb[t] = (k0 + kb < K) ? lb(k0 + kb, c) : 0.0;
+        }
+    };
+    if (K > 0) fetch(0);
     for (int k0 = 0; k0 < K; k0 += MKC) {
         __syncthreads();
-        for (int e = tid; e < MT * MKC; e += WG) {
-            const int r = e % MT, kk = e / MT;
-            sm->a[kk][r] = (k0 + kk < K) ? la(r, k0 + kk) : 0.0;
-            const int kb = e % MKC, c = e / MKC;
-            sm->b[kb][c] = (k0 + kb < K) ? lb(k0 + kb, c) : 0.0;
+#pragma unroll
+        for (int t = 0; t < PER; ++t) {
+            const int e = tid + t * WG;
+            sm->a[e / MT][e % MT] = ra[t];
+            sm->b[e % MKC][e / MKC] = rb[t];
         }
         __syncthreads();
+        if (k0 + MKC < K) fetch(k0 + MKC);
 #pragma unroll
         for (int ks = 0; ks < MKC; ks += 4) {
             double av[2], bv[2];
@@ -176,6 +232,20 @@ __device__ inline void mfma_tile64(int K, const LoadL& la, const LoadR& lb, Mfma
                 for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[j], av[i], acc[i][j], 0, 0, 0);
         }
     }
+}
+
+__device__ inline void mfma_zero(v4d acc[2][2]) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+}
+
+// acc = Left * Right.
+template <class LoadL, class LoadR>
+__device__ inline void mfma_tile64(int K, const LoadL& la, const LoadR& lb, lds_smem* sm, v4d acc[2][2]) {
+    mfma_zero(acc);
+    mfma_tile64_acc(K, la, lb, sm, acc);
 }
 
 // Visit the tile's results: f(row, col, value), row/col within the 64 x 64 tile.
@@ -192,14 +262,29 @@ __device__ inline void mfma_tile64_store(const v4d acc[2][2], const Fn& f) {
             for (int r = 0; r < 4; ++r) f(wm + 16 * i + lr, wn + 16 * j + lk + 4 * r, acc[i][j][r]);
 }
 
+// As mfma_tile64_store, with the running index idx in [0, 16) of the entry
+// within the lane (compile-time after unrolling).
+template <class Fn>
+__device__ inline void mfma_tile64_visit(const v4d acc[2][2], const Fn& f) {
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wm = (w & 1) * 32, wn = (w >> 1) * 32;
+    const int lr = lane & 15, lk = lane >> 4;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) f((i * 2 + j) * 4 + r, wm + 16 * i + lr, wn + 16 * j + lk + 4 * r, acc[i][j][r]);
+}
+
 // ------------------------------------------------------------ cooperative GEMM
 // C (M x N) = alpha op(A) op(B) + beta C; op(A) is M x K, op(B) is K x N, on
 // the FP64 matrix cores, 64 x 64 tiles.  beta == 0 never reads C.
 typedef MfmaSmem GemmSmem;
 
-template <bool TA, bool TB>
-__device__ void wg_gemm(int M, int N, int K, double alpha, const double* A, int lda, const double* B, int ldb,
-                        double beta, double* C, int ldc, GemmSmem* sm) {
+template <bool TA, bool TB, class PA, class PB, class PC>
+__device__ void wg_gemm(int M, int N, int K, double alpha, PA A, int lda, PB B, int ldb, double beta, PC C, int ldc,
+                        lds_smem* sm) {
     for (int r0 = 0; r0 < M; r0 += MT)
         for (int c0 = 0; c0 < N; c0 += MT) {
             v4d acc[2][2];
@@ -214,133 +299,389 @@ __device__ void wg_gemm(int M, int N, int K, double alpha, const double* A, int 
                     return gc < N ? (TB ? B[gc + (int64_t)k * ldb] : B[k + (int64_t)gc * ldb]) : 0.0;
                 },
                 sm, acc);
-            mfma_tile64_store(acc, [&](int r, int c, double v) {
-                const int gr = r0 + r, gc = c0 + c;
-                if (gr < M && gc < N) {
-                    double* p = C + gr + (int64_t)gc * ldc;
-                    *p = (beta == 0.0) ? alpha * v : fma(alpha, v, beta * *p);
-                }
-            });
+            if (beta == 0.0) {
+                mfma_tile64_store(acc, [&](int r, int c, double v) {
+                    const int gr = r0 + r, gc = c0 + c;
+                    if (gr < M && gc < N) C[gr + (int64_t)gc * ldc] = alpha * v;
+                });
+            } else {  // read all 16 old values of the lane, then write
+                double old[16];
+                mfma_tile64_visit(acc, [&](int idx, int r, int c, double) {
+                    const int gr = r0 + r, gc = c0 + c;
+                    old[idx] = (gr < M && gc < N) ? C[gr + (int64_t)gc * ldc] : 0.0;
+                });
+                mfma_tile64_visit(acc, [&](int idx, int r, int c, double v) {
+                    const int gr = r0 + r, gc = c0 + c;
+                    if (gr < M && gc < N) C[gr + (int64_t)gc * ldc] = fma(alpha, v, beta * old[idx]);
+                });
+            }
         }
     __syncthreads();
 }
 
 // ---------------------------------------------------- LU without pivoting
-// In place Doolittle LU of the M x M matrix W (ld ldw).  Returns false on a
-// zero or non-finite pivot (every thread gets the same answer).
-__device__ inline bool wg_lu_nopiv(double* W, int M, int ldw, int* flag_sh) {
-    const int tid = threadIdx.x;
-    if (tid == 0) *flag_sh = 0;
+// In place Doolittle LU of the M x M matrix W (ld ldw), one barrier per
+// elimination step: the multipliers of column j are formed on the fly by the
+// threads of the trailing update and stored one step later, when nothing
+// reads the column any more.  Returns false on a zero or non-finite pivot
+// (every thread reads the same pivot, so every thread returns the same).
+template <class PW>
+__device__ inline bool wg_lu_nopiv(PW W, int M, int ldw) {
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
     __syncthreads();
     for (int j = 0; j < M; ++j) {
         const double p = W[j + (int64_t)j * ldw];
-        if (p == 0.0 || !isfinite(p)) {
-            if (tid == 0) *flag_sh = 1;
-        }
-        __syncthreads();
-        if (*flag_sh) return false;
+        if (p == 0.0 || !isfinite(p)) return false;
         const double inv = 1.0 / p;
-        for (int i = j + 1 + tid; i < M; i += blockDim.x) W[i + (int64_t)j * ldw] *= inv;
-        __syncthreads();
-        const int n = M - j - 1;
-        for (int64_t e = tid; e < (int64_t)n * n; e += blockDim.x) {
-            int i = j + 1 + (int)(e % n), c = j + 1 + (int)(e / n);
-            W[i + (int64_t)c * ldw] -= W[i + (int64_t)j * ldw] * W[j + (int64_t)c * ldw];
+        if (j > 0) {
+            const double ip = 1.0 / W[(j - 1) + (int64_t)(j - 1) * ldw];
+            for (int i = j + tid; i < M; i += blockDim.x) W[i + (int64_t)(j - 1) * ldw] *= ip;
+        }
+        for (int r0 = j + 1; r0 < M; r0 += 64) {
+            const int i = r0 + lane;
+            if (i >= M) break;
+            const double l = W[i + (int64_t)j * ldw] * inv;
+#pragma unroll 4
+            for (int c = j + 1 + wv; c < M; c += nw)
+                W[i + (int64_t)c * ldw] = fma(-l, W[j + (int64_t)c * ldw], W[i + (int64_t)c * ldw]);
         }
         __syncthreads();
     }
     return true;
 }
 
-// out = L^{-1}, L = unit lower triangle of W.  One column of the inverse per thread.
-__device__ inline void wg_trinv_lower_unit(const double* W, int M, int ldw, double* out, int ldo) {
-    for (int c = threadIdx.x; c < M; c += blockDim.x) {
-        double* x = out + (int64_t)c * ldo;
-        for (int i = 0; i < c; ++i) x[i] = 0.0;
-        x[c] = 1.0;
-        for (int i = c + 1; i < M; ++i) {
-            double s = 0.0;
-            for (int j = c; j < i; ++j) s = fma(W[i + (int64_t)j * ldw], x[j], s);
-            x[i] = -s;
+// ------------------------------------------------------- triangular inverses
+// One wave computes two columns (c0, c1) of the inverse by substitution in
+// its registers: row i = 64 s + lane lives in slot s.  The two columns share
+// the loads of the triangle and give the wave two independent chains.
+
+// Triangle columns are read U at a time, double buffered: the loads of the
+// next group are in flight while the current group is applied.
+template <int NS>
+struct TriBuf {
+    static constexpr int U = NS <= 2 ? 4 : (NS <= 4 ? 2 : 1);
+    double v[U][NS];
+    double d[U];  // reciprocals of the diagonal entries (upper triangle only)
+};
+
+// Columns of L^{-1}, L = unit lower triangle of W.
+template <int NS, class PW, class PO>
+__device__ inline void wave_inv_lower_unit(PW W, int M, int ldw, int c0, int c1, PO out, int ldo) {
+    constexpr int U = TriBuf<NS>::U;
+    const int lane = threadIdx.x & 63;
+    double x[NS], y[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        x[s] = (s * 64 + lane == c0) ? 1.0 : 0.0;
+        y[s] = (s * 64 + lane == c1) ? 1.0 : 0.0;
+    }
+#pragma unroll
+    for (int sb = 0; sb < NS; ++sb) {
+        const int j0 = max(c0, sb * 64), j1 = min(M, sb * 64 + 64);
+        // entries L[i, jj] below the diagonal of columns jj in [j, j + U)
+        auto load = [&](TriBuf<NS>& b, int j) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int jj = j + u;
+                auto colj = W + (int64_t)min(jj, M - 1) * ldw;
+#pragma unroll
+                for (int s = sb; s < NS; ++s) {
+                    const int i = s * 64 + lane;
+                    b.v[u][s] = (jj < j1 && i > jj && i < M) ? colj[i] : 0.0;
+                }
+            }
+        };
+        auto apply = [&](const TriBuf<NS>& b, int j) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int jj = j + u;
+                if (jj < j1) {
+                    const double xj = readlane_d(x[sb], jj - sb * 64);
+                    const double yj = readlane_d(y[sb], jj - sb * 64);
+#pragma unroll
+                    for (int s = sb; s < NS; ++s) {
+                        x[s] = fma(-b.v[u][s], xj, x[s]);
+                        y[s] = fma(-b.v[u][s], yj, y[s]);
+                    }
+                }
+            }
+        };
+        TriBuf<NS> ba, bb;
+        if (j0 < j1) load(ba, j0);
+        for (int j = j0; j < j1; j += 2 * U) {
+            if (j + U < j1) load(bb, j + U);
+            apply(ba, j);
+            if (j + U < j1) {
+                if (j + 2 * U < j1) load(ba, j + 2 * U);
+                apply(bb, j + U);
+            }
         }
+    }
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int i = s * 64 + lane;
+        if (i < M) {
+            out[i + (int64_t)c0 * ldo] = x[s];
+            if (c1 < M) out[i + (int64_t)c1 * ldo] = y[s];
+        }
+    }
+}
+
+// Columns of U^{-1}, U = upper triangle of W (with its diagonal); c0 < c1.
+template <int NS, class PW, class PO>
+__device__ inline void wave_inv_upper(PW W, int M, int ldw, int c0, int c1, PO out, int ldo) {
+    constexpr int U = TriBuf<NS>::U;
+    const int lane = threadIdx.x & 63;
+    const int ctop = c1 < M ? c1 : c0;
+    double x[NS], y[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        x[s] = (s * 64 + lane == c0) ? 1.0 : 0.0;
+        y[s] = (s * 64 + lane == c1) ? 1.0 : 0.0;
+    }
+#pragma unroll
+    for (int sb = NS - 1; sb >= 0; --sb) {
+        const int jt = min(ctop, sb * 64 + 63), jb = sb * 64;
+        // column jj (descending from j): entries above the diagonal, and the diagonal
+        auto load = [&](TriBuf<NS>& b, int j) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int jj = j - u;
+                auto colj = W + (int64_t)max(jj, 0) * ldw;
+                b.d[u] = (jj >= jb) ? 1.0 / colj[max(jj, 0)] : 1.0;  // reciprocal, off the chain
+#pragma unroll
+                for (int s = 0; s <= sb; ++s) {
+                    const int i = s * 64 + lane;
+                    b.v[u][s] = (jj >= jb && i < jj) ? colj[i] : 0.0;
+                }
+            }
+        };
+        auto apply = [&](const TriBuf<NS>& b, int j) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int jj = j - u;
+                if (jj >= jb) {
+                    const double xj = readlane_d(x[sb], jj - jb) * b.d[u];
+                    const double yj = readlane_d(y[sb], jj - jb) * b.d[u];
+                    if (lane == jj - jb) {
+                        x[sb] = xj;
+                        y[sb] = yj;
+                    }
+#pragma unroll
+                    for (int s = 0; s <= sb; ++s) {
+                        x[s] = fma(-b.v[u][s], xj, x[s]);
+                        y[s] = fma(-b.v[u][s], yj, y[s]);
+                    }
+                }
+            }
+        };
+        TriBuf<NS> ba, bb;
+        if (jt >= jb) load(ba, jt);
+        for (int j = jt; j >= jb; j -= 2 * U) {
+            if (j - U >= jb) load(bb, j - U);
+            apply(ba, j);
+            if (j - U >= jb) {
+                if (j - 2 * U >= jb) load(ba, j - 2 * U);
+                apply(bb, j - U);
+            }
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int i = s * 64 + lane;
+        if (i < M) {
+            out[i + (int64_t)c0 * ldo] = x[s];
+            if (c1 < M) out[i + (int64_t)c1 * ldo] = y[s];
+        }
+    }
+}
+
+template <bool UPPER, int NS, class PW, class PO>
+__device__ inline void wg_trinv_ns(PW W, int M, int ldw, PO out, int ldo) {
+    const int wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int c = wv; c < M; c += 2 * nw) {
+        if (UPPER)
+            wave_inv_upper<NS, PW, PO>(W, M, ldw, c, c + nw, out, ldo);
+        else
+            wave_inv_lower_unit<NS, PW, PO>(W, M, ldw, c, c + nw, out, ldo);
+    }
+}
+
+template <bool UPPER, class PW, class PO>
+__device__ inline void wg_trinv(PW W, int M, int ldw, PO out, int ldo) {
+    switch ((M + 63) >> 6) {
+        case 0: break;
+        case 1: wg_trinv_ns<UPPER, 1, PW, PO>(W, M, ldw, out, ldo); break;
+        case 2: wg_trinv_ns<UPPER, 2, PW, PO>(W, M, ldw, out, ldo); break;
+        case 3: wg_trinv_ns<UPPER, 3, PW, PO>(W, M, ldw, out, ldo); break;
+        case 4: wg_trinv_ns<UPPER, 4, PW, PO>(W, M, ldw, out, ldo); break;
+        case 5: wg_trinv_ns<UPPER, 5, PW, PO>(W, M, ldw, out, ldo); break;
+        case 6: wg_trinv_ns<UPPER, 6, PW, PO>(W, M, ldw, out, ldo); break;
+        case 7: wg_trinv_ns<UPPER, 7, PW, PO>(W, M, ldw, out, ldo); break;
+        default: wg_trinv_ns<UPPER, 8, PW, PO>(W, M, ldw, out, ldo); break;
     }
     __syncthreads();
 }
 
+// out = L^{-1}, L = unit lower triangle of W.
+template <class PW, class PO>
+__device__ inline void wg_trinv_lower_unit(PW W, int M, int ldw, PO out, int ldo) {
+    wg_trinv<false, PW, PO>(W, M, ldw, out, ldo);
+}
 // out = U^{-1}, U = upper triangle of W (with diagonal).
-__device__ inline void wg_trinv_upper(const double* W, int M, int ldw, double* out, int ldo) {
-    for (int c = threadIdx.x; c < M; c += blockDim.x) {
-        double* x = out + (int64_t)c * ldo;
-        for (int i = c + 1; i < M; ++i) x[i] = 0.0;
-        for (int i = c; i >= 0; --i) {
-            double s = (i == c) ? 1.0 : 0.0;
-            for (int j = i + 1; j <= c; ++j) s = fma(-W[i + (int64_t)j * ldw], x[j], s);
-            x[i] = s / W[i + (int64_t)i * ldw];
-        }
-    }
-    __syncthreads();
+template <class PW, class PO>
+__device__ inline void wg_trinv_upper(PW W, int M, int ldw, PO out, int ldo) {
+    wg_trinv<true, PW, PO>(W, M, ldw, out, ldo);
 }
 
 // ----------------------------------------------------------- Householder QR
-// In place QR of A (M x K, K <= M) with reflectors H_j = I - tau_j v_j v_j^T,
-// v_j(0) = 1, beta_j = -sign(alpha) ||x|| (LAPACK larfg convention, tau = 0
-// when the part below the diagonal is zero).  R on and above the diagonal,
-// v below it; tau in tau_sh (shared, K entries).
-__device__ inline void wg_house_qr(double* A, int M, int K, int lda, double* tau_sh, double* red) {
-    const int tid = threadIdx.x;
-    for (int j = 0; j < K; ++j) {
-        double part = 0.0;
-        for (int i = j + 1 + tid; i < M; i += blockDim.x) {
-            double v = A[i + (int64_t)j * lda];
+// Reflector of column jj of A (rows jj..M-1) by one wave, LAPACK larfg
+// convention: H = I - tau v v^T, v(jj) = 1, beta = -sign(alpha) ||x||, tau = 0
+// when the part below the diagonal is zero.  Lane l handles rows jj + l + 64 t
+// (the mapping of the trailing update, so every lane reads what it wrote).
+template <class PA, class PT>
+__device__ inline void wave_reflector(PA A, int M, int jj, int lda, PT tau_sh) {
+    const int lane = threadIdx.x & 63;
+    auto col = A + (int64_t)jj * lda;
+    double part = 0.0, alpha = 0.0;
+    for (int i = jj + lane; i < M; i += 64) {
+        const double v = col[i];
+        if (i == jj)
+            alpha = v;
+        else
             part = fma(v, v, part);
-        }
-        const double xn2 = block_sum(part, red);
-        const double alpha = A[j + (int64_t)j * lda];
-        double tau = 0.0, beta = alpha, scale = 0.0;
-        if (xn2 != 0.0) {
-            const double nrm = hypot(alpha, sqrt(xn2));
-            beta = (alpha >= 0.0) ? -nrm : nrm;
-            tau = (beta - alpha) / beta;
-            scale = 1.0 / (alpha - beta);
-        }
-        __syncthreads();
-        if (xn2 != 0.0)
-            for (int i = j + 1 + tid; i < M; i += blockDim.x) A[i + (int64_t)j * lda] *= scale;
-        if (tid == 0) tau_sh[j] = tau;
-        __syncthreads();
-        if (tid == 0) A[j + (int64_t)j * lda] = beta;
-        // apply H_j to the trailing columns: one column per thread
-        if (tau != 0.0)
-            for (int c = j + 1 + tid; c < K; c += blockDim.x) {
-                double* col = A + (int64_t)c * lda;
-                const double* v = A + (int64_t)j * lda;
-                double w = col[j];
-                for (int i = j + 1; i < M; ++i) w = fma(v[i], col[i], w);
-                w *= tau;
-                col[j] -= w;
-                for (int i = j + 1; i < M; ++i) col[i] = fma(-w, v[i], col[i]);
+    }
+    const double xn2 = wave_sum(part);
+    alpha = readlane_d(alpha, 0);
+    double tau = 0.0, beta = alpha;
+    if (xn2 != 0.0) {
+        const double nrm = hypot(alpha, sqrt(xn2));
+        beta = (alpha >= 0.0) ? -nrm : nrm;
+        tau = (beta - alpha) / beta;
+        const double scale = 1.0 / (alpha - beta);
+        for (int i = jj + lane; i < M; i += 64)
+            if (i > jj) col[i] *= scale;
+    }
+    if (lane == 0) {
+        col[jj] = beta;
+        tau_sh[jj] = tau;
+    }
+}
+
+// In place QR of A (M x K, K <= M, ld lda): R on and above the diagonal,
+// reflectors below it, tau in tau_sh (shared, K entries).  The trailing update
+// of step j gives one column per wave (lanes over rows); the wave that updates
+// column j + 1 then forms its reflector, so each step needs one barrier.
+template <class PA, class PT>
+__device__ inline void wg_house_qr(PA A, int M, int K, int lda, PT tau_sh) {
+    const int wv = threadIdx.x >> 6, nw = blockDim.x >> 6, lane = threadIdx.x & 63;
+    __syncthreads();
+    if (K > 0 && wv == 0) wave_reflector(A, M, 0, lda, tau_sh);
+    __syncthreads();
+    for (int j = 0; j < K; ++j) {
+        const double tau = tau_sh[j];
+        auto v = A + (int64_t)j * lda;
+        for (int c = j + 1 + wv; c < K; c += nw) {
+            if (tau != 0.0) {
+                auto col = A + (int64_t)c * lda;
+                double part = 0.0;
+                for (int i = j + 1 + lane; i < M; i += 64) part = fma(v[i], col[i], part);
+                const double cj = col[j];
+                const double w = tau * (cj + wave_sum(part));
+                if (lane == 0) col[j] = cj - w;
+                for (int i = j + 1 + lane; i < M; i += 64) col[i] = fma(-w, v[i], col[i]);
             }
+            if (c == j + 1) wave_reflector(A, M, j + 1, lda, tau_sh);
+        }
         __syncthreads();
     }
 }
 
-// Q columns [c0, c0 + nq) of Q = H_0 H_1 ... H_{K-1} (M x M) from the
-// reflectors left in A by wg_house_qr; written to Q (ld ldq), one column per thread.
-__device__ inline void wg_house_form_q(const double* A, int M, int K, int lda, const double* tau_sh, int c0, int nq,
-                                       double* Q, int ldq) {
-    for (int c = threadIdx.x; c < nq; c += blockDim.x) {
-        double* q = Q + (int64_t)c * ldq;
-        for (int i = 0; i < M; ++i) q[i] = (i == c0 + c) ? 1.0 : 0.0;
-        for (int j = K - 1; j >= 0; --j) {
+// Columns [c0, c0 + nq) of Q = H_0 H_1 ... H_{K-1} (M x M) from the reflectors
+// left in A by wg_house_qr, into Q (ld ldq).  With flip, column c < K is
+// negated where R_cc < 0 (the orthonormal factor with a positive diagonal).
+// One wave per pair of columns (the second one only with hb), in registers;
+// no barriers inside.
+template <int NS, class PA, class PT, class PQ>
+__device__ inline void wave_form_q(PA A, int M, int K, int lda, PT tau_sh, int ca, int cb, bool hb, bool flip, PQ Qa,
+                                   PQ Qb) {
+    const int lane = threadIdx.x & 63;
+    double x[NS], y[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        x[s] = (s * 64 + lane == ca) ? 1.0 : 0.0;
+        y[s] = (hb && s * 64 + lane == cb) ? 1.0 : 0.0;
+    }
+#pragma unroll
+    for (int sb = NS - 1; sb >= 0; --sb) {
+        const int jt = min(K - 1, sb * 64 + 63);
+        for (int j = jt; j >= sb * 64; --j) {
             const double tau = tau_sh[j];
             if (tau == 0.0) continue;
-            const double* v = A + (int64_t)j * lda;
-            double w = q[j];
-            for (int i = j + 1; i < M; ++i) w = fma(v[i], q[i], w);
-            w *= tau;
-            q[j] -= w;
-            for (int i = j + 1; i < M; ++i) q[i] = fma(-w, v[i], q[i]);
+            auto v = A + (int64_t)j * lda;
+            double px = 0.0, py = 0.0;
+#pragma unroll
+            for (int s = sb; s < NS; ++s) {
+                const int i = s * 64 + lane;
+                if (i > j && i < M) {
+                    const double vi = v[i];
+                    px = fma(vi, x[s], px);
+                    py = fma(vi, y[s], py);
+                }
+            }
+            const double wx = tau * (readlane_d(x[sb], j - sb * 64) + wave_sum(px));
+            const double wy = tau * (readlane_d(y[sb], j - sb * 64) + wave_sum(py));
+            if (lane == j - sb * 64) {
+                x[sb] -= wx;
+                y[sb] -= wy;
+            }
+#pragma unroll
+            for (int s = sb; s < NS; ++s) {
+                const int i = s * 64 + lane;
+                if (i > j && i < M) {
+                    const double vi = v[i];
+                    x[s] = fma(-wx, vi, x[s]);
+                    y[s] = fma(-wy, vi, y[s]);
+                }
+            }
         }
+    }
+    const double sa = (flip && ca < K && A[ca + (int64_t)ca * lda] < 0.0) ? -1.0 : 1.0;
+    const double sbn = (hb && flip && cb < K && A[cb + (int64_t)cb * lda] < 0.0) ? -1.0 : 1.0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int i = s * 64 + lane;
+        if (i < M) {
+            Qa[i] = sa * x[s];
+            if (hb) Qb[i] = sbn * y[s];
+        }
+    }
+}
+
+template <int NS, class PA, class PT, class PQ>
+__device__ inline void wg_form_q_ns(PA A, int M, int K, int lda, PT tau_sh, int c0, int nq, bool flip, PQ Q, int ldq) {
+    const int wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int c = wv; c < nq; c += 2 * nw) {
+        const int c2 = c + nw;
+        const bool hb = c2 < nq;
+        wave_form_q<NS, PA, PT, PQ>(A, M, K, lda, tau_sh, c0 + c, c0 + c2, hb, flip, Q + (int64_t)c * ldq,
+                                    Q + (int64_t)(hb ? c2 : c) * ldq);
+    }
+}
+
+template <class PA, class PT, class PQ>
+__device__ inline void wg_house_form_q(PA A, int M, int K, int lda, PT tau_sh, int c0, int nq, PQ Q, int ldq,
+                                       bool flip = false) {
+    switch ((M + 63) >> 6) {
+        case 0: break;
+        case 1: wg_form_q_ns<1, PA, PT, PQ>(A, M, K, lda, tau_sh, c0, nq, flip, Q, ldq); break;
+        case 2: wg_form_q_ns<2, PA, PT, PQ>(A, M, K, lda, tau_sh, c0, nq, flip, Q, ldq); break;
+        case 3: wg_form_q_ns<3, PA, PT, PQ>(A, M, K, lda, tau_sh, c0, nq, flip, Q, ldq); break;
+        case 4: wg_form_q_ns<4, PA, PT, PQ>(A, M, K, lda, tau_sh, c0, nq, flip, Q, ldq); break;
+        case 5: wg_form_q_ns<5, PA, PT, PQ>(A, M, K, lda, tau_sh, c0, nq, flip, Q, ldq); break;
+        case 6: wg_form_q_ns<6, PA, PT, PQ>(A, M, K, lda, tau_sh, c0, nq, flip, Q, ldq); break;
+        case 7: wg_form_q_ns<7, PA, PT, PQ>(A, M, K, lda, tau_sh, c0, nq, flip, Q, ldq); break;
+        default: wg_form_q_ns<8, PA, PT, PQ>(A, M, K, lda, tau_sh, c0, nq, flip, Q, ldq); break;
     }
     __syncthreads();
 }

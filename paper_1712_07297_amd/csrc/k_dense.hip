@@ -44,16 +44,17 @@ __global__ void k_dense_assemble(const int* __restrict__ pat_ptr, const int* __r
 // and L11^{-1}, U11^{-1} (nb x nb, ld DNB) to inv.
 __global__ void __launch_bounds__(WG) k_dense_diag(double* __restrict__ D, int64_t ldd, int p, int nb,
                                                    double* __restrict__ inv, int* __restrict__ flag) {
-    extern __shared__ double W[];  // nb x nb
-    __shared__ int fl;
+    extern __shared__ double Wd[];  // nb x nb
+    lds_f64* W = to_lds(Wd);
     double* dp = D + p + (int64_t)p * ldd;
     wg_copy(nb, nb, dp, (int)ldd, W, nb);
     __syncthreads();
-    if (!wg_lu_nopiv(W, nb, nb, &fl)) {
+    if (!wg_lu_nopiv(W, nb, nb)) {
         if (threadIdx.x == 0) *flag = 1;
         return;
     }
     wg_copy(nb, nb, W, nb, dp, (int)ldd);
+    __syncthreads();
     wg_trinv_lower_unit(W, nb, nb, inv, DNB);
     wg_trinv_upper(W, nb, nb, inv + DNB * DNB, DNB);
 }
@@ -73,20 +74,24 @@ __global__ void __launch_bounds__(WG) k_dense_panels(double* __restrict__ D, int
     // reads the whole panel it overwrites
     v4d acc[2][2][2];
     const int halves = (nb + MT - 1) / MT;
-    for (int h = 0; h < halves; ++h) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        if (h >= halves) break;
         const int hh = h * MT, hw = min(MT, nb - hh);
         if (colpanel)
             mfma_tile64(
                 nb, [&](int r, int k) { return (r < hw) ? Linv[(hh + r) + (int64_t)k * DNB] : 0.0; },
-                [&](int k, int c) { return (q0 + c < N) ? D[(p + k) + (int64_t)(q0 + c) * ldd] : 0.0; }, &sm,
+                [&](int k, int c) { return (q0 + c < N) ? D[(p + k) + (int64_t)(q0 + c) * ldd] : 0.0; }, to_lds(&sm),
                 acc[h]);
         else
             mfma_tile64(
                 nb, [&](int r, int k) { return (q0 + r < N) ? D[(q0 + r) + (int64_t)(p + k) * ldd] : 0.0; },
-                [&](int k, int c) { return (c < hw) ? Uinv[k + (int64_t)(hh + c) * DNB] : 0.0; }, &sm, acc[h]);
+                [&](int k, int c) { return (c < hw) ? Uinv[k + (int64_t)(hh + c) * DNB] : 0.0; }, to_lds(&sm), acc[h]);
     }
     __syncthreads();
-    for (int h = 0; h < halves; ++h) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        if (h >= halves) break;
         const int hh = h * MT, hw = min(MT, nb - hh);
         if (colpanel)
             mfma_tile64_store(acc[h], [&](int r, int c, double v) {
@@ -110,7 +115,7 @@ __global__ void __launch_bounds__(WG) k_dense_trailing(double* __restrict__ D, i
     v4d acc[2][2];
     mfma_tile64(
         nb, [&](int r, int k) { return (r0 + r < N) ? D[(r0 + r) + (int64_t)(p + k) * ldd] : 0.0; },
-        [&](int k, int c) { return (c0 + c < N) ? D[(p + k) + (int64_t)(c0 + c) * ldd] : 0.0; }, &sm, acc);
+        [&](int k, int c) { return (c0 + c < N) ? D[(p + k) + (int64_t)(c0 + c) * ldd] : 0.0; }, to_lds(&sm), acc);
     mfma_tile64_store(acc, [&](int r, int c, double v) {
         if (r0 + r < N && c0 + c < N) D[(r0 + r) + (int64_t)(c0 + c) * ldd] -= v;
     });

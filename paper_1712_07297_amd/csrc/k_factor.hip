@@ -49,6 +49,10 @@ __device__ inline int find_cluster64(const int64_t* pre, int n, int64_t q) {
 
 // ============================================================== Gram partials
 
+// G_split = sum over the split's fill partners t of B(s,t) B(s,t)^T (and, for
+// a general matrix, + B(t,s)^T B(t,s)): the Gram matrix F F^T of the fill
+// (Eq. lra) in gram_splits partial sums.  Each 64 x 64 tile of the partial is
+// accumulated over all partners of the split in registers and stored once.
 __global__ void __launch_bounds__(WG) k_gram(LevelDev L, const int* __restrict__ clist) {
     __shared__ GemmSmem sm;
     const int s = clist[blockIdx.y];
@@ -56,22 +60,34 @@ __global__ void __launch_bounds__(WG) k_gram(LevelDev L, const int* __restrict__
     const int M = L.m[s];
     if (M == 0) return;
     double* Gp = L.ws + L.ws_off[s] + (int64_t)(WS_GP + split) * M * M;
-    wg_zero(M, M, Gp, M);
-    __syncthreads();
     const int f0 = L.fill_ptr[s], nf = L.fill_ptr[s + 1] - f0;
     const int chunk = (nf + L.gram_splits - 1) / L.gram_splits;
     const int e0 = f0 + split * chunk, e1 = min(f0 + nf, e0 + chunk);
-    for (int e = e0; e < e1; ++e) {
-        const int t = L.fill_id[e];
-        const int ct = cur_size(L, t, L.fill_before[e]);
-        if (ct == 0) continue;
-        const double* Bst = blk_ptr(L, L.fill_bst[e]);
-        wg_gemm<false, true>(M, M, ct, 1.0, Bst, M, Bst, M, 1.0, Gp, M, &sm);
-        if (!L.symmetric) {
-            const double* Bts = blk_ptr(L, L.fill_bts[e]);
-            wg_gemm<true, false>(M, M, ct, 1.0, Bts, L.m[t], Bts, L.m[t], 1.0, Gp, M, &sm);
+    lds_smem* sm_l = to_lds(&sm);
+    for (int r0 = 0; r0 < M; r0 += MT)
+        for (int c0 = 0; c0 < M; c0 += MT) {
+            v4d acc[2][2];
+            mfma_zero(acc);
+            for (int e = e0; e < e1; ++e) {
+                const int t = L.fill_id[e];
+                const int ct = cur_size(L, t, L.fill_before[e]);
+                if (ct == 0) continue;
+                const double* Bst = blk_ptr(L, L.fill_bst[e]);  // M x ct, ld M
+                mfma_tile64_acc(
+                    ct, [&](int r, int k) { return r0 + r < M ? Bst[(r0 + r) + (int64_t)k * M] : 0.0; },
+                    [&](int k, int c) { return c0 + c < M ? Bst[(c0 + c) + (int64_t)k * M] : 0.0; }, sm_l, acc);
+                if (!L.symmetric) {
+                    const int mt = L.m[t];
+                    const double* Bts = blk_ptr(L, L.fill_bts[e]);  // ct x M, ld m_t
+                    mfma_tile64_acc(
+                        ct, [&](int r, int k) { return r0 + r < M ? Bts[k + (int64_t)(r0 + r) * mt] : 0.0; },
+                        [&](int k, int c) { return c0 + c < M ? Bts[k + (int64_t)(c0 + c) * mt] : 0.0; }, sm_l, acc);
+                }
+            }
+            mfma_tile64_store(acc, [&](int r, int c, double v) {
+                if (r0 + r < M && c0 + c < M) Gp[(r0 + r) + (int64_t)(c0 + c) * M] = v;
+            });
         }
-    }
 }
 
 void launch_gram(const LevelDev& L, const ColourDev& C, hipStream_t st) {
@@ -87,10 +103,11 @@ void launch_gram(const LevelDev& L, const ColourDev& C, hipStream_t st) {
 // physically; stop at the first chosen pivot d_j <= eps^2 d_0 (that is
 // |R_jj| <= eps |R_11|) or at fixed_rank.  On return the first k columns of W
 // hold the factor in the exchanged order and perm[i] is the unknown at
-// position i.
-__device__ int wg_pivoted_cholesky(double* W, int M, double eps, int fixed_rank, int* perm, double* d, double* red,
-                                   int* ired) {
-    const int tid = threadIdx.x;
+// position i.  The pivot search runs on one wave; the trailing update forms
+// the scaled column on the fly and stores it after the update.
+template <class PW, class PI, class PD>
+__device__ int wg_pivoted_cholesky(PW W, int M, double eps, int fixed_rank, PI perm, PD d, PI isc) {
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
     for (int i = tid; i < M; i += blockDim.x) {
         perm[i] = i;
         d[i] = W[i + (int64_t)i * M];
@@ -99,39 +116,44 @@ __device__ int wg_pivoted_cholesky(double* W, int M, double eps, int fixed_rank,
     double d0 = 0.0;
     int kk = 0;
     for (int j = 0; j < M; ++j) {
-        double mx = -1.0;
-        for (int i = j + tid; i < M; i += blockDim.x) mx = fmax(mx, d[i]);
-        mx = block_max(mx, red);
-        if (!(mx > 0.0)) break;
-        const double thr = (1.0 - 1e-10) * mx;
-        int cand = M;
-        for (int i = j + tid; i < M; i += blockDim.x)
-            if (d[i] >= thr) {
-                cand = i;
-                break;
-            }
-        const int p = block_min_int(cand, ired);
+        if (wv == 0) {
+            double mx = -1.0;
+            for (int i = j + lane; i < M; i += 64) mx = fmax(mx, d[i]);
+            mx = wave_max(mx);
+            const double thr = (1.0 - 1e-10) * mx;
+            int cand = M;
+            for (int i = j + lane; i < M; i += 64)
+                if (d[i] >= thr) {
+                    cand = i;
+                    break;
+                }
+            cand = wave_min_int(cand);
+            if (lane == 0) isc[0] = (mx > 0.0) ? cand : -1;
+        }
+        __syncthreads();
+        const int p = isc[0];
+        if (p < 0) break;
         const double dj = d[p];
         if (j == 0) d0 = dj;
         if (dj <= eps * eps * d0) break;
         if (fixed_rank > 0 && j >= fixed_rank) break;
         if (p != j) {
             for (int c = tid; c < M; c += blockDim.x) {
-                double t = W[j + (int64_t)c * M];
+                const double t = W[j + (int64_t)c * M];
                 W[j + (int64_t)c * M] = W[p + (int64_t)c * M];
                 W[p + (int64_t)c * M] = t;
             }
             __syncthreads();
             for (int r = tid; r < M; r += blockDim.x) {
-                double t = W[r + (int64_t)j * M];
+                const double t = W[r + (int64_t)j * M];
                 W[r + (int64_t)j * M] = W[r + (int64_t)p * M];
                 W[r + (int64_t)p * M] = t;
             }
             if (tid == 0) {
-                int ti = perm[j];
+                const int ti = perm[j];
                 perm[j] = perm[p];
                 perm[p] = ti;
-                double td = d[j];
+                const double td = d[j];
                 d[j] = d[p];
                 d[p] = td;
             }
@@ -139,16 +161,19 @@ __device__ int wg_pivoted_cholesky(double* W, int M, double eps, int fixed_rank,
         }
         const double ljj = sqrt(W[j + (int64_t)j * M]);
         const double inv = 1.0 / ljj;
-        for (int i = j + 1 + tid; i < M; i += blockDim.x) W[i + (int64_t)j * M] *= inv;
-        __syncthreads();
-        if (tid == 0) W[j + (int64_t)j * M] = ljj;
-        const int n = M - j - 1;
-        for (int64_t e = tid; e < (int64_t)n * n; e += blockDim.x) {
-            int i = j + 1 + (int)(e % n), c = j + 1 + (int)(e / n);
-            W[i + (int64_t)c * M] -= W[i + (int64_t)j * M] * W[c + (int64_t)j * M];
+        for (int r0 = j + 1; r0 < M; r0 += 64) {
+            const int i = r0 + lane;
+            if (i >= M) break;
+            const double li = W[i + (int64_t)j * M] * inv;
+            for (int c = j + 1 + wv; c < M; c += nw)
+                W[i + (int64_t)c * M] = fma(-li, W[c + (int64_t)j * M] * inv, W[i + (int64_t)c * M]);
         }
         __syncthreads();
-        for (int i = j + 1 + tid; i < M; i += blockDim.x) d[i] = W[i + (int64_t)i * M];
+        for (int i = j + 1 + tid; i < M; i += blockDim.x) {
+            W[i + (int64_t)j * M] *= inv;
+            d[i] = W[i + (int64_t)i * M];
+        }
+        if (tid == 0) W[j + (int64_t)j * M] = ljj;
         kk = j + 1;
         __syncthreads();
     }
@@ -156,21 +181,26 @@ __device__ int wg_pivoted_cholesky(double* W, int M, double eps, int fixed_rank,
     return kk;
 }
 
-// Householder complement: Q columns [K, M) of the QR of X (M x K) into V
-// (ld ldv).  A is an M x K scratch copy destroyed here.
-__device__ void wg_complement(double* A, int M, int K, double* V, int ldv, double* tau_sh, double* red) {
-    wg_house_qr(A, M, K, M, tau_sh, red);
-    wg_house_form_q(A, M, K, M, tau_sh, K, M - K, V, ldv);
+// Householder complement: Q columns [K, M) of the QR of X (M x K, ld M) into
+// V (ld ldv).  X is destroyed.
+template <class PX, class PV, class PT>
+__device__ void wg_complement(PX X, int M, int K, PV V, int ldv, PT tau_sh) {
+    wg_house_qr(X, M, K, M, tau_sh);
+    wg_house_form_q(X, M, K, M, tau_sh, K, M - K, V, ldv);
 }
 
-__global__ void __launch_bounds__(WG) k_pivot(LevelDev L, const int* __restrict__ clist, int lds_m) {
-    extern __shared__ double dyn[];  // lds_m * lds_m doubles
+// Per-cluster elimination operators.  The working M x M matrix W lives in
+// LDS when the colour's largest cluster fits (lds_m), else in the cluster's
+// L2-resident workspace; every dense step below reuses it in turn.
+template <bool INLDS>
+__global__ void __launch_bounds__(WG) k_pivot(LevelDev L, const int* __restrict__ clist) {
+    extern __shared__ double dyn[];  // M * M doubles for the largest cluster M of the colour (INLDS)
     __shared__ GemmSmem sm;
     __shared__ double red[16];
-    __shared__ int ired[16];
-    __shared__ int flag_sh;
+    __shared__ int isc[4];
     __shared__ int perm[MAX_M];
     __shared__ double dsh[MAX_M];
+    __shared__ int fcols_sh;
 
     const int s = clist[blockIdx.x];
     const int tid = threadIdx.x;
@@ -178,7 +208,6 @@ __global__ void __launch_bounds__(WG) k_pivot(LevelDev L, const int* __restrict_
 
     // packed offsets of the current neighbour sizes inside E_L / E_R, and the
     // number of fill columns
-    __shared__ int fcols_sh;
     if (tid == 0) {
         int off = 0;
         for (int e = L.nbr_ptr[s]; e < L.nbr_ptr[s + 1]; ++e) {
@@ -208,35 +237,29 @@ __global__ void __launch_bounds__(WG) k_pivot(LevelDev L, const int* __restrict_
     double* TR = ws + WS_TR * MM;
     double* CU = ws + WS_CU * MM;
     double* UC = ws + WS_UC * MM;
-    double* W = (M <= lds_m) ? dyn : ws + WS_SCR * MM;
+    auto W = [&] {
+        if constexpr (INLDS)
+            return to_lds(dyn);
+        else
+            return ws + WS_SCR * MM;
+    }();
+    lds_f64* red_l = to_lds(red);
+    lds_f64* dsh_l = to_lds(dsh);
+    lds_smem* sm_l = to_lds(&sm);
     double* TLp = L.rec + L.rec_off[s];
     double* TRp = TLp + MM;
     double* Bss = blk_ptr(L, L.diag_blk[s]);
 
-    // ---- 1. A_ss = L U (no pivoting), explicit inverses
-    wg_copy(M, M, Bss, M, W, M);
-    __syncthreads();
-    double ass2 = 0.0;  // ||A_ss||_F^2 (noise floor of the fill)
-    for (int64_t e = tid; e < MM; e += blockDim.x) ass2 = fma(W[e], W[e], ass2);
-    ass2 = block_sum(ass2, red);
-    if (!wg_lu_nopiv(W, M, M, &flag_sh)) {
-        if (tid == 0) {
-            L.flag[s] = 1;
-            L.k[s] = M;  // leave the cluster untouched
-        }
-        return;
-    }
-    wg_trinv_lower_unit(W, M, M, Linv, M);
-    wg_trinv_upper(W, M, M, Uinv, M);
-    wg_gemm<false, false>(M, M, M, 1.0, Uinv, M, Linv, M, 0.0, Ainv, M, &sm);
-
-    // ---- 2. rank of the fill (Eq. lra)
+    // ---- 1. rank of the fill (Eq. lra)
     int kk;
     if (fcols_sh == 0) {
         kk = 0;
     } else if (L.eps == 0.0) {
         kk = M;  // exact mode
     } else {
+        double ass2 = 0.0;  // ||A_ss||_F^2 (noise floor of the fill)
+        for (int64_t e = tid; e < MM; e += blockDim.x) ass2 = fma(Bss[e], Bss[e], ass2);
+        ass2 = block_sum(ass2, red_l);
         // W = sum of the Gram partials
         for (int64_t e = tid; e < MM; e += blockDim.x) {
             double g = 0.0;
@@ -247,55 +270,65 @@ __global__ void __launch_bounds__(WG) k_pivot(LevelDev L, const int* __restrict_
         // fill at the rounding level of A_ss is noise: treat it as zero
         double dmax = 0.0;
         for (int i = tid; i < M; i += blockDim.x) dmax = fmax(dmax, W[i + (int64_t)i * M]);
-        dmax = block_max(dmax, red);
+        dmax = block_max(dmax, red_l);
         if (dmax <= FILL_NOISE_FLOOR * FILL_NOISE_FLOOR * ass2)
             kk = 0;
         else
-            kk = wg_pivoted_cholesky(W, M, L.eps, L.fixed_rank, perm, dsh, red, ired);
+            kk = wg_pivoted_cholesky(W, M, L.eps, L.fixed_rank, to_lds(perm), dsh_l, to_lds(isc));
         if (kk > 0 && kk < M) {
-            // P R_k^T in the unknowns' order, then its orthonormal factor U
-            for (int64_t e = tid; e < (int64_t)M * kk; e += blockDim.x) {
-                int i = (int)(e % M), j = (int)(e / M);
-                X[perm[i] + (int64_t)j * M] = (i >= j) ? W[i + (int64_t)j * M] : 0.0;
-            }
+            // P R_k^T in the unknowns' order (through X), then its orthonormal
+            // factor U with a positive diagonal
+            const int lane = tid & 63, nw = blockDim.x >> 6;
+            for (int j = tid >> 6; j < kk; j += nw)
+                for (int i = lane; i < M; i += 64) X[perm[i] + (int64_t)j * M] = (i >= j) ? W[i + (int64_t)j * M] : 0.0;
             __syncthreads();
-            wg_house_qr(X, M, kk, M, dsh, red);
-            wg_house_form_q(X, M, kk, M, dsh, 0, kk, Umat, M);
-            for (int j = tid; j < kk; j += blockDim.x)
-                if (X[j + (int64_t)j * M] < 0.0)
-                    for (int i = 0; i < M; ++i) Umat[i + (int64_t)j * M] = -Umat[i + (int64_t)j * M];
-            __syncthreads();
+            wg_copy(M, kk, X, M, W, M);
+            wg_house_qr(W, M, kk, M, dsh_l);
+            wg_house_form_q(W, M, kk, M, dsh_l, 0, kk, Umat, M, true);
         }
     }
     if (tid == 0) L.k[s] = kk;
     if (kk == M) return;  // nothing eliminated
-    if (kk == 0) {
-        wg_copy(M, M, Linv, M, TLp, M);
-        wg_copy(M, M, Uinv, M, TRp, M);
+
+    // ---- 2. A_ss = L U (no pivoting) and its inverse factors
+    wg_copy(M, M, Bss, M, W, M);
+    if (!wg_lu_nopiv(W, M, M)) {
+        if (tid == 0) {
+            L.flag[s] = 1;
+            L.k[s] = M;  // leave the cluster untouched
+        }
         return;
     }
+    if (kk == 0) {  // E_s = I: one block LU step
+        wg_trinv_lower_unit(W, M, M, TLp, M);
+        wg_trinv_upper(W, M, M, TRp, M);
+        return;
+    }
+    wg_trinv_lower_unit(W, M, M, Linv, M);
+    wg_trinv_upper(W, M, M, Uinv, M);
+    wg_gemm<false, false>(M, M, M, 1.0, Uinv, M, Linv, M, 0.0, Ainv, M, sm_l);
     const int f = M - kk;
 
     // ---- 3. sparsification operator E_s (Eq. scaling)
-    // X = A^{-1} U; S_L = [V_L U] with V_L the complement of X
-    wg_gemm<false, false>(M, kk, M, 1.0, Ainv, M, Umat, M, 0.0, X, M, &sm);
-    wg_complement(X, M, kk, SL, M, dsh, red);
+    // S_L = [V_L U], V_L the complement of A^{-1} U
+    wg_gemm<false, false>(M, kk, M, 1.0, Ainv, M, Umat, M, 0.0, W, M, sm_l);
+    wg_complement(W, M, kk, SL, M, dsh_l);
     wg_copy(M, kk, Umat, M, SL + (int64_t)f * M, M);
     __syncthreads();
     if (L.symmetric) {
         wg_copy(M, M, SL, M, SR, M);
     } else {
-        wg_gemm<true, false>(M, kk, M, 1.0, Ainv, M, Umat, M, 0.0, X, M, &sm);  // A^{-T} U
-        wg_complement(X, M, kk, SR, M, dsh, red);
+        wg_gemm<true, false>(M, kk, M, 1.0, Ainv, M, Umat, M, 0.0, W, M, sm_l);  // A^{-T} U
+        wg_complement(W, M, kk, SR, M, dsh_l);
         wg_copy(M, kk, Umat, M, SR + (int64_t)f * M, M);
     }
     __syncthreads();
-    wg_gemm<true, false>(M, M, M, 1.0, SL, M, Ainv, M, 0.0, TL, M, &sm);   // T_L = S_L^T A^{-1}
-    wg_gemm<false, false>(M, M, M, 1.0, Ainv, M, SR, M, 0.0, TR, M, &sm);  // T_R = A^{-1} S_R
+    wg_gemm<true, false>(M, M, M, 1.0, SL, M, Ainv, M, 0.0, TL, M, sm_l);   // T_L = S_L^T A^{-1}
+    wg_gemm<false, false>(M, M, M, 1.0, Ainv, M, SR, M, 0.0, TR, M, sm_l);  // T_R = A^{-1} S_R
 
     // ---- 4. elimination operator G_s (Eq. elim): F_ff = T_L[:f] S_R[:, :f] = L_f U_f
-    wg_gemm<false, false>(f, f, M, 1.0, TL, M, SR, M, 0.0, W, M, &sm);
-    if (!wg_lu_nopiv(W, f, M, &flag_sh)) {
+    wg_gemm<false, false>(f, f, M, 1.0, TL, M, SR, M, 0.0, W, M, sm_l);
+    if (!wg_lu_nopiv(W, f, M)) {
         if (tid == 0) {
             L.flag[s] = 2;
             L.k[s] = M;
@@ -305,23 +338,26 @@ __global__ void __launch_bounds__(WG) k_pivot(LevelDev L, const int* __restrict_
     wg_trinv_lower_unit(W, f, M, Linv, M);
     wg_trinv_upper(W, f, M, Uinv, M);
     // T_L' = [L_f^{-1} T_L[:f, :]; T_L[f:, :]],  T_R' = [T_R[:, :f] U_f^{-1}, T_R[:, f:]]
-    wg_gemm<false, false>(f, M, f, 1.0, Linv, M, TL, M, 0.0, TLp, M, &sm);
+    wg_gemm<false, false>(f, M, f, 1.0, Linv, M, TL, M, 0.0, TLp, M, sm_l);
     wg_copy(kk, M, TL + f, M, TLp + f, M);
-    wg_gemm<false, false>(M, f, f, 1.0, TR, M, Uinv, M, 0.0, TRp, M, &sm);
+    wg_gemm<false, false>(M, f, f, 1.0, TR, M, Uinv, M, 0.0, TRp, M, sm_l);
     wg_copy(M, kk, TR + (int64_t)f * M, M, TRp + (int64_t)f * M, M);
 
     // ---- 5. coarse block C = U^T A^{-1} U = T_L[f:] S_R[:, f:] into (s, s); C U^T and U C
-    wg_gemm<false, false>(kk, kk, M, 1.0, TL + f, M, SR + (int64_t)f * M, M, 0.0, W, M, &sm);
+    wg_gemm<false, false>(kk, kk, M, 1.0, TL + f, M, SR + (int64_t)f * M, M, 0.0, W, M, sm_l);
     wg_copy(kk, kk, W, M, Bss, M);
-    wg_gemm<false, true>(kk, M, kk, 1.0, W, M, Umat, M, 0.0, CU, M, &sm);   // C U^T (k x m)
-    wg_gemm<false, false>(M, kk, kk, 1.0, Umat, M, W, M, 0.0, UC, M, &sm);  // U C (m x k)
+    wg_gemm<false, true>(kk, M, kk, 1.0, W, M, Umat, M, 0.0, CU, M, sm_l);   // C U^T (k x m)
+    wg_gemm<false, false>(M, kk, kk, 1.0, Umat, M, W, M, 0.0, UC, M, sm_l);  // U C (m x k)
 }
 
 void launch_pivot(const LevelDev& L, const ColourDev& C, hipStream_t st) {
     if (C.n == 0) return;
-    const int lds_m = C.max_m <= LDS_M ? C.max_m : 0;
-    const size_t shmem = (size_t)lds_m * lds_m * sizeof(double);
-    hipLaunchKernelGGL(k_pivot, dim3(C.n), dim3(WG), shmem, st, L, C.clist, lds_m);
+    if (C.max_m <= LDS_M) {
+        const size_t shmem = (size_t)C.max_m * C.max_m * sizeof(double);
+        hipLaunchKernelGGL(k_pivot<true>, dim3(C.n), dim3(WG), shmem, st, L, C.clist);
+    } else {
+        hipLaunchKernelGGL(k_pivot<false>, dim3(C.n), dim3(WG), 0, st, L, C.clist);
+    }
 }
 
 // ============================================================ fill update
@@ -456,8 +492,10 @@ void launch_nbr_update(const LevelDev& L, const ColourDev& C, hipStream_t st) {
 // A_ab -= E_L[a] E_R[b] for all neighbour pairs of s, computed as the single
 // product E_L E_R (ntot x ntot, inner dimension f) in 64 x 64 tiles whose
 // epilogue scatters every entry into its block (Eq. elim).
-constexpr int PTAB = 256;  // block-pointer table of a Schur tile (row x column neighbours)
+constexpr int PTAB = 256;      // block-pointer table of a Schur tile (row x column neighbours)
+constexpr int NOFF_LDS = 1024;  // neighbour offsets staged in LDS up to this many neighbours
 struct SchurMaps {
+    int noff[NOFF_LDS];  // packed offsets of the neighbours (when nb <= NOFF_LDS)
     int rblk[SCHUR_T];   // neighbour index of every tile row (-1 = none)
     int rloc[SCHUR_T];
     int cblk[SCHUR_T];
@@ -466,8 +504,8 @@ struct SchurMaps {
     int ldtab[SCHUR_T];  // leading dimension of row neighbour bi0 + i
 };
 
-__device__ inline void map_rows(const LevelDev& L, int s, int r0, int nt, int* nbr_of, int* loc_of) {
-    const int e0 = L.nbr_ptr[s], nb = L.nbr_ptr[s + 1] - e0;
+template <class PN>
+__device__ inline void map_rows(PN noff, int nb, int r0, int nt, int* nbr_of, int* loc_of) {
     for (int r = threadIdx.x; r < SCHUR_T; r += blockDim.x) {
         const int g = r0 + r;
         int idx = -1, loc = 0;
@@ -476,13 +514,13 @@ __device__ inline void map_rows(const LevelDev& L, int s, int r0, int nt, int* n
             int lo = 0, hi = nb;
             while (hi - lo > 1) {
                 int mid = (lo + hi) >> 1;
-                if (L.nbr_noff[e0 + mid] <= g)
+                if (noff[mid] <= g)
                     lo = mid;
                 else
                     hi = mid;
             }
             idx = lo;
-            loc = g - L.nbr_noff[e0 + lo];
+            loc = g - noff[lo];
         }
         nbr_of[r] = idx;
         loc_of[r] = loc;
@@ -508,14 +546,21 @@ __global__ void __launch_bounds__(WG) k_schur(LevelDev L, ColourDev C) {
     const int64_t MM = (int64_t)M * M;
     const double* ER = L.rec + L.rec_off[s] + 2 * MM;  // f x ntot, ld M
     const double* EL = ER + (int64_t)M * ncap;          // ntot x f, ld ncap
-    map_rows(L, s, r0, nt, mp.rblk, mp.rloc);
-    map_rows(L, s, c0, nt, mp.cblk, mp.cloc);
+    const int e0 = L.nbr_ptr[s], nb = L.nbr_ptr[s + 1] - e0;
+    if (nb <= NOFF_LDS) {
+        for (int x = threadIdx.x; x < nb; x += blockDim.x) mp.noff[x] = L.nbr_noff[e0 + x];
+        __syncthreads();
+        map_rows(to_lds(mp.noff), nb, r0, nt, mp.rblk, mp.rloc);
+        map_rows(to_lds(mp.noff), nb, c0, nt, mp.cblk, mp.cloc);
+    } else {
+        map_rows(L.nbr_noff + e0, nb, r0, nt, mp.rblk, mp.rloc);
+        map_rows(L.nbr_noff + e0, nb, c0, nt, mp.cblk, mp.cloc);
+    }
     v4d acc[2][2];
     mfma_tile64(
         f, [&](int r, int k) { return (r0 + r < nt && k < f) ? EL[(r0 + r) + (int64_t)k * ncap] : 0.0; },
-        [&](int k, int c) { return (c0 + c < nt && k < f) ? ER[k + (int64_t)(c0 + c) * M] : 0.0; }, &sm, acc);
+        [&](int k, int c) { return (c0 + c < nt && k < f) ? ER[k + (int64_t)(c0 + c) * M] : 0.0; }, to_lds(&sm), acc);
     __syncthreads();
-    const int e0 = L.nbr_ptr[s], nb = L.nbr_ptr[s + 1] - e0;
     const int64_t pb = L.pair_base[s];
     // neighbour ranges covered by the tile; the block pointers of every
     // (row neighbour, column neighbour) pair go to LDS once
@@ -531,17 +576,28 @@ __global__ void __launch_bounds__(WG) k_schur(LevelDev L, ColourDev C) {
         for (int i = threadIdx.x; i < nbi; i += blockDim.x) mp.ldtab[i] = L.m[L.nbr_id[e0 + bi0 + i]];
     }
     __syncthreads();
-    mfma_tile64_store(acc, [&](int r, int c, double v) {
+    // every entry of the tile has its own address: all 16 targets of a lane
+    // are read before any is written back
+    glb_f64* dst[16];
+    mfma_tile64_visit(acc, [&](int idx, int r, int c, double) {
         const int bi = mp.rblk[r], bj = mp.cblk[c];
-        if (bi < 0 || bj < 0) return;
-        if (table) {
-            const int i = bi - bi0;
-            mp.ptab[i * nbj + (bj - bj0)][mp.rloc[r] + (int64_t)mp.cloc[c] * mp.ldtab[i]] -= v;
-        } else {
-            const int a = L.nbr_id[e0 + bi];
-            double* Cb = blk_ptr(L, L.pair_blk[pb + (int64_t)bi * nb + bj]);
-            Cb[mp.rloc[r] + (int64_t)mp.cloc[c] * L.m[a]] -= v;
+        double* p = nullptr;
+        if (bi >= 0 && bj >= 0) {
+            if (table) {
+                const int i = bi - bi0;
+                p = mp.ptab[i * nbj + (bj - bj0)] + mp.rloc[r] + (int64_t)mp.cloc[c] * mp.ldtab[i];
+            } else {
+                const int a = L.nbr_id[e0 + bi];
+                p = blk_ptr(L, L.pair_blk[pb + (int64_t)bi * nb + bj]) + mp.rloc[r] + (int64_t)mp.cloc[c] * L.m[a];
+            }
         }
+        dst[idx] = (glb_f64*)p;
+    });
+    double old[16];
+#pragma unroll
+    for (int x = 0; x < 16; ++x) old[x] = dst[x] ? *dst[x] : 0.0;
+    mfma_tile64_visit(acc, [&](int idx, int, int, double v) {
+        if (dst[idx]) *dst[idx] = old[idx] - v;
     });
 }
 
