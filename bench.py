@@ -19,6 +19,7 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--side 64]
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -30,6 +31,40 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_schur_hbm_traffic_poisson64.md")
+
+
+def schur_source_digest() -> str:
+    """Digest of the Schur-update kernel's source (its section of k_factor.hip
+    and the MFMA tile core it is built on)."""
+    csrc = os.path.join(ROOT, "paper_1712_07297_amd", "csrc")
+
+    def section(name, a, b):
+        with open(os.path.join(csrc, name)) as fh:
+            text = fh.read()
+        i = text.index(a)
+        return text[i : text.index(b, i)]
+
+    h = hashlib.sha256()
+    h.update(section("k_factor.hip", "// " + "=" * 60 + " Schur update", "// " + "=" * 64 + " assembly").encode())
+    h.update(section("device_common.h", "// " + "-" * 60 + " MFMA tile core", "// " + "-" * 60 + " cooperative GEMM").encode())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per k_schur launch from the committed FETCH_SIZE / WRITE_SIZE
+    passes on this workload, or None when the kernel changed since."""
+    try:
+        with open(TRAFFIC_PROFILE) as fh:
+            text = fh.read()
+    except OSError:
+        return None
+    vals = dict(
+        line.split(":", 1) for line in text.splitlines() if line.startswith(("traffic_bytes_per_launch:", "kernel_source_digest:"))
+    )
+    if vals.get("kernel_source_digest", "").strip() != schur_source_digest():
+        return None
+    return float(vals["traffic_bytes_per_launch"])
 
 
 def cpu_baseline(side: int = 24):
@@ -104,8 +139,9 @@ def main():
         F.free()
         return it, rel, ok, info
 
-    for _ in range(args.warmup):
+    for w in range(args.warmup):
         step()
+        print(f"warmup step {w + 1}/{args.warmup} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
 
     P.profile_reset()
@@ -114,8 +150,9 @@ def main():
     t0 = time.perf_counter()
     its, rels, oks = [], [], []
     info = None
-    for _ in range(args.steps):
+    for k in range(args.steps):
         it, rel, ok, info = step()
+        print(f"timed step {k + 1}/{args.steps} done", file=sys.stderr, flush=True)
         its.append(it)
         rels.append(float(rel.max()))
         oks.append(ok)
@@ -158,6 +195,7 @@ def main():
     }
     if schur["launches"] > 0 and schur["seconds"] > 0:
         achieved = schur["bytes"] / schur["seconds"] / 1e9
+        traffic = measured_traffic() if (args.side == 64 and args.nrhs == 8) else None
         out["roofline"] = {
             "kernel": "k_schur (Schur-complement GEMM, Eq. elim)",
             "bound": "hbm",
@@ -165,13 +203,14 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": traffic,
             "launches": schur["launches"],
             "avg_launch_ms": schur["seconds"] / schur["launches"] * 1e3,
             "algorithmic_bytes_per_launch": schur["bytes"] / schur["launches"],
             "achieved_tflops": schur["flops"] / schur["seconds"] / 1e12,
         }
     if not args.no_cpu_baseline:
+        print("timing the CPU oracle sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.cpu_side)
     print(json.dumps(out))
 

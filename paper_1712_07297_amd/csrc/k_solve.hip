@@ -149,6 +149,8 @@ void launch_apply_bwd_acc(const SolveLevelDev& S, const ColourDev& C, const doub
                        S, C, z, out, part, part_off, nrhs);
 }
 
+constexpr int BWD_POFF = 512;
+
 __global__ void __launch_bounds__(WG) k_apply_bwd_t(SolveLevelDev S, ColourDev C, const double* __restrict__ z,
                                                     double* __restrict__ out, const double* __restrict__ part,
                                                     const int64_t* __restrict__ part_off, int nrhs) {
@@ -166,13 +168,33 @@ __global__ void __launch_bounds__(WG) k_apply_bwd_t(SolveLevelDev S, ColourDev C
         for (int x = threadIdx.x; x < tot; x += blockDim.x) os[x] = zs[x];
         return;
     }
+    // partials of the neighbours: offsets staged in LDS, the loads of one
+    // element issued eight at a time
+    __shared__ int64_t poff[BWD_POFF];
     const int q0 = C.nbr_pre[ci], q1 = C.nbr_pre[ci + 1];
-    for (int x = threadIdx.x; x < tot; x += blockDim.x) {
-        const int i = x % M, r = x / M;
-        double v = zs[x];
-        if (i < f)
-            for (int q = q0; q < q1; ++q) v -= part[part_off[q] * nrhs + i + r * f];
-        vs[x] = v;
+    for (int q0c = q0; q0c < q1 || q0c == q0; q0c += BWD_POFF) {
+        const int nq = min(BWD_POFF, q1 - q0c);
+        __syncthreads();
+        for (int q = threadIdx.x; q < nq; q += blockDim.x) poff[q] = part_off[q0c + q] * nrhs;
+        __syncthreads();
+        for (int x = threadIdx.x; x < tot; x += blockDim.x) {
+            const int i = x % M, r = x / M;
+            double v = (q0c == q0) ? zs[x] : vs[x];
+            if (i < f) {
+                const double* pp = part + i + r * f;
+                int q = 0;
+                for (; q + 8 <= nq; q += 8) {
+                    double t[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) t[u] = pp[poff[q + u]];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) v -= t[u];
+                }
+                for (; q < nq; ++q) v -= pp[poff[q]];
+            }
+            vs[x] = v;
+        }
+        if (q1 - q0c <= BWD_POFF) break;
     }
     __syncthreads();
     const double* T = S.rec + S.rec_off[s] + (int64_t)M * M;  // T_R'
