@@ -343,7 +343,8 @@ static int plan_level(hs_factor_s* F, int lvl, Blob& blob, std::vector<size_t>& 
         roff += 2 * (int64_t)m[s] * m[s] + 2 * (int64_t)m[s] * cap;
     }
     LD.rec_elems = roff;
-    LD.gram_splits = std::min(16, std::max(1, (max_nf + 15) / 16));
+    // about four fill partners per Gram workgroup
+    LD.gram_splits = std::min(64, std::max(1, (max_nf + 3) / 4));
     const int64_t slots = ws_slots(LD.gram_splits);
 
     // colours

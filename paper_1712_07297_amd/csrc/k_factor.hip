@@ -90,9 +90,26 @@ __global__ void __launch_bounds__(WG) k_gram(LevelDev L, const int* __restrict__
         }
 }
 
+// Partial 0 += partials 1 .. gram_splits-1 (in that order), one entry per thread.
+__global__ void k_gram_reduce(LevelDev L, const int* __restrict__ clist) {
+    const int s = clist[blockIdx.y];
+    const int M = L.m[s];
+    const int64_t MM = (int64_t)M * M;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= MM) return;
+    double* G = L.ws + L.ws_off[s] + WS_GP * MM;
+    double g = G[e];
+    for (int sp = 1; sp < L.gram_splits; ++sp) g += G[sp * MM + e];
+    G[e] = g;
+}
+
 void launch_gram(const LevelDev& L, const ColourDev& C, hipStream_t st) {
     if (C.n == 0) return;
     hipLaunchKernelGGL(k_gram, dim3(L.gram_splits, C.n), dim3(WG), 0, st, L, C.clist);
+    const int64_t mm = (int64_t)C.max_m * C.max_m;
+    if (L.gram_splits > 1 && mm > 0) {
+        hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((mm + 255) / 256), C.n), dim3(256), 0, st, L, C.clist);
+    }
 }
 
 // ============================================================== pivot kernel
@@ -260,12 +277,8 @@ __global__ void __launch_bounds__(WG) k_pivot(LevelDev L, const int* __restrict_
         double ass2 = 0.0;  // ||A_ss||_F^2 (noise floor of the fill)
         for (int64_t e = tid; e < MM; e += blockDim.x) ass2 = fma(Bss[e], Bss[e], ass2);
         ass2 = block_sum(ass2, red_l);
-        // W = sum of the Gram partials
-        for (int64_t e = tid; e < MM; e += blockDim.x) {
-            double g = 0.0;
-            for (int sp = 0; sp < L.gram_splits; ++sp) g += ws[(WS_GP + sp) * MM + e];
-            W[e] = g;
-        }
+        // W = the Gram matrix (partials already summed into the first slot)
+        for (int64_t e = tid; e < MM; e += blockDim.x) W[e] = ws[WS_GP * MM + e];
         __syncthreads();
         // fill at the rounding level of A_ss is noise: treat it as zero
         double dmax = 0.0;
