@@ -523,15 +523,122 @@ __device__ inline void wg_trinv(PW W, int M, int ldw, PO out, int ldo) {
     __syncthreads();
 }
 
-// out = L^{-1}, L = unit lower triangle of W.
-template <class PW, class PO>
-__device__ inline void wg_trinv_lower_unit(PW W, int M, int ldw, PO out, int ldo) {
-    wg_trinv<false, PW, PO>(W, M, ldw, out, ldo);
+// Blocked triangular inverse on the FP64 matrix cores, M <= 128 (at most 8
+// blocks of 16).  The native result layout of v_mfma_f64_16x16x4f64 (lane l,
+// element r holds D[l/16 + 4r][l%16]) is its B-operand layout for the k-chunk
+// 4r, so a wave keeps one block column of the inverse in accumulators and
+// feeds finished blocks straight back as operands.
+//   lower (unit):  X_JJ = L_JJ^{-1}, X_IJ = -X_II sum_{J<=l<I} L_Il X_lJ  (I > J)
+//   upper:         X_JJ = U_JJ^{-1}, X_IJ = -X_II sum_{I<l<=J} U_Il X_lJ  (I < J)
+// Block columns are independent: wave w takes J = w, w + 4, ...  The 16 x 16
+// diagonal inverses go first, one 16-lane group per block, into scr
+// (8 x 256 doubles of LDS).  Padding beyond M is the identity.
+constexpr int TRI_MFMA_MAX = 128;
+
+// Inverses of the 16 x 16 diagonal blocks, one 16-lane group per block,
+// column c of block g into scr[g * 256 + 16 c ...].
+template <bool UPPER, class PW>
+__device__ __attribute__((noinline)) void diag_block_inverses(PW W, int M, int ldw, lds_f64* scr) {
+    const int tid = threadIdx.x;
+    const int nb = (M + 15) >> 4;
+    const int g = tid >> 4, c = tid & 15;
+    if (g >= nb) return;
+    const int b0 = 16 * g;
+    auto T = [&](int r, int j) -> double {
+        const int gr = b0 + r, gj = b0 + j;
+        if (gr >= M || gj >= M) return (r == j) ? 1.0 : 0.0;
+        return W[gr + (int64_t)gj * ldw];
+    };
+    double x[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) x[r] = (r == c) ? 1.0 : 0.0;
+    if (!UPPER) {
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+#pragma unroll
+            for (int r = j + 1; r < 16; ++r) x[r] = fma(-T(r, j), x[j], x[r]);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    } else {
+#pragma unroll
+        for (int j = 15; j >= 0; --j) {
+            x[j] = x[j] / T(j, j);
+#pragma unroll
+            for (int r = 0; r < j; ++r) x[r] = fma(-T(r, j), x[j], x[r]);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) scr[g * 256 + r + 16 * c] = x[r];
+}
+
+template <bool UPPER, class PW, class PO>
+__device__ inline void wg_trinv_mfma(PW W, int M, int ldw, PO out, int ldo, lds_f64* scr) {
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
+    const int nb = (M + 15) >> 4;
+    diag_block_inverses<UPPER, PW>(W, M, ldw, scr);
+    __syncthreads();
+    const int lr = lane & 15, lk = lane >> 4;
+    v4d ident;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) ident[r] = (lk + 4 * r == lr) ? 1.0 : 0.0;
+    const v4d zero = {0.0, 0.0, 0.0, 0.0};
+    for (int J = wv; J < nb; J += nw) {
+        v4d X[8];
+#pragma unroll
+        for (int ii = 0; ii < 8; ++ii) {
+            const int I = UPPER ? 7 - ii : ii;  // the order in which blocks become available
+            if (I >= nb || (UPPER ? I > J : I < J)) continue;
+            v4d S = (I == J) ? ident : zero;
+#pragma unroll
+            for (int l = 0; l < 8; ++l) {
+                if (l >= nb || (UPPER ? (l <= I || l > J) : (l < J || l >= I))) continue;
+                const int gr = 16 * I + lr;
+                auto colp = W + gr + (int64_t)(16 * l + lk) * ldw;
+                double a[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) a[r] = (gr < M && 16 * l + 4 * r + lk < M) ? -colp[(int64_t)(4 * r) * ldw] : 0.0;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) S = __builtin_amdgcn_mfma_f64_16x16x4f64(a[r], X[l][r], S, 0, 0, 0);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            v4d acc = zero;
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(scr[I * 256 + lr + 16 * (4 * r + lk)], S[r], acc, 0, 0, 0);
+            X[I] = acc;
+        }
+#pragma unroll
+        for (int I = 0; I < 8; ++I) {
+            if (I >= nb) continue;
+            const bool nz = UPPER ? I <= J : I >= J;
+            const int col = 16 * J + lr;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = 16 * I + lk + 4 * r;
+                if (row < M && col < M) out[row + (int64_t)col * ldo] = nz ? X[I][r] : 0.0;
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// out = L^{-1}, L = unit lower triangle of W.  MODE 1: matrix cores (M <=
+// TRI_MFMA_MAX), 0: per-wave substitution, -1: chosen by M.
+template <int MODE = -1, class PW, class PO>
+__device__ inline void wg_trinv_lower_unit(PW W, int M, int ldw, PO out, int ldo, lds_f64* scr) {
+    if (MODE == 1 || (MODE == -1 && M <= TRI_MFMA_MAX))
+        wg_trinv_mfma<false, PW, PO>(W, M, ldw, out, ldo, scr);
+    else
+        wg_trinv<false, PW, PO>(W, M, ldw, out, ldo);
 }
 // out = U^{-1}, U = upper triangle of W (with diagonal).
-template <class PW, class PO>
-__device__ inline void wg_trinv_upper(PW W, int M, int ldw, PO out, int ldo) {
-    wg_trinv<true, PW, PO>(W, M, ldw, out, ldo);
+template <int MODE = -1, class PW, class PO>
+__device__ inline void wg_trinv_upper(PW W, int M, int ldw, PO out, int ldo, lds_f64* scr) {
+    if (MODE == 1 || (MODE == -1 && M <= TRI_MFMA_MAX))
+        wg_trinv_mfma<true, PW, PO>(W, M, ldw, out, ldo, scr);
+    else
+        wg_trinv<true, PW, PO>(W, M, ldw, out, ldo);
 }
 
 // ----------------------------------------------------------- Householder QR

@@ -45,6 +45,7 @@ __global__ void k_dense_assemble(const int* __restrict__ pat_ptr, const int* __r
 __global__ void __launch_bounds__(WG) k_dense_diag(double* __restrict__ D, int64_t ldd, int p, int nb,
                                                    double* __restrict__ inv, int* __restrict__ flag) {
     extern __shared__ double Wd[];  // nb x nb
+    __shared__ double scr_d[8 * 256];
     lds_f64* W = to_lds(Wd);
     double* dp = D + p + (int64_t)p * ldd;
     wg_copy(nb, nb, dp, (int)ldd, W, nb);
@@ -55,8 +56,8 @@ __global__ void __launch_bounds__(WG) k_dense_diag(double* __restrict__ D, int64
     }
     wg_copy(nb, nb, W, nb, dp, (int)ldd);
     __syncthreads();
-    wg_trinv_lower_unit(W, nb, nb, inv, DNB);
-    wg_trinv_upper(W, nb, nb, inv + DNB * DNB, DNB);
+    wg_trinv_lower_unit<1>(W, nb, nb, inv, DNB, to_lds(scr_d));
+    wg_trinv_upper<1>(W, nb, nb, inv + DNB * DNB, DNB, to_lds(scr_d));
 }
 
 // Panel updates, in place: column chunks of U12 = L11^{-1} D[p:p+nb, chunk]
@@ -127,14 +128,15 @@ __global__ void __launch_bounds__(WG) k_dense_trailing(double* __restrict__ D, i
 __global__ void __launch_bounds__(WG) k_dense_inverses(const double* __restrict__ D, int64_t ldd,
                                                        const int* __restrict__ m, const int64_t* __restrict__ off,
                                                        const int64_t* __restrict__ rec_off, double* __restrict__ rec) {
+    __shared__ double scr_d[8 * 256];
     const int s = blockIdx.x;
     const int M = m[s];
     if (M == 0) return;
     const double* dd = D + off[s] + off[s] * ldd;
     double* TL = rec + rec_off[s];
     double* TR = TL + (int64_t)M * M;
-    wg_trinv_lower_unit(dd, M, (int)ldd, TL, M);
-    wg_trinv_upper(dd, M, (int)ldd, TR, M);
+    wg_trinv_lower_unit(dd, M, (int)ldd, TL, M, to_lds(scr_d));
+    wg_trinv_upper(dd, M, (int)ldd, TR, M, to_lds(scr_d));
 }
 
 // E_R = U[s, later] (M x nt, ld M) and E_L = L[later, s] (nt x M, ld ncap).

@@ -263,6 +263,7 @@ __global__ void __launch_bounds__(WG) k_pivot(LevelDev L, const int* __restrict_
     lds_f64* red_l = to_lds(red);
     lds_f64* dsh_l = to_lds(dsh);
     lds_smem* sm_l = to_lds(&sm);
+    lds_f64* scr = (lds_f64*)sm_l;  // 2080 doubles, free outside the GEMMs
     double* TLp = L.rec + L.rec_off[s];
     double* TRp = TLp + MM;
     double* Bss = blk_ptr(L, L.diag_blk[s]);
@@ -313,12 +314,12 @@ __global__ void __launch_bounds__(WG) k_pivot(LevelDev L, const int* __restrict_
         return;
     }
     if (kk == 0) {  // E_s = I: one block LU step
-        wg_trinv_lower_unit(W, M, M, TLp, M);
-        wg_trinv_upper(W, M, M, TRp, M);
+        wg_trinv_lower_unit<INLDS ? 1 : 0>(W, M, M, TLp, M, scr);
+        wg_trinv_upper<INLDS ? 1 : 0>(W, M, M, TRp, M, scr);
         return;
     }
-    wg_trinv_lower_unit(W, M, M, Linv, M);
-    wg_trinv_upper(W, M, M, Uinv, M);
+    wg_trinv_lower_unit<INLDS ? 1 : 0>(W, M, M, Linv, M, scr);
+    wg_trinv_upper<INLDS ? 1 : 0>(W, M, M, Uinv, M, scr);
     wg_gemm<false, false>(M, M, M, 1.0, Uinv, M, Linv, M, 0.0, Ainv, M, sm_l);
     const int f = M - kk;
 
@@ -348,8 +349,8 @@ __global__ void __launch_bounds__(WG) k_pivot(LevelDev L, const int* __restrict_
         }
         return;
     }
-    wg_trinv_lower_unit(W, f, M, Linv, M);
-    wg_trinv_upper(W, f, M, Uinv, M);
+    wg_trinv_lower_unit<INLDS ? 1 : 0>(W, f, M, Linv, M, scr);
+    wg_trinv_upper<INLDS ? 1 : 0>(W, f, M, Uinv, M, scr);
     // T_L' = [L_f^{-1} T_L[:f, :]; T_L[f:, :]],  T_R' = [T_R[:, :f] U_f^{-1}, T_R[:, f:]]
     wg_gemm<false, false>(f, M, f, 1.0, Linv, M, TL, M, 0.0, TLp, M, sm_l);
     wg_copy(kk, M, TL + f, M, TLp + f, M);
