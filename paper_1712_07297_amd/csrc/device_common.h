@@ -350,6 +350,143 @@ __device__ inline bool wg_lu_nopiv(PW W, int M, int ldw) {
     return true;
 }
 
+// Blocked LU without pivoting for M <= 128 with W in LDS: 16-wide panels.
+// The panel is factored by wave 0 in registers (the same operations, in the
+// same order, as the unblocked routine); then U_12 = L_11^{-1} A_12 and
+// A_22 -= L_21 U_12 run as 16 x 16 blocks on the matrix cores, spread over
+// the waves.  scr holds 256 doubles of LDS, flag one int.  Returns false on a
+// zero or non-finite pivot (every thread returns the same).
+template <class PW>
+__device__ __attribute__((noinline)) void tri16_lower_unit_inverse(PW W, int ldw, int b0, lds_f64* scr) {
+    const int c = threadIdx.x & 63;
+    if (c >= 16) return;
+    double x[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) x[r] = (r == c) ? 1.0 : 0.0;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+#pragma unroll
+        for (int r = j + 1; r < 16; ++r) x[r] = fma(-W[(b0 + r) + (int64_t)(b0 + j) * ldw], x[j], x[r]);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) scr[r + 16 * c] = x[r];
+}
+
+template <int NS, class PW>
+__device__ inline bool wg_lu_blocked_ns(PW W, int M, int ldw, lds_f64* scr, lds_i32* flag) {
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    if (tid == 0) *flag = 0;
+    __syncthreads();
+    for (int p = 0; p < M; p += 16) {
+        const int pw = min(16, M - p);
+        if (wv == 0) {  // panel: rows p..M-1, columns p..p+pw-1
+            double x[16][NS];
+#pragma unroll
+            for (int c = 0; c < 16; ++c)
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    const int i = s * 64 + lane;
+                    x[c][s] = (c < pw && i < M) ? W[i + (int64_t)(p + c) * ldw] : 0.0;
+                }
+            bool ok = true;
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const int col = p + j, sj = col >> 6, lj = col & 63;
+                if (ok && j < pw) {
+                    const double piv = readlane_d(NS == 1 || sj == 0 ? x[j][0] : x[j][NS - 1], lj);
+                    ok = (piv != 0.0 && isfinite(piv));
+                    const double inv = 1.0 / piv;
+                    double l[NS];
+#pragma unroll
+                    for (int s = 0; s < NS; ++s) {
+                        const int i = s * 64 + lane;
+                        l[s] = (ok && i > col) ? x[j][s] * inv : 0.0;
+                        x[j][s] = (i > col) ? l[s] : x[j][s];
+                    }
+#pragma unroll
+                    for (int c = j + 1; c < 16; ++c) {
+                        const double u = readlane_d(NS == 1 || sj == 0 ? x[c][0] : x[c][NS - 1], lj);
+#pragma unroll
+                        for (int s = 0; s < NS; ++s) x[c][s] = fma(-l[s], u, x[c][s]);
+                    }
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            if (!ok) {
+                if (lane == 0) *flag = 1;
+            } else {
+#pragma unroll
+                for (int c = 0; c < 16; ++c)
+#pragma unroll
+                    for (int s = 0; s < NS; ++s) {
+                        const int i = s * 64 + lane;
+                        if (c < pw && i >= p && i < M) W[i + (int64_t)(p + c) * ldw] = x[c][s];
+                    }
+            }
+        }
+        __syncthreads();
+        if (*flag) return false;
+        const int q = p + pw, n2 = M - q;
+        if (n2 <= 0) break;
+        if (wv == 0) tri16_lower_unit_inverse(W, ldw, p, scr);
+        __syncthreads();
+        const int nbc = (n2 + 15) >> 4;
+        for (int cb = wv; cb < nbc; cb += nw) {  // U_12 = L_11^{-1} A_12
+            const int c0 = q + 16 * cb;
+            const bool cin = c0 + lr < M;
+            double a[4], b[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                a[r] = scr[lr + 16 * (4 * r + lk)];
+                b[r] = cin ? W[(p + 4 * r + lk) + (int64_t)(c0 + lr) * ldw] : 0.0;
+            }
+            v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[r], b[r], acc, 0, 0, 0);
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if (cin) W[(p + lk + 4 * r) + (int64_t)(c0 + lr) * ldw] = acc[r];
+        }
+        __syncthreads();
+        for (int b = wv; b < nbc * nbc; b += nw) {  // A_22 -= L_21 U_12
+            const int rb = b % nbc, cb = b / nbc;
+            const int r0 = q + 16 * rb, c0 = q + 16 * cb;
+            const bool cin = c0 + lr < M, rin = r0 + lr < M;
+            v4d acc;
+            double a[4], bb[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = r0 + lk + 4 * r;
+                acc[r] = (row < M && cin) ? W[row + (int64_t)(c0 + lr) * ldw] : 0.0;
+                a[r] = rin ? -W[(r0 + lr) + (int64_t)(p + 4 * r + lk) * ldw] : 0.0;
+                bb[r] = cin ? W[(p + 4 * r + lk) + (int64_t)(c0 + lr) * ldw] : 0.0;
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[r], bb[r], acc, 0, 0, 0);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = r0 + lk + 4 * r;
+                if (row < M && cin) W[row + (int64_t)(c0 + lr) * ldw] = acc[r];
+            }
+        }
+        __syncthreads();
+    }
+    return true;
+}
+
+// Unpivoted LU: blocked on the matrix cores (BLK, M <= 128) or the unblocked
+// routine.
+template <bool BLK, class PW>
+__device__ inline bool wg_lu(PW W, int M, int ldw, lds_f64* scr, lds_i32* flag) {
+    if constexpr (BLK) {
+        if (M <= 64) return wg_lu_blocked_ns<1, PW>(W, M, ldw, scr, flag);
+        if (M <= 128) return wg_lu_blocked_ns<2, PW>(W, M, ldw, scr, flag);
+    }
+    return wg_lu_nopiv(W, M, ldw);
+}
+
 // ------------------------------------------------------- triangular inverses
 // One wave computes two columns (c0, c1) of the inverse by substitution in
 // its registers: row i = 64 s + lane lives in slot s.  The two columns share

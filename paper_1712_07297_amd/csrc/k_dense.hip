@@ -50,7 +50,8 @@ __global__ void __launch_bounds__(WG) k_dense_diag(double* __restrict__ D, int64
     double* dp = D + p + (int64_t)p * ldd;
     wg_copy(nb, nb, dp, (int)ldd, W, nb);
     __syncthreads();
-    if (!wg_lu_nopiv(W, nb, nb)) {
+    __shared__ int fl;
+    if (!wg_lu<true>(W, nb, nb, to_lds(scr_d), to_lds(&fl))) {
         if (threadIdx.x == 0) *flag = 1;
         return;
     }

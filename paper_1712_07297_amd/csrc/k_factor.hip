@@ -198,6 +198,43 @@ __device__ int wg_pivoted_cholesky(PW W, int M, double eps, int fixed_rank, PI p
     return kk;
 }
 
+// Orthonormal factor Q (M x k, positive diagonal R) of X = Q R by two passes
+// of Cholesky QR: G = Y^T Y = R^T R, R = D^{-1/2} U_G from the unpivoted LU
+// G = L_G U_G (D = diag U_G), Y <- Y R^{-1}.  Two passes make Q orthonormal
+// to working accuracy while cond(X) stays below about 1e7; beyond that
+// (smallest Gram pivot below 1e-14 of the largest) it returns false and
+// leaves the caller to use Householder QR.  G is a k x k LDS scratch, T1 an
+// M x k and T2 a k x k global scratch.
+template <class PG>
+__device__ bool wg_cholqr2(const double* X, int M, int k, PG G, double* T1, double* T2, double* Q, lds_smem* sm,
+                           lds_f64* scr, lds_f64* red, lds_i32* flag) {
+    const double* src = X;
+    for (int pass = 0; pass < 2; ++pass) {
+        double* dst = pass == 0 ? T1 : Q;
+        wg_gemm<true, false>(k, k, M, 1.0, src, M, src, M, 0.0, G, k, sm);
+        if (!wg_lu<true>(G, k, k, scr, flag)) return false;
+        double pmax = 0.0, nmin = -INFINITY;
+        for (int i = threadIdx.x; i < k; i += blockDim.x) {
+            const double d = G[i + (int64_t)i * k];
+            pmax = fmax(pmax, d);
+            nmin = fmax(nmin, -d);
+        }
+        pmax = block_max(pmax, red);
+        const double pmin = -block_max(nmin, red);
+        if (!(pmin > 1e-14 * pmax)) return false;
+        wg_trinv_upper<1>(G, k, k, T2, k, scr);
+        const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+        for (int j = threadIdx.x >> 6; j < k; j += nw) {
+            const double sj = sqrt(G[j + (int64_t)j * k]);
+            for (int i = lane; i <= j; i += 64) T2[i + (int64_t)j * k] *= sj;
+        }
+        __syncthreads();
+        wg_gemm<false, false>(M, k, k, 1.0, src, M, T2, k, 0.0, dst, M, sm);
+        src = dst;
+    }
+    return true;
+}
+
 // Householder complement: Q columns [K, M) of the QR of X (M x K, ld M) into
 // V (ld ldv).  X is destroyed.
 template <class PX, class PV, class PT>
@@ -296,9 +333,13 @@ __global__ void __launch_bounds__(WG) k_pivot(LevelDev L, const int* __restrict_
             for (int j = tid >> 6; j < kk; j += nw)
                 for (int i = lane; i < M; i += 64) X[perm[i] + (int64_t)j * M] = (i >= j) ? W[i + (int64_t)j * M] : 0.0;
             __syncthreads();
-            wg_copy(M, kk, X, M, W, M);
-            wg_house_qr(W, M, kk, M, dsh_l);
-            wg_house_form_q(W, M, kk, M, dsh_l, 0, kk, Umat, M, true);
+            bool done = false;
+            if constexpr (INLDS) done = wg_cholqr2(X, M, kk, W, Linv, Uinv, Umat, sm_l, scr, red_l, to_lds(isc + 1));
+            if (!done) {
+                wg_copy(M, kk, X, M, W, M);
+                wg_house_qr(W, M, kk, M, dsh_l);
+                wg_house_form_q(W, M, kk, M, dsh_l, 0, kk, Umat, M, true);
+            }
         }
     }
     if (tid == 0) L.k[s] = kk;
@@ -306,7 +347,7 @@ __global__ void __launch_bounds__(WG) k_pivot(LevelDev L, const int* __restrict_
 
     // ---- 2. A_ss = L U (no pivoting) and its inverse factors
     wg_copy(M, M, Bss, M, W, M);
-    if (!wg_lu_nopiv(W, M, M)) {
+    if (!wg_lu<INLDS>(W, M, M, scr, to_lds(isc + 1))) {
         if (tid == 0) {
             L.flag[s] = 1;
             L.k[s] = M;  // leave the cluster untouched
@@ -342,7 +383,7 @@ __global__ void __launch_bounds__(WG) k_pivot(LevelDev L, const int* __restrict_
 
     // ---- 4. elimination operator G_s (Eq. elim): F_ff = T_L[:f] S_R[:, :f] = L_f U_f
     wg_gemm<false, false>(f, f, M, 1.0, TL, M, SR, M, 0.0, W, M, sm_l);
-    if (!wg_lu_nopiv(W, f, M)) {
+    if (!wg_lu<INLDS>(W, f, M, scr, to_lds(isc + 1))) {
         if (tid == 0) {
             L.flag[s] = 2;
             L.k[s] = M;
