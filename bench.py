@@ -1,22 +1,24 @@
-"""Benchmark: unknowns/s to factor and solve to relative residual 1e-10.
+"""Benchmark: unknowns/s to factor and solve to relative residual 1e-10, the
+mixed-precision form against the float64 form.
 
 Workload (default): 3D 7-point Poisson on a 64^3 grid (N = 262,144), FP64 CSR,
 leaves of 64 unknowns, eps = 1e-4, the factorization used as CG
 preconditioner for 8 right-hand sides uniform on [-1, 1), stopping at
 relative residual 1e-10 for every column.  One step = hs_factor + hs_pcg
 (symbolic analysis, numeric factorization and the preconditioned solve of all
-8 right-hand sides), with the CSR and the right-hand sides already resident
-in HBM.  value = N * steps / seconds.
+8 right-hand sides) + hs_free, with the CSR and the right-hand sides already
+resident in HBM.  value = N * steps / seconds of the mixed form (float32
+blocks and records, Schur products on the bfloat16 units, float64 coarse
+levels and Krylov vectors); the float64 form is timed the same way and
+reported beside it.
 
 Also reported: the Schur-complement kernel against the HBM roofline (its
 algorithmic bytes per launch over its average launch time, HIP events on the
 library's stream inside the timed region) and the CPU oracle timed on a
 bounded sample of the same workload family on the host cores.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--side 64]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--side 64] [--forms both|mixed|fp64]
 """
-
-from __future__ import annotations
 
 import argparse
 import hashlib
@@ -51,20 +53,19 @@ def schur_source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per k_schur launch from the committed FETCH_SIZE / WRITE_SIZE
-    passes on this workload, or None when the kernel changed since."""
+def measured_traffic(element: str):
+    """HBM bytes per k_schur<element> launch from the committed FETCH_SIZE /
+    WRITE_SIZE passes on this workload, or None when the kernel changed since."""
     try:
         with open(TRAFFIC_PROFILE) as fh:
             text = fh.read()
     except OSError:
         return None
-    vals = dict(
-        line.split(":", 1) for line in text.splitlines() if line.startswith(("traffic_bytes_per_launch:", "kernel_source_digest:"))
-    )
+    vals = dict(line.split(":", 1) for line in text.splitlines() if line.startswith(("traffic_bytes_per_launch_", "kernel_source_digest:")))
     if vals.get("kernel_source_digest", "").strip() != schur_source_digest():
         return None
-    return float(vals["traffic_bytes_per_launch"])
+    v = vals.get(f"traffic_bytes_per_launch_{element}")
+    return float(v) if v is not None else None
 
 
 def cpu_baseline(side: int = 24):
@@ -94,6 +95,72 @@ def cpu_baseline(side: int = 24):
     }
 
 
+def run_form(P, torch, p, rp, ci, va, B, X, precision, steps, warmup, n):
+    """Warm-up, then `steps` timed steps of one precision form; returns its
+    record (time, convergence, Schur roofline)."""
+
+    def step():
+        F = P.Factor(rp, ci, va, p.dims, p.eps, p.leaf, symmetric=1, precision=precision)
+        _, it, rel, ok = F.pcg(B, p.tol, 200, X=X)
+        info = F.info()
+        F.free()
+        return it, rel, ok, info
+
+    name = "mixed" if precision == P.HS_MIXED else "fp64"
+    for w in range(warmup):
+        step()
+        print(f"{name}: warmup step {w + 1}/{warmup} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    P.profile_reset()
+    P.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its, rels, oks = [], [], []
+    info = None
+    for k in range(steps):
+        it, rel, ok, info = step()
+        print(f"{name}: timed step {k + 1}/{steps} done", file=sys.stderr, flush=True)
+        its.append(it)
+        rels.append(float(rel.max()))
+        oks.append(ok)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    P.profile_enable(False)
+    schur = P.profile_read("schur")
+    # independent check of the final residual (device SpMV by torch, FP64)
+    A_t = torch.sparse_csr_tensor(rp, ci.to(torch.int64), va, size=(n, n))
+    R = B.T - (A_t @ X.T)
+    relres = (torch.linalg.norm(R, dim=0) / torch.linalg.norm(B.T, dim=0)).max().item()
+    rec = {
+        "value": n * steps / dt,
+        "ms_per_step": dt / steps * 1e3,
+        "pcg_iterations": its,
+        "relres_max": max(rels),
+        "relres_check": relres,
+        "converged": all(oks) and relres <= p.tol * 1.01,
+        "levels": info.nlevels,
+        "colour_batches": info.ncolors_total,
+        "factor_gflop": info.factor_flops / 1e9,
+        "factor_bytes_records": info.factor_bytes,
+    }
+    if schur["launches"] > 0 and schur["seconds"] > 0:
+        achieved = schur["bytes"] / schur["seconds"] / 1e9
+        rec["roofline"] = {
+            "kernel": f"k_schur<{'float' if precision == P.HS_MIXED else 'double'}> (Schur-complement update, Eq. elim)",
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "launches": schur["launches"],
+            "avg_launch_ms": schur["seconds"] / schur["launches"] * 1e3,
+            "algorithmic_bytes_per_launch": schur["bytes"] / schur["launches"],
+            "achieved_tflops": schur["flops"] / schur["seconds"] / 1e12,
+        }
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -101,6 +168,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--side", type=int, default=64)
     ap.add_argument("--nrhs", type=int, default=8)
+    ap.add_argument("--forms", choices=["both", "mixed", "fp64"], default="both")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-side", type=int, default=24)
     ap.add_argument("--copy-probe", action="store_true", help="also run a plain device copy of known size (counter calibration)")
@@ -132,83 +200,48 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
 
-    def step():
-        F = P.Factor(rp, ci, va, p.dims, p.eps, p.leaf, symmetric=1)
-        _, it, rel, ok = F.pcg(B, p.tol, 200, X=X)
-        info = F.info()
-        F.free()
-        return it, rel, ok, info
-
-    for w in range(args.warmup):
-        step()
-        print(f"warmup step {w + 1}/{args.warmup} done", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-
-    P.profile_reset()
-    P.profile_enable(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    its, rels, oks = [], [], []
-    info = None
-    for k in range(args.steps):
-        it, rel, ok, info = step()
-        print(f"timed step {k + 1}/{args.steps} done", file=sys.stderr, flush=True)
-        its.append(it)
-        rels.append(float(rel.max()))
-        oks.append(ok)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    P.profile_enable(False)
-    schur = P.profile_read("schur")
-
-    # independent check of the final residual (device SpMV by torch, FP64)
-    A_t = torch.sparse_csr_tensor(rp, ci.to(torch.int64), va, size=(n, n))
-    R = B.T - (A_t @ X.T)
-    relres = (torch.linalg.norm(R, dim=0) / torch.linalg.norm(B.T, dim=0)).max().item()
-
-    value = n * args.steps / dt
+    forms = {"both": [P.HS_MIXED, P.HS_FP64], "mixed": [P.HS_MIXED], "fp64": [P.HS_FP64]}[args.forms]
+    recs = {}
+    for prec in forms:
+        recs["mixed" if prec == P.HS_MIXED else "fp64"] = run_form(P, torch, p, rp, ci, va, B, X, prec, args.steps,
+                                                                   args.warmup, n)
+    head = recs.get("mixed", recs.get("fp64"))
+    head_name = "mixed" if "mixed" in recs else "fp64"
     out = {
-        "metric": "unknowns/s factor+solve to 1e-10 residual",
-        "value": value,
+        "metric": "unknowns/s factor+solve to 1e-10 residual (mixed vs FP64)",
+        "value": head["value"],
         "unit": "unknowns/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": dt / args.steps * 1e3,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32 storage + bf16x3 MFMA Schur, f64 Krylov" if head_name == "mixed" else "f64",
         "data": "synthetic",
         "config": {
             "workload": f"3D 7-point Poisson {args.side}^3 (N={n}), leaf 64, eps 1e-4, PCG preconditioner, {args.nrhs} RHS to relative residual 1e-10",
-            "precision": "fp64",
-            "pcg_iterations": its,
-            "relres_max": max(rels),
-            "relres_check": relres,
-            "converged": all(oks),
-            "levels": info.nlevels,
-            "colour_batches": info.ncolors_total,
-            "factor_gflop": info.factor_flops / 1e9,
-            "factor_bytes_records": info.factor_bytes,
+            "form": head_name,
+            "pcg_iterations": head["pcg_iterations"],
+            "relres_max": head["relres_max"],
+            "relres_check": head["relres_check"],
+            "converged": head["converged"],
+            "levels": head["levels"],
+            "colour_batches": head["colour_batches"],
+            "factor_gflop": head["factor_gflop"],
+            "factor_bytes_records": head["factor_bytes_records"],
         },
     }
-    if schur["launches"] > 0 and schur["seconds"] > 0:
-        achieved = schur["bytes"] / schur["seconds"] / 1e9
-        traffic = measured_traffic() if (args.side == 64 and args.nrhs == 8) else None
-        out["roofline"] = {
-            "kernel": "k_schur (Schur-complement GEMM, Eq. elim)",
-            "bound": "hbm",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": traffic,
-            "launches": schur["launches"],
-            "avg_launch_ms": schur["seconds"] / schur["launches"] * 1e3,
-            "algorithmic_bytes_per_launch": schur["bytes"] / schur["launches"],
-            "achieved_tflops": schur["flops"] / schur["seconds"] / 1e12,
-        }
+    if args.side == 64 and args.nrhs == 8:
+        for name, rec in recs.items():
+            if "roofline" in rec:
+                rec["roofline"]["traffic"] = measured_traffic("float" if name == "mixed" else "double")
+    if "roofline" in head:
+        out["roofline"] = head["roofline"]
+    if "fp64" in recs and head_name != "fp64":
+        out["fp64"] = recs["fp64"]
+        out["mixed_over_fp64"] = head["value"] / recs["fp64"]["value"]
     if not args.no_cpu_baseline:
         print("timing the CPU oracle sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.cpu_side)

@@ -80,7 +80,9 @@ typedef struct hs_geometry {
 } hs_geometry;
 
 #define HS_FP64 0  /* everything in float64 */
-#define HS_MIXED 1 /* float32 factor with float64 on the two coarsest levels */
+#define HS_MIXED 1 /* float32 storage of the fine levels' blocks and records,
+                      bfloat16 Schur products accumulated in float32; float64
+                      on the coarse levels and in every Krylov vector */
 
 /* Options of the factorization.
  *   eps         relative truncation tolerance of the fill compression
@@ -90,10 +92,18 @@ typedef struct hs_geometry {
  *   fixed_rank  if > 0, additionally cap every rank at this value (the fixed
  *               rank K of Sec. 5.1).
  *   leaf_size   target number of unknowns per leaf cluster (> 0).
- *   precision   HS_FP64 or HS_MIXED.
+ *   precision   HS_FP64 or HS_MIXED.  In the mixed form the level blocks and
+ *               factor records of every level with more than
+ *               coarse_fp64_dofs unknowns (and not complete) are float32,
+ *               the Schur update (Eq. elim) multiplies bfloat16-rounded
+ *               E_L, E_R with float32 accumulation, and the per-cluster
+ *               dense algebra still runs in float64 registers; the result
+ *               is a preconditioner for float64 CG / GMRES (Sec. 5).
  *   symmetric   1: A is symmetric (one-sided compression, V_R = V_L);
  *               0: general A (row and column fill compressed together);
- *               -1: detect from the values. */
+ *               -1: detect from the values.
+ *   coarse_fp64_dofs  mixed form only: levels with at most this many
+ *               unknowns keep float64 storage (0 selects 32768). */
 typedef struct hs_opts {
     double eps;
     int32_t fixed_rank;
@@ -102,6 +112,7 @@ typedef struct hs_opts {
     int32_t symmetric;
     int32_t keep_levels; /* 1: keep a host copy of every level's starting matrix
                             (test hook, see hs_factor_level_matrix); 0: off */
+    int32_t coarse_fp64_dofs;
 } hs_opts;
 
 /* Opaque factorization; device resident; owned by the library until hs_free. */

@@ -62,6 +62,7 @@ class hs_opts(ctypes.Structure):
         ("precision", ctypes.c_int32),
         ("symmetric", ctypes.c_int32),
         ("keep_levels", ctypes.c_int32),
+        ("coarse_fp64_dofs", ctypes.c_int32),
     ]
 
 
@@ -207,11 +208,13 @@ class Factor:
     """A device-resident factorization (hs_factor)."""
 
     def __init__(self, row_ptr, col_idx, val, dims, eps: float, leaf: int = 64, symmetric: int = -1,
-                 precision: int = HS_FP64, fixed_rank: int = 0, keep_levels: bool = False, stream=None):
+                 precision: int = HS_FP64, fixed_rank: int = 0, keep_levels: bool = False, stream=None,
+                 coarse_fp64_dofs: int = 0):
         keep: list = []
         A = _csr_struct(row_ptr, col_idx, val, keep)
         self.n = A.n
-        opts = hs_opts(float(eps), int(fixed_rank), int(leaf), int(precision), int(symmetric), 1 if keep_levels else 0)
+        opts = hs_opts(float(eps), int(fixed_rank), int(leaf), int(precision), int(symmetric), 1 if keep_levels else 0,
+                       int(coarse_fp64_dofs))
         geom = _geom(dims)
         h = _P()
         _check(lib().hs_factor(ctypes.byref(A), ctypes.byref(geom), ctypes.byref(opts), _stream(stream), ctypes.byref(h)), "hs_factor")

@@ -19,14 +19,17 @@ constexpr int PANEL = 32;     // column panel of the neighbour / fill update ker
 constexpr int SCHUR_T = 64;   // output tile of the Schur-complement GEMM
 constexpr int MAX_M = 512;    // largest cluster the kernels accept
 // Fill whose largest row norm is at most this fraction of ||A_ss||_F is the
-// rounding noise of earlier Schur updates and is treated as zero.
+// rounding noise of earlier Schur updates and is treated as zero; levels
+// stored in float32 (mixed form) carry float32 rounding noise.
 constexpr double FILL_NOISE_FLOOR = 1e-12;
+constexpr double FILL_NOISE_FLOOR_F32 = 1e-6;
 
 // Pointers into LDS carry their address space: routines instantiated for
 // them compile to ds_* instructions rather than generic (flat) accesses.
 typedef __attribute__((address_space(3))) double lds_f64;
 typedef __attribute__((address_space(3))) int lds_i32;
 typedef __attribute__((address_space(1))) double glb_f64;  // global memory
+typedef __attribute__((address_space(1))) float glb_f32;
 __device__ inline lds_f64* to_lds(double* p) { return (lds_f64*)p; }
 __device__ inline lds_i32* to_lds(int* p) { return (lds_i32*)p; }
 
@@ -41,7 +44,8 @@ struct LevelDev {
     int* k;                   // [ncl] coarse sizes after elimination (rank)
     int* flag;                // [ncl] 1 = breakdown in an unpivoted LU
     const int64_t* blk_off;   // [nblk] element offset of every block (capacity m_a x m_b, ld m_a)
-    double* blocks;
+    double* blocks;           // element type of the level's storage (double, or float in the mixed form)
+    int f32;                  // storage element type is float
     const int* diag_blk;      // [ncl] block id of (s, s)
     const int* nbr_ptr;       // [ncl+1] neighbours n(s)
     const int* nbr_id;
@@ -59,7 +63,7 @@ struct LevelDev {
     const int64_t* pair_base; // [ncl] index of pair (0,0) of s in pair_blk
     const int* pair_blk;      // block id of (a_i, a_j) at pair_base[s] + i*nb + j
     const int64_t* rec_off;   // [ncl] record: T_L' (m^2), T_R' (m^2), E_R (m x ncap, ld m), E_L (ncap x m, ld ncap)
-    double* rec;
+    double* rec;              // same element type as blocks
     const int64_t* ws_off;    // [ncl] per-colour workspace of every cluster
     double* ws;
 };
@@ -69,7 +73,15 @@ enum WsSlot { WS_AINV = 0, WS_LINV, WS_UINV, WS_U, WS_X, WS_SL, WS_SR, WS_TL, WS
 __host__ __device__ inline int64_t ws_slots(int gram_splits) { return WS_GP + gram_splits; }
 
 __device__ inline int cur_size(const LevelDev& L, int a, int before) { return before ? L.k[a] : L.m[a]; }
-__device__ inline double* blk_ptr(const LevelDev& L, int id) { return L.blocks + L.blk_off[id]; }
+// Block id / record of cluster s in the level's storage type T (offsets count elements).
+template <class T>
+__device__ inline T* blk_t(const LevelDev& L, int id) {
+    return reinterpret_cast<T*>(L.blocks) + L.blk_off[id];
+}
+template <class T>
+__device__ inline T* rec_t(const LevelDev& L, int s) {
+    return reinterpret_cast<T*>(L.rec) + L.rec_off[s];
+}
 
 // ---------------------------------------------------------------- reductions
 
@@ -275,6 +287,117 @@ __device__ inline void mfma_tile64_visit(const v4d acc[2][2], const Fn& f) {
         for (int j = 0; j < 2; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r) f((i * 2 + j) * 4 + r, wm + 16 * i + lr, wn + 16 * j + lk + 4 * r, acc[i][j][r]);
+}
+
+// ------------------------------------------------- BF16 tile core (mixed form)
+// One 64 x 64 tile of D = Left (64 x K) * Right (K x 64) on the BF16 matrix
+// cores with FP32 accumulation (v_mfma_f32_16x16x16_bf16): 4 waves as 2 x 2
+// quarters of 32 x 32, each 2 x 2 blocks of 16 x 16.  Instruction layout:
+// operand a of lane l holds A[l%16][4(l/16) + i], operand b holds
+// B[4(l/16) + i][l%16] (i = 0..3), result r of lane l is D[4(l/16) + r][l%16].
+// As in the FP64 core the transposed block is computed, so lane l%16 indexes
+// rows of D.  Every float operand is split into three BF16 parts
+// x = hi + mid + lo (8 + 8 + 8 significand bits, nearest-even rounding at each
+// step) and the six products whose parts sum to at most 2 are accumulated, so
+// the tile carries float32 accuracy on the BF16 units.
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef short v4s __attribute__((ext_vector_type(4)));
+constexpr int NSPLIT = 3;
+struct MfmaSmemB {
+    unsigned short a[NSPLIT][MKC][MT + 2];  // a[part][k][row] = Left(row, k)
+    unsigned short b[NSPLIT][MKC][MT + 2];  // b[part][k][col] = Right(k, col)
+};
+typedef __attribute__((address_space(3))) MfmaSmemB lds_smemb;
+__device__ inline lds_smemb* to_lds(MfmaSmemB* p) { return (lds_smemb*)p; }
+
+__device__ inline unsigned short bf16_rne(float x) {
+    const unsigned int u = __float_as_uint(x);
+    return (unsigned short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ inline float bf16_to_f32(unsigned short h) { return __uint_as_float((unsigned int)h << 16); }
+
+template <class LoadL, class LoadR>
+__device__ inline void mfma_tile64_bf16(int K, const LoadL& la, const LoadR& lb, lds_smemb* sm, v4f acc[2][2]) {
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wm = (w & 1) * 32, wn = (w >> 1) * 32;
+    const int lr = lane & 15, lk = lane >> 4;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+    constexpr int PER = MT * MKC / WG;
+    float ra[PER], rb[PER];
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int t = 0; t < PER; ++t) {
+            const int e = tid + t * WG;
+            const int r = e % MT, kk = e / MT;
+            ra[t] = (k0 + kk < K) ? (float)la(r, k0 + kk) : 0.f;
+            const int kb = e % MKC, c = e / MKC;
+            rb[t] = (k0 + kb < K) ? (float)lb(k0 + kb, c) : 0.f;
+        }
+    };
+    auto split = [](float x, unsigned short* h) {
+#pragma unroll
+        for (int q = 0; q < NSPLIT; ++q) {
+            h[q] = bf16_rne(x);
+            x -= bf16_to_f32(h[q]);
+        }
+    };
+    if (K > 0) fetch(0);
+    for (int k0 = 0; k0 < K; k0 += MKC) {
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < PER; ++t) {
+            const int e = tid + t * WG;
+            unsigned short ha[NSPLIT], hb[NSPLIT];
+            split(ra[t], ha);
+            split(rb[t], hb);
+#pragma unroll
+            for (int q = 0; q < NSPLIT; ++q) {
+                sm->a[q][e / MT][e % MT] = ha[q];
+                sm->b[q][e % MKC][e / MKC] = hb[q];
+            }
+        }
+        __syncthreads();
+        if (k0 + MKC < K) fetch(k0 + MKC);
+        v4s av[NSPLIT][2], bv[NSPLIT][2];
+#pragma unroll
+        for (int q = 0; q < NSPLIT; ++q)
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    av[q][i][u] = (short)sm->a[q][4 * lk + u][wm + 16 * i + lr];
+                    bv[q][i][u] = (short)sm->b[q][4 * lk + u][wn + 16 * i + lr];
+                }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                // smallest terms first: (lo,hi) (hi,lo) (mid,mid) (mid,hi) (hi,mid) (hi,hi)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(bv[2][j], av[0][i], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(bv[0][j], av[2][i], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(bv[1][j], av[1][i], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(bv[1][j], av[0][i], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(bv[0][j], av[1][i], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(bv[0][j], av[0][i], acc[i][j], 0, 0, 0);
+            }
+    }
+}
+
+// Visit the BF16 tile's results: f(idx, row, col, value), idx in [0, 16).
+template <class Fn>
+__device__ inline void mfma_tile64_bf16_visit(const v4f acc[2][2], const Fn& f) {
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wm = (w & 1) * 32, wn = (w >> 1) * 32;
+    const int lr = lane & 15, lk = lane >> 4;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) f((i * 2 + j) * 4 + r, wm + 16 * i + lr, wn + 16 * j + 4 * lk + r, acc[i][j][r]);
 }
 
 // ------------------------------------------------------------ cooperative GEMM

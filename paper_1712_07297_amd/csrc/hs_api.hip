@@ -198,6 +198,8 @@ struct ColourHost {
 struct LevelData {
     int ncl = 0;
     int nblk = 0;
+    int f32 = 0;                                   // blocks and records stored in float (mixed form)
+    size_t esz() const { return f32 ? sizeof(float) : sizeof(double); }
     std::vector<int> m, k;                         // sizes at the start, ranks after
     std::vector<int64_t> blk_off;
     int64_t block_elems = 0;
@@ -250,6 +252,9 @@ struct hs_symbolic_s {
 namespace hs {
 
 static const char* kVersion = "hs 0.1 (gfx950)";
+// Mixed form: levels with at most this many unknowns keep float64 storage
+// (default of hs_opts.coarse_fp64_dofs).
+constexpr int64_t MIXED_FP64_DOFS = 32768;
 
 // =============================================================== validation
 
@@ -439,6 +444,7 @@ static void bind_level(LevelData& LD, const std::vector<size_t>& offs, const hs_
     D.flag = (int*)P(2);
     D.blk_off = (const int64_t*)P(3);
     D.blocks = LD.blocks.as<double>();
+    D.f32 = LD.f32;
     D.diag_blk = (const int*)P(4);
     D.nbr_ptr = (const int*)P(5);
     D.nbr_id = (const int*)P(6);
@@ -480,6 +486,7 @@ static void bind_level(LevelData& LD, const std::vector<size_t>& offs, const hs_
     SD.ncap = D.ncap;
     SD.rec_off = D.rec_off;
     SD.rec = D.rec;
+    SD.f32 = LD.f32;
 }
 
 // =============================================================== flop model
@@ -511,8 +518,17 @@ static double cluster_flops(int m, int k, int nt, int wt, bool symmetric) {
 static int keep_level_matrix(hs_factor_s* F, LevelData& LD, hipStream_t st) {
     const LevelSymbolic& S = F->sym.levels[&LD - F->levels.data()];
     std::vector<double> blk(LD.block_elems);
-    if (LD.block_elems)
-        HIP_TRY(hipMemcpyAsync(blk.data(), LD.blocks.p, LD.block_elems * sizeof(double), hipMemcpyDeviceToHost, st));
+    if (LD.block_elems) {
+        if (LD.f32) {
+            std::vector<float> bf(LD.block_elems);
+            HIP_TRY(hipMemcpyAsync(bf.data(), LD.blocks.p, LD.block_elems * sizeof(float), hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipStreamSynchronize(st));
+            for (int64_t i = 0; i < LD.block_elems; ++i) blk[i] = bf[i];
+        } else {
+            HIP_TRY(hipMemcpyAsync(blk.data(), LD.blocks.p, LD.block_elems * sizeof(double), hipMemcpyDeviceToHost,
+                                   st));
+        }
+    }
     HIP_TRY(hipStreamSynchronize(st));
     std::vector<int64_t> off(LD.ncl + 1, 0);
     for (int c = 0; c < LD.ncl; ++c) off[c + 1] = off[c] + LD.m[c];
@@ -665,17 +681,27 @@ static int factor_impl(hs_factor_s* F, const hs_csr* A, const hs_geometry* G, hi
         Blob blob;
         rc = plan_level(F, lvl, blob, offs);
         if (rc) return rc;
+        // A level whose clusters all neighbour each other has no fill: it is
+        // factored densely (Alg. 1, conventional factorization).
+        bool complete = true;
+        for (int c = 0; c < S.ncl && complete; ++c)
+            if (S.adj_ptr[c + 1] - S.adj_ptr[c] != S.ncl - 1 || S.order[c] != c) complete = false;
+        // mixed form: float storage except on the coarse levels
+        int64_t level_dofs = 0;
+        for (int c = 0; c < S.ncl; ++c) level_dofs += LD.m[c];
+        const int64_t fp64_dofs = F->opts.coarse_fp64_dofs > 0 ? F->opts.coarse_fp64_dofs : MIXED_FP64_DOFS;
+        LD.f32 = (F->opts.precision == HS_MIXED && !complete && level_dofs > fp64_dofs) ? 1 : 0;
         if (!LD.meta.alloc(blob.data.size())) return fail(HS_ERR_NOMEM, "level metadata");
         HIP_TRY(hipMemcpyAsync(LD.meta.p, blob.data.data(), blob.data.size(), hipMemcpyHostToDevice, st));
-        if (!LD.blocks.alloc(LD.block_elems * sizeof(double))) return fail(HS_ERR_NOMEM, "block store");
-        if (!LD.rec.alloc(LD.rec_elems * sizeof(double))) return fail(HS_ERR_NOMEM, "factor records");
+        if (!LD.blocks.alloc(LD.block_elems * LD.esz())) return fail(HS_ERR_NOMEM, "block store");
+        if (!LD.rec.alloc(LD.rec_elems * LD.esz())) return fail(HS_ERR_NOMEM, "factor records");
         if (!F->ws.ensure(LD.ws_elems * sizeof(double))) return fail(HS_ERR_NOMEM, "workspace");
         bind_level(LD, offs, F);
-        launch_fill_zero(LD.blocks.as<double>(), LD.block_elems, st);
+        launch_fill_zero(LD.blocks.p, LD.block_elems, LD.f32, st);
         if (lvl == 0) {
             launch_assemble0(n, F->A_row.as<int64_t>(), F->A_col.as<int32_t>(), F->A_val.as<double>(),
                              F->cluster_of.as<int>(), F->local_of.as<int>(), LD.dev.m, (const int*)(LD.meta.as<char>() + offs[22]),
-                             (const int*)(LD.meta.as<char>() + offs[23]), LD.dev.blk_off, LD.dev.blocks, st);
+                             (const int*)(LD.meta.as<char>() + offs[23]), LD.dev.blk_off, LD.dev.blocks, LD.f32, st);
         } else {
             // parent blocks from the children's coarse blocks
             const LevelSymbolic& PS = F->sym.levels[lvl - 1];
@@ -699,7 +725,8 @@ static int factor_impl(hs_factor_s* F, const hs_csr* A, const hs_geometry* G, hi
                 ProfScope ps(PF_MERGE, st);
                 launch_merge(LD.nblk, (const int*)(mbuf.as<char>() + o_r), (const int*)(mbuf.as<char>() + o_c),
                              (const int*)(mbuf.as<char>() + o_s), prev->dev.k, prev->dev.m, prev->dev.blk_off,
-                             prev->dev.blocks, LD.dev.m, LD.dev.blk_off, LD.dev.blocks, prev->ncl, st);
+                             prev->dev.blocks, prev->f32, LD.dev.m, LD.dev.blk_off, LD.dev.blocks, LD.f32, prev->ncl,
+                             st);
             }
             HIP_TRY(hipStreamSynchronize(st));  // merge metadata and the children's blocks are freed below
             prev->blocks.release();
@@ -709,11 +736,6 @@ static int factor_impl(hs_factor_s* F, const hs_csr* A, const hs_geometry* G, hi
             rc = keep_level_matrix(F, LD, st);
             if (rc) return rc;
         }
-        // A level whose clusters all neighbour each other has no fill: it is
-        // factored densely (Alg. 1, conventional factorization).
-        bool complete = true;
-        for (int c = 0; c < S.ncl && complete; ++c)
-            if (S.adj_ptr[c + 1] - S.adj_ptr[c] != S.ncl - 1 || S.order[c] != c) complete = false;
         if (complete) {
             rc = factor_dense_level(F, lvl, st);
             if (rc) return rc;
@@ -763,7 +785,7 @@ static int factor_impl(hs_factor_s* F, const hs_csr* A, const hs_geometry* G, hi
                 const double f = LD.m[c] - LD.k[c], nt = ntot[c];
                 if (LD.m[c] == 0 || f == 0 || nt == 0) continue;
                 g_prof[PF_SCHUR].flops += 2.0 * f * nt * nt;
-                g_prof[PF_SCHUR].bytes += 8.0 * (2.0 * f * nt + 2.0 * nt * nt);
+                g_prof[PF_SCHUR].bytes += (double)LD.esz() * (2.0 * f * nt + 2.0 * nt * nt);
             }
         }
         for (int c = 0; c < LD.ncl; ++c) {
@@ -836,7 +858,7 @@ static int factor_impl(hs_factor_s* F, const hs_csr* A, const hs_geometry* G, hi
                 const int a = S.adj[e];
                 nt += S.pos[a] < S.pos[c] ? LD.k[a] : LD.m[a];
             }
-            rec_bytes += 8.0 * (2.0 * m * m + 2.0 * f * nt);
+            rec_bytes += (double)LD.esz() * (2.0 * m * m + 2.0 * f * nt);
             apply_flops += 4.0 * m * m + 4.0 * f * nt;
         }
     }
@@ -966,7 +988,11 @@ static int pcg_impl(hs_factor_s* F, int nrhs, const double* B, int64_t ldb, doub
     HIP_TRY(hipMemcpyAsync(d_one, one.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(d_mone, mone.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(d_zero, zero.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st));
-    std::vector<double> bn(nrhs), rz(nrhs), rzn(nrhs), pq(nrhs), rr(nrhs), alpha(nrhs), beta(nrhs);
+    std::vector<double> bn(nrhs), rz(nrhs), rzn(nrhs), rzo(nrhs, 0.0), pq(nrhs), rr(nrhs), alpha(nrhs), beta(nrhs);
+    // A float32 factor is a slightly nonlinear preconditioner: the flexible
+    // (Polak-Ribiere) beta = r_new^T (z_new - z_old) / r_old^T z_old keeps CG
+    // converging; with a float64 factor the classical beta is used.
+    const bool flexible = F->opts.precision == HS_MIXED;
     rc = dots_host(F, n, B, ldb, B, ldb, nrhs, part, d_dot, bn.data(), st);
     if (rc) return rc;
     for (auto& v : bn) v = v > 0 ? std::sqrt(v) : 1.0;
@@ -1000,12 +1026,16 @@ static int pcg_impl(hs_factor_s* F, int nrhs, const double* B, int64_t ldb, doub
             nact += active[j];
         }
         if (nact == 0) break;
+        if (flexible) {
+            rc = dots_host(F, n, R, n, Zv, n, nrhs, part, d_dot, rzo.data(), st);
+            if (rc) return rc;
+        }
         rc = solve_impl(F, nrhs, R, n, Zv, n, st);
         if (rc) return rc;
         rc = dots_host(F, n, R, n, Zv, n, nrhs, part, d_dot, rzn.data(), st);
         if (rc) return rc;
         for (int j = 0; j < nrhs; ++j) {
-            beta[j] = (active[j] && rz[j] != 0.0) ? rzn[j] / rz[j] : 0.0;
+            beta[j] = (active[j] && rz[j] != 0.0) ? (rzn[j] - rzo[j]) / rz[j] : 0.0;
             rz[j] = rzn[j];
         }
         HIP_TRY(hipMemcpyAsync(d_beta, beta.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st));
@@ -1176,7 +1206,7 @@ int hs_factor(const hs_csr* A, const hs_geometry* geom, const hs_opts* opts, voi
     if (!A || !geom || !opts || !A->row_ptr || (A->nnz > 0 && (!A->col_idx || !A->val)))
         return fail(HS_ERR_ARG, "null argument");
     if (A->n <= 0 || A->nnz < 0 || A->n > INT32_MAX) return fail(HS_ERR_ARG, "bad matrix size");
-    if (!(opts->eps >= 0.0) || opts->leaf_size <= 0 || opts->fixed_rank < 0 ||
+    if (!(opts->eps >= 0.0) || opts->leaf_size <= 0 || opts->fixed_rank < 0 || opts->coarse_fp64_dofs < 0 ||
         (opts->precision != HS_FP64 && opts->precision != HS_MIXED))
         return fail(HS_ERR_ARG, "bad options");
     if (geom->dim < 1 || geom->dim > 3 || (int64_t)geom->nx * geom->ny * geom->nz != A->n)
@@ -1265,22 +1295,27 @@ int hs_factor_record(hs_factor_t F, int32_t level, int32_t cluster, int32_t whic
     HIP_TRY(hipMemcpy(ncap.data(), LD.dev.ncap + cluster, sizeof(int), hipMemcpyDeviceToHost));
     HIP_TRY(hipMemcpy(roff.data(), LD.dev.rec_off + cluster, sizeof(int64_t), hipMemcpyDeviceToHost));
     const int64_t MM = (int64_t)m * m;
-    const double* base = LD.rec.as<double>() + roff[0];
-    int64_t r, c, ld;
-    const double* src;
+    int64_t r, c, ld, e0;
     switch (which) {
-        case 0: r = m; c = m; ld = m; src = base; break;
-        case 1: r = m; c = m; ld = m; src = base + MM; break;
-        case 2: r = f; c = ntot[0]; ld = m; src = base + 2 * MM; break;
-        default: r = ntot[0]; c = f; ld = ncap[0]; src = base + 2 * MM + (int64_t)m * ncap[0]; break;
+        case 0: r = m; c = m; ld = m; e0 = 0; break;
+        case 1: r = m; c = m; ld = m; e0 = MM; break;
+        case 2: r = f; c = ntot[0]; ld = m; e0 = 2 * MM; break;
+        default: r = ntot[0]; c = f; ld = ncap[0]; e0 = 2 * MM + (int64_t)m * ncap[0]; break;
     }
     *rows = r;
     *cols = c;
     if (!out) return HS_OK;  // shape query
     if (r * c > cap) return fail(HS_ERR_ARG, "output too small");
-    if (r * c > 0)
-        HIP_TRY(hipMemcpy2D(out, r * sizeof(double), src, ld * sizeof(double), r * sizeof(double), c,
-                            hipMemcpyDeviceToHost));
+    if (r * c == 0) return HS_OK;
+    const size_t es = LD.esz();
+    const char* src = LD.rec.as<char>() + (roff[0] + e0) * es;
+    if (!LD.f32) {
+        HIP_TRY(hipMemcpy2D(out, r * sizeof(double), src, ld * es, r * es, c, hipMemcpyDeviceToHost));
+    } else {
+        std::vector<float> tmp((size_t)(r * c));
+        HIP_TRY(hipMemcpy2D(tmp.data(), r * es, src, ld * es, r * es, c, hipMemcpyDeviceToHost));
+        for (size_t i = 0; i < tmp.size(); ++i) out[i] = tmp[i];
+    }
     return HS_OK;
 }
 

@@ -164,7 +164,7 @@ int dense_level_factor(double* D, int64_t N, const int* pat_ptr, const int* pat,
                        const int64_t* blk_off, const double* blocks, int ncl, int nblk, double* inv, int* flag,
                        const int* ncap, const int64_t* rec_off, double* rec, const std::vector<int>& m_host,
                        const std::vector<int64_t>& off_host, hipStream_t st) {
-    launch_fill_zero(D, N * N, st);
+    launch_fill_zero(D, N * N, 0, st);
     if (nblk > 0)
         hipLaunchKernelGGL(k_dense_assemble, dim3(nblk), dim3(256), 0, st, pat_ptr, pat, m, off, blk_off, blocks, D,
                            (int64_t)N, ncl);

@@ -18,6 +18,8 @@
 //   schur     A_ab -= E_L[a] E_R[b] for every ordered neighbour pair (Eq. elim).
 // A cluster without fill keeps E_s = I (Sec. 2.2): T_L' = L^{-1}, T_R' = U^{-1}.
 // Blocks of a processed cluster keep its coarse rows / columns first.
+#include <type_traits>
+
 #include "device_common.h"
 #include "kernels.h"
 
@@ -53,6 +55,7 @@ __device__ inline int find_cluster64(const int64_t* pre, int n, int64_t q) {
 // a general matrix, + B(t,s)^T B(t,s)): the Gram matrix F F^T of the fill
 // (Eq. lra) in gram_splits partial sums.  Each 64 x 64 tile of the partial is
 // accumulated over all partners of the split in registers and stored once.
+template <class T>
 __global__ void __launch_bounds__(WG) k_gram(LevelDev L, const int* __restrict__ clist) {
     __shared__ GemmSmem sm;
     const int s = clist[blockIdx.y];
@@ -72,13 +75,13 @@ __global__ void __launch_bounds__(WG) k_gram(LevelDev L, const int* __restrict__
                 const int t = L.fill_id[e];
                 const int ct = cur_size(L, t, L.fill_before[e]);
                 if (ct == 0) continue;
-                const double* Bst = blk_ptr(L, L.fill_bst[e]);  // M x ct, ld M
+                const T* Bst = blk_t<T>(L, L.fill_bst[e]);  // M x ct, ld M
                 mfma_tile64_acc(
                     ct, [&](int r, int k) { return r0 + r < M ? Bst[(r0 + r) + (int64_t)k * M] : 0.0; },
                     [&](int k, int c) { return c0 + c < M ? Bst[(c0 + c) + (int64_t)k * M] : 0.0; }, sm_l, acc);
                 if (!L.symmetric) {
                     const int mt = L.m[t];
-                    const double* Bts = blk_ptr(L, L.fill_bts[e]);  // ct x M, ld m_t
+                    const T* Bts = blk_t<T>(L, L.fill_bts[e]);  // ct x M, ld m_t
                     mfma_tile64_acc(
                         ct, [&](int r, int k) { return r0 + r < M ? Bts[k + (int64_t)(r0 + r) * mt] : 0.0; },
                         [&](int k, int c) { return c0 + c < M ? Bts[k + (int64_t)(c0 + c) * mt] : 0.0; }, sm_l, acc);
@@ -105,7 +108,10 @@ __global__ void k_gram_reduce(LevelDev L, const int* __restrict__ clist) {
 
 void launch_gram(const LevelDev& L, const ColourDev& C, hipStream_t st) {
     if (C.n == 0) return;
-    hipLaunchKernelGGL(k_gram, dim3(L.gram_splits, C.n), dim3(WG), 0, st, L, C.clist);
+    if (L.f32)
+        hipLaunchKernelGGL(k_gram<float>, dim3(L.gram_splits, C.n), dim3(WG), 0, st, L, C.clist);
+    else
+        hipLaunchKernelGGL(k_gram<double>, dim3(L.gram_splits, C.n), dim3(WG), 0, st, L, C.clist);
     const int64_t mm = (int64_t)C.max_m * C.max_m;
     if (L.gram_splits > 1 && mm > 0) {
         hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((mm + 255) / 256), C.n), dim3(256), 0, st, L, C.clist);
@@ -246,7 +252,7 @@ __device__ void wg_complement(PX X, int M, int K, PV V, int ldv, PT tau_sh) {
 // Per-cluster elimination operators.  The working M x M matrix W lives in
 // LDS when the colour's largest cluster fits (lds_m), else in the cluster's
 // L2-resident workspace; every dense step below reuses it in turn.
-template <bool INLDS>
+template <bool INLDS, class T>
 __global__ void __launch_bounds__(WG) k_pivot(LevelDev L, const int* __restrict__ clist) {
     extern __shared__ double dyn[];  // M * M doubles for the largest cluster M of the colour (INLDS)
     __shared__ GemmSmem sm;
@@ -301,9 +307,9 @@ __global__ void __launch_bounds__(WG) k_pivot(LevelDev L, const int* __restrict_
     lds_f64* dsh_l = to_lds(dsh);
     lds_smem* sm_l = to_lds(&sm);
     lds_f64* scr = (lds_f64*)sm_l;  // 2080 doubles, free outside the GEMMs
-    double* TLp = L.rec + L.rec_off[s];
-    double* TRp = TLp + MM;
-    double* Bss = blk_ptr(L, L.diag_blk[s]);
+    T* TLp = rec_t<T>(L, s);
+    T* TRp = TLp + MM;
+    T* Bss = blk_t<T>(L, L.diag_blk[s]);
 
     // ---- 1. rank of the fill (Eq. lra)
     int kk;
@@ -313,7 +319,7 @@ __global__ void __launch_bounds__(WG) k_pivot(LevelDev L, const int* __restrict_
         kk = M;  // exact mode
     } else {
         double ass2 = 0.0;  // ||A_ss||_F^2 (noise floor of the fill)
-        for (int64_t e = tid; e < MM; e += blockDim.x) ass2 = fma(Bss[e], Bss[e], ass2);
+        for (int64_t e = tid; e < MM; e += blockDim.x) ass2 = fma((double)Bss[e], (double)Bss[e], ass2);
         ass2 = block_sum(ass2, red_l);
         // W = the Gram matrix (partials already summed into the first slot)
         for (int64_t e = tid; e < MM; e += blockDim.x) W[e] = ws[WS_GP * MM + e];
@@ -322,7 +328,8 @@ __global__ void __launch_bounds__(WG) k_pivot(LevelDev L, const int* __restrict_
         double dmax = 0.0;
         for (int i = tid; i < M; i += blockDim.x) dmax = fmax(dmax, W[i + (int64_t)i * M]);
         dmax = block_max(dmax, red_l);
-        if (dmax <= FILL_NOISE_FLOOR * FILL_NOISE_FLOOR * ass2)
+        constexpr double floor_ = std::is_same<T, float>::value ? FILL_NOISE_FLOOR_F32 : FILL_NOISE_FLOOR;
+        if (dmax <= floor_ * floor_ * ass2)
             kk = 0;
         else
             kk = wg_pivoted_cholesky(W, M, L.eps, L.fixed_rank, to_lds(perm), dsh_l, to_lds(isc));
@@ -407,11 +414,17 @@ __global__ void __launch_bounds__(WG) k_pivot(LevelDev L, const int* __restrict_
 
 void launch_pivot(const LevelDev& L, const ColourDev& C, hipStream_t st) {
     if (C.n == 0) return;
+    const size_t shmem = (size_t)C.max_m * C.max_m * sizeof(double);
     if (C.max_m <= LDS_M) {
-        const size_t shmem = (size_t)C.max_m * C.max_m * sizeof(double);
-        hipLaunchKernelGGL(k_pivot<true>, dim3(C.n), dim3(WG), shmem, st, L, C.clist);
+        if (L.f32)
+            hipLaunchKernelGGL((k_pivot<true, float>), dim3(C.n), dim3(WG), shmem, st, L, C.clist);
+        else
+            hipLaunchKernelGGL((k_pivot<true, double>), dim3(C.n), dim3(WG), shmem, st, L, C.clist);
     } else {
-        hipLaunchKernelGGL(k_pivot<false>, dim3(C.n), dim3(WG), 0, st, L, C.clist);
+        if (L.f32)
+            hipLaunchKernelGGL((k_pivot<false, float>), dim3(C.n), dim3(WG), 0, st, L, C.clist);
+        else
+            hipLaunchKernelGGL((k_pivot<false, double>), dim3(C.n), dim3(WG), 0, st, L, C.clist);
     }
 }
 
@@ -424,6 +437,7 @@ int panel_width(int max_m) {
     return pw < 1 ? 1 : (pw > PANEL ? PANEL : pw);
 }
 
+template <class T>
 __global__ void __launch_bounds__(WG) k_fill_update(LevelDev L, ColourDev C, int pw) {
     extern __shared__ double dyn[];
     const int q = blockIdx.y;
@@ -442,8 +456,8 @@ __global__ void __launch_bounds__(WG) k_fill_update(LevelDev L, ColourDev C, int
     const double* ws = L.ws + L.ws_off[s];
     const double* CU = ws + WS_CU * MM;
     const double* UC = ws + WS_UC * MM;
-    double* Bst = blk_ptr(L, L.fill_bst[e]);
-    double* Bts = blk_ptr(L, L.fill_bts[e]);
+    T* Bst = blk_t<T>(L, L.fill_bst[e]);
+    T* Bts = blk_t<T>(L, L.fill_bts[e]);
     const int mt = L.m[t];
     double* P1 = dyn;                    // M x w (ld M): B(s, t)[:, panel]
     double* P2 = dyn + (int64_t)M * pw;  // w x M (ld pw): B(t, s)[panel, :]
@@ -465,8 +479,8 @@ __global__ void __launch_bounds__(WG) k_fill_update(LevelDev L, ColourDev C, int
             const double src = L.symmetric ? P1[l + j * M] : P2[j + l * pw];
             b = fma(src, UC[l + (int64_t)i * M], b);
         }
-        Bst[i + (int64_t)(c0 + j) * M] = a;
-        Bts[(c0 + j) + (int64_t)i * mt] = b;
+        Bst[i + (int64_t)(c0 + j) * M] = (T)a;
+        Bts[(c0 + j) + (int64_t)i * mt] = (T)b;
     }
 }
 
@@ -474,12 +488,16 @@ void launch_fill_update(const LevelDev& L, const ColourDev& C, hipStream_t st) {
     if (C.fill_total == 0 || C.panels == 0) return;
     const int pw = panel_width(C.max_m);
     const size_t shmem = (size_t)2 * C.max_m * pw * sizeof(double);
-    hipLaunchKernelGGL(k_fill_update, dim3(C.panels, C.fill_total), dim3(WG), shmem, st, L, C, pw);
+    if (L.f32)
+        hipLaunchKernelGGL(k_fill_update<float>, dim3(C.panels, C.fill_total), dim3(WG), shmem, st, L, C, pw);
+    else
+        hipLaunchKernelGGL(k_fill_update<double>, dim3(C.panels, C.fill_total), dim3(WG), shmem, st, L, C, pw);
 }
 
 // ======================================================== neighbour update
 // [E_R; B(s^c, a)] = T_L' B(s, a) and [E_L[a], B(a, s^c)] = B(a, s) T_R',
 // one column panel of one neighbour per workgroup (in place on the blocks).
+template <class T>
 __global__ void __launch_bounds__(WG) k_nbr_update(LevelDev L, ColourDev C, int pw) {
     extern __shared__ double dyn[];
     const int q = blockIdx.y;
@@ -497,13 +515,13 @@ __global__ void __launch_bounds__(WG) k_nbr_update(LevelDev L, ColourDev C, int 
     if (w <= 0) return;
     const int64_t MM = (int64_t)M * M;
     const int ncap = L.ncap[s];
-    const double* TLp = L.rec + L.rec_off[s];
-    const double* TRp = TLp + MM;
-    double* ER = L.rec + L.rec_off[s] + 2 * MM;     // f x ntot, ld M
-    double* EL = ER + (int64_t)M * ncap;            // ntot x f, ld ncap
+    const T* TLp = rec_t<T>(L, s);
+    const T* TRp = TLp + MM;
+    T* ER = rec_t<T>(L, s) + 2 * MM;     // f x ntot, ld M
+    T* EL = ER + (int64_t)M * ncap;      // ntot x f, ld ncap
     const int off = L.nbr_noff[e];
-    double* Bsa = blk_ptr(L, L.nbr_bsa[e]);
-    double* Bas = blk_ptr(L, L.nbr_bas[e]);
+    T* Bsa = blk_t<T>(L, L.nbr_bsa[e]);
+    T* Bas = blk_t<T>(L, L.nbr_bas[e]);
     const int ma = L.m[a];
     double* P1 = dyn;                     // M x w
     double* P2 = dyn + (int64_t)M * pw;   // w x M (ld pw)
@@ -519,20 +537,20 @@ __global__ void __launch_bounds__(WG) k_nbr_update(LevelDev L, ColourDev C, int 
     for (int x = threadIdx.x; x < M * w; x += blockDim.x) {
         int i = x % M, j = x / M;
         double acc = 0.0;
-        for (int l = 0; l < M; ++l) acc = fma(TLp[i + (int64_t)l * M], P1[l + j * M], acc);
+        for (int l = 0; l < M; ++l) acc = fma((double)TLp[i + (int64_t)l * M], P1[l + j * M], acc);
         if (i < f)
-            ER[i + (int64_t)(off + c0 + j) * M] = acc;
+            ER[i + (int64_t)(off + c0 + j) * M] = (T)acc;
         else
-            Bsa[(i - f) + (int64_t)(c0 + j) * M] = acc;
+            Bsa[(i - f) + (int64_t)(c0 + j) * M] = (T)acc;
     }
     for (int x = threadIdx.x; x < M * w; x += blockDim.x) {
         int j = x % w, c = x / w;
         double acc = 0.0;
-        for (int l = 0; l < M; ++l) acc = fma(P2[j + l * pw], TRp[l + (int64_t)c * M], acc);
+        for (int l = 0; l < M; ++l) acc = fma(P2[j + l * pw], (double)TRp[l + (int64_t)c * M], acc);
         if (c < f)
-            EL[(off + c0 + j) + (int64_t)c * ncap] = acc;
+            EL[(off + c0 + j) + (int64_t)c * ncap] = (T)acc;
         else
-            Bas[(c0 + j) + (int64_t)(c - f) * ma] = acc;
+            Bas[(c0 + j) + (int64_t)(c - f) * ma] = (T)acc;
     }
 }
 
@@ -540,7 +558,10 @@ void launch_nbr_update(const LevelDev& L, const ColourDev& C, hipStream_t st) {
     if (C.nbr_total == 0 || C.panels == 0) return;
     const int pw = panel_width(C.max_m);
     const size_t shmem = (size_t)2 * C.max_m * pw * sizeof(double);
-    hipLaunchKernelGGL(k_nbr_update, dim3(C.panels, C.nbr_total), dim3(WG), shmem, st, L, C, pw);
+    if (L.f32)
+        hipLaunchKernelGGL(k_nbr_update<float>, dim3(C.panels, C.nbr_total), dim3(WG), shmem, st, L, C, pw);
+    else
+        hipLaunchKernelGGL(k_nbr_update<double>, dim3(C.panels, C.nbr_total), dim3(WG), shmem, st, L, C, pw);
 }
 
 // ============================================================ Schur update
@@ -582,8 +603,10 @@ __device__ inline void map_rows(PN noff, int nb, int r0, int nt, int* nbr_of, in
     }
 }
 
+template <class T>
 __global__ void __launch_bounds__(WG) k_schur(LevelDev L, ColourDev C) {
-    __shared__ MfmaSmem sm;
+    constexpr bool F64 = std::is_same<T, double>::value;
+    __shared__ std::conditional_t<F64, MfmaSmem, MfmaSmemB> sm;
     __shared__ SchurMaps mp;
     const int64_t q = blockIdx.x;
     const int ci = find_cluster64(C.tile_pre, C.n, q);
@@ -599,8 +622,8 @@ __global__ void __launch_bounds__(WG) k_schur(LevelDev L, ColourDev C) {
     const int r0 = (int)(t / tpr) * SCHUR_T, c0 = (int)(t % tpr) * SCHUR_T;
     if (r0 >= nt || c0 >= nt) return;
     const int64_t MM = (int64_t)M * M;
-    const double* ER = L.rec + L.rec_off[s] + 2 * MM;  // f x ntot, ld M
-    const double* EL = ER + (int64_t)M * ncap;          // ntot x f, ld ncap
+    const T* ER = rec_t<T>(L, s) + 2 * MM;  // f x ntot, ld M
+    const T* EL = ER + (int64_t)M * ncap;   // ntot x f, ld ncap
     const int e0 = L.nbr_ptr[s], nb = L.nbr_ptr[s + 1] - e0;
     if (nb <= NOFF_LDS) {
         for (int x = threadIdx.x; x < nb; x += blockDim.x) mp.noff[x] = L.nbr_noff[e0 + x];
@@ -611,10 +634,13 @@ __global__ void __launch_bounds__(WG) k_schur(LevelDev L, ColourDev C) {
         map_rows(L.nbr_noff + e0, nb, r0, nt, mp.rblk, mp.rloc);
         map_rows(L.nbr_noff + e0, nb, c0, nt, mp.cblk, mp.cloc);
     }
-    v4d acc[2][2];
-    mfma_tile64(
-        f, [&](int r, int k) { return (r0 + r < nt && k < f) ? EL[(r0 + r) + (int64_t)k * ncap] : 0.0; },
-        [&](int k, int c) { return (c0 + c < nt && k < f) ? ER[k + (int64_t)(c0 + c) * M] : 0.0; }, to_lds(&sm), acc);
+    auto la = [&](int r, int k) { return (r0 + r < nt && k < f) ? EL[(r0 + r) + (int64_t)k * ncap] : (T)0; };
+    auto lb = [&](int k, int c) { return (c0 + c < nt && k < f) ? ER[k + (int64_t)(c0 + c) * M] : (T)0; };
+    std::conditional_t<F64, v4d, v4f> acc[2][2];
+    if constexpr (F64)
+        mfma_tile64(f, la, lb, to_lds(&sm), acc);
+    else
+        mfma_tile64_bf16(f, la, lb, to_lds(&sm), acc);
     __syncthreads();
     const int64_t pb = L.pair_base[s];
     // neighbour ranges covered by the tile; the block pointers of every
@@ -626,48 +652,61 @@ __global__ void __launch_bounds__(WG) k_schur(LevelDev L, ColourDev C) {
     if (table) {
         for (int x = threadIdx.x; x < nbi * nbj; x += blockDim.x) {
             const int i = x / nbj, j = x % nbj;
-            mp.ptab[x] = blk_ptr(L, L.pair_blk[pb + (int64_t)(bi0 + i) * nb + (bj0 + j)]);
+            mp.ptab[x] = (double*)blk_t<T>(L, L.pair_blk[pb + (int64_t)(bi0 + i) * nb + (bj0 + j)]);
         }
         for (int i = threadIdx.x; i < nbi; i += blockDim.x) mp.ldtab[i] = L.m[L.nbr_id[e0 + bi0 + i]];
     }
     __syncthreads();
     // every entry of the tile has its own address: all 16 targets of a lane
     // are read before any is written back
-    glb_f64* dst[16];
-    mfma_tile64_visit(acc, [&](int idx, int r, int c, double) {
+    using GT = std::conditional_t<F64, glb_f64, glb_f32>;
+    GT* dst[16];
+    auto addr = [&](int idx, int r, int c, double) {
         const int bi = mp.rblk[r], bj = mp.cblk[c];
-        double* p = nullptr;
+        T* p = nullptr;
         if (bi >= 0 && bj >= 0) {
             if (table) {
                 const int i = bi - bi0;
-                p = mp.ptab[i * nbj + (bj - bj0)] + mp.rloc[r] + (int64_t)mp.cloc[c] * mp.ldtab[i];
+                p = (T*)mp.ptab[i * nbj + (bj - bj0)] + mp.rloc[r] + (int64_t)mp.cloc[c] * mp.ldtab[i];
             } else {
                 const int a = L.nbr_id[e0 + bi];
-                p = blk_ptr(L, L.pair_blk[pb + (int64_t)bi * nb + bj]) + mp.rloc[r] + (int64_t)mp.cloc[c] * L.m[a];
+                p = blk_t<T>(L, L.pair_blk[pb + (int64_t)bi * nb + bj]) + mp.rloc[r] + (int64_t)mp.cloc[c] * L.m[a];
             }
         }
-        dst[idx] = (glb_f64*)p;
-    });
-    double old[16];
+        dst[idx] = (GT*)p;
+    };
+    if constexpr (F64)
+        mfma_tile64_visit(acc, addr);
+    else
+        mfma_tile64_bf16_visit(acc, addr);
+    T old[16];
 #pragma unroll
-    for (int x = 0; x < 16; ++x) old[x] = dst[x] ? *dst[x] : 0.0;
-    mfma_tile64_visit(acc, [&](int idx, int, int, double v) {
-        if (dst[idx]) *dst[idx] = old[idx] - v;
-    });
+    for (int x = 0; x < 16; ++x) old[x] = dst[x] ? *dst[x] : (T)0;
+    auto upd = [&](int idx, int, int, double v) {
+        if (dst[idx]) *dst[idx] = old[idx] - (T)v;
+    };
+    if constexpr (F64)
+        mfma_tile64_visit(acc, upd);
+    else
+        mfma_tile64_bf16_visit(acc, upd);
 }
 
 void launch_schur(const LevelDev& L, const ColourDev& C, hipStream_t st) {
     if (C.tile_total == 0) return;
-    hipLaunchKernelGGL(k_schur, dim3((unsigned)C.tile_total), dim3(WG), 0, st, L, C);
+    if (L.f32)
+        hipLaunchKernelGGL(k_schur<float>, dim3((unsigned)C.tile_total), dim3(WG), 0, st, L, C);
+    else
+        hipLaunchKernelGGL(k_schur<double>, dim3((unsigned)C.tile_total), dim3(WG), 0, st, L, C);
 }
 
 // ================================================================ assembly
 
+template <class T>
 __global__ void k_assemble0(int64_t n, const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx,
                             const double* __restrict__ val, const int* __restrict__ cluster_of,
                             const int* __restrict__ local_of, const int* __restrict__ m,
                             const int* __restrict__ pat_ptr, const int* __restrict__ pat,
-                            const int64_t* __restrict__ blk_off, double* __restrict__ blocks) {
+                            const int64_t* __restrict__ blk_off, T* __restrict__ blocks) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int ci = cluster_of[i], li = local_of[i];
@@ -683,29 +722,35 @@ __global__ void k_assemble0(int64_t n, const int64_t* __restrict__ row_ptr, cons
             else
                 hi = mid;
         }
-        blocks[blk_off[lo] + li + (int64_t)lj * m[ci]] = val[e];
+        blocks[blk_off[lo] + li + (int64_t)lj * m[ci]] = (T)val[e];
     }
 }
 
 void launch_assemble0(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, const double* val,
                       const int* cluster_of, const int* local_of, const int* m, const int* pat_ptr, const int* pat,
-                      const int64_t* blk_off, double* blocks, hipStream_t st) {
+                      const int64_t* blk_off, void* blocks, int f32, hipStream_t st) {
     const int bs = 256;
-    hipLaunchKernelGGL(k_assemble0, dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, st, n, row_ptr, col_idx, val,
-                       cluster_of, local_of, m, pat_ptr, pat, blk_off, blocks);
+    const dim3 g((unsigned)((n + bs - 1) / bs));
+    if (f32)
+        hipLaunchKernelGGL(k_assemble0<float>, g, dim3(bs), 0, st, n, row_ptr, col_idx, val, cluster_of, local_of, m,
+                           pat_ptr, pat, blk_off, (float*)blocks);
+    else
+        hipLaunchKernelGGL(k_assemble0<double>, g, dim3(bs), 0, st, n, row_ptr, col_idx, val, cluster_of, local_of, m,
+                           pat_ptr, pat, blk_off, (double*)blocks);
 }
 
 // Parent block (P, Q) = [[B(l_P, l_Q), B(l_P, r_Q)], [B(r_P, l_Q), B(r_P, r_Q)]]
 // of the children's coarse blocks (Alg. 1 "Extract A_c").
+template <class TS, class TD>
 __global__ void k_merge(const int* __restrict__ nb_row, const int* __restrict__ nb_col, const int* __restrict__ src4,
                         const int* __restrict__ k_prev, const int* __restrict__ m_prev,
-                        const int64_t* __restrict__ blk_off_prev, const double* __restrict__ blocks_prev,
+                        const int64_t* __restrict__ blk_off_prev, const TS* __restrict__ blocks_prev,
                         const int* __restrict__ m_next, const int64_t* __restrict__ blk_off_next,
-                        double* __restrict__ blocks_next, int ncl_prev) {
+                        TD* __restrict__ blocks_next, int ncl_prev) {
     const int b = blockIdx.x;
     const int P = nb_row[b], Q = nb_col[b];
     const int ldn = m_next[P];
-    double* dst = blocks_next + blk_off_next[b];
+    TD* dst = blocks_next + blk_off_next[b];
     for (int h = 0; h < 4; ++h) {
         const int src = src4[4 * b + h];
         if (src < 0) continue;
@@ -713,34 +758,50 @@ __global__ void k_merge(const int* __restrict__ nb_row, const int* __restrict__ 
         const int roff = (h >> 1) ? k_prev[2 * P] : 0;
         const int coff = (h & 1) ? k_prev[2 * Q] : 0;
         const int ka = k_prev[a], kc = k_prev[c];
-        const double* sp = blocks_prev + blk_off_prev[src];
+        const TS* sp = blocks_prev + blk_off_prev[src];
         const int lds = m_prev[a];
         for (int x = threadIdx.x; x < ka * kc; x += blockDim.x) {
             int i = x % ka, j = x / ka;
-            dst[(roff + i) + (int64_t)(coff + j) * ldn] = sp[i + (int64_t)j * lds];
+            dst[(roff + i) + (int64_t)(coff + j) * ldn] = (TD)sp[i + (int64_t)j * lds];
         }
     }
     (void)ncl_prev;
 }
 
 void launch_merge(int nblk_next, const int* nb_row, const int* nb_col, const int* src4, const int* k_prev,
-                  const int* m_prev, const int64_t* blk_off_prev, const double* blocks_prev, const int* m_next,
-                  const int64_t* blk_off_next, double* blocks_next, int ncl_prev, hipStream_t st) {
+                  const int* m_prev, const int64_t* blk_off_prev, const void* blocks_prev, int prev_f32,
+                  const int* m_next, const int64_t* blk_off_next, void* blocks_next, int next_f32, int ncl_prev,
+                  hipStream_t st) {
     if (nblk_next == 0) return;
-    hipLaunchKernelGGL(k_merge, dim3(nblk_next), dim3(256), 0, st, nb_row, nb_col, src4, k_prev, m_prev, blk_off_prev,
-                       blocks_prev, m_next, blk_off_next, blocks_next, ncl_prev);
+    const dim3 g(nblk_next), b(256);
+#define HS_MERGE(TS, TD)                                                                                            \
+    hipLaunchKernelGGL((k_merge<TS, TD>), g, b, 0, st, nb_row, nb_col, src4, k_prev, m_prev, blk_off_prev,           \
+                       (const TS*)blocks_prev, m_next, blk_off_next, (TD*)blocks_next, ncl_prev)
+    if (prev_f32 && next_f32)
+        HS_MERGE(float, float);
+    else if (prev_f32)
+        HS_MERGE(float, double);
+    else if (next_f32)
+        HS_MERGE(double, float);
+    else
+        HS_MERGE(double, double);
+#undef HS_MERGE
 }
 
-__global__ void k_fill_zero(double* p, int64_t n) {
+template <class T>
+__global__ void k_fill_zero(T* p, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = 0.0;
+        p[i] = (T)0;
 }
 
-void launch_fill_zero(double* p, int64_t n, hipStream_t st) {
+void launch_fill_zero(void* p, int64_t n, int f32, hipStream_t st) {
     if (n <= 0) return;
     int64_t blocks = (n + 255) / 256;
     if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)blocks), dim3(256), 0, st, p, n);
+    if (f32)
+        hipLaunchKernelGGL(k_fill_zero<float>, dim3((unsigned)blocks), dim3(256), 0, st, (float*)p, n);
+    else
+        hipLaunchKernelGGL(k_fill_zero<double>, dim3((unsigned)blocks), dim3(256), 0, st, (double*)p, n);
 }
 
 }  // namespace hs

@@ -12,6 +12,11 @@
 
 namespace hs {
 
+template <class T>
+__device__ inline const T* srec(const SolveLevelDev& S, int s) {
+    return reinterpret_cast<const T*>(S.rec) + S.rec_off[s];
+}
+
 __device__ inline int find_pre(const int* pre, int n, int q) {
     int lo = 0, hi = n;
     while (hi - lo > 1) {
@@ -26,6 +31,7 @@ __device__ inline int find_pre(const int* pre, int n, int q) {
 
 // ---------------------------------------------------------------- forward
 
+template <class T>
 __global__ void __launch_bounds__(WG) k_apply_fwd_t(SolveLevelDev S, ColourDev C, const double* __restrict__ y,
                                                     double* __restrict__ z, int nrhs) {
     extern __shared__ double ys[];
@@ -42,11 +48,11 @@ __global__ void __launch_bounds__(WG) k_apply_fwd_t(SolveLevelDev S, ColourDev C
     }
     for (int x = threadIdx.x; x < tot; x += blockDim.x) ys[x] = ysrc[x];
     __syncthreads();
-    const double* T = S.rec + S.rec_off[s];
+    const T* TL = srec<T>(S, s);
     for (int x = threadIdx.x; x < tot; x += blockDim.x) {
         const int i = x % M, r = x / M;
         double acc = 0.0;
-        for (int l = 0; l < M; ++l) acc = fma(T[i + (int64_t)l * M], ys[l + r * M], acc);
+        for (int l = 0; l < M; ++l) acc = fma((double)TL[i + (int64_t)l * M], ys[l + r * M], acc);
         zdst[x] = acc;
     }
 }
@@ -54,12 +60,16 @@ __global__ void __launch_bounds__(WG) k_apply_fwd_t(SolveLevelDev S, ColourDev C
 void launch_apply_fwd_t(const SolveLevelDev& S, const ColourDev& C, const double* y, double* z, int nrhs,
                         hipStream_t st) {
     if (C.n == 0) return;
-    hipLaunchKernelGGL(k_apply_fwd_t, dim3(C.n), dim3(WG), (size_t)C.max_m * nrhs * sizeof(double), st, S, C, y, z,
-                       nrhs);
+    const size_t sh = (size_t)C.max_m * nrhs * sizeof(double);
+    if (S.f32)
+        hipLaunchKernelGGL(k_apply_fwd_t<float>, dim3(C.n), dim3(WG), sh, st, S, C, y, z, nrhs);
+    else
+        hipLaunchKernelGGL(k_apply_fwd_t<double>, dim3(C.n), dim3(WG), sh, st, S, C, y, z, nrhs);
 }
 
 constexpr int UROWS = 64;
 
+template <class T>
 __global__ void __launch_bounds__(WG) k_apply_fwd_u(SolveLevelDev S, ColourDev C, double* __restrict__ y,
                                                     double* __restrict__ z, int nrhs) {
     extern __shared__ double zf[];
@@ -85,14 +95,14 @@ __global__ void __launch_bounds__(WG) k_apply_fwd_u(SolveLevelDev S, ColourDev C
     }
     __syncthreads();
     const int ncap = S.ncap[s];
-    const double* EL = S.rec + S.rec_off[s] + 2 * (int64_t)M * M + (int64_t)M * ncap;  // ld ncap
+    const T* EL = srec<T>(S, s) + 2 * (int64_t)M * M + (int64_t)M * ncap;  // ld ncap
     const int off = S.nbr_noff[e];
     double* tgt = before ? z + S.seg[a] * nrhs + (ma - ca) : y + S.seg[a] * nrhs;  // ld ma
     for (int x = threadIdx.x; x < nr * nrhs; x += blockDim.x) {
         const int i = x % nr, r = x / nr;
         double acc = 0.0;
-        const double* row = EL + off + r0 + i;
-        for (int j = 0; j < f; ++j) acc = fma(row[(int64_t)j * ncap], zf[j + r * f], acc);
+        const T* row = EL + off + r0 + i;
+        for (int j = 0; j < f; ++j) acc = fma((double)row[(int64_t)j * ncap], zf[j + r * f], acc);
         tgt[r0 + i + (int64_t)r * ma] -= acc;
     }
 }
@@ -103,12 +113,16 @@ void launch_apply_fwd_u(const SolveLevelDev& S, const ColourDev& C, double* y, d
     const int chunks = (C.max_nbr_m + UROWS - 1) / UROWS;
     if (chunks == 0) return;
     (void)max_m;
-    hipLaunchKernelGGL(k_apply_fwd_u, dim3(chunks, C.nbr_total), dim3(WG), (size_t)C.max_m * nrhs * sizeof(double), st,
-                       S, C, y, z, nrhs);
+    const size_t sh = (size_t)C.max_m * nrhs * sizeof(double);
+    if (S.f32)
+        hipLaunchKernelGGL(k_apply_fwd_u<float>, dim3(chunks, C.nbr_total), dim3(WG), sh, st, S, C, y, z, nrhs);
+    else
+        hipLaunchKernelGGL(k_apply_fwd_u<double>, dim3(chunks, C.nbr_total), dim3(WG), sh, st, S, C, y, z, nrhs);
 }
 
 // --------------------------------------------------------------- backward
 
+template <class T>
 __global__ void __launch_bounds__(WG) k_apply_bwd_acc(SolveLevelDev S, ColourDev C, const double* __restrict__ z,
                                                       const double* __restrict__ out, double* __restrict__ part,
                                                       const int64_t* __restrict__ part_off, int nrhs) {
@@ -132,12 +146,12 @@ __global__ void __launch_bounds__(WG) k_apply_bwd_acc(SolveLevelDev S, ColourDev
         xs[x] = src[i + (int64_t)r * ma];
     }
     __syncthreads();
-    const double* ER = S.rec + S.rec_off[s] + 2 * (int64_t)M * M;  // ld M
+    const T* ER = srec<T>(S, s) + 2 * (int64_t)M * M;  // ld M
     const int off = S.nbr_noff[e];
     for (int x = threadIdx.x; x < f * nrhs; x += blockDim.x) {
         const int j = x % f, r = x / f;
         double acc = 0.0;
-        for (int i = 0; i < ca; ++i) acc = fma(ER[j + (int64_t)(off + i) * M], xs[i + r * ca], acc);
+        for (int i = 0; i < ca; ++i) acc = fma((double)ER[j + (int64_t)(off + i) * M], xs[i + r * ca], acc);
         dst[x] = acc;
     }
 }
@@ -145,12 +159,18 @@ __global__ void __launch_bounds__(WG) k_apply_bwd_acc(SolveLevelDev S, ColourDev
 void launch_apply_bwd_acc(const SolveLevelDev& S, const ColourDev& C, const double* z, const double* out,
                           double* part, const int64_t* part_off, int nrhs, hipStream_t st) {
     if (C.nbr_total == 0) return;
-    hipLaunchKernelGGL(k_apply_bwd_acc, dim3(C.nbr_total), dim3(WG), (size_t)C.max_nbr_m * nrhs * sizeof(double), st,
-                       S, C, z, out, part, part_off, nrhs);
+    const size_t sh = (size_t)C.max_nbr_m * nrhs * sizeof(double);
+    if (S.f32)
+        hipLaunchKernelGGL(k_apply_bwd_acc<float>, dim3(C.nbr_total), dim3(WG), sh, st, S, C, z, out, part, part_off,
+                           nrhs);
+    else
+        hipLaunchKernelGGL(k_apply_bwd_acc<double>, dim3(C.nbr_total), dim3(WG), sh, st, S, C, z, out, part, part_off,
+                           nrhs);
 }
 
 constexpr int BWD_POFF = 512;
 
+template <class T>
 __global__ void __launch_bounds__(WG) k_apply_bwd_t(SolveLevelDev S, ColourDev C, const double* __restrict__ z,
                                                     double* __restrict__ out, const double* __restrict__ part,
                                                     const int64_t* __restrict__ part_off, int nrhs) {
@@ -197,11 +217,11 @@ __global__ void __launch_bounds__(WG) k_apply_bwd_t(SolveLevelDev S, ColourDev C
         if (q1 - q0c <= BWD_POFF) break;
     }
     __syncthreads();
-    const double* T = S.rec + S.rec_off[s] + (int64_t)M * M;  // T_R'
+    const T* TR = srec<T>(S, s) + (int64_t)M * M;  // T_R'
     for (int x = threadIdx.x; x < tot; x += blockDim.x) {
         const int i = x % M, r = x / M;
         double acc = 0.0;
-        for (int l = 0; l < M; ++l) acc = fma(T[i + (int64_t)l * M], vs[l + r * M], acc);
+        for (int l = 0; l < M; ++l) acc = fma((double)TR[i + (int64_t)l * M], vs[l + r * M], acc);
         os[x] = acc;
     }
 }
@@ -209,8 +229,11 @@ __global__ void __launch_bounds__(WG) k_apply_bwd_t(SolveLevelDev S, ColourDev C
 void launch_apply_bwd_t(const SolveLevelDev& S, const ColourDev& C, const double* z, double* out,
                         const double* part, const int64_t* part_off, int nrhs, hipStream_t st) {
     if (C.n == 0) return;
-    hipLaunchKernelGGL(k_apply_bwd_t, dim3(C.n), dim3(WG), (size_t)C.max_m * nrhs * sizeof(double), st, S, C, z, out,
-                       part, part_off, nrhs);
+    const size_t sh = (size_t)C.max_m * nrhs * sizeof(double);
+    if (S.f32)
+        hipLaunchKernelGGL(k_apply_bwd_t<float>, dim3(C.n), dim3(WG), sh, st, S, C, z, out, part, part_off, nrhs);
+    else
+        hipLaunchKernelGGL(k_apply_bwd_t<double>, dim3(C.n), dim3(WG), sh, st, S, C, z, out, part, part_off, nrhs);
 }
 
 // ---------------------------------------------------------- level transfer

@@ -40,13 +40,15 @@ void launch_schur(const LevelDev& L, const ColourDev& C, hipStream_t st);
 // Scatter the CSR values into the level-0 block store.
 void launch_assemble0(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, const double* val,
                       const int* cluster_of, const int* local_of, const int* m, const int* pat_ptr, const int* pat,
-                      const int64_t* blk_off, double* blocks, hipStream_t st);
+                      const int64_t* blk_off, void* blocks, int f32, hipStream_t st);
 // Gather the coarse blocks of the children into the parent level.  For every
 // parent block: src[4] child block ids (-1 = absent) for (l,l),(l,r),(r,l),(r,r).
+// Blocks are float or double on either side (prev_f32 / next_f32).
 void launch_merge(int nblk_next, const int* nb_row, const int* nb_col, const int* src4, const int* k_prev,
-                  const int* m_prev, const int64_t* blk_off_prev, const double* blocks_prev, const int* m_next,
-                  const int64_t* blk_off_next, double* blocks_next, int ncl_prev, hipStream_t st);
-void launch_fill_zero(double* p, int64_t n, hipStream_t st);
+                  const int* m_prev, const int64_t* blk_off_prev, const void* blocks_prev, int prev_f32,
+                  const int* m_next, const int64_t* blk_off_next, void* blocks_next, int next_f32, int ncl_prev,
+                  hipStream_t st);
+void launch_fill_zero(void* p, int64_t n, int f32, hipStream_t st);
 // Dense level (complete cluster graph): assemble D (N x N, ld N) from the
 // block store, unpivoted blocked LU in place, per-cluster operators into the
 // records.  inv: 2 * 128 * 128 doubles of workspace; flag: device int, set to
@@ -68,7 +70,8 @@ struct SolveLevelDev {
     const int* ntot;
     const int* ncap;
     const int64_t* rec_off;
-    const double* rec;
+    const double* rec;   // records: double, or float when f32
+    int f32;
     const int64_t* seg;  // [ncl+1] offset of every cluster segment (units of unknowns)
 };
 // z_s = T_L' y_s for the clusters of a colour (deferred: z_s = y_s)
