@@ -103,7 +103,7 @@ typedef struct hs_geometry {
  *               0: general A (row and column fill compressed together);
  *               -1: detect from the values.
  *   coarse_fp64_dofs  mixed form only: levels with at most this many
- *               unknowns keep float64 storage (0 selects 32768). */
+ *               unknowns keep float64 storage (0 selects 16384). */
 typedef struct hs_opts {
     double eps;
     int32_t fixed_rank;

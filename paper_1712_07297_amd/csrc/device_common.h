@@ -473,12 +473,20 @@ __device__ inline bool wg_lu_nopiv(PW W, int M, int ldw) {
     return true;
 }
 
-// Blocked LU without pivoting for M <= 128 with W in LDS: 16-wide panels.
+// Blocked LU without pivoting for M <= 192: 16-wide panels.
 // The panel is factored by wave 0 in registers (the same operations, in the
 // same order, as the unblocked routine); then U_12 = L_11^{-1} A_12 and
 // A_22 -= L_21 U_12 run as 16 x 16 blocks on the matrix cores, spread over
 // the waves.  scr holds 256 doubles of LDS, flag one int.  Returns false on a
 // zero or non-finite pivot (every thread returns the same).
+// x[s] for a uniform slot index s < NS <= 3, by value (keeps x in registers).
+template <int NS>
+__device__ inline double pick(const double* x, int s) {
+    if constexpr (NS == 1) return x[0];
+    else if constexpr (NS == 2) return s == 0 ? x[0] : x[1];
+    else return s == 0 ? x[0] : (s == 1 ? x[1] : x[2]);
+}
+
 template <class PW>
 __device__ __attribute__((noinline)) void tri16_lower_unit_inverse(PW W, int ldw, int b0, lds_f64* scr) {
     const int c = threadIdx.x & 63;
@@ -518,7 +526,7 @@ __device__ inline bool wg_lu_blocked_ns(PW W, int M, int ldw, lds_f64* scr, lds_
             for (int j = 0; j < 16; ++j) {
                 const int col = p + j, sj = col >> 6, lj = col & 63;
                 if (ok && j < pw) {
-                    const double piv = readlane_d(NS == 1 || sj == 0 ? x[j][0] : x[j][NS - 1], lj);
+                    const double piv = readlane_d(pick<NS>(x[j], sj), lj);
                     ok = (piv != 0.0 && isfinite(piv));
                     const double inv = 1.0 / piv;
                     double l[NS];
@@ -530,7 +538,7 @@ __device__ inline bool wg_lu_blocked_ns(PW W, int M, int ldw, lds_f64* scr, lds_
                     }
 #pragma unroll
                     for (int c = j + 1; c < 16; ++c) {
-                        const double u = readlane_d(NS == 1 || sj == 0 ? x[c][0] : x[c][NS - 1], lj);
+                        const double u = readlane_d(pick<NS>(x[c], sj), lj);
 #pragma unroll
                         for (int s = 0; s < NS; ++s) x[c][s] = fma(-l[s], u, x[c][s]);
                     }
@@ -606,6 +614,7 @@ __device__ inline bool wg_lu(PW W, int M, int ldw, lds_f64* scr, lds_i32* flag) 
     if constexpr (BLK) {
         if (M <= 64) return wg_lu_blocked_ns<1, PW>(W, M, ldw, scr, flag);
         if (M <= 128) return wg_lu_blocked_ns<2, PW>(W, M, ldw, scr, flag);
+        if (M <= 192) return wg_lu_blocked_ns<3, PW>(W, M, ldw, scr, flag);
     }
     return wg_lu_nopiv(W, M, ldw);
 }
@@ -783,8 +792,8 @@ __device__ inline void wg_trinv(PW W, int M, int ldw, PO out, int ldo) {
     __syncthreads();
 }
 
-// Blocked triangular inverse on the FP64 matrix cores, M <= 128 (at most 8
-// blocks of 16).  The native result layout of v_mfma_f64_16x16x4f64 (lane l,
+// Blocked triangular inverse on the FP64 matrix cores, M <= 16 NBMAX (NBMAX =
+// 8 or 12 blocks of 16).  The native result layout of v_mfma_f64_16x16x4f64 (lane l,
 // element r holds D[l/16 + 4r][l%16]) is its B-operand layout for the k-chunk
 // 4r, so a wave keeps one block column of the inverse in accumulators and
 // feeds finished blocks straight back as operands.
@@ -792,8 +801,9 @@ __device__ inline void wg_trinv(PW W, int M, int ldw, PO out, int ldo) {
 //   upper:         X_JJ = U_JJ^{-1}, X_IJ = -X_II sum_{I<l<=J} U_Il X_lJ  (I < J)
 // Block columns are independent: wave w takes J = w, w + 4, ...  The 16 x 16
 // diagonal inverses go first, one 16-lane group per block, into scr
-// (8 x 256 doubles of LDS).  Padding beyond M is the identity.
-constexpr int TRI_MFMA_MAX = 128;
+// (NBMAX x 256 doubles of LDS).  Padding beyond M is the identity.
+constexpr int TRI_MFMA_MAX = 128;  // with 8 blocks
+constexpr int TRI_MFMA_MAX12 = 192;  // with 12 blocks
 
 // Inverses of the 16 x 16 diagonal blocks, one 16-lane group per block,
 // column c of block g into scr[g * 256 + 16 c ...].
@@ -832,7 +842,7 @@ __device__ __attribute__((noinline)) void diag_block_inverses(PW W, int M, int l
     for (int r = 0; r < 16; ++r) scr[g * 256 + r + 16 * c] = x[r];
 }
 
-template <bool UPPER, class PW, class PO>
+template <bool UPPER, int NBMAX, class PW, class PO>
 __device__ inline void wg_trinv_mfma(PW W, int M, int ldw, PO out, int ldo, lds_f64* scr) {
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
     const int nb = (M + 15) >> 4;
@@ -844,14 +854,14 @@ __device__ inline void wg_trinv_mfma(PW W, int M, int ldw, PO out, int ldo, lds_
     for (int r = 0; r < 4; ++r) ident[r] = (lk + 4 * r == lr) ? 1.0 : 0.0;
     const v4d zero = {0.0, 0.0, 0.0, 0.0};
     for (int J = wv; J < nb; J += nw) {
-        v4d X[8];
+        v4d X[NBMAX];
 #pragma unroll
-        for (int ii = 0; ii < 8; ++ii) {
-            const int I = UPPER ? 7 - ii : ii;  // the order in which blocks become available
+        for (int ii = 0; ii < NBMAX; ++ii) {
+            const int I = UPPER ? NBMAX - 1 - ii : ii;  // the order in which blocks become available
             if (I >= nb || (UPPER ? I > J : I < J)) continue;
             v4d S = (I == J) ? ident : zero;
 #pragma unroll
-            for (int l = 0; l < 8; ++l) {
+            for (int l = 0; l < NBMAX; ++l) {
                 if (l >= nb || (UPPER ? (l <= I || l > J) : (l < J || l >= I))) continue;
                 const int gr = 16 * I + lr;
                 auto colp = W + gr + (int64_t)(16 * l + lk) * ldw;
@@ -869,7 +879,7 @@ __device__ inline void wg_trinv_mfma(PW W, int M, int ldw, PO out, int ldo, lds_
             X[I] = acc;
         }
 #pragma unroll
-        for (int I = 0; I < 8; ++I) {
+        for (int I = 0; I < NBMAX; ++I) {
             if (I >= nb) continue;
             const bool nz = UPPER ? I <= J : I >= J;
             const int col = 16 * J + lr;
@@ -883,12 +893,15 @@ __device__ inline void wg_trinv_mfma(PW W, int M, int ldw, PO out, int ldo, lds_
     __syncthreads();
 }
 
-// out = L^{-1}, L = unit lower triangle of W.  MODE 1: matrix cores (M <=
-// TRI_MFMA_MAX), 0: per-wave substitution, -1: chosen by M.
+// out = L^{-1}, L = unit lower triangle of W.  MODE 1: matrix cores with 8
+// blocks (M <= 128), 2: with 12 blocks (M <= 192, scr of 12 x 256), 0:
+// per-wave substitution, -1: matrix cores when M <= 128.
 template <int MODE = -1, class PW, class PO>
 __device__ inline void wg_trinv_lower_unit(PW W, int M, int ldw, PO out, int ldo, lds_f64* scr) {
     if (MODE == 1 || (MODE == -1 && M <= TRI_MFMA_MAX))
-        wg_trinv_mfma<false, PW, PO>(W, M, ldw, out, ldo, scr);
+        wg_trinv_mfma<false, 8, PW, PO>(W, M, ldw, out, ldo, scr);
+    else if (MODE == 2)
+        wg_trinv_mfma<false, 12, PW, PO>(W, M, ldw, out, ldo, scr);
     else
         wg_trinv<false, PW, PO>(W, M, ldw, out, ldo);
 }
@@ -896,7 +909,9 @@ __device__ inline void wg_trinv_lower_unit(PW W, int M, int ldw, PO out, int ldo
 template <int MODE = -1, class PW, class PO>
 __device__ inline void wg_trinv_upper(PW W, int M, int ldw, PO out, int ldo, lds_f64* scr) {
     if (MODE == 1 || (MODE == -1 && M <= TRI_MFMA_MAX))
-        wg_trinv_mfma<true, PW, PO>(W, M, ldw, out, ldo, scr);
+        wg_trinv_mfma<true, 8, PW, PO>(W, M, ldw, out, ldo, scr);
+    else if (MODE == 2)
+        wg_trinv_mfma<true, 12, PW, PO>(W, M, ldw, out, ldo, scr);
     else
         wg_trinv<true, PW, PO>(W, M, ldw, out, ldo);
 }

@@ -254,7 +254,7 @@ namespace hs {
 static const char* kVersion = "hs 0.1 (gfx950)";
 // Mixed form: levels with at most this many unknowns keep float64 storage
 // (default of hs_opts.coarse_fp64_dofs).
-constexpr int64_t MIXED_FP64_DOFS = 32768;
+constexpr int64_t MIXED_FP64_DOFS = 16384;
 
 // =============================================================== validation
 

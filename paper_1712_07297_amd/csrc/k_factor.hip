@@ -228,7 +228,10 @@ __device__ bool wg_cholqr2(const double* X, int M, int k, PG G, double* T1, doub
         pmax = block_max(pmax, red);
         const double pmin = -block_max(nmin, red);
         if (!(pmin > 1e-14 * pmax)) return false;
-        wg_trinv_upper<1>(G, k, k, T2, k, scr);
+        if (k <= TRI_MFMA_MAX)
+            wg_trinv_upper<1>(G, k, k, T2, k, scr);
+        else
+            wg_trinv_upper<0>(G, k, k, T2, k, scr);
         const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
         for (int j = threadIdx.x >> 6; j < k; j += nw) {
             const double sj = sqrt(G[j + (int64_t)j * k]);
@@ -254,7 +257,7 @@ __device__ void wg_complement(PX X, int M, int K, PV V, int ldv, PT tau_sh) {
 // L2-resident workspace; every dense step below reuses it in turn.
 template <bool INLDS, class T>
 __global__ void __launch_bounds__(WG) k_pivot(LevelDev L, const int* __restrict__ clist) {
-    extern __shared__ double dyn[];  // M * M doubles for the largest cluster M of the colour (INLDS)
+    extern __shared__ double dyn[];  // INLDS: M * M doubles (largest M of the colour); else 12 x 256
     __shared__ GemmSmem sm;
     __shared__ double red[16];
     __shared__ int isc[4];
@@ -306,7 +309,11 @@ __global__ void __launch_bounds__(WG) k_pivot(LevelDev L, const int* __restrict_
     lds_f64* red_l = to_lds(red);
     lds_f64* dsh_l = to_lds(dsh);
     lds_smem* sm_l = to_lds(&sm);
-    lds_f64* scr = (lds_f64*)sm_l;  // 2080 doubles, free outside the GEMMs
+    // block scratch: the GEMM staging area (2080 doubles) when the working
+    // matrix is in LDS, else 12 x 256 doubles of dynamic LDS
+    lds_f64* scr = INLDS ? (lds_f64*)sm_l : to_lds(dyn);
+    constexpr int TRI = INLDS ? 1 : 2;  // matrix-core triangular inverses (8 / 12 blocks)
+    const bool tri_mfma = INLDS || M <= TRI_MFMA_MAX12;
     T* TLp = rec_t<T>(L, s);
     T* TRp = TLp + MM;
     T* Bss = blk_t<T>(L, L.diag_blk[s]);
@@ -341,7 +348,7 @@ __global__ void __launch_bounds__(WG) k_pivot(LevelDev L, const int* __restrict_
                 for (int i = lane; i < M; i += 64) X[perm[i] + (int64_t)j * M] = (i >= j) ? W[i + (int64_t)j * M] : 0.0;
             __syncthreads();
             bool done = false;
-            if constexpr (INLDS) done = wg_cholqr2(X, M, kk, W, Linv, Uinv, Umat, sm_l, scr, red_l, to_lds(isc + 1));
+            done = wg_cholqr2(X, M, kk, W, Linv, Uinv, Umat, sm_l, scr, red_l, to_lds(isc + 1));
             if (!done) {
                 wg_copy(M, kk, X, M, W, M);
                 wg_house_qr(W, M, kk, M, dsh_l);
@@ -354,7 +361,7 @@ __global__ void __launch_bounds__(WG) k_pivot(LevelDev L, const int* __restrict_
 
     // ---- 2. A_ss = L U (no pivoting) and its inverse factors
     wg_copy(M, M, Bss, M, W, M);
-    if (!wg_lu<INLDS>(W, M, M, scr, to_lds(isc + 1))) {
+    if (!wg_lu<true>(W, M, M, scr, to_lds(isc + 1))) {
         if (tid == 0) {
             L.flag[s] = 1;
             L.k[s] = M;  // leave the cluster untouched
@@ -362,12 +369,12 @@ __global__ void __launch_bounds__(WG) k_pivot(LevelDev L, const int* __restrict_
         return;
     }
     if (kk == 0) {  // E_s = I: one block LU step
-        wg_trinv_lower_unit<INLDS ? 1 : 0>(W, M, M, TLp, M, scr);
-        wg_trinv_upper<INLDS ? 1 : 0>(W, M, M, TRp, M, scr);
+        if (tri_mfma) wg_trinv_lower_unit<TRI>(W, M, M, TLp, M, scr); else wg_trinv_lower_unit<0>(W, M, M, TLp, M, scr);
+        if (tri_mfma) wg_trinv_upper<TRI>(W, M, M, TRp, M, scr); else wg_trinv_upper<0>(W, M, M, TRp, M, scr);
         return;
     }
-    wg_trinv_lower_unit<INLDS ? 1 : 0>(W, M, M, Linv, M, scr);
-    wg_trinv_upper<INLDS ? 1 : 0>(W, M, M, Uinv, M, scr);
+    if (tri_mfma) wg_trinv_lower_unit<TRI>(W, M, M, Linv, M, scr); else wg_trinv_lower_unit<0>(W, M, M, Linv, M, scr);
+    if (tri_mfma) wg_trinv_upper<TRI>(W, M, M, Uinv, M, scr); else wg_trinv_upper<0>(W, M, M, Uinv, M, scr);
     wg_gemm<false, false>(M, M, M, 1.0, Uinv, M, Linv, M, 0.0, Ainv, M, sm_l);
     const int f = M - kk;
 
@@ -390,15 +397,15 @@ __global__ void __launch_bounds__(WG) k_pivot(LevelDev L, const int* __restrict_
 
     // ---- 4. elimination operator G_s (Eq. elim): F_ff = T_L[:f] S_R[:, :f] = L_f U_f
     wg_gemm<false, false>(f, f, M, 1.0, TL, M, SR, M, 0.0, W, M, sm_l);
-    if (!wg_lu<INLDS>(W, f, M, scr, to_lds(isc + 1))) {
+    if (!wg_lu<true>(W, f, M, scr, to_lds(isc + 1))) {
         if (tid == 0) {
             L.flag[s] = 2;
             L.k[s] = M;
         }
         return;
     }
-    wg_trinv_lower_unit<INLDS ? 1 : 0>(W, f, M, Linv, M, scr);
-    wg_trinv_upper<INLDS ? 1 : 0>(W, f, M, Uinv, M, scr);
+    if (tri_mfma) wg_trinv_lower_unit<TRI>(W, f, M, Linv, M, scr); else wg_trinv_lower_unit<0>(W, f, M, Linv, M, scr);
+    if (tri_mfma) wg_trinv_upper<TRI>(W, f, M, Uinv, M, scr); else wg_trinv_upper<0>(W, f, M, Uinv, M, scr);
     // T_L' = [L_f^{-1} T_L[:f, :]; T_L[f:, :]],  T_R' = [T_R[:, :f] U_f^{-1}, T_R[:, f:]]
     wg_gemm<false, false>(f, M, f, 1.0, Linv, M, TL, M, 0.0, TLp, M, sm_l);
     wg_copy(kk, M, TL + f, M, TLp + f, M);
@@ -421,10 +428,11 @@ void launch_pivot(const LevelDev& L, const ColourDev& C, hipStream_t st) {
         else
             hipLaunchKernelGGL((k_pivot<true, double>), dim3(C.n), dim3(WG), shmem, st, L, C.clist);
     } else {
+        const size_t scr_bytes = 12 * 256 * sizeof(double);
         if (L.f32)
-            hipLaunchKernelGGL((k_pivot<false, float>), dim3(C.n), dim3(WG), 0, st, L, C.clist);
+            hipLaunchKernelGGL((k_pivot<false, float>), dim3(C.n), dim3(WG), scr_bytes, st, L, C.clist);
         else
-            hipLaunchKernelGGL((k_pivot<false, double>), dim3(C.n), dim3(WG), 0, st, L, C.clist);
+            hipLaunchKernelGGL((k_pivot<false, double>), dim3(C.n), dim3(WG), scr_bytes, st, L, C.clist);
     }
 }
 

@@ -93,7 +93,7 @@ def test_mixed_gmres_convdiff(P):
 
 
 def test_mixed_default_keeps_small_problems_fp64(P):
-    """With the default threshold (32768 unknowns) a small problem has no
+    """With the default threshold (16384 unknowns) a small problem has no
     float32 level: the mixed form gives the float64 form's solve exactly."""
     p = config1()
     Bt = torch.tensor(p.B.T.copy(), device="cuda")
