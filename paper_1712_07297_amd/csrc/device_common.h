@@ -442,6 +442,23 @@ __device__ void wg_gemm(int M, int N, int K, double alpha, PA A, int lda, PB B, 
     __syncthreads();
 }
 
+// C = Left * Right over 64 x 64 output tiles with caller-supplied loaders
+// la(r, k), lb(k, c) (global indices, 0 outside) and store(r, c, v).
+template <class LA, class LB, class ST>
+__device__ void wg_gemm_fn(int M, int N, int K, const LA& la, const LB& lb, lds_smem* sm, const ST& store) {
+    for (int r0 = 0; r0 < M; r0 += MT)
+        for (int c0 = 0; c0 < N; c0 += MT) {
+            v4d acc[2][2];
+            mfma_tile64(
+                K, [&](int r, int k) { return r0 + r < M ? la(r0 + r, k) : 0.0; },
+                [&](int k, int c) { return c0 + c < N ? lb(k, c0 + c) : 0.0; }, sm, acc);
+            mfma_tile64_store(acc, [&](int r, int c, double v) {
+                if (r0 + r < M && c0 + c < N) store(r0 + r, c0 + c, v);
+            });
+        }
+    __syncthreads();
+}
+
 // ---------------------------------------------------- LU without pivoting
 // In place Doolittle LU of the M x M matrix W (ld ldw), one barrier per
 // elimination step: the multipliers of column j are formed on the fly by the
@@ -1066,6 +1083,50 @@ __device__ inline void wg_house_form_q(PA A, int M, int K, int lda, PT tau_sh, i
         default: wg_form_q_ns<8, PA, PT, PQ>(A, M, K, lda, tau_sh, c0, nq, flip, Q, ldq); break;
     }
     __syncthreads();
+}
+
+// Columns [c0, c0 + nq) of Q = H_0 ... H_{K-1} from the reflectors left in A
+// (ld lda) by wg_house_qr, through the compact WY form Q = I - Y T Y^T (Y unit
+// lower trapezoidal; T upper triangular with T^{-1} = diag(1/tau) +
+// strict_upper(Y^T Y), the UT-transform identity; a reflector with tau = 0 is
+// the identity and gets a zero row and column in T):
+//   G = Y^T Y;  T = (diag(1/tau) + strict_upper(G))^{-1};  Z = T Y[c0:c0+nq, :]^T;
+//   Q[:, cols] = E - Y Z.
+// K <= 128.  Gs, Ts (K x K) and Zs (K x nq) are global scratch, scr 8 x 256
+// doubles of LDS.  With flip, column c < K is negated where R_cc < 0.
+template <class PA, class PT, class PQ>
+__device__ void wg_house_form_q_wy(PA A, int M, int K, int lda, PT tau_sh, int c0, int nq, PQ Q, int ldq, bool flip,
+                                   double* Gs, double* Ts, double* Zs, lds_smem* sm, lds_f64* scr) {
+    auto Y = [&](int i, int j) -> double { return i == j ? 1.0 : (i > j ? (double)A[i + (int64_t)j * lda] : 0.0); };
+    wg_gemm_fn(K, K, M, [&](int r, int k) { return Y(k, r); }, [&](int k, int c) { return Y(k, c); }, sm,
+               [&](int r, int c, double v) { Gs[r + (int64_t)c * K] = v; });
+    {
+        const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+        for (int j = threadIdx.x >> 6; j < K; j += nw) {
+            const bool zj = tau_sh[j] == 0.0;
+            for (int i = lane; i <= j; i += 64) {
+                double& g = Gs[i + (int64_t)j * K];
+                if (i == j)
+                    g = zj ? 1.0 : 1.0 / tau_sh[j];
+                else if (zj || tau_sh[i] == 0.0)
+                    g = 0.0;
+            }
+        }
+    }
+    __syncthreads();
+    wg_trinv_upper<1>(Gs, K, K, Ts, K, scr);
+    for (int j = threadIdx.x; j < K; j += blockDim.x)
+        if (tau_sh[j] == 0.0) Ts[j + (int64_t)j * K] = 0.0;
+    __syncthreads();
+    wg_gemm_fn(K, nq, K, [&](int r, int k) { return Ts[r + (int64_t)k * K]; }, [&](int k, int c) { return Y(c0 + c, k); },
+               sm, [&](int r, int c, double v) { Zs[r + (int64_t)c * K] = v; });
+    wg_gemm_fn(M, nq, K, [&](int r, int k) { return Y(r, k); }, [&](int k, int c) { return Zs[k + (int64_t)c * K]; }, sm,
+               [&](int r, int c, double v) {
+                   const int col = c0 + c;
+                   double q = (r == col ? 1.0 : 0.0) - v;
+                   if (flip && col < K && A[col + (int64_t)col * lda] < 0.0) q = -q;
+                   Q[r + (int64_t)c * ldq] = q;
+               });
 }
 
 }  // namespace hs

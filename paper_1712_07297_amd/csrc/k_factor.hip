@@ -204,19 +204,22 @@ __device__ int wg_pivoted_cholesky(PW W, int M, double eps, int fixed_rank, PI p
     return kk;
 }
 
-// Orthonormal factor Q (M x k, positive diagonal R) of X = Q R by two passes
-// of Cholesky QR: G = Y^T Y = R^T R, R = D^{-1/2} U_G from the unpivoted LU
-// G = L_G U_G (D = diag U_G), Y <- Y R^{-1}.  Two passes make Q orthonormal
-// to working accuracy while cond(X) stays below about 1e7; beyond that
-// (smallest Gram pivot below 1e-14 of the largest) it returns false and
-// leaves the caller to use Householder QR.  G is a k x k LDS scratch, T1 an
-// M x k and T2 a k x k global scratch.
+// Orthonormal factor Q (M x k, positive diagonal R) of X = Q R by Cholesky
+// QR: G = Y^T Y = R^T R, R = D^{-1/2} U_G from the unpivoted LU G = L_G U_G
+// (D = diag U_G), Y <- Y R^{-1}.  One pass leaves an orthogonality error of
+// about u cond(X)^2 = u pmax/pmin (Gram pivots); it suffices while
+// pmin/pmax >= one_pass, else a second pass brings it to u.  Beyond cond(X) ~ 1e7
+// (pmin < 1e-14 pmax) it returns false and leaves the caller to use
+// Householder QR.  G is a k x k scratch, T1 an M x k and T2 a k x k global
+// scratch.
+constexpr double CHOLQR_ONE_PASS = 1e-6;  // one pass while cond(X) <= 1e3 (error ~ 1e-10)
+
 template <class PG>
 __device__ bool wg_cholqr2(const double* X, int M, int k, PG G, double* T1, double* T2, double* Q, lds_smem* sm,
-                           lds_f64* scr, lds_f64* red, lds_i32* flag) {
+                           lds_f64* scr, lds_f64* red, lds_i32* flag, double one_pass) {
     const double* src = X;
-    for (int pass = 0; pass < 2; ++pass) {
-        double* dst = pass == 0 ? T1 : Q;
+    bool last = false;
+    for (int pass = 0; pass < 2 && !last; ++pass) {
         wg_gemm<true, false>(k, k, M, 1.0, src, M, src, M, 0.0, G, k, sm);
         if (!wg_lu<true>(G, k, k, scr, flag)) return false;
         double pmax = 0.0, nmin = -INFINITY;
@@ -228,6 +231,8 @@ __device__ bool wg_cholqr2(const double* X, int M, int k, PG G, double* T1, doub
         pmax = block_max(pmax, red);
         const double pmin = -block_max(nmin, red);
         if (!(pmin > 1e-14 * pmax)) return false;
+        last = pass == 1 || pmin >= one_pass * pmax;
+        double* dst = last ? Q : T1;
         if (k <= TRI_MFMA_MAX)
             wg_trinv_upper<1>(G, k, k, T2, k, scr);
         else
@@ -245,11 +250,16 @@ __device__ bool wg_cholqr2(const double* X, int M, int k, PG G, double* T1, doub
 }
 
 // Householder complement: Q columns [K, M) of the QR of X (M x K, ld M) into
-// V (ld ldv).  X is destroyed.
+// V (ld ldv), Q formed through its compact WY form (scratch: three global
+// M x M slots).  X is destroyed.
 template <class PX, class PV, class PT>
-__device__ void wg_complement(PX X, int M, int K, PV V, int ldv, PT tau_sh) {
+__device__ void wg_complement(PX X, int M, int K, PV V, int ldv, PT tau_sh, double* s1, double* s2, double* s3,
+                              lds_smem* sm, lds_f64* scr) {
     wg_house_qr(X, M, K, M, tau_sh);
-    wg_house_form_q(X, M, K, M, tau_sh, K, M - K, V, ldv);
+    if (K <= TRI_MFMA_MAX)
+        wg_house_form_q_wy(X, M, K, M, tau_sh, K, M - K, V, ldv, false, s1, s2, s3, sm, scr);
+    else
+        wg_house_form_q(X, M, K, M, tau_sh, K, M - K, V, ldv);
 }
 
 // Per-cluster elimination operators.  The working M x M matrix W lives in
@@ -348,7 +358,7 @@ __global__ void __launch_bounds__(WG) k_pivot(LevelDev L, const int* __restrict_
                 for (int i = lane; i < M; i += 64) X[perm[i] + (int64_t)j * M] = (i >= j) ? W[i + (int64_t)j * M] : 0.0;
             __syncthreads();
             bool done = false;
-            done = wg_cholqr2(X, M, kk, W, Linv, Uinv, Umat, sm_l, scr, red_l, to_lds(isc + 1));
+            done = wg_cholqr2(X, M, kk, W, Linv, Uinv, Umat, sm_l, scr, red_l, to_lds(isc + 1), CHOLQR_ONE_PASS);
             if (!done) {
                 wg_copy(M, kk, X, M, W, M);
                 wg_house_qr(W, M, kk, M, dsh_l);
@@ -381,14 +391,14 @@ __global__ void __launch_bounds__(WG) k_pivot(LevelDev L, const int* __restrict_
     // ---- 3. sparsification operator E_s (Eq. scaling)
     // S_L = [V_L U], V_L the complement of A^{-1} U
     wg_gemm<false, false>(M, kk, M, 1.0, Ainv, M, Umat, M, 0.0, W, M, sm_l);
-    wg_complement(W, M, kk, SL, M, dsh_l);
+    wg_complement(W, M, kk, SL, M, dsh_l, Linv, Uinv, X, sm_l, scr);
     wg_copy(M, kk, Umat, M, SL + (int64_t)f * M, M);
     __syncthreads();
     if (L.symmetric) {
         wg_copy(M, M, SL, M, SR, M);
     } else {
         wg_gemm<true, false>(M, kk, M, 1.0, Ainv, M, Umat, M, 0.0, W, M, sm_l);  // A^{-T} U
-        wg_complement(W, M, kk, SR, M, dsh_l);
+        wg_complement(W, M, kk, SR, M, dsh_l, Linv, Uinv, X, sm_l, scr);
         wg_copy(M, kk, Umat, M, SR + (int64_t)f * M, M);
     }
     __syncthreads();
