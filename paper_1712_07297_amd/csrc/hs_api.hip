@@ -127,9 +127,15 @@ struct ProfFamily {
     int64_t launches = 0;
     double seconds = 0.0, bytes = 0.0, flops = 0.0;
 };
-enum ProfId { PF_GRAM = 0, PF_PIVOT, PF_FILL, PF_NBR, PF_SCHUR, PF_MERGE, PF_APPLY, PF_SPMV, PF_DENSE, PF_COUNT };
+enum ProfId {
+    PF_GRAM = 0, PF_PIVOT, PF_FILL, PF_NBR, PF_SCHUR, PF_MERGE, PF_APPLY, PF_SPMV, PF_DENSE,
+    // host wall time of the factorization: symbolic analysis, level planning,
+    // metadata uploads, device allocations, per-level rank read-back
+    PF_H_SYMBOLIC, PF_H_PLAN, PF_H_UPLOAD, PF_H_ALLOC, PF_H_SYNC, PF_COUNT
+};
 static ProfFamily g_prof[PF_COUNT] = {{"gram"}, {"pivot"}, {"fill"}, {"nbr"},   {"schur"},
-                                      {"merge"}, {"apply"}, {"spmv"}, {"dense"}};
+                                      {"merge"}, {"apply"}, {"spmv"}, {"dense"},
+                                      {"host_symbolic"}, {"host_plan"}, {"host_upload"}, {"host_alloc"}, {"host_sync"}};
 static bool g_prof_on = false;
 struct ProfPending {
     int fam;
@@ -169,6 +175,19 @@ struct ProfScope {
     }
 };
 
+// Host wall time of a scope, added to a host family.
+struct HostScope {
+    int fam;
+    std::chrono::steady_clock::time_point t0;
+    explicit HostScope(int f) : fam(f), t0(std::chrono::steady_clock::now()) {}
+    ~HostScope() {
+        if (g_prof_on) {
+            g_prof[fam].seconds += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+            g_prof[fam].launches += 1;
+        }
+    }
+};
+
 // Read back finished intervals (the caller has synchronised the stream).
 static void prof_flush() {
     for (auto& p : g_prof_pending) {
@@ -199,6 +218,8 @@ struct LevelData {
     int ncl = 0;
     int nblk = 0;
     int f32 = 0;                                   // blocks and records stored in float (mixed form)
+    int64_t npairs = 0;                            // sum over clusters of |n(s)|^2
+    DevBuf pairs;                                  // block id of every neighbour pair (a_i, a_j) of s
     size_t esz() const { return f32 ? sizeof(float) : sizeof(double); }
     std::vector<int> m, k;                         // sizes at the start, ranks after
     std::vector<int64_t> blk_off;
@@ -299,28 +320,15 @@ static int plan_level(hs_factor_s* F, int lvl, Blob& blob, std::vector<size_t>& 
     // per-cluster lists
     std::vector<int> diag_blk(ncl), nbr_before, nbr_bsa, nbr_bas, ncap(ncl), fill_before, fill_bst, fill_bts;
     std::vector<int64_t> pair_base(ncl), rec_off(ncl), ws_off(ncl, 0);
-    std::vector<int> pair_blk;
     nbr_before.resize(S.adj.size());
     nbr_bsa.resize(S.adj.size());
     nbr_bas.resize(S.adj.size());
     fill_before.resize(S.fill.size());
     fill_bst.resize(S.fill.size());
     fill_bts.resize(S.fill.size());
-    int64_t npairs = 0;
-    for (int s = 0; s < ncl; ++s) {
-        int nb = S.adj_ptr[s + 1] - S.adj_ptr[s];
-        npairs += (int64_t)nb * nb;
-    }
-    pair_blk.resize(npairs);
-    // dense block-id map for small levels, binary search otherwise
-    const bool dense_map = (int64_t)ncl * ncl <= (int64_t)1 << 24;
-    std::vector<int> bmap;
-    if (dense_map) {
-        bmap.assign((size_t)ncl * ncl, -1);
-        for (int a = 0; a < ncl; ++a)
-            for (int e = S.pat_ptr[a]; e < S.pat_ptr[a + 1]; ++e) bmap[(size_t)a * ncl + S.pat[e]] = e;
-    }
-    auto bid = [&](int a, int b) { return dense_map ? bmap[(size_t)a * ncl + b] : S.block_id(a, b); };
+    // (the block ids of all neighbour pairs, sum of |n(s)|^2 entries, are
+    // found on the device: launch_pair_blocks)
+    auto bid = [&](int a, int b) { return S.block_id(a, b); };
     int64_t pp = 0, roff = 0;
     int max_nf = 0;
     for (int s = 0; s < ncl; ++s) {
@@ -342,12 +350,13 @@ static int plan_level(hs_factor_s* F, int lvl, Blob& blob, std::vector<size_t>& 
         }
         max_nf = std::max(max_nf, S.fill_ptr[s + 1] - S.fill_ptr[s]);
         pair_base[s] = pp;
-        for (int e = S.adj_ptr[s]; e < S.adj_ptr[s + 1]; ++e)
-            for (int g = S.adj_ptr[s]; g < S.adj_ptr[s + 1]; ++g) pair_blk[pp++] = bid(S.adj[e], S.adj[g]);
+        const int64_t nb = S.adj_ptr[s + 1] - S.adj_ptr[s];
+        pp += nb * nb;
         rec_off[s] = roff;
         roff += 2 * (int64_t)m[s] * m[s] + 2 * (int64_t)m[s] * cap;
     }
     LD.rec_elems = roff;
+    LD.npairs = pp;
     // about four fill partners per Gram workgroup
     LD.gram_splits = std::min(64, std::max(1, (max_nf + 3) / 4));
     const int64_t slots = ws_slots(LD.gram_splits);
@@ -415,7 +424,7 @@ static int plan_level(hs_factor_s* F, int lvl, Blob& blob, std::vector<size_t>& 
     offs.push_back(blob.add(fill_bst));          // 16
     offs.push_back(blob.add(fill_bts));          // 17
     offs.push_back(blob.add(pair_base));         // 18
-    offs.push_back(blob.add(pair_blk));          // 19
+    offs.push_back(blob.add(std::vector<int>()));  // 19 (pair block ids: LD.pairs)
     offs.push_back(blob.add(rec_off));           // 20
     offs.push_back(blob.add(ws_off));            // 21
     offs.push_back(blob.add(S.pat_ptr));         // 22
@@ -460,7 +469,7 @@ static void bind_level(LevelData& LD, const std::vector<size_t>& offs, const hs_
     D.fill_bst = (const int*)P(16);
     D.fill_bts = (const int*)P(17);
     D.pair_base = (const int64_t*)P(18);
-    D.pair_blk = (const int*)P(19);
+    D.pair_blk = LD.pairs.as<int>();
     D.rec_off = (const int64_t*)P(20);
     D.rec = LD.rec.as<double>();
     D.ws_off = (const int64_t*)P(21);
@@ -650,7 +659,10 @@ static int factor_impl(hs_factor_s* F, const hs_csr* A, const hs_geometry* G, hi
 
     // ---- symbolic analysis (integer work only)
     auto t0 = clock::now();
-    rc = build_symbolic(n, rp, ci, G->nx, G->ny, G->nz, F->opts.leaf_size, F->sym);
+    {
+        HostScope hs_(PF_H_SYMBOLIC);
+        rc = build_symbolic(n, rp, ci, G->nx, G->ny, G->nz, F->opts.leaf_size, F->sym);
+    }
     if (rc) return fail(rc, rc == HS_ERR_GEOMETRY ? "n != nx*ny*nz" : "bad symbolic arguments");
     auto t1 = clock::now();
     F->info.symbolic_seconds = std::chrono::duration<double>(t1 - t0).count();
@@ -679,7 +691,10 @@ static int factor_impl(hs_factor_s* F, const hs_csr* A, const hs_geometry* G, hi
                 for (int c = 2 * p; c < std::min(2 * p + 2, prev->ncl); ++c) LD.m[p] += prev->k[c];
         }
         Blob blob;
-        rc = plan_level(F, lvl, blob, offs);
+        {
+            HostScope hs_(PF_H_PLAN);
+            rc = plan_level(F, lvl, blob, offs);
+        }
         if (rc) return rc;
         // A level whose clusters all neighbour each other has no fill: it is
         // factored densely (Alg. 1, conventional factorization).
@@ -691,12 +706,21 @@ static int factor_impl(hs_factor_s* F, const hs_csr* A, const hs_geometry* G, hi
         for (int c = 0; c < S.ncl; ++c) level_dofs += LD.m[c];
         const int64_t fp64_dofs = F->opts.coarse_fp64_dofs > 0 ? F->opts.coarse_fp64_dofs : MIXED_FP64_DOFS;
         LD.f32 = (F->opts.precision == HS_MIXED && !complete && level_dofs > fp64_dofs) ? 1 : 0;
-        if (!LD.meta.alloc(blob.data.size())) return fail(HS_ERR_NOMEM, "level metadata");
-        HIP_TRY(hipMemcpyAsync(LD.meta.p, blob.data.data(), blob.data.size(), hipMemcpyHostToDevice, st));
-        if (!LD.blocks.alloc(LD.block_elems * LD.esz())) return fail(HS_ERR_NOMEM, "block store");
-        if (!LD.rec.alloc(LD.rec_elems * LD.esz())) return fail(HS_ERR_NOMEM, "factor records");
-        if (!F->ws.ensure(LD.ws_elems * sizeof(double))) return fail(HS_ERR_NOMEM, "workspace");
+        {
+            HostScope hs_(PF_H_ALLOC);
+            if (!LD.meta.alloc(blob.data.size())) return fail(HS_ERR_NOMEM, "level metadata");
+            if (!LD.blocks.alloc(LD.block_elems * LD.esz())) return fail(HS_ERR_NOMEM, "block store");
+            if (!LD.rec.alloc(LD.rec_elems * LD.esz())) return fail(HS_ERR_NOMEM, "factor records");
+            if (!F->ws.ensure(LD.ws_elems * sizeof(double))) return fail(HS_ERR_NOMEM, "workspace");
+            if (!LD.pairs.alloc((LD.npairs + 1) * sizeof(int))) return fail(HS_ERR_NOMEM, "neighbour pairs");
+        }
+        {
+            HostScope hs_(PF_H_UPLOAD);
+            HIP_TRY(hipMemcpyAsync(LD.meta.p, blob.data.data(), blob.data.size(), hipMemcpyHostToDevice, st));
+        }
         bind_level(LD, offs, F);
+        launch_pair_blocks(S.ncl, LD.dev.nbr_ptr, LD.dev.nbr_id, LD.dev_pat_ptr, LD.dev_pat, LD.dev.pair_base,
+                           LD.pairs.as<int>(), st);
         launch_fill_zero(LD.blocks.p, LD.block_elems, LD.f32, st);
         if (lvl == 0) {
             launch_assemble0(n, F->A_row.as<int64_t>(), F->A_col.as<int32_t>(), F->A_val.as<double>(),
@@ -705,6 +729,7 @@ static int factor_impl(hs_factor_s* F, const hs_csr* A, const hs_geometry* G, hi
         } else {
             // parent blocks from the children's coarse blocks
             const LevelSymbolic& PS = F->sym.levels[lvl - 1];
+            HostScope hs_(PF_H_PLAN);
             std::vector<int> nb_row(LD.nblk), nb_col(LD.nblk), src4(4 * (size_t)LD.nblk);
             for (int P = 0; P < S.ncl; ++P)
                 for (int e = S.pat_ptr[P]; e < S.pat_ptr[P + 1]; ++e) {
@@ -767,10 +792,15 @@ static int factor_impl(hs_factor_s* F, const hs_csr* A, const hs_geometry* G, hi
         // ranks decide the next level's sizes: one synchronisation per level
         LD.k.resize(LD.ncl);
         std::vector<int> flag(LD.ncl), ntot(LD.ncl);
-        HIP_TRY(hipMemcpyAsync(LD.k.data(), LD.dev.k, LD.ncl * sizeof(int), hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipMemcpyAsync(flag.data(), LD.dev.flag, LD.ncl * sizeof(int), hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipMemcpyAsync(ntot.data(), LD.dev.ntot, LD.ncl * sizeof(int), hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipStreamSynchronize(st));
+        {
+            HostScope hs_(PF_H_SYNC);
+            HIP_TRY(hipMemcpyAsync(LD.k.data(), LD.dev.k, LD.ncl * sizeof(int), hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipMemcpyAsync(flag.data(), LD.dev.flag, LD.ncl * sizeof(int), hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipMemcpyAsync(ntot.data(), LD.dev.ntot, LD.ncl * sizeof(int), hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipStreamSynchronize(st));
+        }
+        LD.pairs.release();  // used by this level's Schur updates only
+        LD.dev.pair_blk = nullptr;
         for (int c = 0; c < LD.ncl; ++c)
             if (flag[c]) {
                 F->info.breakdown_level = lvl;

@@ -806,6 +806,32 @@ void launch_merge(int nblk_next, const int* nb_row, const int* nb_col, const int
 #undef HS_MERGE
 }
 
+__global__ void k_pair_blocks(const int* __restrict__ nbr_ptr, const int* __restrict__ nbr_id,
+                              const int* __restrict__ pat_ptr, const int* __restrict__ pat,
+                              const int64_t* __restrict__ pair_base, int* __restrict__ pair_blk) {
+    const int s = blockIdx.x;
+    const int e0 = nbr_ptr[s], nb = nbr_ptr[s + 1] - e0;
+    int* out = pair_blk + pair_base[s];
+    for (int x = threadIdx.x; x < nb * nb; x += blockDim.x) {
+        const int a = nbr_id[e0 + x / nb], b = nbr_id[e0 + x % nb];
+        int lo = pat_ptr[a], hi = pat_ptr[a + 1];
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (pat[mid] < b)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        out[x] = (lo < pat_ptr[a + 1] && pat[lo] == b) ? lo : -1;
+    }
+}
+
+void launch_pair_blocks(int ncl, const int* nbr_ptr, const int* nbr_id, const int* pat_ptr, const int* pat,
+                        const int64_t* pair_base, int* pair_blk, hipStream_t st) {
+    if (ncl == 0) return;
+    hipLaunchKernelGGL(k_pair_blocks, dim3(ncl), dim3(256), 0, st, nbr_ptr, nbr_id, pat_ptr, pat, pair_base, pair_blk);
+}
+
 template <class T>
 __global__ void k_fill_zero(T* p, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)

@@ -49,6 +49,11 @@ void launch_merge(int nblk_next, const int* nb_row, const int* nb_col, const int
                   const int* m_next, const int64_t* blk_off_next, void* blocks_next, int next_f32, int ncl_prev,
                   hipStream_t st);
 void launch_fill_zero(void* p, int64_t n, int f32, hipStream_t st);
+// pair_blk[pair_base[s] + i nb + j] = block id of (a_i, a_j) for the
+// neighbours a_0 .. a_{nb-1} of every cluster s (binary search in the level's
+// block pattern pat_ptr / pat).
+void launch_pair_blocks(int ncl, const int* nbr_ptr, const int* nbr_id, const int* pat_ptr, const int* pat,
+                        const int64_t* pair_base, int* pair_blk, hipStream_t st);
 // Dense level (complete cluster graph): assemble D (N x N, ld N) from the
 // block store, unpivoted blocked LU in place, per-cluster operators into the
 // records.  inv: 2 * 128 * 128 doubles of workspace; flag: device int, set to

@@ -10,6 +10,7 @@
 
 #include <algorithm>
 #include <array>
+#include <cstdint>
 #include <cstring>
 
 #include "hs.h"
@@ -30,9 +31,49 @@ struct Box {
     std::array<int, 3> lo, hi;
 };
 
+constexpr int DENSE_MAX = 1 << 14;  // levels up to this many clusters use word bitsets
+
 // Greedy distance-2 colouring by ascending index; returns the colour count.
+// Word-bitset form: the clusters within distance 2 of i are the union of
+// N(j) + {j} over j in N(i); those below i are already coloured.
+int colour_distance2_bits(int ncl, const std::vector<int>& ptr, const std::vector<int>& adj,
+                          std::vector<int>& color) {
+    const int w = (ncl + 63) >> 6;
+    std::vector<uint64_t> nb((size_t)ncl * w, 0), d(w);
+    for (int j = 0; j < ncl; ++j) {
+        uint64_t* r = nb.data() + (size_t)j * w;
+        r[j >> 6] |= uint64_t(1) << (j & 63);
+        for (int e = ptr[j]; e < ptr[j + 1]; ++e) r[adj[e] >> 6] |= uint64_t(1) << (adj[e] & 63);
+    }
+    color.assign(ncl, -1);
+    std::vector<int> mark;
+    int ncolors = 0;
+    for (int i = 0; i < ncl; ++i) {
+        std::fill(d.begin(), d.end(), 0);
+        for (int e = ptr[i]; e < ptr[i + 1]; ++e) {
+            const uint64_t* r = nb.data() + (size_t)adj[e] * w;
+            for (int k = 0; k <= (i >> 6); ++k) d[k] |= r[k];
+        }
+        for (int k = 0; k <= (i >> 6); ++k) {
+            uint64_t x = d[k];
+            if (k == (i >> 6)) x &= (uint64_t(1) << (i & 63)) - 1;  // coloured: below i
+            for (; x; x &= x - 1) {
+                const int c = color[(k << 6) + __builtin_ctzll(x)];
+                if ((int)mark.size() <= c) mark.resize(c + 1, -1);
+                mark[c] = i;
+            }
+        }
+        int c = 0;
+        while (c < (int)mark.size() && mark[c] == i) ++c;
+        color[i] = c;
+        ncolors = std::max(ncolors, c + 1);
+    }
+    return ncolors;
+}
+
 int colour_distance2(int ncl, const std::vector<int>& ptr, const std::vector<int>& adj,
                      std::vector<int>& color) {
+    if (ncl <= DENSE_MAX) return colour_distance2_bits(ncl, ptr, adj, color);
     color.assign(ncl, -1);
     std::vector<int> mark;  // mark[c] == i  <=> colour c used near i
     int ncolors = 0;
@@ -59,44 +100,46 @@ int colour_distance2(int ncl, const std::vector<int>& ptr, const std::vector<int
     return ncolors;
 }
 
-// Sorted-row set with membership test; dense bit rows for small levels.
+// Sorted-row set with membership test; for levels up to 2^14 clusters, rows
+// of 64-bit words (row scans skip empty words and walk set bits).
 class Pattern {
    public:
-    explicit Pattern(int n) : n_(n), dense_((int64_t)n * n <= (int64_t)1 << 26) {
+    explicit Pattern(int n) : n_(n), w_((n + 63) >> 6), dense_(n <= DENSE_MAX) {
         if (dense_)
-            bits_.assign((size_t)n * n, 0);
+            bits_.assign((size_t)n * w_, 0);
         else
             rows_.assign(n, {});
     }
-    bool has(int a, int b) const {
-        if (dense_) return bits_[(size_t)a * n_ + b] != 0;
-        const auto& r = rows_[a];
-        return std::binary_search(r.begin(), r.end(), b);
-    }
     void add(int a, int b) {
         if (dense_) {
-            bits_[(size_t)a * n_ + b] = 1;
+            bits_[(size_t)a * w_ + (b >> 6)] |= uint64_t(1) << (b & 63);
             return;
         }
         auto& r = rows_[a];
         auto it = std::lower_bound(r.begin(), r.end(), b);
         if (it == r.end() || *it != b) r.insert(it, b);
     }
+    bool dense() const { return dense_; }
+    int words() const { return w_; }
+    void or_row(int a, const uint64_t* mask) {  // dense only
+        uint64_t* r = bits_.data() + (size_t)a * w_;
+        for (int k = 0; k < w_; ++k) r[k] |= mask[k];
+    }
     void row(int a, std::vector<int>& out) const {
         out.clear();
         if (dense_) {
-            const uint8_t* p = bits_.data() + (size_t)a * n_;
-            for (int b = 0; b < n_; ++b)
-                if (p[b]) out.push_back(b);
+            const uint64_t* p = bits_.data() + (size_t)a * w_;
+            for (int k = 0; k < w_; ++k)
+                for (uint64_t x = p[k]; x; x &= x - 1) out.push_back((k << 6) + __builtin_ctzll(x));
         } else {
             out = rows_[a];
         }
     }
 
    private:
-    int n_;
+    int n_, w_;
     bool dense_;
-    std::vector<uint8_t> bits_;
+    std::vector<uint64_t> bits_;
     std::vector<std::vector<int>> rows_;
 };
 
@@ -120,6 +163,7 @@ void simulate_level(LevelSymbolic& L, std::vector<int>& next_ptr, std::vector<in
     std::vector<std::vector<int>> fill(ncl);
     std::vector<int> row;
     std::vector<char> isnbr(ncl, 0);
+    std::vector<uint64_t> mask(P.words(), 0);
     for (int s : L.order) {
         for (int e = L.adj_ptr[s]; e < L.adj_ptr[s + 1]; ++e) isnbr[L.adj[e]] = 1;
         P.row(s, row);
@@ -127,8 +171,15 @@ void simulate_level(LevelSymbolic& L, std::vector<int>& next_ptr, std::vector<in
             if (t != s && !isnbr[t]) fill[s].push_back(t);
         std::sort(fill[s].begin(), fill[s].end(), [&](int a, int b) { return L.pos[a] < L.pos[b]; });
         for (int e = L.adj_ptr[s]; e < L.adj_ptr[s + 1]; ++e) isnbr[L.adj[e]] = 0;
-        for (int e = L.adj_ptr[s]; e < L.adj_ptr[s + 1]; ++e)
-            for (int f = L.adj_ptr[s]; f < L.adj_ptr[s + 1]; ++f) P.add(L.adj[e], L.adj[f]);
+        // eliminating s couples every pair of its neighbours
+        if (P.dense()) {
+            for (int e = L.adj_ptr[s]; e < L.adj_ptr[s + 1]; ++e) mask[L.adj[e] >> 6] |= uint64_t(1) << (L.adj[e] & 63);
+            for (int e = L.adj_ptr[s]; e < L.adj_ptr[s + 1]; ++e) P.or_row(L.adj[e], mask.data());
+            for (int e = L.adj_ptr[s]; e < L.adj_ptr[s + 1]; ++e) mask[L.adj[e] >> 6] = 0;
+        } else {
+            for (int e = L.adj_ptr[s]; e < L.adj_ptr[s + 1]; ++e)
+                for (int f = L.adj_ptr[s]; f < L.adj_ptr[s + 1]; ++f) P.add(L.adj[e], L.adj[f]);
+        }
     }
     L.fill_ptr.assign(ncl + 1, 0);
     L.fill.clear();
