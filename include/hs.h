@@ -232,14 +232,18 @@ void hs_symbolic_free(hs_symbolic_t S);
 /* ---- tracing ----------------------------------------------------------- */
 
 /* Per-kernel-family timing with HIP events recorded on the stream of each
- * call (a tracing aid; off by default).  Families: "gram", "pivot", "fill",
- * "nbr", "schur", "merge", "apply", "spmv".  While enabled, every launch of a
- * family is bracketed by two events; intervals are read back at the next
- * synchronisation of the library.  hs_profile_read returns, for one family
- * since the last reset: launches, summed seconds, and the algorithmic bytes
- * and flops of those launches (counted from the sizes the kernels worked on:
- * for "schur", per cluster 2 f n_tot^2 flops and 8 (2 f n_tot + 2 n_tot^2)
- * bytes in float64).  Unknown family: HS_ERR_ARG. */
+ * call (a tracing aid; off by default).  Kernel families: "gram", "pivot",
+ * "fill", "nbr", "schur", "merge", "apply", "spmv", "dense".  While enabled,
+ * every launch of a family is bracketed by two events; intervals are read
+ * back at the next synchronisation of the library.  Host families (wall time
+ * of the factorization's host steps, one count per step): "host_symbolic",
+ * "host_plan", "host_upload", "host_alloc", "host_sync" (the per-level rank
+ * read-back, which waits for the level's kernels).  hs_profile_read returns,
+ * for one family since the last reset: launches, summed seconds, and the
+ * algorithmic bytes and flops of those launches (counted from the sizes the
+ * kernels worked on: for "schur", per cluster 2 f n_tot^2 flops and
+ * b (2 f n_tot + 2 n_tot^2) bytes, b = 8 for float64 levels and 4 for float32
+ * levels of the mixed form).  Unknown family: HS_ERR_ARG. */
 int hs_profile_enable(int32_t enable);
 int hs_profile_reset(void);
 int hs_profile_read(const char* family, int64_t* launches, double* seconds, double* bytes, double* flops);
