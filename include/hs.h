@@ -88,7 +88,12 @@ typedef struct hs_geometry {
  *   eps         relative truncation tolerance of the fill compression
  *               (Eq. lra): a pivot R_jj of the rank-revealing QR is kept while
  *               |R_jj| > eps |R_11|.  eps = 0 selects the exact mode, in which
- *               a cluster with fill is passed whole to the next level.
+ *               a cluster with fill is passed whole to the next level.  The
+ *               pivots come from the Gram matrix F F^T (pivoted Cholesky),
+ *               whose R_jj^2 carry an absolute rounding error near
+ *               u |R_11|^2 (u = 2^-53): ratios |R_jj| / |R_11| are resolved
+ *               to about u / (2 eps^2) relative, so eps below about 1e-7
+ *               decides at the rounding level.
  *   fixed_rank  if > 0, additionally cap every rank at this value (the fixed
  *               rank K of Sec. 5.1).
  *   leaf_size   target number of unknowns per leaf cluster (> 0).
@@ -150,6 +155,30 @@ typedef struct hs_info {
 int hs_factor(const hs_csr* A, const hs_geometry* geom, const hs_opts* opts, void* hip_stream,
               hs_factor_t* F_out);
 
+/* Factor nsys independent systems A[i] (grid geom[i]) together, as the one
+ * block-diagonal system that stacks them in the given order (Alg. 1 on the
+ * forest of their cluster trees, leaves of every system on level 0): each
+ * kernel launch of a level and colour (Sec. 3.4) covers the clusters of
+ * every system, and the stream is synchronised once per level of the
+ * deepest system.  The result is one factorization of n = sum of the A[i].n
+ * unknowns; hs_solve / hs_pcg / hs_gmres take right-hand sides that stack
+ * the systems' rows in the same order, and the Krylov solvers keep one
+ * recurrence and one stopping test per system and column.  Every system's
+ * factor and Krylov numbers are those of hs_factor on that system alone
+ * (the same kernels on the same data in the same order; the work of other
+ * systems only shares the launches), except that a batch containing a
+ * nonsymmetric system factors every system in the general form when
+ * opts->symmetric is -1.  A[i] and geom[i] as for hs_factor (host and device
+ * CSR may be mixed); nsys >= 1.  Errors as hs_factor, with the failing
+ * system named in hs_last_error(). */
+int hs_factor_batch(int32_t nsys, const hs_csr* A, const hs_geometry* geom, const hs_opts* opts,
+                    void* hip_stream, hs_factor_t* F_out);
+
+/* Systems of a factorization: *nsys (1 for hs_factor) and, if row_off is not
+ * NULL, the first row of every system in the stacked vectors (host array of
+ * nsys + 1 entries; row_off[nsys] = n). */
+int hs_factor_systems(hs_factor_t F, int32_t* nsys, int64_t* row_off);
+
 /* Apply the factorization once (Alg. 2): X = A_fac^{-1} B.
  * B, X: device pointers, n x nrhs column major with leading dimensions ldb,
  * ldx >= n; B is not modified; X may alias B only if ldx == ldb.  Stream
@@ -158,18 +187,25 @@ int hs_solve(hs_factor_t F, int64_t nrhs, const double* B, int64_t ldb, double* 
              void* hip_stream);
 
 /* Preconditioned conjugate gradients (symmetric positive definite A), one
- * recurrence per right-hand side, x0 = 0, float64, preconditioner = the
- * factorization (Sec. 5.1).  Iterates until ||b - A x||_2 <= tol ||b||_2 for
- * every column or maxit iterations.  B, X device pointers as in hs_solve.
- * iters_out (host, may be NULL): iterations taken; relres_out (host, nrhs
- * entries, may be NULL): final true relative residual of every column.
- * Returns HS_WARN_NOT_CONVERGED if some column missed tol. */
+ * recurrence per system and right-hand side (lane l = s + nsys * c), x0 = 0,
+ * float64, preconditioner = the factorization (Sec. 5.1).  Iterates until
+ * ||b - A x||_2 <= tol ||b||_2 on every lane (norms over the lane's system)
+ * or maxit iterations; a lane that meets tol is left as it is.  With a mixed
+ * factorization the flexible (Polak-Ribiere) beta is used.  B, X device
+ * pointers as in hs_solve.  iters_out (host, may be NULL): iterations taken
+ * (largest over the lanes); relres_out (host, nsys * nrhs entries, may be
+ * NULL): final true relative residual of every lane.  Returns
+ * HS_WARN_NOT_CONVERGED if some lane missed tol. */
 int hs_pcg(hs_factor_t F, int64_t nrhs, const double* B, int64_t ldb, double* X, int64_t ldx,
            double tol, int32_t maxit, int32_t* iters_out, double* relres_out, void* hip_stream);
 
-/* Right-preconditioned restarted GMRES(restart) with modified Gram-Schmidt,
- * x0 = 0, float64, for general A; each column solved independently; same
- * arguments and stopping rule as hs_pcg. */
+/* Right-preconditioned restarted GMRES(restart), x0 = 0, float64, for
+ * general A (Sec. 5.2): the Krylov basis is orthonormalised by classical
+ * Gram-Schmidt applied twice, one recurrence per lane as in hs_pcg, all lanes
+ * advanced together; a lane whose residual estimate meets tol stops
+ * extending its basis and updates x at the end of the cycle.  Same arguments
+ * and stopping rule as hs_pcg (iters_out: inner iterations of the slowest
+ * lane). */
 int hs_gmres(hs_factor_t F, int64_t nrhs, const double* B, int64_t ldb, double* X, int64_t ldx,
              double tol, int32_t maxit, int32_t restart, int32_t* iters_out, double* relres_out,
              void* hip_stream);
@@ -233,7 +269,9 @@ void hs_symbolic_free(hs_symbolic_t S);
 
 /* Per-kernel-family timing with HIP events recorded on the stream of each
  * call (a tracing aid; off by default).  Kernel families: "gram", "pivot",
- * "fill", "nbr", "schur", "merge", "apply", "spmv", "dense".  While enabled,
+ * "fill", "nbr", "schur" (Schur updates of float64 levels), "schur_f32"
+ * (Schur updates of float32 levels, mixed form), "merge", "apply", "spmv",
+ * "dense".  While enabled,
  * every launch of a family is bracketed by two events; intervals are read
  * back at the next synchronisation of the library.  Host families (wall time
  * of the factorization's host steps, one count per step): "host_symbolic",
@@ -241,9 +279,8 @@ void hs_symbolic_free(hs_symbolic_t S);
  * read-back, which waits for the level's kernels).  hs_profile_read returns,
  * for one family since the last reset: launches, summed seconds, and the
  * algorithmic bytes and flops of those launches (counted from the sizes the
- * kernels worked on: for "schur", per cluster 2 f n_tot^2 flops and
- * b (2 f n_tot + 2 n_tot^2) bytes, b = 8 for float64 levels and 4 for float32
- * levels of the mixed form).  Unknown family: HS_ERR_ARG. */
+ * kernels worked on: for "schur" and "schur_f32", per cluster 2 f n_tot^2
+ * flops and b (2 f n_tot + 2 n_tot^2) bytes, b = 8 and 4 respectively).  Unknown family: HS_ERR_ARG. */
 int hs_profile_enable(int32_t enable);
 int hs_profile_reset(void);
 int hs_profile_read(const char* family, int64_t* launches, double* seconds, double* bytes, double* flops);

@@ -96,6 +96,8 @@ _PD = ctypes.POINTER(ctypes.c_double)
 
 _SIGS = {
     "hs_factor": (ctypes.c_int, [ctypes.POINTER(hs_csr), ctypes.POINTER(hs_geometry), ctypes.POINTER(hs_opts), _P, ctypes.POINTER(_P)]),
+    "hs_factor_batch": (ctypes.c_int, [_I32, ctypes.POINTER(hs_csr), ctypes.POINTER(hs_geometry), ctypes.POINTER(hs_opts), _P, ctypes.POINTER(_P)]),
+    "hs_factor_systems": (ctypes.c_int, [_P, _PI32, ctypes.POINTER(_I64)]),
     "hs_solve": (ctypes.c_int, [_P, _I64, _P, _I64, _P, _I64, _P]),
     "hs_pcg": (ctypes.c_int, [_P, _I64, _P, _I64, _P, _I64, _D, _I32, _PI32, _PD, _P]),
     "hs_gmres": (ctypes.c_int, [_P, _I64, _P, _I64, _P, _I64, _D, _I32, _I32, _PI32, _PD, _P]),
@@ -205,20 +207,45 @@ def _rhs(B):
 
 
 class Factor:
-    """A device-resident factorization (hs_factor)."""
+    """A device-resident factorization (hs_factor, or hs_factor_batch through
+    Factor.batch).  Right-hand sides are (nrhs, n) CUDA float64 tensors, rows
+    of a batch stacked in the order of its systems."""
 
     def __init__(self, row_ptr, col_idx, val, dims, eps: float, leaf: int = 64, symmetric: int = -1,
                  precision: int = HS_FP64, fixed_rank: int = 0, keep_levels: bool = False, stream=None,
-                 coarse_fp64_dofs: int = 0):
+                 coarse_fp64_dofs: int = 0, _systems=None):
         keep: list = []
-        A = _csr_struct(row_ptr, col_idx, val, keep)
-        self.n = A.n
         opts = hs_opts(float(eps), int(fixed_rank), int(leaf), int(precision), int(symmetric), 1 if keep_levels else 0,
                        int(coarse_fp64_dofs))
-        geom = _geom(dims)
         h = _P()
-        _check(lib().hs_factor(ctypes.byref(A), ctypes.byref(geom), ctypes.byref(opts), _stream(stream), ctypes.byref(h)), "hs_factor")
+        if _systems is None:
+            A = _csr_struct(row_ptr, col_idx, val, keep)
+            geom = _geom(dims)
+            _check(lib().hs_factor(ctypes.byref(A), ctypes.byref(geom), ctypes.byref(opts), _stream(stream), ctypes.byref(h)), "hs_factor")
+        else:
+            ns = len(_systems)
+            As = (hs_csr * ns)(*[_csr_struct(r, c, v, keep) for (r, c, v, _) in _systems])
+            Gs = (hs_geometry * ns)(*[_geom(d) for (_, _, _, d) in _systems])
+            _check(lib().hs_factor_batch(ns, As, Gs, ctypes.byref(opts), _stream(stream), ctypes.byref(h)), "hs_factor_batch")
         self._h = h
+        ns = _I32(0)
+        _check(lib().hs_factor_systems(h, ctypes.byref(ns), None), "hs_factor_systems")
+        self.nsys = int(ns.value)
+        off = (_I64 * (self.nsys + 1))()
+        _check(lib().hs_factor_systems(h, ctypes.byref(ns), off), "hs_factor_systems")
+        self.row_off = np.array(off[:], dtype=np.int64)
+        self.n = int(self.row_off[-1])
+
+    @classmethod
+    def batch(cls, systems, eps: float, leaf: int = 64, symmetric: int = -1, precision: int = HS_FP64,
+              fixed_rank: int = 0, stream=None, coarse_fp64_dofs: int = 0) -> "Factor":
+        """hs_factor_batch over systems = [(row_ptr, col_idx, val, dims), ...]."""
+        return cls(None, None, None, None, eps, leaf, symmetric, precision, fixed_rank, False, stream,
+                   coarse_fp64_dofs, _systems=list(systems))
+
+    def _lanes(self, rel, nrhs):
+        a = np.array(rel[:])
+        return a if self.nsys == 1 else a.reshape(nrhs, self.nsys)
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -245,9 +272,9 @@ class Factor:
         if X is None:
             X = torch.empty_like(B2)
         it = _I32(0)
-        rel = (ctypes.c_double * nrhs)()
+        rel = (ctypes.c_double * (nrhs * self.nsys))()
         rc = _check(lib().hs_pcg(self._h, nrhs, _ptr(B2), ldb, _ptr(X), X.stride(0), float(tol), int(maxit), ctypes.byref(it), rel, _stream(stream)), "hs_pcg")
-        return (X.reshape(-1) if sq else X), int(it.value), np.array(rel[:]), rc == HS_OK
+        return (X.reshape(-1) if sq else X), int(it.value), self._lanes(rel, nrhs), rc == HS_OK
 
     def gmres(self, B, tol: float = 1e-10, maxit: int = 500, restart: int = 30, X=None, stream=None):
         import torch
@@ -256,9 +283,9 @@ class Factor:
         if X is None:
             X = torch.empty_like(B2)
         it = _I32(0)
-        rel = (ctypes.c_double * nrhs)()
+        rel = (ctypes.c_double * (nrhs * self.nsys))()
         rc = _check(lib().hs_gmres(self._h, nrhs, _ptr(B2), ldb, _ptr(X), X.stride(0), float(tol), int(maxit), int(restart), ctypes.byref(it), rel, _stream(stream)), "hs_gmres")
-        return (X.reshape(-1) if sq else X), int(it.value), np.array(rel[:]), rc == HS_OK
+        return (X.reshape(-1) if sq else X), int(it.value), self._lanes(rel, nrhs), rc == HS_OK
 
     def info(self) -> hs_info:
         out = hs_info()

@@ -39,13 +39,14 @@ struct LevelDev {
     int symmetric;
     double eps;
     int fixed_rank;
-    int gram_splits;
+    int gram_splits;          // Gram partial slots per cluster workspace (largest of the level)
     const int* m;             // [ncl] sizes at the start of the level
     int* k;                   // [ncl] coarse sizes after elimination (rank)
     int* flag;                // [ncl] 1 = breakdown in an unpivoted LU
-    const int64_t* blk_off;   // [nblk] element offset of every block (capacity m_a x m_b, ld m_a)
-    double* blocks;           // element type of the level's storage (double, or float in the mixed form)
-    int f32;                  // storage element type is float
+    const int64_t* blk_off;   // [nblk] offset of every block in units of its element type
+                              // (capacity m_a x m_b, ld m_a)
+    double* blocks;           // storage of every cluster's blocks: float64, or float32 for the
+                              // clusters of a system whose level is stored in float32 (mixed form)
     const int* diag_blk;      // [ncl] block id of (s, s)
     const int* nbr_ptr;       // [ncl+1] neighbours n(s)
     const int* nbr_id;
@@ -63,7 +64,7 @@ struct LevelDev {
     const int64_t* pair_base; // [ncl] index of pair (0,0) of s in pair_blk
     const int* pair_blk;      // block id of (a_i, a_j) at pair_base[s] + i*nb + j
     const int64_t* rec_off;   // [ncl] record: T_L' (m^2), T_R' (m^2), E_R (m x ncap, ld m), E_L (ncap x m, ld ncap)
-    double* rec;              // same element type as blocks
+    double* rec;              // same element type as the cluster's blocks (offsets in its units)
     const int64_t* ws_off;    // [ncl] per-colour workspace of every cluster
     double* ws;
 };
@@ -71,9 +72,17 @@ struct LevelDev {
 // Workspace slots of a cluster (each m x m, column major, ld m).
 enum WsSlot { WS_AINV = 0, WS_LINV, WS_UINV, WS_U, WS_X, WS_SL, WS_SR, WS_TL, WS_TR, WS_CU, WS_UC, WS_SCR, WS_GP };
 __host__ __device__ inline int64_t ws_slots(int gram_splits) { return WS_GP + gram_splits; }
+// Gram partial sums of a cluster with nf fill partners: about four partners
+// per workgroup.  A function of the cluster alone, so the sums are formed in
+// the same order whatever else shares the launch.
+constexpr int GRAM_SPLITS_MAX = 64;
+__host__ __device__ inline int gram_splits_of(int nf) {
+    const int s = (nf + 3) / 4;
+    return s < 1 ? 1 : (s > GRAM_SPLITS_MAX ? GRAM_SPLITS_MAX : s);
+}
 
 __device__ inline int cur_size(const LevelDev& L, int a, int before) { return before ? L.k[a] : L.m[a]; }
-// Block id / record of cluster s in the level's storage type T (offsets count elements).
+// Block id / record of cluster s in its storage type T (offsets count elements of T).
 template <class T>
 __device__ inline T* blk_t(const LevelDev& L, int id) {
     return reinterpret_cast<T*>(L.blocks) + L.blk_off[id];

@@ -9,6 +9,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -16,6 +18,7 @@
 #include <cstring>
 #include <memory>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "hs.h"
@@ -128,12 +131,12 @@ struct ProfFamily {
     double seconds = 0.0, bytes = 0.0, flops = 0.0;
 };
 enum ProfId {
-    PF_GRAM = 0, PF_PIVOT, PF_FILL, PF_NBR, PF_SCHUR, PF_MERGE, PF_APPLY, PF_SPMV, PF_DENSE,
+    PF_GRAM = 0, PF_PIVOT, PF_FILL, PF_NBR, PF_SCHUR, PF_SCHUR_F32, PF_MERGE, PF_APPLY, PF_SPMV, PF_DENSE,
     // host wall time of the factorization: symbolic analysis, level planning,
     // metadata uploads, device allocations, per-level rank read-back
     PF_H_SYMBOLIC, PF_H_PLAN, PF_H_UPLOAD, PF_H_ALLOC, PF_H_SYNC, PF_COUNT
 };
-static ProfFamily g_prof[PF_COUNT] = {{"gram"}, {"pivot"}, {"fill"}, {"nbr"},   {"schur"},
+static ProfFamily g_prof[PF_COUNT] = {{"gram"}, {"pivot"}, {"fill"}, {"nbr"},   {"schur"}, {"schur_f32"},
                                       {"merge"}, {"apply"}, {"spmv"}, {"dense"},
                                       {"host_symbolic"}, {"host_plan"}, {"host_upload"}, {"host_alloc"}, {"host_sync"}};
 static bool g_prof_on = false;
@@ -206,25 +209,33 @@ static void prof_flush() {
 
 // ------------------------------------------------------------- level state
 
+// Work lists of one colour by storage type: [0] the float32 clusters, [1] the
+// float64 clusters with those factored densely on this level last.  The
+// factor lists (fac) leave the dense clusters out; the solve lists (sol) hold
+// every cluster of the colour.
 struct ColourHost {
     int first = 0, n = 0;                          // slice of the processing order
-    size_t off_clist, off_nbr_pre, off_fill_pre, off_tile_pre, off_part_off;
-    ColourDev dev;
-    const int64_t* part_off = nullptr;             // [nbr_total] in units of f
-    int64_t part_total = 0;                        // sum of f over the entries
+    int n_t[2] = {0, 0};                           // clusters per type
+    int nfac_t[2] = {0, 0};                        // of which factored by the colour kernels
+    size_t off_nbr_pre[2], off_fill_pre[2], off_tile_pre[2];
+    ColourDev fac[2], sol[2];
+    const int64_t* part_off[2] = {nullptr, nullptr};  // [nbr entries + 1] in units of f
+    int64_t part_total[2] = {0, 0};                // sum of f over the entries
 };
 
 struct LevelData {
     int ncl = 0;
     int nblk = 0;
-    int f32 = 0;                                   // blocks and records stored in float (mixed form)
+    int any_f32 = 0;                               // some cluster's blocks and records are float32
+    std::vector<int> f32;                          // per cluster: float32 storage (mixed form)
+    std::vector<char> dense;                       // per cluster: factored densely on this level
     int64_t npairs = 0;                            // sum over clusters of |n(s)|^2
     DevBuf pairs;                                  // block id of every neighbour pair (a_i, a_j) of s
-    size_t esz() const { return f32 ? sizeof(float) : sizeof(double); }
     std::vector<int> m, k;                         // sizes at the start, ranks after
-    std::vector<int64_t> blk_off;
-    int64_t block_elems = 0;
-    int64_t rec_elems = 0;
+    std::vector<int64_t> blk_off;                  // in units of the block's element type
+    std::vector<int64_t> rec_off;                  // in units of the record's element type
+    int64_t block_bytes = 0;
+    int64_t rec_bytes = 0;
     int64_t ws_elems = 0;
     int gram_splits = 1;
     int max_m = 0;
@@ -235,11 +246,14 @@ struct LevelData {
     SolveLevelDev sdev{};
     const int* dev_pat_ptr = nullptr;  // final pattern on the device
     const int* dev_pat = nullptr;
+    const int* dev_f32 = nullptr;      // per-cluster storage type on the device
     std::vector<ColourHost> colours;
+    std::vector<int> order_host;                   // the colour slices by type (host copy of the work lists)
     std::vector<int64_t> seg;                      // [ncl+1] segment offsets
     int64_t nseg = 0;
     int64_t part_max = 0;                          // largest colour part buffer (units of f)
     std::vector<double> kept;                      // dense starting matrix (keep_levels)
+    size_t esz(int s) const { return f32[s] ? sizeof(float) : sizeof(double); }
 };
 
 }  // namespace hs
@@ -249,6 +263,9 @@ struct hs_factor_s {
     hs_opts opts{};
     int symmetric = 1;
     hs::Symbolic sym;
+    hs::Forest forest;                    // the systems (one for hs_factor)
+    hs::DevBuf seg_buf;                   // per-system Krylov segment and chunk tables
+    hs::SegDev segs;
     std::vector<hs::LevelData> levels;
     hs::DevBuf A_row, A_col, A_val;
     hs::DevBuf cluster_of, local_of;
@@ -294,7 +311,8 @@ static int validate_csr_host(int64_t n, int64_t nnz, const int64_t* rp, const in
 // ================================================================ planning
 
 // Plan one level: block offsets, per-cluster lists, colours, records and
-// workspace.  Builds the metadata blob (uploaded by the caller).
+// workspace.  LD.m, LD.f32 and LD.dense are set by the caller.  Builds the
+// metadata blob (uploaded by the caller).
 static int plan_level(hs_factor_s* F, int lvl, Blob& blob, std::vector<size_t>& offs) {
     LevelData& LD = F->levels[lvl];
     const LevelSymbolic& S = F->sym.levels[lvl];
@@ -303,23 +321,30 @@ static int plan_level(hs_factor_s* F, int lvl, Blob& blob, std::vector<size_t>& 
     LD.ncl = ncl;
     LD.nblk = (int)S.pat.size();
     LD.max_m = 0;
-    for (int c = 0; c < ncl; ++c) LD.max_m = std::max(LD.max_m, m[c]);
+    for (int c = 0; c < ncl; ++c)
+        if (!LD.dense[c]) LD.max_m = std::max(LD.max_m, m[c]);
     if (LD.max_m > MAX_M)
         return fail(HS_ERR_UNSUPPORTED, "cluster of size " + std::to_string(LD.max_m) + " at level " +
                                             std::to_string(lvl) + " exceeds the supported " + std::to_string(MAX_M));
-    // blocks (capacity m_a x m_b, column major, ld m_a)
+    // blocks (capacity m_a x m_b, column major, ld m_a), each in its cluster's
+    // element type; offsets count elements of that type
+    auto place = [](int64_t& cursor, int64_t elems, size_t es) {
+        cursor = (cursor + 15) & ~int64_t(15);
+        const int64_t o = cursor / (int64_t)es;
+        cursor += elems * (int64_t)es;
+        return o;
+    };
     LD.blk_off.resize(LD.nblk);
-    int64_t off = 0;
+    int64_t cur = 0;
     for (int a = 0; a < ncl; ++a)
-        for (int e = S.pat_ptr[a]; e < S.pat_ptr[a + 1]; ++e) {
-            LD.blk_off[e] = off;
-            off += (int64_t)m[a] * m[S.pat[e]];
-        }
-    LD.block_elems = off;
+        for (int e = S.pat_ptr[a]; e < S.pat_ptr[a + 1]; ++e)
+            LD.blk_off[e] = place(cur, (int64_t)m[a] * m[S.pat[e]], LD.esz(a));
+    LD.block_bytes = cur;
 
     // per-cluster lists
     std::vector<int> diag_blk(ncl), nbr_before, nbr_bsa, nbr_bas, ncap(ncl), fill_before, fill_bst, fill_bts;
-    std::vector<int64_t> pair_base(ncl), rec_off(ncl), ws_off(ncl, 0);
+    std::vector<int64_t> pair_base(ncl), ws_off(ncl, 0);
+    LD.rec_off.assign(ncl, 0);
     nbr_before.resize(S.adj.size());
     nbr_bsa.resize(S.adj.size());
     nbr_bas.resize(S.adj.size());
@@ -352,58 +377,88 @@ static int plan_level(hs_factor_s* F, int lvl, Blob& blob, std::vector<size_t>& 
         pair_base[s] = pp;
         const int64_t nb = S.adj_ptr[s + 1] - S.adj_ptr[s];
         pp += nb * nb;
-        rec_off[s] = roff;
-        roff += 2 * (int64_t)m[s] * m[s] + 2 * (int64_t)m[s] * cap;
+        LD.rec_off[s] = place(roff, 2 * (int64_t)m[s] * m[s] + 2 * (int64_t)m[s] * cap, LD.esz(s));
     }
-    LD.rec_elems = roff;
+    LD.rec_bytes = roff;
     LD.npairs = pp;
-    // about four fill partners per Gram workgroup
-    LD.gram_splits = std::min(64, std::max(1, (max_nf + 3) / 4));
+    LD.gram_splits = gram_splits_of(max_nf);  // workspace slots; each cluster uses gram_splits_of(its nf)
     const int64_t slots = ws_slots(LD.gram_splits);
 
-    // colours
+    // colours: every colour's slice of the processing order is reordered into
+    // [float32 clusters | float64 clusters | dense clusters] (stable, so each
+    // system keeps its own order; clusters of one colour never interact)
+    std::vector<int> order(ncl);
     LD.colours.assign(S.ncolors, ColourHost());
-    std::vector<std::vector<int>> c_nbr_pre(S.ncolors), c_fill_pre(S.ncolors);
-    std::vector<std::vector<int64_t>> c_tile_pre(S.ncolors);
     int64_t ws_max = 0;
+    struct Pre {
+        std::vector<int> np, fp;
+        std::vector<int64_t> tp;
+    };
+    std::vector<std::array<Pre, 2>> pres(S.ncolors);
     for (int c = 0; c < S.ncolors; ++c) {
         ColourHost& CH = LD.colours[c];
         CH.first = S.color_ptr[c];
         CH.n = S.color_ptr[c + 1] - S.color_ptr[c];
-        auto& np = c_nbr_pre[c];
-        auto& fp = c_fill_pre[c];
-        auto& tp = c_tile_pre[c];
-        np.assign(CH.n + 1, 0);
-        fp.assign(CH.n + 1, 0);
-        tp.assign(CH.n + 1, 0);
-        int max_m = 0, max_nm = 0;
-        int64_t wso = 0;
+        int w = CH.first;
+        for (int pass = 0; pass < 3; ++pass)
+            for (int i = 0; i < CH.n; ++i) {
+                const int s = S.order[CH.first + i];
+                const int cls = LD.f32[s] ? 0 : (LD.dense[s] ? 2 : 1);
+                if (cls == pass) order[w++] = s;
+            }
         for (int i = 0; i < CH.n; ++i) {
-            int s = S.order[CH.first + i];
-            np[i + 1] = np[i] + (S.adj_ptr[s + 1] - S.adj_ptr[s]);
-            fp[i + 1] = fp[i] + (S.fill_ptr[s + 1] - S.fill_ptr[s]);
-            int64_t tpr = (ncap[s] + SCHUR_T - 1) / SCHUR_T;
-            tp[i + 1] = tp[i] + (m[s] > 0 ? tpr * tpr : 0);
-            max_m = std::max(max_m, m[s]);
-            for (int e = S.adj_ptr[s]; e < S.adj_ptr[s + 1]; ++e) max_nm = std::max(max_nm, m[S.adj[e]]);
-            for (int e = S.fill_ptr[s]; e < S.fill_ptr[s + 1]; ++e) max_nm = std::max(max_nm, m[S.fill[e]]);
-            ws_off[s] = wso;
-            wso += slots * (int64_t)m[s] * m[s];
+            const int s = order[CH.first + i];
+            const int t = LD.f32[s] ? 0 : 1;
+            CH.n_t[t]++;
+            if (!LD.dense[s]) CH.nfac_t[t]++;
+        }
+        int64_t wso = 0;
+        int base = CH.first;
+        for (int t = 0; t < 2; ++t) {
+            Pre& P = pres[c][t];
+            const int nt = CH.n_t[t], nf = CH.nfac_t[t];
+            P.np.assign(nt + 1, 0);
+            P.fp.assign(nt + 1, 0);
+            P.tp.assign(nt + 1, 0);
+            int max_m_f = 0, max_nm_f = 0, max_m_s = 0, max_nm_s = 0;
+            for (int i = 0; i < nt; ++i) {
+                const int s = order[base + i];
+                P.np[i + 1] = P.np[i] + (S.adj_ptr[s + 1] - S.adj_ptr[s]);
+                P.fp[i + 1] = P.fp[i] + (S.fill_ptr[s + 1] - S.fill_ptr[s]);
+                const int64_t tpr = (ncap[s] + SCHUR_T - 1) / SCHUR_T;
+                P.tp[i + 1] = P.tp[i] + (m[s] > 0 ? tpr * tpr : 0);
+                int nm = 0;
+                for (int e = S.adj_ptr[s]; e < S.adj_ptr[s + 1]; ++e) nm = std::max(nm, m[S.adj[e]]);
+                for (int e = S.fill_ptr[s]; e < S.fill_ptr[s + 1]; ++e) nm = std::max(nm, m[S.fill[e]]);
+                max_m_s = std::max(max_m_s, m[s]);
+                max_nm_s = std::max(max_nm_s, nm);
+                if (i < nf) {
+                    max_m_f = std::max(max_m_f, m[s]);
+                    max_nm_f = std::max(max_nm_f, nm);
+                    ws_off[s] = wso;
+                    wso += slots * (int64_t)m[s] * m[s];
+                }
+            }
+            auto fillc = [&](ColourDev& D, int n, int mm, int mn) {
+                D.n = n;
+                D.nbr_total = P.np[n];
+                D.fill_total = P.fp[n];
+                D.tile_total = P.tp[n];
+                D.max_m = mm;
+                D.max_nbr_m = mn;
+                const int pw = panel_width(mm);
+                D.panels = (mn + pw - 1) / pw;
+                D.f32 = t == 0;
+            };
+            fillc(CH.fac[t], nf, max_m_f, max_nm_f);
+            fillc(CH.sol[t], nt, max_m_s, max_nm_s);
+            base += nt;
         }
         ws_max = std::max(ws_max, wso);
-        CH.dev.n = CH.n;
-        CH.dev.nbr_total = np[CH.n];
-        CH.dev.fill_total = fp[CH.n];
-        CH.dev.tile_total = tp[CH.n];
-        CH.dev.max_m = max_m;
-        CH.dev.max_nbr_m = max_nm;
-        const int pw = panel_width(max_m);
-        CH.dev.panels = (max_nm + pw - 1) / pw;
     }
     LD.ws_elems = ws_max;
 
     // blob layout
-    std::vector<int> order(S.order);
     offs.clear();
     offs.push_back(blob.add(m));                 // 0 m
     offs.push_back(blob.add(m));                 // 1 k (initialised to m)
@@ -425,16 +480,20 @@ static int plan_level(hs_factor_s* F, int lvl, Blob& blob, std::vector<size_t>& 
     offs.push_back(blob.add(fill_bts));          // 17
     offs.push_back(blob.add(pair_base));         // 18
     offs.push_back(blob.add(std::vector<int>()));  // 19 (pair block ids: LD.pairs)
-    offs.push_back(blob.add(rec_off));           // 20
+    offs.push_back(blob.add(LD.rec_off));        // 20
     offs.push_back(blob.add(ws_off));            // 21
     offs.push_back(blob.add(S.pat_ptr));         // 22
     offs.push_back(blob.add(S.pat));             // 23
-    offs.push_back(blob.add(order));             // 24 processing order (colour lists are slices)
+    offs.push_back(blob.add(order));             // 24 colour slices by type (the work lists)
+    LD.order_host = order;
+    offs.push_back(blob.add(LD.f32));            // 25 per-cluster storage type
     for (int c = 0; c < S.ncolors; ++c) {
         ColourHost& CH = LD.colours[c];
-        CH.off_nbr_pre = blob.add(c_nbr_pre[c]);
-        CH.off_fill_pre = blob.add(c_fill_pre[c]);
-        CH.off_tile_pre = blob.add(c_tile_pre[c]);
+        for (int t = 0; t < 2; ++t) {
+            CH.off_nbr_pre[t] = blob.add(pres[c][t].np);
+            CH.off_fill_pre[t] = blob.add(pres[c][t].fp);
+            CH.off_tile_pre[t] = blob.add(pres[c][t].tp);
+        }
     }
     return HS_OK;
 }
@@ -453,7 +512,6 @@ static void bind_level(LevelData& LD, const std::vector<size_t>& offs, const hs_
     D.flag = (int*)P(2);
     D.blk_off = (const int64_t*)P(3);
     D.blocks = LD.blocks.as<double>();
-    D.f32 = LD.f32;
     D.diag_blk = (const int*)P(4);
     D.nbr_ptr = (const int*)P(5);
     D.nbr_id = (const int*)P(6);
@@ -476,12 +534,19 @@ static void bind_level(LevelData& LD, const std::vector<size_t>& offs, const hs_
     D.ws = F->ws.as<double>();
     LD.dev_pat_ptr = (const int*)P(22);
     LD.dev_pat = (const int*)P(23);
+    LD.dev_f32 = (const int*)P(25);
     const int* order = (const int*)P(24);
     for (auto& CH : LD.colours) {
-        CH.dev.clist = order + CH.first;
-        CH.dev.nbr_pre = (const int*)(base + CH.off_nbr_pre);
-        CH.dev.fill_pre = (const int*)(base + CH.off_fill_pre);
-        CH.dev.tile_pre = (const int64_t*)(base + CH.off_tile_pre);
+        int first = CH.first;
+        for (int t = 0; t < 2; ++t) {
+            for (ColourDev* Cd : {&CH.fac[t], &CH.sol[t]}) {
+                Cd->clist = order + first;
+                Cd->nbr_pre = (const int*)(base + CH.off_nbr_pre[t]);
+                Cd->fill_pre = (const int*)(base + CH.off_fill_pre[t]);
+                Cd->tile_pre = (const int64_t*)(base + CH.off_tile_pre[t]);
+            }
+            first += CH.n_t[t];
+        }
     }
     SolveLevelDev& SD = LD.sdev;
     SD.ncl = LD.ncl;
@@ -495,7 +560,6 @@ static void bind_level(LevelData& LD, const std::vector<size_t>& offs, const hs_
     SD.ncap = D.ncap;
     SD.rec_off = D.rec_off;
     SD.rec = D.rec;
-    SD.f32 = LD.f32;
 }
 
 // =============================================================== flop model
@@ -526,18 +590,9 @@ static double cluster_flops(int m, int k, int nt, int wt, bool symmetric) {
 
 static int keep_level_matrix(hs_factor_s* F, LevelData& LD, hipStream_t st) {
     const LevelSymbolic& S = F->sym.levels[&LD - F->levels.data()];
-    std::vector<double> blk(LD.block_elems);
-    if (LD.block_elems) {
-        if (LD.f32) {
-            std::vector<float> bf(LD.block_elems);
-            HIP_TRY(hipMemcpyAsync(bf.data(), LD.blocks.p, LD.block_elems * sizeof(float), hipMemcpyDeviceToHost, st));
-            HIP_TRY(hipStreamSynchronize(st));
-            for (int64_t i = 0; i < LD.block_elems; ++i) blk[i] = bf[i];
-        } else {
-            HIP_TRY(hipMemcpyAsync(blk.data(), LD.blocks.p, LD.block_elems * sizeof(double), hipMemcpyDeviceToHost,
-                                   st));
-        }
-    }
+    std::vector<char> raw(LD.block_bytes);
+    if (LD.block_bytes)
+        HIP_TRY(hipMemcpyAsync(raw.data(), LD.blocks.p, LD.block_bytes, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     std::vector<int64_t> off(LD.ncl + 1, 0);
     for (int c = 0; c < LD.ncl; ++c) off[c + 1] = off[c] + LD.m[c];
@@ -546,124 +601,200 @@ static int keep_level_matrix(hs_factor_s* F, LevelData& LD, hipStream_t st) {
     for (int a = 0; a < LD.ncl; ++a)
         for (int e = S.pat_ptr[a]; e < S.pat_ptr[a + 1]; ++e) {
             const int b = S.pat[e];
+            const float* bf = reinterpret_cast<const float*>(raw.data()) + LD.blk_off[e];
+            const double* bd = reinterpret_cast<const double*>(raw.data()) + LD.blk_off[e];
             for (int j = 0; j < LD.m[b]; ++j)
-                for (int i = 0; i < LD.m[a]; ++i)
-                    LD.kept[(off[a] + i) + (off[b] + j) * dim] = blk[LD.blk_off[e] + i + (int64_t)j * LD.m[a]];
+                for (int i = 0; i < LD.m[a]; ++i) {
+                    const int64_t x = i + (int64_t)j * LD.m[a];
+                    LD.kept[(off[a] + i) + (off[b] + j) * dim] = LD.f32[a] ? (double)bf[x] : bd[x];
+                }
         }
     return HS_OK;
 }
 
-// Dense factorization of a complete level; ranks become 0 and the solve
-// metadata (packed neighbour offsets, n_tot) is written for every cluster.
-static int factor_dense_level(hs_factor_s* F, int lvl, hipStream_t st) {
+// Dense factorization of the systems that are complete on this level (one
+// cluster range each): ranks become 0 and the solve metadata (packed
+// neighbour offsets, n_tot) is written for every cluster of the ranges.  A
+// zero or non-finite pivot sets the range's entry of dflag (read back with
+// the level's ranks).  aux / dense are workspaces kept until that read-back.
+static int factor_dense_ranges(hs_factor_s* F, int lvl, const std::vector<std::array<int, 2>>& ranges, DevBuf& aux,
+                               DevBuf& dense, int*& dflag, hipStream_t st) {
     LevelData& LD = F->levels[lvl];
     const LevelSymbolic& S = F->sym.levels[lvl];
-    std::vector<int64_t> off(LD.ncl + 1, 0);
-    for (int c = 0; c < LD.ncl; ++c) off[c + 1] = off[c] + LD.m[c];
-    const int64_t N = off[LD.ncl];
+    const int nr = (int)ranges.size();
     // packed offsets: neighbours before s are eliminated (size 0)
-    std::vector<int> noff(S.adj.size()), ntot(LD.ncl), zeros(LD.ncl, 0);
-    for (int s = 0; s < LD.ncl; ++s) {
-        int acc = 0;
-        for (int e = S.adj_ptr[s]; e < S.adj_ptr[s + 1]; ++e) {
-            noff[e] = acc;
-            const int a = S.adj[e];
-            acc += a < s ? 0 : LD.m[a];
+    std::vector<int> noff(S.adj.size(), 0), ntot(LD.ncl, 0), zeros(LD.ncl, 0);
+    std::vector<std::vector<int64_t>> offs(nr);
+    int64_t maxN = 0;
+    for (int r = 0; r < nr; ++r) {
+        const int c0 = ranges[r][0], c1 = ranges[r][1];
+        for (int s = c0; s < c1; ++s) {
+            int acc = 0;
+            for (int e = S.adj_ptr[s]; e < S.adj_ptr[s + 1]; ++e) {
+                noff[e] = acc;
+                const int a = S.adj[e];
+                acc += a < s ? 0 : LD.m[a];
+            }
+            ntot[s] = acc;
         }
-        ntot[s] = acc;
+        offs[r].assign(c1 - c0 + 1, 0);
+        for (int c = c0; c < c1; ++c) offs[r][c - c0 + 1] = offs[r][c - c0] + LD.m[c];
+        maxN = std::max(maxN, offs[r].back());
     }
-    HIP_TRY(hipMemcpyAsync(LD.dev.nbr_noff, noff.data(), noff.size() * sizeof(int), hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(LD.dev.ntot, ntot.data(), ntot.size() * sizeof(int), hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(LD.dev.k, zeros.data(), zeros.size() * sizeof(int), hipMemcpyHostToDevice, st));
-    if (N == 0) return HS_OK;
     Blob b;
-    const size_t o_off = b.add(off);
-    DevBuf aux, dense;
-    if (!aux.alloc(b.data.size() + (2 * 128 * 128 + 64) * sizeof(double))) return fail(HS_ERR_NOMEM, "dense level");
-    if (!dense.alloc((size_t)N * N * sizeof(double))) return fail(HS_ERR_NOMEM, "dense level matrix");
-    HIP_TRY(hipMemcpyAsync(aux.p, b.data.data(), b.data.size(), hipMemcpyHostToDevice, st));
+    const size_t o_noff = b.add(noff), o_ntot = b.add(ntot), o_zero = b.add(zeros);
+    std::vector<size_t> o_off(nr);
+    for (int r = 0; r < nr; ++r) o_off[r] = b.add(offs[r]);
+    const size_t o_flag = b.add(std::vector<int>(nr, 0));
+    const size_t o_inv = b.reserve((2 * 128 * 128) * sizeof(double));
+    if (!aux.alloc(b.data.size())) return fail(HS_ERR_NOMEM, "dense level");
+    if (maxN > 0 && !dense.alloc((size_t)maxN * maxN * sizeof(double)))
+        return fail(HS_ERR_NOMEM, "dense level matrix");
+    // the blob stays alive in aux; copies out of it are device to device
+    HIP_TRY(hipMemcpy(aux.p, b.data.data(), b.data.size(), hipMemcpyHostToDevice));
     char* base = aux.as<char>();
-    const size_t o_inv = (b.data.size() + 255) & ~size_t(255);
+    dflag = (int*)(base + o_flag);
     double* inv = (double*)(base + o_inv);
-    int* flag = (int*)(inv + 2 * 128 * 128);
-    HIP_TRY(hipMemsetAsync(flag, 0, sizeof(int), st));
-    int rc;
-    {
+    for (int r = 0; r < nr; ++r) {
+        const int c0 = ranges[r][0], c1 = ranges[r][1];
+        const int e0 = S.adj_ptr[c0], e1 = S.adj_ptr[c1];
+        if (e1 > e0)
+            HIP_TRY(hipMemcpyAsync(LD.dev.nbr_noff + e0, base + o_noff + e0 * sizeof(int), (e1 - e0) * sizeof(int),
+                                   hipMemcpyDeviceToDevice, st));
+        HIP_TRY(hipMemcpyAsync(LD.dev.ntot + c0, base + o_ntot + c0 * sizeof(int), (c1 - c0) * sizeof(int),
+                               hipMemcpyDeviceToDevice, st));
+        HIP_TRY(hipMemcpyAsync(LD.dev.k + c0, base + o_zero, (c1 - c0) * sizeof(int), hipMemcpyDeviceToDevice, st));
+        const int64_t N = offs[r].back();
+        if (N == 0) continue;
+        std::vector<int> m_host(LD.m.begin() + c0, LD.m.begin() + c1);
         ProfScope ps(PF_DENSE, st);
-        rc = dense_level_factor(dense.as<double>(), N, LD.dev_pat_ptr, LD.dev_pat, LD.dev.m,
-                                (const int64_t*)(base + o_off), LD.dev.blk_off, LD.dev.blocks, LD.ncl, LD.nblk, inv,
-                                flag, LD.dev.ncap, LD.dev.rec_off, LD.dev.rec, LD.m, off, st);
-    }
-    if (rc) return fail(HS_ERR_HIP, "dense level launch failed");
-    int hflag = 0;
-    HIP_TRY(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    if (hflag) {
-        F->info.breakdown_level = lvl;
-        F->info.breakdown_cluster = -1;
-        return fail(HS_ERR_BREAKDOWN, "zero or non-finite pivot at level " + std::to_string(lvl) + " (dense level)");
+        const int b0 = S.pat_ptr[c0];
+        const int rc = dense_level_factor(dense.as<double>(), N, LD.dev_pat_ptr, LD.dev_pat, c0, b0, LD.dev.m + c0,
+                                          (const int64_t*)(base + o_off[r]), LD.dev.blk_off, LD.dev.blocks, c1 - c0,
+                                          S.pat_ptr[c1] - b0, inv, dflag + r, LD.dev.ncap + c0, LD.dev.rec_off + c0,
+                                          LD.dev.rec, m_host, offs[r], st);
+        if (rc) return fail(HS_ERR_HIP, "dense level launch failed");
     }
     return HS_OK;
 }
 
-static int factor_impl(hs_factor_s* F, const hs_csr* A, const hs_geometry* G, hipStream_t st) {
-    using clock = std::chrono::steady_clock;
-    const int64_t n = A->n, nnz = A->nnz;
-    // ---- host copy of the pattern (the symbolic analysis needs it), device copy of A
-    std::vector<int64_t> rp_h;
-    std::vector<int32_t> ci_h;
-    std::vector<double> v_h;
-    const int64_t* rp;
-    const int32_t* ci;
-    if (A->on_device) {
-        rp_h.resize(n + 1);
-        ci_h.resize(nnz);
-        HIP_TRY(hipMemcpyAsync(rp_h.data(), A->row_ptr, (n + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, st));
-        if (nnz) HIP_TRY(hipMemcpyAsync(ci_h.data(), A->col_idx, nnz * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipStreamSynchronize(st));
-        rp = rp_h.data();
-        ci = ci_h.data();
-    } else {
-        rp = A->row_ptr;
-        ci = A->col_idx;
+// Run fn(i) for i < count on up to `threads` host threads.
+template <class Fn>
+static void parallel_for(int count, int threads, Fn fn) {
+    threads = std::max(1, std::min(threads, count));
+    if (threads == 1) {
+        for (int i = 0; i < count; ++i) fn(i);
+        return;
     }
-    int rc = validate_csr_host(n, nnz, rp, ci);
-    if (rc) return rc;
+    std::atomic<int> next(0);
+    std::vector<std::thread> pool;
+    for (int t = 0; t < threads; ++t)
+        pool.emplace_back([&] {
+            for (int i = next++; i < count; i = next++) fn(i);
+        });
+    for (auto& th : pool) th.join();
+}
+
+// Factor nsys independent systems as one block-diagonal system (Alg. 1 on
+// the forest of their cluster trees): every kernel launch of a level and
+// colour covers the clusters of all systems.
+static int factor_impl(hs_factor_s* F, int nsys, const hs_csr* A, const hs_geometry* G, hipStream_t st) {
+    using clock = std::chrono::steady_clock;
+    int rc;
+    int64_t n = 0, nnz = 0;
+    std::vector<int64_t> nnz_off(nsys + 1, 0), row_off(nsys + 1, 0);
+    for (int i = 0; i < nsys; ++i) {
+        row_off[i + 1] = row_off[i] + A[i].n;
+        nnz_off[i + 1] = nnz_off[i] + A[i].nnz;
+    }
+    n = row_off[nsys];
+    nnz = nnz_off[nsys];
+    if (n > INT32_MAX) return fail(HS_ERR_ARG, "more than 2^31 - 1 unknowns in total");
+    F->n = n;
+    // ---- host copies of the patterns (the symbolic analysis needs them)
+    std::vector<std::vector<int64_t>> rp_h(nsys);
+    std::vector<std::vector<int32_t>> ci_h(nsys);
+    std::vector<const int64_t*> rp(nsys);
+    std::vector<const int32_t*> ci(nsys);
+    bool dev_copy = false;
+    for (int i = 0; i < nsys; ++i) {
+        if (A[i].on_device) {
+            rp_h[i].resize(A[i].n + 1);
+            ci_h[i].resize(A[i].nnz);
+            HIP_TRY(hipMemcpyAsync(rp_h[i].data(), A[i].row_ptr, (A[i].n + 1) * sizeof(int64_t),
+                                   hipMemcpyDeviceToHost, st));
+            if (A[i].nnz)
+                HIP_TRY(hipMemcpyAsync(ci_h[i].data(), A[i].col_idx, A[i].nnz * sizeof(int32_t),
+                                       hipMemcpyDeviceToHost, st));
+            rp[i] = rp_h[i].data();
+            ci[i] = ci_h[i].data();
+            dev_copy = true;
+        } else {
+            rp[i] = A[i].row_ptr;
+            ci[i] = A[i].col_idx;
+        }
+    }
+    if (dev_copy) HIP_TRY(hipStreamSynchronize(st));
+    for (int i = 0; i < nsys; ++i) {
+        rc = validate_csr_host(A[i].n, A[i].nnz, rp[i], ci[i]);
+        if (rc) return nsys > 1 ? fail(rc, "system " + std::to_string(i) + ": " + g_err) : rc;
+    }
+    // ---- device copy of A: block diagonal, systems in the caller's order
     if (!F->A_row.alloc((n + 1) * sizeof(int64_t)) || !F->A_col.alloc(nnz * sizeof(int32_t) + 4) ||
         !F->A_val.alloc(nnz * sizeof(double) + 8))
         return fail(HS_ERR_NOMEM, "device copy of A");
-    const hipMemcpyKind kind = A->on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
-    HIP_TRY(hipMemcpyAsync(F->A_row.p, A->row_ptr, (n + 1) * sizeof(int64_t), kind, st));
-    if (nnz) {
-        HIP_TRY(hipMemcpyAsync(F->A_col.p, A->col_idx, nnz * sizeof(int32_t), kind, st));
-        HIP_TRY(hipMemcpyAsync(F->A_val.p, A->val, nnz * sizeof(double), kind, st));
+    for (int i = 0; i < nsys; ++i) {
+        const hipMemcpyKind kind = A[i].on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+        HIP_TRY(hipMemcpyAsync(F->A_row.as<int64_t>() + row_off[i], A[i].row_ptr, (A[i].n + 1) * sizeof(int64_t),
+                               kind, st));
+        if (A[i].nnz) {
+            HIP_TRY(hipMemcpyAsync(F->A_col.as<int32_t>() + nnz_off[i], A[i].col_idx, A[i].nnz * sizeof(int32_t),
+                                   kind, st));
+            HIP_TRY(hipMemcpyAsync(F->A_val.as<double>() + nnz_off[i], A[i].val, A[i].nnz * sizeof(double), kind,
+                                   st));
+        }
+        launch_shift_csr(A[i].n, A[i].nnz, row_off[i], nnz_off[i], F->A_row.as<int64_t>() + row_off[i],
+                         F->A_col.as<int32_t>() + nnz_off[i], st);
     }
+    // ---- symmetry (the batch is factored in the general form unless every system is symmetric)
     if (F->opts.symmetric < 0) {
-        v_h.resize(nnz);
-        if (nnz) HIP_TRY(hipMemcpyAsync(v_h.data(), A->val, nnz * sizeof(double),
-                                        A->on_device ? hipMemcpyDeviceToHost : hipMemcpyHostToHost, st));
-        HIP_TRY(hipStreamSynchronize(st));
         int sym = 1;
-        for (int64_t i = 0; i < n && sym; ++i)
-            for (int64_t e = rp[i]; e < rp[i + 1] && sym; ++e) {
-                const int64_t j = ci[e];
-                const int32_t* lo = ci + rp[j];
-                const int32_t* hi = ci + rp[j + 1];
-                const int32_t* it = std::lower_bound(lo, hi, (int32_t)i);
-                if (it == hi || *it != i || v_h[it - ci] != v_h[e]) sym = 0;
-            }
+        for (int i = 0; i < nsys && sym; ++i) {
+            std::vector<double> v_h(A[i].nnz);
+            if (A[i].nnz)
+                HIP_TRY(hipMemcpyAsync(v_h.data(), A[i].val, A[i].nnz * sizeof(double),
+                                       A[i].on_device ? hipMemcpyDeviceToHost : hipMemcpyHostToHost, st));
+            HIP_TRY(hipStreamSynchronize(st));
+            for (int64_t r = 0; r < A[i].n && sym; ++r)
+                for (int64_t e = rp[i][r]; e < rp[i][r + 1] && sym; ++e) {
+                    const int64_t j = ci[i][e];
+                    const int32_t* lo = ci[i] + rp[i][j];
+                    const int32_t* hi = ci[i] + rp[i][j + 1];
+                    const int32_t* it = std::lower_bound(lo, hi, (int32_t)r);
+                    if (it == hi || *it != r || v_h[it - ci[i]] != v_h[e]) sym = 0;
+                }
+        }
         F->symmetric = sym;
     } else {
         F->symmetric = F->opts.symmetric ? 1 : 0;
     }
 
-    // ---- symbolic analysis (integer work only)
+    // ---- symbolic analysis (integer work only), one host thread per system
     auto t0 = clock::now();
     {
         HostScope hs_(PF_H_SYMBOLIC);
-        rc = build_symbolic(n, rp, ci, G->nx, G->ny, G->nz, F->opts.leaf_size, F->sym);
+        std::vector<Symbolic> parts(nsys);
+        std::vector<int> rcs(nsys, 0);
+        const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
+        parallel_for(nsys, std::min(hw, 16), [&](int i) {
+            rcs[i] = build_symbolic(A[i].n, rp[i], ci[i], G[i].nx, G[i].ny, G[i].nz, F->opts.leaf_size, parts[i]);
+        });
+        for (int i = 0; i < nsys; ++i)
+            if (rcs[i])
+                return fail(rcs[i], (nsys > 1 ? "system " + std::to_string(i) + ": " : std::string()) +
+                                        (rcs[i] == HS_ERR_GEOMETRY ? "n != nx*ny*nz" : "bad symbolic arguments"));
+        combine_symbolic(parts, nsys == 1, F->sym, F->forest);
     }
-    if (rc) return fail(rc, rc == HS_ERR_GEOMETRY ? "n != nx*ny*nz" : "bad symbolic arguments");
     auto t1 = clock::now();
     F->info.symbolic_seconds = std::chrono::duration<double>(t1 - t0).count();
     const int nlev = F->sym.nlevels;
@@ -674,11 +805,37 @@ static int factor_impl(hs_factor_s* F, const hs_csr* A, const hs_geometry* G, hi
         return fail(HS_ERR_NOMEM, "dof maps");
     HIP_TRY(hipMemcpyAsync(F->cluster_of.p, F->sym.cluster_of.data(), n * sizeof(int), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(F->local_of.p, F->sym.local_of.data(), n * sizeof(int), hipMemcpyHostToDevice, st));
+    // ---- per-system Krylov segments: chunks of KRY_CHUNK rows from each system's first row
+    {
+        std::vector<int> chunk_sys, sys_chunk0(nsys + 1, 0);
+        std::vector<int64_t> chunk_r0;
+        for (int i = 0; i < nsys; ++i) {
+            for (int64_t r = row_off[i]; r < row_off[i + 1]; r += KRY_CHUNK) {
+                chunk_sys.push_back(i);
+                chunk_r0.push_back(r);
+            }
+            sys_chunk0[i + 1] = (int)chunk_sys.size();
+        }
+        Blob sb;
+        const size_t o_ro = sb.add(row_off), o_cs = sb.add(chunk_sys), o_cr = sb.add(chunk_r0),
+                     o_sc = sb.add(sys_chunk0);
+        if (!F->seg_buf.alloc(sb.data.size())) return fail(HS_ERR_NOMEM, "segment tables");
+        HIP_TRY(hipMemcpy(F->seg_buf.p, sb.data.data(), sb.data.size(), hipMemcpyHostToDevice));
+        char* b = F->seg_buf.as<char>();
+        F->segs.nsys = nsys;
+        F->segs.nchunks = (int)chunk_sys.size();
+        F->segs.row_off = (const int64_t*)(b + o_ro);
+        F->segs.chunk_sys = (const int*)(b + o_cs);
+        F->segs.chunk_r0 = (const int64_t*)(b + o_cr);
+        F->segs.sys_chunk0 = (const int*)(b + o_sc);
+    }
 
     // ---- numeric factorization, level by level (Alg. 1)
     LevelData* prev = nullptr;
     std::vector<size_t> offs;
     double flops = 0.0;
+    const bool mixed = F->opts.precision == HS_MIXED;
+    const int64_t fp64_dofs = F->opts.coarse_fp64_dofs > 0 ? F->opts.coarse_fp64_dofs : MIXED_FP64_DOFS;
     for (int lvl = 0; lvl < nlev; ++lvl) {
         LevelData& LD = F->levels[lvl];
         const LevelSymbolic& S = F->sym.levels[lvl];
@@ -690,27 +847,40 @@ static int factor_impl(hs_factor_s* F, const hs_csr* A, const hs_geometry* G, hi
             for (int p = 0; p < S.ncl; ++p)
                 for (int c = 2 * p; c < std::min(2 * p + 2, prev->ncl); ++c) LD.m[p] += prev->k[c];
         }
+        // per system: a level whose clusters all neighbour each other has no
+        // fill and is factored densely (Alg. 1, conventional factorization);
+        // the mixed form stores a system's level in float32 when it is not
+        // that level and has more than fp64_dofs unknowns
+        const std::vector<int>& coff = F->forest.cl_off[lvl];
+        const int alive = (int)coff.size() - 1;
+        LD.f32.assign(S.ncl, 0);
+        LD.dense.assign(S.ncl, 0);
+        LD.any_f32 = 0;
+        std::vector<std::array<int, 2>> dense_ranges;
+        for (int j = 0; j < alive; ++j) {
+            const int c0 = coff[j], c1 = coff[j + 1];
+            int64_t dofs = 0;
+            for (int c = c0; c < c1; ++c) dofs += LD.m[c];
+            const bool dn = F->forest.dense[j] == lvl;
+            const int single = (mixed && lvl < F->forest.dense[j] && dofs > fp64_dofs) ? 1 : 0;
+            for (int c = c0; c < c1; ++c) {
+                LD.f32[c] = single;
+                LD.dense[c] = dn;
+            }
+            LD.any_f32 |= single;
+            if (dn) dense_ranges.push_back({c0, c1});
+        }
         Blob blob;
         {
             HostScope hs_(PF_H_PLAN);
             rc = plan_level(F, lvl, blob, offs);
         }
         if (rc) return rc;
-        // A level whose clusters all neighbour each other has no fill: it is
-        // factored densely (Alg. 1, conventional factorization).
-        bool complete = true;
-        for (int c = 0; c < S.ncl && complete; ++c)
-            if (S.adj_ptr[c + 1] - S.adj_ptr[c] != S.ncl - 1 || S.order[c] != c) complete = false;
-        // mixed form: float storage except on the coarse levels
-        int64_t level_dofs = 0;
-        for (int c = 0; c < S.ncl; ++c) level_dofs += LD.m[c];
-        const int64_t fp64_dofs = F->opts.coarse_fp64_dofs > 0 ? F->opts.coarse_fp64_dofs : MIXED_FP64_DOFS;
-        LD.f32 = (F->opts.precision == HS_MIXED && !complete && level_dofs > fp64_dofs) ? 1 : 0;
         {
             HostScope hs_(PF_H_ALLOC);
             if (!LD.meta.alloc(blob.data.size())) return fail(HS_ERR_NOMEM, "level metadata");
-            if (!LD.blocks.alloc(LD.block_elems * LD.esz())) return fail(HS_ERR_NOMEM, "block store");
-            if (!LD.rec.alloc(LD.rec_elems * LD.esz())) return fail(HS_ERR_NOMEM, "factor records");
+            if (!LD.blocks.alloc(LD.block_bytes)) return fail(HS_ERR_NOMEM, "block store");
+            if (!LD.rec.alloc(LD.rec_bytes)) return fail(HS_ERR_NOMEM, "factor records");
             if (!F->ws.ensure(LD.ws_elems * sizeof(double))) return fail(HS_ERR_NOMEM, "workspace");
             if (!LD.pairs.alloc((LD.npairs + 1) * sizeof(int))) return fail(HS_ERR_NOMEM, "neighbour pairs");
         }
@@ -721,11 +891,11 @@ static int factor_impl(hs_factor_s* F, const hs_csr* A, const hs_geometry* G, hi
         bind_level(LD, offs, F);
         launch_pair_blocks(S.ncl, LD.dev.nbr_ptr, LD.dev.nbr_id, LD.dev_pat_ptr, LD.dev_pat, LD.dev.pair_base,
                            LD.pairs.as<int>(), st);
-        launch_fill_zero(LD.blocks.p, LD.block_elems, LD.f32, st);
+        launch_fill_zero(LD.blocks.p, LD.block_bytes, st);
         if (lvl == 0) {
             launch_assemble0(n, F->A_row.as<int64_t>(), F->A_col.as<int32_t>(), F->A_val.as<double>(),
-                             F->cluster_of.as<int>(), F->local_of.as<int>(), LD.dev.m, (const int*)(LD.meta.as<char>() + offs[22]),
-                             (const int*)(LD.meta.as<char>() + offs[23]), LD.dev.blk_off, LD.dev.blocks, LD.f32, st);
+                             F->cluster_of.as<int>(), F->local_of.as<int>(), LD.dev.m, LD.dev_pat_ptr, LD.dev_pat,
+                             LD.dev.blk_off, LD.blocks.p, LD.dev_f32, st);
         } else {
             // parent blocks from the children's coarse blocks
             const LevelSymbolic& PS = F->sym.levels[lvl - 1];
@@ -750,8 +920,7 @@ static int factor_impl(hs_factor_s* F, const hs_csr* A, const hs_geometry* G, hi
                 ProfScope ps(PF_MERGE, st);
                 launch_merge(LD.nblk, (const int*)(mbuf.as<char>() + o_r), (const int*)(mbuf.as<char>() + o_c),
                              (const int*)(mbuf.as<char>() + o_s), prev->dev.k, prev->dev.m, prev->dev.blk_off,
-                             prev->dev.blocks, prev->f32, LD.dev.m, LD.dev.blk_off, LD.dev.blocks, LD.f32, prev->ncl,
-                             st);
+                             prev->blocks.p, prev->dev_f32, LD.dev.m, LD.dev.blk_off, LD.blocks.p, LD.dev_f32, st);
             }
             HIP_TRY(hipStreamSynchronize(st));  // merge metadata and the children's blocks are freed below
             prev->blocks.release();
@@ -761,46 +930,60 @@ static int factor_impl(hs_factor_s* F, const hs_csr* A, const hs_geometry* G, hi
             rc = keep_level_matrix(F, LD, st);
             if (rc) return rc;
         }
-        if (complete) {
-            rc = factor_dense_level(F, lvl, st);
+        DevBuf dense_aux, dense_mat;
+        int* dflag = nullptr;
+        if (!dense_ranges.empty()) {
+            rc = factor_dense_ranges(F, lvl, dense_ranges, dense_aux, dense_mat, dflag, st);
             if (rc) return rc;
         }
-        for (auto& CH : LD.colours) {
-            if (complete) break;
-            if (F->opts.eps > 0.0 && CH.dev.fill_total > 0) {
-                ProfScope ps(PF_GRAM, st);
-                launch_gram(LD.dev, CH.dev, st);
+        for (auto& CH : LD.colours)
+            for (int t = 0; t < 2; ++t) {
+                const ColourDev& C = CH.fac[t];
+                if (C.n == 0) continue;
+                if (F->opts.eps > 0.0 && C.fill_total > 0) {
+                    ProfScope ps(PF_GRAM, st);
+                    launch_gram(LD.dev, C, st);
+                }
+                {
+                    ProfScope ps(PF_PIVOT, st);
+                    launch_pivot(LD.dev, C, st);
+                }
+                if (C.fill_total > 0) {
+                    ProfScope ps(PF_FILL, st);
+                    launch_fill_update(LD.dev, C, st);
+                }
+                if (C.nbr_total > 0) {
+                    ProfScope ps(PF_NBR, st);
+                    launch_nbr_update(LD.dev, C, st);
+                }
+                if (C.tile_total > 0) {
+                    ProfScope ps(t == 0 ? PF_SCHUR_F32 : PF_SCHUR, st);
+                    launch_schur(LD.dev, C, st);
+                }
             }
-            {
-                ProfScope ps(PF_PIVOT, st);
-                launch_pivot(LD.dev, CH.dev, st);
-            }
-            if (CH.dev.fill_total > 0) {
-                ProfScope ps(PF_FILL, st);
-                launch_fill_update(LD.dev, CH.dev, st);
-            }
-            if (CH.dev.nbr_total > 0) {
-                ProfScope ps(PF_NBR, st);
-                launch_nbr_update(LD.dev, CH.dev, st);
-            }
-            if (CH.dev.tile_total > 0) {
-                ProfScope ps(PF_SCHUR, st);
-                launch_schur(LD.dev, CH.dev, st);
-            }
-        }
         HIP_TRY(hipGetLastError());
         // ranks decide the next level's sizes: one synchronisation per level
         LD.k.resize(LD.ncl);
-        std::vector<int> flag(LD.ncl), ntot(LD.ncl);
+        std::vector<int> flag(LD.ncl), ntot(LD.ncl), hdflag(dense_ranges.size(), 0);
         {
             HostScope hs_(PF_H_SYNC);
             HIP_TRY(hipMemcpyAsync(LD.k.data(), LD.dev.k, LD.ncl * sizeof(int), hipMemcpyDeviceToHost, st));
             HIP_TRY(hipMemcpyAsync(flag.data(), LD.dev.flag, LD.ncl * sizeof(int), hipMemcpyDeviceToHost, st));
             HIP_TRY(hipMemcpyAsync(ntot.data(), LD.dev.ntot, LD.ncl * sizeof(int), hipMemcpyDeviceToHost, st));
+            if (dflag)
+                HIP_TRY(hipMemcpyAsync(hdflag.data(), dflag, hdflag.size() * sizeof(int), hipMemcpyDeviceToHost, st));
             HIP_TRY(hipStreamSynchronize(st));
         }
         LD.pairs.release();  // used by this level's Schur updates only
         LD.dev.pair_blk = nullptr;
+        for (size_t r = 0; r < dense_ranges.size(); ++r)
+            if (hdflag[r]) {
+                F->info.breakdown_level = lvl;
+                F->info.breakdown_cluster = -1;
+                return fail(HS_ERR_BREAKDOWN, "zero or non-finite pivot at level " + std::to_string(lvl) +
+                                                  " (dense level, clusters " + std::to_string(dense_ranges[r][0]) +
+                                                  ".." + std::to_string(dense_ranges[r][1] - 1) + ")");
+            }
         for (int c = 0; c < LD.ncl; ++c)
             if (flag[c]) {
                 F->info.breakdown_level = lvl;
@@ -813,9 +996,10 @@ static int factor_impl(hs_factor_s* F, const hs_csr* A, const hs_geometry* G, hi
             prof_flush();
             for (int c = 0; c < LD.ncl; ++c) {
                 const double f = LD.m[c] - LD.k[c], nt = ntot[c];
-                if (LD.m[c] == 0 || f == 0 || nt == 0) continue;
-                g_prof[PF_SCHUR].flops += 2.0 * f * nt * nt;
-                g_prof[PF_SCHUR].bytes += (double)LD.esz() * (2.0 * f * nt + 2.0 * nt * nt);
+                if (LD.m[c] == 0 || f == 0 || nt == 0 || LD.dense[c]) continue;
+                ProfFamily& fam = g_prof[LD.f32[c] ? PF_SCHUR_F32 : PF_SCHUR];
+                fam.flops += 2.0 * f * nt * nt;
+                fam.bytes += (double)LD.esz(c) * (2.0 * f * nt + 2.0 * nt * nt);
             }
         }
         for (int c = 0; c < LD.ncl; ++c) {
@@ -831,12 +1015,17 @@ static int factor_impl(hs_factor_s* F, const hs_csr* A, const hs_geometry* G, hi
         for (int c = 0; c < LD.ncl; ++c) LD.seg[c + 1] = LD.seg[c] + LD.m[c];
         LD.nseg = LD.seg[LD.ncl];
         int64_t coarse = 0;
-        for (int c = 0; c < LD.ncl; ++c) coarse += LD.k[c];
+        int max_all = 0;
+        for (int c = 0; c < LD.ncl; ++c) {
+            coarse += LD.k[c];
+            max_all = std::max(max_all, LD.m[c]);
+        }
         F->info.coarse_dofs[lvl] = coarse;
         F->info.level_clusters[lvl] = LD.ncl;
         F->info.level_colors[lvl] = S.ncolors;
         F->info.ncolors_total += S.ncolors;
-        F->info.max_cluster = std::max(F->info.max_cluster, LD.max_m);
+        F->info.max_cluster = std::max(F->info.max_cluster, max_all);
+        LD.max_m = max_all;  // from here on: the solve's largest cluster
         prev = &LD;
     }
     // the last level's blocks are no longer needed
@@ -846,31 +1035,33 @@ static int factor_impl(hs_factor_s* F, const hs_csr* A, const hs_geometry* G, hi
     }
     F->ws.release();
 
-    // ---- solve plan (needs every rank): segments, part offsets per colour
+    // ---- solve plan (needs every rank): segments, part offsets per colour and type
     double rec_bytes = 0.0, apply_flops = 0.0;
     for (int lvl = 0; lvl < nlev; ++lvl) {
         LevelData& LD = F->levels[lvl];
         const LevelSymbolic& S = F->sym.levels[lvl];
         Blob sb;
         size_t o_seg = sb.add(LD.seg);
-        std::vector<size_t> o_part(LD.colours.size());
+        std::vector<std::array<size_t, 2>> o_part(LD.colours.size());
         LD.part_max = 0;
         for (size_t c = 0; c < LD.colours.size(); ++c) {
             ColourHost& CH = LD.colours[c];
-            std::vector<int64_t> po;
-            int64_t acc = 0;
-            for (int i = 0; i < CH.n; ++i) {
-                const int s = S.order[CH.first + i];
-                const int f = LD.m[s] - LD.k[s];
-                for (int e = S.adj_ptr[s]; e < S.adj_ptr[s + 1]; ++e) {
-                    po.push_back(acc);
-                    acc += f;
+            for (int t = 0; t < 2; ++t) {
+                std::vector<int64_t> po;
+                int64_t acc = 0;
+                for (int i = 0; i < CH.n_t[t]; ++i) {
+                    const int s = LD.order_host[CH.first + (t ? CH.n_t[0] : 0) + i];
+                    const int f = LD.m[s] - LD.k[s];
+                    for (int e = S.adj_ptr[s]; e < S.adj_ptr[s + 1]; ++e) {
+                        po.push_back(acc);
+                        acc += f;
+                    }
                 }
+                po.push_back(acc);
+                CH.part_total[t] = acc;
+                LD.part_max = std::max(LD.part_max, acc);
+                o_part[c][t] = sb.add(po);
             }
-            po.push_back(acc);
-            CH.part_total = acc;
-            LD.part_max = std::max(LD.part_max, acc);
-            o_part[c] = sb.add(po);
         }
         // keep the solve metadata next to the level metadata
         DevBuf buf;
@@ -878,7 +1069,7 @@ static int factor_impl(hs_factor_s* F, const hs_csr* A, const hs_geometry* G, hi
         HIP_TRY(hipMemcpyAsync(buf.p, sb.data.data(), sb.data.size(), hipMemcpyHostToDevice, st));
         LD.sdev.seg = (const int64_t*)(buf.as<char>() + o_seg);
         for (size_t c = 0; c < LD.colours.size(); ++c)
-            LD.colours[c].part_off = (const int64_t*)(buf.as<char>() + o_part[c]);
+            for (int t = 0; t < 2; ++t) LD.colours[c].part_off[t] = (const int64_t*)(buf.as<char>() + o_part[c][t]);
         LD.blocks = std::move(buf);  // the block store slot now owns the solve metadata
         for (int c = 0; c < LD.ncl; ++c) {
             const double m = LD.m[c], k = LD.k[c], f = m - k;
@@ -888,7 +1079,7 @@ static int factor_impl(hs_factor_s* F, const hs_csr* A, const hs_geometry* G, hi
                 const int a = S.adj[e];
                 nt += S.pos[a] < S.pos[c] ? LD.k[a] : LD.m[a];
             }
-            rec_bytes += (double)LD.esz() * (2.0 * m * m + 2.0 * f * nt);
+            rec_bytes += (double)LD.esz(c) * (2.0 * m * m + 2.0 * f * nt);
             apply_flops += 4.0 * m * m + 4.0 * f * nt;
         }
     }
@@ -935,6 +1126,8 @@ static int solve_impl(hs_factor_s* F, int nrhs, const double* B, int64_t ldb, do
     return HS_OK;
 }
 
+// Alg. 2: forward sweep colour by colour up the levels, backward sweep down.
+// A colour's float32 and float64 lists are independent launches.
 static int solve_chunk(hs_factor_s* F, int nrhs, const double* B, int64_t ldb, double* X, int64_t ldx, hipStream_t st) {
     int rc = ensure_solve_buffers(F, nrhs);
     if (rc) return rc;
@@ -949,11 +1142,14 @@ static int solve_chunk(hs_factor_s* F, int nrhs, const double* B, int64_t ldb, d
                        st);
     for (int l = 0; l < nlev; ++l) {
         LevelData& LD = F->levels[l];
-        for (auto& CH : LD.colours) {
-            ProfScope ps(PF_APPLY, st);
-            launch_apply_fwd_t(LD.sdev, CH.dev, Y(l), Z(l), nrhs, st);
-            launch_apply_fwd_u(LD.sdev, CH.dev, Y(l), Z(l), nrhs, CH.dev.max_nbr_m, st);
-        }
+        for (auto& CH : LD.colours)
+            for (int t = 0; t < 2; ++t) {
+                const ColourDev& C = CH.sol[t];
+                if (C.n == 0) continue;
+                ProfScope ps(PF_APPLY, st);
+                launch_apply_fwd_t(LD.sdev, C, Y(l), Z(l), nrhs, st);
+                launch_apply_fwd_u(LD.sdev, C, Y(l), Z(l), nrhs, C.max_nbr_m, st);
+            }
         if (l + 1 < nlev)
             launch_to_coarse(LD.sdev, F->levels[l + 1].sdev.seg, F->levels[l + 1].ncl, Z(l), Y(l + 1), nrhs, st);
     }
@@ -963,9 +1159,13 @@ static int solve_chunk(hs_factor_s* F, int nrhs, const double* B, int64_t ldb, d
             launch_from_coarse(LD.sdev, F->levels[l + 1].sdev.seg, F->levels[l + 1].ncl, O(l + 1), Z(l), nrhs, st);
         for (int c = (int)LD.colours.size() - 1; c >= 0; --c) {
             auto& CH = LD.colours[c];
-            ProfScope ps(PF_APPLY, st);
-            launch_apply_bwd_acc(LD.sdev, CH.dev, Z(l), O(l), part, CH.part_off, nrhs, st);
-            launch_apply_bwd_t(LD.sdev, CH.dev, Z(l), O(l), part, CH.part_off, nrhs, st);
+            for (int t = 0; t < 2; ++t) {
+                const ColourDev& C = CH.sol[t];
+                if (C.n == 0) continue;
+                ProfScope ps(PF_APPLY, st);
+                launch_apply_bwd_acc(LD.sdev, C, Z(l), O(l), part, CH.part_off[t], nrhs, st);
+                launch_apply_bwd_t(LD.sdev, C, Z(l), O(l), part, CH.part_off[t], nrhs, st);
+            }
         }
     }
     launch_gather_sol(F->n, F->cluster_of.as<int>(), F->local_of.as<int>(), L0.sdev.seg, L0.dev.m, O(0), X, ldx, nrhs,
@@ -975,24 +1175,41 @@ static int solve_chunk(hs_factor_s* F, int nrhs, const double* B, int64_t ldb, d
 }
 
 // ================================================================ Krylov
+//
+// CG and GMRES(restart) of Sec. 5 in float64 with the factorization as the
+// preconditioner.  Every system of the factor and every right-hand side is
+// its own lane l = s + nsys * c with its own scalars and stopping test
+// (||b - A x||_2 <= tol ||b||_2); lanes advance together, a finished lane is
+// frozen (its coefficients are zero), so its numbers are those of a solve of
+// that system alone.
 
-// Work vectors: R, Zv, P, Q (n x nrhs each), scalars.
+// Work vectors (n x nrhs each): 4 for CG, 3 + restart + 1 for GMRES; lane
+// scalars and chunk partials behind them.
 static int ensure_krylov(hs_factor_s* F, int nrhs, int restart) {
     const int64_t n = F->n;
-    const int64_t vecs = 4 + (restart > 0 ? restart + 1 : 0);
-    const size_t bytes = (size_t)(vecs * n * nrhs + 8 * nrhs + nrhs * KRYLOV_BLOCKS + 64 * (restart + 2)) * sizeof(double);
+    const int64_t L = (int64_t)F->forest.nsys * nrhs;
+    const int64_t r1 = restart > 0 ? restart + 1 : 1;
+    const int64_t vecs = restart > 0 ? 3 + r1 : 4;
+    const size_t bytes =
+        (size_t)(vecs * n * nrhs + (2 * r1 + 8) * L + r1 * (int64_t)nrhs * F->segs.nchunks + 64) * sizeof(double);
     if (F->kry.bytes >= bytes) return HS_OK;
     if (!F->kry.alloc(bytes)) return fail(HS_ERR_NOMEM, "Krylov workspace");
     return HS_OK;
 }
 
-static int dots_host(hs_factor_s* F, int64_t n, const double* a, int64_t lda, const double* b, int64_t ldb, int nrhs,
-                     double* part, double* dout, double* hout, hipStream_t st) {
-    launch_dots(n, a, lda, b, ldb, nrhs, part, dout, st);
-    HIP_TRY(hipMemcpyAsync(hout, dout, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
+// hout[v * L + l] = per-lane dot products of a_v and b (one synchronisation).
+static int sdots_host(hs_factor_s* F, int nvec, const double* a, int64_t vstride, int64_t lda, const double* b,
+                      int64_t ldb, int nrhs, double* part, double* dout, double* hout, hipStream_t st) {
+    launch_sdots(F->segs, nvec, a, vstride, lda, b, ldb, nrhs, part, dout, st);
+    const int64_t L = (int64_t)F->forest.nsys * nrhs;
+    HIP_TRY(hipMemcpyAsync(hout, dout, nvec * L * sizeof(double), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     if (g_prof_on) prof_flush();
-    (void)F;
+    return HS_OK;
+}
+
+static int upload(double* d, const std::vector<double>& h, hipStream_t st) {
+    HIP_TRY(hipMemcpyAsync(d, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, st));
     return HS_OK;
 }
 
@@ -1001,203 +1218,234 @@ static int pcg_impl(hs_factor_s* F, int nrhs, const double* B, int64_t ldb, doub
     int rc = ensure_krylov(F, nrhs, 0);
     if (rc) return rc;
     const int64_t n = F->n;
+    const int L = F->forest.nsys * nrhs;
+    const SegDev& G = F->segs;
     double* w = F->kry.as<double>();
     double* R = w;
     double* Zv = R + n * nrhs;
     double* P = Zv + n * nrhs;
     double* Q = P + n * nrhs;
-    double* sc = Q + n * nrhs;             // 8 * nrhs scalars
-    double* part = sc + 8 * nrhs;
-    double* d_alpha = sc;
-    double* d_beta = sc + nrhs;
-    double* d_one = sc + 2 * nrhs;
-    double* d_mone = sc + 3 * nrhs;
-    double* d_zero = sc + 4 * nrhs;
-    double* d_dot = sc + 5 * nrhs;
-    std::vector<double> one(nrhs, 1.0), mone(nrhs, -1.0), zero(nrhs, 0.0);
-    HIP_TRY(hipMemcpyAsync(d_one, one.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(d_mone, mone.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(d_zero, zero.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st));
-    std::vector<double> bn(nrhs), rz(nrhs), rzn(nrhs), rzo(nrhs, 0.0), pq(nrhs), rr(nrhs), alpha(nrhs), beta(nrhs);
+    double* d_alpha = Q + n * nrhs;  // lane scalars
+    double* d_beta = d_alpha + L;
+    double* d_one = d_beta + L;
+    double* d_zero = d_one + L;
+    double* d_dot = d_zero + L;
+    double* part = d_dot + 2 * L;
+    std::vector<double> one(L, 1.0), zero(L, 0.0);
+    if ((rc = upload(d_one, one, st)) || (rc = upload(d_zero, zero, st))) return rc;
+    std::vector<double> bn(L), rz(L), rzn(L), rzo(L, 0.0), pq(L), rr(L), alpha(L), beta(L);
     // A float32 factor is a slightly nonlinear preconditioner: the flexible
     // (Polak-Ribiere) beta = r_new^T (z_new - z_old) / r_old^T z_old keeps CG
     // converging; with a float64 factor the classical beta is used.
     const bool flexible = F->opts.precision == HS_MIXED;
-    rc = dots_host(F, n, B, ldb, B, ldb, nrhs, part, d_dot, bn.data(), st);
-    if (rc) return rc;
+    auto dots = [&](const double* a, int64_t lda, const double* b, int64_t ldb_, double* out) {
+        return sdots_host(F, 1, a, 0, lda, b, ldb_, nrhs, part, d_dot, out, st);
+    };
+    if ((rc = dots(B, ldb, B, ldb, bn.data()))) return rc;
     for (auto& v : bn) v = v > 0 ? std::sqrt(v) : 1.0;
     // x0 = 0, r0 = b
-    launch_axpby(n, d_zero, B, ldb, d_zero, X, ldx, nrhs, st);
+    launch_saxpby(G, d_zero, B, ldb, d_zero, X, ldx, nrhs, st);
     launch_copy(n, B, ldb, R, n, nrhs, st);
-    std::vector<char> active(nrhs, 1);
-    int nact = nrhs;
-    rc = solve_impl(F, nrhs, R, n, Zv, n, st);
-    if (rc) return rc;
+    std::vector<char> active(L, 1);
+    int nact = L;
+    if ((rc = solve_impl(F, nrhs, R, n, Zv, n, st))) return rc;
     launch_copy(n, Zv, n, P, n, nrhs, st);
-    rc = dots_host(F, n, R, n, Zv, n, nrhs, part, d_dot, rz.data(), st);
-    if (rc) return rc;
+    if ((rc = dots(R, n, Zv, n, rz.data()))) return rc;
     int it = 0;
     while (nact > 0 && it < maxit) {
         ++it;
         launch_spmv(n, F->A_row.as<int64_t>(), F->A_col.as<int32_t>(), F->A_val.as<double>(), P, n, Q, n, nrhs, st);
-        rc = dots_host(F, n, P, n, Q, n, nrhs, part, d_dot, pq.data(), st);
-        if (rc) return rc;
-        for (int j = 0; j < nrhs; ++j) alpha[j] = (active[j] && pq[j] != 0.0) ? rz[j] / pq[j] : 0.0;
-        HIP_TRY(hipMemcpyAsync(d_alpha, alpha.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st));
-        launch_axpby(n, d_alpha, P, n, d_one, X, ldx, nrhs, st);      // x += alpha p
-        for (int j = 0; j < nrhs; ++j) alpha[j] = -alpha[j];
-        HIP_TRY(hipMemcpyAsync(d_beta, alpha.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st));
-        launch_axpby(n, d_beta, Q, n, d_one, R, n, nrhs, st);          // r -= alpha q
-        rc = dots_host(F, n, R, n, R, n, nrhs, part, d_dot, rr.data(), st);
-        if (rc) return rc;
+        if ((rc = dots(P, n, Q, n, pq.data()))) return rc;
+        for (int l = 0; l < L; ++l) alpha[l] = (active[l] && pq[l] != 0.0) ? rz[l] / pq[l] : 0.0;
+        if ((rc = upload(d_alpha, alpha, st))) return rc;
+        launch_saxpby(G, d_alpha, P, n, d_one, X, ldx, nrhs, st);  // x += alpha p
+        for (int l = 0; l < L; ++l) alpha[l] = -alpha[l];
+        if ((rc = upload(d_beta, alpha, st))) return rc;
+        launch_saxpby(G, d_beta, Q, n, d_one, R, n, nrhs, st);  // r -= alpha q
+        if ((rc = dots(R, n, R, n, rr.data()))) return rc;
         nact = 0;
-        for (int j = 0; j < nrhs; ++j) {
-            if (active[j] && std::sqrt(std::max(rr[j], 0.0)) <= tol * bn[j]) active[j] = 0;
-            nact += active[j];
+        for (int l = 0; l < L; ++l) {
+            if (active[l] && std::sqrt(std::max(rr[l], 0.0)) <= tol * bn[l]) active[l] = 0;
+            nact += active[l];
         }
         if (nact == 0) break;
-        if (flexible) {
-            rc = dots_host(F, n, R, n, Zv, n, nrhs, part, d_dot, rzo.data(), st);
-            if (rc) return rc;
+        if (flexible && (rc = dots(R, n, Zv, n, rzo.data()))) return rc;
+        if ((rc = solve_impl(F, nrhs, R, n, Zv, n, st))) return rc;
+        if ((rc = dots(R, n, Zv, n, rzn.data()))) return rc;
+        for (int l = 0; l < L; ++l) {
+            beta[l] = (active[l] && rz[l] != 0.0) ? (rzn[l] - rzo[l]) / rz[l] : 0.0;
+            rz[l] = rzn[l];
         }
-        rc = solve_impl(F, nrhs, R, n, Zv, n, st);
-        if (rc) return rc;
-        rc = dots_host(F, n, R, n, Zv, n, nrhs, part, d_dot, rzn.data(), st);
-        if (rc) return rc;
-        for (int j = 0; j < nrhs; ++j) {
-            beta[j] = (active[j] && rz[j] != 0.0) ? (rzn[j] - rzo[j]) / rz[j] : 0.0;
-            rz[j] = rzn[j];
-        }
-        HIP_TRY(hipMemcpyAsync(d_beta, beta.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st));
-        launch_axpby(n, d_one, Zv, n, d_beta, P, n, nrhs, st);         // p = z + beta p
+        if ((rc = upload(d_beta, beta, st))) return rc;
+        launch_saxpby(G, d_one, Zv, n, d_beta, P, n, nrhs, st);  // p = z + beta p
     }
     // true residual
     launch_spmv(n, F->A_row.as<int64_t>(), F->A_col.as<int32_t>(), F->A_val.as<double>(), X, ldx, Q, n, nrhs, st);
     launch_xmy(n, B, ldb, Q, n, nrhs, st);
-    rc = dots_host(F, n, Q, n, Q, n, nrhs, part, d_dot, rr.data(), st);
-    if (rc) return rc;
+    if ((rc = dots(Q, n, Q, n, rr.data()))) return rc;
     bool ok = true;
-    for (int j = 0; j < nrhs; ++j) {
-        const double r = std::sqrt(std::max(rr[j], 0.0)) / bn[j];
-        if (relres) relres[j] = r;
+    for (int l = 0; l < L; ++l) {
+        const double r = std::sqrt(std::max(rr[l], 0.0)) / bn[l];
+        if (relres) relres[l] = r;
         if (!(r <= tol)) ok = false;
     }
     if (iters) *iters = it;
     return ok ? HS_OK : HS_WARN_NOT_CONVERGED;
 }
 
+// Right-preconditioned GMRES(restart): x = M^{-1} V y, the basis V
+// orthonormalised by classical Gram-Schmidt applied twice (each pass one
+// batched product V^T w), Givens rotations on the host per lane.
 static int gmres_impl(hs_factor_s* F, int nrhs, const double* B, int64_t ldb, double* X, int64_t ldx, double tol,
                       int maxit, int restart, int* iters, double* relres, hipStream_t st) {
     if (restart < 1) restart = 30;
-    int rc = ensure_krylov(F, 1, restart);
+    int rc = ensure_krylov(F, nrhs, restart);
     if (rc) return rc;
     const int64_t n = F->n;
+    const int L = F->forest.nsys * nrhs;
+    const int R1 = restart + 1;
+    const SegDev& G = F->segs;
+    const int64_t vs = n * nrhs;  // stride between basis vectors
     double* w = F->kry.as<double>();
-    double* R = w;
-    double* T = R + n;      // preconditioned vector
-    double* Wv = T + n;
-    double* Q = Wv + n;
-    double* V = Q + n;      // restart + 1 basis vectors
-    double* sc = V + (int64_t)(restart + 1) * n;
-    double* part = sc + 8;
-    double* d_a = sc;
-    double* d_b = sc + 1;
-    double* d_dot = sc + 2;
-    int total_it = 0;
-    bool ok = true;
-    for (int col = 0; col < nrhs; ++col) {
-        const double* b = B + col * ldb;
-        double* x = X + col * ldx;
-        auto setc = [&](double* d, double v) { return hipMemcpyAsync(d, &v, sizeof(double), hipMemcpyHostToDevice, st); };
-        double bn2;
-        rc = dots_host(F, n, b, n, b, n, 1, part, d_dot, &bn2, st);
-        if (rc) return rc;
-        const double bn = bn2 > 0 ? std::sqrt(bn2) : 1.0;
-        HIP_TRY(setc(d_a, 0.0));
-        launch_axpby(n, d_a, b, n, d_a, x, n, 1, st);  // x = 0
-        int it = 0;
-        double rnorm = bn;
-        launch_copy(n, b, n, R, n, 1, st);
-        while (it < maxit && rnorm > tol * bn) {
-            std::vector<double> H((size_t)(restart + 1) * restart, 0.0), g(restart + 1, 0.0), cs(restart), sn(restart);
-            HIP_TRY(setc(d_a, 1.0 / rnorm));
-            HIP_TRY(setc(d_b, 0.0));
-            launch_axpby(n, d_a, R, n, d_b, V, n, 1, st);
-            g[0] = rnorm;
-            int j_used = 0;
-            for (int j = 0; j < restart && it < maxit; ++j) {
-                ++it;
-                rc = solve_impl(F, 1, V + j * n, n, T, n, st);
-                if (rc) return rc;
-                launch_spmv(n, F->A_row.as<int64_t>(), F->A_col.as<int32_t>(), F->A_val.as<double>(), T, n, Wv, n, 1, st);
-                for (int i = 0; i <= j; ++i) {
-                    double h;
-                    rc = dots_host(F, n, Wv, n, V + i * n, n, 1, part, d_dot, &h, st);
-                    if (rc) return rc;
-                    H[i + j * (restart + 1)] = h;
-                    HIP_TRY(setc(d_a, -h));
-                    HIP_TRY(setc(d_b, 1.0));
-                    launch_axpby(n, d_a, V + i * n, n, d_b, Wv, n, 1, st);
-                }
-                double hn2;
-                rc = dots_host(F, n, Wv, n, Wv, n, 1, part, d_dot, &hn2, st);
-                if (rc) return rc;
-                const double hn = std::sqrt(std::max(hn2, 0.0));
-                H[(j + 1) + j * (restart + 1)] = hn;
-                if (hn > 0) {
-                    HIP_TRY(setc(d_a, 1.0 / hn));
-                    HIP_TRY(setc(d_b, 0.0));
-                    launch_axpby(n, d_a, Wv, n, d_b, V + (j + 1) * n, n, 1, st);
-                }
-                for (int i = 0; i < j; ++i) {
-                    const double a0 = H[i + j * (restart + 1)], a1 = H[(i + 1) + j * (restart + 1)];
-                    H[i + j * (restart + 1)] = cs[i] * a0 + sn[i] * a1;
-                    H[(i + 1) + j * (restart + 1)] = -sn[i] * a0 + cs[i] * a1;
-                }
-                const double a0 = H[j + j * (restart + 1)], a1 = H[(j + 1) + j * (restart + 1)];
-                const double den = std::hypot(a0, a1);
-                cs[j] = den > 0 ? a0 / den : 1.0;
-                sn[j] = den > 0 ? a1 / den : 0.0;
-                H[j + j * (restart + 1)] = cs[j] * a0 + sn[j] * a1;
-                H[(j + 1) + j * (restart + 1)] = 0.0;
-                g[j + 1] = -sn[j] * g[j];
-                g[j] = cs[j] * g[j];
-                j_used = j + 1;
-                if (std::fabs(g[j + 1]) <= tol * bn) break;
-            }
-            // y = H^{-1} g, x += M^{-1} V y
-            std::vector<double> y(j_used);
-            for (int i = j_used - 1; i >= 0; --i) {
-                double s = g[i];
-                for (int c = i + 1; c < j_used; ++c) s -= H[i + c * (restart + 1)] * y[c];
-                y[i] = s / H[i + i * (restart + 1)];
-            }
-            HIP_TRY(setc(d_b, 0.0));
-            HIP_TRY(setc(d_a, 0.0));
-            launch_axpby(n, d_a, Wv, n, d_b, Wv, n, 1, st);  // Wv = 0
-            for (int i = 0; i < j_used; ++i) {
-                HIP_TRY(setc(d_a, y[i]));
-                HIP_TRY(setc(d_b, 1.0));
-                launch_axpby(n, d_a, V + i * n, n, d_b, Wv, n, 1, st);
-            }
-            rc = solve_impl(F, 1, Wv, n, T, n, st);
-            if (rc) return rc;
-            HIP_TRY(setc(d_a, 1.0));
-            HIP_TRY(setc(d_b, 1.0));
-            launch_axpby(n, d_a, T, n, d_b, x, ldx, 1, st);
-            // true residual
-            launch_spmv(n, F->A_row.as<int64_t>(), F->A_col.as<int32_t>(), F->A_val.as<double>(), x, ldx, R, n, 1, st);
-            launch_xmy(n, b, n, R, n, 1, st);
-            double rn2;
-            rc = dots_host(F, n, R, n, R, n, 1, part, d_dot, &rn2, st);
-            if (rc) return rc;
-            rnorm = std::sqrt(std::max(rn2, 0.0));
-        }
-        if (relres) relres[col] = rnorm / bn;
-        if (!(rnorm <= tol * bn)) ok = false;
-        total_it = std::max(total_it, it);
+    double* Rv = w;
+    double* T = Rv + vs;
+    double* Wv = T + vs;
+    double* V = Wv + vs;
+    double* d_coef = V + (int64_t)R1 * vs;  // R1 x L
+    double* d_a = d_coef + (int64_t)R1 * L;
+    double* d_b = d_a + L;
+    double* d_one = d_b + L;
+    double* d_zero = d_one + L;
+    double* d_dot = d_zero + L;  // R1 x L
+    double* part = d_dot + (int64_t)R1 * L;
+    std::vector<double> one(L, 1.0), zero(L, 0.0);
+    if ((rc = upload(d_one, one, st)) || (rc = upload(d_zero, zero, st))) return rc;
+    auto hidx = [&](int i, int j) { return (size_t)i + (size_t)j * R1; };
+    std::vector<double> bn(L), rnorm(L), h1((size_t)R1 * L), h2((size_t)R1 * L), hn2(L), a(L), coef((size_t)R1 * L);
+    std::vector<std::vector<double>> H(L), g(L), cs(L), sn(L);
+    std::vector<int> it_l(L, 0), jused(L, 0);
+    std::vector<char> active(L, 0), inc(L, 0), live(L, 0);
+    if ((rc = sdots_host(F, 1, B, 0, ldb, B, ldb, nrhs, part, d_dot, bn.data(), st))) return rc;
+    for (int l = 0; l < L; ++l) {
+        bn[l] = std::sqrt(std::max(bn[l], 0.0));
+        rnorm[l] = bn[l];
+        active[l] = bn[l] > 0.0;  // b = 0: x = 0 is exact
+        if (bn[l] == 0.0) bn[l] = 1.0;
     }
-    if (iters) *iters = total_it;
+    launch_saxpby(G, d_zero, B, ldb, d_zero, X, ldx, nrhs, st);  // x = 0
+    launch_copy(n, B, ldb, Rv, n, nrhs, st);
+    for (;;) {
+        int ninc = 0;
+        for (int l = 0; l < L; ++l) {
+            inc[l] = active[l] && it_l[l] < maxit;
+            live[l] = inc[l];
+            ninc += inc[l];
+            jused[l] = 0;
+        }
+        if (ninc == 0) break;
+        // V_0 = r / ||r||
+        for (int l = 0; l < L; ++l) {
+            a[l] = inc[l] ? 1.0 / rnorm[l] : 0.0;
+            if (inc[l]) {
+                H[l].assign((size_t)R1 * restart, 0.0);
+                g[l].assign(R1, 0.0);
+                cs[l].assign(restart, 0.0);
+                sn[l].assign(restart, 0.0);
+                g[l][0] = rnorm[l];
+            }
+        }
+        if ((rc = upload(d_a, a, st))) return rc;
+        launch_saxpby(G, d_a, Rv, n, d_zero, V, n, nrhs, st);
+        int jmax = 0;
+        for (int j = 0; j < restart; ++j) {
+            int nlive = 0;
+            for (int l = 0; l < L; ++l) nlive += live[l];
+            if (nlive == 0) break;
+            double* Vj = V + (int64_t)j * vs;
+            if ((rc = solve_impl(F, nrhs, Vj, n, T, n, st))) return rc;
+            launch_spmv(n, F->A_row.as<int64_t>(), F->A_col.as<int32_t>(), F->A_val.as<double>(), T, n, Wv, n, nrhs,
+                        st);
+            // two passes of classical Gram-Schmidt against V_0 .. V_j
+            for (int pass = 0; pass < 2; ++pass) {
+                std::vector<double>& h = pass ? h2 : h1;
+                if ((rc = sdots_host(F, j + 1, V, vs, n, Wv, n, nrhs, part, d_dot, h.data(), st))) return rc;
+                for (int v = 0; v <= j; ++v)
+                    for (int l = 0; l < L; ++l) coef[(size_t)v * L + l] = live[l] ? -h[(size_t)v * L + l] : 0.0;
+                HIP_TRY(hipMemcpyAsync(d_coef, coef.data(), (size_t)(j + 1) * L * sizeof(double),
+                                       hipMemcpyHostToDevice, st));
+                launch_scomb(G, j + 1, d_coef, V, vs, n, d_one, Wv, n, nrhs, st);
+            }
+            if ((rc = sdots_host(F, 1, Wv, 0, n, Wv, n, nrhs, part, d_dot, hn2.data(), st))) return rc;
+            for (int l = 0; l < L; ++l) {
+                a[l] = 0.0;
+                if (!live[l]) continue;
+                std::vector<double>& Hl = H[l];
+                for (int v = 0; v <= j; ++v) Hl[hidx(v, j)] = h1[(size_t)v * L + l] + h2[(size_t)v * L + l];
+                const double hn = std::sqrt(std::max(hn2[l], 0.0));
+                Hl[hidx(j + 1, j)] = hn;
+                for (int i = 0; i < j; ++i) {
+                    const double a0 = Hl[hidx(i, j)], a1 = Hl[hidx(i + 1, j)];
+                    Hl[hidx(i, j)] = cs[l][i] * a0 + sn[l][i] * a1;
+                    Hl[hidx(i + 1, j)] = -sn[l][i] * a0 + cs[l][i] * a1;
+                }
+                const double a0 = Hl[hidx(j, j)], a1 = Hl[hidx(j + 1, j)];
+                const double den = std::hypot(a0, a1);
+                cs[l][j] = den > 0 ? a0 / den : 1.0;
+                sn[l][j] = den > 0 ? a1 / den : 0.0;
+                Hl[hidx(j, j)] = cs[l][j] * a0 + sn[l][j] * a1;
+                Hl[hidx(j + 1, j)] = 0.0;
+                g[l][j + 1] = -sn[l][j] * g[l][j];
+                g[l][j] = cs[l][j] * g[l][j];
+                jused[l] = j + 1;
+                ++it_l[l];
+                if (std::fabs(g[l][j + 1]) <= tol * bn[l] || hn == 0.0 || it_l[l] >= maxit)
+                    live[l] = 0;
+                else
+                    a[l] = 1.0 / hn;
+            }
+            jmax = j + 1;
+            if ((rc = upload(d_a, a, st))) return rc;
+            launch_saxpby(G, d_a, Wv, n, d_zero, V + (int64_t)(j + 1) * vs, n, nrhs, st);
+        }
+        // y = H^{-1} g per lane; x += M^{-1} V y
+        std::fill(coef.begin(), coef.end(), 0.0);
+        for (int l = 0; l < L; ++l) {
+            a[l] = jused[l] > 0 ? 1.0 : 0.0;
+            const int ju = jused[l];
+            std::vector<double> y(ju);
+            for (int i = ju - 1; i >= 0; --i) {
+                double s = g[l][i];
+                for (int c = i + 1; c < ju; ++c) s -= H[l][hidx(i, c)] * y[c];
+                y[i] = s / H[l][hidx(i, i)];
+            }
+            for (int i = 0; i < ju; ++i) coef[(size_t)i * L + l] = y[i];
+        }
+        HIP_TRY(hipMemcpyAsync(d_coef, coef.data(), (size_t)std::max(jmax, 1) * L * sizeof(double),
+                               hipMemcpyHostToDevice, st));
+        launch_scomb(G, jmax, d_coef, V, vs, n, d_zero, Wv, n, nrhs, st);
+        if ((rc = solve_impl(F, nrhs, Wv, n, T, n, st))) return rc;
+        if ((rc = upload(d_a, a, st))) return rc;
+        launch_saxpby(G, d_a, T, n, d_one, X, ldx, nrhs, st);
+        // true residual
+        launch_spmv(n, F->A_row.as<int64_t>(), F->A_col.as<int32_t>(), F->A_val.as<double>(), X, ldx, Rv, n, nrhs, st);
+        launch_xmy(n, B, ldb, Rv, n, nrhs, st);
+        std::vector<double> rn2(L);
+        if ((rc = sdots_host(F, 1, Rv, 0, n, Rv, n, nrhs, part, d_dot, rn2.data(), st))) return rc;
+        for (int l = 0; l < L; ++l) {
+            if (!inc[l]) continue;
+            rnorm[l] = std::sqrt(std::max(rn2[l], 0.0));
+            if (rnorm[l] <= tol * bn[l]) active[l] = 0;
+        }
+    }
+    bool ok = true;
+    int itmax = 0;
+    for (int l = 0; l < L; ++l) {
+        const double r = rnorm[l] / bn[l];
+        if (relres) relres[l] = r;
+        if (!(r <= tol)) ok = false;
+        itmax = std::max(itmax, it_l[l]);
+    }
+    if (iters) *iters = itmax;
     return ok ? HS_OK : HS_WARN_NOT_CONVERGED;
 }
 
@@ -1229,28 +1477,58 @@ using namespace hs;
 
 extern "C" {
 
-int hs_factor(const hs_csr* A, const hs_geometry* geom, const hs_opts* opts, void* hip_stream, hs_factor_t* F_out) {
-    g_err.clear();
-    if (!F_out) return fail(HS_ERR_ARG, "F_out is NULL");
-    *F_out = nullptr;
-    if (!A || !geom || !opts || !A->row_ptr || (A->nnz > 0 && (!A->col_idx || !A->val)))
-        return fail(HS_ERR_ARG, "null argument");
-    if (A->n <= 0 || A->nnz < 0 || A->n > INT32_MAX) return fail(HS_ERR_ARG, "bad matrix size");
+static int check_opts(const hs_opts* opts) {
     if (!(opts->eps >= 0.0) || opts->leaf_size <= 0 || opts->fixed_rank < 0 || opts->coarse_fp64_dofs < 0 ||
         (opts->precision != HS_FP64 && opts->precision != HS_MIXED))
         return fail(HS_ERR_ARG, "bad options");
+    return HS_OK;
+}
+
+static int check_system(const hs_csr* A, const hs_geometry* geom) {
+    if (!A->row_ptr || (A->nnz > 0 && (!A->col_idx || !A->val))) return fail(HS_ERR_ARG, "null argument");
+    if (A->n <= 0 || A->nnz < 0 || A->n > INT32_MAX) return fail(HS_ERR_ARG, "bad matrix size");
     if (geom->dim < 1 || geom->dim > 3 || (int64_t)geom->nx * geom->ny * geom->nz != A->n)
         return fail(HS_ERR_GEOMETRY, "n != nx*ny*nz");
-    int rc = check_device();
+    return HS_OK;
+}
+
+static int factor_entry(int32_t nsys, const hs_csr* A, const hs_geometry* geom, const hs_opts* opts, void* hip_stream,
+                        hs_factor_t* F_out) {
+    g_err.clear();
+    if (!F_out) return fail(HS_ERR_ARG, "F_out is NULL");
+    *F_out = nullptr;
+    if (!A || !geom || !opts || nsys < 1) return fail(HS_ERR_ARG, "null argument or no system");
+    int rc = check_opts(opts);
+    if (rc) return rc;
+    for (int i = 0; i < nsys; ++i) {
+        rc = check_system(&A[i], &geom[i]);
+        if (rc) return nsys > 1 ? fail(rc, "system " + std::to_string(i) + ": " + g_err) : rc;
+    }
+    rc = check_device();
     if (rc) return rc;
     std::unique_ptr<hs_factor_s> F(new hs_factor_s());
-    F->n = A->n;
     F->opts = *opts;
     F->info.breakdown_level = -1;
     F->info.breakdown_cluster = -1;
-    rc = factor_impl(F.get(), A, geom, (hipStream_t)hip_stream);
+    rc = factor_impl(F.get(), nsys, A, geom, (hipStream_t)hip_stream);
     if (rc < 0) return rc;
     *F_out = F.release();
+    return HS_OK;
+}
+
+int hs_factor(const hs_csr* A, const hs_geometry* geom, const hs_opts* opts, void* hip_stream, hs_factor_t* F_out) {
+    return factor_entry(1, A, geom, opts, hip_stream, F_out);
+}
+
+int hs_factor_batch(int32_t nsys, const hs_csr* A, const hs_geometry* geom, const hs_opts* opts, void* hip_stream,
+                    hs_factor_t* F_out) {
+    return factor_entry(nsys, A, geom, opts, hip_stream, F_out);
+}
+
+int hs_factor_systems(hs_factor_t F, int32_t* nsys, int64_t* row_off) {
+    if (!F) return fail(HS_ERR_ARG, "null factor");
+    if (nsys) *nsys = F->forest.nsys;
+    if (row_off) std::copy(F->forest.row_off.begin(), F->forest.row_off.end(), row_off);
     return HS_OK;
 }
 
@@ -1320,10 +1598,8 @@ int hs_factor_record(hs_factor_t F, int32_t level, int32_t cluster, int32_t whic
         return HS_OK;
     }
     std::vector<int> ntot(1), ncap(1);
-    std::vector<int64_t> roff(1);
     HIP_TRY(hipMemcpy(ntot.data(), LD.dev.ntot + cluster, sizeof(int), hipMemcpyDeviceToHost));
     HIP_TRY(hipMemcpy(ncap.data(), LD.dev.ncap + cluster, sizeof(int), hipMemcpyDeviceToHost));
-    HIP_TRY(hipMemcpy(roff.data(), LD.dev.rec_off + cluster, sizeof(int64_t), hipMemcpyDeviceToHost));
     const int64_t MM = (int64_t)m * m;
     int64_t r, c, ld, e0;
     switch (which) {
@@ -1337,9 +1613,9 @@ int hs_factor_record(hs_factor_t F, int32_t level, int32_t cluster, int32_t whic
     if (!out) return HS_OK;  // shape query
     if (r * c > cap) return fail(HS_ERR_ARG, "output too small");
     if (r * c == 0) return HS_OK;
-    const size_t es = LD.esz();
-    const char* src = LD.rec.as<char>() + (roff[0] + e0) * es;
-    if (!LD.f32) {
+    const size_t es = LD.esz(cluster);
+    const char* src = LD.rec.as<char>() + (LD.rec_off[cluster] + e0) * es;
+    if (!LD.f32[cluster]) {
         HIP_TRY(hipMemcpy2D(out, r * sizeof(double), src, ld * es, r * es, c, hipMemcpyDeviceToHost));
     } else {
         std::vector<float> tmp((size_t)(r * c));

@@ -16,21 +16,23 @@ namespace hs {
 
 constexpr int DNB = 128;  // panel width
 
-// D[o_a + i, o_b + j] = B(a, b)[i, j] for every block of the level.
-__global__ void k_dense_assemble(const int* __restrict__ pat_ptr, const int* __restrict__ pat, const int* __restrict__ m,
-                                 const int64_t* __restrict__ off, const int64_t* __restrict__ blk_off,
-                                 const double* __restrict__ blocks, double* __restrict__ D, int64_t ldd, int ncl) {
-    const int b = blockIdx.x;
-    // row cluster of block b: last a with pat_ptr[a] <= b
+// D[o_a + i, o_b + j] = B(a, b)[i, j] for every block of the clusters
+// c0 .. c0 + ncl - 1 (pattern entries from b0; a, c local to the range).
+__global__ void k_dense_assemble(const int* __restrict__ pat_ptr, const int* __restrict__ pat, int c0, int b0,
+                                 const int* __restrict__ m, const int64_t* __restrict__ off,
+                                 const int64_t* __restrict__ blk_off, const double* __restrict__ blocks,
+                                 double* __restrict__ D, int64_t ldd, int ncl) {
+    const int b = b0 + blockIdx.x;
+    // row cluster of block b: last a with pat_ptr[c0 + a] <= b
     int lo = 0, hi = ncl;
     while (hi - lo > 1) {
         int mid = (lo + hi) >> 1;
-        if (pat_ptr[mid] <= b)
+        if (pat_ptr[c0 + mid] <= b)
             lo = mid;
         else
             hi = mid;
     }
-    const int a = lo, c = pat[b];
+    const int a = lo, c = pat[b] - c0;
     const int ma = m[a], mc = m[c];
     const double* src = blocks + blk_off[b];
     double* dst = D + off[a] + off[c] * ldd;
@@ -160,14 +162,14 @@ __global__ void k_dense_couplings(const double* __restrict__ D, int64_t ldd, int
     }
 }
 
-int dense_level_factor(double* D, int64_t N, const int* pat_ptr, const int* pat, const int* m, const int64_t* off,
-                       const int64_t* blk_off, const double* blocks, int ncl, int nblk, double* inv, int* flag,
-                       const int* ncap, const int64_t* rec_off, double* rec, const std::vector<int>& m_host,
-                       const std::vector<int64_t>& off_host, hipStream_t st) {
-    launch_fill_zero(D, N * N, 0, st);
+int dense_level_factor(double* D, int64_t N, const int* pat_ptr, const int* pat, int c0, int b0, const int* m,
+                       const int64_t* off, const int64_t* blk_off, const double* blocks, int ncl, int nblk,
+                       double* inv, int* flag, const int* ncap, const int64_t* rec_off, double* rec,
+                       const std::vector<int>& m_host, const std::vector<int64_t>& off_host, hipStream_t st) {
+    launch_fill_zero(D, N * N * (int64_t)sizeof(double), st);
     if (nblk > 0)
-        hipLaunchKernelGGL(k_dense_assemble, dim3(nblk), dim3(256), 0, st, pat_ptr, pat, m, off, blk_off, blocks, D,
-                           (int64_t)N, ncl);
+        hipLaunchKernelGGL(k_dense_assemble, dim3(nblk), dim3(256), 0, st, pat_ptr, pat, c0, b0, m, off, blk_off,
+                           blocks, D, (int64_t)N, ncl);
     for (int64_t p = 0; p < N; p += DNB) {
         const int nb = (int)std::min<int64_t>(DNB, N - p);
         hipLaunchKernelGGL(k_dense_diag, dim3(1), dim3(WG), (size_t)nb * nb * sizeof(double), st, D, (int64_t)N, (int)p,

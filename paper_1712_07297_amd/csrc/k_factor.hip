@@ -18,6 +18,7 @@
 //   schur     A_ab -= E_L[a] E_R[b] for every ordered neighbour pair (Eq. elim).
 // A cluster without fill keeps E_s = I (Sec. 2.2): T_L' = L^{-1}, T_R' = U^{-1}.
 // Blocks of a processed cluster keep its coarse rows / columns first.
+#include <algorithm>
 #include <type_traits>
 
 #include "device_common.h"
@@ -53,7 +54,7 @@ __device__ inline int find_cluster64(const int64_t* pre, int n, int64_t q) {
 
 // G_split = sum over the split's fill partners t of B(s,t) B(s,t)^T (and, for
 // a general matrix, + B(t,s)^T B(t,s)): the Gram matrix F F^T of the fill
-// (Eq. lra) in gram_splits partial sums.  Each 64 x 64 tile of the partial is
+// (Eq. lra) in gram_splits_of(nf) partial sums.  Each 64 x 64 tile of the partial is
 // accumulated over all partners of the split in registers and stored once.
 template <class T>
 __global__ void __launch_bounds__(WG) k_gram(LevelDev L, const int* __restrict__ clist) {
@@ -64,7 +65,9 @@ __global__ void __launch_bounds__(WG) k_gram(LevelDev L, const int* __restrict__
     if (M == 0) return;
     double* Gp = L.ws + L.ws_off[s] + (int64_t)(WS_GP + split) * M * M;
     const int f0 = L.fill_ptr[s], nf = L.fill_ptr[s + 1] - f0;
-    const int chunk = (nf + L.gram_splits - 1) / L.gram_splits;
+    const int splits = gram_splits_of(nf);
+    if (split >= splits) return;
+    const int chunk = (nf + splits - 1) / splits;
     const int e0 = f0 + split * chunk, e1 = min(f0 + nf, e0 + chunk);
     lds_smem* sm_l = to_lds(&sm);
     for (int r0 = 0; r0 < M; r0 += MT)
@@ -93,22 +96,23 @@ __global__ void __launch_bounds__(WG) k_gram(LevelDev L, const int* __restrict__
         }
 }
 
-// Partial 0 += partials 1 .. gram_splits-1 (in that order), one entry per thread.
+// Partial 0 += partials 1 .. splits-1 (in that order), one entry per thread.
 __global__ void k_gram_reduce(LevelDev L, const int* __restrict__ clist) {
     const int s = clist[blockIdx.y];
     const int M = L.m[s];
     const int64_t MM = (int64_t)M * M;
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= MM) return;
+    const int splits = gram_splits_of(L.fill_ptr[s + 1] - L.fill_ptr[s]);
     double* G = L.ws + L.ws_off[s] + WS_GP * MM;
     double g = G[e];
-    for (int sp = 1; sp < L.gram_splits; ++sp) g += G[sp * MM + e];
+    for (int sp = 1; sp < splits; ++sp) g += G[sp * MM + e];
     G[e] = g;
 }
 
 void launch_gram(const LevelDev& L, const ColourDev& C, hipStream_t st) {
     if (C.n == 0) return;
-    if (L.f32)
+    if (C.f32)
         hipLaunchKernelGGL(k_gram<float>, dim3(L.gram_splits, C.n), dim3(WG), 0, st, L, C.clist);
     else
         hipLaunchKernelGGL(k_gram<double>, dim3(L.gram_splits, C.n), dim3(WG), 0, st, L, C.clist);
@@ -322,8 +326,25 @@ __global__ void __launch_bounds__(WG) k_pivot(LevelDev L, const int* __restrict_
     // block scratch: the GEMM staging area (2080 doubles) when the working
     // matrix is in LDS, else 12 x 256 doubles of dynamic LDS
     lds_f64* scr = INLDS ? (lds_f64*)sm_l : to_lds(dyn);
-    constexpr int TRI = INLDS ? 1 : 2;  // matrix-core triangular inverses (8 / 12 blocks)
-    const bool tri_mfma = INLDS || M <= TRI_MFMA_MAX12;
+    // triangular inverses: matrix cores with 8 blocks up to 128, 12 blocks up
+    // to 192, per-wave substitution beyond (chosen by M alone)
+    const int tri = M <= TRI_MFMA_MAX ? 1 : (M <= TRI_MFMA_MAX12 ? 2 : 0);
+    auto inv_lower = [&](auto Wp, int n, auto out) {
+        if (INLDS || tri == 1)
+            wg_trinv_lower_unit<1>(Wp, n, M, out, M, scr);
+        else if (tri == 2)
+            wg_trinv_lower_unit<2>(Wp, n, M, out, M, scr);
+        else
+            wg_trinv_lower_unit<0>(Wp, n, M, out, M, scr);
+    };
+    auto inv_upper = [&](auto Wp, int n, auto out) {
+        if (INLDS || tri == 1)
+            wg_trinv_upper<1>(Wp, n, M, out, M, scr);
+        else if (tri == 2)
+            wg_trinv_upper<2>(Wp, n, M, out, M, scr);
+        else
+            wg_trinv_upper<0>(Wp, n, M, out, M, scr);
+    };
     T* TLp = rec_t<T>(L, s);
     T* TRp = TLp + MM;
     T* Bss = blk_t<T>(L, L.diag_blk[s]);
@@ -379,12 +400,12 @@ __global__ void __launch_bounds__(WG) k_pivot(LevelDev L, const int* __restrict_
         return;
     }
     if (kk == 0) {  // E_s = I: one block LU step
-        if (tri_mfma) wg_trinv_lower_unit<TRI>(W, M, M, TLp, M, scr); else wg_trinv_lower_unit<0>(W, M, M, TLp, M, scr);
-        if (tri_mfma) wg_trinv_upper<TRI>(W, M, M, TRp, M, scr); else wg_trinv_upper<0>(W, M, M, TRp, M, scr);
+        inv_lower(W, M, TLp);
+        inv_upper(W, M, TRp);
         return;
     }
-    if (tri_mfma) wg_trinv_lower_unit<TRI>(W, M, M, Linv, M, scr); else wg_trinv_lower_unit<0>(W, M, M, Linv, M, scr);
-    if (tri_mfma) wg_trinv_upper<TRI>(W, M, M, Uinv, M, scr); else wg_trinv_upper<0>(W, M, M, Uinv, M, scr);
+    inv_lower(W, M, Linv);
+    inv_upper(W, M, Uinv);
     wg_gemm<false, false>(M, M, M, 1.0, Uinv, M, Linv, M, 0.0, Ainv, M, sm_l);
     const int f = M - kk;
 
@@ -414,8 +435,8 @@ __global__ void __launch_bounds__(WG) k_pivot(LevelDev L, const int* __restrict_
         }
         return;
     }
-    if (tri_mfma) wg_trinv_lower_unit<TRI>(W, f, M, Linv, M, scr); else wg_trinv_lower_unit<0>(W, f, M, Linv, M, scr);
-    if (tri_mfma) wg_trinv_upper<TRI>(W, f, M, Uinv, M, scr); else wg_trinv_upper<0>(W, f, M, Uinv, M, scr);
+    inv_lower(W, f, Linv);
+    inv_upper(W, f, Uinv);
     // T_L' = [L_f^{-1} T_L[:f, :]; T_L[f:, :]],  T_R' = [T_R[:, :f] U_f^{-1}, T_R[:, f:]]
     wg_gemm<false, false>(f, M, f, 1.0, Linv, M, TL, M, 0.0, TLp, M, sm_l);
     wg_copy(kk, M, TL + f, M, TLp + f, M);
@@ -433,13 +454,13 @@ void launch_pivot(const LevelDev& L, const ColourDev& C, hipStream_t st) {
     if (C.n == 0) return;
     const size_t shmem = (size_t)C.max_m * C.max_m * sizeof(double);
     if (C.max_m <= LDS_M) {
-        if (L.f32)
+        if (C.f32)
             hipLaunchKernelGGL((k_pivot<true, float>), dim3(C.n), dim3(WG), shmem, st, L, C.clist);
         else
             hipLaunchKernelGGL((k_pivot<true, double>), dim3(C.n), dim3(WG), shmem, st, L, C.clist);
     } else {
         const size_t scr_bytes = 12 * 256 * sizeof(double);
-        if (L.f32)
+        if (C.f32)
             hipLaunchKernelGGL((k_pivot<false, float>), dim3(C.n), dim3(WG), scr_bytes, st, L, C.clist);
         else
             hipLaunchKernelGGL((k_pivot<false, double>), dim3(C.n), dim3(WG), scr_bytes, st, L, C.clist);
@@ -506,7 +527,7 @@ void launch_fill_update(const LevelDev& L, const ColourDev& C, hipStream_t st) {
     if (C.fill_total == 0 || C.panels == 0) return;
     const int pw = panel_width(C.max_m);
     const size_t shmem = (size_t)2 * C.max_m * pw * sizeof(double);
-    if (L.f32)
+    if (C.f32)
         hipLaunchKernelGGL(k_fill_update<float>, dim3(C.panels, C.fill_total), dim3(WG), shmem, st, L, C, pw);
     else
         hipLaunchKernelGGL(k_fill_update<double>, dim3(C.panels, C.fill_total), dim3(WG), shmem, st, L, C, pw);
@@ -576,7 +597,7 @@ void launch_nbr_update(const LevelDev& L, const ColourDev& C, hipStream_t st) {
     if (C.nbr_total == 0 || C.panels == 0) return;
     const int pw = panel_width(C.max_m);
     const size_t shmem = (size_t)2 * C.max_m * pw * sizeof(double);
-    if (L.f32)
+    if (C.f32)
         hipLaunchKernelGGL(k_nbr_update<float>, dim3(C.panels, C.nbr_total), dim3(WG), shmem, st, L, C, pw);
     else
         hipLaunchKernelGGL(k_nbr_update<double>, dim3(C.panels, C.nbr_total), dim3(WG), shmem, st, L, C, pw);
@@ -711,7 +732,7 @@ __global__ void __launch_bounds__(WG) k_schur(LevelDev L, ColourDev C) {
 
 void launch_schur(const LevelDev& L, const ColourDev& C, hipStream_t st) {
     if (C.tile_total == 0) return;
-    if (L.f32)
+    if (C.f32)
         hipLaunchKernelGGL(k_schur<float>, dim3((unsigned)C.tile_total), dim3(WG), 0, st, L, C);
     else
         hipLaunchKernelGGL(k_schur<double>, dim3((unsigned)C.tile_total), dim3(WG), 0, st, L, C);
@@ -719,16 +740,17 @@ void launch_schur(const LevelDev& L, const ColourDev& C, hipStream_t st) {
 
 // ================================================================ assembly
 
-template <class T>
 __global__ void k_assemble0(int64_t n, const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx,
                             const double* __restrict__ val, const int* __restrict__ cluster_of,
                             const int* __restrict__ local_of, const int* __restrict__ m,
                             const int* __restrict__ pat_ptr, const int* __restrict__ pat,
-                            const int64_t* __restrict__ blk_off, T* __restrict__ blocks) {
+                            const int64_t* __restrict__ blk_off, void* __restrict__ blocks,
+                            const int* __restrict__ f32) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int ci = cluster_of[i], li = local_of[i];
     const int lo0 = pat_ptr[ci], hi0 = pat_ptr[ci + 1];
+    const bool single = f32[ci] != 0;
     for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
         const int j = col_idx[e];
         const int cj = cluster_of[j], lj = local_of[j];
@@ -740,32 +762,31 @@ __global__ void k_assemble0(int64_t n, const int64_t* __restrict__ row_ptr, cons
             else
                 hi = mid;
         }
-        blocks[blk_off[lo] + li + (int64_t)lj * m[ci]] = (T)val[e];
+        const int64_t x = blk_off[lo] + li + (int64_t)lj * m[ci];
+        if (single)
+            static_cast<float*>(blocks)[x] = (float)val[e];
+        else
+            static_cast<double*>(blocks)[x] = val[e];
     }
 }
 
 void launch_assemble0(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, const double* val,
                       const int* cluster_of, const int* local_of, const int* m, const int* pat_ptr, const int* pat,
-                      const int64_t* blk_off, void* blocks, int f32, hipStream_t st) {
+                      const int64_t* blk_off, void* blocks, const int* f32, hipStream_t st) {
+    if (n == 0) return;
     const int bs = 256;
-    const dim3 g((unsigned)((n + bs - 1) / bs));
-    if (f32)
-        hipLaunchKernelGGL(k_assemble0<float>, g, dim3(bs), 0, st, n, row_ptr, col_idx, val, cluster_of, local_of, m,
-                           pat_ptr, pat, blk_off, (float*)blocks);
-    else
-        hipLaunchKernelGGL(k_assemble0<double>, g, dim3(bs), 0, st, n, row_ptr, col_idx, val, cluster_of, local_of, m,
-                           pat_ptr, pat, blk_off, (double*)blocks);
+    hipLaunchKernelGGL(k_assemble0, dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, st, n, row_ptr, col_idx, val,
+                       cluster_of, local_of, m, pat_ptr, pat, blk_off, blocks, f32);
 }
 
 // Parent block (P, Q) = [[B(l_P, l_Q), B(l_P, r_Q)], [B(r_P, l_Q), B(r_P, r_Q)]]
 // of the children's coarse blocks (Alg. 1 "Extract A_c").
 template <class TS, class TD>
-__global__ void k_merge(const int* __restrict__ nb_row, const int* __restrict__ nb_col, const int* __restrict__ src4,
-                        const int* __restrict__ k_prev, const int* __restrict__ m_prev,
-                        const int64_t* __restrict__ blk_off_prev, const TS* __restrict__ blocks_prev,
-                        const int* __restrict__ m_next, const int64_t* __restrict__ blk_off_next,
-                        TD* __restrict__ blocks_next, int ncl_prev) {
-    const int b = blockIdx.x;
+__device__ void merge_block(int b, const int* __restrict__ nb_row, const int* __restrict__ nb_col,
+                            const int* __restrict__ src4, const int* __restrict__ k_prev,
+                            const int* __restrict__ m_prev, const int64_t* __restrict__ blk_off_prev,
+                            const TS* __restrict__ blocks_prev, const int* __restrict__ m_next,
+                            const int64_t* __restrict__ blk_off_next, TD* __restrict__ blocks_next) {
     const int P = nb_row[b], Q = nb_col[b];
     const int ldn = m_next[P];
     TD* dst = blocks_next + blk_off_next[b];
@@ -783,27 +804,40 @@ __global__ void k_merge(const int* __restrict__ nb_row, const int* __restrict__ 
             dst[(roff + i) + (int64_t)(coff + j) * ldn] = (TD)sp[i + (int64_t)j * lds];
         }
     }
-    (void)ncl_prev;
 }
 
-void launch_merge(int nblk_next, const int* nb_row, const int* nb_col, const int* src4, const int* k_prev,
-                  const int* m_prev, const int64_t* blk_off_prev, const void* blocks_prev, int prev_f32,
-                  const int* m_next, const int64_t* blk_off_next, void* blocks_next, int next_f32, int ncl_prev,
-                  hipStream_t st) {
-    if (nblk_next == 0) return;
-    const dim3 g(nblk_next), b(256);
-#define HS_MERGE(TS, TD)                                                                                            \
-    hipLaunchKernelGGL((k_merge<TS, TD>), g, b, 0, st, nb_row, nb_col, src4, k_prev, m_prev, blk_off_prev,           \
-                       (const TS*)blocks_prev, m_next, blk_off_next, (TD*)blocks_next, ncl_prev)
-    if (prev_f32 && next_f32)
+// Element types per block from the clusters (a system's children and
+// parent may differ: float32 below, float64 from the level where it stops).
+__global__ void k_merge(const int* __restrict__ nb_row, const int* __restrict__ nb_col, const int* __restrict__ src4,
+                        const int* __restrict__ k_prev, const int* __restrict__ m_prev,
+                        const int64_t* __restrict__ blk_off_prev, const void* __restrict__ blocks_prev,
+                        const int* __restrict__ f32_prev, const int* __restrict__ m_next,
+                        const int64_t* __restrict__ blk_off_next, void* __restrict__ blocks_next,
+                        const int* __restrict__ f32_next) {
+    const int b = blockIdx.x;
+    const int P = nb_row[b];
+    const bool s32 = f32_prev[2 * P] != 0, d32 = f32_next[P] != 0;
+#define HS_MERGE(TS, TD)                                                                                           \
+    merge_block<TS, TD>(b, nb_row, nb_col, src4, k_prev, m_prev, blk_off_prev, static_cast<const TS*>(blocks_prev), \
+                        m_next, blk_off_next, static_cast<TD*>(blocks_next))
+    if (s32 && d32)
         HS_MERGE(float, float);
-    else if (prev_f32)
+    else if (s32)
         HS_MERGE(float, double);
-    else if (next_f32)
+    else if (d32)
         HS_MERGE(double, float);
     else
         HS_MERGE(double, double);
 #undef HS_MERGE
+}
+
+void launch_merge(int nblk_next, const int* nb_row, const int* nb_col, const int* src4, const int* k_prev,
+                  const int* m_prev, const int64_t* blk_off_prev, const void* blocks_prev, const int* f32_prev,
+                  const int* m_next, const int64_t* blk_off_next, void* blocks_next, const int* f32_next,
+                  hipStream_t st) {
+    if (nblk_next == 0) return;
+    hipLaunchKernelGGL(k_merge, dim3(nblk_next), dim3(256), 0, st, nb_row, nb_col, src4, k_prev, m_prev, blk_off_prev,
+                       blocks_prev, f32_prev, m_next, blk_off_next, blocks_next, f32_next);
 }
 
 __global__ void k_pair_blocks(const int* __restrict__ nbr_ptr, const int* __restrict__ nbr_id,
@@ -832,20 +866,33 @@ void launch_pair_blocks(int ncl, const int* nbr_ptr, const int* nbr_id, const in
     hipLaunchKernelGGL(k_pair_blocks, dim3(ncl), dim3(256), 0, st, nbr_ptr, nbr_id, pat_ptr, pat, pair_base, pair_blk);
 }
 
-template <class T>
-__global__ void k_fill_zero(T* p, int64_t n) {
+__global__ void k_fill_zero(uint32_t* p, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = (T)0;
+        p[i] = 0u;
 }
 
-void launch_fill_zero(void* p, int64_t n, int f32, hipStream_t st) {
+void launch_fill_zero(void* p, int64_t bytes, hipStream_t st) {
+    const int64_t n = bytes / 4;
     if (n <= 0) return;
     int64_t blocks = (n + 255) / 256;
     if (blocks > 65536) blocks = 65536;
-    if (f32)
-        hipLaunchKernelGGL(k_fill_zero<float>, dim3((unsigned)blocks), dim3(256), 0, st, (float*)p, n);
-    else
-        hipLaunchKernelGGL(k_fill_zero<double>, dim3((unsigned)blocks), dim3(256), 0, st, (double*)p, n);
+    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)blocks), dim3(256), 0, st, (uint32_t*)p, n);
+}
+
+__global__ void k_shift_csr(int64_t n_i, int64_t nnz_i, int64_t row_off, int64_t nnz_off, int64_t* __restrict__ row_ptr,
+                            int32_t* __restrict__ col_idx) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= n_i; i += stride) row_ptr[i] += nnz_off;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz_i; e += stride)
+        col_idx[e] += (int32_t)row_off;
+}
+
+void launch_shift_csr(int64_t n_i, int64_t nnz_i, int64_t row_off, int64_t nnz_off, int64_t* row_ptr,
+                      int32_t* col_idx, hipStream_t st) {
+    if (row_off == 0 && nnz_off == 0) return;
+    const int64_t work = std::max(n_i + 1, nnz_i);
+    const unsigned g = (unsigned)std::min<int64_t>((work + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_shift_csr, dim3(g), dim3(256), 0, st, n_i, nnz_i, row_off, nnz_off, row_ptr, col_idx);
 }
 
 }  // namespace hs

@@ -61,7 +61,7 @@ void launch_apply_fwd_t(const SolveLevelDev& S, const ColourDev& C, const double
                         hipStream_t st) {
     if (C.n == 0) return;
     const size_t sh = (size_t)C.max_m * nrhs * sizeof(double);
-    if (S.f32)
+    if (C.f32)
         hipLaunchKernelGGL(k_apply_fwd_t<float>, dim3(C.n), dim3(WG), sh, st, S, C, y, z, nrhs);
     else
         hipLaunchKernelGGL(k_apply_fwd_t<double>, dim3(C.n), dim3(WG), sh, st, S, C, y, z, nrhs);
@@ -114,7 +114,7 @@ void launch_apply_fwd_u(const SolveLevelDev& S, const ColourDev& C, double* y, d
     if (chunks == 0) return;
     (void)max_m;
     const size_t sh = (size_t)C.max_m * nrhs * sizeof(double);
-    if (S.f32)
+    if (C.f32)
         hipLaunchKernelGGL(k_apply_fwd_u<float>, dim3(chunks, C.nbr_total), dim3(WG), sh, st, S, C, y, z, nrhs);
     else
         hipLaunchKernelGGL(k_apply_fwd_u<double>, dim3(chunks, C.nbr_total), dim3(WG), sh, st, S, C, y, z, nrhs);
@@ -160,7 +160,7 @@ void launch_apply_bwd_acc(const SolveLevelDev& S, const ColourDev& C, const doub
                           double* part, const int64_t* part_off, int nrhs, hipStream_t st) {
     if (C.nbr_total == 0) return;
     const size_t sh = (size_t)C.max_nbr_m * nrhs * sizeof(double);
-    if (S.f32)
+    if (C.f32)
         hipLaunchKernelGGL(k_apply_bwd_acc<float>, dim3(C.nbr_total), dim3(WG), sh, st, S, C, z, out, part, part_off,
                            nrhs);
     else
@@ -230,7 +230,7 @@ void launch_apply_bwd_t(const SolveLevelDev& S, const ColourDev& C, const double
                         const double* part, const int64_t* part_off, int nrhs, hipStream_t st) {
     if (C.n == 0) return;
     const size_t sh = (size_t)C.max_m * nrhs * sizeof(double);
-    if (S.f32)
+    if (C.f32)
         hipLaunchKernelGGL(k_apply_bwd_t<float>, dim3(C.n), dim3(WG), sh, st, S, C, z, out, part, part_off, nrhs);
     else
         hipLaunchKernelGGL(k_apply_bwd_t<double>, dim3(C.n), dim3(WG), sh, st, S, C, z, out, part, part_off, nrhs);
@@ -299,88 +299,6 @@ void launch_gather_sol(int64_t n, const int* cluster_of, const int* local_of, co
                        const double* out, double* X, int64_t ldx, int nrhs, hipStream_t st) {
     hipLaunchKernelGGL(k_scatter_gather, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, cluster_of, local_of,
                        seg, m, X, ldx, const_cast<double*>(out), nrhs, 0);
-}
-
-// ------------------------------------------------------------------ Krylov
-
-__global__ void k_spmv(int64_t n, const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx,
-                       const double* __restrict__ val, const double* __restrict__ X, int64_t ldx,
-                       double* __restrict__ Y, int64_t ldy, int nrhs) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int64_t e0 = row_ptr[i], e1 = row_ptr[i + 1];
-    for (int r = 0; r < nrhs; ++r) {
-        const double* x = X + r * ldx;
-        double acc = 0.0;
-        for (int64_t e = e0; e < e1; ++e) acc = fma(val[e], x[col_idx[e]], acc);
-        Y[i + r * ldy] = acc;
-    }
-}
-
-void launch_spmv(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, const double* val, const double* X,
-                 int64_t ldx, double* Y, int64_t ldy, int nrhs, hipStream_t st) {
-    hipLaunchKernelGGL(k_spmv, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, row_ptr, col_idx, val, X, ldx,
-                       Y, ldy, nrhs);
-}
-
-__global__ void k_dots_part(int64_t n, const double* __restrict__ a, int64_t lda, const double* __restrict__ b,
-                            int64_t ldb, double* __restrict__ part) {
-    __shared__ double red[16];
-    const int r = blockIdx.y;
-    double acc = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        acc = fma(a[i + r * lda], b[i + r * ldb], acc);
-    acc = block_sum(acc, red);
-    if (threadIdx.x == 0) part[r * gridDim.x + blockIdx.x] = acc;
-}
-
-__global__ void k_dots_final(const double* __restrict__ part, int nb, double* __restrict__ out) {
-    __shared__ double red[16];
-    const int r = blockIdx.x;
-    double acc = 0.0;
-    for (int i = threadIdx.x; i < nb; i += blockDim.x) acc += part[r * nb + i];
-    acc = block_sum(acc, red);
-    if (threadIdx.x == 0) out[r] = acc;
-}
-
-void launch_dots(int64_t n, const double* a, int64_t lda, const double* b, int64_t ldb, int nrhs, double* part,
-                 double* out, hipStream_t st) {
-    hipLaunchKernelGGL(k_dots_part, dim3(KRYLOV_BLOCKS, nrhs), dim3(256), 0, st, n, a, lda, b, ldb, part);
-    hipLaunchKernelGGL(k_dots_final, dim3(nrhs), dim3(256), 0, st, part, KRYLOV_BLOCKS, out);
-}
-
-__global__ void k_axpby(int64_t n, const double* __restrict__ alpha, const double* __restrict__ x, int64_t ldx,
-                        const double* __restrict__ beta, double* __restrict__ y, int64_t ldy, int nrhs) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    for (int r = 0; r < nrhs; ++r) {
-        // a zero coefficient never reads its operand (uninitialised memory may hold NaN)
-        double v = 0.0;
-        if (alpha[r] != 0.0) v = alpha[r] * x[i + r * ldx];
-        if (beta[r] != 0.0) v = fma(beta[r], y[i + r * ldy], v);
-        y[i + r * ldy] = v;
-    }
-}
-
-void launch_axpby(int64_t n, const double* alpha, const double* x, int64_t ldx, const double* beta, double* y,
-                  int64_t ldy, int nrhs, hipStream_t st) {
-    hipLaunchKernelGGL(k_axpby, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, alpha, x, ldx, beta, y, ldy,
-                       nrhs);
-}
-
-__global__ void k_xmy(int64_t n, const double* __restrict__ x, int64_t ldx, double* __restrict__ y, int64_t ldy,
-                      int nrhs, int copy) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    for (int r = 0; r < nrhs; ++r) y[i + r * ldy] = copy ? x[i + r * ldx] : x[i + r * ldx] - y[i + r * ldy];
-}
-
-void launch_xmy(int64_t n, const double* x, int64_t ldx, double* y, int64_t ldy, int nrhs, hipStream_t st) {
-    hipLaunchKernelGGL(k_xmy, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, x, ldx, y, ldy, nrhs, 0);
-}
-
-void launch_copy(int64_t n, const double* x, int64_t ldx, double* y, int64_t ldy, int nrhs, hipStream_t st) {
-    hipLaunchKernelGGL(k_xmy, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, x, ldx, y, ldy, nrhs, 1);
 }
 
 }  // namespace hs

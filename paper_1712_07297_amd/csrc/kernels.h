@@ -25,6 +25,7 @@ struct ColourDev {
     int panels = 0;                   // column panels per neighbour / partner block (capacity)
     int max_m = 0;                    // largest cluster of the colour
     int max_nbr_m = 0;                // largest neighbour or fill partner of a cluster of the colour
+    int f32 = 0;                      // the clusters' blocks and records are float32 (else float64)
 };
 
 // ---- factorization, one colour at a time
@@ -38,17 +39,23 @@ void launch_schur(const LevelDev& L, const ColourDev& C, hipStream_t st);
 
 // ---- level set-up
 // Scatter the CSR values into the level-0 block store.
+// Blocks of cluster c are float32 where f32[c] != 0, else float64.
 void launch_assemble0(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, const double* val,
                       const int* cluster_of, const int* local_of, const int* m, const int* pat_ptr, const int* pat,
-                      const int64_t* blk_off, void* blocks, int f32, hipStream_t st);
+                      const int64_t* blk_off, void* blocks, const int* f32, hipStream_t st);
 // Gather the coarse blocks of the children into the parent level.  For every
 // parent block: src[4] child block ids (-1 = absent) for (l,l),(l,r),(r,l),(r,r).
-// Blocks are float or double on either side (prev_f32 / next_f32).
+// Element types per cluster on either side (f32_prev / f32_next).
 void launch_merge(int nblk_next, const int* nb_row, const int* nb_col, const int* src4, const int* k_prev,
-                  const int* m_prev, const int64_t* blk_off_prev, const void* blocks_prev, int prev_f32,
-                  const int* m_next, const int64_t* blk_off_next, void* blocks_next, int next_f32, int ncl_prev,
+                  const int* m_prev, const int64_t* blk_off_prev, const void* blocks_prev, const int* f32_prev,
+                  const int* m_next, const int64_t* blk_off_next, void* blocks_next, const int* f32_next,
                   hipStream_t st);
-void launch_fill_zero(void* p, int64_t n, int f32, hipStream_t st);
+// Zero `bytes` bytes (a multiple of 4) from p.
+void launch_fill_zero(void* p, int64_t bytes, hipStream_t st);
+// System i's CSR copied into a block-diagonal one: its n_i + 1 row pointers
+// (from 0) are shifted by nnz_off and its column indices by row_off.
+void launch_shift_csr(int64_t n_i, int64_t nnz_i, int64_t row_off, int64_t nnz_off, int64_t* row_ptr,
+                      int32_t* col_idx, hipStream_t st);
 // pair_blk[pair_base[s] + i nb + j] = block id of (a_i, a_j) for the
 // neighbours a_0 .. a_{nb-1} of every cluster s (binary search in the level's
 // block pattern pat_ptr / pat).
@@ -58,10 +65,13 @@ void launch_pair_blocks(int ncl, const int* nbr_ptr, const int* nbr_id, const in
 // block store, unpivoted blocked LU in place, per-cluster operators into the
 // records.  inv: 2 * 128 * 128 doubles of workspace; flag: device int, set to
 // 1 on a zero or non-finite pivot.
-int dense_level_factor(double* D, int64_t N, const int* pat_ptr, const int* pat, const int* m, const int64_t* off,
-                       const int64_t* blk_off, const double* blocks, int ncl, int nblk, double* inv, int* flag,
-                       const int* ncap, const int64_t* rec_off, double* rec, const std::vector<int>& m_host,
-                       const std::vector<int64_t>& off_host, hipStream_t st);
+// The clusters are c0 .. c0 + ncl - 1 of the level (one system); their blocks
+// are pattern entries b0 .. b0 + nblk - 1; m, off, ncap, rec_off point at
+// cluster c0's entry; m_host / off_host are local to the range.
+int dense_level_factor(double* D, int64_t N, const int* pat_ptr, const int* pat, int c0, int b0, const int* m,
+                       const int64_t* off, const int64_t* blk_off, const double* blocks, int ncl, int nblk,
+                       double* inv, int* flag, const int* ncap, const int64_t* rec_off, double* rec,
+                       const std::vector<int>& m_host, const std::vector<int64_t>& off_host, hipStream_t st);
 
 // ---- solve (Alg. 2)
 struct SolveLevelDev {
@@ -75,8 +85,7 @@ struct SolveLevelDev {
     const int* ntot;
     const int* ncap;
     const int64_t* rec_off;
-    const double* rec;   // records: double, or float when f32
-    int f32;
+    const double* rec;   // records: float64, or float32 for the clusters of a float32 list
     const int64_t* seg;  // [ncl+1] offset of every cluster segment (units of unknowns)
 };
 // z_s = T_L' y_s for the clusters of a colour (deferred: z_s = y_s)
@@ -103,17 +112,35 @@ void launch_scatter_rhs(int64_t n, const int* cluster_of, const int* local_of, c
 void launch_gather_sol(int64_t n, const int* cluster_of, const int* local_of, const int64_t* seg, const int* m,
                        const double* out, double* X, int64_t ldx, int nrhs, hipStream_t st);
 
-// ---- Krylov building blocks (float64, n x nrhs column major)
+// ---- Krylov building blocks (float64, n x nrhs column major).  A vector
+// stacks the unknowns of independent systems; every per-system quantity is
+// formed in an order fixed by that system alone: chunks of KRY_CHUNK rows
+// counted from the system's first row, each reduced by one workgroup, chunk
+// results added in chunk order.  Per-system scalars are indexed by the lane
+// l = s + nsys * c (system s, column c).
+constexpr int KRY_CHUNK = 4096;
+struct SegDev {
+    int nsys = 0;
+    int nchunks = 0;
+    const int64_t* row_off = nullptr;    // [nsys+1]
+    const int* chunk_sys = nullptr;      // [nchunks]
+    const int64_t* chunk_r0 = nullptr;   // [nchunks] first row of the chunk
+    const int* sys_chunk0 = nullptr;     // [nsys+1] first chunk of every system
+};
 void launch_spmv(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, const double* val, const double* X,
                  int64_t ldx, double* Y, int64_t ldy, int nrhs, hipStream_t st);
-// out[j] = sum_i a[i,j] * b[i,j] for every column (deterministic two-pass); part has room for
-// nrhs * KRYLOV_BLOCKS doubles.
-constexpr int KRYLOV_BLOCKS = 256;
-void launch_dots(int64_t n, const double* a, int64_t lda, const double* b, int64_t ldb, int nrhs, double* part,
-                 double* out, hipStream_t st);
-// y[:, j] = alpha[j] * x[:, j] + beta[j] * y[:, j] (alpha / beta device arrays, may be per column)
-void launch_axpby(int64_t n, const double* alpha, const double* x, int64_t ldx, const double* beta, double* y,
-                  int64_t ldy, int nrhs, hipStream_t st);
+// out[v * L + l] = sum over system s's rows i of a_v[i, c] b[i, c], with
+// a_v = a + v * vstride (v < nvec) and L = nsys * nrhs; part holds
+// nvec * nrhs * nchunks doubles.
+void launch_sdots(const SegDev& G, int nvec, const double* a, int64_t vstride, int64_t lda, const double* b,
+                  int64_t ldb, int nrhs, double* part, double* out, hipStream_t st);
+// y[:, c] = alpha[l] x[:, c] + beta[l] y[:, c] on system s's rows (a zero
+// coefficient never reads its operand)
+void launch_saxpby(const SegDev& G, const double* alpha, const double* x, int64_t ldx, const double* beta, double* y,
+                   int64_t ldy, int nrhs, hipStream_t st);
+// y[:, c] = beta[l] y[:, c] + sum_{v < nvec} coef[v * L + l] a_v[:, c] (v ascending)
+void launch_scomb(const SegDev& G, int nvec, const double* coef, const double* a, int64_t vstride, int64_t lda,
+                  const double* beta, double* y, int64_t ldy, int nrhs, hipStream_t st);
 // y = x - y (elementwise, n x nrhs)
 void launch_xmy(int64_t n, const double* x, int64_t ldx, double* y, int64_t ldy, int nrhs, hipStream_t st);
 void launch_copy(int64_t n, const double* x, int64_t ldx, double* y, int64_t ldy, int nrhs, hipStream_t st);

@@ -307,4 +307,126 @@ int build_symbolic(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, in
     return HS_OK;
 }
 
+int complete_level(const Symbolic& S) {
+    for (int l = 0; l < S.nlevels; ++l) {
+        const LevelSymbolic& L = S.levels[l];
+        bool c = true;
+        for (int s = 0; s < L.ncl && c; ++s)
+            if (L.adj_ptr[s + 1] - L.adj_ptr[s] != L.ncl - 1 || L.order[s] != s) c = false;
+        if (c) return l;
+    }
+    return S.nlevels - 1;
+}
+
+void combine_symbolic(std::vector<Symbolic>& parts, bool keep_empty_levels, Symbolic& out, Forest& F) {
+    const int ns = (int)parts.size();
+    F = Forest();
+    F.nsys = ns;
+    F.row_off.assign(ns + 1, 0);
+    for (int i = 0; i < ns; ++i) F.row_off[i + 1] = F.row_off[i] + parts[i].n;
+    std::vector<int> dense(ns), last(ns);
+    for (int i = 0; i < ns; ++i) {
+        dense[i] = complete_level(parts[i]);
+        last[i] = keep_empty_levels ? parts[i].nlevels - 1 : dense[i];
+    }
+    F.sys.resize(ns);
+    for (int i = 0; i < ns; ++i) F.sys[i] = i;
+    std::stable_sort(F.sys.begin(), F.sys.end(), [&](int a, int b) { return last[a] > last[b]; });
+    F.last.resize(ns);
+    F.dense.resize(ns);
+    for (int j = 0; j < ns; ++j) {
+        F.last[j] = last[F.sys[j]];
+        F.dense[j] = dense[F.sys[j]];
+    }
+    out = Symbolic();
+    out.n = F.row_off[ns];
+    out.nlevels = ns ? F.last[0] + 1 : 0;
+    for (auto& P : parts) out.depth = std::max(out.depth, P.depth);
+    F.cl_off.assign(out.nlevels, {});
+
+    // leaves: placement order; unknown ids in the caller's system order
+    {
+        std::vector<int> off(ns + 1, 0);
+        for (int j = 0; j < ns; ++j) off[j + 1] = off[j] + parts[F.sys[j]].levels[0].ncl;
+        const int nleaf = off[ns];
+        out.leaf_ptr.assign(nleaf + 1, 0);
+        out.leaf_dofs.resize(out.n);
+        out.cluster_of.assign(out.n, -1);
+        out.local_of.assign(out.n, -1);
+        int64_t w = 0;
+        for (int j = 0; j < ns; ++j) {
+            Symbolic& P = parts[F.sys[j]];
+            const int64_t r0 = F.row_off[F.sys[j]];
+            const int c0 = off[j];
+            for (int c = 0; c < P.levels[0].ncl; ++c) {
+                for (int e = P.leaf_ptr[c]; e < P.leaf_ptr[c + 1]; ++e) out.leaf_dofs[w++] = r0 + P.leaf_dofs[e];
+                out.leaf_ptr[c0 + c + 1] = (int)w;
+            }
+            for (int64_t i = 0; i < P.n; ++i) {
+                out.cluster_of[r0 + i] = c0 + P.cluster_of[i];
+                out.local_of[r0 + i] = P.local_of[i];
+            }
+            std::vector<int>().swap(P.cluster_of);
+            std::vector<int>().swap(P.local_of);
+            std::vector<int64_t>().swap(P.leaf_dofs);
+        }
+    }
+
+    out.levels.resize(out.nlevels);
+    for (int l = 0; l < out.nlevels; ++l) {
+        int alive = 0;
+        while (alive < ns && F.last[alive] >= l) ++alive;
+        std::vector<int>& off = F.cl_off[l];
+        off.assign(alive + 1, 0);
+        int ncolors = 0;
+        size_t nadj = 0, nfill = 0, npat = 0;
+        for (int j = 0; j < alive; ++j) {
+            const LevelSymbolic& L = parts[F.sys[j]].levels[l];
+            off[j + 1] = off[j] + L.ncl;
+            ncolors = std::max(ncolors, L.ncolors);
+            nadj += L.adj.size();
+            nfill += L.fill.size();
+            npat += L.pat.size();
+        }
+        LevelSymbolic& C = out.levels[l];
+        C.ncl = off[alive];
+        C.ncolors = ncolors;
+        C.color.resize(C.ncl);
+        C.adj_ptr.assign(C.ncl + 1, 0);
+        C.fill_ptr.assign(C.ncl + 1, 0);
+        C.pat_ptr.assign(C.ncl + 1, 0);
+        C.adj.reserve(nadj);
+        C.fill.reserve(nfill);
+        C.pat.reserve(npat);
+        for (int j = 0; j < alive; ++j) {
+            const LevelSymbolic& L = parts[F.sys[j]].levels[l];
+            const int c0 = off[j];
+            for (int s = 0; s < L.ncl; ++s) {
+                C.color[c0 + s] = L.color[s];
+                for (int e = L.adj_ptr[s]; e < L.adj_ptr[s + 1]; ++e) C.adj.push_back(c0 + L.adj[e]);
+                for (int e = L.fill_ptr[s]; e < L.fill_ptr[s + 1]; ++e) C.fill.push_back(c0 + L.fill[e]);
+                for (int e = L.pat_ptr[s]; e < L.pat_ptr[s + 1]; ++e) C.pat.push_back(c0 + L.pat[e]);
+                C.adj_ptr[c0 + s + 1] = (int)C.adj.size();
+                C.fill_ptr[c0 + s + 1] = (int)C.fill.size();
+                C.pat_ptr[c0 + s + 1] = (int)C.pat.size();
+            }
+        }
+        // processing order: colour by colour, systems in placement order
+        C.order.clear();
+        C.order.reserve(C.ncl);
+        C.color_ptr.assign(ncolors + 1, 0);
+        for (int c = 0; c < ncolors; ++c) {
+            for (int j = 0; j < alive; ++j) {
+                const LevelSymbolic& L = parts[F.sys[j]].levels[l];
+                if (c >= L.ncolors) continue;
+                for (int x = L.color_ptr[c]; x < L.color_ptr[c + 1]; ++x) C.order.push_back(off[j] + L.order[x]);
+            }
+            C.color_ptr[c + 1] = (int)C.order.size();
+        }
+        C.pos.assign(C.ncl, 0);
+        for (int x = 0; x < C.ncl; ++x) C.pos[C.order[x]] = x;
+        for (int j = 0; j < alive; ++j) parts[F.sys[j]].levels[l] = LevelSymbolic();
+    }
+}
+
 }  // namespace hs

@@ -39,4 +39,30 @@ struct Symbolic {
 int build_symbolic(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, int nx, int ny, int nz,
                    int leaf, Symbolic& out);
 
+// First level whose clusters all neighbour each other in processing order
+// (factored densely; every later level of the system is empty).  The root
+// level (one cluster) always qualifies.
+int complete_level(const Symbolic& S);
+
+// Several independent systems analysed as one block-diagonal system: a
+// forest whose trees are the systems' cluster trees, all with their leaves
+// on level 0.  Trees are placed by descending last level, so the systems
+// present on a level are a prefix of the placement and the children of
+// cluster p are 2p and 2p + 1 on every level.  Every per-system array
+// (colours, processing order, neighbours, fill partners, pattern) is the
+// system's own, shifted; the processing order of a colour lists the systems
+// in placement order.
+struct Forest {
+    int nsys = 0;
+    std::vector<int> sys;                  // placement -> system (caller's index)
+    std::vector<int> last;                 // per placement: last level present
+    std::vector<int> dense;                // per placement: complete level
+    std::vector<int64_t> row_off;          // per system (caller's order): first unknown, nsys + 1 entries
+    std::vector<std::vector<int>> cl_off;  // per level: first cluster of every present placement (+ end)
+};
+// parts[i] is system i's analysis (consumed).  With keep_empty_levels the
+// levels after a system's complete level are kept (empty clusters), else
+// each tree ends at its complete level.
+void combine_symbolic(std::vector<Symbolic>& parts, bool keep_empty_levels, Symbolic& out, Forest& F);
+
 }  // namespace hs
