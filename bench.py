@@ -17,7 +17,15 @@ algorithmic bytes per launch over its average launch time, HIP events on the
 library's stream inside the timed region) and the CPU oracle timed on a
 bounded sample of the same workload family on the host cores.
 
+Batched workload (--workload batch): 256 independent 2D upwind
+convection-diffusion systems (sides uniform in [64, 512], Peclet uniform in
+[1, 100], random direction; about 2.7e7 unknowns), one right-hand side each,
+GMRES(30) to 1e-10 per system.  Systems are factored together with
+hs_factor_batch in groups whose measured device footprint fits the memory
+budget; one step = every group's hs_factor_batch + hs_gmres + hs_free.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--side 64] [--forms both|mixed|fp64]
+                       [--workload poisson64|batch] [--batch-count 256] [--budget-gb 200]
 """
 
 import argparse
@@ -163,6 +171,110 @@ def run_form(P, torch, p, rp, ci, va, B, X, precision, steps, warmup, n):
     return rec
 
 
+def run_batch(args):
+    """The batched convection-diffusion workload, mixed and float64 forms."""
+    import torch
+
+    import paper_1712_07297_amd as P
+    from workloads import config4_batch
+
+    dev = torch.device("cuda:0")
+    probs = config4_batch(count=args.batch_count)
+    ns = [p.A.n for p in probs]
+    ntot = int(sum(ns))
+    sys_dev = [(torch.tensor(p.A.row_ptr, device=dev), torch.tensor(p.A.col_idx, device=dev),
+                torch.tensor(p.A.val, device=dev), p.dims) for p in probs]
+    rhs = [torch.tensor(np.ascontiguousarray(p.B[:, 0]), device=dev) for p in probs]
+    torch.cuda.synchronize()
+    budget = args.budget_gb * 1e9
+
+    def run_group(idx, precision):
+        F = P.Factor.batch([sys_dev[i] for i in idx], 1e-3, 64, symmetric=0, precision=precision)
+        B = torch.cat([rhs[i] for i in idx]).reshape(1, -1)
+        _, it, rel, ok = F.gmres(B, 1e-10, 300, 30)
+        info = F.info()
+        F.free()
+        return it, float(np.max(rel)), ok, info
+
+    out_forms = {}
+    forms = {"both": [P.HS_MIXED, P.HS_FP64], "mixed": [P.HS_MIXED], "fp64": [P.HS_FP64]}[args.forms]
+    for prec in forms:
+        name = "mixed" if prec == P.HS_MIXED else "fp64"
+        # footprint per unknown from a calibration group (also the warm-up)
+        cal = list(range(min(8, len(probs))))
+        _, _, _, info = run_group(cal, prec)
+        per_unknown = info.peak_device_bytes / sum(ns[i] for i in cal)
+        cap = max(1, int(budget / (1.25 * per_unknown)))
+        groups, cur, acc = [], [], 0
+        for i in range(len(probs)):
+            if cur and acc + ns[i] > cap:
+                groups.append(cur)
+                cur, acc = [], 0
+            cur.append(i)
+            acc += ns[i]
+        groups.append(cur)
+        print(f"batch {name}: {len(groups)} group(s), {per_unknown:.0f} B/unknown", file=sys.stderr, flush=True)
+        times, its, rels, oks, peaks = [], [], [], [], []
+        if args.profile:
+            P.profile_reset()
+            P.profile_enable(True)
+        for st in range(args.steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for g in groups:
+                it, rel, ok, info = run_group(g, prec)
+                its.append(it)
+                rels.append(rel)
+                oks.append(ok)
+                peaks.append(info.peak_device_bytes)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+            print(f"batch {name}: step {st + 1}/{args.steps} {times[-1]:.2f} s", file=sys.stderr, flush=True)
+        if args.profile:
+            P.profile_enable(False)
+            fams = ["gram", "pivot", "fill", "nbr", "schur", "schur_f32", "merge", "apply", "spmv", "dense",
+                    "host_symbolic", "host_plan", "host_upload", "host_alloc", "host_sync",
+                    "host_solve_plan"]
+            prof = {f: round(P.profile_read(f)["seconds"] / args.steps, 4) for f in fams}
+            print(f"batch {name}: seconds per step by family {json.dumps(prof)}", file=sys.stderr, flush=True)
+        dt = float(np.median(times))
+        out_forms[name] = {
+            "value": ntot / dt,
+            "ms_per_step": dt * 1e3,
+            "groups": len(groups),
+            "gmres_iterations_max": int(max(its)),
+            "relres_max": float(max(rels)),
+            "converged": bool(all(oks)) and max(rels) <= 1e-10,
+            "peak_device_gb": float(max(peaks)) / 1e9,
+        }
+    head_name = "mixed" if "mixed" in out_forms else "fp64"
+    head = out_forms[head_name]
+    out = {
+        "metric": "unknowns/s factor+solve to 1e-10 residual (mixed vs FP64)",
+        "value": head["value"],
+        "unit": "unknowns/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": 1,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 storage + bf16x3 MFMA Schur, f64 Krylov" if head_name == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"batch of {len(probs)} 2D upwind convection-diffusion systems (sides 64..512, N total {ntot}), "
+                        "leaf 64, eps 1e-3, hs_factor_batch + GMRES(30) to 1e-10 per system, 1 RHS each",
+            "form": head_name,
+            **{k: v for k, v in head.items() if k not in ("value", "ms_per_step")},
+        },
+    }
+    if "fp64" in out_forms and head_name != "fp64":
+        out["fp64"] = out_forms["fp64"]
+        out["mixed_over_fp64"] = head["value"] / out_forms["fp64"]["value"]
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -174,11 +286,18 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-side", type=int, default=24)
     ap.add_argument("--copy-probe", action="store_true", help="also run a plain device copy of known size (counter calibration)")
+    ap.add_argument("--workload", choices=["poisson64", "batch"], default="poisson64")
+    ap.add_argument("--batch-count", type=int, default=256)
+    ap.add_argument("--budget-gb", type=float, default=200.0, help="device memory per batched group")
+    ap.add_argument("--profile", action="store_true", help="batch workload: per-family times to stderr")
     args = ap.parse_args()
 
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1"}))
         sys.exit(2)
+    if args.workload == "batch":
+        run_batch(args)
+        return
 
     import torch
 

@@ -139,6 +139,10 @@ typedef struct hs_info {
     double factor_bytes;       /* bytes of the stored factor records */
     double symbolic_seconds;   /* host time of the symbolic analysis */
     double numeric_seconds;    /* wall time of the numeric factorization */
+    double device_bytes;       /* device memory the factorization holds now (records,
+                                  metadata, its copy of A, solve / Krylov workspaces) */
+    double peak_device_bytes;  /* largest device memory it has held (hs_factor's level
+                                  block stores and workspaces included) */
 } hs_info;
 
 /* ---- entry points -------------------------------------------------------- */
@@ -275,8 +279,9 @@ void hs_symbolic_free(hs_symbolic_t S);
  * every launch of a family is bracketed by two events; intervals are read
  * back at the next synchronisation of the library.  Host families (wall time
  * of the factorization's host steps, one count per step): "host_symbolic",
- * "host_plan", "host_upload", "host_alloc", "host_sync" (the per-level rank
- * read-back, which waits for the level's kernels).  hs_profile_read returns,
+ * "host_plan" (per-level work lists and offsets), "host_upload", "host_alloc", "host_sync" (the per-level rank
+ * read-back, which waits for the level's kernels, and the wait before the
+ * children's blocks are freed), "host_solve_plan".  hs_profile_read returns,
  * for one family since the last reset: launches, summed seconds, and the
  * algorithmic bytes and flops of those launches (counted from the sizes the
  * kernels worked on: for "schur" and "schur_f32", per cluster 2 f n_tot^2

@@ -82,6 +82,8 @@ class hs_info(ctypes.Structure):
         ("factor_bytes", ctypes.c_double),
         ("symbolic_seconds", ctypes.c_double),
         ("numeric_seconds", ctypes.c_double),
+        ("device_bytes", ctypes.c_double),
+        ("peak_device_bytes", ctypes.c_double),
     ]
 
 

@@ -67,36 +67,60 @@ static void dev_free(void* p) {
         (void)hipFree(p);
 }
 
+// Device bytes held by one factorization (current and largest so far).
+// Buffers allocated while a call works on a factorization are charged to it
+// (t_acct is set for the duration of the call).
+struct ByteAccount {
+    int64_t held = 0, peak = 0;
+};
+static thread_local ByteAccount* t_acct = nullptr;
+struct AcctScope {
+    ByteAccount* prev;
+    explicit AcctScope(ByteAccount* a) : prev(t_acct) { t_acct = a; }
+    ~AcctScope() { t_acct = prev; }
+};
+
 struct DevBuf {
     void* p = nullptr;
     size_t bytes = 0;
+    ByteAccount* acct = nullptr;
     DevBuf() = default;
     DevBuf(const DevBuf&) = delete;
     DevBuf& operator=(const DevBuf&) = delete;
-    DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes) {
+    DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes), acct(o.acct) {
         o.p = nullptr;
         o.bytes = 0;
+        o.acct = nullptr;
     }
     DevBuf& operator=(DevBuf&& o) noexcept {
         if (this != &o) {
             release();
             p = o.p;
             bytes = o.bytes;
+            acct = o.acct;
             o.p = nullptr;
             o.bytes = 0;
+            o.acct = nullptr;
         }
         return *this;
     }
     ~DevBuf() { release(); }
     void release() {
         dev_free(p);
+        if (acct) acct->held -= (int64_t)bytes;
         p = nullptr;
         bytes = 0;
+        acct = nullptr;
     }
     bool alloc(size_t n) {
         release();
         p = dev_alloc(n);
         bytes = p ? n : 0;
+        if (p && t_acct) {
+            acct = t_acct;
+            acct->held += (int64_t)n;
+            acct->peak = std::max(acct->peak, acct->held);
+        }
         return p != nullptr;
     }
     bool ensure(size_t n) { return bytes >= n ? true : alloc(n); }
@@ -134,11 +158,12 @@ enum ProfId {
     PF_GRAM = 0, PF_PIVOT, PF_FILL, PF_NBR, PF_SCHUR, PF_SCHUR_F32, PF_MERGE, PF_APPLY, PF_SPMV, PF_DENSE,
     // host wall time of the factorization: symbolic analysis, level planning,
     // metadata uploads, device allocations, per-level rank read-back
-    PF_H_SYMBOLIC, PF_H_PLAN, PF_H_UPLOAD, PF_H_ALLOC, PF_H_SYNC, PF_COUNT
+    PF_H_SYMBOLIC, PF_H_PLAN, PF_H_UPLOAD, PF_H_ALLOC, PF_H_SYNC, PF_H_SOLVE_PLAN, PF_COUNT
 };
 static ProfFamily g_prof[PF_COUNT] = {{"gram"}, {"pivot"}, {"fill"}, {"nbr"},   {"schur"}, {"schur_f32"},
                                       {"merge"}, {"apply"}, {"spmv"}, {"dense"},
-                                      {"host_symbolic"}, {"host_plan"}, {"host_upload"}, {"host_alloc"}, {"host_sync"}};
+                                      {"host_symbolic"}, {"host_plan"}, {"host_upload"}, {"host_alloc"}, {"host_sync"},
+                                      {"host_solve_plan"}};
 static bool g_prof_on = false;
 struct ProfPending {
     int fam;
@@ -213,12 +238,20 @@ static void prof_flush() {
 // float64 clusters with those factored densely on this level last.  The
 // factor lists (fac) leave the dense clusters out; the solve lists (sol) hold
 // every cluster of the colour.
+// Factor lists are cut into chunks whose per-cluster workspace stays within
+// WS_CHUNK_BYTES (launched one after the other, reusing the workspace).
+struct ListPlan {
+    int start = 0;                                 // first cluster within the type's list
+    size_t off_pre[3] = {0, 0, 0};                 // blob offsets: neighbour, fill, tile prefixes
+};
 struct ColourHost {
     int first = 0, n = 0;                          // slice of the processing order
     int n_t[2] = {0, 0};                           // clusters per type
     int nfac_t[2] = {0, 0};                        // of which factored by the colour kernels
-    size_t off_nbr_pre[2], off_fill_pre[2], off_tile_pre[2];
-    ColourDev fac[2], sol[2];
+    ListPlan sol_plan[2];
+    std::vector<ListPlan> fac_plan[2];
+    std::vector<ColourDev> fac[2];                 // factor lists (chunks)
+    ColourDev sol[2];
     const int64_t* part_off[2] = {nullptr, nullptr};  // [nbr entries + 1] in units of f
     int64_t part_total[2] = {0, 0};                // sum of f over the entries
 };
@@ -247,6 +280,9 @@ struct LevelData {
     const int* dev_pat_ptr = nullptr;  // final pattern on the device
     const int* dev_pat = nullptr;
     const int* dev_f32 = nullptr;      // per-cluster storage type on the device
+    const int* dev_pos = nullptr;      // processing positions on the device
+    DevBuf ids;                        // block ids / flags of the entries (launch_level_ids)
+    int64_t nadj = 0, nfill = 0;
     std::vector<ColourHost> colours;
     std::vector<int> order_host;                   // the colour slices by type (host copy of the work lists)
     std::vector<int64_t> seg;                      // [ncl+1] segment offsets
@@ -259,6 +295,7 @@ struct LevelData {
 }  // namespace hs
 
 struct hs_factor_s {
+    hs::ByteAccount acct;                 // first member: outlives every buffer below
     int64_t n = 0;
     hs_opts opts{};
     int symmetric = 1;
@@ -293,6 +330,9 @@ static const char* kVersion = "hs 0.1 (gfx950)";
 // Mixed form: levels with at most this many unknowns keep float64 storage
 // (default of hs_opts.coarse_fp64_dofs).
 constexpr int64_t MIXED_FP64_DOFS = 16384;
+// Per-cluster workspace of one factor launch at most (colours beyond it are
+// launched in chunks that reuse the workspace).
+constexpr int64_t WS_CHUNK_BYTES = int64_t(4) << 30;
 
 // =============================================================== validation
 
@@ -320,6 +360,8 @@ static int plan_level(hs_factor_s* F, int lvl, Blob& blob, std::vector<size_t>& 
     const std::vector<int>& m = LD.m;
     LD.ncl = ncl;
     LD.nblk = (int)S.pat.size();
+    LD.nadj = (int64_t)S.adj.size();
+    LD.nfill = (int64_t)S.fill.size();
     LD.max_m = 0;
     for (int c = 0; c < ncl; ++c)
         if (!LD.dense[c]) LD.max_m = std::max(LD.max_m, m[c]);
@@ -341,38 +383,18 @@ static int plan_level(hs_factor_s* F, int lvl, Blob& blob, std::vector<size_t>& 
             LD.blk_off[e] = place(cur, (int64_t)m[a] * m[S.pat[e]], LD.esz(a));
     LD.block_bytes = cur;
 
-    // per-cluster lists
-    std::vector<int> diag_blk(ncl), nbr_before, nbr_bsa, nbr_bas, ncap(ncl), fill_before, fill_bst, fill_bts;
+    // per-cluster lists (the block ids of every neighbour / fill entry and of
+    // all neighbour pairs are found on the device: launch_level_ids,
+    // launch_pair_blocks)
+    std::vector<int> ncap(ncl);
     std::vector<int64_t> pair_base(ncl), ws_off(ncl, 0);
     LD.rec_off.assign(ncl, 0);
-    nbr_before.resize(S.adj.size());
-    nbr_bsa.resize(S.adj.size());
-    nbr_bas.resize(S.adj.size());
-    fill_before.resize(S.fill.size());
-    fill_bst.resize(S.fill.size());
-    fill_bts.resize(S.fill.size());
-    // (the block ids of all neighbour pairs, sum of |n(s)|^2 entries, are
-    // found on the device: launch_pair_blocks)
-    auto bid = [&](int a, int b) { return S.block_id(a, b); };
     int64_t pp = 0, roff = 0;
     int max_nf = 0;
     for (int s = 0; s < ncl; ++s) {
-        diag_blk[s] = bid(s, s);
         int cap = 0;
-        for (int e = S.adj_ptr[s]; e < S.adj_ptr[s + 1]; ++e) {
-            int a = S.adj[e];
-            nbr_before[e] = S.pos[a] < S.pos[s];
-            nbr_bsa[e] = bid(s, a);
-            nbr_bas[e] = bid(a, s);
-            cap += m[a];
-        }
+        for (int e = S.adj_ptr[s]; e < S.adj_ptr[s + 1]; ++e) cap += m[S.adj[e]];
         ncap[s] = cap;
-        for (int e = S.fill_ptr[s]; e < S.fill_ptr[s + 1]; ++e) {
-            int t = S.fill[e];
-            fill_before[e] = S.pos[t] < S.pos[s];
-            fill_bst[e] = bid(s, t);
-            fill_bts[e] = bid(t, s);
-        }
         max_nf = std::max(max_nf, S.fill_ptr[s + 1] - S.fill_ptr[s]);
         pair_base[s] = pp;
         const int64_t nb = S.adj_ptr[s + 1] - S.adj_ptr[s];
@@ -394,7 +416,12 @@ static int plan_level(hs_factor_s* F, int lvl, Blob& blob, std::vector<size_t>& 
         std::vector<int> np, fp;
         std::vector<int64_t> tp;
     };
-    std::vector<std::array<Pre, 2>> pres(S.ncolors);
+    struct ListPre {
+        int start;
+        Pre pre;
+    };
+    std::vector<std::array<ListPre, 2>> spres(S.ncolors);
+    std::vector<std::array<std::vector<ListPre>, 2>> fpres(S.ncolors);
     for (int c = 0; c < S.ncolors; ++c) {
         ColourHost& CH = LD.colours[c];
         CH.first = S.color_ptr[c];
@@ -412,34 +439,29 @@ static int plan_level(hs_factor_s* F, int lvl, Blob& blob, std::vector<size_t>& 
             CH.n_t[t]++;
             if (!LD.dense[s]) CH.nfac_t[t]++;
         }
-        int64_t wso = 0;
         int base = CH.first;
         for (int t = 0; t < 2; ++t) {
-            Pre& P = pres[c][t];
             const int nt = CH.n_t[t], nf = CH.nfac_t[t];
-            P.np.assign(nt + 1, 0);
-            P.fp.assign(nt + 1, 0);
-            P.tp.assign(nt + 1, 0);
-            int max_m_f = 0, max_nm_f = 0, max_m_s = 0, max_nm_s = 0;
-            for (int i = 0; i < nt; ++i) {
-                const int s = order[base + i];
-                P.np[i + 1] = P.np[i] + (S.adj_ptr[s + 1] - S.adj_ptr[s]);
-                P.fp[i + 1] = P.fp[i] + (S.fill_ptr[s + 1] - S.fill_ptr[s]);
-                const int64_t tpr = (ncap[s] + SCHUR_T - 1) / SCHUR_T;
-                P.tp[i + 1] = P.tp[i] + (m[s] > 0 ? tpr * tpr : 0);
-                int nm = 0;
-                for (int e = S.adj_ptr[s]; e < S.adj_ptr[s + 1]; ++e) nm = std::max(nm, m[S.adj[e]]);
-                for (int e = S.fill_ptr[s]; e < S.fill_ptr[s + 1]; ++e) nm = std::max(nm, m[S.fill[e]]);
-                max_m_s = std::max(max_m_s, m[s]);
-                max_nm_s = std::max(max_nm_s, nm);
-                if (i < nf) {
-                    max_m_f = std::max(max_m_f, m[s]);
-                    max_nm_f = std::max(max_nm_f, nm);
-                    ws_off[s] = wso;
-                    wso += slots * (int64_t)m[s] * m[s];
+            // prefix arrays and maxima of the list entries [i0, i1)
+            auto make = [&](int i0, int i1, ColourDev& D, Pre& P) {
+                const int n = i1 - i0;
+                P.np.assign(n + 1, 0);
+                P.fp.assign(n + 1, 0);
+                P.tp.assign(n + 1, 0);
+                int mm = 0, mn = 0;
+                for (int i = 0; i < n; ++i) {
+                    const int s = order[base + i0 + i];
+                    P.np[i + 1] = P.np[i] + (S.adj_ptr[s + 1] - S.adj_ptr[s]);
+                    P.fp[i + 1] = P.fp[i] + (S.fill_ptr[s + 1] - S.fill_ptr[s]);
+                    const int64_t tpr = (ncap[s] + SCHUR_T - 1) / SCHUR_T;
+                    P.tp[i + 1] = P.tp[i] + (m[s] > 0 ? tpr * tpr : 0);
+                    int nm = 0;
+                    for (int e = S.adj_ptr[s]; e < S.adj_ptr[s + 1]; ++e) nm = std::max(nm, m[S.adj[e]]);
+                    for (int e = S.fill_ptr[s]; e < S.fill_ptr[s + 1]; ++e) nm = std::max(nm, m[S.fill[e]]);
+                    mm = std::max(mm, m[s]);
+                    mn = std::max(mn, nm);
                 }
-            }
-            auto fillc = [&](ColourDev& D, int n, int mm, int mn) {
+                D = ColourDev();
                 D.n = n;
                 D.nbr_total = P.np[n];
                 D.fill_total = P.fp[n];
@@ -450,11 +472,30 @@ static int plan_level(hs_factor_s* F, int lvl, Blob& blob, std::vector<size_t>& 
                 D.panels = (mn + pw - 1) / pw;
                 D.f32 = t == 0;
             };
-            fillc(CH.fac[t], nf, max_m_f, max_nm_f);
-            fillc(CH.sol[t], nt, max_m_s, max_nm_s);
+            spres[c][t].start = 0;
+            make(0, nt, CH.sol[t], spres[c][t].pre);
+            // factor chunks: workspace offsets restart in every chunk
+            CH.fac[t].clear();
+            int i0 = 0;
+            while (i0 < nf) {
+                int64_t wso = 0;
+                int i1 = i0;
+                while (i1 < nf) {
+                    const int s = order[base + i1];
+                    const int64_t need = slots * (int64_t)m[s] * m[s];
+                    if (i1 > i0 && (wso + need) * (int64_t)sizeof(double) > WS_CHUNK_BYTES) break;
+                    ws_off[s] = wso;
+                    wso += need;
+                    ++i1;
+                }
+                ws_max = std::max(ws_max, wso);
+                fpres[c][t].push_back(ListPre{i0, Pre()});
+                CH.fac[t].emplace_back();
+                make(i0, i1, CH.fac[t].back(), fpres[c][t].back().pre);
+                i0 = i1;
+            }
             base += nt;
         }
-        ws_max = std::max(ws_max, wso);
     }
     LD.ws_elems = ws_max;
 
@@ -464,20 +505,20 @@ static int plan_level(hs_factor_s* F, int lvl, Blob& blob, std::vector<size_t>& 
     offs.push_back(blob.add(m));                 // 1 k (initialised to m)
     offs.push_back(blob.add(std::vector<int>(ncl, 0)));  // 2 flag
     offs.push_back(blob.add(LD.blk_off));        // 3
-    offs.push_back(blob.add(diag_blk));          // 4
+    offs.push_back(blob.add(S.pos));             // 4 processing position
     offs.push_back(blob.add(S.adj_ptr));         // 5
     offs.push_back(blob.add(S.adj));             // 6
-    offs.push_back(blob.add(nbr_before));        // 7
-    offs.push_back(blob.add(nbr_bsa));           // 8
-    offs.push_back(blob.add(nbr_bas));           // 9
+    offs.push_back(0);                           // 7-9 (LD.ids)
+    offs.push_back(0);
+    offs.push_back(0);
     offs.push_back(blob.add(std::vector<int>(S.adj.size(), 0)));  // 10 nbr_noff
     offs.push_back(blob.add(std::vector<int>(ncl, 0)));           // 11 ntot
     offs.push_back(blob.add(ncap));              // 12
     offs.push_back(blob.add(S.fill_ptr));        // 13
     offs.push_back(blob.add(S.fill));            // 14
-    offs.push_back(blob.add(fill_before));       // 15
-    offs.push_back(blob.add(fill_bst));          // 16
-    offs.push_back(blob.add(fill_bts));          // 17
+    offs.push_back(0);                           // 15-17 (LD.ids)
+    offs.push_back(0);
+    offs.push_back(0);
     offs.push_back(blob.add(pair_base));         // 18
     offs.push_back(blob.add(std::vector<int>()));  // 19 (pair block ids: LD.pairs)
     offs.push_back(blob.add(LD.rec_off));        // 20
@@ -487,12 +528,18 @@ static int plan_level(hs_factor_s* F, int lvl, Blob& blob, std::vector<size_t>& 
     offs.push_back(blob.add(order));             // 24 colour slices by type (the work lists)
     LD.order_host = order;
     offs.push_back(blob.add(LD.f32));            // 25 per-cluster storage type
+    auto add_pre = [&](ListPlan& L, const ListPre& lp) {
+        L.start = lp.start;
+        L.off_pre[0] = blob.add(lp.pre.np);
+        L.off_pre[1] = blob.add(lp.pre.fp);
+        L.off_pre[2] = blob.add(lp.pre.tp);
+    };
     for (int c = 0; c < S.ncolors; ++c) {
         ColourHost& CH = LD.colours[c];
         for (int t = 0; t < 2; ++t) {
-            CH.off_nbr_pre[t] = blob.add(pres[c][t].np);
-            CH.off_fill_pre[t] = blob.add(pres[c][t].fp);
-            CH.off_tile_pre[t] = blob.add(pres[c][t].tp);
+            add_pre(CH.sol_plan[t], spres[c][t]);
+            CH.fac_plan[t].assign(fpres[c][t].size(), ListPlan());
+            for (size_t q = 0; q < fpres[c][t].size(); ++q) add_pre(CH.fac_plan[t][q], fpres[c][t][q]);
         }
     }
     return HS_OK;
@@ -512,20 +559,24 @@ static void bind_level(LevelData& LD, const std::vector<size_t>& offs, const hs_
     D.flag = (int*)P(2);
     D.blk_off = (const int64_t*)P(3);
     D.blocks = LD.blocks.as<double>();
-    D.diag_blk = (const int*)P(4);
+    // block ids and processed-before flags: [diag | nbr_before, bsa, bas | fill_before, bst, bts]
+    int* ids = LD.ids.as<int>();
+    const int64_t na = LD.nadj, nf = LD.nfill;
+    D.diag_blk = ids;
     D.nbr_ptr = (const int*)P(5);
     D.nbr_id = (const int*)P(6);
-    D.nbr_before = (const int*)P(7);
-    D.nbr_bsa = (const int*)P(8);
-    D.nbr_bas = (const int*)P(9);
+    D.nbr_before = ids + LD.ncl;
+    D.nbr_bsa = ids + LD.ncl + na;
+    D.nbr_bas = ids + LD.ncl + 2 * na;
     D.nbr_noff = (int*)P(10);
     D.ntot = (int*)P(11);
     D.ncap = (const int*)P(12);
     D.fill_ptr = (const int*)P(13);
     D.fill_id = (const int*)P(14);
-    D.fill_before = (const int*)P(15);
-    D.fill_bst = (const int*)P(16);
-    D.fill_bts = (const int*)P(17);
+    D.fill_before = ids + LD.ncl + 3 * na;
+    D.fill_bst = ids + LD.ncl + 3 * na + nf;
+    D.fill_bts = ids + LD.ncl + 3 * na + 2 * nf;
+    LD.dev_pos = (const int*)P(4);
     D.pair_base = (const int64_t*)P(18);
     D.pair_blk = LD.pairs.as<int>();
     D.rec_off = (const int64_t*)P(20);
@@ -536,15 +587,17 @@ static void bind_level(LevelData& LD, const std::vector<size_t>& offs, const hs_
     LD.dev_pat = (const int*)P(23);
     LD.dev_f32 = (const int*)P(25);
     const int* order = (const int*)P(24);
+    auto bind = [&](ColourDev& Cd, const ListPlan& L, int first) {
+        Cd.clist = order + first + L.start;
+        Cd.nbr_pre = (const int*)(base + L.off_pre[0]);
+        Cd.fill_pre = (const int*)(base + L.off_pre[1]);
+        Cd.tile_pre = (const int64_t*)(base + L.off_pre[2]);
+    };
     for (auto& CH : LD.colours) {
         int first = CH.first;
         for (int t = 0; t < 2; ++t) {
-            for (ColourDev* Cd : {&CH.fac[t], &CH.sol[t]}) {
-                Cd->clist = order + first;
-                Cd->nbr_pre = (const int*)(base + CH.off_nbr_pre[t]);
-                Cd->fill_pre = (const int*)(base + CH.off_fill_pre[t]);
-                Cd->tile_pre = (const int64_t*)(base + CH.off_tile_pre[t]);
-            }
+            bind(CH.sol[t], CH.sol_plan[t], first);
+            for (size_t q = 0; q < CH.fac[t].size(); ++q) bind(CH.fac[t][q], CH.fac_plan[t][q], first);
             first += CH.n_t[t];
         }
     }
@@ -883,12 +936,19 @@ static int factor_impl(hs_factor_s* F, int nsys, const hs_csr* A, const hs_geome
             if (!LD.rec.alloc(LD.rec_bytes)) return fail(HS_ERR_NOMEM, "factor records");
             if (!F->ws.ensure(LD.ws_elems * sizeof(double))) return fail(HS_ERR_NOMEM, "workspace");
             if (!LD.pairs.alloc((LD.npairs + 1) * sizeof(int))) return fail(HS_ERR_NOMEM, "neighbour pairs");
+            if (!LD.ids.alloc((LD.ncl + 3 * (LD.nadj + LD.nfill) + 1) * sizeof(int)))
+                return fail(HS_ERR_NOMEM, "level block ids");
         }
         {
             HostScope hs_(PF_H_UPLOAD);
             HIP_TRY(hipMemcpyAsync(LD.meta.p, blob.data.data(), blob.data.size(), hipMemcpyHostToDevice, st));
         }
         bind_level(LD, offs, F);
+        launch_level_ids(S.ncl, LD.dev.nbr_ptr, LD.dev.nbr_id, LD.dev.fill_ptr, LD.dev.fill_id, LD.dev_pos,
+                         LD.dev_pat_ptr, LD.dev_pat, LD.ids.as<int>(), LD.ids.as<int>() + LD.ncl,
+                         LD.ids.as<int>() + LD.ncl + LD.nadj, LD.ids.as<int>() + LD.ncl + 2 * LD.nadj,
+                         LD.ids.as<int>() + LD.ncl + 3 * LD.nadj, LD.ids.as<int>() + LD.ncl + 3 * LD.nadj + LD.nfill,
+                         LD.ids.as<int>() + LD.ncl + 3 * LD.nadj + 2 * LD.nfill, st);
         launch_pair_blocks(S.ncl, LD.dev.nbr_ptr, LD.dev.nbr_id, LD.dev_pat_ptr, LD.dev_pat, LD.dev.pair_base,
                            LD.pairs.as<int>(), st);
         launch_fill_zero(LD.blocks.p, LD.block_bytes, st);
@@ -898,31 +958,14 @@ static int factor_impl(hs_factor_s* F, int nsys, const hs_csr* A, const hs_geome
                              LD.dev.blk_off, LD.blocks.p, LD.dev_f32, st);
         } else {
             // parent blocks from the children's coarse blocks
-            const LevelSymbolic& PS = F->sym.levels[lvl - 1];
-            HostScope hs_(PF_H_PLAN);
-            std::vector<int> nb_row(LD.nblk), nb_col(LD.nblk), src4(4 * (size_t)LD.nblk);
-            for (int P = 0; P < S.ncl; ++P)
-                for (int e = S.pat_ptr[P]; e < S.pat_ptr[P + 1]; ++e) {
-                    const int Q = S.pat[e];
-                    nb_row[e] = P;
-                    nb_col[e] = Q;
-                    for (int h = 0; h < 4; ++h) {
-                        const int a = 2 * P + (h >> 1), c = 2 * Q + (h & 1);
-                        src4[4 * (size_t)e + h] = (a < PS.ncl && c < PS.ncl) ? PS.block_id(a, c) : -1;
-                    }
-                }
-            Blob mb;
-            size_t o_r = mb.add(nb_row), o_c = mb.add(nb_col), o_s = mb.add(src4);
-            DevBuf mbuf;
-            if (!mbuf.alloc(mb.data.size())) return fail(HS_ERR_NOMEM, "merge metadata");
-            HIP_TRY(hipMemcpyAsync(mbuf.p, mb.data.data(), mb.data.size(), hipMemcpyHostToDevice, st));
             {
                 ProfScope ps(PF_MERGE, st);
-                launch_merge(LD.nblk, (const int*)(mbuf.as<char>() + o_r), (const int*)(mbuf.as<char>() + o_c),
-                             (const int*)(mbuf.as<char>() + o_s), prev->dev.k, prev->dev.m, prev->dev.blk_off,
-                             prev->blocks.p, prev->dev_f32, LD.dev.m, LD.dev.blk_off, LD.blocks.p, LD.dev_f32, st);
+                launch_merge(LD.nblk, LD.dev_pat_ptr, LD.dev_pat, LD.ncl, prev->dev_pat_ptr, prev->dev_pat, prev->ncl,
+                             prev->dev.k, prev->dev.m, prev->dev.blk_off, prev->blocks.p, prev->dev_f32, LD.dev.m,
+                             LD.dev.blk_off, LD.blocks.p, LD.dev_f32, st);
             }
-            HIP_TRY(hipStreamSynchronize(st));  // merge metadata and the children's blocks are freed below
+            HostScope hs_(PF_H_SYNC);
+            HIP_TRY(hipStreamSynchronize(st));  // the children's blocks are freed below
             prev->blocks.release();
             prev->dev.blocks = nullptr;
         }
@@ -937,8 +980,8 @@ static int factor_impl(hs_factor_s* F, int nsys, const hs_csr* A, const hs_geome
             if (rc) return rc;
         }
         for (auto& CH : LD.colours)
-            for (int t = 0; t < 2; ++t) {
-                const ColourDev& C = CH.fac[t];
+            for (int t = 0; t < 2; ++t)
+                for (const ColourDev& C : CH.fac[t]) {
                 if (C.n == 0) continue;
                 if (F->opts.eps > 0.0 && C.fill_total > 0) {
                     ProfScope ps(PF_GRAM, st);
@@ -1037,6 +1080,7 @@ static int factor_impl(hs_factor_s* F, int nsys, const hs_csr* A, const hs_geome
 
     // ---- solve plan (needs every rank): segments, part offsets per colour and type
     double rec_bytes = 0.0, apply_flops = 0.0;
+    HostScope hs_solve(PF_H_SOLVE_PLAN);
     for (int lvl = 0; lvl < nlev; ++lvl) {
         LevelData& LD = F->levels[lvl];
         const LevelSymbolic& S = F->sym.levels[lvl];
@@ -1510,6 +1554,7 @@ static int factor_entry(int32_t nsys, const hs_csr* A, const hs_geometry* geom, 
     F->opts = *opts;
     F->info.breakdown_level = -1;
     F->info.breakdown_cluster = -1;
+    AcctScope scope(&F->acct);
     rc = factor_impl(F.get(), nsys, A, geom, (hipStream_t)hip_stream);
     if (rc < 0) return rc;
     *F_out = F.release();
@@ -1536,6 +1581,7 @@ int hs_solve(hs_factor_t F, int64_t nrhs, const double* B, int64_t ldb, double* 
     g_err.clear();
     if (!F || !B || !X || nrhs < 1 || nrhs > 64 || ldb < F->n || ldx < F->n) return fail(HS_ERR_ARG, "bad argument");
     if (B == X && ldb != ldx) return fail(HS_ERR_ARG, "aliased B and X need equal leading dimensions");
+    AcctScope scope(&F->acct);
     return solve_impl(F, (int)nrhs, B, ldb, X, ldx, (hipStream_t)hip_stream);
 }
 
@@ -1544,6 +1590,7 @@ int hs_pcg(hs_factor_t F, int64_t nrhs, const double* B, int64_t ldb, double* X,
     g_err.clear();
     if (!F || !B || !X || nrhs < 1 || nrhs > 64 || ldb < F->n || ldx < F->n || !(tol >= 0) || maxit < 0 || B == X)
         return fail(HS_ERR_ARG, "bad argument");
+    AcctScope scope(&F->acct);
     return pcg_impl(F, (int)nrhs, B, ldb, X, ldx, tol, maxit, iters_out, relres_out, (hipStream_t)hip_stream);
 }
 
@@ -1553,12 +1600,15 @@ int hs_gmres(hs_factor_t F, int64_t nrhs, const double* B, int64_t ldb, double* 
     if (!F || !B || !X || nrhs < 1 || ldb < F->n || ldx < F->n || !(tol >= 0) || maxit < 0 || restart < 1 ||
         restart > 1000 || B == X)
         return fail(HS_ERR_ARG, "bad argument");
+    AcctScope scope(&F->acct);
     return gmres_impl(F, (int)nrhs, B, ldb, X, ldx, tol, maxit, restart, iters_out, relres_out,
                       (hipStream_t)hip_stream);
 }
 
 int hs_factor_info(hs_factor_t F, hs_info* out) {
     if (!F || !out) return fail(HS_ERR_ARG, "null argument");
+    F->info.device_bytes = (double)F->acct.held;
+    F->info.peak_device_bytes = (double)F->acct.peak;
     *out = F->info;
     return HS_OK;
 }

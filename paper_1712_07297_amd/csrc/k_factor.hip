@@ -270,7 +270,7 @@ __device__ void wg_complement(PX X, int M, int K, PV V, int ldv, PT tau_sh, doub
 // LDS when the colour's largest cluster fits (lds_m), else in the cluster's
 // L2-resident workspace; every dense step below reuses it in turn.
 template <bool INLDS, class T>
-__global__ void __launch_bounds__(WG) k_pivot(LevelDev L, const int* __restrict__ clist) {
+__global__ void __launch_bounds__(WG, 2) k_pivot(LevelDev L, const int* __restrict__ clist) {
     extern __shared__ double dyn[];  // INLDS: M * M doubles (largest M of the colour); else 12 x 256
     __shared__ GemmSmem sm;
     __shared__ double red[16];
@@ -779,21 +779,35 @@ void launch_assemble0(int64_t n, const int64_t* row_ptr, const int32_t* col_idx,
                        cluster_of, local_of, m, pat_ptr, pat, blk_off, blocks, f32);
 }
 
+// Position of block (a, b) in a level's pattern (rows sorted), -1 if absent.
+__device__ inline int pat_find(const int* __restrict__ pat_ptr, const int* __restrict__ pat, int a, int b) {
+    int lo = pat_ptr[a], hi = pat_ptr[a + 1];
+    const int end = hi;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (pat[mid] < b)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return (lo < end && pat[lo] == b) ? lo : -1;
+}
+
 // Parent block (P, Q) = [[B(l_P, l_Q), B(l_P, r_Q)], [B(r_P, l_Q), B(r_P, r_Q)]]
 // of the children's coarse blocks (Alg. 1 "Extract A_c").
 template <class TS, class TD>
-__device__ void merge_block(int b, const int* __restrict__ nb_row, const int* __restrict__ nb_col,
-                            const int* __restrict__ src4, const int* __restrict__ k_prev,
+__device__ void merge_block(int b, int P, int Q, const int* __restrict__ pat_ptr_prev,
+                            const int* __restrict__ pat_prev, int ncl_prev, const int* __restrict__ k_prev,
                             const int* __restrict__ m_prev, const int64_t* __restrict__ blk_off_prev,
                             const TS* __restrict__ blocks_prev, const int* __restrict__ m_next,
                             const int64_t* __restrict__ blk_off_next, TD* __restrict__ blocks_next) {
-    const int P = nb_row[b], Q = nb_col[b];
     const int ldn = m_next[P];
     TD* dst = blocks_next + blk_off_next[b];
     for (int h = 0; h < 4; ++h) {
-        const int src = src4[4 * b + h];
-        if (src < 0) continue;
         const int a = 2 * P + (h >> 1), c = 2 * Q + (h & 1);
+        if (a >= ncl_prev || c >= ncl_prev) continue;
+        const int src = pat_find(pat_ptr_prev, pat_prev, a, c);
+        if (src < 0) continue;
         const int roff = (h >> 1) ? k_prev[2 * P] : 0;
         const int coff = (h & 1) ? k_prev[2 * Q] : 0;
         const int ka = k_prev[a], kc = k_prev[c];
@@ -806,20 +820,30 @@ __device__ void merge_block(int b, const int* __restrict__ nb_row, const int* __
     }
 }
 
-// Element types per block from the clusters (a system's children and
-// parent may differ: float32 below, float64 from the level where it stops).
-__global__ void k_merge(const int* __restrict__ nb_row, const int* __restrict__ nb_col, const int* __restrict__ src4,
+// One workgroup per parent block; its row P by binary search over the
+// pattern's row pointers.  Element types per cluster on either side (a
+// system's children and parent may differ).
+__global__ void k_merge(const int* __restrict__ pat_ptr_next, const int* __restrict__ pat_next, int ncl_next,
+                        const int* __restrict__ pat_ptr_prev, const int* __restrict__ pat_prev, int ncl_prev,
                         const int* __restrict__ k_prev, const int* __restrict__ m_prev,
                         const int64_t* __restrict__ blk_off_prev, const void* __restrict__ blocks_prev,
                         const int* __restrict__ f32_prev, const int* __restrict__ m_next,
                         const int64_t* __restrict__ blk_off_next, void* __restrict__ blocks_next,
                         const int* __restrict__ f32_next) {
     const int b = blockIdx.x;
-    const int P = nb_row[b];
+    int lo = 0, hi = ncl_next;  // last P with pat_ptr_next[P] <= b
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (pat_ptr_next[mid] <= b)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    const int P = lo, Q = pat_next[b];
     const bool s32 = f32_prev[2 * P] != 0, d32 = f32_next[P] != 0;
-#define HS_MERGE(TS, TD)                                                                                           \
-    merge_block<TS, TD>(b, nb_row, nb_col, src4, k_prev, m_prev, blk_off_prev, static_cast<const TS*>(blocks_prev), \
-                        m_next, blk_off_next, static_cast<TD*>(blocks_next))
+#define HS_MERGE(TS, TD)                                                                                             \
+    merge_block<TS, TD>(b, P, Q, pat_ptr_prev, pat_prev, ncl_prev, k_prev, m_prev, blk_off_prev,                      \
+                        static_cast<const TS*>(blocks_prev), m_next, blk_off_next, static_cast<TD*>(blocks_next))
     if (s32 && d32)
         HS_MERGE(float, float);
     else if (s32)
@@ -831,13 +855,47 @@ __global__ void k_merge(const int* __restrict__ nb_row, const int* __restrict__ 
 #undef HS_MERGE
 }
 
-void launch_merge(int nblk_next, const int* nb_row, const int* nb_col, const int* src4, const int* k_prev,
-                  const int* m_prev, const int64_t* blk_off_prev, const void* blocks_prev, const int* f32_prev,
-                  const int* m_next, const int64_t* blk_off_next, void* blocks_next, const int* f32_next,
-                  hipStream_t st) {
+void launch_merge(int nblk_next, const int* pat_ptr_next, const int* pat_next, int ncl_next,
+                  const int* pat_ptr_prev, const int* pat_prev, int ncl_prev, const int* k_prev, const int* m_prev,
+                  const int64_t* blk_off_prev, const void* blocks_prev, const int* f32_prev, const int* m_next,
+                  const int64_t* blk_off_next, void* blocks_next, const int* f32_next, hipStream_t st) {
     if (nblk_next == 0) return;
-    hipLaunchKernelGGL(k_merge, dim3(nblk_next), dim3(256), 0, st, nb_row, nb_col, src4, k_prev, m_prev, blk_off_prev,
-                       blocks_prev, f32_prev, m_next, blk_off_next, blocks_next, f32_next);
+    hipLaunchKernelGGL(k_merge, dim3(nblk_next), dim3(256), 0, st, pat_ptr_next, pat_next, ncl_next, pat_ptr_prev,
+                       pat_prev, ncl_prev, k_prev, m_prev, blk_off_prev, blocks_prev, f32_prev, m_next, blk_off_next,
+                       blocks_next, f32_next);
+}
+
+// Block ids of (s, s), of (s, a) and (a, s) for every neighbour a and of
+// (s, t) and (t, s) for every fill partner t, and whether a / t is processed
+// before s; one workgroup per cluster.
+__global__ void k_level_ids(const int* __restrict__ nbr_ptr, const int* __restrict__ nbr_id,
+                            const int* __restrict__ fill_ptr, const int* __restrict__ fill_id,
+                            const int* __restrict__ pos, const int* __restrict__ pat_ptr,
+                            const int* __restrict__ pat, int* __restrict__ diag_blk, int* __restrict__ nbr_before,
+                            int* __restrict__ nbr_bsa, int* __restrict__ nbr_bas, int* __restrict__ fill_before,
+                            int* __restrict__ fill_bst, int* __restrict__ fill_bts) {
+    const int s = blockIdx.x;
+    if (threadIdx.x == 0) diag_blk[s] = pat_find(pat_ptr, pat, s, s);
+    for (int e = nbr_ptr[s] + threadIdx.x; e < nbr_ptr[s + 1]; e += blockDim.x) {
+        const int a = nbr_id[e];
+        nbr_before[e] = pos[a] < pos[s];
+        nbr_bsa[e] = pat_find(pat_ptr, pat, s, a);
+        nbr_bas[e] = pat_find(pat_ptr, pat, a, s);
+    }
+    for (int e = fill_ptr[s] + threadIdx.x; e < fill_ptr[s + 1]; e += blockDim.x) {
+        const int t = fill_id[e];
+        fill_before[e] = pos[t] < pos[s];
+        fill_bst[e] = pat_find(pat_ptr, pat, s, t);
+        fill_bts[e] = pat_find(pat_ptr, pat, t, s);
+    }
+}
+
+void launch_level_ids(int ncl, const int* nbr_ptr, const int* nbr_id, const int* fill_ptr, const int* fill_id,
+                      const int* pos, const int* pat_ptr, const int* pat, int* diag_blk, int* nbr_before,
+                      int* nbr_bsa, int* nbr_bas, int* fill_before, int* fill_bst, int* fill_bts, hipStream_t st) {
+    if (ncl == 0) return;
+    hipLaunchKernelGGL(k_level_ids, dim3(ncl), dim3(64), 0, st, nbr_ptr, nbr_id, fill_ptr, fill_id, pos, pat_ptr, pat,
+                       diag_blk, nbr_before, nbr_bsa, nbr_bas, fill_before, fill_bst, fill_bts);
 }
 
 __global__ void k_pair_blocks(const int* __restrict__ nbr_ptr, const int* __restrict__ nbr_id,

@@ -43,13 +43,20 @@ void launch_schur(const LevelDev& L, const ColourDev& C, hipStream_t st);
 void launch_assemble0(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, const double* val,
                       const int* cluster_of, const int* local_of, const int* m, const int* pat_ptr, const int* pat,
                       const int64_t* blk_off, void* blocks, const int* f32, hipStream_t st);
-// Gather the coarse blocks of the children into the parent level.  For every
-// parent block: src[4] child block ids (-1 = absent) for (l,l),(l,r),(r,l),(r,r).
-// Element types per cluster on either side (f32_prev / f32_next).
-void launch_merge(int nblk_next, const int* nb_row, const int* nb_col, const int* src4, const int* k_prev,
-                  const int* m_prev, const int64_t* blk_off_prev, const void* blocks_prev, const int* f32_prev,
-                  const int* m_next, const int64_t* blk_off_next, void* blocks_next, const int* f32_next,
-                  hipStream_t st);
+// Gather the coarse blocks of the children into the parent level: parent
+// block b = (P, Q) of the next level's pattern takes the children's blocks
+// (2P + i, 2Q + j) found in the previous level's pattern.  Element types per
+// cluster on either side (f32_prev / f32_next).
+void launch_merge(int nblk_next, const int* pat_ptr_next, const int* pat_next, int ncl_next,
+                  const int* pat_ptr_prev, const int* pat_prev, int ncl_prev, const int* k_prev, const int* m_prev,
+                  const int64_t* blk_off_prev, const void* blocks_prev, const int* f32_prev, const int* m_next,
+                  const int64_t* blk_off_next, void* blocks_next, const int* f32_next, hipStream_t st);
+// Per level: block ids of (s, s), (s, a), (a, s), (s, t), (t, s) for the
+// neighbours a and fill partners t of every cluster, and their
+// processed-before flags (pos = processing position).
+void launch_level_ids(int ncl, const int* nbr_ptr, const int* nbr_id, const int* fill_ptr, const int* fill_id,
+                      const int* pos, const int* pat_ptr, const int* pat, int* diag_blk, int* nbr_before,
+                      int* nbr_bsa, int* nbr_bas, int* fill_before, int* fill_bst, int* fill_bts, hipStream_t st);
 // Zero `bytes` bytes (a multiple of 4) from p.
 void launch_fill_zero(void* p, int64_t bytes, hipStream_t st);
 // System i's CSR copied into a block-diagonal one: its n_i + 1 row pointers
