@@ -34,8 +34,10 @@
  *     HIP stream passed in (NULL = the default stream); functions that return
  *     host-visible results (ranks, iteration counts) synchronise that stream.
  *   - The library allocates its own device memory (factor storage,
- *     workspaces) with hipMalloc unless hs_set_allocator() installs another
- *     allocator.  It never frees or writes caller buffers other than the
+ *     workspaces) with HIP's stream-ordered allocator on the stream of the
+ *     call (the device's default memory pool, whose release threshold it
+ *     raises so that freed memory is kept for reuse rather than unmapped),
+ *     unless hs_set_allocator() installs another allocator.  It never frees or writes caller buffers other than the
  *     documented outputs.
  */
 #ifndef HS_H_
@@ -292,6 +294,90 @@ int hs_profile_read(const char* family, int64_t* launches, double* seconds, doub
 
 /* Release F and all its device memory.  NULL is ignored. */
 void hs_free(hs_factor_t F);
+
+/* ---- serving ------------------------------------------------------------ */
+
+/* A request loop for a stream of solve requests on one GPU (the factorization
+ * of Sec. 2 as preconditioner of CG / GMRES, Sec. 5), with continuous
+ * batching: worker threads, each with its own HIP stream, take the oldest
+ * waiting request and every other waiting request that fits with it, as long
+ * as the device memory they need fits under the cap:
+ *   - requests whose operator (op_key) has a resident factorization reuse it
+ *     (only the Krylov solve runs);
+ *   - new operators of the batch are factored together (hs_factor_batch),
+ *     and the resulting factorization stays resident for later requests
+ *     until it is evicted (least recently used, only when idle, only when
+ *     memory is needed);
+ *   - requests that arrive while others run are admitted as soon as a worker
+ *     and the memory are free, so their work overlaps on the device.
+ * Every result equals that of hs_factor (+ hs_pcg for symmetric operators,
+ * hs_gmres(restart 30) otherwise) on the request alone: batched systems get
+ * the same kernels in the same order and one Krylov recurrence per system
+ * and column.  The memory of a new factorization is estimated as its
+ * unknowns times the largest peak bytes per unknown seen so far for the same
+ * grid dimension and precision (before the first: 16 KB / unknown), plus the
+ * Krylov work vectors. */
+typedef struct hs_server_s* hs_server_t;
+
+typedef struct hs_server_opts {
+    double hbm_cap_bytes;   /* device memory the server may hold: resident factors plus work
+                               in flight (> 0) */
+    int32_t workers;        /* batches in flight at once, one stream each (0: 2) */
+    int32_t max_batch;      /* most requests in one batch (0: 32) */
+    int32_t max_new_ops;    /* most new operators factored together (0: 8) */
+} hs_server_opts;
+
+typedef struct hs_result {
+    int32_t status;         /* HS_OK, HS_WARN_NOT_CONVERGED, or the HS_ERR_* of the failing call */
+    int32_t iterations;     /* Krylov iterations of the request's batch */
+    double relres;          /* largest true relative residual over the request's columns */
+    double latency_s;       /* submission to completion */
+    double queue_s;         /* submission to the start of its batch */
+    int32_t reused;         /* 1 if the operator's factorization was resident */
+    int32_t batch_size;     /* requests in its batch */
+} hs_result;
+
+typedef struct hs_server_stats {
+    int64_t submitted, completed, failed;
+    int64_t batches;        /* batches started */
+    int64_t reused;         /* requests served by a resident factorization */
+    int64_t factored_ops;   /* operators factored */
+    int64_t evictions;
+    double p50_latency_s, p99_latency_s, mean_queue_s;
+    double unknowns_per_s;  /* sum of n * nrhs over completed requests / span from the first
+                               submission to the last completion */
+    double requests_per_s;
+    double held_bytes;      /* now: resident factors + reservations of running batches */
+    double peak_held_bytes;
+} hs_server_stats;
+
+/* Start a server on the current HIP device. */
+int hs_server_create(const hs_server_opts* opts, hs_server_t* S_out);
+
+/* Queue one request: solve A X = B to relative residual tol (maxit
+ * iterations at most).  op_key names the operator: requests with the same
+ * key must pass the same matrix and options (the resident factorization is
+ * reused without checking).  A, B, X: device or host CSR as hs_csr, B and X
+ * device pointers, n x nrhs column major (ld n), caller-owned and untouched
+ * by the caller until the request completes; opts->symmetric must be 0 or 1
+ * (it selects GMRES or CG).  *ticket receives the request's id.  Errors:
+ * HS_ERR_ARG (bad argument; nothing queued). */
+int hs_submit(hs_server_t S, int64_t op_key, const hs_csr* A, const hs_geometry* geom, const hs_opts* opts,
+              int32_t nrhs, const double* B, double* X, double tol, int32_t maxit, int64_t* ticket);
+
+/* *done = 1 once the request has completed (its X written). */
+int hs_poll(hs_server_t S, int64_t ticket, int32_t* done);
+
+/* Block until the request completes; *out receives its result (may be NULL).
+ * A ticket can be waited for once; afterwards it is unknown (HS_ERR_ARG). */
+int hs_wait(hs_server_t S, int64_t ticket, hs_result* out);
+
+/* Counters and latency percentiles over the completed requests. */
+int hs_server_stats_get(hs_server_t S, hs_server_stats* out);
+
+/* Finish every queued request, stop the workers, free the resident
+ * factorizations.  NULL is ignored. */
+void hs_server_destroy(hs_server_t S);
 
 /* Install the device allocator used for all library-owned memory.
  * alloc(bytes, ctx) returns a device pointer or NULL; free(ptr, ctx).  Pass

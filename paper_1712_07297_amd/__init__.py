@@ -9,6 +9,7 @@ from ._lib import (  # noqa: F401
     HS_MIXED,
     Factor,
     HsError,
+    Server,
     Symbolic,
     header_functions,
     lib,

@@ -96,6 +96,33 @@ _D = ctypes.c_double
 _PI32 = ctypes.POINTER(ctypes.c_int32)
 _PD = ctypes.POINTER(ctypes.c_double)
 
+class hs_server_opts(ctypes.Structure):
+    _fields_ = [
+        ("hbm_cap_bytes", ctypes.c_double),
+        ("workers", ctypes.c_int32),
+        ("max_batch", ctypes.c_int32),
+        ("max_new_ops", ctypes.c_int32),
+    ]
+
+
+class hs_result(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int32),
+        ("iterations", ctypes.c_int32),
+        ("relres", ctypes.c_double),
+        ("latency_s", ctypes.c_double),
+        ("queue_s", ctypes.c_double),
+        ("reused", ctypes.c_int32),
+        ("batch_size", ctypes.c_int32),
+    ]
+
+
+class hs_server_stats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in ("submitted", "completed", "failed", "batches", "reused", "factored_ops", "evictions")] + [
+        (k, ctypes.c_double) for k in ("p50_latency_s", "p99_latency_s", "mean_queue_s", "unknowns_per_s", "requests_per_s", "held_bytes", "peak_held_bytes")
+    ]
+
+
 _SIGS = {
     "hs_factor": (ctypes.c_int, [ctypes.POINTER(hs_csr), ctypes.POINTER(hs_geometry), ctypes.POINTER(hs_opts), _P, ctypes.POINTER(_P)]),
     "hs_factor_batch": (ctypes.c_int, [_I32, ctypes.POINTER(hs_csr), ctypes.POINTER(hs_geometry), ctypes.POINTER(hs_opts), _P, ctypes.POINTER(_P)]),
@@ -109,6 +136,12 @@ _SIGS = {
     "hs_factor_level_matrix": (ctypes.c_int, [_P, _I32, _PD, _I64]),
     "hs_factor_record": (ctypes.c_int, [_P, _I32, _I32, _I32, _PD, _I64, ctypes.POINTER(_I64), ctypes.POINTER(_I64)]),
     "hs_free": (None, [_P]),
+    "hs_server_create": (ctypes.c_int, [ctypes.POINTER(hs_server_opts), ctypes.POINTER(_P)]),
+    "hs_submit": (ctypes.c_int, [_P, _I64, ctypes.POINTER(hs_csr), ctypes.POINTER(hs_geometry), ctypes.POINTER(hs_opts), _I32, _P, _P, _D, _I32, ctypes.POINTER(_I64)]),
+    "hs_poll": (ctypes.c_int, [_P, _I64, _PI32]),
+    "hs_wait": (ctypes.c_int, [_P, _I64, ctypes.POINTER(hs_result)]),
+    "hs_server_stats_get": (ctypes.c_int, [_P, ctypes.POINTER(hs_server_stats)]),
+    "hs_server_destroy": (None, [_P]),
     "hs_symbolic_create": (ctypes.c_int, [ctypes.POINTER(hs_csr), ctypes.POINTER(hs_geometry), _I32, ctypes.POINTER(_P)]),
     "hs_symbolic_levels": (ctypes.c_int, [_P, _PI32]),
     "hs_symbolic_level": (ctypes.c_int, [_P, _I32, _PI32, _PI32, ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(_I64)]),
@@ -321,6 +354,68 @@ class Factor:
         out = np.zeros((dim, dim), order="F")
         _check(lib().hs_factor_level_matrix(self._h, level, out.ctypes.data_as(_PD), dim), "hs_factor_level_matrix")
         return out
+
+
+class Server:
+    """The serving request loop (hs_server_*).  submit() queues one solve and
+    returns a ticket; wait() blocks until its X is written.  The tensors of a
+    request are kept alive here until it completes."""
+
+    def __init__(self, hbm_cap_gb: float, workers: int = 2, max_batch: int = 32, max_new_ops: int = 8):
+        o = hs_server_opts(float(hbm_cap_gb) * 1e9, int(workers), int(max_batch), int(max_new_ops))
+        h = _P()
+        _check(lib().hs_server_create(ctypes.byref(o), ctypes.byref(h)), "hs_server_create")
+        self._h = h
+        self._keep = {}
+
+    def submit(self, op_key: int, row_ptr, col_idx, val, dims, B, eps: float, leaf: int = 64, symmetric: int = 1,
+               precision: int = HS_FP64, tol: float = 1e-10, maxit: int = 300, X=None, coarse_fp64_dofs: int = 0) -> int:
+        import torch
+
+        keep: list = []
+        A = _csr_struct(row_ptr, col_idx, val, keep)
+        B2, nrhs, ldb, sq = _rhs(B)
+        if ldb != A.n:
+            B2 = B2.contiguous()
+        if X is None:
+            X = torch.empty_like(B2)
+        opts = hs_opts(float(eps), 0, int(leaf), int(precision), int(symmetric), 0, int(coarse_fp64_dofs))
+        geom = _geom(dims)
+        t = _I64(0)
+        _check(lib().hs_submit(self._h, int(op_key), ctypes.byref(A), ctypes.byref(geom), ctypes.byref(opts), nrhs,
+                               _ptr(B2), _ptr(X), float(tol), int(maxit), ctypes.byref(t)), "hs_submit")
+        self._keep[int(t.value)] = (keep, B2, X, sq)
+        return int(t.value)
+
+    def poll(self, ticket: int) -> bool:
+        d = _I32(0)
+        _check(lib().hs_poll(self._h, int(ticket), ctypes.byref(d)), "hs_poll")
+        return bool(d.value)
+
+    def wait(self, ticket: int):
+        """(X, result dict) of a request."""
+        r = hs_result()
+        rc = lib().hs_wait(self._h, int(ticket), ctypes.byref(r))
+        keep, B2, X, sq = self._keep.pop(int(ticket))
+        res = {k: getattr(r, k) for k, _ in hs_result._fields_}
+        if rc < 0 and r.status == 0:
+            _check(rc, "hs_wait")
+        return (X.reshape(-1) if sq else X), res
+
+    def stats(self) -> dict:
+        s = hs_server_stats()
+        _check(lib().hs_server_stats_get(self._h, ctypes.byref(s)), "hs_server_stats_get")
+        return {k: getattr(s, k) for k, _ in hs_server_stats._fields_}
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.hs_server_destroy(h)
+            self._h = None
+            self._keep.clear()
+
+    def __del__(self):
+        self.close()
 
 
 class Symbolic:

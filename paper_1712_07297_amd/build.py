@@ -17,7 +17,7 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhs.so")
 
-SOURCES = ["symbolic.cpp", "k_factor.hip", "k_dense.hip", "k_solve.hip", "k_krylov.hip", "hs_api.hip"]
+SOURCES = ["symbolic.cpp", "serve.cpp", "k_factor.hip", "k_dense.hip", "k_solve.hip", "k_krylov.hip", "hs_api.hip"]
 
 ARCH = "gfx950"
 COMMON = [

@@ -17,6 +17,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <vector>
@@ -35,6 +36,9 @@ static int fail(int code, const std::string& msg) {
     g_err = msg;
     return code;
 }
+
+// For the serving runtime (same library): record the calling thread's message.
+int fail_with(int code, const char* msg) { return fail(code, msg); }
 
 #define HIP_TRY(expr)                                                                        \
     do {                                                                                     \
@@ -67,6 +71,43 @@ static void dev_free(void* p) {
         (void)hipFree(p);
 }
 
+// Stream-ordered allocation: inside an entry point (StreamScope) library
+// buffers come from the device's default memory pool on the caller's stream,
+// whose release threshold is raised so freed memory stays reserved for the
+// next allocation instead of being unmapped (large level stores come and go
+// every level).  A buffer is freed on the stream it was allocated on; freed
+// from elsewhere, the device is synchronised first.
+static thread_local hipStream_t t_stream = nullptr;
+static thread_local bool t_stream_set = false;
+static thread_local bool t_device_synced = false;
+struct StreamScope {
+    hipStream_t prev;
+    bool prev_set, prev_synced;
+    StreamScope(hipStream_t s, bool device_synced = false)
+        : prev(t_stream), prev_set(t_stream_set), prev_synced(t_device_synced) {
+        t_stream = s;
+        t_stream_set = true;
+        t_device_synced = device_synced;
+    }
+    ~StreamScope() {
+        t_stream = prev;
+        t_stream_set = prev_set;
+        t_device_synced = prev_synced;
+    }
+};
+static void pool_init() {
+    static std::once_flag once;
+    std::call_once(once, [] {
+        int dev = 0;
+        hipMemPool_t pool;
+        if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+            uint64_t keep = UINT64_MAX;
+            (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+        }
+        (void)hipGetLastError();
+    });
+}
+
 // Device bytes held by one factorization (current and largest so far).
 // Buffers allocated while a call works on a factorization are charged to it
 // (t_acct is set for the duration of the call).
@@ -84,10 +125,12 @@ struct DevBuf {
     void* p = nullptr;
     size_t bytes = 0;
     ByteAccount* acct = nullptr;
+    bool pooled = false;
+    hipStream_t stream = nullptr;
     DevBuf() = default;
     DevBuf(const DevBuf&) = delete;
     DevBuf& operator=(const DevBuf&) = delete;
-    DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes), acct(o.acct) {
+    DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes), acct(o.acct), pooled(o.pooled), stream(o.stream) {
         o.p = nullptr;
         o.bytes = 0;
         o.acct = nullptr;
@@ -98,6 +141,8 @@ struct DevBuf {
             p = o.p;
             bytes = o.bytes;
             acct = o.acct;
+            pooled = o.pooled;
+            stream = o.stream;
             o.p = nullptr;
             o.bytes = 0;
             o.acct = nullptr;
@@ -106,15 +151,35 @@ struct DevBuf {
     }
     ~DevBuf() { release(); }
     void release() {
-        dev_free(p);
+        if (p && pooled) {
+            if (t_stream_set && t_stream == stream) {
+                (void)hipFreeAsync(p, stream);
+            } else {
+                if (!t_device_synced) (void)hipDeviceSynchronize();
+                (void)hipFreeAsync(p, nullptr);
+            }
+        } else {
+            dev_free(p);
+        }
         if (acct) acct->held -= (int64_t)bytes;
         p = nullptr;
         bytes = 0;
         acct = nullptr;
+        pooled = false;
     }
     bool alloc(size_t n) {
         release();
-        p = dev_alloc(n);
+        if (!g_alloc_fn && t_stream_set) {
+            pool_init();
+            if (hipMallocAsync(&p, n ? n : 256, t_stream) != hipSuccess) {
+                (void)hipGetLastError();
+                p = nullptr;
+            }
+            pooled = p != nullptr;
+            stream = t_stream;
+        } else {
+            p = dev_alloc(n);
+        }
         bytes = p ? n : 0;
         if (p && t_acct) {
             acct = t_acct;
@@ -1555,6 +1620,7 @@ static int factor_entry(int32_t nsys, const hs_csr* A, const hs_geometry* geom, 
     F->info.breakdown_level = -1;
     F->info.breakdown_cluster = -1;
     AcctScope scope(&F->acct);
+    StreamScope sscope((hipStream_t)hip_stream);
     rc = factor_impl(F.get(), nsys, A, geom, (hipStream_t)hip_stream);
     if (rc < 0) return rc;
     *F_out = F.release();
@@ -1582,6 +1648,7 @@ int hs_solve(hs_factor_t F, int64_t nrhs, const double* B, int64_t ldb, double* 
     if (!F || !B || !X || nrhs < 1 || nrhs > 64 || ldb < F->n || ldx < F->n) return fail(HS_ERR_ARG, "bad argument");
     if (B == X && ldb != ldx) return fail(HS_ERR_ARG, "aliased B and X need equal leading dimensions");
     AcctScope scope(&F->acct);
+    StreamScope sscope((hipStream_t)hip_stream);
     return solve_impl(F, (int)nrhs, B, ldb, X, ldx, (hipStream_t)hip_stream);
 }
 
@@ -1591,6 +1658,7 @@ int hs_pcg(hs_factor_t F, int64_t nrhs, const double* B, int64_t ldb, double* X,
     if (!F || !B || !X || nrhs < 1 || nrhs > 64 || ldb < F->n || ldx < F->n || !(tol >= 0) || maxit < 0 || B == X)
         return fail(HS_ERR_ARG, "bad argument");
     AcctScope scope(&F->acct);
+    StreamScope sscope((hipStream_t)hip_stream);
     return pcg_impl(F, (int)nrhs, B, ldb, X, ldx, tol, maxit, iters_out, relres_out, (hipStream_t)hip_stream);
 }
 
@@ -1601,6 +1669,7 @@ int hs_gmres(hs_factor_t F, int64_t nrhs, const double* B, int64_t ldb, double* 
         restart > 1000 || B == X)
         return fail(HS_ERR_ARG, "bad argument");
     AcctScope scope(&F->acct);
+    StreamScope sscope((hipStream_t)hip_stream);
     return gmres_impl(F, (int)nrhs, B, ldb, X, ldx, tol, maxit, restart, iters_out, relres_out,
                       (hipStream_t)hip_stream);
 }
@@ -1675,7 +1744,12 @@ int hs_factor_record(hs_factor_t F, int32_t level, int32_t cluster, int32_t whic
     return HS_OK;
 }
 
-void hs_free(hs_factor_t F) { delete F; }
+void hs_free(hs_factor_t F) {
+    if (!F) return;
+    (void)hipDeviceSynchronize();  // nothing may still use the buffers
+    StreamScope sscope(nullptr, true);
+    delete F;
+}
 
 int hs_symbolic_create(const hs_csr* A, const hs_geometry* geom, int32_t leaf_size, hs_symbolic_t* S_out) {
     g_err.clear();

@@ -1,0 +1,77 @@
+"""Seeded input generators (no GPU): sizes, symmetry and the statistics the
+workloads are specified by."""
+
+import math
+
+import numpy as np
+import scipy.sparse as sp
+
+from workloads import (config4_batch, convdiff2d_upwind, diffusion3d_from_coeff, gaussian_field3d, serving_stream,
+                       build_request_operator)
+
+
+def _csr(A):
+    return sp.csr_matrix((A.val, A.col_idx, A.row_ptr), shape=(A.n, A.n))
+
+
+def test_gaussian_field_keeps_grid_size_and_sigma():
+    """Sides below the kernel length (2 ceil(3 * 8 / sqrt 2) + 1 = 35) keep
+    their size; standard deviation is the requested sigma; on a side above
+    the kernel length each axis pass equals numpy's centred convolution."""
+    for n in (8, 20, 34, 35, 48):
+        g = gaussian_field3d(np.random.default_rng(1), n, n + 1, n + 2, 8.0, 1.5)
+        assert g.shape == (n + 2, n + 1, n)
+        assert abs(g.std() - 1.5) < 1e-12 and abs(g.mean()) < 1e-12
+    s = 8.0 / math.sqrt(2.0)
+    r = int(math.ceil(3 * s))
+    t = np.arange(-r, r + 1, dtype=float)
+    ker = np.exp(-0.5 * (t / s) ** 2)
+    ker /= ker.sum()
+    v = np.random.default_rng(2).standard_normal(50)
+    assert np.allclose(np.convolve(v, ker, mode="full")[r : r + 50], np.convolve(v, ker, mode="same"))
+
+
+def test_diffusion_operator_is_spd_m_matrix():
+    a = np.exp(gaussian_field3d(np.random.default_rng(3), 6, 5, 4, 8.0, 2.0))
+    A = _csr(diffusion3d_from_coeff(a)).toarray()
+    assert A.shape == (120, 120)
+    assert np.allclose(A, A.T)
+    assert np.all(np.diag(A) > 0) and np.all(A - np.diag(np.diag(A)) <= 0)
+    assert np.linalg.eigvalsh(A).min() > 0
+
+
+def test_convdiff_upwind_row_sums_and_nonsymmetry():
+    A = _csr(convdiff2d_upwind(10, 50.0, 0.7)).toarray()
+    assert not np.allclose(A, A.T)
+    # interior rows sum to zero (consistent discretisation of -Lap + b.grad)
+    interior = [i + 10 * j for i in range(1, 9) for j in range(1, 9)]
+    assert np.allclose(A[interior].sum(axis=1), 0.0)
+    assert np.all(np.diag(A) >= np.abs(A - np.diag(np.diag(A))).sum(axis=1) - 1e-12)
+
+
+def test_batch_workload_ranges():
+    probs = config4_batch(count=64)
+    sides = np.array([p.dims[0] for p in probs])
+    assert len(probs) == 64 and sides.min() >= 64 and sides.max() <= 512
+    assert all(p.A.n == p.dims[0] * p.dims[1] for p in probs)
+    assert all(p.B.shape == (p.A.n, 1) for p in probs)
+
+
+def test_serving_stream_mix_and_reuse():
+    reqs = serving_stream(5, 2000, rate=10.0)
+    t = np.array([r.t_arrival for r in reqs])
+    assert np.all(np.diff(t) > 0) and abs(np.mean(np.diff(t)) - 0.1) < 0.01
+    keys = [r.op_key for r in reqs]
+    reuse = 1 - len(set(keys)) / len(keys)
+    assert 0.25 < reuse < 0.35
+    new = {}
+    for r in reqs:
+        new.setdefault(r.op_key, r)
+    frac3d = np.mean([r.kind == "diff3d" for r in new.values()])
+    assert 0.55 < frac3d < 0.65
+    assert all(1 <= r.nrhs <= 16 for r in reqs)
+    small = [r for r in new.values() if r.kind == "diff3d"][:2] + [r for r in new.values() if r.kind == "convdiff2d"][:1]
+    for r in small:
+        r.side = min(r.side, 24)  # keep the check cheap
+        A, dims, dim, sym = build_request_operator(r)
+        assert A.n == int(np.prod(dims)) and sym == (r.kind == "diff3d")

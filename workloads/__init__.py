@@ -12,6 +12,7 @@ from .pde import (  # noqa: F401
     poisson2d,
     poisson3d,
     diffusion3d_expgauss,
+    diffusion3d_from_coeff,
     convdiff2d_upwind,
     gaussian_field3d,
     rhs_uniform,
@@ -21,6 +22,8 @@ from .pde import (  # noqa: F401
     config3,
     config4_batch,
     serving_stream,
+    build_request_operator,
+    Request,
     chain1d,
     random_spd_blocks,
     random_nonsym_dd,

@@ -138,8 +138,10 @@ def gaussian_field3d(rng: np.random.Generator, nx: int, ny: int, nz: int, corr_l
     ker = np.exp(-0.5 * (t / s) ** 2)
     ker /= ker.sum()
     g = white
+    # centred part of the full convolution: the grid keeps its size also when
+    # the kernel is longer than a side
     for axis in range(3):
-        g = np.apply_along_axis(lambda v: np.convolve(v, ker, mode="same"), axis, g)
+        g = np.apply_along_axis(lambda v: np.convolve(v, ker, mode="full")[r : r + v.size], axis, g)
     g = g - g.mean()
     return sigma * g / g.std()
 
