@@ -24,8 +24,16 @@ GMRES(30) to 1e-10 per system.  Systems are factored together with
 hs_factor_batch in groups whose measured device footprint fits the memory
 budget; one step = every group's hs_factor_batch + hs_gmres + hs_free.
 
+Serving workload (--workload serve): a Poisson stream of solve requests
+(60 % 3D lognormal diffusion with sides 32..96, 40 % 2D convection-diffusion
+with sides 256..1024, 1-16 right-hand sides, 30 % operator reuse) served by
+the library's request loop at rho times its capacity measured on a burst;
+value = unknowns x right-hand sides solved per second, with p50 / p99
+latency.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--side 64] [--forms both|mixed|fp64]
-                       [--workload poisson64|batch] [--batch-count 256] [--budget-gb 200]
+                       [--workload poisson64|batch|serve] [--batch-count 256] [--budget-gb 200]
+                       [--requests 100] [--rho 0.8] [--cap-gb 200] [--workers 2]
 """
 
 import argparse
@@ -275,6 +283,110 @@ def run_batch(args):
     print(json.dumps(out))
 
 
+def run_serve(args):
+    """The serving stream: Poisson arrivals of solve requests (60 % 3D
+    lognormal diffusion, CG; 40 % 2D convection-diffusion, GMRES(30); 1-16
+    right-hand sides; 30 % reuse an earlier operator), mixed form, served by
+    the library's request loop at a load of rho times its measured capacity."""
+    import torch
+
+    import paper_1712_07297_amd as P
+    from workloads import build_request_operator, serving_stream
+
+    dev = torch.device("cuda:0")
+    reqs = serving_stream(args.seed, args.requests, rate=1.0)
+    ops, rhs = {}, []
+    rng = np.random.default_rng(args.seed + 1)
+    t0 = time.perf_counter()
+    for r in reqs:
+        if r.op_key not in ops:
+            A, dims, _, sym = build_request_operator(r)
+            ops[r.op_key] = (torch.tensor(A.row_ptr, device=dev), torch.tensor(A.col_idx, device=dev),
+                             torch.tensor(A.val, device=dev), dims, int(sym), A.n)
+        n = ops[r.op_key][5]
+        rhs.append(torch.tensor(rng.uniform(-1.0, 1.0, (r.nrhs, n)), device=dev))
+    torch.cuda.synchronize()
+    print(f"serve: {len(ops)} operators, {len(reqs)} requests prepared in {time.perf_counter() - t0:.1f} s",
+          file=sys.stderr, flush=True)
+
+    def make_server():
+        return P.Server(hbm_cap_gb=args.cap_gb, workers=args.workers, max_batch=32, max_new_ops=8)
+
+    def submit(srv, i, key_base=0):
+        r = reqs[i]
+        rp, ci, va, dims, sym, n = ops[r.op_key]
+        return srv.submit(key_base + r.op_key, rp, ci, va, dims, rhs[i], eps=1e-3, leaf=64, symmetric=sym,
+                          precision=P.HS_MIXED, tol=1e-10, maxit=300)
+
+    # capacity: a burst of the first requests on a separate server (warm-up too)
+    cal = min(args.calibrate, len(reqs))
+    srv = make_server()
+    tc = time.perf_counter()
+    ts = [submit(srv, i) for i in range(cal)]
+    for t in ts:
+        srv.wait(t)
+    mu = cal / (time.perf_counter() - tc)
+    srv.close()
+    lam = args.rho * mu
+    print(f"serve: capacity {mu:.2f} requests/s from a burst of {cal}; arrival rate {lam:.2f}/s", file=sys.stderr,
+          flush=True)
+
+    srv = make_server()
+    arrivals = np.array([r.t_arrival for r in reqs]) / lam  # unit-rate stream scaled to lam
+    tickets = []
+    torch.cuda.synchronize()
+    start = time.perf_counter()
+    for i in range(len(reqs)):
+        delay = start + arrivals[i] - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        tickets.append(submit(srv, i))
+        if (i + 1) % 25 == 0:
+            print(f"serve: {i + 1}/{len(reqs)} submitted", file=sys.stderr, flush=True)
+    results = [srv.wait(t)[1] for t in tickets]
+    wall = time.perf_counter() - start
+    st = srv.stats()
+    srv.close()
+    ok = all(r["status"] == 0 for r in results) and max(r["relres"] for r in results) <= 1e-10
+    out = {
+        "metric": "unknowns/s factor+solve to 1e-10 residual; p50/p99 latency (serving)",
+        "value": st["unknowns_per_s"],
+        "unit": "unknowns/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 1,
+        "ms_per_step": wall * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 storage + bf16x3 MFMA Schur, f64 Krylov",
+        "data": "synthetic",
+        "config": {
+            "workload": f"serving stream of {len(reqs)} requests ({len(ops)} operators): 60% 3D lognormal diffusion "
+                        "(sides 32..96, CG), 40% 2D convection-diffusion (sides 256..1024, GMRES(30)), 1-16 RHS, "
+                        "30% operator reuse, Poisson arrivals, eps 1e-3, tol 1e-10",
+            "rho": args.rho,
+            "arrival_rate_per_s": lam,
+            "capacity_per_s": mu,
+            "p50_latency_s": st["p50_latency_s"],
+            "p99_latency_s": st["p99_latency_s"],
+            "mean_queue_s": st["mean_queue_s"],
+            "requests_per_s": st["requests_per_s"],
+            "completed": st["completed"],
+            "reused": st["reused"],
+            "batches": st["batches"],
+            "factored_ops": st["factored_ops"],
+            "evictions": st["evictions"],
+            "peak_held_gb": st["peak_held_bytes"] / 1e9,
+            "cap_gb": args.cap_gb,
+            "workers": args.workers,
+            "max_relres": max(r["relres"] for r in results),
+            "converged": ok,
+        },
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -286,7 +398,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-side", type=int, default=24)
     ap.add_argument("--copy-probe", action="store_true", help="also run a plain device copy of known size (counter calibration)")
-    ap.add_argument("--workload", choices=["poisson64", "batch"], default="poisson64")
+    ap.add_argument("--workload", choices=["poisson64", "batch", "serve"], default="poisson64")
+    ap.add_argument("--requests", type=int, default=100, help="serve workload: requests in the stream")
+    ap.add_argument("--rho", type=float, default=0.8, help="serve workload: load over measured capacity")
+    ap.add_argument("--cap-gb", type=float, default=200.0, help="serve workload: device memory cap")
+    ap.add_argument("--workers", type=int, default=2, help="serve workload: batches in flight")
+    ap.add_argument("--calibrate", type=int, default=12, help="serve workload: burst size for the capacity")
+    ap.add_argument("--seed", type=int, default=5)
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--budget-gb", type=float, default=200.0, help="device memory per batched group")
     ap.add_argument("--profile", action="store_true", help="batch workload: per-family times to stderr")
@@ -297,6 +415,9 @@ def main():
         sys.exit(2)
     if args.workload == "batch":
         run_batch(args)
+        return
+    if args.workload == "serve":
+        run_serve(args)
         return
 
     import torch

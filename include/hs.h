@@ -292,6 +292,11 @@ int hs_profile_enable(int32_t enable);
 int hs_profile_reset(void);
 int hs_profile_read(const char* family, int64_t* launches, double* seconds, double* bytes, double* flops);
 
+/* Release F's solve and Krylov work vectors (the next hs_solve / hs_pcg /
+ * hs_gmres allocates them again), keeping the factorization itself; for a
+ * resident factorization between uses.  Stream ordered on hip_stream. */
+int hs_factor_trim(hs_factor_t F, void* hip_stream);
+
 /* Release F and all its device memory.  NULL is ignored. */
 void hs_free(hs_factor_t F);
 

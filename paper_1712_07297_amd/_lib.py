@@ -136,6 +136,7 @@ _SIGS = {
     "hs_factor_level_matrix": (ctypes.c_int, [_P, _I32, _PD, _I64]),
     "hs_factor_record": (ctypes.c_int, [_P, _I32, _I32, _I32, _PD, _I64, ctypes.POINTER(_I64), ctypes.POINTER(_I64)]),
     "hs_free": (None, [_P]),
+    "hs_factor_trim": (ctypes.c_int, [_P, _P]),
     "hs_server_create": (ctypes.c_int, [ctypes.POINTER(hs_server_opts), ctypes.POINTER(_P)]),
     "hs_submit": (ctypes.c_int, [_P, _I64, ctypes.POINTER(hs_csr), ctypes.POINTER(hs_geometry), ctypes.POINTER(hs_opts), _I32, _P, _P, _D, _I32, ctypes.POINTER(_I64)]),
     "hs_poll": (ctypes.c_int, [_P, _I64, _PI32]),
@@ -321,6 +322,10 @@ class Factor:
         rel = (ctypes.c_double * (nrhs * self.nsys))()
         rc = _check(lib().hs_gmres(self._h, nrhs, _ptr(B2), ldb, _ptr(X), X.stride(0), float(tol), int(maxit), int(restart), ctypes.byref(it), rel, _stream(stream)), "hs_gmres")
         return (X.reshape(-1) if sq else X), int(it.value), self._lanes(rel, nrhs), rc == HS_OK
+
+    def trim(self, stream=None):
+        """Release the solve / Krylov work vectors (hs_factor_trim)."""
+        _check(lib().hs_factor_trim(self._h, _stream(stream)), "hs_factor_trim")
 
     def info(self) -> hs_info:
         out = hs_info()

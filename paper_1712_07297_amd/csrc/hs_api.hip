@@ -1744,6 +1744,16 @@ int hs_factor_record(hs_factor_t F, int32_t level, int32_t cluster, int32_t whic
     return HS_OK;
 }
 
+int hs_factor_trim(hs_factor_t F, void* hip_stream) {
+    if (!F) return fail(HS_ERR_ARG, "null factor");
+    StreamScope sscope((hipStream_t)hip_stream);
+    F->vecs.release();
+    F->part.release();
+    F->kry.release();
+    F->solve_nrhs = 0;
+    return HS_OK;
+}
+
 void hs_free(hs_factor_t F) {
     if (!F) return;
     (void)hipDeviceSynchronize();  // nothing may still use the buffers

@@ -208,8 +208,9 @@ struct hs_server_s {
         const int ns = (int)g->keys.size();
         double *Bs = nullptr, *Xs = nullptr;
         int rc = HS_OK;
-        if (hipMalloc(&Bs, (size_t)n * nr * sizeof(double)) != hipSuccess ||
-            hipMalloc(&Xs, (size_t)n * nr * sizeof(double)) != hipSuccess)
+        // stream-ordered (no device-wide synchronisation that would stall the other workers)
+        if (hipMallocAsync((void**)&Bs, (size_t)n * nr * sizeof(double), st) != hipSuccess ||
+            hipMallocAsync((void**)&Xs, (size_t)n * nr * sizeof(double), st) != hipSuccess)
             rc = HS_ERR_NOMEM;
         std::vector<double> rel((size_t)ns * nr, 0.0);
         int iters = 0;
@@ -233,6 +234,7 @@ struct hs_server_s {
                                        r->nrhs, hipMemcpyDeviceToDevice, st);
             }
         }
+        hs_factor_trim(g->F, st);  // resident between uses: only the factorization itself
         if (hipStreamSynchronize(st) != hipSuccess && rc >= 0) rc = HS_ERR_HIP;
         for (auto& it : items) {
             Req* r = it.first;
@@ -242,8 +244,8 @@ struct hs_server_s {
             r->res.relres = worst;
             r->res.status = rc < 0 ? rc : (worst <= r->tol ? HS_OK : HS_WARN_NOT_CONVERGED);
         }
-        if (Bs) (void)hipFree(Bs);
-        if (Xs) (void)hipFree(Xs);
+        if (Bs) (void)hipFreeAsync(Bs, st);
+        if (Xs) (void)hipFreeAsync(Xs, st);
     }
 
     // Run a batch (no lock held).  Returns the new factorization, if any.
