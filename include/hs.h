@@ -83,8 +83,9 @@ typedef struct hs_geometry {
 
 #define HS_FP64 0  /* everything in float64 */
 #define HS_MIXED 1 /* float32 storage of the fine levels' blocks and records,
-                      bfloat16 Schur products accumulated in float32; float64
-                      on the coarse levels and in every Krylov vector */
+                      Schur products on the bfloat16 units (three-part split,
+                      float32 accumulation); float64 on the coarse levels and
+                      in every Krylov vector */
 
 /* Options of the factorization.
  *   eps         relative truncation tolerance of the fill compression
@@ -100,17 +101,19 @@ typedef struct hs_geometry {
  *               rank K of Sec. 5.1).
  *   leaf_size   target number of unknowns per leaf cluster (> 0).
  *   precision   HS_FP64 or HS_MIXED.  In the mixed form the level blocks and
- *               factor records of every level with more than
- *               coarse_fp64_dofs unknowns (and not complete) are float32,
- *               the Schur update (Eq. elim) multiplies bfloat16-rounded
- *               E_L, E_R with float32 accumulation, and the per-cluster
- *               dense algebra still runs in float64 registers; the result
- *               is a preconditioner for float64 CG / GMRES (Sec. 5).
+ *               factor records of a system's level are float32 when the
+ *               level has more than coarse_fp64_dofs unknowns of that system
+ *               and is not its complete (dense) level; the Schur update
+ *               (Eq. elim) on those levels splits E_L and E_R into three
+ *               bfloat16 parts each and accumulates the six products down to
+ *               2^-24 in float32 on the matrix cores; the per-cluster dense
+ *               algebra still runs in float64 registers; the result is a
+ *               preconditioner for float64 CG / GMRES (Sec. 5).
  *   symmetric   1: A is symmetric (one-sided compression, V_R = V_L);
  *               0: general A (row and column fill compressed together);
  *               -1: detect from the values.
- *   coarse_fp64_dofs  mixed form only: levels with at most this many
- *               unknowns keep float64 storage (0 selects 16384). */
+ *   coarse_fp64_dofs  mixed form only: a system's levels with at most this
+ *               many unknowns keep float64 storage (0 selects 16384). */
 typedef struct hs_opts {
     double eps;
     int32_t fixed_rank;
