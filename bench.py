@@ -111,7 +111,7 @@ def cpu_baseline(side: int = 24):
     }
 
 
-def run_form(P, torch, p, rp, ci, va, B, X, precision, steps, warmup, n):
+def run_form(P, torch, p, rp, ci, va, B, X, precision, steps, warmup, n, profile=False):
     """Warm-up, then `steps` timed steps of one precision form; returns its
     record (time, convergence, Schur roofline)."""
 
@@ -142,6 +142,11 @@ def run_form(P, torch, p, rp, ci, va, B, X, precision, steps, warmup, n):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     P.profile_enable(False)
+    if profile:
+        fams = ["gram", "pivot", "fill", "nbr", "schur", "schur_f32", "merge", "apply", "spmv", "dense",
+                "host_symbolic", "host_plan", "host_upload", "host_alloc", "host_sync", "host_solve_plan"]
+        prof = {f: round(P.profile_read(f)["seconds"] / steps, 4) for f in fams}
+        print(f"{name}: seconds per step by family {json.dumps(prof)}", file=sys.stderr, flush=True)
     # dominant kernel: the Schur updates of the levels stored in the form's
     # bulk precision (float32 levels in the mixed form, all levels in FP64)
     schur = P.profile_read("schur_f32" if precision == P.HS_MIXED else "schur")
@@ -407,7 +412,7 @@ def main():
     ap.add_argument("--seed", type=int, default=5)
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--budget-gb", type=float, default=200.0, help="device memory per batched group")
-    ap.add_argument("--profile", action="store_true", help="batch workload: per-family times to stderr")
+    ap.add_argument("--profile", action="store_true", help="per-family times (HIP events, host wall) to stderr")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -446,7 +451,7 @@ def main():
     recs = {}
     for prec in forms:
         recs["mixed" if prec == P.HS_MIXED else "fp64"] = run_form(P, torch, p, rp, ci, va, B, X, prec, args.steps,
-                                                                   args.warmup, n)
+                                                                   args.warmup, n, args.profile)
     head = recs.get("mixed", recs.get("fp64"))
     head_name = "mixed" if "mixed" in recs else "fp64"
     out = {

@@ -642,8 +642,12 @@ __device__ inline void map_rows(PN noff, int nb, int r0, int nt, int* nbr_of, in
     }
 }
 
+// At most 102 registers per lane (five waves per SIMD): the float kernel then
+// fits 79 without spilling and runs six workgroups per CU, the double one
+// five; the update is bound by the latency of its scattered loads and
+// stores, so more resident waves serve it better than more registers.
 template <class T>
-__global__ void __launch_bounds__(WG) k_schur(LevelDev L, ColourDev C) {
+__global__ void __launch_bounds__(WG, 5) k_schur(LevelDev L, ColourDev C) {
     constexpr bool F64 = std::is_same<T, double>::value;
     __shared__ std::conditional_t<F64, MfmaSmem, MfmaSmemB> sm;
     __shared__ SchurMaps mp;
