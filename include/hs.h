@@ -292,6 +292,11 @@ void hs_symbolic_free(hs_symbolic_t S);
  * kernels worked on: for "schur" and "schur_f32", per cluster 2 f n_tot^2
  * flops and b (2 f n_tot + 2 n_tot^2) bytes, b = 8 and 4 respectively).  Unknown family: HS_ERR_ARG. */
 int hs_profile_enable(int32_t enable);
+/* Time only the listed families while profiling is on (comma-separated
+ * names; NULL or "" = all).  Untimed launches run as without profiling (the
+ * solve's level sweeps from their captured graph unless "apply" is timed).
+ * Unknown name: HS_ERR_ARG. */
+int hs_profile_select(const char* families);
 int hs_profile_reset(void);
 int hs_profile_read(const char* family, int64_t* launches, double* seconds, double* bytes, double* flops);
 

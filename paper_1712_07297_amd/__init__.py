@@ -16,6 +16,7 @@ from ._lib import (  # noqa: F401
     profile_enable,
     profile_read,
     profile_reset,
+    profile_select,
     strerror,
     version,
 )

@@ -152,6 +152,7 @@ _SIGS = {
     "hs_set_allocator": (ctypes.c_int, [_P, _P, _P]),
     "hs_profile_enable": (ctypes.c_int, [_I32]),
     "hs_profile_reset": (ctypes.c_int, []),
+    "hs_profile_select": (ctypes.c_int, [ctypes.c_char_p]),
     "hs_profile_read": (ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(_I64), _PD, _PD, _PD]),
     "hs_last_error": (ctypes.c_char_p, []),
     "hs_strerror": (ctypes.c_char_p, [ctypes.c_int]),
@@ -466,6 +467,11 @@ class Symbolic:
 
 def profile_enable(on: bool = True) -> None:
     _check(lib().hs_profile_enable(1 if on else 0), "hs_profile_enable")
+
+
+def profile_select(families: str = "") -> None:
+    """Time only these families (comma-separated; "" = all)."""
+    _check(lib().hs_profile_select(families.encode()), "hs_profile_select")
 
 
 def profile_reset() -> None:

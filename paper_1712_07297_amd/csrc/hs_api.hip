@@ -77,6 +77,14 @@ static void dev_free(void* p) {
 // next allocation instead of being unmapped (large level stores come and go
 // every level).  A buffer is freed on the stream it was allocated on; freed
 // from elsewhere, the device is synchronised first.
+// A device-wide synchronisation from one thread would invalidate a graph
+// capture running in another (serving workers): both take this lock.
+static std::mutex g_capture_mu;
+static void device_sync() {
+    std::lock_guard<std::mutex> lk(g_capture_mu);
+    (void)hipDeviceSynchronize();
+}
+
 static thread_local hipStream_t t_stream = nullptr;
 static thread_local bool t_stream_set = false;
 static thread_local bool t_device_synced = false;
@@ -155,7 +163,7 @@ struct DevBuf {
             if (t_stream_set && t_stream == stream) {
                 (void)hipFreeAsync(p, stream);
             } else {
-                if (!t_device_synced) (void)hipDeviceSynchronize();
+                if (!t_device_synced) device_sync();
                 (void)hipFreeAsync(p, nullptr);
             }
         } else {
@@ -230,6 +238,8 @@ static ProfFamily g_prof[PF_COUNT] = {{"gram"}, {"pivot"}, {"fill"}, {"nbr"},   
                                       {"host_symbolic"}, {"host_plan"}, {"host_upload"}, {"host_alloc"}, {"host_sync"},
                                       {"host_solve_plan"}};
 static bool g_prof_on = false;
+static uint32_t g_prof_mask = 0xffffffffu;  // families timed while on (hs_profile_select)
+static bool prof_timed(int fam) { return g_prof_on && ((g_prof_mask >> fam) & 1u); }
 struct ProfPending {
     int fam;
     hipEvent_t a, b;
@@ -254,7 +264,7 @@ struct ProfScope {
     hipStream_t st;
     hipEvent_t a = nullptr;
     ProfScope(int f, hipStream_t s) : fam(f), st(s) {
-        if (g_prof_on) {
+        if (prof_timed(fam)) {
             a = prof_event();
             (void)hipEventRecord(a, st);
         }
@@ -274,7 +284,7 @@ struct HostScope {
     std::chrono::steady_clock::time_point t0;
     explicit HostScope(int f) : fam(f), t0(std::chrono::steady_clock::now()) {}
     ~HostScope() {
-        if (g_prof_on) {
+        if (prof_timed(fam)) {
             g_prof[fam].seconds += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
             g_prof[fam].launches += 1;
         }
@@ -383,6 +393,23 @@ struct hs_factor_s {
     int kry_nrhs = 0;
     int kry_restart = 0;
     hs_info info{};
+    // The level sweeps of a solve (Alg. 2 between scattering the right-hand
+    // sides and gathering the solution) captured as one HIP graph per
+    // right-hand-side count: they touch only the solve buffers above, so a
+    // graph stays valid until those are reallocated or released.
+    std::vector<std::pair<int, hipGraphExec_t>> sweeps;
+    hipStream_t cap_stream = nullptr;
+    hipStream_t sweep_stream = nullptr;  // stream of the latest graph launch
+    void drop_sweeps() {
+        if (sweeps.empty()) return;
+        (void)hipStreamSynchronize(sweep_stream);  // no launch of them may still be pending
+        for (auto& g : sweeps) (void)hipGraphExecDestroy(g.second);
+        sweeps.clear();
+    }
+    ~hs_factor_s() {
+        drop_sweeps();
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    }
 };
 
 struct hs_symbolic_s {
@@ -1105,7 +1132,9 @@ static int factor_impl(hs_factor_s* F, int nsys, const hs_csr* A, const hs_geome
             for (int c = 0; c < LD.ncl; ++c) {
                 const double f = LD.m[c] - LD.k[c], nt = ntot[c];
                 if (LD.m[c] == 0 || f == 0 || nt == 0 || LD.dense[c]) continue;
-                ProfFamily& fam = g_prof[LD.f32[c] ? PF_SCHUR_F32 : PF_SCHUR];
+                const int fid = LD.f32[c] ? PF_SCHUR_F32 : PF_SCHUR;
+                if (!prof_timed(fid)) continue;
+                ProfFamily& fam = g_prof[fid];
                 fam.flops += 2.0 * f * nt * nt;
                 fam.bytes += (double)LD.esz(c) * (2.0 * f * nt + 2.0 * nt * nt);
             }
@@ -1207,6 +1236,7 @@ static int factor_impl(hs_factor_s* F, int nsys, const hs_csr* A, const hs_geome
 
 static int ensure_solve_buffers(hs_factor_s* F, int nrhs) {
     if (F->solve_nrhs >= nrhs && F->vecs.p) return HS_OK;
+    F->drop_sweeps();  // captured sweeps refer to the buffers reallocated below
     const int nlev = (int)F->levels.size();
     F->vec_off.assign(nlev + 1, 0);
     for (int l = 0; l < nlev; ++l) F->vec_off[l + 1] = F->vec_off[l] + 3 * F->levels[l].nseg;
@@ -1235,20 +1265,16 @@ static int solve_impl(hs_factor_s* F, int nrhs, const double* B, int64_t ldb, do
     return HS_OK;
 }
 
-// Alg. 2: forward sweep colour by colour up the levels, backward sweep down.
-// A colour's float32 and float64 lists are independent launches.
-static int solve_chunk(hs_factor_s* F, int nrhs, const double* B, int64_t ldb, double* X, int64_t ldx, hipStream_t st) {
-    int rc = ensure_solve_buffers(F, nrhs);
-    if (rc) return rc;
+// Alg. 2: forward sweep colour by colour up the levels, backward sweep down
+// (level vectors only).  A colour's float32 and float64 lists are independent
+// launches.
+static void solve_sweeps(hs_factor_s* F, int nrhs, hipStream_t st) {
     const int nlev = (int)F->levels.size();
     double* base = F->vecs.as<double>();
     auto Y = [&](int l) { return base + F->vec_off[l] * nrhs; };
     auto Z = [&](int l) { return base + (F->vec_off[l] + F->levels[l].nseg) * nrhs; };
     auto O = [&](int l) { return base + (F->vec_off[l] + 2 * F->levels[l].nseg) * nrhs; };
     double* part = F->part.as<double>();
-    LevelData& L0 = F->levels[0];
-    launch_scatter_rhs(F->n, F->cluster_of.as<int>(), F->local_of.as<int>(), L0.sdev.seg, L0.dev.m, B, ldb, Y(0), nrhs,
-                       st);
     for (int l = 0; l < nlev; ++l) {
         LevelData& LD = F->levels[l];
         for (auto& CH : LD.colours)
@@ -1277,7 +1303,44 @@ static int solve_chunk(hs_factor_s* F, int nrhs, const double* B, int64_t ldb, d
             }
         }
     }
-    launch_gather_sol(F->n, F->cluster_of.as<int>(), F->local_of.as<int>(), L0.sdev.seg, L0.dev.m, O(0), X, ldx, nrhs,
+}
+
+// The sweeps run from a graph captured at the first solve with this
+// right-hand-side count (thousands of small launches become one), or launch
+// by launch while the per-family profiler is on.
+static int solve_chunk(hs_factor_s* F, int nrhs, const double* B, int64_t ldb, double* X, int64_t ldx, hipStream_t st) {
+    int rc = ensure_solve_buffers(F, nrhs);
+    if (rc) return rc;
+    const int nlev = (int)F->levels.size();
+    LevelData& L0 = F->levels[0];
+    double* Y0 = F->vecs.as<double>();
+    double* O0 = Y0 + 2 * L0.nseg * nrhs;
+    launch_scatter_rhs(F->n, F->cluster_of.as<int>(), F->local_of.as<int>(), L0.sdev.seg, L0.dev.m, B, ldb, Y0, nrhs,
+                       st);
+    if (prof_timed(PF_APPLY) || nlev == 0) {
+        solve_sweeps(F, nrhs, st);
+    } else {
+        hipGraphExec_t ex = nullptr;
+        for (auto& g : F->sweeps)
+            if (g.first == nrhs) ex = g.second;
+        if (!ex) {
+            if (!F->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&F->cap_stream, hipStreamNonBlocking));
+            hipGraph_t g = nullptr;
+            {
+                std::lock_guard<std::mutex> lk(g_capture_mu);
+                HIP_TRY(hipStreamBeginCapture(F->cap_stream, hipStreamCaptureModeThreadLocal));
+                solve_sweeps(F, nrhs, F->cap_stream);
+                HIP_TRY(hipStreamEndCapture(F->cap_stream, &g));
+            }
+            const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            HIP_TRY(e);
+            F->sweeps.push_back({nrhs, ex});
+        }
+        HIP_TRY(hipGraphLaunch(ex, st));
+        F->sweep_stream = st;
+    }
+    launch_gather_sol(F->n, F->cluster_of.as<int>(), F->local_of.as<int>(), L0.sdev.seg, L0.dev.m, O0, X, ldx, nrhs,
                       st);
     HIP_TRY(hipGetLastError());
     return HS_OK;
@@ -1747,6 +1810,7 @@ int hs_factor_record(hs_factor_t F, int32_t level, int32_t cluster, int32_t whic
 int hs_factor_trim(hs_factor_t F, void* hip_stream) {
     if (!F) return fail(HS_ERR_ARG, "null factor");
     StreamScope sscope((hipStream_t)hip_stream);
+    F->drop_sweeps();
     F->vecs.release();
     F->part.release();
     F->kry.release();
@@ -1756,7 +1820,9 @@ int hs_factor_trim(hs_factor_t F, void* hip_stream) {
 
 void hs_free(hs_factor_t F) {
     if (!F) return;
-    (void)hipDeviceSynchronize();  // nothing may still use the buffers
+    device_sync();  // nothing may still use the buffers or the graphs
+    for (auto& g : F->sweeps) (void)hipGraphExecDestroy(g.second);
+    F->sweeps.clear();
     StreamScope sscope(nullptr, true);
     delete F;
 }
@@ -1830,6 +1896,29 @@ int hs_set_allocator(void* (*alloc_fn)(size_t, void*), void (*free_fn)(void*, vo
 
 int hs_profile_enable(int32_t enable) {
     g_prof_on = enable != 0;
+    return HS_OK;
+}
+
+int hs_profile_select(const char* families) {
+    if (!families || !*families) {
+        g_prof_mask = 0xffffffffu;
+        return HS_OK;
+    }
+    uint32_t mask = 0;
+    std::string list(families);
+    size_t p0 = 0;
+    while (p0 <= list.size()) {
+        size_t p1 = list.find(',', p0);
+        if (p1 == std::string::npos) p1 = list.size();
+        const std::string name = list.substr(p0, p1 - p0);
+        int id = -1;
+        for (int f = 0; f < PF_COUNT; ++f)
+            if (name == g_prof[f].name) id = f;
+        if (id < 0) return fail(HS_ERR_ARG, "unknown family " + name);
+        mask |= 1u << id;
+        p0 = p1 + 1;
+    }
+    g_prof_mask = mask;
     return HS_OK;
 }
 

@@ -252,3 +252,25 @@ def test_symmetric_detection(P):
     G = P.Factor(A.row_ptr, A.col_idx, A.val, (12, 12, 1), 1e-4, 16, symmetric=1)
     for l in range(F.info().nlevels):
         assert np.array_equal(F.ranks(l), G.ranks(l))
+
+
+def test_graph_sweeps_equal_eager(P):
+    """The solve's level sweeps replayed from a captured HIP graph equal the
+    launch-by-launch sweeps (run while the profiler is on) bit for bit, over
+    several replays with other work on the device in between, for two
+    right-hand-side counts (each with its own graph)."""
+    A = poisson3d(16, 16, 16)
+    F = P.Factor(A.row_ptr, A.col_idx, A.val, (16, 16, 16), 1e-4, 64, symmetric=1, precision=P.HS_MIXED,
+                 coarse_fp64_dofs=1)
+    rng = np.random.default_rng(12)
+    for nrhs in (3, 1, 3):
+        B = torch.tensor(rng.uniform(-1, 1, (nrhs, A.n)), device="cuda")
+        P.profile_enable(True)
+        ref = F.solve(B).clone()
+        P.profile_enable(False)
+        for rep in range(3):
+            X = F.solve(B)
+            torch.cuda.synchronize()
+            assert torch.equal(X, ref), (nrhs, rep)
+            _ = (B * 2.0).sum().item()  # unrelated device work between replays
+        P.profile_reset()
