@@ -1005,6 +1005,98 @@ __device__ inline void wg_house_qr(PA A, int M, int K, int lda, PT tau_sh) {
     }
 }
 
+// The same QR with the columns held in registers (M <= 64 NS, K <= 64):
+// column c lives in wave c % 4, lane l holding rows l + 64 q.  Step j: the
+// wave holding column j forms its reflector (LAPACK larfg convention, as
+// wave_reflector), stores the finished column to A and publishes v (zero
+// above row j, one at it) and tau; after one barrier every wave applies the
+// reflector to its later columns, whose sums are independent so their
+// reductions overlap.  v alternates between two halves of vsh (2 M doubles),
+// so one barrier per step suffices.
+template <int NS, class PA, class PT>
+__device__ __attribute__((noinline)) void wg_house_qr_reg(PA A, int M, int K, int lda, PT tau_sh, lds_f64* vsh) {
+    constexpr int NW = WG / 64, CW = 64 / NW;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    double x[CW][NS];
+#pragma unroll
+    for (int t = 0; t < CW; ++t) {
+        const int c = wv + NW * t;
+#pragma unroll
+        for (int q = 0; q < NS; ++q) {
+            const int i = lane + 64 * q;
+            x[t][q] = (c < K && i < M) ? (double)A[i + (int64_t)c * lda] : 0.0;
+        }
+    }
+    __syncthreads();
+    for (int j = 0; j < K; ++j) {
+        lds_f64* v = vsh + (j & 1) * M;
+        if (wv == j % NW) {
+            const int ot = j / NW;
+#pragma unroll
+            for (int t = 0; t < CW; ++t) {
+                if (t != ot) continue;
+                double part = 0.0, alpha = 0.0;
+#pragma unroll
+                for (int q = 0; q < NS; ++q) {
+                    const int i = lane + 64 * q;
+                    if (i == j) alpha = x[t][q];
+                    if (i > j && i < M) part = fma(x[t][q], x[t][q], part);
+                }
+                const double xn2 = wave_sum(part);
+                alpha = wave_sum(alpha);  // one lane holds it, the others add zeros
+                double tau = 0.0, beta = alpha, scale = 0.0;
+                if (xn2 != 0.0) {
+                    const double nrm = hypot(alpha, sqrt(xn2));
+                    beta = (alpha >= 0.0) ? -nrm : nrm;
+                    tau = (beta - alpha) / beta;
+                    scale = 1.0 / (alpha - beta);
+                }
+#pragma unroll
+                for (int q = 0; q < NS; ++q) {
+                    const int i = lane + 64 * q;
+                    if (i >= M) continue;
+                    double val = x[t][q], vi = 0.0;
+                    if (i == j) {
+                        val = beta;
+                        vi = 1.0;
+                    } else if (i > j) {
+                        val = x[t][q] * scale;
+                        vi = val;
+                    }
+                    A[i + (int64_t)j * lda] = val;
+                    v[i] = vi;
+                }
+                if (lane == 0) tau_sh[j] = tau;
+            }
+        }
+        __syncthreads();
+        const double tau = tau_sh[j];
+        if (tau == 0.0) continue;
+        double vq[NS];
+#pragma unroll
+        for (int q = 0; q < NS; ++q) {
+            const int i = lane + 64 * q;
+            vq[q] = i < M ? (double)v[i] : 0.0;
+        }
+        double w[CW];
+#pragma unroll
+        for (int t = 0; t < CW; ++t) {
+            double part = 0.0;
+#pragma unroll
+            for (int q = 0; q < NS; ++q) part = fma(vq[q], x[t][q], part);
+            w[t] = part;
+        }
+#pragma unroll
+        for (int t = 0; t < CW; ++t) {
+            const int c = wv + NW * t;
+            const double wt = (c > j && c < K) ? tau * wave_sum(w[t]) : 0.0;
+#pragma unroll
+            for (int q = 0; q < NS; ++q) x[t][q] = fma(-wt, vq[q], x[t][q]);
+        }
+    }
+    __syncthreads();
+}
+
 // Columns [c0, c0 + nq) of Q = H_0 H_1 ... H_{K-1} (M x M) from the reflectors
 // left in A by wg_house_qr, into Q (ld ldq).  With flip, column c < K is
 // negated where R_cc < 0 (the orthonormal factor with a positive diagonal).

@@ -255,11 +255,17 @@ __device__ bool wg_cholqr2(const double* X, int M, int k, PG G, double* T1, doub
 
 // Householder complement: Q columns [K, M) of the QR of X (M x K, ld M) into
 // V (ld ldv), Q formed through its compact WY form (scratch: three global
-// M x M slots).  X is destroyed.
+// M x M slots).  X is destroyed.  The QR keeps X in registers when it fits
+// (M <= 128, K <= 64); scr then holds the published reflectors.
 template <class PX, class PV, class PT>
 __device__ void wg_complement(PX X, int M, int K, PV V, int ldv, PT tau_sh, double* s1, double* s2, double* s3,
                               lds_smem* sm, lds_f64* scr) {
-    wg_house_qr(X, M, K, M, tau_sh);
+    if (K <= 64 && M <= 64)
+        wg_house_qr_reg<1>(X, M, K, M, tau_sh, scr);
+    else if (K <= 64 && M <= 128)
+        wg_house_qr_reg<2>(X, M, K, M, tau_sh, scr);
+    else
+        wg_house_qr(X, M, K, M, tau_sh);
     if (K <= TRI_MFMA_MAX)
         wg_house_form_q_wy(X, M, K, M, tau_sh, K, M - K, V, ldv, false, s1, s2, s3, sm, scr);
     else
