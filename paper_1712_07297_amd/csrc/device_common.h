@@ -209,12 +209,17 @@ typedef __attribute__((address_space(3))) MfmaSmem lds_smem;
 __device__ inline lds_smem* to_lds(MfmaSmem* p) { return (lds_smem*)p; }
 
 // la(r, k) / lb(k, c) return the operand element or 0 outside the matrix.
-// Accumulates into acc (acc += Left * Right).
+// Accumulates into acc (acc += Left * Right).  Only the first rv rows and cv
+// columns of the tile are wanted: a wave skips the matrix-core work of its
+// 16 x 16 blocks that lie wholly beyond them (the skip is uniform per wave,
+// and the accumulators of skipped blocks are left as they were).
 template <class LoadL, class LoadR>
-__device__ inline void mfma_tile64_acc(int K, const LoadL& la, const LoadR& lb, lds_smem* sm, v4d acc[2][2]) {
+__device__ inline void mfma_tile64_acc(int K, const LoadL& la, const LoadR& lb, lds_smem* sm, v4d acc[2][2],
+                                       int rv = MT, int cv = MT) {
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wm = (w & 1) * 32, wn = (w >> 1) * 32;
     const int lr = lane & 15, lk = lane >> 4;
+    const bool ri[2] = {wm < rv, wm + 16 < rv}, cj[2] = {wn < cv, wn + 16 < cv};
     // each thread stages 4 elements of each operand per K chunk; the next
     // chunk is fetched into registers while the matrix cores work on this one
     constexpr int PER = MT * MKC / WG;
@@ -240,6 +245,7 @@ __device__ inline void mfma_tile64_acc(int K, const LoadL& la, const LoadR& lb, 
         }
         __syncthreads();
         if (k0 + MKC < K) fetch(k0 + MKC);
+        if (!ri[0] || !cj[0]) continue;  // nothing of this wave's quarter is wanted
 #pragma unroll
         for (int ks = 0; ks < MKC; ks += 4) {
             double av[2], bv[2];
@@ -250,7 +256,8 @@ __device__ inline void mfma_tile64_acc(int K, const LoadL& la, const LoadR& lb, 
 #pragma unroll
             for (int i = 0; i < 2; ++i)
 #pragma unroll
-                for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[j], av[i], acc[i][j], 0, 0, 0);
+                for (int j = 0; j < 2; ++j)
+                    if (ri[i] && cj[j]) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[j], av[i], acc[i][j], 0, 0, 0);
         }
     }
 }
@@ -264,9 +271,10 @@ __device__ inline void mfma_zero(v4d acc[2][2]) {
 
 // acc = Left * Right.
 template <class LoadL, class LoadR>
-__device__ inline void mfma_tile64(int K, const LoadL& la, const LoadR& lb, lds_smem* sm, v4d acc[2][2]) {
+__device__ inline void mfma_tile64(int K, const LoadL& la, const LoadR& lb, lds_smem* sm, v4d acc[2][2], int rv = MT,
+                                   int cv = MT) {
     mfma_zero(acc);
-    mfma_tile64_acc(K, la, lb, sm, acc);
+    mfma_tile64_acc(K, la, lb, sm, acc, rv, cv);
 }
 
 // Visit the tile's results: f(row, col, value), row/col within the 64 x 64 tile.
@@ -430,7 +438,7 @@ __device__ void wg_gemm(int M, int N, int K, double alpha, PA A, int lda, PB B, 
                     const int gc = c0 + c;
                     return gc < N ? (TB ? B[gc + (int64_t)k * ldb] : B[k + (int64_t)gc * ldb]) : 0.0;
                 },
-                sm, acc);
+                sm, acc, M - r0, N - c0);
             if (beta == 0.0) {
                 mfma_tile64_store(acc, [&](int r, int c, double v) {
                     const int gr = r0 + r, gc = c0 + c;
@@ -460,7 +468,7 @@ __device__ void wg_gemm_fn(int M, int N, int K, const LA& la, const LB& lb, lds_
             v4d acc[2][2];
             mfma_tile64(
                 K, [&](int r, int k) { return r0 + r < M ? la(r0 + r, k) : 0.0; },
-                [&](int k, int c) { return c0 + c < N ? lb(k, c0 + c) : 0.0; }, sm, acc);
+                [&](int k, int c) { return c0 + c < N ? lb(k, c0 + c) : 0.0; }, sm, acc, M - r0, N - c0);
             mfma_tile64_store(acc, [&](int r, int c, double v) {
                 if (r0 + r < M && c0 + c < N) store(r0 + r, c0 + c, v);
             });

@@ -86,11 +86,12 @@ __global__ void __launch_bounds__(WG) k_dense_panels(double* __restrict__ D, int
             mfma_tile64(
                 nb, [&](int r, int k) { return (r < hw) ? Linv[(hh + r) + (int64_t)k * DNB] : 0.0; },
                 [&](int k, int c) { return (q0 + c < N) ? D[(p + k) + (int64_t)(q0 + c) * ldd] : 0.0; }, to_lds(&sm),
-                acc[h]);
+                acc[h], hw, N - q0);
         else
             mfma_tile64(
                 nb, [&](int r, int k) { return (q0 + r < N) ? D[(q0 + r) + (int64_t)(p + k) * ldd] : 0.0; },
-                [&](int k, int c) { return (c < hw) ? Uinv[k + (int64_t)(hh + c) * DNB] : 0.0; }, to_lds(&sm), acc[h]);
+                [&](int k, int c) { return (c < hw) ? Uinv[k + (int64_t)(hh + c) * DNB] : 0.0; }, to_lds(&sm), acc[h],
+                N - q0, hw);
     }
     __syncthreads();
 #pragma unroll
@@ -119,7 +120,8 @@ __global__ void __launch_bounds__(WG) k_dense_trailing(double* __restrict__ D, i
     v4d acc[2][2];
     mfma_tile64(
         nb, [&](int r, int k) { return (r0 + r < N) ? D[(r0 + r) + (int64_t)(p + k) * ldd] : 0.0; },
-        [&](int k, int c) { return (c0 + c < N) ? D[(p + k) + (int64_t)(c0 + c) * ldd] : 0.0; }, to_lds(&sm), acc);
+        [&](int k, int c) { return (c0 + c < N) ? D[(p + k) + (int64_t)(c0 + c) * ldd] : 0.0; }, to_lds(&sm), acc,
+        N - r0, N - c0);
     mfma_tile64_store(acc, [&](int r, int c, double v) {
         if (r0 + r < N && c0 + c < N) D[(r0 + r) + (int64_t)(c0 + c) * ldd] -= v;
     });

@@ -81,13 +81,15 @@ __global__ void __launch_bounds__(WG) k_gram(LevelDev L, const int* __restrict__
                 const T* Bst = blk_t<T>(L, L.fill_bst[e]);  // M x ct, ld M
                 mfma_tile64_acc(
                     ct, [&](int r, int k) { return r0 + r < M ? Bst[(r0 + r) + (int64_t)k * M] : 0.0; },
-                    [&](int k, int c) { return c0 + c < M ? Bst[(c0 + c) + (int64_t)k * M] : 0.0; }, sm_l, acc);
+                    [&](int k, int c) { return c0 + c < M ? Bst[(c0 + c) + (int64_t)k * M] : 0.0; }, sm_l, acc, M - r0,
+                    M - c0);
                 if (!L.symmetric) {
                     const int mt = L.m[t];
                     const T* Bts = blk_t<T>(L, L.fill_bts[e]);  // ct x M, ld m_t
                     mfma_tile64_acc(
                         ct, [&](int r, int k) { return r0 + r < M ? Bts[k + (int64_t)(r0 + r) * mt] : 0.0; },
-                        [&](int k, int c) { return c0 + c < M ? Bts[k + (int64_t)(c0 + c) * mt] : 0.0; }, sm_l, acc);
+                        [&](int k, int c) { return c0 + c < M ? Bts[k + (int64_t)(c0 + c) * mt] : 0.0; }, sm_l, acc,
+                        M - r0, M - c0);
                 }
             }
             mfma_tile64_store(acc, [&](int r, int c, double v) {
@@ -208,6 +210,97 @@ __device__ int wg_pivoted_cholesky(PW W, int M, double eps, int fixed_rank, PI p
     return kk;
 }
 
+// The same factorization, left-looking, for a Gram matrix held in LDS with
+// M <= 128: nothing is exchanged physically.  Every wave keeps a replica of
+// the remaining diagonal and of the current positions (lane l, slot s: the
+// unknown l + 64 s) and finds the pivot itself, so a step needs one barrier.
+// Column j is formed for every row u as W(u, p_j) - sum_{i<j} L(u, i) L(p_j, i)
+// in the same order of fused multiply-adds as the right-looking update and is
+// stored over column p_j of W, which no later step reads: the factor, the
+// pivots and the stopping decisions are bit for bit those of the routine
+// above.  piv[j] is the unknown chosen at step j, pos[u] the final position
+// of unknown u.
+template <class PW, class PI>
+__device__ int wg_pivoted_cholesky_ll(PW W, int M, double eps, int fixed_rank, PI piv, PI pos) {
+    const int tid = threadIdx.x, lane = tid & 63;
+    double dr[2];
+    int pr[2];
+#pragma unroll
+    for (int sl = 0; sl < 2; ++sl) {
+        const int u = lane + 64 * sl;
+        dr[sl] = u < M ? W[u + (int64_t)u * M] : 0.0;
+        pr[sl] = u;
+    }
+    double d0 = 0.0;
+    int kk = 0;
+    for (int j = 0; j < M; ++j) {
+        if (j > 0) {  // the previous column updates the remaining diagonal
+            const int pc = piv[j - 1];
+#pragma unroll
+            for (int sl = 0; sl < 2; ++sl) {
+                const int u = lane + 64 * sl;
+                if (u < M && pr[sl] >= j) {
+                    const double l = W[u + (int64_t)pc * M];
+                    dr[sl] = fma(-l, l, dr[sl]);
+                }
+            }
+        }
+        double mx = -1.0;
+#pragma unroll
+        for (int sl = 0; sl < 2; ++sl)
+            if (lane + 64 * sl < M && pr[sl] >= j) mx = fmax(mx, dr[sl]);
+        mx = wave_max(mx);
+        if (!(mx > 0.0)) break;
+        const double thr = (1.0 - 1e-10) * mx;
+        int cand = M;
+#pragma unroll
+        for (int sl = 0; sl < 2; ++sl)
+            if (lane + 64 * sl < M && pr[sl] >= j && dr[sl] >= thr) cand = min(cand, pr[sl]);
+        const int p = wave_min_int(cand);
+        int up = M, uj = M;
+#pragma unroll
+        for (int sl = 0; sl < 2; ++sl) {
+            const int u = lane + 64 * sl;
+            if (u < M && pr[sl] == p) up = u;
+            if (u < M && pr[sl] == j) uj = u;
+        }
+        up = wave_min_int(up);
+        uj = wave_min_int(uj);
+        const double dj = readlane_d(up < 64 ? dr[0] : dr[1], up & 63);
+        if (j == 0) d0 = dj;
+        if (dj <= eps * eps * d0) break;
+        if (fixed_rank > 0 && j >= fixed_rank) break;
+#pragma unroll
+        for (int sl = 0; sl < 2; ++sl) {  // exchange positions j and p
+            const int u = lane + 64 * sl;
+            if (u == up) pr[sl] = j;
+            else if (u == uj) pr[sl] = p;
+        }
+        if (tid == 0) piv[j] = up;
+        const double ljj = sqrt(dj);
+        const double inv = 1.0 / ljj;
+        if (tid < M) {
+            const int u = tid;
+            double c = W[u + (int64_t)up * M];
+#pragma unroll 4
+            for (int i = 0; i < j; ++i) {
+                const int pi = piv[i];
+                c = fma(-W[u + (int64_t)pi * M], W[up + (int64_t)pi * M], c);
+            }
+            W[u + (int64_t)up * M] = (u == up) ? ljj : c * inv;
+        }
+        kk = j + 1;
+        __syncthreads();
+    }
+    if (tid < 64) {
+#pragma unroll
+        for (int sl = 0; sl < 2; ++sl)
+            if (lane + 64 * sl < M) pos[lane + 64 * sl] = pr[sl];
+    }
+    __syncthreads();
+    return kk;
+}
+
 // Orthonormal factor Q (M x k, positive diagonal R) of X = Q R by Cholesky
 // QR: G = Y^T Y = R^T R, R = D^{-1/2} U_G from the unpivoted LU G = L_G U_G
 // (D = diag U_G), Y <- Y R^{-1}.  One pass leaves an orthogonality error of
@@ -282,6 +375,7 @@ __global__ void __launch_bounds__(WG, 2) k_pivot(LevelDev L, const int* __restri
     __shared__ double red[16];
     __shared__ int isc[4];
     __shared__ int perm[MAX_M];
+    __shared__ int pos_sh[LDS_M];
     __shared__ double dsh[MAX_M];
     __shared__ int fcols_sh;
 
@@ -375,14 +469,23 @@ __global__ void __launch_bounds__(WG, 2) k_pivot(LevelDev L, const int* __restri
         constexpr double floor_ = std::is_same<T, float>::value ? FILL_NOISE_FLOOR_F32 : FILL_NOISE_FLOOR;
         if (dmax <= floor_ * floor_ * ass2)
             kk = 0;
+        else if constexpr (INLDS)
+            kk = wg_pivoted_cholesky_ll(W, M, L.eps, L.fixed_rank, to_lds(perm), to_lds(pos_sh));
         else
             kk = wg_pivoted_cholesky(W, M, L.eps, L.fixed_rank, to_lds(perm), dsh_l, to_lds(isc));
         if (kk > 0 && kk < M) {
             // P R_k^T in the unknowns' order (through X), then its orthonormal
             // factor U with a positive diagonal
             const int lane = tid & 63, nw = blockDim.x >> 6;
-            for (int j = tid >> 6; j < kk; j += nw)
-                for (int i = lane; i < M; i += 64) X[perm[i] + (int64_t)j * M] = (i >= j) ? W[i + (int64_t)j * M] : 0.0;
+            if constexpr (INLDS) {  // column j sits over column piv[j] of W
+                for (int j = tid >> 6; j < kk; j += nw)
+                    for (int u = lane; u < M; u += 64)
+                        X[u + (int64_t)j * M] = (pos_sh[u] >= j) ? W[u + (int64_t)perm[j] * M] : 0.0;
+            } else {
+                for (int j = tid >> 6; j < kk; j += nw)
+                    for (int i = lane; i < M; i += 64)
+                        X[perm[i] + (int64_t)j * M] = (i >= j) ? W[i + (int64_t)j * M] : 0.0;
+            }
             __syncthreads();
             bool done = false;
             done = wg_cholqr2(X, M, kk, W, Linv, Uinv, Umat, sm_l, scr, red_l, to_lds(isc + 1), CHOLQR_ONE_PASS);
@@ -687,7 +790,7 @@ __global__ void __launch_bounds__(WG, 5) k_schur(LevelDev L, ColourDev C) {
     auto lb = [&](int k, int c) { return (c0 + c < nt && k < f) ? ER[k + (int64_t)(c0 + c) * M] : (T)0; };
     std::conditional_t<F64, v4d, v4f> acc[2][2];
     if constexpr (F64)
-        mfma_tile64(f, la, lb, to_lds(&sm), acc);
+        mfma_tile64(f, la, lb, to_lds(&sm), acc, nt - r0, nt - c0);
     else
         mfma_tile64_bf16(f, la, lb, to_lds(&sm), acc);
     __syncthreads();

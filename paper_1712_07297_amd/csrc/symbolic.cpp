@@ -104,7 +104,7 @@ int colour_distance2(int ncl, const std::vector<int>& ptr, const std::vector<int
 // of 64-bit words (row scans skip empty words and walk set bits).
 class Pattern {
    public:
-    explicit Pattern(int n) : n_(n), w_((n + 63) >> 6), dense_(n <= DENSE_MAX) {
+    explicit Pattern(int n) : w_((n + 63) >> 6), dense_(n <= DENSE_MAX) {
         if (dense_)
             bits_.assign((size_t)n * w_, 0);
         else
@@ -137,7 +137,7 @@ class Pattern {
     }
 
    private:
-    int n_, w_;
+    int w_;
     bool dense_;
     std::vector<uint64_t> bits_;
     std::vector<std::vector<int>> rows_;
