@@ -115,9 +115,17 @@ def run_form(P, torch, p, rp, ci, va, B, X, precision, steps, warmup, n, profile
     """Warm-up, then `steps` timed steps of one precision form; returns its
     record (time, convergence, Schur roofline)."""
 
+    split = {"factor": 0.0, "solve": 0.0}
+
     def step():
+        t0 = time.perf_counter()
         F = P.Factor(rp, ci, va, p.dims, p.eps, p.leaf, symmetric=1, precision=precision)
+        t1 = time.perf_counter()
         _, it, rel, ok = F.pcg(B, p.tol, 200, X=X)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        split["factor"] += t1 - t0
+        split["solve"] += t2 - t1
         info = F.info()
         F.free()
         return it, rel, ok, info
@@ -133,6 +141,7 @@ def run_form(P, torch, p, rp, ci, va, B, X, precision, steps, warmup, n, profile
     P.profile_select("" if profile else ("schur_f32" if precision == P.HS_MIXED else "schur"))
     P.profile_enable(True)
     torch.cuda.synchronize()
+    split["factor"] = split["solve"] = 0.0
     t0 = time.perf_counter()
     its, rels, oks = [], [], []
     info = None
@@ -160,6 +169,8 @@ def run_form(P, torch, p, rp, ci, va, B, X, precision, steps, warmup, n, profile
     rec = {
         "value": n * steps / dt,
         "ms_per_step": dt / steps * 1e3,
+        "factor_ms": split["factor"] / steps * 1e3,
+        "solve_ms": split["solve"] / steps * 1e3,
         "pcg_iterations": its,
         "relres_max": max(rels),
         "relres_check": relres,
@@ -473,6 +484,8 @@ def main():
         "config": {
             "workload": f"3D 7-point Poisson {args.side}^3 (N={n}), leaf 64, eps 1e-4, PCG preconditioner, {args.nrhs} RHS to relative residual 1e-10",
             "form": head_name,
+            "factor_ms": head["factor_ms"],
+            "solve_ms": head["solve_ms"],
             "pcg_iterations": head["pcg_iterations"],
             "relres_max": head["relres_max"],
             "relres_check": head["relres_check"],

@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 namespace hs {
 
@@ -177,11 +178,35 @@ __device__ inline int block_min_int(int v, PR red) {
 // ------------------------------------------------------------ cooperative copy
 // Columns over waves, rows over lanes (no integer division in the loops).
 
+// Workgroup copy of n elements: st(e, ld(e)) for e < n.  Every thread has
+// U loads in flight before it stores any (a loop of load-store pairs would
+// wait out the full memory latency once per element).  The loads are
+// unconditional (the index is clamped), so they issue back to back.
+template <int U = 8, class LD, class ST>
+__device__ inline void wg_stage(int n, const LD& ld, const ST& st) {
+    if (n <= 0) return;
+    for (int b = threadIdx.x; b < n; b += blockDim.x * U) {
+        decltype(ld(0)) v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = ld(min(b + u * (int)blockDim.x, n - 1));
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = b + u * (int)blockDim.x;
+            if (e < n) st(e, v[u]);
+        }
+    }
+}
+
 template <class PS, class PD>
 __device__ inline void wg_copy(int M, int N, PS src, int lds, PD dst, int ldd) {
-    const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
-    for (int j = threadIdx.x >> 6; j < N; j += nw)
-        for (int i = lane; i < M; i += 64) dst[i + (int64_t)j * ldd] = src[i + (int64_t)j * lds];
+    if (M <= 0 || N <= 0) return;
+    if (lds == M && ldd == M) {  // both packed: one contiguous range
+        wg_stage(M * N, [&](int e) { return src[e]; }, [&](int e, auto v) { dst[e] = v; });
+        return;
+    }
+    wg_stage(
+        M * N, [&](int e) { return src[(e % M) + (int64_t)(e / M) * lds]; },
+        [&](int e, auto v) { dst[(e % M) + (int64_t)(e / M) * ldd] = v; });
 }
 template <class PD>
 __device__ inline void wg_zero(int M, int N, PD dst, int ldd) {
@@ -209,17 +234,19 @@ typedef __attribute__((address_space(3))) MfmaSmem lds_smem;
 __device__ inline lds_smem* to_lds(MfmaSmem* p) { return (lds_smem*)p; }
 
 // la(r, k) / lb(k, c) return the operand element or 0 outside the matrix.
-// Accumulates into acc (acc += Left * Right).  Only the first rv rows and cv
-// columns of the tile are wanted: a wave skips the matrix-core work of its
-// 16 x 16 blocks that lie wholly beyond them (the skip is uniform per wave,
-// and the accumulators of skipped blocks are left as they were).
-template <class LoadL, class LoadR>
+// Accumulates into acc (acc += Left * Right).  With PART, only the first rv
+// rows and cv columns of the tile are wanted: a wave then skips the
+// matrix-core work of its 16 x 16 blocks that lie wholly beyond them (the
+// skip is uniform per wave; skipped accumulators keep their values).
+template <bool PART = false, class LoadL, class LoadR>
 __device__ inline void mfma_tile64_acc(int K, const LoadL& la, const LoadR& lb, lds_smem* sm, v4d acc[2][2],
                                        int rv = MT, int cv = MT) {
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wm = (w & 1) * 32, wn = (w >> 1) * 32;
     const int lr = lane & 15, lk = lane >> 4;
-    const bool ri[2] = {wm < rv, wm + 16 < rv}, cj[2] = {wn < cv, wn + 16 < cv};
+    // 3: 2 x 2 blocks wanted, 2: 1 x 2, 1: 2 x 1, 0: 1 x 1, -1: none
+    const int shape =
+        PART ? ((wm < rv && wn < cv) ? ((wm + 16 < rv) ? 1 : 0) + ((wn + 16 < cv) ? 2 : 0) : -1) : 3;
     // each thread stages 4 elements of each operand per K chunk; the next
     // chunk is fetched into registers while the matrix cores work on this one
     constexpr int PER = MT * MKC / WG;
@@ -234,6 +261,24 @@ __device__ inline void mfma_tile64_acc(int K, const LoadL& la, const LoadR& lb, 
             rb[t] = (k0 + kb < K) ? lb(k0 + kb, c) : 0.0;
         }
     };
+    // straight-line matrix-core code for an NI x NJ block shape
+    auto steps = [&](auto NI, auto NJ) {
+#pragma unroll
+        for (int ks = 0; ks < MKC; ks += 4) {
+            double av[2], bv[2];
+#pragma unroll
+            for (int i = 0; i < NI; ++i) av[i] = sm->a[ks + lk][wm + 16 * i + lr];
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) bv[j] = sm->b[ks + lk][wn + 16 * j + lr];
+#pragma unroll
+            for (int i = 0; i < NI; ++i)
+#pragma unroll
+                for (int j = 0; j < NJ; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[j], av[i], acc[i][j], 0, 0, 0);
+        }
+    };
+    using one = std::integral_constant<int, 1>;
+    using two = std::integral_constant<int, 2>;
     if (K > 0) fetch(0);
     for (int k0 = 0; k0 < K; k0 += MKC) {
         __syncthreads();
@@ -245,19 +290,28 @@ __device__ inline void mfma_tile64_acc(int K, const LoadL& la, const LoadR& lb, 
         }
         __syncthreads();
         if (k0 + MKC < K) fetch(k0 + MKC);
-        if (!ri[0] || !cj[0]) continue;  // nothing of this wave's quarter is wanted
+        if constexpr (!PART) {
 #pragma unroll
-        for (int ks = 0; ks < MKC; ks += 4) {
-            double av[2], bv[2];
+            for (int ks = 0; ks < MKC; ks += 4) {
+                double av[2], bv[2];
 #pragma unroll
-            for (int i = 0; i < 2; ++i) av[i] = sm->a[ks + lk][wm + 16 * i + lr];
+                for (int i = 0; i < 2; ++i) av[i] = sm->a[ks + lk][wm + 16 * i + lr];
 #pragma unroll
-            for (int j = 0; j < 2; ++j) bv[j] = sm->b[ks + lk][wn + 16 * j + lr];
+                for (int j = 0; j < 2; ++j) bv[j] = sm->b[ks + lk][wn + 16 * j + lr];
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
+                for (int i = 0; i < 2; ++i)
 #pragma unroll
-                for (int j = 0; j < 2; ++j)
-                    if (ri[i] && cj[j]) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[j], av[i], acc[i][j], 0, 0, 0);
+                    for (int j = 0; j < 2; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[j], av[i], acc[i][j], 0, 0, 0);
+            }
+        } else if (shape == 3) {
+            steps(two{}, two{});
+        } else if (shape == 2) {
+            steps(one{}, two{});
+        } else if (shape == 1) {
+            steps(two{}, one{});
+        } else if (shape == 0) {
+            steps(one{}, one{});
         }
     }
 }
@@ -270,11 +324,11 @@ __device__ inline void mfma_zero(v4d acc[2][2]) {
 }
 
 // acc = Left * Right.
-template <class LoadL, class LoadR>
+template <bool PART = false, class LoadL, class LoadR>
 __device__ inline void mfma_tile64(int K, const LoadL& la, const LoadR& lb, lds_smem* sm, v4d acc[2][2], int rv = MT,
                                    int cv = MT) {
     mfma_zero(acc);
-    mfma_tile64_acc(K, la, lb, sm, acc, rv, cv);
+    mfma_tile64_acc<PART>(K, la, lb, sm, acc, rv, cv);
 }
 
 // Visit the tile's results: f(row, col, value), row/col within the 64 x 64 tile.
@@ -428,7 +482,7 @@ __device__ void wg_gemm(int M, int N, int K, double alpha, PA A, int lda, PB B, 
     for (int r0 = 0; r0 < M; r0 += MT)
         for (int c0 = 0; c0 < N; c0 += MT) {
             v4d acc[2][2];
-            mfma_tile64(
+            mfma_tile64<true>(
                 K,
                 [&](int r, int k) {
                     const int gr = r0 + r;
@@ -466,7 +520,7 @@ __device__ void wg_gemm_fn(int M, int N, int K, const LA& la, const LB& lb, lds_
     for (int r0 = 0; r0 < M; r0 += MT)
         for (int c0 = 0; c0 < N; c0 += MT) {
             v4d acc[2][2];
-            mfma_tile64(
+            mfma_tile64<true>(
                 K, [&](int r, int k) { return r0 + r < M ? la(r0 + r, k) : 0.0; },
                 [&](int k, int c) { return c0 + c < N ? lb(k, c0 + c) : 0.0; }, sm, acc, M - r0, N - c0);
             mfma_tile64_store(acc, [&](int r, int c, double v) {

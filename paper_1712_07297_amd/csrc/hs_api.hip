@@ -327,8 +327,8 @@ struct ColourHost {
     std::vector<ListPlan> fac_plan[2];
     std::vector<ColourDev> fac[2];                 // factor lists (chunks)
     ColourDev sol[2];
-    const int64_t* part_off[2] = {nullptr, nullptr};  // [nbr entries + 1] in units of f
-    int64_t part_total[2] = {0, 0};                // sum of f over the entries
+    const int64_t* part_off[2] = {nullptr, nullptr};  // [neighbour groups + 1] in units of f
+    int64_t part_total[2] = {0, 0};                // sum of f over the groups
 };
 
 struct LevelData {
@@ -795,8 +795,11 @@ static int factor_dense_ranges(hs_factor_s* F, int lvl, const std::vector<std::a
     if (!aux.alloc(b.data.size())) return fail(HS_ERR_NOMEM, "dense level");
     if (maxN > 0 && !dense.alloc((size_t)maxN * maxN * sizeof(double)))
         return fail(HS_ERR_NOMEM, "dense level matrix");
-    // the blob stays alive in aux; copies out of it are device to device
-    HIP_TRY(hipMemcpy(aux.p, b.data.data(), b.data.size(), hipMemcpyHostToDevice));
+    // the blob stays alive in aux; copies out of it are device to device.
+    // Copies are stream-ordered: a legacy-stream copy would synchronise with
+    // a graph capture that another thread may be running.
+    HIP_TRY(hipMemcpyAsync(aux.p, b.data.data(), b.data.size(), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
     char* base = aux.as<char>();
     dflag = (int*)(base + o_flag);
     double* inv = (double*)(base + o_inv);
@@ -965,7 +968,8 @@ static int factor_impl(hs_factor_s* F, int nsys, const hs_csr* A, const hs_geome
         const size_t o_ro = sb.add(row_off), o_cs = sb.add(chunk_sys), o_cr = sb.add(chunk_r0),
                      o_sc = sb.add(sys_chunk0);
         if (!F->seg_buf.alloc(sb.data.size())) return fail(HS_ERR_NOMEM, "segment tables");
-        HIP_TRY(hipMemcpy(F->seg_buf.p, sb.data.data(), sb.data.size(), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpyAsync(F->seg_buf.p, sb.data.data(), sb.data.size(), hipMemcpyHostToDevice, st));
+        HIP_TRY(hipStreamSynchronize(st));
         char* b = F->seg_buf.as<char>();
         F->segs.nsys = nsys;
         F->segs.nchunks = (int)chunk_sys.size();
@@ -1180,25 +1184,50 @@ static int factor_impl(hs_factor_s* F, int nsys, const hs_csr* A, const hs_geome
         const LevelSymbolic& S = F->sym.levels[lvl];
         Blob sb;
         size_t o_seg = sb.add(LD.seg);
-        std::vector<std::array<size_t, 2>> o_part(LD.colours.size());
+        // neighbour groups of the backward sweep: consecutive entries of a
+        // cluster's list up to SOLVE_GROUP_COLS columns of E_R and
+        // SOLVE_GROUP_ENTRIES entries; one f x nrhs partial per group
+        struct GroupPlan {
+            size_t part, pre, e0, e1;
+        };
+        std::vector<std::array<GroupPlan, 2>> o_grp(LD.colours.size());
         LD.part_max = 0;
         for (size_t c = 0; c < LD.colours.size(); ++c) {
             ColourHost& CH = LD.colours[c];
             for (int t = 0; t < 2; ++t) {
                 std::vector<int64_t> po;
+                std::vector<int> pre(1, 0), ge0, ge1;
                 int64_t acc = 0;
                 for (int i = 0; i < CH.n_t[t]; ++i) {
                     const int s = LD.order_host[CH.first + (t ? CH.n_t[0] : 0) + i];
                     const int f = LD.m[s] - LD.k[s];
-                    for (int e = S.adj_ptr[s]; e < S.adj_ptr[s + 1]; ++e) {
-                        po.push_back(acc);
-                        acc += f;
+                    int ng = 0;
+                    if (LD.m[s] > 0 && f > 0) {
+                        int cols = 0;
+                        for (int e = S.adj_ptr[s]; e < S.adj_ptr[s + 1]; ++e) {
+                            const int a = S.adj[e];
+                            const int ca = S.pos[a] < S.pos[s] ? LD.k[a] : LD.m[a];
+                            const bool open = ng > 0 && ge1.back() == e;
+                            if (open && cols + ca <= SOLVE_GROUP_COLS && e - ge0.back() < SOLVE_GROUP_ENTRIES) {
+                                ge1.back() = e + 1;
+                                cols += ca;
+                            } else {
+                                ge0.push_back(e);
+                                ge1.push_back(e + 1);
+                                po.push_back(acc);
+                                acc += f;
+                                cols = ca;
+                                ++ng;
+                            }
+                        }
                     }
+                    pre.push_back(pre.back() + ng);
                 }
                 po.push_back(acc);
                 CH.part_total[t] = acc;
+                CH.sol[t].grp_total = pre.back();
                 LD.part_max = std::max(LD.part_max, acc);
-                o_part[c][t] = sb.add(po);
+                o_grp[c][t] = {sb.add(po), sb.add(pre), sb.add(ge0), sb.add(ge1)};
             }
         }
         // keep the solve metadata next to the level metadata
@@ -1207,7 +1236,14 @@ static int factor_impl(hs_factor_s* F, int nsys, const hs_csr* A, const hs_geome
         HIP_TRY(hipMemcpyAsync(buf.p, sb.data.data(), sb.data.size(), hipMemcpyHostToDevice, st));
         LD.sdev.seg = (const int64_t*)(buf.as<char>() + o_seg);
         for (size_t c = 0; c < LD.colours.size(); ++c)
-            for (int t = 0; t < 2; ++t) LD.colours[c].part_off[t] = (const int64_t*)(buf.as<char>() + o_part[c][t]);
+            for (int t = 0; t < 2; ++t) {
+                ColourHost& CH = LD.colours[c];
+                const char* b = buf.as<char>();
+                CH.part_off[t] = (const int64_t*)(b + o_grp[c][t].part);
+                CH.sol[t].grp_pre = (const int*)(b + o_grp[c][t].pre);
+                CH.sol[t].grp_e0 = (const int*)(b + o_grp[c][t].e0);
+                CH.sol[t].grp_e1 = (const int*)(b + o_grp[c][t].e1);
+            }
         LD.blocks = std::move(buf);  // the block store slot now owns the solve metadata
         for (int c = 0; c < LD.ncl; ++c) {
             const double m = LD.m[c], k = LD.k[c], f = m - k;
@@ -1326,19 +1362,33 @@ static int solve_chunk(hs_factor_s* F, int nrhs, const double* B, int64_t ldb, d
         if (!ex) {
             if (!F->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&F->cap_stream, hipStreamNonBlocking));
             hipGraph_t g = nullptr;
+            bool ok;
             {
                 std::lock_guard<std::mutex> lk(g_capture_mu);
-                HIP_TRY(hipStreamBeginCapture(F->cap_stream, hipStreamCaptureModeThreadLocal));
-                solve_sweeps(F, nrhs, F->cap_stream);
-                HIP_TRY(hipStreamEndCapture(F->cap_stream, &g));
+                ok = hipStreamBeginCapture(F->cap_stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+                if (ok) {
+                    solve_sweeps(F, nrhs, F->cap_stream);
+                    ok = hipStreamEndCapture(F->cap_stream, &g) == hipSuccess && g;
+                }
             }
-            const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(g);
-            HIP_TRY(e);
-            F->sweeps.push_back({nrhs, ex});
+            if (ok) ok = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) == hipSuccess;
+            if (g) (void)hipGraphDestroy(g);
+            if (ok) {
+                F->sweeps.push_back({nrhs, ex});
+            } else {
+                // a capture can be invalidated from outside (for instance by
+                // work another thread puts on the legacy default stream):
+                // nothing it recorded ran, so the sweeps run launch by launch
+                (void)hipGetLastError();
+                ex = nullptr;
+            }
         }
-        HIP_TRY(hipGraphLaunch(ex, st));
-        F->sweep_stream = st;
+        if (ex) {
+            HIP_TRY(hipGraphLaunch(ex, st));
+            F->sweep_stream = st;
+        } else {
+            solve_sweeps(F, nrhs, st);
+        }
     }
     launch_gather_sol(F->n, F->cluster_of.as<int>(), F->local_of.as<int>(), L0.sdev.seg, L0.dev.m, O0, X, ldx, nrhs,
                       st);

@@ -83,12 +83,12 @@ __global__ void __launch_bounds__(WG) k_dense_panels(double* __restrict__ D, int
         if (h >= halves) break;
         const int hh = h * MT, hw = min(MT, nb - hh);
         if (colpanel)
-            mfma_tile64(
+            mfma_tile64<true>(
                 nb, [&](int r, int k) { return (r < hw) ? Linv[(hh + r) + (int64_t)k * DNB] : 0.0; },
                 [&](int k, int c) { return (q0 + c < N) ? D[(p + k) + (int64_t)(q0 + c) * ldd] : 0.0; }, to_lds(&sm),
                 acc[h], hw, N - q0);
         else
-            mfma_tile64(
+            mfma_tile64<true>(
                 nb, [&](int r, int k) { return (q0 + r < N) ? D[(q0 + r) + (int64_t)(p + k) * ldd] : 0.0; },
                 [&](int k, int c) { return (c < hw) ? Uinv[k + (int64_t)(hh + c) * DNB] : 0.0; }, to_lds(&sm), acc[h],
                 N - q0, hw);
@@ -118,7 +118,7 @@ __global__ void __launch_bounds__(WG) k_dense_trailing(double* __restrict__ D, i
     const int tiles = (N - q + MT - 1) / MT;
     const int r0 = q + (blockIdx.x % tiles) * MT, c0 = q + (blockIdx.x / tiles) * MT;
     v4d acc[2][2];
-    mfma_tile64(
+    mfma_tile64<true>(
         nb, [&](int r, int k) { return (r0 + r < N) ? D[(r0 + r) + (int64_t)(p + k) * ldd] : 0.0; },
         [&](int k, int c) { return (c0 + c < N) ? D[(p + k) + (int64_t)(c0 + c) * ldd] : 0.0; }, to_lds(&sm), acc,
         N - r0, N - c0);

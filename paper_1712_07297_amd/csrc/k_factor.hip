@@ -79,14 +79,14 @@ __global__ void __launch_bounds__(WG) k_gram(LevelDev L, const int* __restrict__
                 const int ct = cur_size(L, t, L.fill_before[e]);
                 if (ct == 0) continue;
                 const T* Bst = blk_t<T>(L, L.fill_bst[e]);  // M x ct, ld M
-                mfma_tile64_acc(
+                mfma_tile64_acc<true>(
                     ct, [&](int r, int k) { return r0 + r < M ? Bst[(r0 + r) + (int64_t)k * M] : 0.0; },
                     [&](int k, int c) { return c0 + c < M ? Bst[(c0 + c) + (int64_t)k * M] : 0.0; }, sm_l, acc, M - r0,
                     M - c0);
                 if (!L.symmetric) {
                     const int mt = L.m[t];
                     const T* Bts = blk_t<T>(L, L.fill_bts[e]);  // ct x M, ld m_t
-                    mfma_tile64_acc(
+                    mfma_tile64_acc<true>(
                         ct, [&](int r, int k) { return r0 + r < M ? Bts[k + (int64_t)(r0 + r) * mt] : 0.0; },
                         [&](int k, int c) { return c0 + c < M ? Bts[k + (int64_t)(c0 + c) * mt] : 0.0; }, sm_l, acc,
                         M - r0, M - c0);
@@ -457,10 +457,11 @@ __global__ void __launch_bounds__(WG, 2) k_pivot(LevelDev L, const int* __restri
         kk = M;  // exact mode
     } else {
         double ass2 = 0.0;  // ||A_ss||_F^2 (noise floor of the fill)
-        for (int64_t e = tid; e < MM; e += blockDim.x) ass2 = fma((double)Bss[e], (double)Bss[e], ass2);
+        wg_stage((int)MM, [&](int e) { return (double)Bss[e]; }, [&](int, double v) { ass2 = fma(v, v, ass2); });
         ass2 = block_sum(ass2, red_l);
         // W = the Gram matrix (partials already summed into the first slot)
-        for (int64_t e = tid; e < MM; e += blockDim.x) W[e] = ws[WS_GP * MM + e];
+        const double* Gp = ws + WS_GP * MM;
+        wg_stage((int)MM, [&](int e) { return Gp[e]; }, [&](int e, double v) { W[e] = v; });
         __syncthreads();
         // fill at the rounding level of A_ss is noise: treat it as zero
         double dmax = 0.0;
@@ -790,7 +791,7 @@ __global__ void __launch_bounds__(WG, 5) k_schur(LevelDev L, ColourDev C) {
     auto lb = [&](int k, int c) { return (c0 + c < nt && k < f) ? ER[k + (int64_t)(c0 + c) * M] : (T)0; };
     std::conditional_t<F64, v4d, v4f> acc[2][2];
     if constexpr (F64)
-        mfma_tile64(f, la, lb, to_lds(&sm), acc, nt - r0, nt - c0);
+        mfma_tile64(f, la, lb, to_lds(&sm), acc);
     else
         mfma_tile64_bf16(f, la, lb, to_lds(&sm), acc);
     __syncthreads();

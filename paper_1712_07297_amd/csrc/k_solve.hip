@@ -29,12 +29,71 @@ __device__ inline int find_pre(const int* pre, int n, int q) {
     return lo;
 }
 
+// ------------------------------------------------------- staged products
+// The record operands pass through LDS in tiles of at most TILE_BYTES (read
+// once from memory, coalesced), so the long dot products read LDS and not
+// memory; a thread holds at most OUT_PER_THREAD running sums.
+constexpr int TILE_BYTES = 32768;
+constexpr int OUT_PER_THREAD = 4;
+constexpr int OUT_CAP = OUT_PER_THREAD * WG;
+
+// out(i, r) = sum_{l < K} A(i, l) X(l, r) for i < R, r < nrhs, every sum taken
+// from zero in ascending l.  la(i, l) loads A from memory (consecutive i are
+// consecutive addresses), lx(l, r) reads X (LDS), store(i, r, v) receives
+// each result once.  abuf: TILE_BYTES of LDS.  Ends with a barrier.
+template <class T, class LA, class LX, class ST>
+__device__ void wg_rows_times(int R, int K, int nrhs, const LA& la, const LX& lx, T* abuf, const ST& store) {
+    const int tid = threadIdx.x;
+    const int RR = min(nrhs, OUT_CAP);
+    const int RJ = max(1, min(R, OUT_CAP / max(RR, 1)));
+    constexpr int ABUF_N = TILE_BYTES / (int)sizeof(T);
+    for (int r0 = 0; r0 < nrhs; r0 += RR) {
+        const int rr = min(RR, nrhs - r0);
+        for (int i0 = 0; i0 < R; i0 += RJ) {
+            const int rj = min(RJ, R - i0);
+            const int CC = max(1, min(K, ABUF_N / rj));
+            double acc[OUT_PER_THREAD];
+#pragma unroll
+            for (int t = 0; t < OUT_PER_THREAD; ++t) acc[t] = 0.0;
+            for (int l0 = 0; l0 < K; l0 += CC) {
+                const int cc = min(CC, K - l0);
+                __syncthreads();
+                wg_stage(
+                    rj * cc, [&](int e) { return la(i0 + e % rj, l0 + e / rj); }, [&](int e, T v) { abuf[e] = v; });
+                __syncthreads();
+#pragma unroll
+                for (int t = 0; t < OUT_PER_THREAD; ++t) {
+                    const int x = tid + t * WG;
+                    if (x < rj * rr) {
+                        const int i = x % rj, r = r0 + x / rj;
+                        double a = acc[t];
+#pragma unroll 4
+                        for (int l = 0; l < cc; ++l) a = fma((double)abuf[i + l * rj], lx(l0 + l, r), a);
+                        acc[t] = a;
+                    }
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < OUT_PER_THREAD; ++t) {
+                const int x = tid + t * WG;
+                if (x < rj * rr) store(i0 + x % rj, r0 + x / rj, acc[t]);
+            }
+        }
+    }
+    __syncthreads();
+}
+
+template <class T>
+__device__ inline T* tile_buf(double* after) {
+    return reinterpret_cast<T*>(after);
+}
+
 // ---------------------------------------------------------------- forward
 
 template <class T>
 __global__ void __launch_bounds__(WG) k_apply_fwd_t(SolveLevelDev S, ColourDev C, const double* __restrict__ y,
                                                     double* __restrict__ z, int nrhs) {
-    extern __shared__ double ys[];
+    extern __shared__ double ys[];  // max_m x nrhs, then the operand tile
     const int s = C.clist[blockIdx.x];
     const int M = S.m[s];
     if (M == 0) return;
@@ -43,24 +102,22 @@ __global__ void __launch_bounds__(WG) k_apply_fwd_t(SolveLevelDev S, ColourDev C
     double* zdst = z + S.seg[s] * nrhs;
     const int tot = M * nrhs;
     if (kk == M) {
-        for (int x = threadIdx.x; x < tot; x += blockDim.x) zdst[x] = ysrc[x];
+        wg_stage(tot, [&](int x) { return ysrc[x]; }, [&](int x, double v) { zdst[x] = v; });
         return;
     }
-    for (int x = threadIdx.x; x < tot; x += blockDim.x) ys[x] = ysrc[x];
-    __syncthreads();
+    wg_stage(tot, [&](int x) { return ysrc[x]; }, [&](int x, double v) { ys[x] = v; });
     const T* TL = srec<T>(S, s);
-    for (int x = threadIdx.x; x < tot; x += blockDim.x) {
-        const int i = x % M, r = x / M;
-        double acc = 0.0;
-        for (int l = 0; l < M; ++l) acc = fma((double)TL[i + (int64_t)l * M], ys[l + r * M], acc);
-        zdst[x] = acc;
-    }
+    wg_rows_times<T>(
+        M, M, nrhs, [&](int i, int l) { return TL[i + (int64_t)l * M]; }, [&](int l, int r) { return ys[l + r * M]; },
+        tile_buf<T>(ys + (size_t)C.max_m * nrhs), [&](int i, int r, double v) { zdst[i + r * M] = v; });
 }
+
+static size_t tile_shmem(size_t doubles) { return doubles * sizeof(double) + TILE_BYTES; }
 
 void launch_apply_fwd_t(const SolveLevelDev& S, const ColourDev& C, const double* y, double* z, int nrhs,
                         hipStream_t st) {
     if (C.n == 0) return;
-    const size_t sh = (size_t)C.max_m * nrhs * sizeof(double);
+    const size_t sh = tile_shmem((size_t)C.max_m * nrhs);
     if (C.f32)
         hipLaunchKernelGGL(k_apply_fwd_t<float>, dim3(C.n), dim3(WG), sh, st, S, C, y, z, nrhs);
     else
@@ -72,7 +129,7 @@ constexpr int UROWS = 64;
 template <class T>
 __global__ void __launch_bounds__(WG) k_apply_fwd_u(SolveLevelDev S, ColourDev C, double* __restrict__ y,
                                                     double* __restrict__ z, int nrhs) {
-    extern __shared__ double zf[];
+    extern __shared__ double zf[];  // max_m x nrhs, then the operand tile
     const int q = blockIdx.y;
     const int ci = find_pre(C.nbr_pre, C.n, q);
     const int s = C.clist[ci];
@@ -89,22 +146,14 @@ __global__ void __launch_bounds__(WG) k_apply_fwd_u(SolveLevelDev S, ColourDev C
     if (r0 >= ca) return;
     const int nr = min(UROWS, ca - r0);
     const double* zs = z + S.seg[s] * nrhs;
-    for (int x = threadIdx.x; x < f * nrhs; x += blockDim.x) {
-        const int j = x % f, r = x / f;
-        zf[x] = zs[j + r * M];
-    }
-    __syncthreads();
+    wg_stage(
+        f * nrhs, [&](int x) { return zs[(x % f) + (x / f) * M]; }, [&](int x, double v) { zf[x] = v; });
     const int ncap = S.ncap[s];
-    const T* EL = srec<T>(S, s) + 2 * (int64_t)M * M + (int64_t)M * ncap;  // ld ncap
-    const int off = S.nbr_noff[e];
-    double* tgt = before ? z + S.seg[a] * nrhs + (ma - ca) : y + S.seg[a] * nrhs;  // ld ma
-    for (int x = threadIdx.x; x < nr * nrhs; x += blockDim.x) {
-        const int i = x % nr, r = x / nr;
-        double acc = 0.0;
-        const T* row = EL + off + r0 + i;
-        for (int j = 0; j < f; ++j) acc = fma((double)row[(int64_t)j * ncap], zf[j + r * f], acc);
-        tgt[r0 + i + (int64_t)r * ma] -= acc;
-    }
+    const T* EL = srec<T>(S, s) + 2 * (int64_t)M * M + (int64_t)M * ncap + S.nbr_noff[e] + r0;  // ld ncap
+    double* tgt = (before ? z + S.seg[a] * nrhs + (ma - ca) : y + S.seg[a] * nrhs) + r0;    // ld ma
+    wg_rows_times<T>(
+        nr, f, nrhs, [&](int i, int j) { return EL[i + (int64_t)j * ncap]; }, [&](int j, int r) { return zf[j + r * f]; },
+        tile_buf<T>(zf + (size_t)C.max_m * nrhs), [&](int i, int r, double v) { tgt[i + (int64_t)r * ma] -= v; });
 }
 
 void launch_apply_fwd_u(const SolveLevelDev& S, const ColourDev& C, double* y, double* z, int nrhs, int max_m,
@@ -113,7 +162,7 @@ void launch_apply_fwd_u(const SolveLevelDev& S, const ColourDev& C, double* y, d
     const int chunks = (C.max_nbr_m + UROWS - 1) / UROWS;
     if (chunks == 0) return;
     (void)max_m;
-    const size_t sh = (size_t)C.max_m * nrhs * sizeof(double);
+    const size_t sh = tile_shmem((size_t)C.max_m * nrhs);
     if (C.f32)
         hipLaunchKernelGGL(k_apply_fwd_u<float>, dim3(chunks, C.nbr_total), dim3(WG), sh, st, S, C, y, z, nrhs);
     else
@@ -122,49 +171,106 @@ void launch_apply_fwd_u(const SolveLevelDev& S, const ColourDev& C, double* y, d
 
 // --------------------------------------------------------------- backward
 
+// One workgroup per neighbour group of a cluster: part = E_R[:, cols] x over
+// the group's columns (consecutive in E_R), each sum from zero in column order.
+// The x values of a column chunk are gathered into LDS beside the E_R tile.
+constexpr int XBUF_DOUBLES = 4096;
+
 template <class T>
 __global__ void __launch_bounds__(WG) k_apply_bwd_acc(SolveLevelDev S, ColourDev C, const double* __restrict__ z,
                                                       const double* __restrict__ out, double* __restrict__ part,
                                                       const int64_t* __restrict__ part_off, int nrhs) {
-    extern __shared__ double xs[];
-    const int q = blockIdx.x;
-    const int ci = find_pre(C.nbr_pre, C.n, q);
+    extern __shared__ double xsb[];  // XBUF_DOUBLES, then the E_R tile
+    __shared__ int tab_c[SOLVE_GROUP_ENTRIES + 1];
+    __shared__ int tab_ld[SOLVE_GROUP_ENTRIES];
+    __shared__ const double* tab_src[SOLVE_GROUP_ENTRIES];
+    const int g = blockIdx.x;
+    const int ci = find_pre(C.grp_pre, C.n, g);
     const int s = C.clist[ci];
-    const int e = S.nbr_ptr[s] + (q - C.nbr_pre[ci]);
     const int M = S.m[s];
-    const int kk = S.k[s];
-    const int f = M - kk;
+    const int f = M - S.k[s];
     if (M == 0 || f == 0) return;
-    const int a = S.nbr_id[e];
-    const int before = S.nbr_before[e];
-    const int ma = S.m[a];
-    const int ca = before ? S.k[a] : ma;
-    double* dst = part + part_off[q] * nrhs;  // f x nrhs
-    const double* src = before ? z + S.seg[a] * nrhs + (ma - ca) : out + S.seg[a] * nrhs;  // ld ma
-    for (int x = threadIdx.x; x < ca * nrhs; x += blockDim.x) {
-        const int i = x % ca, r = x / ca;
-        xs[x] = src[i + (int64_t)r * ma];
+    const int e0 = C.grp_e0[g], e1 = C.grp_e1[g], ne = e1 - e0;
+    const int tid = threadIdx.x;
+    if (tid < ne) {
+        const int e = e0 + tid;
+        const int a = S.nbr_id[e];
+        const int ma = S.m[a];
+        const int before = S.nbr_before[e];
+        const int ca = before ? S.k[a] : ma;
+        tab_c[tid + 1] = S.nbr_noff[e] - S.nbr_noff[e0] + ca;
+        tab_ld[tid] = ma;
+        tab_src[tid] = before ? z + S.seg[a] * nrhs + (ma - ca) : out + S.seg[a] * nrhs;
     }
+    if (tid == 0) tab_c[0] = 0;
     __syncthreads();
-    const T* ER = srec<T>(S, s) + 2 * (int64_t)M * M;  // ld M
-    const int off = S.nbr_noff[e];
-    for (int x = threadIdx.x; x < f * nrhs; x += blockDim.x) {
-        const int j = x % f, r = x / f;
-        double acc = 0.0;
-        for (int i = 0; i < ca; ++i) acc = fma((double)ER[j + (int64_t)(off + i) * M], xs[i + r * ca], acc);
-        dst[x] = acc;
+    const int ncols = tab_c[ne];
+    const T* ER = srec<T>(S, s) + 2 * (int64_t)M * M + (int64_t)S.nbr_noff[e0] * M;  // ld M
+    double* dst = part + part_off[g] * nrhs;                                           // f x nrhs
+    T* abuf = tile_buf<T>(xsb + XBUF_DOUBLES);
+    constexpr int ABUF_N = TILE_BYTES / (int)sizeof(T);
+    const int RR = min(nrhs, OUT_CAP);
+    const int RJ = max(1, min(f, OUT_CAP / RR));
+    for (int r0 = 0; r0 < nrhs; r0 += RR) {
+        const int rr = min(RR, nrhs - r0);
+        for (int j0 = 0; j0 < f; j0 += RJ) {
+            const int rj = min(RJ, f - j0);
+            const int CC = max(1, min(max(ncols, 1), min(ABUF_N / rj, XBUF_DOUBLES / rr)));
+            double acc[OUT_PER_THREAD];
+#pragma unroll
+            for (int t = 0; t < OUT_PER_THREAD; ++t) acc[t] = 0.0;
+            for (int c0 = 0; c0 < ncols; c0 += CC) {
+                const int cc = min(CC, ncols - c0);
+                __syncthreads();
+                wg_stage(
+                    rj * cc, [&](int x) { return ER[(j0 + x % rj) + (int64_t)(c0 + x / rj) * M]; },
+                    [&](int x, T v) { abuf[x] = v; });
+                wg_stage(
+                    cc * rr,
+                    [&](int x) {
+                        const int c = c0 + x % cc, r = r0 + x / cc;
+                        int lo = 0, hi = ne;  // the entry holding column c: tab_c[lo] <= c < tab_c[lo + 1]
+                        while (hi - lo > 1) {
+                            const int mid = (lo + hi) >> 1;
+                            if (tab_c[mid] <= c)
+                                lo = mid;
+                            else
+                                hi = mid;
+                        }
+                        return tab_src[lo][(c - tab_c[lo]) + (int64_t)r * tab_ld[lo]];
+                    },
+                    [&](int x, double v) { xsb[x] = v; });
+                __syncthreads();
+#pragma unroll
+                for (int t = 0; t < OUT_PER_THREAD; ++t) {
+                    const int x = tid + t * WG;
+                    if (x < rj * rr) {
+                        const int j = x % rj, r = x / rj;
+                        double a = acc[t];
+#pragma unroll 4
+                        for (int l = 0; l < cc; ++l) a = fma((double)abuf[j + l * rj], xsb[l + r * cc], a);
+                        acc[t] = a;
+                    }
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < OUT_PER_THREAD; ++t) {
+                const int x = tid + t * WG;
+                if (x < rj * rr) dst[(j0 + x % rj) + (int64_t)(r0 + x / rj) * f] = acc[t];
+            }
+        }
     }
 }
 
 void launch_apply_bwd_acc(const SolveLevelDev& S, const ColourDev& C, const double* z, const double* out,
                           double* part, const int64_t* part_off, int nrhs, hipStream_t st) {
-    if (C.nbr_total == 0) return;
-    const size_t sh = (size_t)C.max_nbr_m * nrhs * sizeof(double);
+    if (C.grp_total == 0) return;
+    const size_t sh = tile_shmem(XBUF_DOUBLES);
     if (C.f32)
-        hipLaunchKernelGGL(k_apply_bwd_acc<float>, dim3(C.nbr_total), dim3(WG), sh, st, S, C, z, out, part, part_off,
+        hipLaunchKernelGGL(k_apply_bwd_acc<float>, dim3(C.grp_total), dim3(WG), sh, st, S, C, z, out, part, part_off,
                            nrhs);
     else
-        hipLaunchKernelGGL(k_apply_bwd_acc<double>, dim3(C.nbr_total), dim3(WG), sh, st, S, C, z, out, part, part_off,
+        hipLaunchKernelGGL(k_apply_bwd_acc<double>, dim3(C.grp_total), dim3(WG), sh, st, S, C, z, out, part, part_off,
                            nrhs);
 }
 
@@ -174,7 +280,7 @@ template <class T>
 __global__ void __launch_bounds__(WG) k_apply_bwd_t(SolveLevelDev S, ColourDev C, const double* __restrict__ z,
                                                     double* __restrict__ out, const double* __restrict__ part,
                                                     const int64_t* __restrict__ part_off, int nrhs) {
-    extern __shared__ double vs[];
+    extern __shared__ double vs[];  // max_m x nrhs, then the operand tile
     const int ci = blockIdx.x;
     const int s = C.clist[ci];
     const int M = S.m[s];
@@ -185,13 +291,13 @@ __global__ void __launch_bounds__(WG) k_apply_bwd_t(SolveLevelDev S, ColourDev C
     double* os = out + S.seg[s] * nrhs;
     const int tot = M * nrhs;
     if (f == 0) {
-        for (int x = threadIdx.x; x < tot; x += blockDim.x) os[x] = zs[x];
+        wg_stage(tot, [&](int x) { return zs[x]; }, [&](int x, double v) { os[x] = v; });
         return;
     }
-    // partials of the neighbours: offsets staged in LDS, the loads of one
-    // element issued eight at a time
+    // partials of the neighbour groups: offsets staged in LDS, the loads of
+    // one element issued eight at a time
     __shared__ int64_t poff[BWD_POFF];
-    const int q0 = C.nbr_pre[ci], q1 = C.nbr_pre[ci + 1];
+    const int q0 = C.grp_pre[ci], q1 = C.grp_pre[ci + 1];
     for (int q0c = q0; q0c < q1 || q0c == q0; q0c += BWD_POFF) {
         const int nq = min(BWD_POFF, q1 - q0c);
         __syncthreads();
@@ -216,20 +322,16 @@ __global__ void __launch_bounds__(WG) k_apply_bwd_t(SolveLevelDev S, ColourDev C
         }
         if (q1 - q0c <= BWD_POFF) break;
     }
-    __syncthreads();
     const T* TR = srec<T>(S, s) + (int64_t)M * M;  // T_R'
-    for (int x = threadIdx.x; x < tot; x += blockDim.x) {
-        const int i = x % M, r = x / M;
-        double acc = 0.0;
-        for (int l = 0; l < M; ++l) acc = fma((double)TR[i + (int64_t)l * M], vs[l + r * M], acc);
-        os[x] = acc;
-    }
+    wg_rows_times<T>(
+        M, M, nrhs, [&](int i, int l) { return TR[i + (int64_t)l * M]; }, [&](int l, int r) { return vs[l + r * M]; },
+        tile_buf<T>(vs + (size_t)C.max_m * nrhs), [&](int i, int r, double v) { os[i + r * M] = v; });
 }
 
 void launch_apply_bwd_t(const SolveLevelDev& S, const ColourDev& C, const double* z, double* out,
                         const double* part, const int64_t* part_off, int nrhs, hipStream_t st) {
     if (C.n == 0) return;
-    const size_t sh = (size_t)C.max_m * nrhs * sizeof(double);
+    const size_t sh = tile_shmem((size_t)C.max_m * nrhs);
     if (C.f32)
         hipLaunchKernelGGL(k_apply_bwd_t<float>, dim3(C.n), dim3(WG), sh, st, S, C, z, out, part, part_off, nrhs);
     else

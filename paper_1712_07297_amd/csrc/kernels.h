@@ -26,7 +26,17 @@ struct ColourDev {
     int max_m = 0;                    // largest cluster of the colour
     int max_nbr_m = 0;                // largest neighbour or fill partner of a cluster of the colour
     int f32 = 0;                      // the clusters' blocks and records are float32 (else float64)
+    // solve lists: the neighbours of every cluster cut into groups of
+    // consecutive entries (one backward partial per group)
+    const int* grp_pre = nullptr;     // [n+1] prefix of group counts
+    const int* grp_e0 = nullptr;      // [grp_total] first neighbour entry of the group
+    const int* grp_e1 = nullptr;      // [grp_total] one past its last entry
+    int grp_total = 0;
 };
+// neighbour groups of the backward sweep: at most this many columns of E_R
+// (unless one neighbour alone is wider) and this many entries
+constexpr int SOLVE_GROUP_COLS = 256;
+constexpr int SOLVE_GROUP_ENTRIES = 32;
 
 // ---- factorization, one colour at a time
 void launch_gram(const LevelDev& L, const ColourDev& C, hipStream_t st);
@@ -101,10 +111,11 @@ void launch_apply_fwd_t(const SolveLevelDev& S, const ColourDev& C, const double
 // neighbours: y_a (or z_a's coarse part) -= E_L[a] z_s[:f]
 void launch_apply_fwd_u(const SolveLevelDev& S, const ColourDev& C, double* y, double* z, int nrhs, int max_m,
                         hipStream_t st);
-// part[s][i] = E_R[:, a_i] x_a (current values); part_off in units of f (times nrhs)
+// part[g] = sum over the neighbours a of group g of E_R[:, a] x_a (current
+// values); part_off per group in units of f (times nrhs)
 void launch_apply_bwd_acc(const SolveLevelDev& S, const ColourDev& C, const double* z, const double* out,
                           double* part, const int64_t* part_off, int nrhs, hipStream_t st);
-// out_s = T_R' [z_f - sum_i part[s][i]; z_c]
+// out_s = T_R' [z_f - sum_g part[g]; z_c], the groups of s in order
 void launch_apply_bwd_t(const SolveLevelDev& S, const ColourDev& C, const double* z, double* out,
                         const double* part, const int64_t* part_off, int nrhs, hipStream_t st);
 // next-level y = coarse parts of z (parent = left child then right child)
