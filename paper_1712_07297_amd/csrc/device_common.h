@@ -215,6 +215,68 @@ __device__ inline void wg_zero(int M, int N, PD dst, int ldd) {
         for (int i = lane; i < M; i += 64) dst[i + (int64_t)j * ldd] = 0.0;
 }
 
+// ------------------------------------------------------- staged products
+// Operands in memory pass through LDS in tiles of at most TILE_BYTES (read
+// once, coalesced, many loads in flight), so long dot products read LDS and
+// not memory; a thread holds at most OUT_PER_THREAD running sums.
+constexpr int TILE_BYTES = 32768;
+constexpr int OUT_PER_THREAD = 4;
+constexpr int OUT_CAP = OUT_PER_THREAD * WG;
+
+// out(i, r) = sum_{l < K} A(i, l) X(l, r) for i < R, r < nrhs, every sum taken
+// from zero in ascending l.  la(i, l) loads A from memory: the tile is
+// fetched with i varying fastest, or with l fastest when ACOL (A stored with
+// consecutive l adjacent), so the loads coalesce either way.  lx(l, r) reads
+// X (LDS), store(i, r, v) receives each result once.  abuf: TILE_BYTES of
+// LDS.  Ends with a barrier.
+template <class T, bool ACOL = false, class LA, class LX, class ST>
+__device__ void wg_rows_times(int R, int K, int nrhs, const LA& la, const LX& lx, T* abuf, const ST& store) {
+    const int tid = threadIdx.x;
+    const int RR = min(nrhs, OUT_CAP);
+    const int RJ = max(1, min(R, OUT_CAP / max(RR, 1)));
+    constexpr int ABUF_N = TILE_BYTES / (int)sizeof(T);
+    for (int r0 = 0; r0 < nrhs; r0 += RR) {
+        const int rr = min(RR, nrhs - r0);
+        for (int i0 = 0; i0 < R; i0 += RJ) {
+            const int rj = min(RJ, R - i0);
+            const int CC = max(1, min(K, ABUF_N / rj));
+            double acc[OUT_PER_THREAD];
+#pragma unroll
+            for (int t = 0; t < OUT_PER_THREAD; ++t) acc[t] = 0.0;
+            for (int l0 = 0; l0 < K; l0 += CC) {
+                const int cc = min(CC, K - l0);
+                __syncthreads();
+                if constexpr (ACOL)
+                    wg_stage(
+                        rj * cc, [&](int e) { return (T)la(i0 + e / cc, l0 + e % cc); },
+                        [&](int e, T v) { abuf[(e / cc) + (e % cc) * rj] = v; });
+                else
+                    wg_stage(
+                        rj * cc, [&](int e) { return (T)la(i0 + e % rj, l0 + e / rj); },
+                        [&](int e, T v) { abuf[e] = v; });
+                __syncthreads();
+#pragma unroll
+                for (int t = 0; t < OUT_PER_THREAD; ++t) {
+                    const int x = tid + t * WG;
+                    if (x < rj * rr) {
+                        const int i = x % rj, r = r0 + x / rj;
+                        double a = acc[t];
+#pragma unroll 4
+                        for (int l = 0; l < cc; ++l) a = fma((double)abuf[i + l * rj], lx(l0 + l, r), a);
+                        acc[t] = a;
+                    }
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < OUT_PER_THREAD; ++t) {
+                const int x = tid + t * WG;
+                if (x < rj * rr) store(i0 + x % rj, r0 + x / rj, acc[t]);
+            }
+        }
+    }
+    __syncthreads();
+}
+
 // ------------------------------------------------------------ MFMA tile core
 // One 64 x 64 tile of D = Left (64 x K) * Right (K x 64) on the FP64 matrix
 // cores (v_mfma_f64_16x16x4f64): 4 waves as 2 x 2 quarters of 32 x 32, each

@@ -610,16 +610,16 @@ __global__ void __launch_bounds__(WG) k_fill_update(LevelDev L, ColourDev C, int
     const int mt = L.m[t];
     double* P1 = dyn;                    // M x w (ld M): B(s, t)[:, panel]
     double* P2 = dyn + (int64_t)M * pw;  // w x M (ld pw): B(t, s)[panel, :]
-    for (int x = threadIdx.x; x < M * w; x += blockDim.x) {
-        int i = x % M, j = x / M;
-        P1[i + j * M] = Bst[i + (int64_t)(c0 + j) * M];
-    }
+    wg_stage(
+        M * w, [&](int x) { return (double)Bst[(x % M) + (int64_t)(c0 + x / M) * M]; },
+        [&](int x, double v) { P1[x] = v; });
     if (!L.symmetric)
-        for (int x = threadIdx.x; x < M * w; x += blockDim.x) {
-            int j = x % w, i = x / w;
-            P2[j + i * pw] = Bts[(c0 + j) + (int64_t)i * mt];
-        }
+        wg_stage(
+            M * w, [&](int x) { return (double)Bts[(c0 + x % w) + (int64_t)(x / w) * mt]; },
+            [&](int x, double v) { P2[(x % w) + (x / w) * pw] = v; });
     __syncthreads();
+    // many workgroups run at once here: the operator columns come straight
+    // from memory (L2), not through a staged tile
     for (int x = threadIdx.x; x < kk * w; x += blockDim.x) {
         int i = x % kk, j = x / kk;
         double a = 0.0, b = 0.0;
@@ -674,14 +674,12 @@ __global__ void __launch_bounds__(WG) k_nbr_update(LevelDev L, ColourDev C, int 
     const int ma = L.m[a];
     double* P1 = dyn;                     // M x w
     double* P2 = dyn + (int64_t)M * pw;   // w x M (ld pw)
-    for (int x = threadIdx.x; x < M * w; x += blockDim.x) {
-        int i = x % M, j = x / M;
-        P1[i + j * M] = Bsa[i + (int64_t)(c0 + j) * M];
-    }
-    for (int x = threadIdx.x; x < M * w; x += blockDim.x) {
-        int j = x % w, i = x / w;
-        P2[j + i * pw] = Bas[(c0 + j) + (int64_t)i * ma];
-    }
+    wg_stage(
+        M * w, [&](int x) { return (double)Bsa[(x % M) + (int64_t)(c0 + x / M) * M]; },
+        [&](int x, double v) { P1[x] = v; });
+    wg_stage(
+        M * w, [&](int x) { return (double)Bas[(c0 + x % w) + (int64_t)(x / w) * ma]; },
+        [&](int x, double v) { P2[(x % w) + (x / w) * pw] = v; });
     __syncthreads();
     for (int x = threadIdx.x; x < M * w; x += blockDim.x) {
         int i = x % M, j = x / M;
@@ -927,10 +925,10 @@ __device__ void merge_block(int b, int P, int Q, const int* __restrict__ pat_ptr
         const int ka = k_prev[a], kc = k_prev[c];
         const TS* sp = blocks_prev + blk_off_prev[src];
         const int lds = m_prev[a];
-        for (int x = threadIdx.x; x < ka * kc; x += blockDim.x) {
-            int i = x % ka, j = x / ka;
-            dst[(roff + i) + (int64_t)(coff + j) * ldn] = (TD)sp[i + (int64_t)j * lds];
-        }
+        if (ka == 0) continue;
+        wg_stage(
+            ka * kc, [&](int x) { return sp[(x % ka) + (int64_t)(x / ka) * lds]; },
+            [&](int x, TS v) { dst[(roff + x % ka) + (int64_t)(coff + x / ka) * ldn] = (TD)v; });
     }
 }
 
