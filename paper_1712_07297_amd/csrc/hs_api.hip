@@ -1318,8 +1318,7 @@ static void solve_sweeps(hs_factor_s* F, int nrhs, hipStream_t st) {
                 const ColourDev& C = CH.sol[t];
                 if (C.n == 0) continue;
                 ProfScope ps(PF_APPLY, st);
-                launch_apply_fwd_t(LD.sdev, C, Y(l), Z(l), nrhs, st);
-                launch_apply_fwd_u(LD.sdev, C, Y(l), Z(l), nrhs, C.max_nbr_m, st);
+                launch_apply_fwd(LD.sdev, C, Y(l), Z(l), nrhs, st);
             }
         if (l + 1 < nlev)
             launch_to_coarse(LD.sdev, F->levels[l + 1].sdev.seg, F->levels[l + 1].ncl, Z(l), Y(l + 1), nrhs, st);

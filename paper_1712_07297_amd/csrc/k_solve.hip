@@ -115,6 +115,83 @@ void launch_apply_fwd_u(const SolveLevelDev& S, const ColourDev& C, double* y, d
         hipLaunchKernelGGL(k_apply_fwd_u<double>, dim3(chunks, C.nbr_total), dim3(WG), sh, st, S, C, y, z, nrhs);
 }
 
+// Forward step of a colour in one launch: workgroups (x, q) for q below the
+// neighbour count update neighbour rows, each forming the z_s[:f] it needs
+// itself (the same products, in the same order, as the cluster's own
+// workgroup, so every copy is bit for bit the same); workgroups q = nbr_total
+// + i write z_i = T_L' y_i for cluster i of the colour.  Clusters of a colour
+// are more than two apart, so no workgroup reads what another writes.
+template <class T>
+__global__ void __launch_bounds__(WG) k_apply_fwd(SolveLevelDev S, ColourDev C, double* __restrict__ y,
+                                                  double* __restrict__ z, int nrhs) {
+    extern __shared__ double ys[];  // max_m x nrhs, then z_f (max_m x nrhs), then the operand tile
+    const int q = blockIdx.y;
+    const bool own = q >= C.nbr_total;
+    if (own && blockIdx.x > 0) return;
+    const int ci = own ? q - C.nbr_total : find_pre(C.nbr_pre, C.n, q);
+    const int s = C.clist[ci];
+    const int M = S.m[s];
+    if (M == 0) return;
+    const int kk = S.k[s];
+    const int f = M - kk;
+    const double* ysrc = y + S.seg[s] * nrhs;
+    const int tot = M * nrhs;
+    const size_t cap = (size_t)C.max_m * nrhs;
+    const T* TL = srec<T>(S, s);
+    if (own) {
+        double* zdst = z + S.seg[s] * nrhs;
+        if (kk == M) {
+            wg_stage(tot, [&](int x) { return ysrc[x]; }, [&](int x, double v) { zdst[x] = v; });
+            return;
+        }
+        wg_stage(tot, [&](int x) { return ysrc[x]; }, [&](int x, double v) { ys[x] = v; });
+        wg_rows_times<T>(
+            M, M, nrhs, [&](int i, int l) { return TL[i + (int64_t)l * M]; }, [&](int l, int r) { return ys[l + r * M]; },
+            tile_buf<T>(ys + 2 * cap), [&](int i, int r, double v) { zdst[i + r * M] = v; });
+        return;
+    }
+    if (f == 0) return;
+    const int e = S.nbr_ptr[s] + (q - C.nbr_pre[ci]);
+    const int a = S.nbr_id[e];
+    const int before = S.nbr_before[e];
+    const int ma = S.m[a];
+    const int ca = before ? S.k[a] : ma;
+    const int r0 = blockIdx.x * UROWS;
+    if (r0 >= ca) return;
+    const int nr = min(UROWS, ca - r0);
+    double* zf = ys + cap;
+    wg_stage(tot, [&](int x) { return ysrc[x]; }, [&](int x, double v) { ys[x] = v; });
+    wg_rows_times<T>(
+        f, M, nrhs, [&](int i, int l) { return TL[i + (int64_t)l * M]; }, [&](int l, int r) { return ys[l + r * M]; },
+        tile_buf<T>(ys + 2 * cap), [&](int i, int r, double v) { zf[i + r * f] = v; });
+    const int ncap = S.ncap[s];
+    const T* EL = srec<T>(S, s) + 2 * (int64_t)M * M + (int64_t)M * ncap + S.nbr_noff[e] + r0;  // ld ncap
+    double* tgt = (before ? z + S.seg[a] * nrhs + (ma - ca) : y + S.seg[a] * nrhs) + r0;    // ld ma
+    wg_rows_times<T>(
+        nr, f, nrhs, [&](int i, int j) { return EL[i + (int64_t)j * ncap]; }, [&](int j, int r) { return zf[j + r * f]; },
+        tile_buf<T>(ys + 2 * cap), [&](int i, int r, double v) { tgt[i + (int64_t)r * ma] -= v; });
+}
+
+// LDS of the one-launch forward step; above FWD_FUSED_MAX_LDS the two
+// kernels run instead.
+constexpr size_t FWD_FUSED_MAX_LDS = 150 * 1024;
+
+void launch_apply_fwd(const SolveLevelDev& S, const ColourDev& C, double* y, double* z, int nrhs, hipStream_t st) {
+    if (C.n == 0) return;
+    const size_t sh = tile_shmem(2 * (size_t)C.max_m * nrhs);
+    if (sh > FWD_FUSED_MAX_LDS) {
+        launch_apply_fwd_t(S, C, y, z, nrhs, st);
+        launch_apply_fwd_u(S, C, y, z, nrhs, C.max_nbr_m, st);
+        return;
+    }
+    const int chunks = std::max(1, (C.max_nbr_m + UROWS - 1) / UROWS);
+    const dim3 grid(chunks, C.nbr_total + C.n);
+    if (C.f32)
+        hipLaunchKernelGGL(k_apply_fwd<float>, grid, dim3(WG), sh, st, S, C, y, z, nrhs);
+    else
+        hipLaunchKernelGGL(k_apply_fwd<double>, grid, dim3(WG), sh, st, S, C, y, z, nrhs);
+}
+
 // --------------------------------------------------------------- backward
 
 // One workgroup per neighbour group of a cluster: part = E_R[:, cols] x over

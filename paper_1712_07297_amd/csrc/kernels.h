@@ -108,6 +108,8 @@ struct SolveLevelDev {
 // z_s = T_L' y_s for the clusters of a colour (deferred: z_s = y_s)
 void launch_apply_fwd_t(const SolveLevelDev& S, const ColourDev& C, const double* y, double* z, int nrhs,
                         hipStream_t st);
+// both steps above in one launch (when their LDS fits), bit for bit the same
+void launch_apply_fwd(const SolveLevelDev& S, const ColourDev& C, double* y, double* z, int nrhs, hipStream_t st);
 // neighbours: y_a (or z_a's coarse part) -= E_L[a] z_s[:f]
 void launch_apply_fwd_u(const SolveLevelDev& S, const ColourDev& C, double* y, double* z, int nrhs, int max_m,
                         hipStream_t st);
