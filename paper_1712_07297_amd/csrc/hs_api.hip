@@ -1087,13 +1087,17 @@ static int factor_impl(hs_factor_s* F, int nsys, const hs_csr* A, const hs_geome
                     ProfScope ps(PF_PIVOT, st);
                     launch_pivot(LD.dev, C, st);
                 }
-                if (C.fill_total > 0) {
-                    ProfScope ps(PF_FILL, st);
-                    launch_fill_update(LD.dev, C, st);
-                }
-                if (C.nbr_total > 0) {
-                    ProfScope ps(PF_NBR, st);
-                    launch_nbr_update(LD.dev, C, st);
+                if (prof_timed(PF_FILL) || prof_timed(PF_NBR)) {  // one family per launch
+                    if (C.fill_total > 0) {
+                        ProfScope ps(PF_FILL, st);
+                        launch_fill_update(LD.dev, C, st);
+                    }
+                    if (C.nbr_total > 0) {
+                        ProfScope ps(PF_NBR, st);
+                        launch_nbr_update(LD.dev, C, st);
+                    }
+                } else {
+                    launch_fill_nbr_update(LD.dev, C, st);
                 }
                 if (C.tile_total > 0) {
                     ProfScope ps(t == 0 ? PF_SCHUR_F32 : PF_SCHUR, st);

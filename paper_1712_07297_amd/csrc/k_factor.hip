@@ -587,9 +587,8 @@ int panel_width(int max_m) {
 }
 
 template <class T>
-__global__ void __launch_bounds__(WG) k_fill_update(LevelDev L, ColourDev C, int pw) {
+__device__ void fill_update_body(const LevelDev& L, const ColourDev& C, int pw, int q) {
     extern __shared__ double dyn[];
-    const int q = blockIdx.y;
     const int ci = find_cluster(C.fill_pre, C.n, q);
     const int s = C.clist[ci];
     const int e = L.fill_ptr[s] + (q - C.fill_pre[ci]);
@@ -633,6 +632,11 @@ __global__ void __launch_bounds__(WG) k_fill_update(LevelDev L, ColourDev C, int
     }
 }
 
+template <class T>
+__global__ void __launch_bounds__(WG) k_fill_update(LevelDev L, ColourDev C, int pw) {
+    fill_update_body<T>(L, C, pw, blockIdx.y);
+}
+
 void launch_fill_update(const LevelDev& L, const ColourDev& C, hipStream_t st) {
     if (C.fill_total == 0 || C.panels == 0) return;
     const int pw = panel_width(C.max_m);
@@ -647,9 +651,8 @@ void launch_fill_update(const LevelDev& L, const ColourDev& C, hipStream_t st) {
 // [E_R; B(s^c, a)] = T_L' B(s, a) and [E_L[a], B(a, s^c)] = B(a, s) T_R',
 // one column panel of one neighbour per workgroup (in place on the blocks).
 template <class T>
-__global__ void __launch_bounds__(WG) k_nbr_update(LevelDev L, ColourDev C, int pw) {
+__device__ void nbr_update_body(const LevelDev& L, const ColourDev& C, int pw, int q) {
     extern __shared__ double dyn[];
-    const int q = blockIdx.y;
     const int ci = find_cluster(C.nbr_pre, C.n, q);
     const int s = C.clist[ci];
     const int e = L.nbr_ptr[s] + (q - C.nbr_pre[ci]);
@@ -699,6 +702,34 @@ __global__ void __launch_bounds__(WG) k_nbr_update(LevelDev L, ColourDev C, int 
         else
             Bas[(c0 + j) + (int64_t)(c - f) * ma] = (T)acc;
     }
+}
+
+template <class T>
+__global__ void __launch_bounds__(WG) k_nbr_update(LevelDev L, ColourDev C, int pw) {
+    nbr_update_body<T>(L, C, pw, blockIdx.y);
+}
+
+// Both updates of a colour in one launch: rows below fill_total of the grid
+// are fill-partner panels, the rest neighbour panels.  They touch disjoint
+// blocks (fill partners are not neighbours), so they may run side by side.
+template <class T>
+__global__ void __launch_bounds__(WG) k_fill_nbr_update(LevelDev L, ColourDev C, int pw) {
+    const int q = blockIdx.y;
+    if (q < C.fill_total)
+        fill_update_body<T>(L, C, pw, q);
+    else
+        nbr_update_body<T>(L, C, pw, q - C.fill_total);
+}
+
+void launch_fill_nbr_update(const LevelDev& L, const ColourDev& C, hipStream_t st) {
+    if (C.fill_total + C.nbr_total == 0 || C.panels == 0) return;
+    const int pw = panel_width(C.max_m);
+    const size_t shmem = (size_t)2 * C.max_m * pw * sizeof(double);
+    const dim3 grid(C.panels, C.fill_total + C.nbr_total);
+    if (C.f32)
+        hipLaunchKernelGGL(k_fill_nbr_update<float>, grid, dim3(WG), shmem, st, L, C, pw);
+    else
+        hipLaunchKernelGGL(k_fill_nbr_update<double>, grid, dim3(WG), shmem, st, L, C, pw);
 }
 
 void launch_nbr_update(const LevelDev& L, const ColourDev& C, hipStream_t st) {

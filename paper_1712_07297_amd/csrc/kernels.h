@@ -43,6 +43,8 @@ void launch_gram(const LevelDev& L, const ColourDev& C, hipStream_t st);
 void launch_pivot(const LevelDev& L, const ColourDev& C, hipStream_t st);
 void launch_fill_update(const LevelDev& L, const ColourDev& C, hipStream_t st);
 void launch_nbr_update(const LevelDev& L, const ColourDev& C, hipStream_t st);
+// both in one launch (they touch disjoint blocks)
+void launch_fill_nbr_update(const LevelDev& L, const ColourDev& C, hipStream_t st);
 // column panel width used by the fill / neighbour updates for clusters up to max_m
 int panel_width(int max_m);
 void launch_schur(const LevelDev& L, const ColourDev& C, hipStream_t st);
