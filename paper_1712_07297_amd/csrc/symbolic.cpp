@@ -12,6 +12,7 @@
 #include <array>
 #include <cstdint>
 #include <cstring>
+#include <thread>
 
 #include "hs.h"
 
@@ -169,7 +170,6 @@ void simulate_level(LevelSymbolic& L, std::vector<int>& next_ptr, std::vector<in
         P.row(s, row);
         for (int t : row)
             if (t != s && !isnbr[t]) fill[s].push_back(t);
-        std::sort(fill[s].begin(), fill[s].end(), [&](int a, int b) { return L.pos[a] < L.pos[b]; });
         for (int e = L.adj_ptr[s]; e < L.adj_ptr[s + 1]; ++e) isnbr[L.adj[e]] = 0;
         // eliminating s couples every pair of its neighbours
         if (P.dense()) {
@@ -180,6 +180,20 @@ void simulate_level(LevelSymbolic& L, std::vector<int>& next_ptr, std::vector<in
             for (int e = L.adj_ptr[s]; e < L.adj_ptr[s + 1]; ++e)
                 for (int f = L.adj_ptr[s]; f < L.adj_ptr[s + 1]; ++f) P.add(L.adj[e], L.adj[f]);
         }
+    }
+    // every fill list in processing order; the lists are independent, so
+    // large levels sort them on several threads
+    auto sort_fill = [&](int c0, int c1) {
+        for (int c = c0; c < c1; ++c)
+            std::sort(fill[c].begin(), fill[c].end(), [&](int a, int b) { return L.pos[a] < L.pos[b]; });
+    };
+    const int nth = ncl >= 512 ? (int)std::min(8u, std::max(1u, std::thread::hardware_concurrency())) : 1;
+    if (nth > 1) {
+        std::vector<std::thread> th;
+        for (int i = 0; i < nth; ++i) th.emplace_back(sort_fill, (int)((int64_t)ncl * i / nth), (int)((int64_t)ncl * (i + 1) / nth));
+        for (auto& t : th) t.join();
+    } else {
+        sort_fill(0, ncl);
     }
     L.fill_ptr.assign(ncl + 1, 0);
     L.fill.clear();
