@@ -73,12 +73,12 @@ struct LevelDev {
 // Workspace slots of a cluster (each m x m, column major, ld m).
 enum WsSlot { WS_AINV = 0, WS_LINV, WS_UINV, WS_U, WS_X, WS_SL, WS_SR, WS_TL, WS_TR, WS_CU, WS_UC, WS_SCR, WS_GP };
 __host__ __device__ inline int64_t ws_slots(int gram_splits) { return WS_GP + gram_splits; }
-// Gram partial sums of a cluster with nf fill partners: about four partners
-// per workgroup.  A function of the cluster alone, so the sums are formed in
-// the same order whatever else shares the launch.
-constexpr int GRAM_SPLITS_MAX = 64;
+// Gram partial sums of a cluster with nf fill partners: one partner per
+// workgroup up to GRAM_SPLITS_MAX.  A function of the cluster alone, so the
+// sums are formed in the same order whatever else shares the launch.
+constexpr int GRAM_SPLITS_MAX = 256;
 __host__ __device__ inline int gram_splits_of(int nf) {
-    const int s = (nf + 3) / 4;
+    const int s = nf;
     return s < 1 ? 1 : (s > GRAM_SPLITS_MAX ? GRAM_SPLITS_MAX : s);
 }
 
