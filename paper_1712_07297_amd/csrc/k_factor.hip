@@ -108,7 +108,15 @@ __global__ void k_gram_reduce(LevelDev L, const int* __restrict__ clist) {
     const int splits = gram_splits_of(L.fill_ptr[s + 1] - L.fill_ptr[s]);
     double* G = L.ws + L.ws_off[s] + WS_GP * MM;
     double g = G[e];
-    for (int sp = 1; sp < splits; ++sp) g += G[sp * MM + e];
+    int sp = 1;
+    for (; sp + 8 <= splits; sp += 8) {  // eight loads in flight, added in order
+        double t[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) t[u] = G[(sp + u) * MM + e];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) g += t[u];
+    }
+    for (; sp < splits; ++sp) g += G[sp * MM + e];
     G[e] = g;
 }
 

@@ -74,7 +74,16 @@ __global__ void k_sdots_final(SegDev G, int nvec, int nrhs, const double* __rest
     const int s = l % G.nsys, c = l / G.nsys;
     const double* p = part + ((int64_t)v * nrhs + c) * G.nchunks;
     double acc = 0.0;
-    for (int q = G.sys_chunk0[s]; q < G.sys_chunk0[s + 1]; ++q) acc += p[q];
+    const int q1 = G.sys_chunk0[s + 1];
+    int q = G.sys_chunk0[s];
+    for (; q + 8 <= q1; q += 8) {  // eight loads in flight, added in chunk order
+        double t[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) t[u] = p[q + u];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += t[u];
+    }
+    for (; q < q1; ++q) acc += p[q];
     out[x] = acc;
 }
 
