@@ -197,6 +197,22 @@ __device__ inline void wg_stage(int n, const LD& ld, const ST& st) {
     }
 }
 
+// acc + sum_{l < n} a[l * as] * b(l), added in ascending l with fused
+// multiply-adds; the loads of a (memory) are issued eight at a time.
+template <class TA, class FB>
+__device__ inline double dot_batched(int n, const TA* a, int64_t as, const FB& b, double acc) {
+    int l = 0;
+    for (; l + 8 <= n; l += 8) {
+        double t[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) t[u] = (double)a[(int64_t)(l + u) * as];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc = fma(t[u], b(l + u), acc);
+    }
+    for (; l < n; ++l) acc = fma((double)a[(int64_t)l * as], b(l), acc);
+    return acc;
+}
+
 template <class PS, class PD>
 __device__ inline void wg_copy(int M, int N, PS src, int lds, PD dst, int ldd) {
     if (M <= 0 || N <= 0) return;

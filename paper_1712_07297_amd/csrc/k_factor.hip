@@ -629,12 +629,9 @@ __device__ void fill_update_body(const LevelDev& L, const ColourDev& C, int pw, 
     // from memory (L2), not through a staged tile
     for (int x = threadIdx.x; x < kk * w; x += blockDim.x) {
         int i = x % kk, j = x / kk;
-        double a = 0.0, b = 0.0;
-        for (int l = 0; l < M; ++l) {
-            a = fma(CU[i + (int64_t)l * M], P1[l + j * M], a);
-            const double src = L.symmetric ? P1[l + j * M] : P2[j + l * pw];
-            b = fma(src, UC[l + (int64_t)i * M], b);
-        }
+        const double a = dot_batched(M, CU + i, M, [&](int l) { return P1[l + j * M]; }, 0.0);
+        const double b = dot_batched(
+            M, UC + (int64_t)i * M, 1, [&](int l) { return L.symmetric ? P1[l + j * M] : P2[j + l * pw]; }, 0.0);
         Bst[i + (int64_t)(c0 + j) * M] = (T)a;
         Bts[(c0 + j) + (int64_t)i * mt] = (T)b;
     }
@@ -694,8 +691,7 @@ __device__ void nbr_update_body(const LevelDev& L, const ColourDev& C, int pw, i
     __syncthreads();
     for (int x = threadIdx.x; x < M * w; x += blockDim.x) {
         int i = x % M, j = x / M;
-        double acc = 0.0;
-        for (int l = 0; l < M; ++l) acc = fma((double)TLp[i + (int64_t)l * M], P1[l + j * M], acc);
+        const double acc = dot_batched(M, TLp + i, M, [&](int l) { return P1[l + j * M]; }, 0.0);
         if (i < f)
             ER[i + (int64_t)(off + c0 + j) * M] = (T)acc;
         else
@@ -703,8 +699,7 @@ __device__ void nbr_update_body(const LevelDev& L, const ColourDev& C, int pw, i
     }
     for (int x = threadIdx.x; x < M * w; x += blockDim.x) {
         int j = x % w, c = x / w;
-        double acc = 0.0;
-        for (int l = 0; l < M; ++l) acc = fma(P2[j + l * pw], (double)TRp[l + (int64_t)c * M], acc);
+        const double acc = dot_batched(M, TRp + (int64_t)c * M, 1, [&](int l) { return P2[j + l * pw]; }, 0.0);
         if (c < f)
             EL[(off + c0 + j) + (int64_t)c * ncap] = (T)acc;
         else
