@@ -137,6 +137,25 @@ __device__ inline int wave_min_int(int v) {
                min(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
 }
 
+// Exclusive prefix sum of v over the workgroup in thread order; *total gets
+// the sum (the same in every thread).  buf: blockDim.x ints of LDS.  Starts
+// with a barrier, so it may be called in a loop.
+template <class PI>
+__device__ inline int block_scan_excl(int v, PI buf, int* total) {
+    const int tid = threadIdx.x, n = blockDim.x;
+    __syncthreads();
+    buf[tid] = v;
+    __syncthreads();
+    int before = 0, tot = 0;
+    for (int i = 0; i < n; ++i) {  // the same address in every lane: broadcast reads
+        const int t = buf[i];
+        before += i < tid ? t : 0;
+        tot += t;
+    }
+    *total = tot;
+    return before;
+}
+
 // Block-wide reductions (blockDim.x a multiple of 64, <= 1024); red has >= 16 slots.
 template <class PR>
 __device__ inline double block_sum(double v, PR red) {

@@ -391,15 +391,9 @@ __global__ void __launch_bounds__(WG, 2) k_pivot(LevelDev L, const int* __restri
     const int tid = threadIdx.x;
     const int M = L.m[s];
 
-    // packed offsets of the current neighbour sizes inside E_L / E_R, and the
-    // number of fill columns
+    // the number of fill columns (the packed neighbour offsets come from
+    // k_offsets, launched just before)
     if (tid == 0) {
-        int off = 0;
-        for (int e = L.nbr_ptr[s]; e < L.nbr_ptr[s + 1]; ++e) {
-            L.nbr_noff[e] = off;
-            off += cur_size(L, L.nbr_id[e], L.nbr_before[e]);
-        }
-        L.ntot[s] = off;
         int fc = 0;
         for (int e = L.fill_ptr[s]; e < L.fill_ptr[s + 1]; ++e) fc += cur_size(L, L.fill_id[e], L.fill_before[e]);
         fcols_sh = fc;
@@ -568,8 +562,29 @@ __global__ void __launch_bounds__(WG, 2) k_pivot(LevelDev L, const int* __restri
     wg_gemm<false, false>(M, kk, kk, 1.0, Umat, M, W, M, 0.0, UC, M, sm_l);  // U C (m x k)
 }
 
+// Packed offsets of every cluster's current neighbour sizes inside E_L / E_R
+// (nbr_noff) and their sum (ntot): a prefix sum over the neighbour list, one
+// workgroup per cluster of the colour, a workgroup's width at a time.
+__global__ void __launch_bounds__(WG) k_offsets(LevelDev L, const int* __restrict__ clist) {
+    __shared__ int buf[WG];
+    const int s = clist[blockIdx.x];
+    const int tid = threadIdx.x;
+    const int e0 = L.nbr_ptr[s], ne = L.nbr_ptr[s + 1] - e0;
+    int carry = 0;
+    for (int b = 0; b < ne; b += blockDim.x) {
+        const int e = b + tid;
+        const int v = e < ne ? cur_size(L, L.nbr_id[e0 + e], L.nbr_before[e0 + e]) : 0;
+        int tot;
+        const int ex = block_scan_excl(v, to_lds(buf), &tot);
+        if (e < ne) L.nbr_noff[e0 + e] = carry + ex;
+        carry += tot;
+    }
+    if (tid == 0) L.ntot[s] = carry;
+}
+
 void launch_pivot(const LevelDev& L, const ColourDev& C, hipStream_t st) {
     if (C.n == 0) return;
+    hipLaunchKernelGGL(k_offsets, dim3(C.n), dim3(WG), 0, st, L, C.clist);
     const size_t shmem = (size_t)C.max_m * C.max_m * sizeof(double);
     if (C.max_m <= LDS_M) {
         if (C.f32)
