@@ -54,8 +54,9 @@ struct LevelDev {
     const int* nbr_before;    // neighbour processed before s (then it has its coarse size)
     const int* nbr_bsa;       // block id of (s, a)
     const int* nbr_bas;       // block id of (a, s)
-    int* nbr_noff;            // packed offset of a inside E_L / E_R (written by the pivot kernel)
-    int* ntot;                // [ncl] sum of the current neighbour sizes (written by the pivot kernel)
+    int* nbr_noff;            // packed offset of a inside E_L / E_R (written by k_offsets)
+    int* ntot;                // [ncl] sum of the current neighbour sizes (written by k_offsets)
+    int* fcols;               // [ncl] sum of the current fill-partner sizes (written by k_offsets)
     const int* ncap;          // [ncl] sum of the neighbours' level-start sizes (record capacity)
     const int* fill_ptr;      // [ncl+1] fill partners w(s)
     const int* fill_id;

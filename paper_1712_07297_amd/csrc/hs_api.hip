@@ -620,6 +620,7 @@ static int plan_level(hs_factor_s* F, int lvl, Blob& blob, std::vector<size_t>& 
     offs.push_back(blob.add(order));             // 24 colour slices by type (the work lists)
     LD.order_host = order;
     offs.push_back(blob.add(LD.f32));            // 25 per-cluster storage type
+    offs.push_back(blob.add(std::vector<int>(ncl, 0)));  // 26 fill columns (written by k_offsets)
     auto add_pre = [&](ListPlan& L, const ListPre& lp) {
         L.start = lp.start;
         L.off_pre[0] = blob.add(lp.pre.np);
@@ -678,6 +679,7 @@ static void bind_level(LevelData& LD, const std::vector<size_t>& offs, const hs_
     LD.dev_pat_ptr = (const int*)P(22);
     LD.dev_pat = (const int*)P(23);
     LD.dev_f32 = (const int*)P(25);
+    D.fcols = (int*)P(26);
     const int* order = (const int*)P(24);
     auto bind = [&](ColourDev& Cd, const ListPlan& L, int first) {
         Cd.clist = order + first + L.start;

@@ -391,13 +391,9 @@ __global__ void __launch_bounds__(WG, 2) k_pivot(LevelDev L, const int* __restri
     const int tid = threadIdx.x;
     const int M = L.m[s];
 
-    // the number of fill columns (the packed neighbour offsets come from
-    // k_offsets, launched just before)
-    if (tid == 0) {
-        int fc = 0;
-        for (int e = L.fill_ptr[s]; e < L.fill_ptr[s + 1]; ++e) fc += cur_size(L, L.fill_id[e], L.fill_before[e]);
-        fcols_sh = fc;
-    }
+    // the number of fill columns (counted, like the packed neighbour offsets,
+    // by k_offsets just before)
+    if (tid == 0) fcols_sh = L.fcols[s];
     __syncthreads();
     if (M == 0) {
         if (tid == 0) L.k[s] = 0;
@@ -564,7 +560,8 @@ __global__ void __launch_bounds__(WG, 2) k_pivot(LevelDev L, const int* __restri
 
 // Packed offsets of every cluster's current neighbour sizes inside E_L / E_R
 // (nbr_noff) and their sum (ntot): a prefix sum over the neighbour list, one
-// workgroup per cluster of the colour, a workgroup's width at a time.
+// workgroup per cluster of the colour, a workgroup's width at a time; and the
+// sum of its current fill-partner sizes (fcols).
 __global__ void __launch_bounds__(WG) k_offsets(LevelDev L, const int* __restrict__ clist) {
     __shared__ int buf[WG];
     const int s = clist[blockIdx.x];
@@ -580,6 +577,16 @@ __global__ void __launch_bounds__(WG) k_offsets(LevelDev L, const int* __restric
         carry += tot;
     }
     if (tid == 0) L.ntot[s] = carry;
+    const int f0 = L.fill_ptr[s], nf = L.fill_ptr[s + 1] - f0;
+    int fc = 0;
+    for (int b = 0; b < nf; b += blockDim.x) {
+        const int e = b + tid;
+        const int v = e < nf ? cur_size(L, L.fill_id[f0 + e], L.fill_before[f0 + e]) : 0;
+        int tot;
+        (void)block_scan_excl(v, to_lds(buf), &tot);
+        fc += tot;
+    }
+    if (tid == 0) L.fcols[s] = fc;
 }
 
 void launch_pivot(const LevelDev& L, const ColourDev& C, hipStream_t st) {
