@@ -318,6 +318,10 @@ __device__ int wg_pivoted_cholesky_ll(PW W, int M, double eps, int fixed_rank, P
 // Householder QR.  G is a k x k scratch, T1 an M x k and T2 a k x k global
 // scratch.
 constexpr double CHOLQR_ONE_PASS = 1e-6;  // one pass while cond(X) <= 1e3 (error ~ 1e-10)
+// Clusters stored in float32 keep the orthogonality error of one pass below
+// the rounding of their stored operators (6e-8) while cond(X) <= 1e4, which
+// covers every truncation at eps >= 1e-4 (the kept pivots stay above eps^2).
+constexpr double CHOLQR_ONE_PASS_F32 = 1e-8;
 
 template <class PG>
 __device__ bool wg_cholqr2(const double* X, int M, int k, PG G, double* T1, double* T2, double* Q, lds_smem* sm,
@@ -487,7 +491,8 @@ __global__ void __launch_bounds__(WG, 2) k_pivot(LevelDev L, const int* __restri
             }
             __syncthreads();
             bool done = false;
-            done = wg_cholqr2(X, M, kk, W, Linv, Uinv, Umat, sm_l, scr, red_l, to_lds(isc + 1), CHOLQR_ONE_PASS);
+            done = wg_cholqr2(X, M, kk, W, Linv, Uinv, Umat, sm_l, scr, red_l, to_lds(isc + 1),
+                              std::is_same<T, float>::value ? CHOLQR_ONE_PASS_F32 : CHOLQR_ONE_PASS);
             if (!done) {
                 wg_copy(M, kk, X, M, W, M);
                 wg_house_qr(W, M, kk, M, dsh_l);
