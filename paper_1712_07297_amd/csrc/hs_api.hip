@@ -1081,13 +1081,16 @@ static int factor_impl(hs_factor_s* F, int nsys, const hs_csr* A, const hs_geome
             for (int t = 0; t < 2; ++t)
                 for (const ColourDev& C : CH.fac[t]) {
                 if (C.n == 0) continue;
-                if (F->opts.eps > 0.0 && C.fill_total > 0) {
+                const bool gram = F->opts.eps > 0.0 && C.fill_total > 0;
+                // the offsets ride in the Gram launch unless either family is timed
+                const bool fused_offsets = gram && !prof_timed(PF_GRAM) && !prof_timed(PF_PIVOT);
+                if (gram) {
                     ProfScope ps(PF_GRAM, st);
-                    launch_gram(LD.dev, C, st);
+                    launch_gram(LD.dev, C, st, fused_offsets);
                 }
                 {
                     ProfScope ps(PF_PIVOT, st);
-                    launch_pivot(LD.dev, C, st);
+                    launch_pivot(LD.dev, C, st, fused_offsets);
                 }
                 if (prof_timed(PF_FILL) || prof_timed(PF_NBR)) {  // one family per launch
                     if (C.fill_total > 0) {

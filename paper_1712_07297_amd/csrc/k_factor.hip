@@ -50,6 +50,42 @@ __device__ inline int find_cluster64(const int64_t* pre, int n, int64_t q) {
     return lo;
 }
 
+// Packed offsets of every cluster's current neighbour sizes inside E_L / E_R
+// (nbr_noff) and their sum (ntot): a prefix sum over the neighbour list, a
+// workgroup's width at a time; and the sum of its current fill-partner sizes
+// (fcols).  One workgroup per cluster of the colour, either in a launch of
+// its own or as the last column of the Gram launch's grid (the Gram partials
+// neither read nor write these arrays).
+__device__ void offsets_body(const LevelDev& L, int s, lds_i32* buf) {
+    const int tid = threadIdx.x;
+    const int e0 = L.nbr_ptr[s], ne = L.nbr_ptr[s + 1] - e0;
+    int carry = 0;
+    for (int b = 0; b < ne; b += blockDim.x) {
+        const int e = b + tid;
+        const int v = e < ne ? cur_size(L, L.nbr_id[e0 + e], L.nbr_before[e0 + e]) : 0;
+        int tot;
+        const int ex = block_scan_excl(v, buf, &tot);
+        if (e < ne) L.nbr_noff[e0 + e] = carry + ex;
+        carry += tot;
+    }
+    if (tid == 0) L.ntot[s] = carry;
+    const int f0 = L.fill_ptr[s], nf = L.fill_ptr[s + 1] - f0;
+    int fc = 0;
+    for (int b = 0; b < nf; b += blockDim.x) {
+        const int e = b + tid;
+        const int v = e < nf ? cur_size(L, L.fill_id[f0 + e], L.fill_before[f0 + e]) : 0;
+        int tot;
+        (void)block_scan_excl(v, buf, &tot);
+        fc += tot;
+    }
+    if (tid == 0) L.fcols[s] = fc;
+}
+
+__global__ void __launch_bounds__(WG) k_offsets(LevelDev L, const int* __restrict__ clist) {
+    __shared__ int buf[WG];
+    offsets_body(L, clist[blockIdx.x], to_lds(buf));
+}
+
 // ============================================================== Gram partials
 
 // G_split = sum over the split's fill partners t of B(s,t) B(s,t)^T (and, for
@@ -57,10 +93,15 @@ __device__ inline int find_cluster64(const int64_t* pre, int n, int64_t q) {
 // (Eq. lra) in gram_splits_of(nf) partial sums.  Each 64 x 64 tile of the partial is
 // accumulated over all partners of the split in registers and stored once.
 template <class T>
-__global__ void __launch_bounds__(WG) k_gram(LevelDev L, const int* __restrict__ clist) {
+__global__ void __launch_bounds__(WG) k_gram(LevelDev L, const int* __restrict__ clist, int with_offsets) {
     __shared__ GemmSmem sm;
+    __shared__ int obuf[WG];
     const int s = clist[blockIdx.y];
     const int split = blockIdx.x;
+    if (with_offsets && split == (int)gridDim.x - 1) {
+        offsets_body(L, s, to_lds(obuf));
+        return;
+    }
     const int M = L.m[s];
     if (M == 0) return;
     double* Gp = L.ws + L.ws_off[s] + (int64_t)(WS_GP + split) * M * M;
@@ -120,12 +161,13 @@ __global__ void k_gram_reduce(LevelDev L, const int* __restrict__ clist) {
     G[e] = g;
 }
 
-void launch_gram(const LevelDev& L, const ColourDev& C, hipStream_t st) {
+void launch_gram(const LevelDev& L, const ColourDev& C, hipStream_t st, bool with_offsets) {
     if (C.n == 0) return;
+    const dim3 grid(L.gram_splits + (with_offsets ? 1 : 0), C.n);
     if (C.f32)
-        hipLaunchKernelGGL(k_gram<float>, dim3(L.gram_splits, C.n), dim3(WG), 0, st, L, C.clist);
+        hipLaunchKernelGGL(k_gram<float>, grid, dim3(WG), 0, st, L, C.clist, (int)with_offsets);
     else
-        hipLaunchKernelGGL(k_gram<double>, dim3(L.gram_splits, C.n), dim3(WG), 0, st, L, C.clist);
+        hipLaunchKernelGGL(k_gram<double>, grid, dim3(WG), 0, st, L, C.clist, (int)with_offsets);
     const int64_t mm = (int64_t)C.max_m * C.max_m;
     if (L.gram_splits > 1 && mm > 0) {
         hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((mm + 255) / 256), C.n), dim3(256), 0, st, L, C.clist);
@@ -396,7 +438,7 @@ __global__ void __launch_bounds__(WG, 2) k_pivot(LevelDev L, const int* __restri
     const int M = L.m[s];
 
     // the number of fill columns (counted, like the packed neighbour offsets,
-    // by k_offsets just before)
+    // by the offsets workgroups of an earlier launch of the colour)
     if (tid == 0) fcols_sh = L.fcols[s];
     __syncthreads();
     if (M == 0) {
@@ -563,40 +605,9 @@ __global__ void __launch_bounds__(WG, 2) k_pivot(LevelDev L, const int* __restri
     wg_gemm<false, false>(M, kk, kk, 1.0, Umat, M, W, M, 0.0, UC, M, sm_l);  // U C (m x k)
 }
 
-// Packed offsets of every cluster's current neighbour sizes inside E_L / E_R
-// (nbr_noff) and their sum (ntot): a prefix sum over the neighbour list, one
-// workgroup per cluster of the colour, a workgroup's width at a time; and the
-// sum of its current fill-partner sizes (fcols).
-__global__ void __launch_bounds__(WG) k_offsets(LevelDev L, const int* __restrict__ clist) {
-    __shared__ int buf[WG];
-    const int s = clist[blockIdx.x];
-    const int tid = threadIdx.x;
-    const int e0 = L.nbr_ptr[s], ne = L.nbr_ptr[s + 1] - e0;
-    int carry = 0;
-    for (int b = 0; b < ne; b += blockDim.x) {
-        const int e = b + tid;
-        const int v = e < ne ? cur_size(L, L.nbr_id[e0 + e], L.nbr_before[e0 + e]) : 0;
-        int tot;
-        const int ex = block_scan_excl(v, to_lds(buf), &tot);
-        if (e < ne) L.nbr_noff[e0 + e] = carry + ex;
-        carry += tot;
-    }
-    if (tid == 0) L.ntot[s] = carry;
-    const int f0 = L.fill_ptr[s], nf = L.fill_ptr[s + 1] - f0;
-    int fc = 0;
-    for (int b = 0; b < nf; b += blockDim.x) {
-        const int e = b + tid;
-        const int v = e < nf ? cur_size(L, L.fill_id[f0 + e], L.fill_before[f0 + e]) : 0;
-        int tot;
-        (void)block_scan_excl(v, to_lds(buf), &tot);
-        fc += tot;
-    }
-    if (tid == 0) L.fcols[s] = fc;
-}
-
-void launch_pivot(const LevelDev& L, const ColourDev& C, hipStream_t st) {
+void launch_pivot(const LevelDev& L, const ColourDev& C, hipStream_t st, bool offsets_done) {
     if (C.n == 0) return;
-    hipLaunchKernelGGL(k_offsets, dim3(C.n), dim3(WG), 0, st, L, C.clist);
+    if (!offsets_done) hipLaunchKernelGGL(k_offsets, dim3(C.n), dim3(WG), 0, st, L, C.clist);
     const size_t shmem = (size_t)C.max_m * C.max_m * sizeof(double);
     if (C.max_m <= LDS_M) {
         if (C.f32)

@@ -7,6 +7,9 @@
 * The fill-partner and neighbour updates of a colour run in one launch, or in
   two while their profiler families are timed: the factorizations agree bit
   for bit.
+* The packed neighbour offsets of a colour are computed by extra workgroups of
+  its Gram launch, or by a launch of their own while the Gram or pivot family
+  is timed: again the factorizations agree bit for bit.
 """
 
 import numpy as np
@@ -44,6 +47,38 @@ def test_forward_step_paths_agree(P):
     for c in (0, 17, 63):
         x1 = F.solve(B[c : c + 1].contiguous())
         assert torch.equal(X[c : c + 1], x1), c
+
+
+def _factor_both_ways(P, A, dims, sym, families):
+    """The same factorization without profiling and while `families` are
+    timed (which switches the launches under test to their separate form)."""
+    F1 = P.Factor(A.row_ptr, A.col_idx, A.val, dims, 1e-3, 32, symmetric=sym, precision=P.HS_MIXED)
+    P.profile_reset()
+    P.profile_select(families)
+    P.profile_enable(True)
+    try:
+        F2 = P.Factor(A.row_ptr, A.col_idx, A.val, dims, 1e-3, 32, symmetric=sym, precision=P.HS_MIXED)
+    finally:
+        P.profile_enable(False)
+        P.profile_select("")
+        P.profile_reset()
+    return F1, F2
+
+
+@pytest.mark.parametrize("sym", [1, 0])
+def test_offsets_in_gram_launch_agree(P, sym):
+    """Level ranks and solves with the offsets computed inside the Gram launch
+    equal those with the offsets launched on their own."""
+    if sym:
+        A, dims = poisson3d(12, 12, 12), (12, 12, 12)
+    else:
+        A, dims = convdiff2d_upwind(48, 40.0, 0.9), (48, 48, 1)
+    F1, F2 = _factor_both_ways(P, A, dims, sym, "gram")
+    info = F1.info()
+    for l in range(info.nlevels):
+        assert np.array_equal(F1.ranks(l), F2.ranks(l)), l
+    b = torch.tensor(np.random.default_rng(6).uniform(-1, 1, (2, A.n)), device="cuda")
+    assert torch.equal(F1.solve(b), F2.solve(b))
 
 
 @pytest.mark.parametrize("sym", [1, 0])
