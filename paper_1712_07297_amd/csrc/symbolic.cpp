@@ -208,21 +208,27 @@ void simulate_level(LevelSymbolic& L, std::vector<int>& next_ptr, std::vector<in
         L.pat.insert(L.pat.end(), row.begin(), row.end());
         L.pat_ptr[a + 1] = (int)L.pat.size();
     }
-    // quotient of the final pattern over parent clusters
+    // quotient of the final pattern over parent clusters: the row of parent
+    // p holds the parents of the columns of its children's rows 2p and 2p+1,
+    // other than p; each parent is taken once (marker) and the row sorted
     const int npar = (ncl + 1) / 2;
-    std::vector<std::vector<int>> nadj(npar);
-    for (int a = 0; a < ncl; ++a)
-        for (int e = L.pat_ptr[a]; e < L.pat_ptr[a + 1]; ++e) {
-            int pa = a / 2, pb = L.pat[e] / 2;
-            if (pa != pb) nadj[pa].push_back(pb);
-        }
     next_ptr.assign(npar + 1, 0);
     next_adj.clear();
+    std::vector<char> seen(npar, 0);
+    std::vector<int> cur;
     for (int p = 0; p < npar; ++p) {
-        auto& v = nadj[p];
-        std::sort(v.begin(), v.end());
-        v.erase(std::unique(v.begin(), v.end()), v.end());
-        next_adj.insert(next_adj.end(), v.begin(), v.end());
+        cur.clear();
+        for (int a = 2 * p; a < std::min(2 * p + 2, ncl); ++a)
+            for (int e = L.pat_ptr[a]; e < L.pat_ptr[a + 1]; ++e) {
+                const int pb = L.pat[e] / 2;
+                if (pb != p && !seen[pb]) {
+                    seen[pb] = 1;
+                    cur.push_back(pb);
+                }
+            }
+        std::sort(cur.begin(), cur.end());
+        for (int q : cur) seen[q] = 0;
+        next_adj.insert(next_adj.end(), cur.begin(), cur.end());
         next_ptr[p + 1] = (int)next_adj.size();
     }
 }
@@ -283,15 +289,29 @@ int build_symbolic(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, in
         S.leaf_ptr[c + 1] = (int)w;
     }
 
-    // level-0 block graph from the stored entries, symmetrised
+    // level-0 block graph from the stored entries, symmetrised: the distinct
+    // clusters that each cluster's rows reach (marker over its own rows), then
+    // every such pair entered in both directions
     std::vector<std::vector<int>> adj(nleaf);
-    for (int64_t i = 0; i < n; ++i) {
-        int ci = S.cluster_of[i];
-        for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
-            int cj = S.cluster_of[col_idx[e]];
-            if (ci != cj) {
-                adj[ci].push_back(cj);
-                adj[cj].push_back(ci);
+    {
+        std::vector<char> seen(nleaf, 0);
+        std::vector<int> out;
+        for (int c = 0; c < nleaf; ++c) {
+            out.clear();
+            for (int w0 = S.leaf_ptr[c]; w0 < S.leaf_ptr[c + 1]; ++w0) {
+                const int64_t i = S.leaf_dofs[w0];
+                for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+                    const int cj = S.cluster_of[col_idx[e]];
+                    if (cj != c && !seen[cj]) {
+                        seen[cj] = 1;
+                        out.push_back(cj);
+                    }
+                }
+            }
+            for (int d : out) {
+                seen[d] = 0;
+                adj[c].push_back(d);
+                adj[d].push_back(c);
             }
         }
     }
