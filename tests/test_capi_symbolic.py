@@ -10,7 +10,7 @@ import pytest
 
 import oracle as O
 from paper_1712_07297_amd import _lib as H
-from workloads import poisson2d, poisson3d, random_nonsym_dd, convdiff2d_upwind, chain1d
+from workloads import poisson2d, poisson3d, random_nonsym_dd, convdiff2d_upwind, chain1d, one_sided_dd
 
 
 def test_library_exports_every_declared_function():
@@ -44,36 +44,9 @@ def test_argument_errors_need_no_device():
     assert e.value.code == H.HS_ERR_GEOMETRY
 
 
-class _Pattern:
-    """A CSR pattern only (symbolic analysis reads no values)."""
-
-    def __init__(self, row_ptr, col_idx):
-        self.row_ptr, self.col_idx = row_ptr, col_idx
-
-
-def _one_sided_pattern(nx, ny, seed):
-    """The 5-point grid pattern with off-diagonal entries dropped one at a time
-    (so (i, j) often has no (j, i)) and, in a few rows, one far column: the
-    level-0 block graph must symmetrise both."""
-    A = poisson2d(nx, ny)
-    rng = np.random.default_rng(seed)
-    n = A.row_ptr.size - 1
-    rows = []
-    for i in range(n):
-        cols = A.col_idx[A.row_ptr[i]:A.row_ptr[i + 1]]
-        keep = [c for c in cols if c == i or rng.uniform() >= 0.35]
-        if rng.uniform() < 0.06:
-            keep.append(int(rng.integers(0, n)))
-        rows.append(sorted(set(keep)))
-    row_ptr = np.zeros(n + 1, dtype=np.int64)
-    row_ptr[1:] = np.cumsum([len(r) for r in rows])
-    col_idx = np.array([c for r in rows for c in r], dtype=np.int32)
-    return _Pattern(row_ptr, col_idx)
-
-
 CASES = [
     ("p2d_32", lambda: (poisson2d(32, 32), (32, 32, 1), 16)),
-    ("one_sided", lambda: (_one_sided_pattern(29, 22, 7), (29, 22, 1), 12)),
+    ("one_sided", lambda: (one_sided_dd(np.random.default_rng(7), 29, 22), (29, 22, 1), 12)),
     ("p2d_ragged", lambda: (poisson2d(37, 23), (37, 23, 1), 10)),
     ("p3d_16", lambda: (poisson3d(16, 16, 16), (16, 16, 16), 64)),
     ("p3d_ragged", lambda: (poisson3d(9, 7, 5), (9, 7, 5), 8)),

@@ -27,4 +27,5 @@ from .pde import (  # noqa: F401
     chain1d,
     random_spd_blocks,
     random_nonsym_dd,
+    one_sided_dd,
 )

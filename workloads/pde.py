@@ -213,6 +213,43 @@ def random_spd_blocks(rng: np.random.Generator, nx: int, ny: int, nz: int = 1, s
     return _coo_to_csr(n, np.concatenate(rows), np.concatenate(cols), np.concatenate(vals))
 
 
+def one_sided_dd(rng: np.random.Generator, nx: int, ny: int, drop: float = 0.35, far: float = 0.06) -> CSR:
+    """Structurally nonsymmetric 2D grid operator: each 5-point coupling is
+    kept with probability 1 - drop on its own (so (i, j) often has no (j, i)),
+    and a fraction `far` of the rows gains one coupling to a uniformly chosen
+    unknown.  Off-diagonals uniform on (-1, 0]; diagonal = 1.5 * max(row sum,
+    column sum) + 0.1, so the matrix is diagonally dominant by rows and
+    columns."""
+    n = nx * ny
+    x, y, _ = _grid_ids(nx, ny, 1)
+    idx = np.arange(n)
+    rows, cols = [], []
+    for (dx, dy) in [(1, 0), (-1, 0), (0, 1), (0, -1)]:
+        ok = (x + dx >= 0) & (x + dx < nx) & (y + dy >= 0) & (y + dy < ny)
+        i = idx[ok]
+        i = i[rng.uniform(size=i.size) >= drop]
+        rows.append(i)
+        cols.append(i + dx + nx * dy)
+    fr = idx[rng.uniform(size=n) < far]
+    fc = rng.integers(0, n, size=fr.size)
+    keep = fc != fr
+    rows.append(fr[keep])
+    cols.append(fc[keep])
+    r = np.concatenate(rows)
+    c = np.concatenate(cols)
+    pair = np.unique(r.astype(np.int64) * n + c)  # a far coupling may repeat a grid one
+    r, c = pair // n, pair % n
+    v = -rng.uniform(0.0, 1.0, size=r.size)
+    rsum = np.zeros(n)
+    csum = np.zeros(n)
+    np.add.at(rsum, r, -v)
+    np.add.at(csum, c, -v)
+    r = np.concatenate([r, idx])
+    c = np.concatenate([c, idx])
+    v = np.concatenate([v, 1.5 * np.maximum(rsum, csum) + 0.1])
+    return _coo_to_csr(n, r, c, v)
+
+
 def random_nonsym_dd(rng: np.random.Generator, nx: int, ny: int, nz: int = 1) -> CSR:
     """Random nonsymmetric grid operator with positive diagonal dominance:
     off-diagonals uniform on (-2, 0], diagonal = 1.2 * max(row, column) sum."""
