@@ -7,7 +7,7 @@ import numpy as np
 import scipy.sparse as sp
 
 from workloads import (config4_batch, convdiff2d_upwind, diffusion3d_from_coeff, gaussian_field3d, serving_stream,
-                       build_request_operator)
+                       build_request_operator, one_sided_dd)
 
 
 def _csr(A):
@@ -47,6 +47,20 @@ def test_convdiff_upwind_row_sums_and_nonsymmetry():
     interior = [i + 10 * j for i in range(1, 9) for j in range(1, 9)]
     assert np.allclose(A[interior].sum(axis=1), 0.0)
     assert np.all(np.diag(A) >= np.abs(A - np.diag(np.diag(A))).sum(axis=1) - 1e-12)
+
+
+def test_one_sided_operator_pattern_and_dominance():
+    """Sorted, duplicate-free rows; couplings without their transpose; strict
+    diagonal dominance by rows and by columns."""
+    C = one_sided_dd(np.random.default_rng(7), 29, 22)
+    for i in range(C.n):
+        row = C.col_idx[C.row_ptr[i]:C.row_ptr[i + 1]]
+        assert np.all(np.diff(row) > 0)
+    A = _csr(C).toarray()
+    S = A != 0
+    assert (S & ~S.T).sum() > 0
+    off = np.abs(A - np.diag(np.diag(A)))
+    assert np.all(np.diag(A) > off.sum(axis=1)) and np.all(np.diag(A) > off.sum(axis=0))
 
 
 def test_batch_workload_ranges():
