@@ -398,6 +398,49 @@ void hs_server_destroy(hs_server_t S);
  * factorization exists. */
 int hs_set_allocator(void* (*alloc_fn)(size_t, void*), void (*free_fn)(void*, void*), void* ctx);
 
+/* ---- kernel-variant thresholds ----------------------------------------- */
+
+/* Several steps have kernel variants that compute the same numbers and
+ * differ only in where their working data lives or how the work is split;
+ * size thresholds pick one.  These calls read and lower the thresholds for
+ * the whole process (test hooks, so that every variant runs on inputs small
+ * enough for a CPU reference, and a tuning aid).  A factorization copies the
+ * values when hs_factor / hs_factor_batch starts; later changes do not touch
+ * it.  Parameters (default, allowed range):
+ *   pivot_lds_max    128, 0..128   the pivot-block kernel keeps its working
+ *                                  matrix in LDS while the colour's largest
+ *                                  cluster is at most this size
+ *   trinv8_max       128, 0..128   triangular inverses (Eq. elim) on the
+ *                                  matrix cores with 8 blocks of 16 up to
+ *                                  this cluster size,
+ *   trinv12_max      192, 0..192   with 12 blocks up to this size (working
+ *                                  matrix in memory only), per-wave
+ *                                  substitution beyond
+ *   qr_reg1_max      64, 0..64     complement of A_ss^{-1} U (Eq. scaling):
+ *   qr_reg2_max      128, 0..128   Householder QR in registers with one / two
+ *                                  row slots per lane up to this cluster size
+ *                                  (for at most 64 coarse unknowns), in
+ *                                  memory beyond
+ *   wy_max           128, 0..128   its Q formed through the compact WY form
+ *                                  while the coarse size is at most this
+ *   gram_splits_max  256, 1..256   partial sums of the fill's Gram matrix
+ *                                  (Eq. lra) per cluster at most
+ *   schur_ptab_max   256, 0..256   Schur tile (Eq. elim): block pointers of
+ *                                  its neighbour pairs staged in LDS while
+ *                                  there are at most this many
+ *   schur_noff_max   1024, 0..1024 Schur tile: neighbour offsets staged in
+ *                                  LDS while there are at most this many
+ *   cholqr           1, 0..1       basis U of the fill by Cholesky QR (0:
+ *                                  always Householder QR)
+ *   dense_panel      128, 16..128  panel width of the dense LU of a complete
+ *                                  level (Alg. 1, final dense factorization)
+ * Errors: HS_ERR_ARG (unknown name, value outside its range, or a fraction
+ * for an integer parameter; nothing changed). */
+int hs_config_set(const char* name, double value);
+int hs_config_get(const char* name, double* value);
+/* Every parameter back to its default. */
+int hs_config_reset(void);
+
 /* Message describing the calling thread's last failure ("" if none). */
 const char* hs_last_error(void);
 

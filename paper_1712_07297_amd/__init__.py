@@ -11,6 +11,9 @@ from ._lib import (  # noqa: F401
     HsError,
     Server,
     Symbolic,
+    config_get,
+    config_reset,
+    config_set,
     header_functions,
     lib,
     profile_enable,

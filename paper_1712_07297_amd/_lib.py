@@ -157,6 +157,9 @@ _SIGS = {
     "hs_last_error": (ctypes.c_char_p, []),
     "hs_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "hs_version": (ctypes.c_char_p, []),
+    "hs_config_set": (ctypes.c_int, [ctypes.c_char_p, _D]),
+    "hs_config_get": (ctypes.c_int, [ctypes.c_char_p, _PD]),
+    "hs_config_reset": (ctypes.c_int, []),
 }
 
 
@@ -491,3 +494,18 @@ def strerror(code: int) -> str:
 
 def version() -> str:
     return lib().hs_version().decode()
+
+
+def config_set(name: str, value: float) -> None:
+    """hs_config_set: lower a kernel-variant threshold (process-wide)."""
+    _check(lib().hs_config_set(name.encode(), float(value)), f"hs_config_set({name})")
+
+
+def config_get(name: str) -> float:
+    v = ctypes.c_double()
+    _check(lib().hs_config_get(name.encode(), ctypes.byref(v)), f"hs_config_get({name})")
+    return v.value
+
+
+def config_reset() -> None:
+    _check(lib().hs_config_reset(), "hs_config_reset")

@@ -34,6 +34,26 @@ typedef __attribute__((address_space(1))) float glb_f32;
 __device__ inline lds_f64* to_lds(double* p) { return (lds_f64*)p; }
 __device__ inline lds_i32* to_lds(int* p) { return (lds_i32*)p; }
 
+// Size thresholds that choose between kernel variants computing the same
+// numbers (they differ in where the working data lives and how the work is
+// split).  The defaults are the production choices; hs_config_set() lowers
+// them so that every variant can be run on small inputs.  All are clamped to
+// the compile-time capacities below.
+struct Knobs {
+    int pivot_lds_max;    // pivot kernel: working matrix in LDS while the colour's largest cluster <= this
+    int trinv8_max;       // triangular inverses on the matrix cores (8 blocks of 16) up to this size
+    int trinv12_max;      // ... with 12 blocks up to this size (global-memory pivot kernel); beyond:
+                          // per-wave substitution
+    int qr_reg1_max;      // complement: Householder QR in registers, one row slot per lane, up to this m
+    int qr_reg2_max;      // ... two row slots per lane up to this m (both for k <= 64); else in memory
+    int wy_max;           // complement's Q formed through the compact WY form while k <= this
+    int gram_splits_max;  // Gram partial sums of one cluster at most (fill partners per workgroup beyond)
+    int schur_ptab_max;   // Schur tile: block pointers of its neighbour pairs in LDS while their count <= this
+    int schur_noff_max;   // Schur tile: packed neighbour offsets in LDS while the neighbours <= this
+    int cholqr;           // 1: basis U by Cholesky QR (Householder when ill conditioned); 0: Householder
+    int qrcp;             // 1: rank and U by Householder QR with column pivoting of F^T (not the Gram route)
+};
+
 // Per-level view of the factorization state (device pointers).
 struct LevelDev {
     int ncl;
@@ -69,18 +89,20 @@ struct LevelDev {
     double* rec;              // same element type as the cluster's blocks (offsets in its units)
     const int64_t* ws_off;    // [ncl] per-colour workspace of every cluster
     double* ws;
+    Knobs kn;
 };
 
 // Workspace slots of a cluster (each m x m, column major, ld m).
 enum WsSlot { WS_AINV = 0, WS_LINV, WS_UINV, WS_U, WS_X, WS_SL, WS_SR, WS_TL, WS_TR, WS_CU, WS_UC, WS_SCR, WS_GP };
 __host__ __device__ inline int64_t ws_slots(int gram_splits) { return WS_GP + gram_splits; }
 // Gram partial sums of a cluster with nf fill partners: one partner per
-// workgroup up to GRAM_SPLITS_MAX.  A function of the cluster alone, so the
+// workgroup up to max_splits (at most GRAM_SPLITS_MAX), then consecutive
+// partners share a workgroup.  A function of the cluster alone, so the
 // sums are formed in the same order whatever else shares the launch.
 constexpr int GRAM_SPLITS_MAX = 256;
-__host__ __device__ inline int gram_splits_of(int nf) {
-    const int s = nf;
-    return s < 1 ? 1 : (s > GRAM_SPLITS_MAX ? GRAM_SPLITS_MAX : s);
+__host__ __device__ inline int gram_splits_of(int nf, int max_splits) {
+    const int cap = max_splits < 1 ? 1 : (max_splits > GRAM_SPLITS_MAX ? GRAM_SPLITS_MAX : max_splits);
+    return nf < 1 ? 1 : (nf > cap ? cap : nf);
 }
 
 __device__ inline int cur_size(const LevelDev& L, int a, int before) { return before ? L.k[a] : L.m[a]; }

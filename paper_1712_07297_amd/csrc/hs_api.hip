@@ -367,12 +367,20 @@ struct LevelData {
     size_t esz(int s) const { return f32[s] ? sizeof(float) : sizeof(double); }
 };
 
+// Process-wide kernel-variant thresholds (hs_config_set), copied into a
+// factorization when it starts; the variants compute the same numbers.
+struct Config {
+    Knobs kn{LDS_M, TRI_MFMA_MAX, TRI_MFMA_MAX12, 64, 128, TRI_MFMA_MAX, GRAM_SPLITS_MAX, 256, 1024, 1, 0};
+    int dense_panel = 128;
+};
+
 }  // namespace hs
 
 struct hs_factor_s {
     hs::ByteAccount acct;                 // first member: outlives every buffer below
     int64_t n = 0;
     hs_opts opts{};
+    hs::Config cfg;                       // kernel-variant thresholds of this factorization
     int symmetric = 1;
     hs::Symbolic sym;
     hs::Forest forest;                    // the systems (one for hs_factor)
@@ -425,6 +433,36 @@ constexpr int64_t MIXED_FP64_DOFS = 16384;
 // Per-cluster workspace of one factor launch at most (colours beyond it are
 // launched in chunks that reuse the workspace).
 constexpr int64_t WS_CHUNK_BYTES = int64_t(4) << 30;
+
+// ============================================================ configuration
+
+static std::mutex g_config_mu;
+static Config g_config;
+static Config config_snapshot() {
+    std::lock_guard<std::mutex> lk(g_config_mu);
+    return g_config;
+}
+struct ConfigEntry {
+    const char* name;
+    double lo, hi;
+    int* ival;        // integer parameter, or
+    double* dval;     // real parameter
+};
+static std::vector<ConfigEntry> config_table(Config& c) {
+    return {
+        {"pivot_lds_max", 0, LDS_M, &c.kn.pivot_lds_max, nullptr},
+        {"trinv8_max", 0, TRI_MFMA_MAX, &c.kn.trinv8_max, nullptr},
+        {"trinv12_max", 0, TRI_MFMA_MAX12, &c.kn.trinv12_max, nullptr},
+        {"qr_reg1_max", 0, 64, &c.kn.qr_reg1_max, nullptr},
+        {"qr_reg2_max", 0, 128, &c.kn.qr_reg2_max, nullptr},
+        {"wy_max", 0, TRI_MFMA_MAX, &c.kn.wy_max, nullptr},
+        {"gram_splits_max", 1, GRAM_SPLITS_MAX, &c.kn.gram_splits_max, nullptr},
+        {"schur_ptab_max", 0, 256, &c.kn.schur_ptab_max, nullptr},
+        {"schur_noff_max", 0, 1024, &c.kn.schur_noff_max, nullptr},
+        {"cholqr", 0, 1, &c.kn.cholqr, nullptr},
+        {"dense_panel", 16, 128, &c.dense_panel, nullptr},
+    };
+}
 
 // =============================================================== validation
 
@@ -495,7 +533,7 @@ static int plan_level(hs_factor_s* F, int lvl, Blob& blob, std::vector<size_t>& 
     }
     LD.rec_bytes = roff;
     LD.npairs = pp;
-    LD.gram_splits = gram_splits_of(max_nf);  // workspace slots; each cluster uses gram_splits_of(its nf)
+    LD.gram_splits = gram_splits_of(max_nf, F->cfg.kn.gram_splits_max);  // workspace slots; each cluster uses gram_splits_of(its nf)
     const int64_t slots = ws_slots(LD.gram_splits);
 
     // colours: every colour's slice of the processing order is reordered into
@@ -647,6 +685,7 @@ static void bind_level(LevelData& LD, const std::vector<size_t>& offs, const hs_
     D.eps = F->opts.eps;
     D.fixed_rank = F->opts.fixed_rank;
     D.gram_splits = LD.gram_splits;
+    D.kn = F->cfg.kn;
     D.m = (const int*)P(0);
     D.k = (int*)P(1);
     D.flag = (int*)P(2);
@@ -822,7 +861,7 @@ static int factor_dense_ranges(hs_factor_s* F, int lvl, const std::vector<std::a
         const int rc = dense_level_factor(dense.as<double>(), N, LD.dev_pat_ptr, LD.dev_pat, c0, b0, LD.dev.m + c0,
                                           (const int64_t*)(base + o_off[r]), LD.dev.blk_off, LD.dev.blocks, c1 - c0,
                                           S.pat_ptr[c1] - b0, inv, dflag + r, LD.dev.ncap + c0, LD.dev.rec_off + c0,
-                                          LD.dev.rec, m_host, offs[r], st);
+                                          LD.dev.rec, m_host, offs[r], F->cfg.dense_panel, st);
         if (rc) return fail(HS_ERR_HIP, "dense level launch failed");
     }
     return HS_OK;
@@ -1738,6 +1777,7 @@ static int factor_entry(int32_t nsys, const hs_csr* A, const hs_geometry* geom, 
     if (rc) return rc;
     std::unique_ptr<hs_factor_s> F(new hs_factor_s());
     F->opts = *opts;
+    F->cfg = config_snapshot();
     F->info.breakdown_level = -1;
     F->info.breakdown_cluster = -1;
     AcctScope scope(&F->acct);
@@ -2021,5 +2061,41 @@ const char* hs_strerror(int code) {
 }
 
 const char* hs_version(void) { return kVersion; }
+
+int hs_config_set(const char* name, double value) {
+    if (!name) return fail(HS_ERR_ARG, "null name");
+    std::lock_guard<std::mutex> lk(g_config_mu);
+    for (const ConfigEntry& e : config_table(g_config)) {
+        if (std::strcmp(e.name, name) != 0) continue;
+        if (!(value >= e.lo && value <= e.hi))
+            return fail(HS_ERR_ARG, std::string(name) + " outside [" + std::to_string(e.lo) + ", " +
+                                        std::to_string(e.hi) + "]");
+        if (e.ival) {
+            if (value != std::floor(value)) return fail(HS_ERR_ARG, std::string(name) + " takes an integer");
+            *e.ival = (int)value;
+        } else {
+            *e.dval = value;
+        }
+        return HS_OK;
+    }
+    return fail(HS_ERR_ARG, std::string("unknown configuration parameter ") + name);
+}
+
+int hs_config_get(const char* name, double* value) {
+    if (!name || !value) return fail(HS_ERR_ARG, "null argument");
+    std::lock_guard<std::mutex> lk(g_config_mu);
+    for (const ConfigEntry& e : config_table(g_config))
+        if (std::strcmp(e.name, name) == 0) {
+            *value = e.ival ? (double)*e.ival : *e.dval;
+            return HS_OK;
+        }
+    return fail(HS_ERR_ARG, std::string("unknown configuration parameter ") + name);
+}
+
+int hs_config_reset(void) {
+    std::lock_guard<std::mutex> lk(g_config_mu);
+    g_config = Config();
+    return HS_OK;
+}
 
 }  // extern "C"

@@ -3,9 +3,10 @@
 // cluster is eliminated exactly by a block LU step and the level is the
 // "small enough" case of Alg. 1, factored by the conventional dense
 // factorization: here an unpivoted LU of the whole level matrix in
-// processing order, blocked with 128-wide panels.  The per-cluster operators
-// of the solve (T_L' = L_ss^{-1}, T_R' = U_ss^{-1}, E_R = U[s, later],
-// E_L = L[later, s]) are then cut out of the factors.
+// processing order, blocked with panels of at most 128 columns (128 by
+// default; narrower panels run the same kernels on smaller matrices).  The
+// per-cluster operators of the solve (T_L' = L_ss^{-1}, T_R' = U_ss^{-1},
+// E_R = U[s, later], E_L = L[later, s]) are then cut out of the factors.
 #include <algorithm>
 #include <vector>
 
@@ -14,7 +15,7 @@
 
 namespace hs {
 
-constexpr int DNB = 128;  // panel width
+constexpr int DNB = 128;  // widest panel (layout of the diagonal inverses)
 
 // D[o_a + i, o_b + j] = B(a, b)[i, j] for every block of the clusters
 // c0 .. c0 + ncl - 1 (pattern entries from b0; a, c local to the range).
@@ -167,13 +168,14 @@ __global__ void k_dense_couplings(const double* __restrict__ D, int64_t ldd, int
 int dense_level_factor(double* D, int64_t N, const int* pat_ptr, const int* pat, int c0, int b0, const int* m,
                        const int64_t* off, const int64_t* blk_off, const double* blocks, int ncl, int nblk,
                        double* inv, int* flag, const int* ncap, const int64_t* rec_off, double* rec,
-                       const std::vector<int>& m_host, const std::vector<int64_t>& off_host, hipStream_t st) {
+                       const std::vector<int>& m_host, const std::vector<int64_t>& off_host, int panel, hipStream_t st) {
+    const int pw = std::max(16, std::min(DNB, panel));
     launch_fill_zero(D, N * N * (int64_t)sizeof(double), st);
     if (nblk > 0)
         hipLaunchKernelGGL(k_dense_assemble, dim3(nblk), dim3(256), 0, st, pat_ptr, pat, c0, b0, m, off, blk_off,
                            blocks, D, (int64_t)N, ncl);
-    for (int64_t p = 0; p < N; p += DNB) {
-        const int nb = (int)std::min<int64_t>(DNB, N - p);
+    for (int64_t p = 0; p < N; p += pw) {
+        const int nb = (int)std::min<int64_t>(pw, N - p);
         hipLaunchKernelGGL(k_dense_diag, dim3(1), dim3(WG), (size_t)nb * nb * sizeof(double), st, D, (int64_t)N, (int)p,
                            nb, inv, flag);
         const int64_t rest = N - p - nb;

@@ -106,7 +106,7 @@ __global__ void __launch_bounds__(WG) k_gram(LevelDev L, const int* __restrict__
     if (M == 0) return;
     double* Gp = L.ws + L.ws_off[s] + (int64_t)(WS_GP + split) * M * M;
     const int f0 = L.fill_ptr[s], nf = L.fill_ptr[s + 1] - f0;
-    const int splits = gram_splits_of(nf);
+    const int splits = gram_splits_of(nf, L.kn.gram_splits_max);
     if (split >= splits) return;
     const int chunk = (nf + splits - 1) / splits;
     const int e0 = f0 + split * chunk, e1 = min(f0 + nf, e0 + chunk);
@@ -146,7 +146,7 @@ __global__ void k_gram_reduce(LevelDev L, const int* __restrict__ clist) {
     const int64_t MM = (int64_t)M * M;
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= MM) return;
-    const int splits = gram_splits_of(L.fill_ptr[s + 1] - L.fill_ptr[s]);
+    const int splits = gram_splits_of(L.fill_ptr[s + 1] - L.fill_ptr[s], L.kn.gram_splits_max);
     double* G = L.ws + L.ws_off[s] + WS_GP * MM;
     double g = G[e];
     int sp = 1;
@@ -403,17 +403,18 @@ __device__ bool wg_cholqr2(const double* X, int M, int k, PG G, double* T1, doub
 // Householder complement: Q columns [K, M) of the QR of X (M x K, ld M) into
 // V (ld ldv), Q formed through its compact WY form (scratch: three global
 // M x M slots).  X is destroyed.  The QR keeps X in registers when it fits
-// (M <= 128, K <= 64); scr then holds the published reflectors.
+// (M <= 128, K <= 64); scr then holds the published reflectors.  Which form
+// runs is set by the size thresholds of kn (all give the same reflectors).
 template <class PX, class PV, class PT>
 __device__ void wg_complement(PX X, int M, int K, PV V, int ldv, PT tau_sh, double* s1, double* s2, double* s3,
-                              lds_smem* sm, lds_f64* scr) {
-    if (K <= 64 && M <= 64)
+                              lds_smem* sm, lds_f64* scr, const Knobs& kn) {
+    if (K <= 64 && M <= min(64, kn.qr_reg1_max))
         wg_house_qr_reg<1>(X, M, K, M, tau_sh, scr);
-    else if (K <= 64 && M <= 128)
+    else if (K <= 64 && M <= min(128, kn.qr_reg2_max))
         wg_house_qr_reg<2>(X, M, K, M, tau_sh, scr);
     else
         wg_house_qr(X, M, K, M, tau_sh);
-    if (K <= TRI_MFMA_MAX)
+    if (K <= min(TRI_MFMA_MAX, kn.wy_max))
         wg_house_form_q_wy(X, M, K, M, tau_sh, K, M - K, V, ldv, false, s1, s2, s3, sm, scr);
     else
         wg_house_form_q(X, M, K, M, tau_sh, K, M - K, V, ldv);
@@ -422,8 +423,14 @@ __device__ void wg_complement(PX X, int M, int K, PV V, int ldv, PT tau_sh, doub
 // Per-cluster elimination operators.  The working M x M matrix W lives in
 // LDS when the colour's largest cluster fits (lds_m), else in the cluster's
 // L2-resident workspace; every dense step below reuses it in turn.
+// One workgroup per CU: with 512 registers per lane (256 of them
+// accumulation registers) the kernel keeps every value in registers; with
+// two workgroups per CU it spilled 20-160 registers per lane to scratch
+// memory, and builds that spilled more than about 30 gave wrong factors at
+// random clusters of large launches (see the tests that check the compiled
+// kernel spills nothing).
 template <bool INLDS, class T>
-__global__ void __launch_bounds__(WG, 2) k_pivot(LevelDev L, const int* __restrict__ clist) {
+__global__ void __launch_bounds__(WG, 1) k_pivot(LevelDev L, const int* __restrict__ clist) {
     extern __shared__ double dyn[];  // INLDS: M * M doubles (largest M of the colour); else 12 x 256
     __shared__ GemmSmem sm;
     __shared__ double red[16];
@@ -470,11 +477,15 @@ __global__ void __launch_bounds__(WG, 2) k_pivot(LevelDev L, const int* __restri
     // block scratch: the GEMM staging area (2080 doubles) when the working
     // matrix is in LDS, else 12 x 256 doubles of dynamic LDS
     lds_f64* scr = INLDS ? (lds_f64*)sm_l : to_lds(dyn);
-    // triangular inverses: matrix cores with 8 blocks up to 128, 12 blocks up
-    // to 192, per-wave substitution beyond (chosen by M alone)
-    const int tri = M <= TRI_MFMA_MAX ? 1 : (M <= TRI_MFMA_MAX12 ? 2 : 0);
+    // triangular inverses: matrix cores with 8 blocks up to 128 (always in
+    // the LDS kernel, whose clusters are at most 128), 12 blocks up to 192,
+    // per-wave substitution beyond (chosen by M and the thresholds alone)
+    const int tri = INLDS ? 1
+                          : (M <= min(TRI_MFMA_MAX, L.kn.trinv8_max)
+                                 ? 1
+                                 : (M <= min(TRI_MFMA_MAX12, L.kn.trinv12_max) ? 2 : 0));
     auto inv_lower = [&](auto Wp, int n, auto out) {
-        if (INLDS || tri == 1)
+        if (tri == 1)
             wg_trinv_lower_unit<1>(Wp, n, M, out, M, scr);
         else if (tri == 2)
             wg_trinv_lower_unit<2>(Wp, n, M, out, M, scr);
@@ -482,7 +493,7 @@ __global__ void __launch_bounds__(WG, 2) k_pivot(LevelDev L, const int* __restri
             wg_trinv_lower_unit<0>(Wp, n, M, out, M, scr);
     };
     auto inv_upper = [&](auto Wp, int n, auto out) {
-        if (INLDS || tri == 1)
+        if (tri == 1)
             wg_trinv_upper<1>(Wp, n, M, out, M, scr);
         else if (tri == 2)
             wg_trinv_upper<2>(Wp, n, M, out, M, scr);
@@ -533,7 +544,8 @@ __global__ void __launch_bounds__(WG, 2) k_pivot(LevelDev L, const int* __restri
             }
             __syncthreads();
             bool done = false;
-            done = wg_cholqr2(X, M, kk, W, Linv, Uinv, Umat, sm_l, scr, red_l, to_lds(isc + 1),
+            if (L.kn.cholqr)
+                done = wg_cholqr2(X, M, kk, W, Linv, Uinv, Umat, sm_l, scr, red_l, to_lds(isc + 1),
                               std::is_same<T, float>::value ? CHOLQR_ONE_PASS_F32 : CHOLQR_ONE_PASS);
             if (!done) {
                 wg_copy(M, kk, X, M, W, M);
@@ -567,14 +579,14 @@ __global__ void __launch_bounds__(WG, 2) k_pivot(LevelDev L, const int* __restri
     // ---- 3. sparsification operator E_s (Eq. scaling)
     // S_L = [V_L U], V_L the complement of A^{-1} U
     wg_gemm<false, false>(M, kk, M, 1.0, Ainv, M, Umat, M, 0.0, W, M, sm_l);
-    wg_complement(W, M, kk, SL, M, dsh_l, Linv, Uinv, X, sm_l, scr);
+    wg_complement(W, M, kk, SL, M, dsh_l, Linv, Uinv, X, sm_l, scr, L.kn);
     wg_copy(M, kk, Umat, M, SL + (int64_t)f * M, M);
     __syncthreads();
     if (L.symmetric) {
         wg_copy(M, M, SL, M, SR, M);
     } else {
         wg_gemm<true, false>(M, kk, M, 1.0, Ainv, M, Umat, M, 0.0, W, M, sm_l);  // A^{-T} U
-        wg_complement(W, M, kk, SR, M, dsh_l, Linv, Uinv, X, sm_l, scr);
+        wg_complement(W, M, kk, SR, M, dsh_l, Linv, Uinv, X, sm_l, scr, L.kn);
         wg_copy(M, kk, Umat, M, SR + (int64_t)f * M, M);
     }
     __syncthreads();
@@ -609,7 +621,7 @@ void launch_pivot(const LevelDev& L, const ColourDev& C, hipStream_t st, bool of
     if (C.n == 0) return;
     if (!offsets_done) hipLaunchKernelGGL(k_offsets, dim3(C.n), dim3(WG), 0, st, L, C.clist);
     const size_t shmem = (size_t)C.max_m * C.max_m * sizeof(double);
-    if (C.max_m <= LDS_M) {
+    if (C.max_m <= min(LDS_M, L.kn.pivot_lds_max)) {
         if (C.f32)
             hipLaunchKernelGGL((k_pivot<true, float>), dim3(C.n), dim3(WG), shmem, st, L, C.clist);
         else
@@ -848,7 +860,7 @@ __global__ void __launch_bounds__(WG, 5) k_schur(LevelDev L, ColourDev C) {
     const T* ER = rec_t<T>(L, s) + 2 * MM;  // f x ntot, ld M
     const T* EL = ER + (int64_t)M * ncap;   // ntot x f, ld ncap
     const int e0 = L.nbr_ptr[s], nb = L.nbr_ptr[s + 1] - e0;
-    if (nb <= NOFF_LDS) {
+    if (nb <= min(NOFF_LDS, L.kn.schur_noff_max)) {
         for (int x = threadIdx.x; x < nb; x += blockDim.x) mp.noff[x] = L.nbr_noff[e0 + x];
         __syncthreads();
         map_rows(to_lds(mp.noff), nb, r0, nt, mp.rblk, mp.rloc);
@@ -871,7 +883,7 @@ __global__ void __launch_bounds__(WG, 5) k_schur(LevelDev L, ColourDev C) {
     const int nr = min(SCHUR_T, nt - r0), nc = min(SCHUR_T, nt - c0);
     const int bi0 = mp.rblk[0], bj0 = mp.cblk[0];
     const int nbi = mp.rblk[nr - 1] - bi0 + 1, nbj = mp.cblk[nc - 1] - bj0 + 1;
-    const bool table = nbi * nbj <= PTAB;
+    const bool table = nbi * nbj <= min(PTAB, L.kn.schur_ptab_max);
     if (table) {
         for (int x = threadIdx.x; x < nbi * nbj; x += blockDim.x) {
             const int i = x / nbj, j = x % nbj;

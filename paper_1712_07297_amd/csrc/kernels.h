@@ -84,15 +84,17 @@ void launch_pair_blocks(int ncl, const int* nbr_ptr, const int* nbr_id, const in
                         const int64_t* pair_base, int* pair_blk, hipStream_t st);
 // Dense level (complete cluster graph): assemble D (N x N, ld N) from the
 // block store, unpivoted blocked LU in place, per-cluster operators into the
-// records.  inv: 2 * 128 * 128 doubles of workspace; flag: device int, set to
-// 1 on a zero or non-finite pivot.
+// records, with panels of `panel` columns (16..128).  inv: 2 * 128 * 128
+// doubles of workspace; flag: device int, set to 1 on a zero or non-finite
+// pivot.
 // The clusters are c0 .. c0 + ncl - 1 of the level (one system); their blocks
 // are pattern entries b0 .. b0 + nblk - 1; m, off, ncap, rec_off point at
 // cluster c0's entry; m_host / off_host are local to the range.
 int dense_level_factor(double* D, int64_t N, const int* pat_ptr, const int* pat, int c0, int b0, const int* m,
                        const int64_t* off, const int64_t* blk_off, const double* blocks, int ncl, int nblk,
                        double* inv, int* flag, const int* ncap, const int64_t* rec_off, double* rec,
-                       const std::vector<int>& m_host, const std::vector<int64_t>& off_host, hipStream_t st);
+                       const std::vector<int>& m_host, const std::vector<int64_t>& off_host, int panel,
+                       hipStream_t st);
 
 // ---- solve (Alg. 2)
 struct SolveLevelDev {

@@ -134,3 +134,25 @@ def test_batch_convdiff_sample(P):
         x = X[Fb.row_off[i]:Fb.row_off[i + 1]]
         r = p.B[:, 0] - _csr(p.A) @ x
         assert np.linalg.norm(r) <= 1.01e-10 * np.linalg.norm(p.B[:, 0]), i
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_batch_factor_is_deterministic(P, precision):
+    """The 24-system convection-diffusion batch factored three times gives the
+    same preconditioner bit for bit (hundreds of pivot workgroups per launch
+    at level 0: a regression test for results that changed from run to run
+    when the pivot kernel spilled registers to scratch memory)."""
+    probs = config4_batch(count=24)
+    systems = [(p.A.row_ptr, p.A.col_idx, p.A.val, p.dims) for p in probs]
+    prec = P.HS_MIXED if precision == "mixed" else P.HS_FP64
+    B = torch.tensor(np.random.default_rng(5).uniform(-1, 1, (1, sum(p.A.n for p in probs))), device="cuda")
+    ref = None
+    for rep in range(3):
+        Fb = P.Factor.batch(systems, eps=1e-3, leaf=64, symmetric=0, precision=prec)
+        X = Fb.solve(B)
+        torch.cuda.synchronize()
+        if ref is None:
+            ref = X.clone()
+        else:
+            assert torch.equal(X, ref), rep
+        Fb.free()

@@ -1,15 +1,10 @@
 """Parity of the HIP library with the CPU oracle, through the C ABI.
 
-Bars (from the method's accuracy requirements):
-  * integer work (tree, colours, ranks, sizes): bit-exact;
-  * factor entries at eps = 0 (every level's matrix, every stored operator):
-    within 1e-10 relative;
-  * at eps > 0 with no pivot near-tie: ranks bit-exact, level matrices and
-    stored operators within TOL_EPS(eps) = max(1e-9, 1e-13 / eps^2) relative
-    (the Gram-matrix form of the rank-revealing QR resolves the weakest kept
-    direction to about u / eps^2);
-  * solves within 1e-8 relative of the oracle's (1e-7 under a fixed-rank
-    cap, whose kept basis is only as well determined as the gap below it).
+Bars (parity_util): sizes and ranks bit-exact; level matrices and stored
+operators within 1e-10 relative at eps = 0, within tol_eps(eps) =
+max(1e-9, 1e-13 / eps^2) (records 100 tol_eps) at eps > 0 on the Gram route;
+solves within 1e-8 relative of the oracle's (1e-7 under a fixed-rank cap,
+whose kept basis is only as well determined as the gap below it).
 """
 
 import numpy as np
@@ -19,6 +14,7 @@ import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
 import oracle as O
+from parity_util import compare_factor, solve_both
 from workloads import (
     chain1d,
     config1,
@@ -46,61 +42,13 @@ def P():
     return P
 
 
-def _tol_eps(eps):
-    return 1e-10 if eps == 0 else max(1e-9, 1e-13 / eps**2)
-
-
-def _oracle_ops(rec):
-    """T_L', T_R', E_R, E_L of an oracle record, as the library stores them."""
-    if rec.kind == "full":
-        return np.linalg.inv(rec.L), np.linalg.inv(rec.Uu), rec.ER, rec.EL
-    Ainv = np.linalg.inv(rec.L @ rec.Uu)
-    TL = np.vstack([np.linalg.solve(rec.Lf, rec.VL.T @ Ainv), rec.U.T @ Ainv])
-    TR = np.hstack([Ainv @ rec.VR @ np.linalg.inv(rec.Uf), Ainv @ rec.U])
-    return TL, TR, rec.ER, rec.EL
-
-
-def _rel(a, b, scale):
-    return np.abs(a - b).max() / scale if a.size else 0.0
-
-
 def _compare_factor(P, A, dims, leaf, eps, sym, check_records=True, max_level_check=99):
-    fo = O.factor(A.row_ptr, A.col_idx, A.val, dims, leaf, eps, sym, keep_blocks=True)
-    F = P.Factor(A.row_ptr, A.col_idx, A.val, dims, eps, leaf, symmetric=1 if sym else 0, keep_levels=True)
-    tol = _tol_eps(eps)
-    info = F.info()
-    assert info.nlevels == len(fo.levels)
-    for l, lev in enumerate(fo.levels):
-        assert np.array_equal(F.sizes(l), lev.m), f"sizes level {l}"
-        assert np.array_equal(F.ranks(l), lev.k), f"ranks level {l}"
-        if sum(lev.m) == 0 or l > max_level_check:
-            continue
-        Mo, _ = O.assemble_level_dense(lev)
-        Mg = F.level_matrix(l)
-        scale = np.abs(Mo).max()
-        assert _rel(Mg, Mo, scale) <= tol, f"level {l} matrix"
-        if not check_records:
-            continue
-        for s, rec in enumerate(lev.records):
-            if rec.kind not in ("full", "lowrank"):
-                continue
-            ops = _oracle_ops(rec)
-            base = max(1.0, np.abs(ops[0]).max())
-            for name, o in zip(("TL", "TR", "ER", "EL"), ops):
-                g = F.record(l, s, name)
-                assert g.shape == o.shape, (l, s, name)
-                if o.size == 0:
-                    continue
-                sc = max(np.abs(o).max(), 1e-8 * base)
-                assert _rel(g, o, sc) <= max(tol * 100, 1e-9), (l, s, name, _rel(g, o, sc))
+    fo, F, _ = compare_factor(P, A, dims, leaf, eps, sym, check_records, max_level_check)
     return fo, F
 
 
 def _solve_both(P, fo, F, n, nrhs=3, seed=0):
-    B = np.random.default_rng(seed).uniform(-1, 1, (n, nrhs))
-    Xo = O.solve(fo, B)
-    Xg = F.solve(torch.tensor(B.T.copy(), device="cuda")).cpu().numpy().T
-    return B, Xo, Xg
+    return solve_both(P, torch, fo, F, n, nrhs, seed)
 
 
 EXACT = [

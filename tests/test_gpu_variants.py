@@ -1,0 +1,129 @@
+"""Every kernel variant of the factorization compared with the CPU oracle,
+element by element, through the C ABI.
+
+Two routes reach the variants that production picks by size:
+  * inputs with large leaves, which reach them the way full-size problems
+    do (clusters above 128 and 192 unknowns, coarse sizes above 64, complete
+    levels wider than one 128-column panel);
+  * hs_config_set, which lowers the size thresholds so that the same
+    production code paths run on inputs small enough for the oracle (a Gram
+    workgroup that sums several fill partners, Schur tiles without the LDS
+    pointer table or offsets, the memory-resident pivot kernel, the per-wave
+    triangular inverses, the in-memory Householder complement, Q without the
+    WY form, U by Householder QR, narrow dense panels).
+
+Bars are those of parity_util: sizes and ranks bit-exact, level matrices and
+stored operators within 1e-10 relative at eps = 0 (tol_eps(eps) and
+100 tol_eps(eps) at eps > 0), solves within 1e-8.
+"""
+
+import numpy as np
+import pytest
+
+from parity_util import compare_factor, fill_ratio_of_c1, knobs, scaled_coupling_poisson, solve_both
+from workloads import convdiff2d_upwind, poisson2d, poisson3d, random_nonsym_dd
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1712_07297_amd as P
+
+    P.lib()
+    P.config_reset()
+    return P
+
+
+def _check_solve(P, fo, F, A):
+    B, Xo, Xg = solve_both(P, torch, fo, F, A.n)
+    err = np.linalg.norm(Xg - Xo) / np.linalg.norm(Xo)
+    assert err < 1e-8, err
+    return err
+
+
+# ---------------------------------------------------------------- large leaves
+# (name, matrix, dims, leaf, eps, symmetric, what the oracle must show)
+LARGE = [
+    # level 0: clusters of 144 > 128 with fill at eps > 0 -> pivot kernel with
+    # its working matrix in memory, right-looking pivoted Cholesky, complement
+    # QR in memory, 12-block triangular inverses (128 < m <= 192)
+    ("p2d_leaf144", lambda: poisson2d(48, 48), (48, 48, 1), 144, 1e-4, True, dict(max_lowrank_m=144)),
+    # clusters of 256 > 192: per-wave triangular inverses
+    ("p2d_leaf256", lambda: poisson2d(64, 64), (64, 64, 1), 256, 1e-4, True, dict(max_lowrank_m=256)),
+    # coarse sizes above 64 (k = 65 at m = 108): complement QR in memory at
+    # m <= 128; two-slot register QR for 64 < m <= 128 with k <= 64
+    ("p3d_leaf200", lambda: poisson3d(12, 12, 12), (12, 12, 12), 200, 1e-4, True, dict(max_k=65)),
+    # exact mode: block LU steps of clusters up to 216 (per-wave inverses in the
+    # memory-resident pivot kernel), complete level of 1080 unknowns factored
+    # with 9 dense panels, its clusters of up to 324 inverted per wave
+    ("p3d_leaf160_exact", lambda: poisson3d(12, 12, 12), (12, 12, 12), 160, 0.0, True, dict(max_m=324)),
+    # nonsymmetric with clusters of 144: both complements, row and column fill
+    ("convdiff_leaf144", lambda: convdiff2d_upwind(48, 50.0, 0.3), (48, 48, 1), 144, 1e-4, False,
+     dict(max_lowrank_m=144)),
+]
+
+
+@pytest.mark.parametrize("name,mk,dims,leaf,eps,sym,expect", LARGE, ids=[c[0] for c in LARGE])
+def test_large_clusters(P, name, mk, dims, leaf, eps, sym, expect):
+    A = mk()
+    print(f"[variants] {name}: n={A.n} leaf={leaf} eps={eps}", flush=True)
+    fo, F, st = compare_factor(P, A, dims, leaf, eps, sym)
+    for key, val in expect.items():
+        assert st[key] >= val, (key, st[key], val)
+    err = _check_solve(P, fo, F, A)
+    print(f"[variants] {name}: {st} solve {err:.2e}", flush=True)
+
+
+# ------------------------------------------------------- thresholds lowered
+SMALL = {
+    "p3d": (lambda: poisson3d(10, 9, 8), (10, 9, 8), 32, 1e-4, True),
+    "nonsym": (lambda: random_nonsym_dd(np.random.default_rng(12), 20, 16), (20, 16, 1), 10, 1e-3, False),
+    "p2d_exact": (lambda: poisson2d(16, 12), (16, 12, 1), 8, 0.0, True),
+}
+
+FORCED = [
+    ("pivot_in_memory", dict(pivot_lds_max=0), ["p3d", "nonsym", "p2d_exact"]),
+    ("trinv_12_blocks", dict(pivot_lds_max=0, trinv8_max=0), ["p3d", "nonsym"]),
+    ("trinv_per_wave", dict(pivot_lds_max=0, trinv8_max=0, trinv12_max=0), ["p3d", "nonsym", "p2d_exact"]),
+    ("complement_two_slots", dict(qr_reg1_max=0), ["p3d", "nonsym"]),
+    ("complement_in_memory", dict(qr_reg1_max=0, qr_reg2_max=0), ["p3d", "nonsym"]),
+    ("complement_q_without_wy", dict(wy_max=0), ["p3d", "nonsym"]),
+    ("gram_partners_shared", dict(gram_splits_max=2), ["p3d", "nonsym"]),
+    ("gram_single_partial", dict(gram_splits_max=1), ["p3d"]),
+    ("schur_no_pointer_table", dict(schur_ptab_max=0), ["p3d", "nonsym", "p2d_exact"]),
+    ("schur_offsets_in_memory", dict(schur_noff_max=0, schur_ptab_max=3), ["p3d", "nonsym"]),
+    ("basis_by_householder", dict(cholqr=0), ["p3d", "nonsym"]),
+    ("dense_panels_16", dict(dense_panel=16), ["p3d", "p2d_exact"]),
+]
+
+FORCED_CASES = [(v, kn, inp) for v, kn, inputs in FORCED for inp in inputs]
+
+
+@pytest.mark.parametrize("variant,kn,inp", FORCED_CASES, ids=[f"{v}-{i}" for v, _, i in FORCED_CASES])
+def test_forced_variant(P, variant, kn, inp):
+    mk, dims, leaf, eps, sym = SMALL[inp]
+    A = mk()
+    print(f"[variants] {variant} on {inp}: {kn}", flush=True)
+    with knobs(P, **kn):
+        fo, F, st = compare_factor(P, A, dims, leaf, eps, sym)
+    _check_solve(P, fo, F, A)
+
+
+@pytest.mark.parametrize("factor_of_floor", [0.5, 2.0])
+def test_noise_floor_decision(P, factor_of_floor):
+    """Reading R12 on the device: fill at half the 1e-12 ||A_ss||_F floor is
+    dropped (k = 0), at twice the floor it is compressed; ranks, factor and
+    solve as the oracle's."""
+    d0 = 1e-6
+    _, leaf = scaled_coupling_poisson(1.0)
+    r1 = fill_ratio_of_c1(scaled_coupling_poisson(d0)[0], leaf) / d0
+    A, _ = scaled_coupling_poisson(factor_of_floor * 1e-12 / r1)
+    print(f"[variants] noise floor x{factor_of_floor}", flush=True)
+    fo, F, st = compare_factor(P, A, (4, 4, 1), 4, 1e-6, True)
+    assert (F.ranks(0)[1] == 0) == (factor_of_floor < 1.0)
+    _check_solve(P, fo, F, A)

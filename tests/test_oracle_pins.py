@@ -10,6 +10,7 @@ import pytest
 import scipy.linalg as sla
 
 import oracle as O
+from parity_util import fill_ratio_of_c1, scaled_coupling_poisson
 from workloads import (
     chain1d,
     config1,
@@ -410,3 +411,36 @@ def test_config1_direct_solve_accuracy():
     r = _relres(p.A, x[:, 0], p.B[:, 0])
     assert r < 1e-6
     assert len(fac.levels) == 7
+
+
+# ------------------------------------------------------------- R12 noise floor
+
+NOISE_FLOOR_R12 = 1e-12  # the fraction of ||A_ss||_F that reading R12 states
+
+
+@pytest.mark.parametrize("factor_of_floor,expect_zero", [(0.5, True), (2.0, False), (1e6, False)])
+def test_noise_floor_reading_r12(factor_of_floor, expect_zero):
+    """Reading R12: fill whose largest row norm is at most 1e-12 ||A_ss||_F is
+    rounding noise, k = 0; fill just above it is compressed (k > 0).  The
+    ratio is placed by scaling one inter-leaf coupling, using that the fill
+    B(c1, c2) = -A_10 A_00^{-1} A_02 is linear in it (computed here from the
+    dense Schur complement, not by the oracle)."""
+    _, leaf = scaled_coupling_poisson(1.0)
+    # the ratio is linear in delta up to the O(delta^2) change of B(c1, c1)
+    d0 = 1e-6
+    r1 = fill_ratio_of_c1(scaled_coupling_poisson(d0)[0], leaf) / d0
+    delta = factor_of_floor * NOISE_FLOOR_R12 / r1
+    A, _ = scaled_coupling_poisson(delta)
+    ratio = fill_ratio_of_c1(A, leaf)
+    assert abs(ratio / (factor_of_floor * NOISE_FLOOR_R12) - 1.0) < 1e-6
+    fo = _fac(A, (4, 4, 1), 4, 1e-6, True)
+    lev = fo.levels[0]
+    assert lev.sym.order[:2] == [0, 1] and lev.sym.fill[1] == [2]
+    k1 = lev.k[1]
+    if expect_zero:
+        assert k1 == 0 and lev.records[1].kind == "full"
+    else:
+        assert 0 < k1 < lev.m[1] and lev.records[1].kind == "lowrank"
+    # either way the factorization solves the system to eps-level accuracy
+    b = np.random.default_rng(0).uniform(-1, 1, A.n)
+    assert _relres(A, O.solve(fo, b), b) < 1e-5
