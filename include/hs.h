@@ -195,6 +195,30 @@ int hs_factor_systems(hs_factor_t F, int32_t* nsys, int64_t* row_off);
 int hs_solve(hs_factor_t F, int64_t nrhs, const double* B, int64_t ldb, double* X, int64_t ldx,
              void* hip_stream);
 
+/* Allocation-free variant of hs_solve, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Same arguments, result and stream ordering as
+ * hs_solve (X = A_fac^{-1} B, Alg. 2, the same kernels in the same order, so
+ * the same numbers bit for bit), but the level vectors and partial sums of the
+ * sweeps live in a fixed device array of the library instead of buffers it
+ * allocates: 64 MiB (HS_NOALLOC_SCRATCH_BYTES) on every GPU the library runs
+ * on, held from when the library's code is loaded on that GPU until the
+ * process ends.  The call allocates and frees no device memory, launches its
+ * kernels one by one on hip_stream (no graph of its own, no events) and does
+ * not synchronise.  The first call with a device current looks up that
+ * device's array (hipGetSymbolAddress); F must live on the current device.
+ * Columns are processed in passes of as many as fit: one column needs
+ * 8 (3 n_l summed over the levels + the largest backward-partial buffer + 1)
+ * bytes, about 24 bytes per unknown for a 3D Poisson factorization.
+ * Errors: HS_ERR_ARG as hs_solve; HS_ERR_NOMEM when one column does not fit
+ * in the array (nothing is launched; hs_solve has no such limit).  Every call
+ * on one GPU shares that GPU's array and leaves its contents behind (each
+ * call writes everything it reads): calls that overlap in time on one GPU,
+ * from other streams or threads, race and must be serialised by the caller. */
+#define HS_NOALLOC_SCRATCH_BYTES (64u << 20)
+int hs_solve_noalloc(hs_factor_t F, int64_t nrhs, const double* B, int64_t ldb, double* X, int64_t ldx,
+                     void* hip_stream);
+
 /* Preconditioned conjugate gradients (symmetric positive definite A), one
  * recurrence per system and right-hand side (lane l = s + nsys * c), x0 = 0,
  * float64, preconditioner = the factorization (Sec. 5.1).  Iterates until
@@ -434,6 +458,9 @@ int hs_set_allocator(void* (*alloc_fn)(size_t, void*), void (*free_fn)(void*, vo
  *                                  always Householder QR)
  *   dense_panel      128, 16..128  panel width of the dense LU of a complete
  *                                  level (Alg. 1, final dense factorization)
+ *   noalloc_scratch_max  HS_NOALLOC_SCRATCH_BYTES, 0..that   bytes of its
+ *                                  device array hs_solve_noalloc may use
+ *                                  (read at every call)
  * Errors: HS_ERR_ARG (unknown name, value outside its range, or a fraction
  * for an integer parameter; nothing changed). */
 int hs_config_set(const char* name, double value);

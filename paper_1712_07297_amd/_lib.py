@@ -128,6 +128,7 @@ _SIGS = {
     "hs_factor_batch": (ctypes.c_int, [_I32, ctypes.POINTER(hs_csr), ctypes.POINTER(hs_geometry), ctypes.POINTER(hs_opts), _P, ctypes.POINTER(_P)]),
     "hs_factor_systems": (ctypes.c_int, [_P, _PI32, ctypes.POINTER(_I64)]),
     "hs_solve": (ctypes.c_int, [_P, _I64, _P, _I64, _P, _I64, _P]),
+    "hs_solve_noalloc": (ctypes.c_int, [_P, _I64, _P, _I64, _P, _I64, _P]),
     "hs_pcg": (ctypes.c_int, [_P, _I64, _P, _I64, _P, _I64, _D, _I32, _PI32, _PD, _P]),
     "hs_gmres": (ctypes.c_int, [_P, _I64, _P, _I64, _P, _I64, _D, _I32, _I32, _PI32, _PD, _P]),
     "hs_factor_info": (ctypes.c_int, [_P, ctypes.POINTER(hs_info)]),
@@ -304,6 +305,17 @@ class Factor:
             X = torch.empty_like(B2)
         _check(lib().hs_solve(self._h, nrhs, _ptr(B2), ldb, _ptr(X), X.stride(0), _stream(stream)), "hs_solve")
         return X.reshape(-1) if sq else X
+
+    def solve_noalloc(self, B, X, stream=None):
+        """hs_solve_noalloc: X = A_fac^{-1} B with no device allocation by the
+        library (X is the caller's output tensor, shaped like B)."""
+        B2, nrhs, ldb, sq = _rhs(B)
+        X2 = X.reshape(B2.shape) if sq else X
+        if X2.shape != B2.shape or X2.dtype != B2.dtype or not X2.is_cuda or X2.stride(1) != 1:
+            raise TypeError("X must be a CUDA float64 tensor shaped like B with unit column stride")
+        _check(lib().hs_solve_noalloc(self._h, nrhs, _ptr(B2), ldb, _ptr(X2), X2.stride(0), _stream(stream)),
+               "hs_solve_noalloc")
+        return X
 
     def pcg(self, B, tol: float = 1e-10, maxit: int = 500, X=None, stream=None):
         import torch

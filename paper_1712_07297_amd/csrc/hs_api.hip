@@ -239,7 +239,7 @@ static ProfFamily g_prof[PF_COUNT] = {{"gram"}, {"pivot"}, {"fill"}, {"nbr"},   
                                       {"host_solve_plan"}};
 static bool g_prof_on = false;
 static uint32_t g_prof_mask = 0xffffffffu;  // families timed while on (hs_profile_select)
-static bool prof_timed(int fam) { return g_prof_on && ((g_prof_mask >> fam) & 1u); }
+static bool prof_timed(int fam) { return fam >= 0 && g_prof_on && ((g_prof_mask >> fam) & 1u); }
 struct ProfPending {
     int fam;
     hipEvent_t a, b;
@@ -393,8 +393,9 @@ struct hs_factor_s {
     // solve buffers
     int solve_nrhs = 0;
     hs::DevBuf vecs;                      // y, z, out of every level
-    std::vector<int64_t> vec_off;         // per level base (units of doubles / nrhs)
+    std::vector<int64_t> vec_off;         // per level base (units of doubles / nrhs), set by hs_factor
     int64_t vec_total = 0;
+    int64_t part_max = 0;                 // largest backward-partial buffer of a colour (units of nrhs)
     hs::DevBuf part;
     // Krylov buffers
     hs::DevBuf kry;
@@ -1305,6 +1306,14 @@ static int factor_impl(hs_factor_s* F, int nsys, const hs_csr* A, const hs_geome
             apply_flops += 4.0 * m * m + 4.0 * f * nt;
         }
     }
+    // solve vector layout: y, z and out of every level, level after level
+    F->vec_off.assign(nlev + 1, 0);
+    F->part_max = 0;
+    for (int l = 0; l < nlev; ++l) {
+        F->vec_off[l + 1] = F->vec_off[l] + 3 * F->levels[l].nseg;
+        F->part_max = std::max(F->part_max, F->levels[l].part_max);
+    }
+    F->vec_total = F->vec_off[nlev];
     HIP_TRY(hipStreamSynchronize(st));
     if (g_prof_on) prof_flush();
     F->info.factor_flops = flops;
@@ -1321,14 +1330,8 @@ static int factor_impl(hs_factor_s* F, int nsys, const hs_csr* A, const hs_geome
 static int ensure_solve_buffers(hs_factor_s* F, int nrhs) {
     if (F->solve_nrhs >= nrhs && F->vecs.p) return HS_OK;
     F->drop_sweeps();  // captured sweeps refer to the buffers reallocated below
-    const int nlev = (int)F->levels.size();
-    F->vec_off.assign(nlev + 1, 0);
-    for (int l = 0; l < nlev; ++l) F->vec_off[l + 1] = F->vec_off[l] + 3 * F->levels[l].nseg;
-    F->vec_total = F->vec_off[nlev];
-    int64_t pm = 0;
-    for (auto& LD : F->levels) pm = std::max(pm, LD.part_max);
     if (!F->vecs.alloc((F->vec_total * nrhs + 1) * sizeof(double))) return fail(HS_ERR_NOMEM, "solve vectors");
-    if (!F->part.alloc((pm * nrhs + 1) * sizeof(double))) return fail(HS_ERR_NOMEM, "solve partials");
+    if (!F->part.alloc((F->part_max * nrhs + 1) * sizeof(double))) return fail(HS_ERR_NOMEM, "solve partials");
     F->solve_nrhs = nrhs;
     return HS_OK;
 }
@@ -1351,21 +1354,22 @@ static int solve_impl(hs_factor_s* F, int nrhs, const double* B, int64_t ldb, do
 
 // Alg. 2: forward sweep colour by colour up the levels, backward sweep down
 // (level vectors only).  A colour's float32 and float64 lists are independent
-// launches.
-static void solve_sweeps(hs_factor_s* F, int nrhs, hipStream_t st) {
+// launches.  base: the level vectors (vec_total x nrhs doubles), part: the
+// backward partials (part_max x nrhs); prof: bracket the launches for the
+// per-family profiler.
+static void solve_sweeps(hs_factor_s* F, int nrhs, hipStream_t st, double* base, double* part, bool prof = true) {
     const int nlev = (int)F->levels.size();
-    double* base = F->vecs.as<double>();
     auto Y = [&](int l) { return base + F->vec_off[l] * nrhs; };
     auto Z = [&](int l) { return base + (F->vec_off[l] + F->levels[l].nseg) * nrhs; };
     auto O = [&](int l) { return base + (F->vec_off[l] + 2 * F->levels[l].nseg) * nrhs; };
-    double* part = F->part.as<double>();
+    const int fam = prof ? PF_APPLY : -1;
     for (int l = 0; l < nlev; ++l) {
         LevelData& LD = F->levels[l];
         for (auto& CH : LD.colours)
             for (int t = 0; t < 2; ++t) {
                 const ColourDev& C = CH.sol[t];
                 if (C.n == 0) continue;
-                ProfScope ps(PF_APPLY, st);
+                ProfScope ps(fam, st);
                 launch_apply_fwd(LD.sdev, C, Y(l), Z(l), nrhs, st);
             }
         if (l + 1 < nlev)
@@ -1380,7 +1384,7 @@ static void solve_sweeps(hs_factor_s* F, int nrhs, hipStream_t st) {
             for (int t = 0; t < 2; ++t) {
                 const ColourDev& C = CH.sol[t];
                 if (C.n == 0) continue;
-                ProfScope ps(PF_APPLY, st);
+                ProfScope ps(fam, st);
                 launch_apply_bwd_acc(LD.sdev, C, Z(l), O(l), part, CH.part_off[t], nrhs, st);
                 launch_apply_bwd_t(LD.sdev, C, Z(l), O(l), part, CH.part_off[t], nrhs, st);
             }
@@ -1401,7 +1405,7 @@ static int solve_chunk(hs_factor_s* F, int nrhs, const double* B, int64_t ldb, d
     launch_scatter_rhs(F->n, F->cluster_of.as<int>(), F->local_of.as<int>(), L0.sdev.seg, L0.dev.m, B, ldb, Y0, nrhs,
                        st);
     if (prof_timed(PF_APPLY) || nlev == 0) {
-        solve_sweeps(F, nrhs, st);
+        solve_sweeps(F, nrhs, st, F->vecs.as<double>(), F->part.as<double>());
     } else {
         hipGraphExec_t ex = nullptr;
         for (auto& g : F->sweeps)
@@ -1414,7 +1418,7 @@ static int solve_chunk(hs_factor_s* F, int nrhs, const double* B, int64_t ldb, d
                 std::lock_guard<std::mutex> lk(g_capture_mu);
                 ok = hipStreamBeginCapture(F->cap_stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
                 if (ok) {
-                    solve_sweeps(F, nrhs, F->cap_stream);
+                    solve_sweeps(F, nrhs, F->cap_stream, F->vecs.as<double>(), F->part.as<double>());
                     ok = hipStreamEndCapture(F->cap_stream, &g) == hipSuccess && g;
                 }
             }
@@ -1434,11 +1438,79 @@ static int solve_chunk(hs_factor_s* F, int nrhs, const double* B, int64_t ldb, d
             HIP_TRY(hipGraphLaunch(ex, st));
             F->sweep_stream = st;
         } else {
-            solve_sweeps(F, nrhs, st);
+            solve_sweeps(F, nrhs, st, F->vecs.as<double>(), F->part.as<double>());
         }
     }
     launch_gather_sol(F->n, F->cluster_of.as<int>(), F->local_of.as<int>(), L0.sdev.seg, L0.dev.m, O0, X, ldx, nrhs,
                       st);
+    HIP_TRY(hipGetLastError());
+    return HS_OK;
+}
+
+// ------------------------------------------------- allocation-free solve
+// hs_solve_noalloc keeps the level vectors and backward partials of the
+// sweeps in this file-scope device array instead of buffers of its own.  Each
+// GPU holds its own copy, from when the library's code is loaded on it until
+// the process ends.  In host code the name `scratch` stands for a host-side
+// shadow, not for device memory: the array's device address is taken once per
+// device with hipGetSymbolAddress (scratch_ptr) and only that address is
+// handed to kernels.
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(64) << 20;
+static __device__ __align__(256) double scratch[NOALLOC_SCRATCH_BYTES / sizeof(double)];
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static double* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+static size_t g_noalloc_limit = NOALLOC_SCRATCH_BYTES;  // test hook: bytes of the array a call may use
+
+// Device address of the current device's array (looked up on the first call
+// with that device current).
+static int scratch_ptr(double** out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return fail(HS_ERR_ARG, "device index beyond the supported 64");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(HS_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = static_cast<double*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return HS_OK;
+}
+
+// The sweeps of Alg. 2 on buffers cut from the array at base (launch by
+// launch, no graph, no profiler events): columns in passes of as many as the
+// array and the apply kernels' LDS tiles allow.
+static int solve_noalloc_impl(hs_factor_s* F, int nrhs, const double* B, int64_t ldb, double* X, int64_t ldx,
+                              hipStream_t st, double* base) {
+    const int64_t per_col = F->vec_total + F->part_max + 1;  // doubles per right-hand side
+    size_t limit_bytes;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        limit_bytes = g_noalloc_limit;
+    }
+    const int64_t cap = (int64_t)(limit_bytes / sizeof(double));
+    if (per_col > cap)
+        return fail(HS_ERR_NOMEM, "the allocation-free solve needs " + std::to_string(per_col * sizeof(double)) +
+                                      " bytes of scratch per right-hand side; its device array has " +
+                                      std::to_string(limit_bytes) + " (use hs_solve)");
+    int maxm = 1;
+    for (auto& LD : F->levels) maxm = std::max(maxm, LD.max_m);
+    const int per = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)nrhs, 8192 / maxm, cap / per_col}));
+    LevelData& L0 = F->levels[0];
+    for (int r0 = 0; r0 < nrhs; r0 += per) {
+        const int nr = std::min(per, nrhs - r0);
+        double* Y0 = base;
+        double* O0 = Y0 + 2 * L0.nseg * nr;
+        double* part = base + F->vec_total * nr;
+        launch_scatter_rhs(F->n, F->cluster_of.as<int>(), F->local_of.as<int>(), L0.sdev.seg, L0.dev.m,
+                           B + r0 * ldb, ldb, Y0, nr, st);
+        solve_sweeps(F, nr, st, base, part, false);
+        launch_gather_sol(F->n, F->cluster_of.as<int>(), F->local_of.as<int>(), L0.sdev.seg, L0.dev.m, O0,
+                          X + r0 * ldx, ldx, nr, st);
+    }
     HIP_TRY(hipGetLastError());
     return HS_OK;
 }
@@ -1813,6 +1885,17 @@ int hs_solve(hs_factor_t F, int64_t nrhs, const double* B, int64_t ldb, double* 
     return solve_impl(F, (int)nrhs, B, ldb, X, ldx, (hipStream_t)hip_stream);
 }
 
+int hs_solve_noalloc(hs_factor_t F, int64_t nrhs, const double* B, int64_t ldb, double* X, int64_t ldx,
+                     void* hip_stream) {
+    g_err.clear();
+    if (!F || !B || !X || nrhs < 1 || nrhs > 64 || ldb < F->n || ldx < F->n) return fail(HS_ERR_ARG, "bad argument");
+    if (B == X && ldb != ldx) return fail(HS_ERR_ARG, "aliased B and X need equal leading dimensions");
+    double* base = nullptr;
+    const int rc = scratch_ptr(&base);
+    if (rc) return rc;
+    return solve_noalloc_impl(F, (int)nrhs, B, ldb, X, ldx, (hipStream_t)hip_stream, base);
+}
+
 int hs_pcg(hs_factor_t F, int64_t nrhs, const double* B, int64_t ldb, double* X, int64_t ldx, double tol, int32_t maxit,
            int32_t* iters_out, double* relres_out, void* hip_stream) {
     g_err.clear();
@@ -2064,6 +2147,13 @@ const char* hs_version(void) { return kVersion; }
 
 int hs_config_set(const char* name, double value) {
     if (!name) return fail(HS_ERR_ARG, "null name");
+    if (std::strcmp(name, "noalloc_scratch_max") == 0) {
+        if (!(value >= 0 && value <= (double)NOALLOC_SCRATCH_BYTES) || value != std::floor(value))
+            return fail(HS_ERR_ARG, "noalloc_scratch_max outside [0, " + std::to_string(NOALLOC_SCRATCH_BYTES) + "]");
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        g_noalloc_limit = (size_t)value;
+        return HS_OK;
+    }
     std::lock_guard<std::mutex> lk(g_config_mu);
     for (const ConfigEntry& e : config_table(g_config)) {
         if (std::strcmp(e.name, name) != 0) continue;
@@ -2083,6 +2173,11 @@ int hs_config_set(const char* name, double value) {
 
 int hs_config_get(const char* name, double* value) {
     if (!name || !value) return fail(HS_ERR_ARG, "null argument");
+    if (std::strcmp(name, "noalloc_scratch_max") == 0) {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        *value = (double)g_noalloc_limit;
+        return HS_OK;
+    }
     std::lock_guard<std::mutex> lk(g_config_mu);
     for (const ConfigEntry& e : config_table(g_config))
         if (std::strcmp(e.name, name) == 0) {
@@ -2093,8 +2188,12 @@ int hs_config_get(const char* name, double* value) {
 }
 
 int hs_config_reset(void) {
-    std::lock_guard<std::mutex> lk(g_config_mu);
-    g_config = Config();
+    {
+        std::lock_guard<std::mutex> lk(g_config_mu);
+        g_config = Config();
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    g_noalloc_limit = NOALLOC_SCRATCH_BYTES;
     return HS_OK;
 }
 
