@@ -1,38 +1,35 @@
 """Benchmark: unknowns/s to factor and solve to relative residual 1e-10, the
-mixed-precision form against the float64 form.
+mixed-precision form against the float64 form, on one MI355X.
 
-Workload (default): 3D 7-point Poisson on a 64^3 grid (N = 262,144), FP64 CSR,
-leaves of 64 unknowns, eps = 1e-4, the factorization used as CG
-preconditioner for 8 right-hand sides uniform on [-1, 1), stopping at
-relative residual 1e-10 for every column.  One step = hs_factor + hs_pcg
-(symbolic analysis, numeric factorization and the preconditioned solve of all
-8 right-hand sides) + hs_free, with the CSR and the right-hand sides already
-resident in HBM.  value = N * steps / seconds of the mixed form (float32
-blocks and records, Schur products on the bfloat16 units, float64 coarse
-levels and Krylov vectors); the float64 form is timed the same way and
-reported beside it.
-
-Also reported: the Schur-complement kernel against the HBM roofline (its
-algorithmic bytes per launch over its average launch time, HIP events on the
-library's stream inside the timed region) and the CPU oracle timed on a
-bounded sample of the same workload family on the host cores.
-
-Batched workload (--workload batch): 256 independent 2D upwind
+Workload (default, --workload batch): 256 independent 2D upwind
 convection-diffusion systems (sides uniform in [64, 512], Peclet uniform in
-[1, 100], random direction; about 2.7e7 unknowns), one right-hand side each,
-GMRES(30) to 1e-10 per system.  Systems are factored together with
-hs_factor_batch in groups whose measured device footprint fits the memory
-budget; one step = every group's hs_factor_batch + hs_gmres + hs_free.
+[1, 100], random direction; 26.6 M unknowns in total), leaves of 64, eps 1e-3,
+one right-hand side each, right-preconditioned GMRES(30) to 1e-10 per system.
+Systems are factored together with hs_factor_batch in groups whose measured
+device footprint fits the memory budget; one step = every group's
+hs_factor_batch + hs_gmres + hs_free, with the CSR matrices and right-hand
+sides already resident in HBM.  value = unknowns * steps / seconds of the
+mixed form (float32 blocks and records on the fine levels, Schur products on
+the bfloat16 units, float64 coarse levels and Krylov vectors); the float64
+form is timed the same way (min(steps, 3) steps) and reported beside it.
 
-Serving workload (--workload serve): a Poisson stream of solve requests
-(60 % 3D lognormal diffusion with sides 32..96, 40 % 2D convection-diffusion
-with sides 256..1024, 1-16 right-hand sides, 30 % operator reuse) served by
-the library's request loop at rho times its capacity measured on a burst;
-value = unknowns x right-hand sides solved per second, with p50 / p99
-latency.
+Also reported:
+  * roofline: the pivot-block kernel on the float32 levels (k_pivot<true,
+    float>, the kernel with the most GPU time in the mixed step), its
+    algorithmic flops per launch over its average launch time (HIP events
+    recorded on the library's stream around its launches inside the timed
+    steps) against the FP64 peak (its arithmetic runs in float64);
+  * cpu_baseline: the CPU oracle (plain numpy, FP64) on the 40 smallest of the
+    same 256 systems, factor + GMRES(30) to 1e-10 each.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--side 64] [--forms both|mixed|fp64]
-                       [--workload poisson64|batch|serve] [--batch-count 256] [--budget-gb 200]
+Other workloads: --workload poisson64 (3D Poisson 64^3, eps 1e-4, PCG for 8
+RHS), --workload vcd128 (3D lognormal diffusion 128^3, eps 1e-3, PCG),
+--workload serve (a Poisson stream of solve requests through the library's
+request loop, p50 / p99 latency).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--forms both|mixed|fp64]
+                       [--workload batch|poisson64|vcd128|serve] [--batch-count 256] [--budget-gb 200]
+                       [--fp64-steps S] [--profile] [--no-cpu-baseline]
                        [--requests 100] [--rho 0.8] [--cap-gb 200] [--workers 2]
 """
 
@@ -48,54 +45,93 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+METRIC = "unknowns/s factor+solve to 1e-10 residual, mixed vs FP64; p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_schur_hbm_traffic_poisson64.md")
+FP64_PEAK_TFLOPS = 78.6  # 256 CUs x 4 SIMDs x 16 lanes x 2 (fma) x 2.4 GHz; FP64 matrix cores: the same
+PROFILES = os.path.join(ROOT, "profiles")
+FAMILIES = ["gram", "pivot", "pivot_f32", "fill", "nbr", "schur", "schur_f32", "merge", "apply", "spmv", "dense",
+            "host_symbolic", "host_plan", "host_upload", "host_alloc", "host_sync", "host_solve_plan"]
 
 
-def schur_source_digest() -> str:
-    """Digest of the Schur-update kernel's source (its section of k_factor.hip
-    and the MFMA tile core it is built on)."""
-    csrc = os.path.join(ROOT, "paper_1712_07297_amd", "csrc")
+def _section(name, a, b):
+    with open(os.path.join(ROOT, "paper_1712_07297_amd", "csrc", name)) as fh:
+        text = fh.read()
+    i = text.index(a)
+    return text[i : text.index(b, i)]
 
-    def section(name, a, b):
-        with open(os.path.join(csrc, name)) as fh:
-            text = fh.read()
-        i = text.index(a)
-        return text[i : text.index(b, i)]
 
+def kernel_source_digest(kernel: str) -> str:
+    """Digest of a kernel's source: its section of k_factor.hip and the
+    device_common.h routines it is built on."""
     h = hashlib.sha256()
-    h.update(section("k_factor.hip", "// " + "=" * 60 + " Schur update", "// " + "=" * 64 + " assembly").encode())
-    h.update(section("device_common.h", "// " + "-" * 60 + " MFMA tile core", "// " + "-" * 60 + " cooperative GEMM").encode())
+    if kernel == "schur":
+        h.update(_section("k_factor.hip", "// " + "=" * 60 + " Schur update", "// " + "=" * 64 + " assembly").encode())
+        h.update(_section("device_common.h", "// " + "-" * 60 + " MFMA tile core",
+                          "// " + "-" * 60 + " cooperative GEMM").encode())
+    else:  # pivot: the kernel and every cooperative routine of the header
+        h.update(_section("k_factor.hip", "// " + "=" * 62 + " pivot kernel",
+                          "// " + "=" * 60 + " fill update").encode())
+        with open(os.path.join(ROOT, "paper_1712_07297_amd", "csrc", "device_common.h")) as fh:
+            h.update(fh.read().encode())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(element: str):
-    """HBM bytes per k_schur<element> launch from the committed FETCH_SIZE /
-    WRITE_SIZE passes on this workload, or None when the kernel changed since."""
+def measured_traffic(profile: str, kernel: str, key: str):
+    """HBM bytes per launch from a committed FETCH_SIZE / WRITE_SIZE summary
+    (profiles/<profile>), or None when the kernel's source changed since."""
     try:
-        with open(TRAFFIC_PROFILE) as fh:
+        with open(os.path.join(PROFILES, profile)) as fh:
             text = fh.read()
     except OSError:
         return None
-    vals = dict(line.split(":", 1) for line in text.splitlines() if line.startswith(("traffic_bytes_per_launch_", "kernel_source_digest:")))
-    if vals.get("kernel_source_digest", "").strip() != schur_source_digest():
+    vals = dict(line.split(":", 1) for line in text.splitlines() if ":" in line and not line.startswith(("#", "|", " ")))
+    if vals.get("kernel_source_digest", "").strip() != kernel_source_digest(kernel):
         return None
-    v = vals.get(f"traffic_bytes_per_launch_{element}")
+    v = vals.get(key)
     return float(v) if v is not None else None
 
 
-def cpu_baseline(side: int = 24):
-    """The oracle (plain numpy FP64) on a side^3 Poisson sample of the same
-    workload family: factor + PCG for 8 RHS to 1e-10."""
-    import oracle as O
-    from workloads import config2
-
+def _blas_threads():
     try:
         from threadpoolctl import threadpool_info
 
-        cores = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+        return max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
     except Exception:  # pragma: no cover
-        cores = os.cpu_count() or 1
+        return os.cpu_count() or 1
+
+
+def cpu_baseline_batch(probs, count: int = 40):
+    """The oracle (plain numpy FP64) on the `count` smallest systems of the
+    benchmarked batch: factor + GMRES(30) to 1e-10 each."""
+    import oracle as O
+
+    idx = sorted(range(len(probs)), key=lambda i: (probs[i].A.n, i))[:count]
+    t0 = time.perf_counter()
+    nsum = 0
+    for i in idx:
+        p = probs[i]
+        fo = O.factor(p.A.row_ptr, p.A.col_idx, p.A.val, p.dims, p.leaf, p.eps, False)
+        _, it, rel = O.gmres(p.A.row_ptr, p.A.col_idx, p.A.val, p.B[:, 0], lambda R: O.solve(fo, R), p.tol, 300, 30)
+        assert rel <= p.tol
+        nsum += p.A.n
+    dt = time.perf_counter() - t0
+    sides = sorted(probs[i].dims[0] for i in idx)
+    return {
+        "value": nsum / dt,
+        "unit": "unknowns/s",
+        "cores": int(_blas_threads()),
+        "kind": "oracle",
+        "sample": f"the {count} smallest of the same {len(probs)} systems (sides {sides[0]}..{sides[-1]}, {nsum} "
+                  f"unknowns), leaf 64, eps 1e-3, factor + GMRES(30) to 1e-10 each: {dt:.1f} s",
+    }
+
+
+def cpu_baseline_poisson(side: int = 24):
+    """The oracle on a side^3 Poisson sample of the 64^3 workload family:
+    factor + PCG for 8 RHS to 1e-10."""
+    import oracle as O
+    from workloads import config2
+
     p = config2(side=side, nrhs=8)
     t0 = time.perf_counter()
     fo = O.factor(p.A.row_ptr, p.A.col_idx, p.A.val, p.dims, p.leaf, p.eps, True)
@@ -105,97 +141,36 @@ def cpu_baseline(side: int = 24):
     return {
         "value": p.A.n / dt,
         "unit": "unknowns/s",
-        "cores": int(cores),
+        "cores": int(_blas_threads()),
         "kind": "oracle",
-        "sample": f"3D Poisson {side}^3 (N={p.A.n}), leaf 64, eps 1e-4, 8 RHS, PCG to 1e-10: one factor+solve in {dt:.1f} s",
+        "sample": f"3D Poisson {side}^3 (N={p.A.n}), leaf 64, eps 1e-4, 8 RHS, PCG to 1e-10: one factor+solve "
+                  f"in {dt:.1f} s (a smaller input of the same family)",
     }
 
 
-def run_form(P, torch, p, rp, ci, va, B, X, precision, steps, warmup, n, profile=False):
-    """Warm-up, then `steps` timed steps of one precision form; returns its
-    record (time, convergence, Schur roofline)."""
-
-    split = {"factor": 0.0, "solve": 0.0}
-
-    def step():
-        t0 = time.perf_counter()
-        F = P.Factor(rp, ci, va, p.dims, p.eps, p.leaf, symmetric=1, precision=precision)
-        t1 = time.perf_counter()
-        _, it, rel, ok = F.pcg(B, p.tol, 200, X=X)
-        torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        split["factor"] += t1 - t0
-        split["solve"] += t2 - t1
-        info = F.info()
-        F.free()
-        return it, rel, ok, info
-
-    name = "mixed" if precision == P.HS_MIXED else "fp64"
-    for w in range(warmup):
-        step()
-        print(f"{name}: warmup step {w + 1}/{warmup} done", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    P.profile_reset()
-    # the dominant kernel is timed by events around its launches; the rest
-    # runs as in production unless every family is profiled
-    P.profile_select("" if profile else ("schur_f32" if precision == P.HS_MIXED else "schur"))
-    P.profile_enable(True)
-    torch.cuda.synchronize()
-    split["factor"] = split["solve"] = 0.0
-    t0 = time.perf_counter()
-    its, rels, oks = [], [], []
-    info = None
-    for k in range(steps):
-        it, rel, ok, info = step()
-        print(f"{name}: timed step {k + 1}/{steps} done", file=sys.stderr, flush=True)
-        its.append(it)
-        rels.append(float(rel.max()))
-        oks.append(ok)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    P.profile_enable(False)
-    if profile:
-        fams = ["gram", "pivot", "fill", "nbr", "schur", "schur_f32", "merge", "apply", "spmv", "dense",
-                "host_symbolic", "host_plan", "host_upload", "host_alloc", "host_sync", "host_solve_plan"]
-        prof = {f: round(P.profile_read(f)["seconds"] / steps, 4) for f in fams}
-        print(f"{name}: seconds per step by family {json.dumps(prof)}", file=sys.stderr, flush=True)
-    # dominant kernel: the Schur updates of the levels stored in the form's
-    # bulk precision (float32 levels in the mixed form, all levels in FP64)
-    schur = P.profile_read("schur_f32" if precision == P.HS_MIXED else "schur")
-    # independent check of the final residual (device SpMV by torch, FP64)
-    A_t = torch.sparse_csr_tensor(rp, ci.to(torch.int64), va, size=(n, n))
-    R = B.T - (A_t @ X.T)
-    relres = (torch.linalg.norm(R, dim=0) / torch.linalg.norm(B.T, dim=0)).max().item()
-    rec = {
-        "value": n * steps / dt,
-        "ms_per_step": dt / steps * 1e3,
-        "factor_ms": split["factor"] / steps * 1e3,
-        "solve_ms": split["solve"] / steps * 1e3,
-        "pcg_iterations": its,
-        "relres_max": max(rels),
-        "relres_check": relres,
-        "converged": all(oks) and relres <= p.tol * 1.01,
-        "levels": info.nlevels,
-        "colour_batches": info.ncolors_total,
-        "factor_gflop": info.factor_flops / 1e9,
-        "factor_bytes_records": info.factor_bytes,
-    }
-    if schur["launches"] > 0 and schur["seconds"] > 0:
-        achieved = schur["bytes"] / schur["seconds"] / 1e9
-        rec["roofline"] = {
-            "kernel": f"k_schur<{'float' if precision == P.HS_MIXED else 'double'}> (Schur-complement update, Eq. elim)",
-            "bound": "hbm",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
-            "launches": schur["launches"],
-            "avg_launch_ms": schur["seconds"] / schur["launches"] * 1e3,
-            "algorithmic_bytes_per_launch": schur["bytes"] / schur["launches"],
-            "achieved_tflops": schur["flops"] / schur["seconds"] / 1e12,
-        }
-    return rec
+def roofline_from(P, family, kernel_label, bound, traffic=None):
+    """Roofline record of one kernel family timed by the library's events."""
+    r = P.profile_read(family)
+    if r["launches"] == 0 or r["seconds"] <= 0:
+        return None
+    out = {"kernel": kernel_label, "bound": bound}
+    if bound == "hbm":
+        achieved = r["bytes"] / r["seconds"] / 1e9
+        out.update({"achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS})
+    else:
+        achieved = r["flops"] / r["seconds"] / 1e12
+        out.update({"achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": achieved / FP64_PEAK_TFLOPS})
+    out.update({
+        "traffic": traffic,
+        "launches": r["launches"],
+        "avg_launch_ms": r["seconds"] / r["launches"] * 1e3,
+        "algorithmic_flops_per_launch": r["flops"] / r["launches"],
+        "algorithmic_bytes_per_launch": r["bytes"] / r["launches"],
+        "achieved_tflops": r["flops"] / r["seconds"] / 1e12,
+        "achieved_gbs": r["bytes"] / r["seconds"] / 1e9,
+    })
+    return out
 
 
 def run_batch(args):
@@ -206,6 +181,7 @@ def run_batch(args):
     from workloads import config4_batch
 
     dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
     probs = config4_batch(count=args.batch_count)
     ns = [p.A.n for p in probs]
     ntot = int(sum(ns))
@@ -213,23 +189,34 @@ def run_batch(args):
                 torch.tensor(p.A.val, device=dev), p.dims) for p in probs]
     rhs = [torch.tensor(np.ascontiguousarray(p.B[:, 0]), device=dev) for p in probs]
     torch.cuda.synchronize()
+    print(f"batch: {len(probs)} systems, {ntot} unknowns generated and uploaded in {time.perf_counter() - t0:.1f} s",
+          file=sys.stderr, flush=True)
     budget = args.budget_gb * 1e9
+    if args.copy_probe:
+        src = torch.ones(64 * 1024 * 1024 // 8, dtype=torch.float64, device=dev)  # 64 MiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
 
     def run_group(idx, precision):
         F = P.Factor.batch([sys_dev[i] for i in idx], 1e-3, 64, symmetric=0, precision=precision)
         B = torch.cat([rhs[i] for i in idx]).reshape(1, -1)
-        _, it, rel, ok = F.gmres(B, 1e-10, 300, 30)
+        X, it, rel, ok = F.gmres(B, 1e-10, 300, 30)
         info = F.info()
         F.free()
-        return it, float(np.max(rel)), ok, info
+        return X, it, float(np.max(rel)), ok, info
 
     out_forms = {}
     forms = {"both": [P.HS_MIXED, P.HS_FP64], "mixed": [P.HS_MIXED], "fp64": [P.HS_FP64]}[args.forms]
     for prec in forms:
         name = "mixed" if prec == P.HS_MIXED else "fp64"
-        # footprint per unknown from a calibration group (also the warm-up)
+        head = prec == forms[0]
+        steps = args.steps if head else max(1, min(args.steps, args.fp64_steps))
+        warmup = args.warmup if head else min(args.warmup, 1)
+        # footprint per unknown from a calibration group of the first systems
         cal = list(range(min(8, len(probs))))
-        _, _, _, info = run_group(cal, prec)
+        info = run_group(cal, prec)[4]
         per_unknown = info.peak_device_bytes / sum(ns[i] for i in cal)
         cap = max(1, int(budget / (1.25 * per_unknown)))
         groups, cur, acc = [], [], 0
@@ -241,48 +228,79 @@ def run_batch(args):
             acc += ns[i]
         groups.append(cur)
         print(f"batch {name}: {len(groups)} group(s), {per_unknown:.0f} B/unknown", file=sys.stderr, flush=True)
-        times, its, rels, oks, peaks = [], [], [], [], []
-        if args.profile:
-            P.profile_reset()
-            P.profile_enable(True)
-        for st in range(args.steps):
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
+
+        def step(record):
             for g in groups:
-                it, rel, ok, info = run_group(g, prec)
-                its.append(it)
-                rels.append(rel)
-                oks.append(ok)
-                peaks.append(info.peak_device_bytes)
-            torch.cuda.synchronize()
-            times.append(time.perf_counter() - t0)
-            print(f"batch {name}: step {st + 1}/{args.steps} {times[-1]:.2f} s", file=sys.stderr, flush=True)
+                X, it, rel, ok, info = run_group(g, prec)
+                if record is not None:
+                    record["its"].append(it)
+                    record["rels"].append(rel)
+                    record["oks"].append(ok)
+                    record["peaks"].append(info.peak_device_bytes)
+                    record["flops"] += info.factor_flops
+                    record["X"].append((g, X))
+
+        for w in range(warmup):
+            step(None)
+            print(f"batch {name}: warmup step {w + 1}/{warmup} done", file=sys.stderr, flush=True)
+        pivot_family = "pivot_f32" if prec == P.HS_MIXED else "pivot"
+        P.profile_reset()
+        P.profile_select("" if args.profile else pivot_family)
+        P.profile_enable(True)
+        rec = {"its": [], "rels": [], "oks": [], "peaks": [], "flops": 0.0, "X": []}
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for st in range(steps):
+            rec["X"] = []
+            step(rec)
+            print(f"batch {name}: timed step {st + 1}/{steps} done", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        P.profile_enable(False)
         if args.profile:
-            P.profile_enable(False)
-            fams = ["gram", "pivot", "fill", "nbr", "schur", "schur_f32", "merge", "apply", "spmv", "dense",
-                    "host_symbolic", "host_plan", "host_upload", "host_alloc", "host_sync",
-                    "host_solve_plan"]
-            prof = {f: round(P.profile_read(f)["seconds"] / args.steps, 4) for f in fams}
+            prof = {f: round(P.profile_read(f)["seconds"] / steps, 4) for f in FAMILIES}
             print(f"batch {name}: seconds per step by family {json.dumps(prof)}", file=sys.stderr, flush=True)
-        dt = float(np.median(times))
+        label = ("k_pivot<true, float>" if prec == P.HS_MIXED else "k_pivot<true, double>") + \
+            " (pivot-block LU, rank, complement, F_ff; Eqs. lra, scaling, elim)"
+        traffic = measured_traffic("k_pivot_hbm_traffic_batch_convdiff256.md", "pivot",
+                                   f"traffic_bytes_per_launch_{'float' if prec == P.HS_MIXED else 'double'}")
+        roof = roofline_from(P, pivot_family, label, "alu", traffic)
+        P.profile_select("")
+        P.profile_reset()
+        # independent check of every system's final residual (device SpMV by torch, FP64)
+        relcheck = 0.0
+        for g, X in rec["X"]:
+            x = X.reshape(-1)
+            off = 0
+            for i in g:
+                rp, ci, va, _ = sys_dev[i]
+                A_t = torch.sparse_csr_tensor(rp, ci.to(torch.int64), va, size=(ns[i], ns[i]))
+                xi = x[off : off + ns[i]]
+                r = rhs[i] - A_t @ xi
+                relcheck = max(relcheck, (torch.linalg.norm(r) / torch.linalg.norm(rhs[i])).item())
+                off += ns[i]
         out_forms[name] = {
             "value": ntot / dt,
             "ms_per_step": dt * 1e3,
+            "steps": steps,
             "groups": len(groups),
-            "gmres_iterations_max": int(max(its)),
-            "relres_max": float(max(rels)),
-            "converged": bool(all(oks)) and max(rels) <= 1e-10,
-            "peak_device_gb": float(max(peaks)) / 1e9,
+            "gmres_iterations_max": int(max(rec["its"])),
+            "relres_max": float(max(rec["rels"])),
+            "relres_check": relcheck,
+            "converged": bool(all(rec["oks"])) and max(rec["rels"]) <= 1e-10 and relcheck <= 1.01e-10,
+            "peak_device_gb": float(max(rec["peaks"])) / 1e9,
+            "factor_gflop_per_step": rec["flops"] / steps / 1e9,
+            "roofline": roof,
         }
     head_name = "mixed" if "mixed" in out_forms else "fp64"
     head = out_forms[head_name]
     out = {
-        "metric": "unknowns/s factor+solve to 1e-10 residual (mixed vs FP64)",
+        "metric": METRIC,
         "value": head["value"],
         "unit": "unknowns/s",
         "n_gpus": 1,
         "steps": args.steps,
-        "warmup": 1,
+        "warmup": args.warmup,
         "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
@@ -290,15 +308,143 @@ def run_batch(args):
         "dtype": "f32 storage + bf16x3 MFMA Schur, f64 Krylov" if head_name == "mixed" else "f64",
         "data": "synthetic",
         "config": {
-            "workload": f"batch of {len(probs)} 2D upwind convection-diffusion systems (sides 64..512, N total {ntot}), "
-                        "leaf 64, eps 1e-3, hs_factor_batch + GMRES(30) to 1e-10 per system, 1 RHS each",
+            "workload": f"batch of {len(probs)} 2D upwind convection-diffusion systems (sides 64..512, Peclet 1..100, "
+                        f"N total {ntot}), leaf 64, eps 1e-3, hs_factor_batch + GMRES(30) to 1e-10 per system, "
+                        "1 RHS each",
             "form": head_name,
-            **{k: v for k, v in head.items() if k not in ("value", "ms_per_step")},
+            **{k: v for k, v in head.items() if k not in ("value", "ms_per_step", "roofline")},
         },
     }
+    if head.get("roofline"):
+        out["roofline"] = head["roofline"]
     if "fp64" in out_forms and head_name != "fp64":
         out["fp64"] = out_forms["fp64"]
         out["mixed_over_fp64"] = head["value"] / out_forms["fp64"]["value"]
+    if not args.no_cpu_baseline:
+        print("timing the CPU oracle sample", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline_batch(probs)
+    print(json.dumps(out))
+
+
+def run_single(args):
+    """One large system: 3D Poisson 64^3 (poisson64, PCG for 8 RHS) or 3D
+    lognormal diffusion 128^3 (vcd128, PCG for 1 RHS); mixed and float64."""
+    import torch
+
+    import paper_1712_07297_amd as P
+    from workloads import config2, config3
+
+    dev = torch.device("cuda:0")
+    if args.workload == "poisson64":
+        p = config2(side=args.side, nrhs=args.nrhs)
+        label = (f"3D 7-point Poisson {args.side}^3 (N={p.A.n}), leaf 64, eps 1e-4, PCG preconditioner, "
+                 f"{args.nrhs} RHS to relative residual 1e-10")
+    else:
+        p = config3(side=args.side if args.side != 64 else 128)
+        label = (f"3D finite-volume diffusion {p.dims[0]}^3 (N={p.A.n}), coefficients exp(g), g Gaussian, sigma 2, "
+                 "correlation 8 cells, leaf 64, eps 1e-3, PCG preconditioner, 1 RHS to relative residual 1e-10")
+    n = p.A.n
+    rp = torch.tensor(p.A.row_ptr, device=dev)
+    ci = torch.tensor(p.A.col_idx, device=dev)
+    va = torch.tensor(p.A.val, device=dev)
+    B = torch.tensor(np.ascontiguousarray(p.B.T), device=dev)  # (nrhs, n) = column-major n x nrhs
+    X = torch.empty_like(B)
+    torch.cuda.synchronize()
+    forms = {"both": [P.HS_MIXED, P.HS_FP64], "mixed": [P.HS_MIXED], "fp64": [P.HS_FP64]}[args.forms]
+    recs = {}
+    for prec in forms:
+        name = "mixed" if prec == P.HS_MIXED else "fp64"
+        split = {"factor": 0.0, "solve": 0.0}
+
+        def step():
+            t0 = time.perf_counter()
+            F = P.Factor(rp, ci, va, p.dims, p.eps, p.leaf, symmetric=1, precision=prec)
+            t1 = time.perf_counter()
+            _, it, rel, ok = F.pcg(B, p.tol, 300, X=X)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            split["factor"] += t1 - t0
+            split["solve"] += t2 - t1
+            info = F.info()
+            F.free()
+            return it, rel, ok, info
+
+        for w in range(args.warmup):
+            step()
+            print(f"{name}: warmup step {w + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+        fam = "schur_f32" if prec == P.HS_MIXED else "schur"
+        P.profile_reset()
+        P.profile_select("" if args.profile else fam)
+        P.profile_enable(True)
+        torch.cuda.synchronize()
+        split["factor"] = split["solve"] = 0.0
+        t0 = time.perf_counter()
+        its, rels, oks, info = [], [], [], None
+        for k in range(args.steps):
+            it, rel, ok, info = step()
+            print(f"{name}: timed step {k + 1}/{args.steps} done", file=sys.stderr, flush=True)
+            its.append(it)
+            rels.append(float(rel.max()))
+            oks.append(ok)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        P.profile_enable(False)
+        if args.profile:
+            prof = {f: round(P.profile_read(f)["seconds"] / args.steps, 4) for f in FAMILIES}
+            print(f"{name}: seconds per step by family {json.dumps(prof)}", file=sys.stderr, flush=True)
+        traffic = None
+        if args.workload == "poisson64" and args.side == 64 and args.nrhs == 8:
+            traffic = measured_traffic("k_schur_hbm_traffic_poisson64.md", "schur",
+                                       f"traffic_bytes_per_launch_{'float' if prec == P.HS_MIXED else 'double'}")
+        roof = roofline_from(P, fam, f"k_schur<{'float' if prec == P.HS_MIXED else 'double'}> "
+                                     "(Schur-complement update, Eq. elim)", "hbm", traffic)
+        P.profile_select("")
+        P.profile_reset()
+        A_t = torch.sparse_csr_tensor(rp, ci.to(torch.int64), va, size=(n, n))
+        R = B.T - (A_t @ X.T)
+        relres = (torch.linalg.norm(R, dim=0) / torch.linalg.norm(B.T, dim=0)).max().item()
+        recs[name] = {
+            "value": n * args.steps / dt,
+            "ms_per_step": dt / args.steps * 1e3,
+            "factor_ms": split["factor"] / args.steps * 1e3,
+            "solve_ms": split["solve"] / args.steps * 1e3,
+            "pcg_iterations": its,
+            "relres_max": max(rels),
+            "relres_check": relres,
+            "converged": all(oks) and relres <= p.tol * 1.01,
+            "levels": info.nlevels,
+            "colour_batches": info.ncolors_total,
+            "factor_gflop": info.factor_flops / 1e9,
+            "factor_bytes_records": info.factor_bytes,
+            "peak_device_gb": info.peak_device_bytes / 1e9,
+            "roofline": roof,
+        }
+    head_name = "mixed" if "mixed" in recs else "fp64"
+    head = recs[head_name]
+    out = {
+        "metric": METRIC,
+        "value": head["value"],
+        "unit": "unknowns/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 storage + bf16x3 MFMA Schur, f64 Krylov" if head_name == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": label, "form": head_name,
+                   **{k: v for k, v in head.items() if k not in ("value", "ms_per_step", "roofline")}},
+    }
+    if head.get("roofline"):
+        out["roofline"] = head["roofline"]
+    if "fp64" in recs and head_name != "fp64":
+        out["fp64"] = recs["fp64"]
+        out["mixed_over_fp64"] = head["value"] / recs["fp64"]["value"]
+    if not args.no_cpu_baseline and args.workload == "poisson64":
+        print("timing the CPU oracle sample", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline_poisson(args.cpu_side)
     print(json.dumps(out))
 
 
@@ -368,7 +514,7 @@ def run_serve(args):
     srv.close()
     ok = all(r["status"] == 0 for r in results) and max(r["relres"] for r in results) <= 1e-10
     out = {
-        "metric": "unknowns/s factor+solve to 1e-10 residual; p50/p99 latency (serving)",
+        "metric": METRIC,
         "value": st["unknowns_per_s"],
         "unit": "unknowns/s",
         "n_gpus": 1,
@@ -411,13 +557,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--fp64-steps", type=int, default=3, help="timed steps of the float64 form (at most --steps)")
     ap.add_argument("--side", type=int, default=64)
     ap.add_argument("--nrhs", type=int, default=8)
     ap.add_argument("--forms", choices=["both", "mixed", "fp64"], default="both")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-side", type=int, default=24)
     ap.add_argument("--copy-probe", action="store_true", help="also run a plain device copy of known size (counter calibration)")
-    ap.add_argument("--workload", choices=["poisson64", "batch", "serve"], default="poisson64")
+    ap.add_argument("--workload", choices=["batch", "poisson64", "vcd128", "serve"], default="batch")
     ap.add_argument("--requests", type=int, default=100, help="serve workload: requests in the stream")
     ap.add_argument("--rho", type=float, default=0.8, help="serve workload: load over measured capacity")
     ap.add_argument("--cap-gb", type=float, default=200.0, help="serve workload: device memory cap")
@@ -434,81 +581,10 @@ def main():
         sys.exit(2)
     if args.workload == "batch":
         run_batch(args)
-        return
-    if args.workload == "serve":
+    elif args.workload == "serve":
         run_serve(args)
-        return
-
-    import torch
-
-    import paper_1712_07297_amd as P
-    from workloads import config2
-
-    dev = torch.device("cuda:0")
-    p = config2(side=args.side, nrhs=args.nrhs)
-    n = p.A.n
-    rp = torch.tensor(p.A.row_ptr, device=dev)
-    ci = torch.tensor(p.A.col_idx, device=dev)
-    va = torch.tensor(p.A.val, device=dev)
-    B = torch.tensor(np.ascontiguousarray(p.B.T), device=dev)  # (nrhs, n) = column-major n x nrhs
-    X = torch.empty_like(B)
-    torch.cuda.synchronize()
-
-    if args.copy_probe:
-        src = torch.ones(64 * 1024 * 1024 // 8, dtype=torch.float64, device=dev)  # 64 MiB
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-
-    forms = {"both": [P.HS_MIXED, P.HS_FP64], "mixed": [P.HS_MIXED], "fp64": [P.HS_FP64]}[args.forms]
-    recs = {}
-    for prec in forms:
-        recs["mixed" if prec == P.HS_MIXED else "fp64"] = run_form(P, torch, p, rp, ci, va, B, X, prec, args.steps,
-                                                                   args.warmup, n, args.profile)
-    head = recs.get("mixed", recs.get("fp64"))
-    head_name = "mixed" if "mixed" in recs else "fp64"
-    out = {
-        "metric": "unknowns/s factor+solve to 1e-10 residual (mixed vs FP64)",
-        "value": head["value"],
-        "unit": "unknowns/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": head["ms_per_step"],
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32 storage + bf16x3 MFMA Schur, f64 Krylov" if head_name == "mixed" else "f64",
-        "data": "synthetic",
-        "config": {
-            "workload": f"3D 7-point Poisson {args.side}^3 (N={n}), leaf 64, eps 1e-4, PCG preconditioner, {args.nrhs} RHS to relative residual 1e-10",
-            "form": head_name,
-            "factor_ms": head["factor_ms"],
-            "solve_ms": head["solve_ms"],
-            "pcg_iterations": head["pcg_iterations"],
-            "relres_max": head["relres_max"],
-            "relres_check": head["relres_check"],
-            "converged": head["converged"],
-            "levels": head["levels"],
-            "colour_batches": head["colour_batches"],
-            "factor_gflop": head["factor_gflop"],
-            "factor_bytes_records": head["factor_bytes_records"],
-        },
-    }
-    if args.side == 64 and args.nrhs == 8:
-        for name, rec in recs.items():
-            if "roofline" in rec:
-                rec["roofline"]["traffic"] = measured_traffic("float" if name == "mixed" else "double")
-    if "roofline" in head:
-        out["roofline"] = head["roofline"]
-    if "fp64" in recs and head_name != "fp64":
-        out["fp64"] = recs["fp64"]
-        out["mixed_over_fp64"] = head["value"] / recs["fp64"]["value"]
-    if not args.no_cpu_baseline:
-        print("timing the CPU oracle sample", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(args.cpu_side)
-    print(json.dumps(out))
+    else:
+        run_single(args)
 
 
 if __name__ == "__main__":

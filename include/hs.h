@@ -301,20 +301,30 @@ void hs_symbolic_free(hs_symbolic_t S);
 /* ---- tracing ----------------------------------------------------------- */
 
 /* Per-kernel-family timing with HIP events recorded on the stream of each
- * call (a tracing aid; off by default).  Kernel families: "gram", "pivot",
- * "fill", "nbr", "schur" (Schur updates of float64 levels), "schur_f32"
- * (Schur updates of float32 levels, mixed form), "merge", "apply", "spmv",
- * "dense".  While enabled,
- * every launch of a family is bracketed by two events; intervals are read
- * back at the next synchronisation of the library.  Host families (wall time
- * of the factorization's host steps, one count per step): "host_symbolic",
- * "host_plan" (per-level work lists and offsets), "host_upload", "host_alloc", "host_sync" (the per-level rank
- * read-back, which waits for the level's kernels, and the wait before the
- * children's blocks are freed), "host_solve_plan".  hs_profile_read returns,
- * for one family since the last reset: launches, summed seconds, and the
- * algorithmic bytes and flops of those launches (counted from the sizes the
- * kernels worked on: for "schur" and "schur_f32", per cluster 2 f n_tot^2
- * flops and b (2 f n_tot + 2 n_tot^2) bytes, b = 8 and 4 respectively).  Unknown family: HS_ERR_ARG. */
+ * call (a tracing aid; off by default).  Kernel families: "gram", "pivot"
+ * (pivot-block kernel on float64 levels), "pivot_f32" (on float32 levels,
+ * mixed form), "fill", "nbr", "schur" (Schur updates of float64 levels),
+ * "schur_f32" (Schur updates of float32 levels, mixed form), "merge",
+ * "apply", "spmv", "dense".  While enabled, every launch of a family is
+ * bracketed by two events; intervals are read back at the next
+ * synchronisation of the library.  Host families (wall time of the
+ * factorization's host steps, one count per step): "host_symbolic",
+ * "host_plan" (per-level work lists and offsets), "host_upload",
+ * "host_alloc", "host_sync" (the per-level rank read-back, which waits for
+ * the level's kernels, and the wait before the children's blocks are freed),
+ * "host_solve_plan".  hs_profile_read returns, for one family since the last
+ * reset: launches, summed seconds, and the algorithmic bytes and flops of
+ * those launches, counted from the sizes the kernels worked on (b = bytes per
+ * stored element, 8 or 4):
+ *   "schur", "schur_f32": per cluster 2 f n_tot^2 flops and
+ *       b (2 f n_tot + 2 n_tot^2) bytes (Eq. elim);
+ *   "pivot", "pivot_f32": per cluster with f > 0, 2/3 m^3 flops (LU of
+ *       A_ss), plus with fill (0 < k < m) s (2 m^2 k + 4 m k f) + 2 m^2 f +
+ *       2 m f^2 + 2/3 f^3 + 2 m k^2 (X = A_ss^{-1} U and the complement, once
+ *       per side s = 1 or 2; A_ss^{-1} V; F_ff and its LU; C, Eqs. scaling and
+ *       elim); bytes 3 b m^2 (A_ss read, T_L' and T_R' written), plus
+ *       8 m^2 + b k^2 with fill (Gram matrix read, C written).
+ * Unknown family: HS_ERR_ARG. */
 int hs_profile_enable(int32_t enable);
 /* Time only the listed families while profiling is on (comma-separated
  * names; NULL or "" = all).  Untimed launches run as without profiling (the

@@ -229,12 +229,13 @@ struct ProfFamily {
 };
 enum ProfId {
     PF_GRAM = 0, PF_PIVOT, PF_FILL, PF_NBR, PF_SCHUR, PF_SCHUR_F32, PF_MERGE, PF_APPLY, PF_SPMV, PF_DENSE,
+    PF_PIVOT_F32,
     // host wall time of the factorization: symbolic analysis, level planning,
     // metadata uploads, device allocations, per-level rank read-back
     PF_H_SYMBOLIC, PF_H_PLAN, PF_H_UPLOAD, PF_H_ALLOC, PF_H_SYNC, PF_H_SOLVE_PLAN, PF_COUNT
 };
 static ProfFamily g_prof[PF_COUNT] = {{"gram"}, {"pivot"}, {"fill"}, {"nbr"},   {"schur"}, {"schur_f32"},
-                                      {"merge"}, {"apply"}, {"spmv"}, {"dense"},
+                                      {"merge"}, {"apply"}, {"spmv"}, {"dense"}, {"pivot_f32"},
                                       {"host_symbolic"}, {"host_plan"}, {"host_upload"}, {"host_alloc"}, {"host_sync"},
                                       {"host_solve_plan"}};
 static bool g_prof_on = false;
@@ -1123,14 +1124,16 @@ static int factor_impl(hs_factor_s* F, int nsys, const hs_csr* A, const hs_geome
                 if (C.n == 0) continue;
                 const bool gram = F->opts.eps > 0.0 && C.fill_total > 0;
                 // the offsets ride in the Gram launch unless either family is timed
-                const bool fused_offsets = gram && !prof_timed(PF_GRAM) && !prof_timed(PF_PIVOT);
+                const int pivot_fam = t == 0 ? PF_PIVOT_F32 : PF_PIVOT;
+                const bool fused_offsets = gram && !prof_timed(PF_GRAM) && !prof_timed(pivot_fam);
                 if (gram) {
                     ProfScope ps(PF_GRAM, st);
                     launch_gram(LD.dev, C, st, fused_offsets);
                 }
+                if (!fused_offsets) launch_offsets(LD.dev, C, st);
                 {
-                    ProfScope ps(PF_PIVOT, st);
-                    launch_pivot(LD.dev, C, st, fused_offsets);
+                    ProfScope ps(pivot_fam, st);
+                    launch_pivot(LD.dev, C, st);
                 }
                 if (prof_timed(PF_FILL) || prof_timed(PF_NBR)) {  // one family per launch
                     if (C.fill_total > 0) {
@@ -1183,8 +1186,25 @@ static int factor_impl(hs_factor_s* F, int nsys, const hs_csr* A, const hs_geome
         if (g_prof_on) {
             prof_flush();
             for (int c = 0; c < LD.ncl; ++c) {
-                const double f = LD.m[c] - LD.k[c], nt = ntot[c];
-                if (LD.m[c] == 0 || f == 0 || nt == 0 || LD.dense[c]) continue;
+                const double m = LD.m[c], kk = LD.k[c], f = m - kk, nt = ntot[c];
+                if (LD.m[c] == 0 || LD.dense[c]) continue;
+                const int pid = LD.f32[c] ? PF_PIVOT_F32 : PF_PIVOT;
+                if (prof_timed(pid) && f > 0) {
+                    // the pivot kernel's share of the algorithmic work (counted as in the
+                    // flop model below): LU of A_ss; with fill X = A^{-1} U, the
+                    // complement(s), A^{-1} V, F_ff and its LU, C = U^T A^{-1} U; bytes:
+                    // A_ss and the Gram matrix read, T_L', T_R' and C written
+                    const double sides = F->symmetric ? 1.0 : 2.0;
+                    double fl = 2.0 * m * m * m / 3.0, by = (double)LD.esz(c) * (3.0 * m * m);
+                    if (kk > 0)
+                        fl += sides * (2.0 * m * m * kk + 4.0 * m * kk * f) + 2.0 * m * m * f + 2.0 * m * f * f +
+                              2.0 * f * f * f / 3.0 + 2.0 * m * kk * kk;
+                    if (S.fill_ptr[c + 1] > S.fill_ptr[c] && F->opts.eps > 0.0)
+                        by += 8.0 * m * m + (double)LD.esz(c) * kk * kk;
+                    g_prof[pid].flops += fl;
+                    g_prof[pid].bytes += by;
+                }
+                if (f == 0 || nt == 0) continue;
                 const int fid = LD.f32[c] ? PF_SCHUR_F32 : PF_SCHUR;
                 if (!prof_timed(fid)) continue;
                 ProfFamily& fam = g_prof[fid];

@@ -617,9 +617,13 @@ __global__ void __launch_bounds__(WG, 1) k_pivot(LevelDev L, const int* __restri
     wg_gemm<false, false>(M, kk, kk, 1.0, Umat, M, W, M, 0.0, UC, M, sm_l);  // U C (m x k)
 }
 
-void launch_pivot(const LevelDev& L, const ColourDev& C, hipStream_t st, bool offsets_done) {
+void launch_offsets(const LevelDev& L, const ColourDev& C, hipStream_t st) {
     if (C.n == 0) return;
-    if (!offsets_done) hipLaunchKernelGGL(k_offsets, dim3(C.n), dim3(WG), 0, st, L, C.clist);
+    hipLaunchKernelGGL(k_offsets, dim3(C.n), dim3(WG), 0, st, L, C.clist);
+}
+
+void launch_pivot(const LevelDev& L, const ColourDev& C, hipStream_t st) {
+    if (C.n == 0) return;
     const size_t shmem = (size_t)C.max_m * C.max_m * sizeof(double);
     if (C.max_m <= min(LDS_M, L.kn.pivot_lds_max)) {
         if (C.f32)

@@ -40,9 +40,11 @@ constexpr int SOLVE_GROUP_ENTRIES = 32;
 
 // ---- factorization, one colour at a time
 // with_offsets: the Gram launch also computes nbr_noff / ntot / fcols (one
-// extra workgroup per cluster); launch_pivot then gets offsets_done = true.
+// extra workgroup per cluster); otherwise launch_offsets computes them, before
+// launch_pivot.
 void launch_gram(const LevelDev& L, const ColourDev& C, hipStream_t st, bool with_offsets);
-void launch_pivot(const LevelDev& L, const ColourDev& C, hipStream_t st, bool offsets_done);
+void launch_offsets(const LevelDev& L, const ColourDev& C, hipStream_t st);
+void launch_pivot(const LevelDev& L, const ColourDev& C, hipStream_t st);
 void launch_fill_update(const LevelDev& L, const ColourDev& C, hipStream_t st);
 void launch_nbr_update(const LevelDev& L, const ColourDev& C, hipStream_t st);
 // both in one launch (they touch disjoint blocks)
