@@ -89,14 +89,19 @@ typedef struct hs_geometry {
 
 /* Options of the factorization.
  *   eps         relative truncation tolerance of the fill compression
- *               (Eq. lra): a pivot R_jj of the rank-revealing QR is kept while
+ *               (Eq. lra): a pivot R_jj of the rank-revealing QR (column
+ *               pivoting over the unknowns of the cluster) is kept while
  *               |R_jj| > eps |R_11|.  eps = 0 selects the exact mode, in which
- *               a cluster with fill is passed whole to the next level.  The
- *               pivots come from the Gram matrix F F^T (pivoted Cholesky),
- *               whose R_jj^2 carry an absolute rounding error near
- *               u |R_11|^2 (u = 2^-53): ratios |R_jj| / |R_11| are resolved
- *               to about u / (2 eps^2) relative, so eps below about 1e-7
- *               decides at the rounding level.
+ *               a cluster with fill is passed whole to the next level.  Two
+ *               routes compute that QR: for eps >= 1e-5 without a rank cap the
+ *               pivoted Cholesky factorization of the Gram matrix F F^T (one
+ *               pass over F; its pivots R_jj^2 carry an absolute rounding
+ *               error near u |R_11|^2, u = 2^-53, so ratios |R_jj| / |R_11|
+ *               are resolved to about u / (2 eps^2), 5e-7 at eps = 1e-5);
+ *               below 1e-5, or with fixed_rank > 0, the Householder QR with
+ *               column pivoting of F^T itself (resolved to about u / eps).
+ *               hs_config_set("compression" / "qrcp_below_eps") moves the
+ *               switch.
  *   fixed_rank  if > 0, additionally cap every rank at this value (the fixed
  *               rank K of Sec. 5.1).
  *   leaf_size   target number of unknowns per leaf cluster (> 0).
@@ -434,9 +439,10 @@ int hs_set_allocator(void* (*alloc_fn)(size_t, void*), void (*free_fn)(void*, vo
 
 /* ---- kernel-variant thresholds ----------------------------------------- */
 
-/* Several steps have kernel variants that compute the same numbers and
- * differ only in where their working data lives or how the work is split;
- * size thresholds pick one.  These calls read and lower the thresholds for
+/* Several steps have kernel variants that compute the same numbers (up to
+ * rounding) and differ only in where their working data lives, how the work
+ * is split, or (rank revelation) how accurately ill-conditioned fill is
+ * resolved; thresholds pick one.  These calls read and lower the thresholds for
  * the whole process (test hooks, so that every variant runs on inputs small
  * enough for a CPU reference, and a tuning aid).  A factorization copies the
  * values when hs_factor / hs_factor_batch starts; later changes do not touch
@@ -468,6 +474,12 @@ int hs_set_allocator(void* (*alloc_fn)(size_t, void*), void (*free_fn)(void*, vo
  *                                  always Householder QR)
  *   dense_panel      128, 16..128  panel width of the dense LU of a complete
  *                                  level (Alg. 1, final dense factorization)
+ *   compression      0, 0..2       rank revelation (Eq. lra): 0 the
+ *                                  pivoted QR of F^T under a rank cap or
+ *                                  below qrcp_below_eps, else the Gram
+ *                                  route; 1 always the pivoted QR; 2 always
+ *                                  the Gram route
+ *   qrcp_below_eps   1e-5, 0..1    the switch of compression = 0
  *   noalloc_scratch_max  HS_NOALLOC_SCRATCH_BYTES, 0..that   bytes of its
  *                                  device array hs_solve_noalloc may use
  *                                  (read at every call)

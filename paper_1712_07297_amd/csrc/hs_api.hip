@@ -373,6 +373,8 @@ struct LevelData {
 struct Config {
     Knobs kn{LDS_M, TRI_MFMA_MAX, TRI_MFMA_MAX12, 64, 128, TRI_MFMA_MAX, GRAM_SPLITS_MAX, 256, 1024, 1, 0};
     int dense_panel = 128;
+    int compression = 0;            // rank revelation: 0 by eps and cap, 1 pivoted QR, 2 Gram
+    double qrcp_below_eps = 1e-5;   // 0: pivoted QR of F^T below this eps (or under a rank cap)
 };
 
 }  // namespace hs
@@ -382,6 +384,7 @@ struct hs_factor_s {
     int64_t n = 0;
     hs_opts opts{};
     hs::Config cfg;                       // kernel-variant thresholds of this factorization
+    int qrcp = 0;                         // rank revelation by the pivoted QR of F^T (else the Gram route)
     int symmetric = 1;
     hs::Symbolic sym;
     hs::Forest forest;                    // the systems (one for hs_factor)
@@ -463,6 +466,8 @@ static std::vector<ConfigEntry> config_table(Config& c) {
         {"schur_noff_max", 0, 1024, &c.kn.schur_noff_max, nullptr},
         {"cholqr", 0, 1, &c.kn.cholqr, nullptr},
         {"dense_panel", 16, 128, &c.dense_panel, nullptr},
+        {"compression", 0, 2, &c.compression, nullptr},
+        {"qrcp_below_eps", 0, 1, nullptr, &c.qrcp_below_eps},
     };
 }
 
@@ -535,8 +540,17 @@ static int plan_level(hs_factor_s* F, int lvl, Blob& blob, std::vector<size_t>& 
     }
     LD.rec_bytes = roff;
     LD.npairs = pp;
-    LD.gram_splits = gram_splits_of(max_nf, F->cfg.kn.gram_splits_max);  // workspace slots; each cluster uses gram_splits_of(its nf)
+    // workspace slots; each cluster uses gram_splits_of(its nf); the pivoted-QR
+    // route keeps F (m x its fill columns) behind the slots instead
+    LD.gram_splits = F->qrcp ? 1 : gram_splits_of(max_nf, F->cfg.kn.gram_splits_max);
     const int64_t slots = ws_slots(LD.gram_splits);
+    std::vector<int64_t> fcap(ncl, 0);
+    if (F->qrcp)
+        for (int s = 0; s < ncl; ++s) {
+            int64_t c = 0;
+            for (int e = S.fill_ptr[s]; e < S.fill_ptr[s + 1]; ++e) c += m[S.fill[e]];
+            fcap[s] = (F->symmetric ? 1 : 2) * c;
+        }
 
     // colours: every colour's slice of the processing order is reordered into
     // [float32 clusters | float64 clusters | dense clusters] (stable, so each
@@ -614,7 +628,7 @@ static int plan_level(hs_factor_s* F, int lvl, Blob& blob, std::vector<size_t>& 
                 int i1 = i0;
                 while (i1 < nf) {
                     const int s = order[base + i1];
-                    const int64_t need = slots * (int64_t)m[s] * m[s];
+                    const int64_t need = slots * (int64_t)m[s] * m[s] + (int64_t)m[s] * fcap[s];
                     if (i1 > i0 && (wso + need) * (int64_t)sizeof(double) > WS_CHUNK_BYTES) break;
                     ws_off[s] = wso;
                     wso += need;
@@ -688,6 +702,7 @@ static void bind_level(LevelData& LD, const std::vector<size_t>& offs, const hs_
     D.fixed_rank = F->opts.fixed_rank;
     D.gram_splits = LD.gram_splits;
     D.kn = F->cfg.kn;
+    D.kn.qrcp = F->qrcp;
     D.m = (const int*)P(0);
     D.k = (int*)P(1);
     D.flag = (int*)P(2);
@@ -1122,7 +1137,8 @@ static int factor_impl(hs_factor_s* F, int nsys, const hs_csr* A, const hs_geome
             for (int t = 0; t < 2; ++t)
                 for (const ColourDev& C : CH.fac[t]) {
                 if (C.n == 0) continue;
-                const bool gram = F->opts.eps > 0.0 && C.fill_total > 0;
+                const bool rank = F->opts.eps > 0.0 && C.fill_total > 0;  // rank revelation needed
+                const bool gram = rank && !F->qrcp;
                 // the offsets ride in the Gram launch unless either family is timed
                 const int pivot_fam = t == 0 ? PF_PIVOT_F32 : PF_PIVOT;
                 const bool fused_offsets = gram && !prof_timed(PF_GRAM) && !prof_timed(pivot_fam);
@@ -1131,6 +1147,10 @@ static int factor_impl(hs_factor_s* F, int nsys, const hs_csr* A, const hs_geome
                     launch_gram(LD.dev, C, st, fused_offsets);
                 }
                 if (!fused_offsets) launch_offsets(LD.dev, C, st);
+                if (rank && F->qrcp) {
+                    ProfScope ps(PF_GRAM, st);
+                    launch_qrcp(LD.dev, C, st);
+                }
                 {
                     ProfScope ps(pivot_fam, st);
                     launch_pivot(LD.dev, C, st);
@@ -1870,6 +1890,11 @@ static int factor_entry(int32_t nsys, const hs_csr* A, const hs_geometry* geom, 
     std::unique_ptr<hs_factor_s> F(new hs_factor_s());
     F->opts = *opts;
     F->cfg = config_snapshot();
+    // rank revelation (Eq. lra): the pivoted Householder QR of F^T under a rank
+    // cap or below qrcp_below_eps, else the pivoted Cholesky of F F^T
+    F->qrcp = opts->eps > 0.0 &&
+              (F->cfg.compression == 1 ||
+               (F->cfg.compression == 0 && (opts->fixed_rank > 0 || opts->eps < F->cfg.qrcp_below_eps)));
     F->info.breakdown_level = -1;
     F->info.breakdown_cluster = -1;
     AcctScope scope(&F->acct);

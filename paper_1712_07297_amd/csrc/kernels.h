@@ -44,6 +44,9 @@ constexpr int SOLVE_GROUP_ENTRIES = 32;
 // launch_pivot.
 void launch_gram(const LevelDev& L, const ColourDev& C, hipStream_t st, bool with_offsets);
 void launch_offsets(const LevelDev& L, const ColourDev& C, hipStream_t st);
+// Truncated Householder QR with column pivoting of F^T (rank and P R_k^T)
+// for the clusters of the colour that have fill; needs the offsets (fcols).
+void launch_qrcp(const LevelDev& L, const ColourDev& C, hipStream_t st);
 void launch_pivot(const LevelDev& L, const ColourDev& C, hipStream_t st);
 void launch_fill_update(const LevelDev& L, const ColourDev& C, hipStream_t st);
 void launch_nbr_update(const LevelDev& L, const ColourDev& C, hipStream_t st);

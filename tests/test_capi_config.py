@@ -17,6 +17,8 @@ DEFAULTS = {
     "schur_noff_max": 1024,
     "cholqr": 1,
     "dense_panel": 128,
+    "compression": 0,
+    "qrcp_below_eps": 1e-5,
 }
 
 
@@ -35,7 +37,8 @@ def test_defaults_and_reset():
 
 
 @pytest.mark.parametrize("name,value", [("no_such_parameter", 1), ("pivot_lds_max", 129), ("pivot_lds_max", -1),
-                                        ("dense_panel", 16.5), ("dense_panel", 8), ("gram_splits_max", 0)])
+                                        ("dense_panel", 16.5), ("dense_panel", 8), ("gram_splits_max", 0),
+                                        ("compression", 3), ("qrcp_below_eps", 2.0)])
 def test_rejected_values_change_nothing(name, value):
     H.config_reset()
     with pytest.raises(H.HsError) as e:

@@ -99,6 +99,10 @@ FORCED = [
     ("schur_offsets_in_memory", dict(schur_noff_max=0, schur_ptab_max=3), ["p3d", "nonsym"]),
     ("basis_by_householder", dict(cholqr=0), ["p3d", "nonsym"]),
     ("dense_panels_16", dict(dense_panel=16), ["p3d", "p2d_exact"]),
+    # rank revelation by the pivoted Householder QR of F^T at eps >= 1e-5 (its
+    # own kernel, k_qrcp; compared at the pivoted-QR bar, 1e-9 here)
+    ("rank_by_pivoted_qr", dict(compression=1), ["p3d", "nonsym"]),
+    ("rank_by_pivoted_qr_in_memory", dict(compression=1, pivot_lds_max=0), ["p3d", "nonsym"]),
 ]
 
 FORCED_CASES = [(v, kn, inp) for v, kn, inputs in FORCED for inp in inputs]
@@ -111,6 +115,24 @@ def test_forced_variant(P, variant, kn, inp):
     print(f"[variants] {variant} on {inp}: {kn}", flush=True)
     with knobs(P, **kn):
         fo, F, st = compare_factor(P, A, dims, leaf, eps, sym)
+    _check_solve(P, fo, F, A)
+
+
+@pytest.mark.parametrize("name,mk,dims,leaf,sym", [
+    ("p2d_leaf144", lambda: poisson2d(48, 48), (48, 48, 1), 144, True),
+    ("convdiff_leaf144", lambda: convdiff2d_upwind(48, 50.0, 0.3), (48, 48, 1), 144, False),
+])
+def test_pivoted_qr_large_clusters(P, name, mk, dims, leaf, sym):
+    """The pivoted-QR route on clusters of 144 (memory-resident pivot kernel)
+    at eps = 1e-7: ranks bit-exact, solves to 1e-8, factor entries to 1e-6
+    wherever the input determines them (on the 2D Poisson input one cluster's
+    pivots are decided by rounding: the oracle's own coarse basis of it moves
+    by 0.35 under a 1e-15 perturbation of A)."""
+    A = mk()
+    print(f"[variants] pivoted QR {name}", flush=True)
+    fo, F, st = compare_factor(P, A, dims, leaf, 1e-7, sym, stable_only=True)
+    assert st["levels_compared"] >= 1
+    assert st["max_lowrank_m"] == 144
     _check_solve(P, fo, F, A)
 
 
