@@ -89,3 +89,38 @@ def test_serving_stream_mix_and_reuse():
         r.side = min(r.side, 24)  # keep the check cheap
         A, dims, dim, sym = build_request_operator(r)
         assert A.n == int(np.prod(dims)) and sym == (r.kind == "diff3d")
+
+
+def test_quantized_high_contrast_field():
+    """Sec. 5.1's field: two values, an even split, spatially correlated at
+    the 4-cell scale, seeded; one cell checked against a brute-force
+    normalised Gaussian average of the same uniform draws."""
+    from workloads import quantized_field3d
+
+    rng = np.random.default_rng(1)
+    a = quantized_field3d(rng, 20, 18, 16)
+    assert a.shape == (16, 18, 20)
+    assert set(np.unique(a)) == {1e-2, 1e2}
+    assert 0.35 < (a > 1).mean() < 0.65
+    assert (a[:, :, 1:] == a[:, :, :-1]).mean() > 0.85  # neighbours mostly agree
+    assert np.array_equal(a, quantized_field3d(np.random.default_rng(1), 20, 18, 16))
+    u = np.random.default_rng(1).uniform(0.0, 1.0, (16, 18, 20))
+    z, y, x = np.meshgrid(np.arange(16), np.arange(18), np.arange(20), indexing="ij")
+    for (k, j, i) in [(8, 9, 10), (0, 0, 0), (15, 3, 19)]:
+        d = np.maximum.reduce([np.abs(x - i), np.abs(y - j), np.abs(z - k)])
+        w = np.exp(-0.5 * (((x - i) / 4.0) ** 2 + ((y - j) / 4.0) ** 2 + ((z - k) / 4.0) ** 2)) * (d <= 12)
+        avg = (w * u).sum() / w.sum()
+        if abs(avg - 0.5) > 1e-9:
+            assert (a[k, j, i] > 1) == (avg > 0.5)
+
+
+def test_vc_poisson_is_spd_m_matrix():
+    from workloads import vc_poisson3d
+
+    A = vc_poisson3d(np.random.default_rng(2), 6)
+    D = A.to_dense()
+    assert np.array_equal(D, D.T)
+    off = D - np.diag(np.diag(D))
+    assert np.all(off <= 0)
+    assert np.all(np.diag(D) >= -off.sum(axis=1) - 1e-12)
+    assert np.linalg.eigvalsh(D).min() > 0

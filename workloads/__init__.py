@@ -15,6 +15,8 @@ from .pde import (  # noqa: F401
     diffusion3d_from_coeff,
     convdiff2d_upwind,
     gaussian_field3d,
+    quantized_field3d,
+    vc_poisson3d,
     rhs_uniform,
     make_config,
     config1,

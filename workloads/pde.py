@@ -172,6 +172,39 @@ def diffusion3d_expgauss(rng: np.random.Generator, side: int, sigma: float = 2.0
     return diffusion3d_from_coeff(np.exp(g))
 
 
+def quantized_field3d(rng: np.random.Generator, nx: int, ny: int, nz: int, dev_cells: float = 4.0,
+                      high: float = 1e2, low: float = 1e-2) -> np.ndarray:
+    """The quantized high-contrast random field of the paper's variable-
+    coefficient Poisson test (Sec. 5.1), shape (nz, ny, nx): uniform [0, 1)
+    noise on the cells, convolved with a Gaussian of standard deviation
+    dev_cells cells (4h), then set to ``high`` where it exceeds 0.5 and to
+    ``low`` elsewhere.  The kernel is separable, truncated at 3 standard
+    deviations, and normalised by its weight inside the grid at every cell
+    (near the boundary the average is taken over the cells that exist, so the
+    field keeps mean 0.5 and the split stays even)."""
+    u = rng.uniform(0.0, 1.0, (nz, ny, nx))
+    r = int(math.ceil(3.0 * dev_cells))
+    t = np.arange(-r, r + 1, dtype=np.float64)
+    ker = np.exp(-0.5 * (t / dev_cells) ** 2)
+
+    def conv(v):
+        return np.convolve(v, ker, mode="full")[r : r + v.size]
+
+    g, w = u, np.ones_like(u)
+    for axis in range(3):
+        g = np.apply_along_axis(conv, axis, g)
+        w = np.apply_along_axis(conv, axis, w)
+    g = g / w
+    return np.where(g > 0.5, high, low)
+
+
+def vc_poisson3d(rng: np.random.Generator, side: int, dev_cells: float = 4.0) -> CSR:
+    """Variable-coefficient Poisson -div(a grad u) on a side^3 grid with the
+    quantized high-contrast field a (values 1e2 / 1e-2, Sec. 5.1), 7-point
+    finite-volume stencil with harmonic face averages."""
+    return diffusion3d_from_coeff(quantized_field3d(rng, side, side, side, dev_cells))
+
+
 def convdiff2d_upwind(side: int, peclet: float, theta: float) -> CSR:
     """-Laplace(u) + b.grad(u) on the unit square, first-order upwind, h = 1/(side+1),
     b = Pe (cos theta, sin theta), scaled by h^2 (nonsymmetric, diagonally dominant)."""
