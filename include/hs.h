@@ -21,8 +21,9 @@
  * Conventions shared by every entry point:
  *   - Matrices are square, CSR with int64 row pointers, int32 column indices
  *     (sorted, unique within a row, in range) and float64 values.
- *   - Unknowns are the points of an nx*ny*nz grid, index x + nx*(y + ny*z);
- *     the geometry is used to build the cluster tree (recursive bisection).
+ *   - Unknowns are the points of an nx*ny*nz grid, index x + nx*(y + ny*z),
+ *     and the geometry is used to build the cluster tree (recursive
+ *     bisection), or, with dim = 0, the graph of A is bisected instead.
  *   - Dense right-hand sides and solutions are column major, n rows, leading
  *     dimension >= n, float64.
  *   - Every function returns 0 on success, a negative HS_ERR_* code on error,
@@ -54,7 +55,7 @@ extern "C" {
 #define HS_OK 0
 #define HS_ERR_ARG (-1)         /* null pointer, negative size, bad option */
 #define HS_ERR_PATTERN (-2)     /* unsorted / duplicate / out-of-range CSR index */
-#define HS_ERR_GEOMETRY (-3)    /* n != nx*ny*nz, or a non-grid coupling */
+#define HS_ERR_GEOMETRY (-3)    /* n != nx*ny*nz (dim 1..3), or dim outside 0..3 */
 #define HS_ERR_BREAKDOWN (-4)   /* zero or non-finite pivot in an unpivoted LU */
 #define HS_ERR_NOMEM (-5)       /* device allocation failed or above the cap */
 #define HS_ERR_HIP (-6)         /* a HIP runtime call failed */
@@ -75,7 +76,12 @@ typedef struct hs_csr {
     int32_t on_device;
 } hs_csr;
 
-/* Grid of the unknowns (lexicographic, x fastest). dim = 1, 2 or 3. */
+/* Grid of the unknowns (lexicographic, x fastest), dim = 1, 2 or 3: the
+ * cluster tree bisects the grid box.  dim = 0: no grid (nx, ny, nz ignored);
+ * the cluster tree bisects the graph of A + A^T instead (Alg. 1, "Partition
+ * the graph of A"): every set is put in breadth-first order from a
+ * pseudo-peripheral vertex (connected components by their lowest vertex,
+ * neighbours in ascending order) and its first half forms the left child. */
 typedef struct hs_geometry {
     int32_t dim;
     int32_t nx, ny, nz;

@@ -10,6 +10,7 @@ from .hs_oracle import (  # noqa: F401
     Tree,
     LevelSymbolic,
     build_tree,
+    build_tree_algebraic,
     level0_graph,
     greedy_distance2_coloring,
     processing_order,

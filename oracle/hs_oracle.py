@@ -62,6 +62,11 @@ R11 structural fill a-b for every pair of neighbours of a processed cluster
 R12 fill whose largest row norm is at most 1e-12 ||A_ss||_F is rounding noise
     of earlier Schur updates (the relative rule of Eq. lra would compress
     noise): it is treated as zero, k = 0 (eps > 0 only).
+R14 clusters without a grid: complete recursive bisection of the graph of
+    A + A^T to the same depth D; each set is ordered breadth first from a
+    pseudo-peripheral vertex (component by component, lowest vertex first,
+    neighbours ascending) and its first floor(|S|/2) vertices form the left
+    child.
 """
 
 from __future__ import annotations
@@ -122,6 +127,86 @@ def build_tree(dims: Tuple[int, int, int], leaf: int) -> Tree:
         cluster_of[ids] = c
         local_of[ids] = np.arange(ids.size)
     return Tree(depth, depth + 1, leaf_dofs, cluster_of, local_of)
+
+
+def _level_structure_order(S: np.ndarray, nbrs: List[np.ndarray], inset: np.ndarray) -> List[int]:
+    """Reading R14: the vertices of S in breadth-first order from
+    pseudo-peripheral roots, one connected component (of the subgraph induced
+    by S) after the other, components taken by their lowest vertex.  A root
+    search starts at the component's lowest vertex and moves to the lowest
+    vertex of the last breadth-first level while that increases the
+    eccentricity (at most 8 moves).  Neighbours are visited in ascending
+    order."""
+    todo = set(int(v) for v in S)
+    order: List[int] = []
+
+    def bfs(root):
+        seen = {root}
+        levels = [[root]]
+        while True:
+            nxt = []
+            for u in levels[-1]:
+                for v in nbrs[u]:
+                    v = int(v)
+                    if inset[v] and v in todo and v not in seen:
+                        seen.add(v)
+                        nxt.append(v)
+            if not nxt:
+                return levels
+            levels.append(nxt)
+
+    while todo:
+        root = min(todo)
+        levels = bfs(root)
+        for _ in range(8):
+            cand = min(levels[-1])
+            lv = bfs(cand)
+            if len(lv) <= len(levels):
+                break
+            root, levels = cand, lv
+        comp = [v for lev in levels for v in lev]
+        order.extend(comp)
+        todo.difference_update(comp)
+    return order
+
+
+def build_tree_algebraic(row_ptr: np.ndarray, col_idx: np.ndarray, leaf: int) -> Tree:
+    """Reading R14 (Alg. 1 "Partition the graph of A" without a geometry):
+    complete recursive bisection of the graph of A + A^T to depth
+    D = ceil(log2(N / leaf)); a set goes to two children, the first
+    floor(|S| / 2) vertices of its level-structure order to the left one,
+    the rest to the right one.  Leaves keep their unknowns in ascending
+    order."""
+    row_ptr = np.asarray(row_ptr)
+    col_idx = np.asarray(col_idx).astype(np.int64)
+    n = row_ptr.size - 1
+    depth = 0 if n <= leaf else int(math.ceil(math.log2(n / leaf)))
+    sets = [set() for _ in range(n)]
+    for i in range(n):
+        for j in col_idx[row_ptr[i] : row_ptr[i + 1]]:
+            j = int(j)
+            if j != i:
+                sets[i].add(j)
+                sets[j].add(i)
+    nbrs = [np.array(sorted(x), dtype=np.int64) for x in sets]
+    nodes = [np.arange(n)]
+    inset = np.zeros(n, dtype=bool)
+    for _ in range(depth):
+        nxt = []
+        for S in nodes:
+            inset[:] = False
+            inset[S] = True
+            order = _level_structure_order(S, nbrs, inset)
+            h = len(order) // 2
+            nxt.append(np.array(sorted(order[:h]), dtype=np.int64))
+            nxt.append(np.array(sorted(order[h:]), dtype=np.int64))
+        nodes = nxt
+    cluster_of = np.empty(n, dtype=np.int64)
+    local_of = np.empty(n, dtype=np.int64)
+    for c, ids in enumerate(nodes):
+        cluster_of[ids] = c
+        local_of[ids] = np.arange(ids.size)
+    return Tree(depth, depth + 1, nodes, cluster_of, local_of)
 
 
 def level0_graph(row_ptr: np.ndarray, col_idx: np.ndarray, cluster_of: np.ndarray, ncl: int) -> List[List[int]]:
@@ -204,7 +289,9 @@ def simulate_level_pattern(adj: List[List[int]]) -> LevelSymbolic:
 
 
 def symbolic_analysis(row_ptr, col_idx, dims, leaf) -> Tuple[Tree, List[LevelSymbolic]]:
-    tree = build_tree(dims, leaf)
+    """dims: the grid (nx, ny, nz), or None to partition the graph of A
+    (reading R14)."""
+    tree = build_tree(dims, leaf) if dims is not None else build_tree_algebraic(row_ptr, col_idx, leaf)
     ncl = len(tree.leaf_dofs)
     adj = level0_graph(row_ptr, col_idx, tree.cluster_of_dof, ncl)
     levels = []

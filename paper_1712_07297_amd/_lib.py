@@ -228,7 +228,10 @@ def _stream(stream) -> int:
     return int(torch.cuda.current_stream().cuda_stream)
 
 
-def _geom(dims: Sequence[int]) -> hs_geometry:
+def _geom(dims: Optional[Sequence[int]]) -> hs_geometry:
+    """Grid of the unknowns; None: no grid (the graph of A is partitioned)."""
+    if dims is None:
+        return hs_geometry(0, 0, 0, 0)
     nx, ny, nz = (list(dims) + [1, 1])[:3]
     dim = 3 if nz > 1 else (2 if ny > 1 else 1)
     return hs_geometry(dim, int(nx), int(ny), int(nz))

@@ -993,7 +993,9 @@ static int factor_impl(hs_factor_s* F, int nsys, const hs_csr* A, const hs_geome
         std::vector<int> rcs(nsys, 0);
         const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
         parallel_for(nsys, std::min(hw, 16), [&](int i) {
-            rcs[i] = build_symbolic(A[i].n, rp[i], ci[i], G[i].nx, G[i].ny, G[i].nz, F->opts.leaf_size, parts[i]);
+            const bool grid = G[i].dim > 0;  // dim 0: partition the graph of A
+            rcs[i] = build_symbolic(A[i].n, rp[i], ci[i], grid ? G[i].nx : 0, grid ? G[i].ny : 0, grid ? G[i].nz : 0,
+                                    F->opts.leaf_size, parts[i]);
         });
         for (int i = 0; i < nsys; ++i)
             if (rcs[i])
@@ -1868,7 +1870,7 @@ static int check_opts(const hs_opts* opts) {
 static int check_system(const hs_csr* A, const hs_geometry* geom) {
     if (!A->row_ptr || (A->nnz > 0 && (!A->col_idx || !A->val))) return fail(HS_ERR_ARG, "null argument");
     if (A->n <= 0 || A->nnz < 0 || A->n > INT32_MAX) return fail(HS_ERR_ARG, "bad matrix size");
-    if (geom->dim < 1 || geom->dim > 3 || (int64_t)geom->nx * geom->ny * geom->nz != A->n)
+    if (geom->dim < 0 || geom->dim > 3 || (geom->dim > 0 && (int64_t)geom->nx * geom->ny * geom->nz != A->n))
         return fail(HS_ERR_GEOMETRY, "n != nx*ny*nz");
     return HS_OK;
 }
@@ -2061,7 +2063,10 @@ int hs_symbolic_create(const hs_csr* A, const hs_geometry* geom, int32_t leaf_si
     int rc = validate_csr_host(A->n, A->nnz, A->row_ptr, A->col_idx);
     if (rc) return rc;
     std::unique_ptr<hs_symbolic_s> S(new hs_symbolic_s());
-    rc = build_symbolic(A->n, A->row_ptr, A->col_idx, geom->nx, geom->ny, geom->nz, leaf_size, S->sym);
+    if (geom->dim < 0 || geom->dim > 3) return fail(HS_ERR_GEOMETRY, "dim must be 0..3");
+    const bool grid = geom->dim > 0;  // dim 0: partition the graph of A
+    rc = build_symbolic(A->n, A->row_ptr, A->col_idx, grid ? geom->nx : 0, grid ? geom->ny : 0, grid ? geom->nz : 0,
+                        leaf_size, S->sym);
     if (rc) return fail(rc, "symbolic analysis failed");
     *S_out = S.release();
     return HS_OK;

@@ -235,60 +235,11 @@ void simulate_level(LevelSymbolic& L, std::vector<int>& next_ptr, std::vector<in
 
 }  // namespace
 
-int build_symbolic(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, int nx, int ny, int nz, int leaf,
-                   Symbolic& S) {
-    if (n <= 0 || leaf <= 0 || nx <= 0 || ny <= 0 || nz <= 0) return HS_ERR_ARG;
-    if ((int64_t)nx * ny * nz != n) return HS_ERR_GEOMETRY;
-    S = Symbolic();
-    S.n = n;
-    int depth = 0;
-    while ((int64_t)leaf << depth < n) ++depth;
-    if (depth > 30) return HS_ERR_ARG;
-    S.depth = depth;
-    S.nlevels = depth + 1;
-
-    std::vector<Box> boxes{Box{{0, 0, 0}, {nx, ny, nz}}};
-    for (int d = 0; d < depth; ++d) {
-        std::vector<Box> nxt;
-        nxt.reserve(boxes.size() * 2);
-        for (const Box& b : boxes) {
-            int axis = 0;
-            int best = b.hi[0] - b.lo[0];
-            for (int a = 1; a < 3; ++a)
-                if (b.hi[a] - b.lo[a] > best) {
-                    best = b.hi[a] - b.lo[a];
-                    axis = a;
-                }
-            int cut = b.lo[axis] + best / 2;
-            Box l = b, r = b;
-            l.hi[axis] = cut;
-            r.lo[axis] = cut;
-            nxt.push_back(l);
-            nxt.push_back(r);
-        }
-        boxes.swap(nxt);
-    }
-    const int nleaf = (int)boxes.size();
-    S.leaf_ptr.assign(nleaf + 1, 0);
-    S.leaf_dofs.resize(n);
-    S.cluster_of.assign(n, -1);
-    S.local_of.assign(n, -1);
-    int64_t w = 0;
-    for (int c = 0; c < nleaf; ++c) {
-        const Box& b = boxes[c];
-        int loc = 0;
-        // ids x + nx*(y + ny*z) ascending: z outermost, x innermost
-        for (int z = b.lo[2]; z < b.hi[2]; ++z)
-            for (int y = b.lo[1]; y < b.hi[1]; ++y)
-                for (int x = b.lo[0]; x < b.hi[0]; ++x) {
-                    int64_t id = x + (int64_t)nx * (y + (int64_t)ny * z);
-                    S.leaf_dofs[w++] = id;
-                    S.cluster_of[id] = c;
-                    S.local_of[id] = loc++;
-                }
-        S.leaf_ptr[c + 1] = (int)w;
-    }
-
+// The level-0 block graph and every level's symbolic analysis, once the
+// leaves (S.leaf_ptr, leaf_dofs, cluster_of, local_of) are set.
+static int finish_symbolic(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, Symbolic& S) {
+    (void)n;
+    const int nleaf = (int)S.leaf_ptr.size() - 1;
     // level-0 block graph from the stored entries, symmetrised: the distinct
     // clusters that each cluster's rows reach (marker over its own rows), then
     // every such pair entered in both directions
@@ -339,6 +290,196 @@ int build_symbolic(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, in
         }
     }
     return HS_OK;
+}
+
+// Leaves by complete recursive bisection of the graph of A + A^T (no grid):
+// every set S of a tree level is put in level-structure order (breadth first
+// from a pseudo-peripheral vertex, one connected component of the induced
+// subgraph after the other, components by their lowest vertex; the root
+// search starts at the component's lowest vertex and moves to the lowest
+// vertex of the last breadth-first level while that increases the
+// eccentricity, at most 8 times; neighbours in ascending order), and its
+// first floor(|S| / 2) vertices form the left child.  Leaves list their
+// unknowns in ascending order.
+static void algebraic_leaves(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, int depth,
+                      std::vector<std::vector<int>>& nodes) {
+    // symmetrised pattern without the diagonal, rows sorted
+    std::vector<int> deg(n, 0);
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+            const int j = col_idx[e];
+            if (j != i) {
+                ++deg[i];
+                ++deg[j];
+            }
+        }
+    std::vector<int64_t> ptr(n + 1, 0);
+    for (int64_t i = 0; i < n; ++i) ptr[i + 1] = ptr[i] + deg[i];
+    std::vector<int> nb(ptr[n]);
+    {
+        std::vector<int64_t> w(ptr.begin(), ptr.end() - 1);
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+                const int j = col_idx[e];
+                if (j != i) {
+                    nb[w[i]++] = j;
+                    nb[w[j]++] = (int)i;
+                }
+            }
+        for (int64_t i = 0; i < n; ++i) {
+            auto b = nb.begin() + ptr[i], en = nb.begin() + ptr[i + 1];
+            std::sort(b, en);
+            en = std::unique(b, en);
+            // keep the row's length; duplicates (a_ij and a_ji both stored) are marked -1
+            for (auto it = en; it != nb.begin() + ptr[i + 1]; ++it) *it = -1;
+        }
+    }
+    std::vector<int> tag(n, -1), seen(n, 0);
+    std::vector<char> done(n, 0);
+    int stamp = 0, ntag = 0;
+    std::vector<int> flat, lp, flat2, lp2, order;
+    auto bfs = [&](int root, int cur, std::vector<int>& fl, std::vector<int>& lv) {
+        ++stamp;
+        fl.assign(1, root);
+        seen[root] = stamp;
+        lv.assign({0, 1});
+        for (;;) {
+            const int a = lv[lv.size() - 2], b = lv.back();
+            for (int q = a; q < b; ++q) {
+                const int u = fl[q];
+                for (int64_t e = ptr[u]; e < ptr[u + 1]; ++e) {
+                    const int v = nb[e];
+                    if (v < 0) break;
+                    if (tag[v] == cur && !done[v] && seen[v] != stamp) {
+                        seen[v] = stamp;
+                        fl.push_back(v);
+                    }
+                }
+            }
+            if ((int)fl.size() == b) return;
+            lv.push_back((int)fl.size());
+        }
+    };
+    nodes.assign(1, std::vector<int>(n));
+    for (int64_t i = 0; i < n; ++i) nodes[0][i] = (int)i;
+    for (int d = 0; d < depth; ++d) {
+        std::vector<std::vector<int>> nxt;
+        nxt.reserve(nodes.size() * 2);
+        for (const std::vector<int>& S : nodes) {
+            const int cur = ntag++;
+            for (int v : S) {
+                tag[v] = cur;
+                done[v] = 0;
+            }
+            order.clear();
+            size_t start = 0;
+            for (;;) {
+                while (start < S.size() && done[S[start]]) ++start;
+                if (start == S.size()) break;
+                int root = S[start];
+                bfs(root, cur, flat, lp);
+                for (int it = 0; it < 8; ++it) {
+                    int cand = INT32_MAX;
+                    for (int q = lp[lp.size() - 2]; q < lp.back(); ++q) cand = std::min(cand, flat[q]);
+                    bfs(cand, cur, flat2, lp2);
+                    if (lp2.size() <= lp.size()) break;
+                    root = cand;
+                    flat.swap(flat2);
+                    lp.swap(lp2);
+                }
+                for (int v : flat) {
+                    order.push_back(v);
+                    done[v] = 1;
+                }
+            }
+            const size_t h = order.size() / 2;
+            std::vector<int> l(order.begin(), order.begin() + h), r(order.begin() + h, order.end());
+            std::sort(l.begin(), l.end());
+            std::sort(r.begin(), r.end());
+            nxt.push_back(std::move(l));
+            nxt.push_back(std::move(r));
+        }
+        nodes.swap(nxt);
+    }
+}
+
+int build_symbolic(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, int nx, int ny, int nz, int leaf,
+                   Symbolic& S) {
+    const bool algebraic = nx == 0 && ny == 0 && nz == 0;
+    if (n <= 0 || leaf <= 0 || (!algebraic && (nx <= 0 || ny <= 0 || nz <= 0))) return HS_ERR_ARG;
+    if (!algebraic && (int64_t)nx * ny * nz != n) return HS_ERR_GEOMETRY;
+    S = Symbolic();
+    S.n = n;
+    int depth = 0;
+    while ((int64_t)leaf << depth < n) ++depth;
+    if (depth > 30) return HS_ERR_ARG;
+    S.depth = depth;
+    S.nlevels = depth + 1;
+
+    if (algebraic) {
+        std::vector<std::vector<int>> nodes;
+        algebraic_leaves(n, row_ptr, col_idx, depth, nodes);
+        const int nleaf = (int)nodes.size();
+        S.leaf_ptr.assign(nleaf + 1, 0);
+        S.leaf_dofs.resize(n);
+        S.cluster_of.assign(n, -1);
+        S.local_of.assign(n, -1);
+        int64_t w = 0;
+        for (int c = 0; c < nleaf; ++c) {
+            int loc = 0;
+            for (int id : nodes[c]) {
+                S.leaf_dofs[w++] = id;
+                S.cluster_of[id] = c;
+                S.local_of[id] = loc++;
+            }
+            S.leaf_ptr[c + 1] = (int)w;
+        }
+        return finish_symbolic(n, row_ptr, col_idx, S);
+    }
+
+    std::vector<Box> boxes{Box{{0, 0, 0}, {nx, ny, nz}}};
+    for (int d = 0; d < depth; ++d) {
+        std::vector<Box> nxt;
+        nxt.reserve(boxes.size() * 2);
+        for (const Box& b : boxes) {
+            int axis = 0;
+            int best = b.hi[0] - b.lo[0];
+            for (int a = 1; a < 3; ++a)
+                if (b.hi[a] - b.lo[a] > best) {
+                    best = b.hi[a] - b.lo[a];
+                    axis = a;
+                }
+            int cut = b.lo[axis] + best / 2;
+            Box l = b, r = b;
+            l.hi[axis] = cut;
+            r.lo[axis] = cut;
+            nxt.push_back(l);
+            nxt.push_back(r);
+        }
+        boxes.swap(nxt);
+    }
+    const int nleaf = (int)boxes.size();
+    S.leaf_ptr.assign(nleaf + 1, 0);
+    S.leaf_dofs.resize(n);
+    S.cluster_of.assign(n, -1);
+    S.local_of.assign(n, -1);
+    int64_t w = 0;
+    for (int c = 0; c < nleaf; ++c) {
+        const Box& b = boxes[c];
+        int loc = 0;
+        // ids x + nx*(y + ny*z) ascending: z outermost, x innermost
+        for (int z = b.lo[2]; z < b.hi[2]; ++z)
+            for (int y = b.lo[1]; y < b.hi[1]; ++y)
+                for (int x = b.lo[0]; x < b.hi[0]; ++x) {
+                    int64_t id = x + (int64_t)nx * (y + (int64_t)ny * z);
+                    S.leaf_dofs[w++] = id;
+                    S.cluster_of[id] = c;
+                    S.local_of[id] = loc++;
+                }
+        S.leaf_ptr[c + 1] = (int)w;
+    }
+
+    return finish_symbolic(n, row_ptr, col_idx, S);
 }
 
 int complete_level(const Symbolic& S) {

@@ -10,7 +10,7 @@ import pytest
 
 import oracle as O
 from paper_1712_07297_amd import _lib as H
-from workloads import poisson2d, poisson3d, random_nonsym_dd, convdiff2d_upwind, chain1d, one_sided_dd
+from workloads import poisson2d, poisson3d, random_nonsym_dd, convdiff2d_upwind, chain1d, one_sided_dd, random_geometric_spd
 
 
 def test_library_exports_every_declared_function():
@@ -54,7 +54,22 @@ CASES = [
     ("convdiff", lambda: (convdiff2d_upwind(40, 30.0, 1.0), (40, 40, 1), 64)),
     ("chain", lambda: (chain1d(100), (100, 1, 1), 3)),
     ("tiny", lambda: (poisson2d(3, 2), (3, 2, 1), 64)),
+    # no grid: the graph of A is bisected (reading R14)
+    ("geo_nogrid", lambda: (random_geometric_spd(np.random.default_rng(1), 1500), None, 48)),
+    ("geo_nonsym_nogrid", lambda: (random_geometric_spd(np.random.default_rng(2), 900, nonsym=0.3), None, 30)),
+    ("p2d_nogrid", lambda: (poisson2d(37, 23), None, 10)),
+    ("one_sided_nogrid", lambda: (one_sided_dd(np.random.default_rng(7), 29, 22), None, 12)),
+    ("chain_nogrid", lambda: (chain1d(100), None, 3)),
+    ("two_components_nogrid", lambda: (_two_components(), None, 20)),
 ]
+
+
+def _two_components():
+    A1 = random_geometric_spd(np.random.default_rng(5), 300)
+    A2 = random_geometric_spd(np.random.default_rng(6), 200)
+    rp = np.concatenate([A1.row_ptr, A2.row_ptr[1:] + A1.nnz])
+    ci = np.concatenate([A1.col_idx, A2.col_idx + A1.n]).astype(np.int32)
+    return type(A1)(A1.n + A2.n, rp, ci, np.concatenate([A1.val, A2.val]))
 
 
 @pytest.mark.parametrize("name,mk", CASES)

@@ -444,3 +444,77 @@ def test_noise_floor_reading_r12(factor_of_floor, expect_zero):
     # either way the factorization solves the system to eps-level accuracy
     b = np.random.default_rng(0).uniform(-1, 1, A.n)
     assert _relres(A, O.solve(fo, b), b) < 1e-5
+
+
+# ------------------------------------------------- R14 partition without a grid
+
+
+def test_algebraic_tree_golden():
+    """Reading R14 on inputs small enough to follow by hand.  Path 0-1-...-7,
+    leaf 2: breadth-first from 0 (moving to 7 does not lengthen the
+    structure) gives 0..7, halves {0..3} | {4..7}, then {0,1} | {2,3} and
+    {4,5} | {6,7}.  4 x 4 grid (id x + 4y), leaf 4: from 0 the levels are
+    0 | 1 4 | 2 5 8 | 3 6 9 12 | ...  and 15 is no farther, so the first half
+    of 0 1 4 2 5 8 3 6 9 12 ... is {0,1,2,3,4,5,6,8}; inside it the search
+    moves to 3 (eccentricity 5 > 3), whose order 3 2 1 6 0 5 4 8 splits
+    {1,2,3,6} | {0,4,5,8}; the other half from 7 (12 is no farther) orders
+    7 11 10 15 9 14 13 12 and splits {7,10,11,15} | {9,12,13,14}."""
+    A = chain1d(8)
+    t = O.build_tree_algebraic(A.row_ptr, A.col_idx, 2)
+    assert [d.tolist() for d in t.leaf_dofs] == [[0, 1], [2, 3], [4, 5], [6, 7]]
+    A = poisson2d(4, 4)
+    t = O.build_tree_algebraic(A.row_ptr, A.col_idx, 4)
+    assert [d.tolist() for d in t.leaf_dofs] == [[1, 2, 3, 6], [0, 4, 5, 8], [7, 10, 11, 15], [9, 12, 13, 14]]
+
+
+@pytest.mark.parametrize("n,leaf,seed", [(1500, 48, 1), (777, 20, 2), (64, 64, 3), (10, 1, 4)])
+def test_algebraic_tree_partitions_balanced_and_local(n, leaf, seed):
+    """Every unknown in exactly one leaf, 2^D leaves, leaf sizes the floor or
+    ceiling of each halving, and a far smaller edge cut between the two
+    halves of the root than a random equal split has (locality)."""
+    from workloads import random_geometric_spd
+
+    A = random_geometric_spd(np.random.default_rng(seed), n)
+    t = O.build_tree_algebraic(A.row_ptr, A.col_idx, leaf)
+    D = 0 if n <= leaf else int(np.ceil(np.log2(n / leaf)))
+    assert t.depth == D and len(t.leaf_dofs) == 2 ** D
+    assert np.array_equal(np.sort(np.concatenate(t.leaf_dofs)), np.arange(n))
+    sizes = {n}
+    for _ in range(D):
+        sizes = {h for s in sizes for h in (s // 2, s - s // 2)}
+    assert {d.size for d in t.leaf_dofs} <= sizes
+    if D >= 1 and n >= 200:
+        rows = np.repeat(np.arange(n), np.diff(A.row_ptr))
+        left = np.zeros(n, dtype=bool)
+        for d in t.leaf_dofs[: len(t.leaf_dofs) // 2]:
+            left[d] = True
+        cut = np.count_nonzero(left[rows] != left[A.col_idx])
+        perm = np.random.default_rng(0).permutation(n)
+        rnd = np.zeros(n, dtype=bool)
+        rnd[perm[: n // 2]] = True
+        cut_random = np.count_nonzero(rnd[rows] != rnd[A.col_idx])
+        assert cut < 0.5 * cut_random, (cut, cut_random)
+
+
+def test_algebraic_tree_components_and_exact_mode():
+    """A graph of two components: breadth-first orders take the component of
+    the lowest vertex first (the root's left half holds 50 of the first
+    component's 60 vertices, the right half the rest and all of the second);
+    and the exact mode on an ungridded input still
+    reproduces the dense solve."""
+    from workloads import random_geometric_spd
+
+    A1 = random_geometric_spd(np.random.default_rng(5), 60)
+    A2 = random_geometric_spd(np.random.default_rng(6), 40)
+    n = A1.n + A2.n
+    rp = np.concatenate([A1.row_ptr, A2.row_ptr[1:] + A1.nnz])
+    ci = np.concatenate([A1.col_idx, A2.col_idx + A1.n]).astype(np.int32)
+    va = np.concatenate([A1.val, A2.val])
+    t = O.build_tree_algebraic(rp, ci, 25)
+    first = set(np.concatenate(t.leaf_dofs[:2]).tolist())
+    assert len(first) == 50 and first <= set(range(60))
+    assert set(range(60, 100)) <= set(np.concatenate(t.leaf_dofs[2:]).tolist())
+    A = type(A1)(n, rp, ci, va)
+    fo = O.factor(rp, ci, va, None, 16, 0.0, True)
+    b = np.random.default_rng(0).uniform(-1, 1, n)
+    assert _relres(A, O.solve(fo, b), b) < 1e-12

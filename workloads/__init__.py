@@ -30,4 +30,5 @@ from .pde import (  # noqa: F401
     random_spd_blocks,
     random_nonsym_dd,
     one_sided_dd,
+    random_geometric_spd,
 )

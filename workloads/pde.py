@@ -205,6 +205,50 @@ def vc_poisson3d(rng: np.random.Generator, side: int, dev_cells: float = 4.0) ->
     return diffusion3d_from_coeff(quantized_field3d(rng, side, side, side, dev_cells))
 
 
+def random_geometric_spd(rng: np.random.Generator, n: int, degree: float = 8.0, shift: float = 0.05,
+                         nonsym: float = 0.0) -> CSR:
+    """An unstructured sparse matrix with no grid: n random points in the unit
+    square, numbered in random order, coupled when closer than the radius
+    that gives about ``degree`` neighbours each; weights w_ij = 1 + u_ij
+    (u_ij uniform [0, 1)).  The matrix is the weighted graph Laplacian plus
+    ``shift`` times its diagonal (symmetric positive definite); with
+    nonsym > 0 every coupling a_ij is scaled by (1 + nonsym v_ij), v_ij
+    uniform [-1, 1) drawn per direction (then diagonally dominant by rows)."""
+    pts = rng.uniform(0.0, 1.0, (n, 2))
+    r = math.sqrt(degree / (math.pi * n))
+    cell = np.floor(pts / r).astype(np.int64)
+    ncell = int(math.ceil(1.0 / r)) + 1
+    key = cell[:, 0] * ncell + cell[:, 1]
+    order = np.argsort(key, kind="stable")
+    rows, cols = [], []
+    buckets = {}
+    for i in order:
+        buckets.setdefault(int(key[i]), []).append(int(i))
+    for i in range(n):
+        cx, cy = cell[i]
+        for dx in (-1, 0, 1):
+            for dy in (-1, 0, 1):
+                for j in buckets.get(int((cx + dx) * ncell + (cy + dy)), ()):
+                    if j > i and np.sum((pts[i] - pts[j]) ** 2) < r * r:
+                        rows.append(i)
+                        cols.append(j)
+    rows = np.array(rows, dtype=np.int64)
+    cols = np.array(cols, dtype=np.int64)
+    w = 1.0 + rng.uniform(0.0, 1.0, rows.size)
+    R = np.concatenate([rows, cols])
+    C = np.concatenate([cols, rows])
+    V = -np.concatenate([w, w])
+    if nonsym > 0:
+        V = V * (1.0 + nonsym * rng.uniform(-1.0, 1.0, V.size))
+    diag = np.zeros(n)
+    np.add.at(diag, R, -V)
+    diag = diag * (1.0 + shift) + shift
+    R = np.concatenate([R, np.arange(n)])
+    C = np.concatenate([C, np.arange(n)])
+    V = np.concatenate([V, diag])
+    return _coo_to_csr(n, R, C, V)
+
+
 def convdiff2d_upwind(side: int, peclet: float, theta: float) -> CSR:
     """-Laplace(u) + b.grad(u) on the unit square, first-order upwind, h = 1/(side+1),
     b = Pe (cos theta, sin theta), scaled by h^2 (nonsymmetric, diagonally dominant)."""
