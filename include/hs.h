@@ -437,11 +437,19 @@ int hs_server_stats_get(hs_server_t S, hs_server_stats* out);
  * factorizations.  NULL is ignored. */
 void hs_server_destroy(hs_server_t S);
 
-/* Install the device allocator used for all library-owned memory.
- * alloc(bytes, ctx) returns a device pointer or NULL; free(ptr, ctx).  Pass
- * NULLs to go back to hipMalloc / hipFree.  Must not be called while a
- * factorization exists. */
-int hs_set_allocator(void* (*alloc_fn)(size_t, void*), void (*free_fn)(void*, void*), void* ctx);
+/* Install a stream-ordered device allocator for all library-owned memory of
+ * later factorizations (their level stores, records, workspaces and solve
+ * vectors).  alloc_fn(bytes, hip_stream, ctx) returns device memory that the
+ * library uses on hip_stream (the stream of the call that needs it), or NULL
+ * (HS_ERR_NOMEM); free_fn(ptr, hip_stream, ctx) takes it back, hip_stream
+ * being the stream it was allocated for.  Before free_fn the library has put
+ * every use of the buffer on that stream, or synchronised the device, so an
+ * allocator that gives the block to later work on the same stream without a
+ * wait (PyTorch's caching allocator does) is safe.  Each buffer goes back to
+ * the allocator that gave it.  NULLs: back to the built-in allocator (HIP's
+ * stream-ordered pool).  Both functions or neither, else HS_ERR_ARG; while
+ * any factorization exists, HS_ERR_ARG. */
+int hs_set_allocator(void* (*alloc_fn)(size_t, void*, void*), void (*free_fn)(void*, void*, void*), void* ctx);
 
 /* ---- kernel-variant thresholds ----------------------------------------- */
 

@@ -21,5 +21,7 @@ from ._lib import (  # noqa: F401
     profile_reset,
     profile_select,
     strerror,
+    torch_allocator_installed,
+    use_torch_allocator,
     version,
 )

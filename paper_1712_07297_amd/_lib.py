@@ -150,7 +150,7 @@ _SIGS = {
     "hs_symbolic_leaves": (ctypes.c_int, [_P, _PI32, _PI32]),
     "hs_symbolic_arrays": (ctypes.c_int, [_P, _I32, _PI32, _PI32, _PI32, _PI32, _PI32, _PI32, _PI32, _PI32]),
     "hs_symbolic_free": (None, [_P]),
-    "hs_set_allocator": (ctypes.c_int, [_P, _P, _P]),
+    "hs_set_allocator": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, _P]),
     "hs_profile_enable": (ctypes.c_int, [_I32]),
     "hs_profile_reset": (ctypes.c_int, []),
     "hs_profile_select": (ctypes.c_int, [ctypes.c_char_p]),
@@ -173,18 +173,76 @@ def header_functions() -> list:
 
 
 def lib() -> ctypes.CDLL:
-    """Load libhs.so (built by paper_1712_07297_amd.build); raises if absent."""
+    """Load libhs.so (built by paper_1712_07297_amd.build); raises if absent.
+    With a GPU visible, the library's device memory then comes from PyTorch's
+    caching allocator (use_torch_allocator) unless HS_ALLOCATOR=hip."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1712_07297_amd.build`")
+        want_torch = os.environ.get("HS_ALLOCATOR", "torch") == "torch" and _torch_gpu()
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in _SIGS.items():
             fn = getattr(L, name)
             fn.restype = res
             fn.argtypes = args
         _lib = L
+        if want_torch:
+            use_torch_allocator(True)
     return _lib
+
+
+def _torch_gpu() -> bool:
+    try:
+        import torch
+    except ImportError:
+        return False
+    return torch.cuda.is_available()
+
+
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+_torch_callbacks = None  # (alloc, free) kept alive while installed
+
+
+def _torch_alloc(nbytes, stream, ctx):
+    import torch
+
+    try:
+        return torch.cuda.caching_allocator_alloc(int(nbytes), torch.cuda.current_device(), int(stream or 0))
+    except Exception:  # out of memory: the library reports HS_ERR_NOMEM
+        return None
+
+
+def _torch_free(ptr, stream, ctx):
+    try:
+        import torch
+
+        torch.cuda.caching_allocator_delete(int(ptr))
+    except Exception:  # interpreter shutdown: the process's memory goes with it
+        pass
+
+
+def use_torch_allocator(on: bool = True) -> None:
+    """Give the library's device memory (level stores, records, workspaces,
+    solve vectors) from PyTorch's caching allocator, on the stream each call
+    runs on (hs_set_allocator), so that the library and torch share one cache
+    and repeated factorizations reuse blocks instead of mapping memory; off:
+    HIP's stream-ordered pool.  No factorization may exist (HsError)."""
+    global _torch_callbacks
+    L = lib()
+    if on:
+        cbs = (_ALLOC_FN(_torch_alloc), _FREE_FN(_torch_free))
+        _check(L.hs_set_allocator(ctypes.cast(cbs[0], ctypes.c_void_p), ctypes.cast(cbs[1], ctypes.c_void_p), None),
+               "hs_set_allocator")
+        _torch_callbacks = cbs
+    else:
+        _check(L.hs_set_allocator(None, None, None), "hs_set_allocator")
+        _torch_callbacks = None
+
+
+def torch_allocator_installed() -> bool:
+    return _torch_callbacks is not None
 
 
 def _check(code: int, what: str) -> int:

@@ -49,26 +49,23 @@ int fail_with(int code, const char* msg) { return fail(code, msg); }
 
 // --------------------------------------------------------------- allocator
 
-static void* (*g_alloc_fn)(size_t, void*) = nullptr;
-static void (*g_free_fn)(void*, void*) = nullptr;
+// An installed allocator is stream-ordered: alloc(bytes, stream, ctx) gives
+// memory for use on `stream`, free(ptr, stream, ctx) takes it back for reuse
+// by later work on that stream.
+static void* (*g_alloc_fn)(size_t, void*, void*) = nullptr;
+static void (*g_free_fn)(void*, void*, void*) = nullptr;
 static void* g_alloc_ctx = nullptr;
+static std::atomic<int> g_live_factors{0};  // the allocator may change only while this is 0
 
-static void* dev_alloc(size_t bytes) {
+static void* dev_alloc(size_t bytes, hipStream_t st) {
     if (bytes == 0) bytes = 256;
-    if (g_alloc_fn) return g_alloc_fn(bytes, g_alloc_ctx);
+    if (g_alloc_fn) return g_alloc_fn(bytes, (void*)st, g_alloc_ctx);
     void* p = nullptr;
     if (hipMalloc(&p, bytes) != hipSuccess) {
         (void)hipGetLastError();
         return nullptr;
     }
     return p;
-}
-static void dev_free(void* p) {
-    if (!p) return;
-    if (g_free_fn)
-        g_free_fn(p, g_alloc_ctx);
-    else
-        (void)hipFree(p);
 }
 
 // Stream-ordered allocation: inside an entry point (StreamScope) library
@@ -135,10 +132,14 @@ struct DevBuf {
     ByteAccount* acct = nullptr;
     bool pooled = false;
     hipStream_t stream = nullptr;
+    void (*free_fn)(void*, void*, void*) = nullptr;  // the installed allocator that gave p, if any
+    void* free_ctx = nullptr;
     DevBuf() = default;
     DevBuf(const DevBuf&) = delete;
     DevBuf& operator=(const DevBuf&) = delete;
-    DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes), acct(o.acct), pooled(o.pooled), stream(o.stream) {
+    DevBuf(DevBuf&& o) noexcept
+        : p(o.p), bytes(o.bytes), acct(o.acct), pooled(o.pooled), stream(o.stream), free_fn(o.free_fn),
+          free_ctx(o.free_ctx) {
         o.p = nullptr;
         o.bytes = 0;
         o.acct = nullptr;
@@ -151,6 +152,8 @@ struct DevBuf {
             acct = o.acct;
             pooled = o.pooled;
             stream = o.stream;
+            free_fn = o.free_fn;
+            free_ctx = o.free_ctx;
             o.p = nullptr;
             o.bytes = 0;
             o.acct = nullptr;
@@ -166,14 +169,20 @@ struct DevBuf {
                 if (!t_device_synced) device_sync();
                 (void)hipFreeAsync(p, nullptr);
             }
-        } else {
-            dev_free(p);
+        } else if (p && free_fn) {
+            // an installed allocator may hand the block to the next request on
+            // its stream at once: every use must be ordered on that stream
+            if (!(t_stream_set && t_stream == stream) && !t_device_synced) device_sync();
+            free_fn(p, (void*)stream, free_ctx);
+        } else if (p) {
+            (void)hipFree(p);
         }
         if (acct) acct->held -= (int64_t)bytes;
         p = nullptr;
         bytes = 0;
         acct = nullptr;
         pooled = false;
+        free_fn = nullptr;
     }
     bool alloc(size_t n) {
         release();
@@ -186,7 +195,10 @@ struct DevBuf {
             pooled = p != nullptr;
             stream = t_stream;
         } else {
-            p = dev_alloc(n);
+            stream = t_stream_set ? t_stream : nullptr;
+            p = dev_alloc(n, stream);
+            free_fn = g_alloc_fn ? g_free_fn : nullptr;
+            free_ctx = g_alloc_ctx;
         }
         bytes = p ? n : 0;
         if (p && t_acct) {
@@ -380,6 +392,10 @@ struct Config {
 }  // namespace hs
 
 struct hs_factor_s {
+    struct Live {  // counts existing factorizations; first member, so destroyed after every buffer
+        Live() { ++hs::g_live_factors; }
+        ~Live() { --hs::g_live_factors; }
+    } live;
     hs::ByteAccount acct;                 // first member: outlives every buffer below
     int64_t n = 0;
     hs_opts opts{};
@@ -2117,8 +2133,9 @@ int hs_symbolic_arrays(hs_symbolic_t S, int32_t level, int32_t* colors, int32_t*
 
 void hs_symbolic_free(hs_symbolic_t S) { delete S; }
 
-int hs_set_allocator(void* (*alloc_fn)(size_t, void*), void (*free_fn)(void*, void*), void* ctx) {
+int hs_set_allocator(void* (*alloc_fn)(size_t, void*, void*), void (*free_fn)(void*, void*, void*), void* ctx) {
     if ((alloc_fn == nullptr) != (free_fn == nullptr)) return fail(HS_ERR_ARG, "give both functions or neither");
+    if (g_live_factors.load() != 0) return fail(HS_ERR_ARG, "factorizations still exist");
     g_alloc_fn = alloc_fn;
     g_free_fn = free_fn;
     g_alloc_ctx = ctx;
