@@ -488,6 +488,12 @@ int hs_set_allocator(void* (*alloc_fn)(size_t, void*, void*), void (*free_fn)(vo
  *                                  always Householder QR)
  *   dense_panel      128, 16..128  panel width of the dense LU of a complete
  *                                  level (Alg. 1, final dense factorization)
+ *   apply_fwd        0, 0..2       forward step of the solve (Alg. 2) per
+ *                                  colour: 1 one launch whose neighbour
+ *                                  workgroups each form z_s[:f] again; 2 two
+ *                                  launches (z_s once, then the neighbour
+ *                                  updates); 0 two launches where the first
+ *                                  would re-read more than twice T_L'
  *   compression      0, 0..2       rank revelation (Eq. lra): 0 the
  *                                  pivoted QR of F^T under a rank cap or
  *                                  below qrcp_below_eps, else the Gram

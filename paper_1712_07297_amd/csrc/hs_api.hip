@@ -385,6 +385,7 @@ struct LevelData {
 struct Config {
     Knobs kn{LDS_M, TRI_MFMA_MAX, TRI_MFMA_MAX12, 64, 128, TRI_MFMA_MAX, GRAM_SPLITS_MAX, 256, 1024, 1, 0};
     int dense_panel = 128;
+    int apply_fwd = 0;              // forward solve step: 0 by cost, 1 one launch, 2 two launches
     int compression = 0;            // rank revelation: 0 by eps and cap, 1 pivoted QR, 2 Gram
     double qrcp_below_eps = 1e-5;   // 0: pivoted QR of F^T below this eps (or under a rank cap)
 };
@@ -482,6 +483,7 @@ static std::vector<ConfigEntry> config_table(Config& c) {
         {"schur_noff_max", 0, 1024, &c.kn.schur_noff_max, nullptr},
         {"cholqr", 0, 1, &c.kn.cholqr, nullptr},
         {"dense_panel", 16, 128, &c.dense_panel, nullptr},
+        {"apply_fwd", 0, 2, &c.apply_fwd, nullptr},
         {"compression", 0, 2, &c.compression, nullptr},
         {"qrcp_below_eps", 0, 1, nullptr, &c.qrcp_below_eps},
     };
@@ -1305,15 +1307,28 @@ static int factor_impl(hs_factor_s* F, int nsys, const hs_csr* A, const hs_geome
                 std::vector<int64_t> po;
                 std::vector<int> pre(1, 0), ge0, ge1;
                 int64_t acc = 0;
+                // forward step in one launch: every neighbour-row workgroup
+                // forms z_s[:f] = T_L'[:f] y_s again (f m reads each); in two,
+                // z_s is formed once and read back
+                double own_elems = 0.0, reformed_elems = 0.0;
+                int max_nt = 0;
                 for (int i = 0; i < CH.n_t[t]; ++i) {
                     const int s = LD.order_host[CH.first + (t ? CH.n_t[0] : 0) + i];
                     const int f = LD.m[s] - LD.k[s];
+                    own_elems += (double)LD.m[s] * LD.m[s];
+                    int nt_s = 0;
+                    for (int e = S.adj_ptr[s]; e < S.adj_ptr[s + 1]; ++e) {
+                        const int a = S.adj[e];
+                        nt_s += S.pos[a] < S.pos[s] ? LD.k[a] : LD.m[a];
+                    }
+                    max_nt = std::max(max_nt, nt_s);
                     int ng = 0;
                     if (LD.m[s] > 0 && f > 0) {
                         int cols = 0;
                         for (int e = S.adj_ptr[s]; e < S.adj_ptr[s + 1]; ++e) {
                             const int a = S.adj[e];
                             const int ca = S.pos[a] < S.pos[s] ? LD.k[a] : LD.m[a];
+                            reformed_elems += (double)((ca + 63) / 64) * f * LD.m[s];
                             const bool open = ng > 0 && ge1.back() == e;
                             if (open && cols + ca <= SOLVE_GROUP_COLS && e - ge0.back() < SOLVE_GROUP_ENTRIES) {
                                 ge1.back() = e + 1;
@@ -1333,6 +1348,8 @@ static int factor_impl(hs_factor_s* F, int nsys, const hs_csr* A, const hs_geome
                 po.push_back(acc);
                 CH.part_total[t] = acc;
                 CH.sol[t].grp_total = pre.back();
+                CH.sol[t].fwd_split = F->cfg.apply_fwd == 2 || (F->cfg.apply_fwd == 0 && reformed_elems > 2.0 * own_elems);
+                CH.sol[t].max_nt = max_nt;
                 LD.part_max = std::max(LD.part_max, acc);
                 o_grp[c][t] = {sb.add(po), sb.add(pre), sb.add(ge0), sb.add(ge1)};
             }

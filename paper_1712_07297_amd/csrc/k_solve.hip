@@ -36,26 +36,37 @@ __device__ inline T* tile_buf(double* after) {
 
 // ---------------------------------------------------------------- forward
 
+// rows of a cluster's own products per workgroup (the split forward step
+// and the backward step)
+constexpr int UROWS = 64;
+
+// z_s = T_L' y_s, rows r0 .. r0 + 63 of cluster s = clist[blockIdx.y] per
+// workgroup (blockIdx.x = r0 / 64); every row's sum runs over the whole of
+// y_s in ascending order, so the rows do not depend on the chunking.
 template <class T>
 __global__ void __launch_bounds__(WG) k_apply_fwd_t(SolveLevelDev S, ColourDev C, const double* __restrict__ y,
                                                     double* __restrict__ z, int nrhs) {
     extern __shared__ double ys[];  // max_m x nrhs, then the operand tile
-    const int s = C.clist[blockIdx.x];
+    const int s = C.clist[blockIdx.y];
     const int M = S.m[s];
-    if (M == 0) return;
+    const int r0 = blockIdx.x * UROWS;
+    if (r0 >= M) return;
+    const int nr = min(UROWS, M - r0);
     const int kk = S.k[s];
     const double* ysrc = y + S.seg[s] * nrhs;
     double* zdst = z + S.seg[s] * nrhs;
     const int tot = M * nrhs;
     if (kk == M) {
-        wg_stage(tot, [&](int x) { return ysrc[x]; }, [&](int x, double v) { zdst[x] = v; });
+        wg_stage(
+            nr * nrhs, [&](int x) { return ysrc[r0 + x % nr + (x / nr) * M]; },
+            [&](int x, double v) { zdst[r0 + x % nr + (x / nr) * M] = v; });
         return;
     }
     wg_stage(tot, [&](int x) { return ysrc[x]; }, [&](int x, double v) { ys[x] = v; });
-    const T* TL = srec<T>(S, s);
+    const T* TL = srec<T>(S, s) + r0;
     wg_rows_times<T>(
-        M, M, nrhs, [&](int i, int l) { return TL[i + (int64_t)l * M]; }, [&](int l, int r) { return ys[l + r * M]; },
-        tile_buf<T>(ys + (size_t)C.max_m * nrhs), [&](int i, int r, double v) { zdst[i + r * M] = v; });
+        nr, M, nrhs, [&](int i, int l) { return TL[i + (int64_t)l * M]; }, [&](int l, int r) { return ys[l + r * M]; },
+        tile_buf<T>(ys + (size_t)C.max_m * nrhs), [&](int i, int r, double v) { zdst[r0 + i + r * M] = v; });
 }
 
 static size_t tile_shmem(size_t doubles) { return doubles * sizeof(double) + TILE_BYTES; }
@@ -64,55 +75,93 @@ void launch_apply_fwd_t(const SolveLevelDev& S, const ColourDev& C, const double
                         hipStream_t st) {
     if (C.n == 0) return;
     const size_t sh = tile_shmem((size_t)C.max_m * nrhs);
+    const dim3 grid(std::max(1, (C.max_m + UROWS - 1) / UROWS), C.n);
     if (C.f32)
-        hipLaunchKernelGGL(k_apply_fwd_t<float>, dim3(C.n), dim3(WG), sh, st, S, C, y, z, nrhs);
+        hipLaunchKernelGGL(k_apply_fwd_t<float>, grid, dim3(WG), sh, st, S, C, y, z, nrhs);
     else
-        hipLaunchKernelGGL(k_apply_fwd_t<double>, dim3(C.n), dim3(WG), sh, st, S, C, y, z, nrhs);
+        hipLaunchKernelGGL(k_apply_fwd_t<double>, grid, dim3(WG), sh, st, S, C, y, z, nrhs);
 }
 
-constexpr int UROWS = 64;
+// Neighbour updates of the split forward step: y_a (or z_a's coarse part) -=
+// E_L[a] z_s[:f], one thread per neighbour row (rows row0 .. row0 + 255 of
+// cluster s = clist[blockIdx.y], packed in the order of s's neighbour list,
+// blockIdx.x = row0 / 256).  A row's sum runs over j ascending from zero, as
+// in the one-launch form, so both give the same bits; consecutive threads
+// read consecutive rows of each column of E_L.
+constexpr int NB_TAB = 512;  // neighbour entries of a cluster looked up in LDS
 
 template <class T>
 __global__ void __launch_bounds__(WG) k_apply_fwd_u(SolveLevelDev S, ColourDev C, double* __restrict__ y,
                                                     double* __restrict__ z, int nrhs) {
-    extern __shared__ double zf[];  // max_m x nrhs, then the operand tile
-    const int q = blockIdx.y;
-    const int ci = find_pre(C.nbr_pre, C.n, q);
-    const int s = C.clist[ci];
-    const int e = S.nbr_ptr[s] + (q - C.nbr_pre[ci]);
+    extern __shared__ double zf[];  // f x nrhs
+    __shared__ int noff_sh[NB_TAB];
+    const int s = C.clist[blockIdx.y];
     const int M = S.m[s];
-    const int kk = S.k[s];
-    const int f = M - kk;
+    const int f = M - S.k[s];
     if (M == 0 || f == 0) return;
+    const int row0 = blockIdx.x * WG;
+    const int nt = S.ntot[s];
+    if (row0 >= nt) return;
+    const int e0 = S.nbr_ptr[s], ne = S.nbr_ptr[s + 1] - e0;
+    const double* zs = z + S.seg[s] * nrhs;
+    wg_stage(
+        f * nrhs, [&](int x) { return zs[(x % f) + (x / f) * M]; }, [&](int x, double v) { zf[x] = v; });
+    const bool in_lds = ne <= NB_TAB;
+    if (in_lds)
+        for (int q = threadIdx.x; q < ne; q += blockDim.x) noff_sh[q] = S.nbr_noff[e0 + q];
+    __syncthreads();
+    const int i = row0 + threadIdx.x;
+    if (i >= nt) return;
+    // the entry holding packed row i: the last e with noff[e] <= i (entries
+    // with no rows share their offset with the next one, which holds i)
+    int lo = 0, hi = ne;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if ((in_lds ? noff_sh[mid] : S.nbr_noff[e0 + mid]) <= i)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    const int e = e0 + lo;
     const int a = S.nbr_id[e];
     const int before = S.nbr_before[e];
     const int ma = S.m[a];
     const int ca = before ? S.k[a] : ma;
-    const int r0 = blockIdx.x * UROWS;
-    if (r0 >= ca) return;
-    const int nr = min(UROWS, ca - r0);
-    const double* zs = z + S.seg[s] * nrhs;
-    wg_stage(
-        f * nrhs, [&](int x) { return zs[(x % f) + (x / f) * M]; }, [&](int x, double v) { zf[x] = v; });
+    const int li = i - (in_lds ? noff_sh[lo] : S.nbr_noff[e]);
+    double* tgt = (before ? z + S.seg[a] * nrhs + (ma - ca) : y + S.seg[a] * nrhs) + li;  // ld ma
     const int ncap = S.ncap[s];
-    const T* EL = srec<T>(S, s) + 2 * (int64_t)M * M + (int64_t)M * ncap + S.nbr_noff[e] + r0;  // ld ncap
-    double* tgt = (before ? z + S.seg[a] * nrhs + (ma - ca) : y + S.seg[a] * nrhs) + r0;    // ld ma
-    wg_rows_times<T>(
-        nr, f, nrhs, [&](int i, int j) { return EL[i + (int64_t)j * ncap]; }, [&](int j, int r) { return zf[j + r * f]; },
-        tile_buf<T>(zf + (size_t)C.max_m * nrhs), [&](int i, int r, double v) { tgt[i + (int64_t)r * ma] -= v; });
+    const T* EL = srec<T>(S, s) + 2 * (int64_t)M * M + (int64_t)M * ncap + i;  // row i, ld ncap
+    for (int r0 = 0; r0 < nrhs; r0 += 4) {
+        const int rr = min(4, nrhs - r0);
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        if (rr == 1) {
+#pragma unroll 8
+            for (int jj = 0; jj < f; ++jj) acc[0] = fma((double)EL[(int64_t)jj * ncap], zf[jj + r0 * f], acc[0]);
+        } else {
+#pragma unroll 4
+            for (int jj = 0; jj < f; ++jj) {
+                const double av = (double)EL[(int64_t)jj * ncap];
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    if (t < rr) acc[t] = fma(av, zf[jj + (r0 + t) * f], acc[t]);
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+            if (t < rr) tgt[(int64_t)(r0 + t) * ma] -= acc[t];
+    }
 }
 
 void launch_apply_fwd_u(const SolveLevelDev& S, const ColourDev& C, double* y, double* z, int nrhs, int max_m,
                         hipStream_t st) {
-    if (C.nbr_total == 0) return;
-    const int chunks = (C.max_nbr_m + UROWS - 1) / UROWS;
-    if (chunks == 0) return;
+    if (C.nbr_total == 0 || C.max_nt == 0) return;
     (void)max_m;
-    const size_t sh = tile_shmem((size_t)C.max_m * nrhs);
+    const size_t sh = (size_t)C.max_m * nrhs * sizeof(double);
+    const dim3 grid((C.max_nt + WG - 1) / WG, C.n);
     if (C.f32)
-        hipLaunchKernelGGL(k_apply_fwd_u<float>, dim3(chunks, C.nbr_total), dim3(WG), sh, st, S, C, y, z, nrhs);
+        hipLaunchKernelGGL(k_apply_fwd_u<float>, grid, dim3(WG), sh, st, S, C, y, z, nrhs);
     else
-        hipLaunchKernelGGL(k_apply_fwd_u<double>, dim3(chunks, C.nbr_total), dim3(WG), sh, st, S, C, y, z, nrhs);
+        hipLaunchKernelGGL(k_apply_fwd_u<double>, grid, dim3(WG), sh, st, S, C, y, z, nrhs);
 }
 
 // Forward step of a colour in one launch: workgroups (x, q) for q below the
@@ -179,7 +228,7 @@ constexpr size_t FWD_FUSED_MAX_LDS = 150 * 1024;
 void launch_apply_fwd(const SolveLevelDev& S, const ColourDev& C, double* y, double* z, int nrhs, hipStream_t st) {
     if (C.n == 0) return;
     const size_t sh = tile_shmem(2 * (size_t)C.max_m * nrhs);
-    if (sh > FWD_FUSED_MAX_LDS) {
+    if (C.fwd_split || sh > FWD_FUSED_MAX_LDS) {
         launch_apply_fwd_t(S, C, y, z, nrhs, st);
         launch_apply_fwd_u(S, C, y, z, nrhs, C.max_nbr_m, st);
         return;
@@ -194,16 +243,18 @@ void launch_apply_fwd(const SolveLevelDev& S, const ColourDev& C, double* y, dou
 
 // --------------------------------------------------------------- backward
 
-// One workgroup per neighbour group of a cluster: part = E_R[:, cols] x over
-// the group's columns (consecutive in E_R), each sum from zero in column order.
-// The x values of a column chunk are gathered into LDS beside the E_R tile.
-constexpr int XBUF_DOUBLES = 4096;
+// part = E_R[:, cols] x over the group's columns: the four waves take four
+// consecutive slices of the columns, each lane one row of E_R (consecutive
+// lanes read consecutive rows of a column), and the four slice sums are added
+// in slice order.  The x values of the group are gathered into LDS first.
+constexpr int BWD_XCOLS = 512;   // columns of x held in LDS per pass (times 4 right-hand sides)
 
 template <class T>
 __global__ void __launch_bounds__(WG) k_apply_bwd_acc(SolveLevelDev S, ColourDev C, const double* __restrict__ z,
                                                       const double* __restrict__ out, double* __restrict__ part,
                                                       const int64_t* __restrict__ part_off, int nrhs) {
-    extern __shared__ double xsb[];  // XBUF_DOUBLES, then the E_R tile
+    __shared__ double xs[4 * BWD_XCOLS];
+    __shared__ double red[3][64][4];
     __shared__ int tab_c[SOLVE_GROUP_ENTRIES + 1];
     __shared__ int tab_ld[SOLVE_GROUP_ENTRIES];
     __shared__ const double* tab_src[SOLVE_GROUP_ENTRIES];
@@ -214,7 +265,7 @@ __global__ void __launch_bounds__(WG) k_apply_bwd_acc(SolveLevelDev S, ColourDev
     const int f = M - S.k[s];
     if (M == 0 || f == 0) return;
     const int e0 = C.grp_e0[g], e1 = C.grp_e1[g], ne = e1 - e0;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     if (tid < ne) {
         const int e = e0 + tid;
         const int a = S.nbr_id[e];
@@ -230,57 +281,56 @@ __global__ void __launch_bounds__(WG) k_apply_bwd_acc(SolveLevelDev S, ColourDev
     const int ncols = tab_c[ne];
     const T* ER = srec<T>(S, s) + 2 * (int64_t)M * M + (int64_t)S.nbr_noff[e0] * M;  // ld M
     double* dst = part + part_off[g] * nrhs;                                           // f x nrhs
-    T* abuf = tile_buf<T>(xsb + XBUF_DOUBLES);
-    constexpr int ABUF_N = TILE_BYTES / (int)sizeof(T);
-    const int RR = min(nrhs, OUT_CAP);
-    const int RJ = max(1, min(f, OUT_CAP / RR));
-    for (int r0 = 0; r0 < nrhs; r0 += RR) {
-        const int rr = min(RR, nrhs - r0);
-        for (int j0 = 0; j0 < f; j0 += RJ) {
-            const int rj = min(RJ, f - j0);
-            const int CC = max(1, min(max(ncols, 1), min(ABUF_N / rj, XBUF_DOUBLES / rr)));
-            double acc[OUT_PER_THREAD];
-#pragma unroll
-            for (int t = 0; t < OUT_PER_THREAD; ++t) acc[t] = 0.0;
-            for (int c0 = 0; c0 < ncols; c0 += CC) {
-                const int cc = min(CC, ncols - c0);
+    for (int r0 = 0; r0 < nrhs; r0 += 4) {
+        const int rr = min(4, nrhs - r0);
+        for (int j0 = 0; j0 < f; j0 += 64) {
+            const int j = j0 + lane;
+            double acc[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int c0 = 0; c0 < ncols; c0 += BWD_XCOLS) {
+                const int cc = min(BWD_XCOLS, ncols - c0);
                 __syncthreads();
-                wg_stage(
-                    rj * cc, [&](int x) { return ER[(j0 + x % rj) + (int64_t)(c0 + x / rj) * M]; },
-                    [&](int x, T v) { abuf[x] = v; });
-                wg_stage(
-                    cc * rr,
-                    [&](int x) {
-                        const int c = c0 + x % cc, r = r0 + x / cc;
-                        int lo = 0, hi = ne;  // the entry holding column c: tab_c[lo] <= c < tab_c[lo + 1]
-                        while (hi - lo > 1) {
-                            const int mid = (lo + hi) >> 1;
-                            if (tab_c[mid] <= c)
-                                lo = mid;
-                            else
-                                hi = mid;
-                        }
-                        return tab_src[lo][(c - tab_c[lo]) + (int64_t)r * tab_ld[lo]];
-                    },
-                    [&](int x, double v) { xsb[x] = v; });
+                for (int x = tid; x < cc * rr; x += WG) {
+                    const int c = c0 + x % cc, r = r0 + x / cc;
+                    int lo = 0, hi = ne;  // the entry holding column c: tab_c[lo] <= c < tab_c[lo + 1]
+                    while (hi - lo > 1) {
+                        const int mid = (lo + hi) >> 1;
+                        if (tab_c[mid] <= c)
+                            lo = mid;
+                        else
+                            hi = mid;
+                    }
+                    xs[x] = tab_src[lo][(c - tab_c[lo]) + (int64_t)r * tab_ld[lo]];
+                }
                 __syncthreads();
-#pragma unroll
-                for (int t = 0; t < OUT_PER_THREAD; ++t) {
-                    const int x = tid + t * WG;
-                    if (x < rj * rr) {
-                        const int j = x % rj, r = x / rj;
-                        double a = acc[t];
+                // this wave's slice of the pass's columns
+                const int q0 = (int)(((int64_t)cc * w) / 4), q1 = (int)(((int64_t)cc * (w + 1)) / 4);
+                if (j < f) {
+                    const T* col = ER + j + (int64_t)c0 * M;
+                    if (rr == 1) {
+#pragma unroll 8
+                        for (int q = q0; q < q1; ++q) acc[0] = fma((double)col[(int64_t)q * M], xs[q], acc[0]);
+                    } else {
 #pragma unroll 4
-                        for (int l = 0; l < cc; ++l) a = fma((double)abuf[j + l * rj], xsb[l + r * cc], a);
-                        acc[t] = a;
+                        for (int q = q0; q < q1; ++q) {
+                            const double av = (double)col[(int64_t)q * M];
+#pragma unroll
+                            for (int t = 0; t < 4; ++t)
+                                if (t < rr) acc[t] = fma(av, xs[q + t * cc], acc[t]);
+                        }
                     }
                 }
             }
+            if (w > 0)
 #pragma unroll
-            for (int t = 0; t < OUT_PER_THREAD; ++t) {
-                const int x = tid + t * WG;
-                if (x < rj * rr) dst[(j0 + x % rj) + (int64_t)(r0 + x / rj) * f] = acc[t];
-            }
+                for (int t = 0; t < 4; ++t) red[w - 1][lane][t] = acc[t];
+            __syncthreads();
+            if (w == 0 && j < f)
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    if (t < rr)
+                        dst[j + (int64_t)(r0 + t) * f] =
+                            ((acc[t] + red[0][lane][t]) + red[1][lane][t]) + red[2][lane][t];
+            __syncthreads();
         }
     }
 }
@@ -288,33 +338,39 @@ __global__ void __launch_bounds__(WG) k_apply_bwd_acc(SolveLevelDev S, ColourDev
 void launch_apply_bwd_acc(const SolveLevelDev& S, const ColourDev& C, const double* z, const double* out,
                           double* part, const int64_t* part_off, int nrhs, hipStream_t st) {
     if (C.grp_total == 0) return;
-    const size_t sh = tile_shmem(XBUF_DOUBLES);
     if (C.f32)
-        hipLaunchKernelGGL(k_apply_bwd_acc<float>, dim3(C.grp_total), dim3(WG), sh, st, S, C, z, out, part, part_off,
+        hipLaunchKernelGGL(k_apply_bwd_acc<float>, dim3(C.grp_total), dim3(WG), 0, st, S, C, z, out, part, part_off,
                            nrhs);
     else
-        hipLaunchKernelGGL(k_apply_bwd_acc<double>, dim3(C.grp_total), dim3(WG), sh, st, S, C, z, out, part, part_off,
+        hipLaunchKernelGGL(k_apply_bwd_acc<double>, dim3(C.grp_total), dim3(WG), 0, st, S, C, z, out, part, part_off,
                            nrhs);
 }
 
 constexpr int BWD_POFF = 512;
 
+// out_s = T_R' v_s, v_s = [z_f - sum of the partials; z_c], rows r0 .. r0 + 63
+// per workgroup (blockIdx.x = r0 / 64, blockIdx.y = cluster of the colour);
+// every workgroup of a cluster forms the whole of v_s the same way.
 template <class T>
 __global__ void __launch_bounds__(WG) k_apply_bwd_t(SolveLevelDev S, ColourDev C, const double* __restrict__ z,
                                                     double* __restrict__ out, const double* __restrict__ part,
                                                     const int64_t* __restrict__ part_off, int nrhs) {
     extern __shared__ double vs[];  // max_m x nrhs, then the operand tile
-    const int ci = blockIdx.x;
+    const int ci = blockIdx.y;
     const int s = C.clist[ci];
     const int M = S.m[s];
-    if (M == 0) return;
+    const int r0 = blockIdx.x * UROWS;
+    if (r0 >= M) return;
+    const int nr = min(UROWS, M - r0);
     const int kk = S.k[s];
     const int f = M - kk;
     const double* zs = z + S.seg[s] * nrhs;
     double* os = out + S.seg[s] * nrhs;
     const int tot = M * nrhs;
     if (f == 0) {
-        wg_stage(tot, [&](int x) { return zs[x]; }, [&](int x, double v) { os[x] = v; });
+        wg_stage(
+            nr * nrhs, [&](int x) { return zs[r0 + x % nr + (x / nr) * M]; },
+            [&](int x, double v) { os[r0 + x % nr + (x / nr) * M] = v; });
         return;
     }
     // partials of the neighbour groups: offsets staged in LDS, the loads of
@@ -345,20 +401,21 @@ __global__ void __launch_bounds__(WG) k_apply_bwd_t(SolveLevelDev S, ColourDev C
         }
         if (q1 - q0c <= BWD_POFF) break;
     }
-    const T* TR = srec<T>(S, s) + (int64_t)M * M;  // T_R'
+    const T* TR = srec<T>(S, s) + (int64_t)M * M + r0;  // T_R', from row r0
     wg_rows_times<T>(
-        M, M, nrhs, [&](int i, int l) { return TR[i + (int64_t)l * M]; }, [&](int l, int r) { return vs[l + r * M]; },
-        tile_buf<T>(vs + (size_t)C.max_m * nrhs), [&](int i, int r, double v) { os[i + r * M] = v; });
+        nr, M, nrhs, [&](int i, int l) { return TR[i + (int64_t)l * M]; }, [&](int l, int r) { return vs[l + r * M]; },
+        tile_buf<T>(vs + (size_t)C.max_m * nrhs), [&](int i, int r, double v) { os[r0 + i + r * M] = v; });
 }
 
 void launch_apply_bwd_t(const SolveLevelDev& S, const ColourDev& C, const double* z, double* out,
                         const double* part, const int64_t* part_off, int nrhs, hipStream_t st) {
     if (C.n == 0) return;
     const size_t sh = tile_shmem((size_t)C.max_m * nrhs);
+    const dim3 grid(std::max(1, (C.max_m + UROWS - 1) / UROWS), C.n);
     if (C.f32)
-        hipLaunchKernelGGL(k_apply_bwd_t<float>, dim3(C.n), dim3(WG), sh, st, S, C, z, out, part, part_off, nrhs);
+        hipLaunchKernelGGL(k_apply_bwd_t<float>, grid, dim3(WG), sh, st, S, C, z, out, part, part_off, nrhs);
     else
-        hipLaunchKernelGGL(k_apply_bwd_t<double>, dim3(C.n), dim3(WG), sh, st, S, C, z, out, part, part_off, nrhs);
+        hipLaunchKernelGGL(k_apply_bwd_t<double>, grid, dim3(WG), sh, st, S, C, z, out, part, part_off, nrhs);
 }
 
 // ---------------------------------------------------------- level transfer

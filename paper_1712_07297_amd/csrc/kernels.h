@@ -32,6 +32,8 @@ struct ColourDev {
     const int* grp_e0 = nullptr;      // [grp_total] first neighbour entry of the group
     const int* grp_e1 = nullptr;      // [grp_total] one past its last entry
     int grp_total = 0;
+    int fwd_split = 0;                // forward step in two launches (own products, then neighbour updates)
+    int max_nt = 0;                   // most neighbour rows (current sizes) of a cluster of the colour
 };
 // neighbour groups of the backward sweep: at most this many columns of E_R
 // (unless one neighbour alone is wider) and this many entries

@@ -99,6 +99,9 @@ FORCED = [
     ("schur_offsets_in_memory", dict(schur_noff_max=0, schur_ptab_max=3), ["p3d", "nonsym"]),
     ("basis_by_householder", dict(cholqr=0), ["p3d", "nonsym"]),
     ("dense_panels_16", dict(dense_panel=16), ["p3d", "p2d_exact"]),
+    # forward solve step in one launch / in two
+    ("apply_one_launch", dict(apply_fwd=1), ["p3d", "nonsym", "p2d_exact"]),
+    ("apply_two_launches", dict(apply_fwd=2), ["p3d", "nonsym", "p2d_exact"]),
     # rank revelation by the pivoted Householder QR of F^T at eps >= 1e-5 (its
     # own kernel, k_qrcp; compared at the pivoted-QR bar, 1e-9 here)
     ("rank_by_pivoted_qr", dict(compression=1), ["p3d", "nonsym"]),
@@ -149,3 +152,20 @@ def test_noise_floor_decision(P, factor_of_floor):
     fo, F, st = compare_factor(P, A, (4, 4, 1), 4, 1e-6, True)
     assert (F.ranks(0)[1] == 0) == (factor_of_floor < 1.0)
     _check_solve(P, fo, F, A)
+
+
+@pytest.mark.parametrize("nrhs", [1, 5])
+def test_apply_launch_forms_bitwise(P, nrhs):
+    """The forward step in one launch (neighbour workgroups form z_s[:f]
+    again) and in two (z_s once), and the own products cut into 64-row
+    chunks: the same sums in the same order, so the solves agree bit for bit
+    (clusters up to 324 unknowns, several chunks each)."""
+    A = poisson3d(12, 12, 12)
+    b = torch.tensor(np.random.default_rng(9).uniform(-1, 1, (nrhs, A.n)), device="cuda")
+    xs = []
+    for mode in (0, 1, 2):
+        with knobs(P, apply_fwd=mode):
+            F = P.Factor(A.row_ptr, A.col_idx, A.val, (12, 12, 12), 1e-4, 200, symmetric=1)
+        xs.append(F.solve(b).cpu().numpy())
+        F.free()
+    assert np.array_equal(xs[0], xs[1]) and np.array_equal(xs[0], xs[2])
