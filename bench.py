@@ -257,8 +257,8 @@ def run_batch(args):
         print(f"batch {name}: {len(groups)} group(s), {per_unknown:.0f} B/unknown", file=sys.stderr, flush=True)
 
         def step(record):
-            for g in groups:
-                X, it, rel, ok, info = run_group(g, prec)
+            results = [run_group(g, prec) for g in groups]
+            for g, (X, it, rel, ok, info) in zip(groups, results):
                 if record is not None:
                     record["its"].append(it)
                     record["rels"].append(rel)
@@ -294,6 +294,7 @@ def run_batch(args):
         roof = roofline_from(P, pivot_family, label, "alu", traffic)
         P.profile_select("")
         P.profile_reset()
+        torch.cuda.empty_cache()  # hand cached blocks back before the next allocations
         apply = measure_apply(P, torch, groups[0], sys_dev, rhs, prec)
         print(f"batch {name}: apply {json.dumps(apply)}", file=sys.stderr, flush=True)
         # independent check of every system's final residual (device SpMV by torch, FP64)

@@ -259,8 +259,10 @@ struct ProfPending {
 };
 static std::vector<ProfPending> g_prof_pending;
 static std::vector<hipEvent_t> g_prof_pool;
+static std::mutex g_prof_mu;  // calls on several threads (serving workers, concurrent factorizations)
 
 static hipEvent_t prof_event() {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
     if (!g_prof_pool.empty()) {
         hipEvent_t e = g_prof_pool.back();
         g_prof_pool.pop_back();
@@ -286,6 +288,7 @@ struct ProfScope {
         if (g_prof_on && a) {
             hipEvent_t b = prof_event();
             (void)hipEventRecord(b, st);
+            std::lock_guard<std::mutex> lk(g_prof_mu);
             g_prof_pending.push_back({fam, a, b});
         }
     }
@@ -298,15 +301,24 @@ struct HostScope {
     explicit HostScope(int f) : fam(f), t0(std::chrono::steady_clock::now()) {}
     ~HostScope() {
         if (prof_timed(fam)) {
+            std::lock_guard<std::mutex> lk(g_prof_mu);
             g_prof[fam].seconds += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
             g_prof[fam].launches += 1;
         }
     }
 };
 
-// Read back finished intervals (the caller has synchronised the stream).
+// Read back finished intervals; those still running (another thread's
+// stream) stay pending.
 static void prof_flush() {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    std::vector<ProfPending> left;
     for (auto& p : g_prof_pending) {
+        if (hipEventQuery(p.b) != hipSuccess) {
+            (void)hipGetLastError();
+            left.push_back(p);
+            continue;
+        }
         float ms = 0.0f;
         if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
             g_prof[p.fam].seconds += ms * 1e-3;
@@ -317,7 +329,7 @@ static void prof_flush() {
         g_prof_pool.push_back(p.a);
         g_prof_pool.push_back(p.b);
     }
-    g_prof_pending.clear();
+    g_prof_pending.swap(left);
 }
 
 // ------------------------------------------------------------- level state
@@ -1225,6 +1237,7 @@ static int factor_impl(hs_factor_s* F, int nsys, const hs_csr* A, const hs_geome
             }
         if (g_prof_on) {
             prof_flush();
+            std::lock_guard<std::mutex> lk(g_prof_mu);
             for (int c = 0; c < LD.ncl; ++c) {
                 const double m = LD.m[c], kk = LD.k[c], f = m - kk, nt = ntot[c];
                 if (LD.m[c] == 0 || LD.dense[c]) continue;
@@ -2188,6 +2201,7 @@ int hs_profile_select(const char* families) {
 }
 
 int hs_profile_reset(void) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
     for (auto& f : g_prof) {
         f.launches = 0;
         f.seconds = f.bytes = f.flops = 0.0;
@@ -2198,6 +2212,8 @@ int hs_profile_reset(void) {
 
 int hs_profile_read(const char* family, int64_t* launches, double* seconds, double* bytes, double* flops) {
     if (!family) return fail(HS_ERR_ARG, "null family");
+    prof_flush();  // intervals finished since the last synchronisation of the library
+    std::lock_guard<std::mutex> lk(g_prof_mu);
     for (auto& f : g_prof)
         if (std::strcmp(f.name, family) == 0) {
             if (launches) *launches = f.launches;
