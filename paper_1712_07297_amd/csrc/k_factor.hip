@@ -351,226 +351,6 @@ __device__ int wg_pivoted_cholesky_ll(PW W, int M, double eps, int fixed_rank, P
     return kk;
 }
 
-// ================================================== pivoted Householder QR
-// Rank revelation by the truncated Householder QR with column pivoting of
-// F^T itself (Eq. lra, reading R4), for a rank cap or a small eps, where the
-// Gram route cannot resolve the weakest kept directions.  F (M x ncol: the
-// fill blocks B(s, t), then for a general matrix the B(t, s)^T) is gathered
-// into the cluster's workspace behind its slots, column major, ld M.  The
-// columns of F^T are the unknowns of s (rows of F) and its rows are the
-// columns of F, so a reflector of step j acts on columns j.. of F:
-//   norms  n_u = sum_{c >= j} F(u, c)^2, recomputed every step;
-//   pivot  the lowest position whose norm is within a relative 1e-10 of the
-//          largest (positions are exchanged as the pivots are chosen);
-//   stop   at the first |R_jj| <= eps |R_11|, at fixed_rank, or when every
-//          remaining norm is zero;
-//   H_j    LAPACK's larfg convention on x = F(u_p, j..); w_u = v^T F(u, j..),
-//          F(u, j..) -= tau w_u v; row u_p becomes (beta, 0, ...);
-//   sign   column j negated when beta < 0, so that R_jj > 0.
-// Afterwards F(u, j) = R(j, position of u) for j < k: the first k columns of
-// F are P R_k^T, written to the X slot; k goes to L.k[s].  Rows are spread
-// over the threads (RR rows at a time, GG column groups), every sum over the
-// column groups is added in group order.
-constexpr int QR_PART = 512;
-template <class T>
-__global__ void __launch_bounds__(WG) k_qrcp(LevelDev L, const int* __restrict__ clist) {
-    __shared__ int perm[MAX_M];     // position -> unknown
-    __shared__ int posof[MAX_M];    // unknown -> position
-    __shared__ double nrm[MAX_M];   // remaining norms of the unknowns
-    __shared__ double wt[MAX_M];    // tau w_u of the current step
-    __shared__ double part[QR_PART];
-    __shared__ double red[16];
-    __shared__ int ctl[4];          // pivot position, stop flag
-    const int s = clist[blockIdx.x];
-    const int tid = threadIdx.x;
-    const int M = L.m[s];
-    const int fc = L.fcols[s];
-    if (M == 0 || fc == 0 || L.eps <= 0.0) return;
-    const int ncol = L.symmetric ? fc : 2 * fc;
-    const int64_t MM = (int64_t)M * M;
-    double* ws = L.ws + L.ws_off[s];
-    double* X = ws + WS_X * MM;
-    double* Fw = ws + ws_slots(L.gram_splits) * MM;  // M x ncol, ld M
-    lds_f64* red_l = to_lds(red);
-    // ---- gather F
-    {
-        const int f0 = L.fill_ptr[s], nf = L.fill_ptr[s + 1] - f0;
-        int coff = 0;
-        for (int e = f0; e < f0 + nf; ++e) {
-            const int t = L.fill_id[e];
-            const int ct = cur_size(L, t, L.fill_before[e]);
-            if (ct == 0) continue;
-            const T* Bst = blk_t<T>(L, L.fill_bst[e]);  // M x ct, ld M
-            double* dst = Fw + (int64_t)coff * M;
-            wg_stage(M * ct, [&](int x) { return (double)Bst[x]; }, [&](int x, double v) { dst[x] = v; });
-            if (!L.symmetric) {
-                const int mt = L.m[t];
-                const T* Bts = blk_t<T>(L, L.fill_bts[e]);  // ct x M, ld m_t
-                double* dst2 = Fw + (int64_t)(fc + coff) * M;
-                wg_stage(
-                    M * ct, [&](int x) { return (double)Bts[(x / M) + (int64_t)(x % M) * mt]; },
-                    [&](int x, double v) { dst2[x] = v; });
-            }
-            coff += ct;
-        }
-    }
-    // ||A_ss||_F^2 for the noise floor (reading R12)
-    double ass2 = 0.0;
-    {
-        const T* Bss = blk_t<T>(L, L.diag_blk[s]);
-        wg_stage((int)MM, [&](int e) { return (double)Bss[e]; }, [&](int, double v) { ass2 = fma(v, v, ass2); });
-        ass2 = block_sum(ass2, red_l);
-    }
-    __syncthreads();
-    const int RR = M < WG ? M : WG;   // rows per pass
-    const int GG = WG / RR;           // column groups
-    const int r = tid % RR, g = tid / RR;
-    const bool active = g < GG;
-    // norms of every row over columns >= c0, summed over the groups in order
-    auto row_norms = [&](int c0) {
-        for (int u0 = 0; u0 < M; u0 += RR) {
-            const int u = u0 + r;
-            if (active && u < M) {
-                double acc = 0.0;
-                for (int c = c0 + g; c < ncol; c += GG) {
-                    const double v = Fw[u + (int64_t)c * M];
-                    acc = fma(v, v, acc);
-                }
-                part[g * RR + r] = acc;
-            }
-            __syncthreads();
-            if (g == 0 && u < M) {
-                double sum = 0.0;
-                for (int q = 0; q < GG; ++q) sum += part[q * RR + r];
-                nrm[u] = sum;
-            }
-            __syncthreads();
-        }
-    };
-    for (int u = tid; u < M; u += WG) {
-        perm[u] = u;
-        posof[u] = u;
-    }
-    row_norms(0);
-    double dmax = 0.0;
-    for (int u = tid; u < M; u += WG) dmax = fmax(dmax, nrm[u]);
-    dmax = block_max(dmax, red_l);
-    constexpr double floor_ = std::is_same<T, float>::value ? FILL_NOISE_FLOOR_F32 : FILL_NOISE_FLOOR;
-    int kk = 0;
-    if (!(dmax <= floor_ * floor_ * ass2)) {
-        double r11 = 0.0;
-        const int jmax = min(ncol, M);
-        for (int j = 0; j < jmax; ++j) {
-            // ---- pivot: lowest position within 1e-10 of the largest norm
-            if (tid < 64) {
-                double mx = -1.0;
-                for (int q = j + tid; q < M; q += 64) mx = fmax(mx, nrm[perm[q]]);
-                mx = wave_max(mx);
-                const double thr = (1.0 - 1e-10) * mx;
-                int cand = M;
-                for (int q = j + tid; q < M; q += 64)
-                    if (nrm[perm[q]] >= thr) {
-                        cand = q;
-                        break;
-                    }
-                cand = wave_min_int(cand);
-                if (tid == 0) {
-                    int stop = !(mx > 0.0);
-                    if (!stop) {
-                        const double rjj = sqrt(nrm[perm[cand]]);
-                        if (j == 0) r11 = rjj;
-                        stop = (rjj <= L.eps * r11) || (L.fixed_rank > 0 && j >= L.fixed_rank);
-                    }
-                    ctl[0] = cand;
-                    ctl[1] = stop;
-                    if (!stop && cand != j) {  // exchange positions j and cand
-                        const int a = perm[j], b = perm[cand];
-                        perm[j] = b;
-                        perm[cand] = a;
-                        posof[b] = j;
-                        posof[a] = cand;
-                    }
-                }
-            }
-            __syncthreads();
-            if (ctl[1]) break;
-            const int up = perm[j];
-            // ---- reflector of x = F(up, j..ncol)
-            double xn2 = 0.0;
-            for (int c = j + 1 + tid; c < ncol; c += WG) {
-                const double v = Fw[up + (int64_t)c * M];
-                xn2 = fma(v, v, xn2);
-            }
-            xn2 = block_sum(xn2, red_l);
-            const double alpha = Fw[up + (int64_t)j * M];
-            double tau = 0.0, beta = alpha, scale = 0.0;
-            if (xn2 != 0.0) {
-                const double nrm2 = hypot(alpha, sqrt(xn2));
-                beta = (alpha >= 0.0) ? -nrm2 : nrm2;
-                tau = (beta - alpha) / beta;
-                scale = 1.0 / (alpha - beta);
-            }
-            if (xn2 != 0.0)
-                for (int c = j + 1 + tid; c < ncol; c += WG) Fw[up + (int64_t)c * M] *= scale;  // v(c), v(j) = 1
-            __syncthreads();
-            // ---- w_u = v^T F(u, j..) for the rows still unpivoted, then the update
-            if (tau != 0.0) {
-                for (int u0 = 0; u0 < M; u0 += RR) {
-                    const int u = u0 + r;
-                    const bool live = active && u < M && posof[u] > j;
-                    if (active && u < M) {
-                        double acc = 0.0;
-                        if (live) {
-                            if (g == 0) acc = Fw[u + (int64_t)j * M];
-                            for (int c = j + 1 + g; c < ncol; c += GG)
-                                acc = fma(Fw[up + (int64_t)c * M], Fw[u + (int64_t)c * M], acc);
-                        }
-                        part[g * RR + r] = acc;
-                    }
-                    __syncthreads();
-                    if (g == 0 && u < M) {
-                        double sum = 0.0;
-                        for (int q = 0; q < GG; ++q) sum += part[q * RR + r];
-                        wt[u] = (posof[u] > j) ? tau * sum : 0.0;
-                    }
-                    __syncthreads();
-                }
-                for (int u0 = 0; u0 < M; u0 += RR) {
-                    const int u = u0 + r;
-                    if (active && u < M && posof[u] > j) {
-                        const double w = wt[u];
-                        if (g == 0) Fw[u + (int64_t)j * M] -= w;
-                        for (int c = j + 1 + g; c < ncol; c += GG)
-                            Fw[u + (int64_t)c * M] = fma(-w, Fw[up + (int64_t)c * M], Fw[u + (int64_t)c * M]);
-                    }
-                }
-                __syncthreads();
-            }
-            // ---- the pivot row becomes (beta, 0, ...); R_jj > 0
-            for (int c = j + 1 + tid; c < ncol; c += WG) Fw[up + (int64_t)c * M] = 0.0;
-            if (tid == 0) Fw[up + (int64_t)j * M] = beta;
-            __syncthreads();
-            if (beta < 0.0)
-                for (int u = tid; u < M; u += WG) Fw[u + (int64_t)j * M] = -Fw[u + (int64_t)j * M];
-            kk = j + 1;
-            __syncthreads();
-            row_norms(j + 1);
-        }
-    }
-    // ---- P R_k^T into the X slot; the rank for the pivot kernel
-    if (kk > 0 && kk < M)
-        wg_stage(M * kk, [&](int x) { return Fw[x]; }, [&](int x, double v) { X[x] = v; });
-    if (tid == 0) L.k[s] = kk;
-}
-
-void launch_qrcp(const LevelDev& L, const ColourDev& C, hipStream_t st) {
-    if (C.n == 0 || C.fill_total == 0) return;
-    if (C.f32)
-        hipLaunchKernelGGL(k_qrcp<float>, dim3(C.n), dim3(WG), 0, st, L, C.clist);
-    else
-        hipLaunchKernelGGL(k_qrcp<double>, dim3(C.n), dim3(WG), 0, st, L, C.clist);
-}
-
 // Orthonormal factor Q (M x k, positive diagonal R) of X = Q R by Cholesky
 // QR: G = Y^T Y = R^T R, R = D^{-1/2} U_G from the unpivoted LU G = L_G U_G
 // (D = diag U_G), Y <- Y R^{-1}.  One pass leaves an orthogonality error of
@@ -872,6 +652,262 @@ void launch_pivot(const LevelDev& L, const ColourDev& C, hipStream_t st) {
         else
             hipLaunchKernelGGL((k_pivot<false, double>), dim3(C.n), dim3(WG), scr_bytes, st, L, C.clist);
     }
+}
+
+// ================================================== pivoted Householder QR
+// Rank revelation by the truncated Householder QR with column pivoting of
+// F^T itself (Eq. lra, reading R4), for a rank cap or a small eps, where the
+// Gram route cannot resolve the weakest kept directions.  F (M x ncol: the
+// fill blocks B(s, t), then for a general matrix the B(t, s)^T) is gathered
+// into the cluster's workspace behind its slots, column major, ld M.  The
+// columns of F^T are the unknowns of s (rows of F) and its rows are the
+// columns of F, so a reflector of step j acts on columns j.. of F:
+//   norms  n_u = sum_{c >= j} F(u, c)^2, recomputed every step;
+//   pivot  the lowest position whose norm is within a relative 1e-10 of the
+//          largest (positions are exchanged as the pivots are chosen);
+//   stop   at the first |R_jj| <= eps |R_11|, at fixed_rank, or when every
+//          remaining norm is zero;
+//   H_j    LAPACK's larfg convention on x = F(u_p, j..); w_u = v^T F(u, j..),
+//          F(u, j..) -= tau w_u v; row u_p becomes (beta, 0, ...);
+//   sign   column j negated when beta < 0, so that R_jj > 0.
+// Afterwards F(u, j) = R(j, position of u) for j < k: the first k columns of
+// F are P R_k^T, written to the X slot; k goes to L.k[s].  Rows are spread
+// over the threads (RR rows at a time, GG column groups), every sum over the
+// column groups is added in group order.
+// One workgroup of QR_WG threads per cluster: the rows of F over lanes, its
+// columns over QR_WG / m groups (more threads per row shorten the per-thread
+// sums over the fill columns, the latency of every step).
+constexpr int QR_WG = 1024;
+constexpr int QR_PART = QR_WG;
+template <class T>
+__global__ void __launch_bounds__(QR_WG) k_qrcp(LevelDev L, const int* __restrict__ clist) {
+    __shared__ int perm[MAX_M];     // position -> unknown
+    __shared__ int posof[MAX_M];    // unknown -> position
+    __shared__ double nrm[MAX_M];   // remaining norms of the unknowns
+    __shared__ double wt[MAX_M];    // tau w_u of the current step
+    __shared__ double part[QR_PART];
+    __shared__ double red[16];
+    __shared__ int ctl[4];          // pivot position, stop flag
+    const int s = clist[blockIdx.x];
+    const int tid = threadIdx.x;
+    const int M = L.m[s];
+    const int fc = L.fcols[s];
+    if (M == 0 || fc == 0 || L.eps <= 0.0) return;
+    const int ncol = L.symmetric ? fc : 2 * fc;
+    const int64_t MM = (int64_t)M * M;
+    double* ws = L.ws + L.ws_off[s];
+    double* X = ws + WS_X * MM;
+    double* Fw = ws + ws_slots(L.gram_splits) * MM;  // M x ncol, ld M
+    lds_f64* red_l = to_lds(red);
+    // ---- gather F
+    {
+        const int f0 = L.fill_ptr[s], nf = L.fill_ptr[s + 1] - f0;
+        int coff = 0;
+        for (int e = f0; e < f0 + nf; ++e) {
+            const int t = L.fill_id[e];
+            const int ct = cur_size(L, t, L.fill_before[e]);
+            if (ct == 0) continue;
+            const T* Bst = blk_t<T>(L, L.fill_bst[e]);  // M x ct, ld M
+            double* dst = Fw + (int64_t)coff * M;
+            wg_stage(M * ct, [&](int x) { return (double)Bst[x]; }, [&](int x, double v) { dst[x] = v; });
+            if (!L.symmetric) {
+                const int mt = L.m[t];
+                const T* Bts = blk_t<T>(L, L.fill_bts[e]);  // ct x M, ld m_t
+                double* dst2 = Fw + (int64_t)(fc + coff) * M;
+                wg_stage(
+                    M * ct, [&](int x) { return (double)Bts[(x / M) + (int64_t)(x % M) * mt]; },
+                    [&](int x, double v) { dst2[x] = v; });
+            }
+            coff += ct;
+        }
+    }
+    // ||A_ss||_F^2 for the noise floor (reading R12)
+    double ass2 = 0.0;
+    {
+        const T* Bss = blk_t<T>(L, L.diag_blk[s]);
+        wg_stage((int)MM, [&](int e) { return (double)Bss[e]; }, [&](int, double v) { ass2 = fma(v, v, ass2); });
+        ass2 = block_sum(ass2, red_l);
+    }
+    __syncthreads();
+    const int RR = M < QR_WG ? M : QR_WG;   // rows per pass
+    const int GG = QR_WG / RR;           // column groups
+    const int r = tid % RR, g = tid / RR;
+    const bool active = g < GG;
+    // norms of every row over columns >= c0, summed over the groups in order
+    auto row_norms = [&](int c0) {
+        for (int u0 = 0; u0 < M; u0 += RR) {
+            const int u = u0 + r;
+            if (active && u < M) {
+                double acc = 0.0;
+#pragma unroll 8
+                for (int c = c0 + g; c < ncol; c += GG) {
+                    const double v = Fw[u + (int64_t)c * M];
+                    acc = fma(v, v, acc);
+                }
+                part[g * RR + r] = acc;
+            }
+            __syncthreads();
+            if (g == 0 && u < M) {
+                double sum = 0.0;
+                for (int q = 0; q < GG; ++q) sum += part[q * RR + r];
+                nrm[u] = sum;
+            }
+            __syncthreads();
+        }
+    };
+    for (int u = tid; u < M; u += QR_WG) {
+        perm[u] = u;
+        posof[u] = u;
+    }
+    row_norms(0);
+    double dmax = 0.0;
+    for (int u = tid; u < M; u += QR_WG) dmax = fmax(dmax, nrm[u]);
+    dmax = block_max(dmax, red_l);
+    constexpr double floor_ = std::is_same<T, float>::value ? FILL_NOISE_FLOOR_F32 : FILL_NOISE_FLOOR;
+    int kk = 0;
+    if (!(dmax <= floor_ * floor_ * ass2)) {
+        double r11 = 0.0;
+        const int jmax = min(ncol, M);
+        for (int j = 0; j < jmax; ++j) {
+            // ---- pivot: lowest position within 1e-10 of the largest norm
+            if (tid < 64) {
+                double mx = -1.0;
+                for (int q = j + tid; q < M; q += 64) mx = fmax(mx, nrm[perm[q]]);
+                mx = wave_max(mx);
+                const double thr = (1.0 - 1e-10) * mx;
+                int cand = M;
+                for (int q = j + tid; q < M; q += 64)
+                    if (nrm[perm[q]] >= thr) {
+                        cand = q;
+                        break;
+                    }
+                cand = wave_min_int(cand);
+                if (tid == 0) {
+                    int stop = !(mx > 0.0);
+                    if (!stop) {
+                        const double rjj = sqrt(nrm[perm[cand]]);
+                        if (j == 0) r11 = rjj;
+                        stop = (rjj <= L.eps * r11) || (L.fixed_rank > 0 && j >= L.fixed_rank);
+                    }
+                    ctl[0] = cand;
+                    ctl[1] = stop;
+                    if (!stop && cand != j) {  // exchange positions j and cand
+                        const int a = perm[j], b = perm[cand];
+                        perm[j] = b;
+                        perm[cand] = a;
+                        posof[b] = j;
+                        posof[a] = cand;
+                    }
+                }
+            }
+            __syncthreads();
+            if (ctl[1]) break;
+            const int up = perm[j];
+            // ---- reflector of x = F(up, j..ncol)
+            double xn2 = 0.0;
+            for (int c = j + 1 + tid; c < ncol; c += QR_WG) {
+                const double v = Fw[up + (int64_t)c * M];
+                xn2 = fma(v, v, xn2);
+            }
+            xn2 = block_sum(xn2, red_l);
+            const double alpha = Fw[up + (int64_t)j * M];
+            double tau = 0.0, beta = alpha, scale = 0.0;
+            if (xn2 != 0.0) {
+                const double nrm2 = hypot(alpha, sqrt(xn2));
+                beta = (alpha >= 0.0) ? -nrm2 : nrm2;
+                tau = (beta - alpha) / beta;
+                scale = 1.0 / (alpha - beta);
+            }
+            if (xn2 != 0.0)
+                for (int c = j + 1 + tid; c < ncol; c += QR_WG) Fw[up + (int64_t)c * M] *= scale;  // v(c), v(j) = 1
+            __syncthreads();
+            // ---- w_u = v^T F(u, j..) for the rows still unpivoted, then the update
+            if (tau != 0.0) {
+                for (int u0 = 0; u0 < M; u0 += RR) {
+                    const int u = u0 + r;
+                    const bool live = active && u < M && posof[u] > j;
+                    if (active && u < M) {
+                        double acc = 0.0;
+                        if (live) {
+                            if (g == 0) acc = Fw[u + (int64_t)j * M];
+#pragma unroll 8
+                            for (int c = j + 1 + g; c < ncol; c += GG)
+                                acc = fma(Fw[up + (int64_t)c * M], Fw[u + (int64_t)c * M], acc);
+                        }
+                        part[g * RR + r] = acc;
+                    }
+                    __syncthreads();
+                    if (g == 0 && u < M) {
+                        double sum = 0.0;
+                        for (int q = 0; q < GG; ++q) sum += part[q * RR + r];
+                        wt[u] = (posof[u] > j) ? tau * sum : 0.0;
+                    }
+                    __syncthreads();
+                }
+                // the update, with each row's remaining norm over columns >= j + 1
+                // summed as it is written (same columns, order and grouping as
+                // row_norms, so the same bits); eight columns' loads are issued
+                // before their stores
+                for (int u0 = 0; u0 < M; u0 += RR) {
+                    const int u = u0 + r;
+                    double acc = 0.0;
+                    if (active && u < M && posof[u] > j) {
+                        const double w = wt[u];
+                        if (g == 0) Fw[u + (int64_t)j * M] -= w;
+                        int c = j + 1 + g;
+                        for (; c + 7 * GG < ncol; c += 8 * GG) {
+                            double pv[8], fv[8];
+#pragma unroll
+                            for (int q = 0; q < 8; ++q) {
+                                pv[q] = Fw[up + (int64_t)(c + q * GG) * M];
+                                fv[q] = Fw[u + (int64_t)(c + q * GG) * M];
+                            }
+#pragma unroll
+                            for (int q = 0; q < 8; ++q) {
+                                const double nv = fma(-w, pv[q], fv[q]);
+                                Fw[u + (int64_t)(c + q * GG) * M] = nv;
+                                acc = fma(nv, nv, acc);
+                            }
+                        }
+                        for (; c < ncol; c += GG) {
+                            const double nv = fma(-w, Fw[up + (int64_t)c * M], Fw[u + (int64_t)c * M]);
+                            Fw[u + (int64_t)c * M] = nv;
+                            acc = fma(nv, nv, acc);
+                        }
+                    }
+                    if (active && u < M) part[g * RR + r] = acc;
+                    __syncthreads();
+                    if (g == 0 && u < M) {  // rows already pivoted: unused
+                        double sum = 0.0;
+                        for (int q = 0; q < GG; ++q) sum += part[q * RR + r];
+                        nrm[u] = sum;
+                    }
+                    __syncthreads();
+                }
+            }
+            // ---- the pivot row becomes (beta, 0, ...); R_jj > 0
+            for (int c = j + 1 + tid; c < ncol; c += QR_WG) Fw[up + (int64_t)c * M] = 0.0;
+            if (tid == 0) Fw[up + (int64_t)j * M] = beta;
+            __syncthreads();
+            if (beta < 0.0)
+                for (int u = tid; u < M; u += QR_WG) Fw[u + (int64_t)j * M] = -Fw[u + (int64_t)j * M];
+            kk = j + 1;
+            __syncthreads();
+            if (tau == 0.0) row_norms(j + 1);  // else summed during the update
+        }
+    }
+    // ---- P R_k^T into the X slot; the rank for the pivot kernel
+    if (kk > 0 && kk < M)
+        wg_stage(M * kk, [&](int x) { return Fw[x]; }, [&](int x, double v) { X[x] = v; });
+    if (tid == 0) L.k[s] = kk;
+}
+
+void launch_qrcp(const LevelDev& L, const ColourDev& C, hipStream_t st) {
+    if (C.n == 0 || C.fill_total == 0) return;
+    if (C.f32)
+        hipLaunchKernelGGL(k_qrcp<float>, dim3(C.n), dim3(QR_WG), 0, st, L, C.clist);
+    else
+        hipLaunchKernelGGL(k_qrcp<double>, dim3(C.n), dim3(QR_WG), 0, st, L, C.clist);
 }
 
 // ============================================================ fill update

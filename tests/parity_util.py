@@ -82,6 +82,20 @@ def complement_pivot_ratio(rec, sym):
 BASIS_PIVOT_MIN = 1e-10
 
 
+def lu_inverse_bar(rec, level_err=0.0):
+    """Bar of a record built from the inverses of the unpivoted LU factors of
+    A_ss (reading R9), kappa = max(cond L, cond U): the inverse of a
+    triangular matrix computed in floating point carries a relative error up
+    to about m u kappa (the standard forward error bound of triangular
+    inversion), and an error e in the level matrix that A_ss comes from moves
+    the inverse by up to kappa e to first order; a factor 10 covers the
+    operations around them.  On well-conditioned blocks this stays far below
+    the 1e-10 bar; the LU of an indefinite block without pivoting can have
+    cond(L) in the thousands."""
+    kappa = max(np.linalg.cond(rec.L), np.linalg.cond(rec.Uu))
+    return 10.0 * kappa * (rec.m * np.finfo(np.float64).eps + level_err)
+
+
 def perturbed(A, rel=1e-15, seed=0):
     """A with every stored value scaled by (1 + rel r), r standard normal, the
     same r for (i, j) and (j, i): a rounding-level perturbation that keeps the
@@ -147,6 +161,7 @@ def compare_factor(P, A, dims, leaf, eps, sym, check_records=True, max_level_che
         Mo, _ = O.assemble_level_dense(lev)
         Mg = F.level_matrix(l)
         scale = np.abs(Mo).max()
+        level_err = rel(Mg, Mo, scale)  # what the records of this level start from
         if any(not np.array_equal(fp.levels[l].m, lev.m) or
                rel(O.assemble_level_dense(fp.levels[l])[0], Mo, scale) > tol / 10 for fp in fps):
             stats["skipped_unstable"] += 1
@@ -166,6 +181,7 @@ def compare_factor(P, A, dims, leaf, eps, sym, check_records=True, max_level_che
             ops = oracle_ops(rec)
             gops = [F.record(l, s, name) for name in ("TL", "TR", "ER", "EL")]
             base = max(1.0, np.abs(ops[0]).max())
+            bar = max(rec_tol, lu_inverse_bar(rec, level_err))
             pops = []
             for fp in fps:
                 rp = fp.levels[l].records[s]
@@ -184,7 +200,7 @@ def compare_factor(P, A, dims, leaf, eps, sym, check_records=True, max_level_che
                     continue
                 e = rel(g, o, sc)
                 stats["worst_record"] = max(stats["worst_record"], e)
-                assert e <= rec_tol, (l, s, name, e)
+                assert e <= bar, (l, s, name, e, bar)
             if rec.kind == "lowrank":  # basis-invariant quantities, on every route
                 f = rec.m - rec.k
                 io, ig = invariant_ops(*ops, f), invariant_ops(*gops, f)
@@ -202,7 +218,7 @@ def compare_factor(P, A, dims, leaf, eps, sym, check_records=True, max_level_che
                         continue
                     e = rel(ig[name], io[name], sc)
                     stats["worst_invariant"] = max(stats["worst_invariant"], e)
-                    assert e <= rec_tol, (l, s, name, e)
+                    assert e <= bar, (l, s, name, e, bar)
             stats["records"] += 1
     return fo, F, stats
 

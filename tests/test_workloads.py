@@ -124,3 +124,30 @@ def test_vc_poisson_is_spd_m_matrix():
     assert np.all(off <= 0)
     assert np.all(np.diag(D) >= -off.sum(axis=1) - 1e-12)
     assert np.linalg.eigvalsh(D).min() > 0
+
+
+def test_helmholtz_negative_eigenvalues_closed_form():
+    """The Dirichlet 7-point Laplacian on n^3 has the eigenvalues
+    sum_d 4 sin^2(pi i_d / (2 (n + 1))), i_d = 1..n; the Helmholtz matrix
+    shifts them by -(2 pi / ppw)^2, so its negative eigenvalues are counted
+    in closed form.  Checked against a dense eigensolver (inertia), with the
+    diagonal, the couplings and the symmetry."""
+    from workloads import helmholtz3d
+
+    for side, ppw in ((8, 4.0), (10, 6.0), (12, 8.0)):
+        A = helmholtz3d(side, ppw)
+        D = A.to_dense()
+        assert np.allclose(D, D.T)
+        kh2 = (2 * np.pi / ppw) ** 2
+        assert np.allclose(np.diag(D), 6.0 - kh2)
+        off = D - np.diag(np.diag(D))
+        assert set(np.unique(off)) <= {0.0, -1.0} and np.all((off != 0).sum(axis=1) <= 6)
+        lam1 = 4 * np.sin(np.pi * np.arange(1, side + 1) / (2 * (side + 1))) ** 2
+        lam = lam1[:, None, None] + lam1[None, :, None] + lam1[None, None, :]
+        neg = int(np.sum(lam < kh2))
+        assert neg > 0
+        assert int(np.sum(np.linalg.eigvalsh(D) < 0)) == neg
+    # the paper's resolution: 32 points per wavelength, 1 Hz on 32^3
+    A = helmholtz3d(32)
+    assert A.n == 32 ** 3 and np.isclose(A.val[A.col_idx == np.repeat(np.arange(A.n), np.diff(A.row_ptr))][0],
+                                         6.0 - (2 * np.pi / 32) ** 2)

@@ -17,6 +17,7 @@ from .pde import (  # noqa: F401
     gaussian_field3d,
     quantized_field3d,
     vc_poisson3d,
+    helmholtz3d,
     rhs_uniform,
     make_config,
     config1,

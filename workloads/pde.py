@@ -205,6 +205,20 @@ def vc_poisson3d(rng: np.random.Generator, side: int, dev_cells: float = 4.0) ->
     return diffusion3d_from_coeff(quantized_field3d(rng, side, side, side, dev_cells))
 
 
+def helmholtz3d(side: int, points_per_wavelength: float = 32.0) -> CSR:
+    """The paper's third test problem (Sec. 5.1): (-Laplace - k^2) u on a
+    side^3 grid of the unit cube, 7-point stencil with Dirichlet boundaries,
+    scaled by h^2: 6 - (k h)^2 on the diagonal and -1 to each neighbour.  The
+    resolution is fixed, k h = 2 pi / points_per_wavelength (32 in the paper),
+    so the wave number grows with the grid: with unit wave speed, side = 32 f
+    for the frequency f (1 Hz at 32^3, 4 Hz at 128^3).  Symmetric and
+    indefinite once (k h)^2 exceeds the smallest Laplacian eigenvalue."""
+    n = side ** 3
+    kh2 = (2.0 * math.pi / points_per_wavelength) ** 2
+    offs = [(-1, 0, 0), (1, 0, 0), (0, -1, 0), (0, 1, 0), (0, 0, -1), (0, 0, 1)]
+    return _stencil_csr(side, side, side, np.full(n, 6.0 - kh2), [(o, -1.0) for o in offs])
+
+
 def random_geometric_spd(rng: np.random.Generator, n: int, degree: float = 8.0, shift: float = 0.05,
                          nonsym: float = 0.0) -> CSR:
     """An unstructured sparse matrix with no grid: n random points in the unit
