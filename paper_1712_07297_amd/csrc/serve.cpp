@@ -117,20 +117,35 @@ struct hs_server_s {
     // Free least recently used idle factorizations (not in P) until `need`
     // more bytes fit under the cap; true if they do.
     bool make_room(double need, const Plan& P) {
+        bool evicted = false;
         while (held + reserved + need > o.hbm_cap_bytes) {
             Group* victim = nullptr;
             for (auto& g : groups)
                 if (!g->busy && std::find(P.groups.begin(), P.groups.end(), g.get()) == P.groups.end() &&
                     (!victim || g->last_use < victim->last_use))
                     victim = g.get();
-            if (!victim) return false;
+            if (!victim) break;
             for (int64_t k : victim->keys) cache.erase(k);
             held -= victim->bytes;
-            hs_free(victim->F);
+            hs_free(victim->F);  // synchronises the device first
             ++evictions;
+            evicted = true;
             groups.erase(std::find_if(groups.begin(), groups.end(), [&](auto& g) { return g.get() == victim; }));
         }
-        return true;
+        if (evicted) trim_pool();
+        return held + reserved + need <= o.hbm_cap_bytes;
+    }
+
+    // Hand the stream-ordered pool's unused memory back to the device: the
+    // pool keeps freed blocks for reuse, and blocks of evicted factorizations
+    // that later requests cannot reuse (other sizes) would otherwise hold
+    // device memory outside the cap (and away from the caller's allocations).
+    static void trim_pool() {
+        int dev = 0;
+        hipMemPool_t pool;
+        if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess)
+            (void)hipMemPoolTrimTo(pool, 0);
+        (void)hipGetLastError();
     }
 
     // Form a batch from the waiting requests (lock held).  False: nothing

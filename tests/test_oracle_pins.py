@@ -518,3 +518,30 @@ def test_algebraic_tree_components_and_exact_mode():
     fo = O.factor(rp, ci, va, None, 16, 0.0, True)
     b = np.random.default_rng(0).uniform(-1, 1, n)
     assert _relres(A, O.solve(fo, b), b) < 1e-12
+
+
+def test_colour_count_is_the_critical_path():
+    """Reading R3's greedy distance-2 colouring, processed colour by colour:
+    the dependency graph of the processing order (clusters within distance
+    2, earlier position first) has exactly as many levels as there are
+    colours.  (A cluster of colour c has, for every c' < c, a distance-2
+    neighbour of colour c' coloured before it; following colour c - 1, c - 2,
+    ... gives a chain of c + 1 clusters.)  So no schedule that keeps the
+    processing order of interacting clusters can take fewer steps than the
+    colours."""
+    from workloads import convdiff2d_upwind, poisson3d
+
+    for A, dims in ((poisson3d(16, 16, 16), (16, 16, 16)), (convdiff2d_upwind(128, 50.0, 0.3), (128, 128, 1))):
+        _, levels = O.hs_oracle.symbolic_analysis(A.row_ptr, A.col_idx, dims, 32)
+        for ls in levels:
+            n = len(ls.adj)
+            if n == 0:
+                continue
+            depth = [0] * n
+            for s in ls.order:
+                d2 = set(ls.adj[s])
+                for t in ls.adj[s]:
+                    d2.update(ls.adj[t])
+                d2.discard(s)
+                depth[s] = 1 + max([depth[t] for t in d2 if ls.pos[t] < ls.pos[s]], default=0)
+            assert max(depth) == max(ls.color) + 1
