@@ -660,7 +660,9 @@ def run_serve(args):
             "factored_ops": st["factored_ops"],
             "evictions": st["evictions"],
             "peak_held_gb": st["peak_held_bytes"] / 1e9,
-            "max_relres": max(r["relres"] for r in results),
+            "max_relres": max(r["relres"] for r in results if r["status"] == 0),
+            "failed": sum(1 for r in results if r["status"] != 0),
+            "failed_status": sorted({int(r["status"]) for r in results if r["status"] != 0}),
             "converged": all(r["status"] == 0 for r in results) and max(r["relres"] for r in results) <= 1e-10,
         })
         print(f"serve: rho {rho}: {json.dumps(runs[-1])}", file=sys.stderr, flush=True)

@@ -124,7 +124,18 @@ typedef struct hs_geometry {
  *               0: general A (row and column fill compressed together);
  *               -1: detect from the values.
  *   coarse_fp64_dofs  mixed form only: a system's levels with at most this
- *               many unknowns keep float64 storage (0 selects 16384). */
+ *               many unknowns keep float64 storage (0 selects 16384).
+ *   pivoting    0: A_ss and F_ff are factored by LU without pivoting (the
+ *               nonsymmetric counterpart of the Cholesky factor of Eq. elim);
+ *               1: by LU with partial pivoting inside each cluster (P A = L U:
+ *               at step j the lowest row at or below j whose |entry| is within
+ *               1e-10 of the column's largest), for indefinite systems whose
+ *               blocks have small or zero leading pivots (the extension to
+ *               indefinite matrices of Sec. 6); the stored operators become
+ *               L^{-1} P and U^{-1}.  Complete levels then run through the
+ *               per-cluster kernels too (no dense level factorization), so
+ *               every cluster must stay within the 512-unknown limit
+ *               (HS_ERR_UNSUPPORTED otherwise).  Other values: HS_ERR_ARG. */
 typedef struct hs_opts {
     double eps;
     int32_t fixed_rank;
@@ -134,6 +145,7 @@ typedef struct hs_opts {
     int32_t keep_levels; /* 1: keep a host copy of every level's starting matrix
                             (test hook, see hs_factor_level_matrix); 0: off */
     int32_t coarse_fp64_dofs;
+    int32_t pivoting;
 } hs_opts;
 
 /* Opaque factorization; device resident; owned by the library until hs_free. */

@@ -67,6 +67,11 @@ R14 clusters without a grid: complete recursive bisection of the graph of
     pseudo-peripheral vertex (component by component, lowest vertex first,
     neighbours ascending) and its first floor(|S|/2) vertices form the left
     child.
+R16 (opt-in, for indefinite systems) A_ss and F_ff are factored with partial
+    pivoting, P A = L U: at step j the lowest row at or below j whose |entry|
+    is within 1e-10 of the column's largest, rows exchanged across the block.
+    The permutation stays inside the cluster, so the stored operators become
+    L^{-1} P (and U^{-1}); everything else is unchanged.
 """
 
 from __future__ import annotations
@@ -318,7 +323,35 @@ def lu_nopiv(a: np.ndarray) -> Tuple[np.ndarray, np.ndarray]:
     return np.tril(lu, -1) + np.eye(n), np.triu(lu)
 
 
-def _lsolve(L, B):
+PIVOT_TIE_LU = 1e-10
+
+
+def lu_partial(a: np.ndarray) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """Reading R16: LU with partial pivoting, P A = L U, L unit lower.  At step
+    j the pivot is the lowest row at or below j whose |entry| is within
+    1e-10 of the column's largest; rows are exchanged across the whole
+    matrix.  Returns (L, U, p) with (P A)[i, :] = A[p[i], :]."""
+    n = a.shape[0]
+    lu = np.array(a, dtype=np.float64, copy=True)
+    p = np.arange(n)
+    for j in range(n):
+        col = np.abs(lu[j:, j])
+        mx = col.max() if col.size else 0.0
+        if mx == 0.0 or not np.isfinite(mx):
+            raise Breakdown(f"pivot {j} of a {n}x{n} block is {mx}")
+        i = j + int(np.flatnonzero(col >= (1.0 - PIVOT_TIE_LU) * mx)[0])
+        if i != j:
+            lu[[j, i], :] = lu[[i, j], :]
+            p[[j, i]] = p[[i, j]]
+        lu[j + 1 :, j] /= lu[j, j]
+        lu[j + 1 :, j + 1 :] -= np.outer(lu[j + 1 :, j], lu[j, j + 1 :])
+    return np.tril(lu, -1) + np.eye(n), np.triu(lu), p
+
+
+def _lsolve(L, B, p=None):
+    """L^{-1} P B (P the row permutation p of a pivoted LU; none: identity)."""
+    if p is not None:
+        B = B[p]
     return sla.solve_triangular(L, B, lower=True, unit_diagonal=True) if L.size else B.copy()
 
 
@@ -326,14 +359,20 @@ def _usolve(U, B):
     return sla.solve_triangular(U, B, lower=False) if U.size else B.copy()
 
 
-def _lu_solve(L, U, B):
-    return _usolve(U, _lsolve(L, B))
+def _lu_solve(L, U, B, p=None):
+    """A^{-1} B with P A = L U."""
+    return _usolve(U, _lsolve(L, B, p))
 
 
-def _lu_solve_t(L, U, B):
-    """A^{-T} B with A = L U."""
+def _lu_solve_t(L, U, B, p=None):
+    """A^{-T} B with P A = L U: P^T L^{-T} U^{-T} B."""
     y = sla.solve_triangular(U, B, lower=False, trans="T") if U.size else B.copy()
-    return sla.solve_triangular(L, y, lower=True, unit_diagonal=True, trans="T") if L.size else y
+    y = sla.solve_triangular(L, y, lower=True, unit_diagonal=True, trans="T") if L.size else y
+    if p is None:
+        return y
+    out = np.empty_like(y)
+    out[p] = y
+    return out
 
 
 def _right_usolve(B, U):
@@ -442,8 +481,10 @@ class Record:
     nbr_sizes: List[int]  # current sizes of the neighbours when s was processed
     fill: List[int]
     fill_sizes: List[int]
-    L: Optional[np.ndarray] = None  # LU of A_ss
+    L: Optional[np.ndarray] = None  # LU of A_ss (P A_ss = L Uu with pivoting)
     Uu: Optional[np.ndarray] = None
+    p: Optional[np.ndarray] = None  # row permutation of A_ss's LU (None: unpivoted)
+    pf: Optional[np.ndarray] = None  # ... of F_ff's LU
     U: Optional[np.ndarray] = None  # m x k
     Z: Optional[np.ndarray] = None
     VL: Optional[np.ndarray] = None  # m x f
@@ -507,7 +548,7 @@ def _get(blocks, a, b, cur):
 
 def factor(row_ptr, col_idx, val, dims, leaf: int, eps: float, symmetric: bool,
            fixed_rank: int = 0, keep_blocks: bool = False, progress=None,
-           shuffle_within_colors: Optional[np.random.Generator] = None) -> Factor:
+           shuffle_within_colors: Optional[np.random.Generator] = None, pivoting: bool = False) -> Factor:
     """Alg. 1 (Hierarchical_Factor) with the low-rank elimination of Sec. 2.1.
 
     ``shuffle_within_colors`` permutes the execution order of the clusters of
@@ -534,7 +575,7 @@ def factor(row_ptr, col_idx, val, dims, leaf: int, eps: float, symmetric: bool,
                 grp = [s for s in sym.order if sym.color[s] == c]
                 exec_order += [grp[i] for i in shuffle_within_colors.permutation(len(grp))]
         for s in exec_order:
-            records[s] = _low_rank_elimination(s, sym, blocks, cur, eps, symmetric, fixed_rank)
+            records[s] = _low_rank_elimination(s, sym, blocks, cur, eps, symmetric, fixed_rank, pivoting)
             if dofs is not None:
                 r = records[s]
                 if r.kind in ("full", "empty"):
@@ -551,7 +592,8 @@ def factor(row_ptr, col_idx, val, dims, leaf: int, eps: float, symmetric: bool,
     return Factor(n, symmetric, eps, tree, levels)
 
 
-def _low_rank_elimination(s, sym: LevelSymbolic, blocks, cur, eps, symmetric, fixed_rank) -> Record:
+def _low_rank_elimination(s, sym: LevelSymbolic, blocks, cur, eps, symmetric, fixed_rank,
+                          pivoting: bool = False) -> Record:
     """LowRank_Elimination of Alg. 1 for cluster s: W_s = P_s G_s E_s."""
     m = cur[s]
     nb = list(sym.adj[s])
@@ -585,12 +627,15 @@ def _low_rank_elimination(s, sym: LevelSymbolic, blocks, cur, eps, symmetric, fi
         rec.kind = "deferred"  # reading R7: nothing eliminated
         return rec
 
-    L, Uu = lu_nopiv(A_ss)
-    rec.L, rec.Uu = L, Uu
+    if pivoting:
+        L, Uu, pa = lu_partial(A_ss)  # reading R16
+    else:
+        (L, Uu), pa = lu_nopiv(A_ss), None
+    rec.L, rec.Uu, rec.p = L, Uu, pa
     if k == 0:
         # E_s = I (Sec. 2.2): one block LU step; any fill of s is dropped.
         rec.kind = "full"
-        rec.ER = _lsolve(L, A_sn)
+        rec.ER = _lsolve(L, A_sn, pa)
         rec.EL = _right_usolve(A_ns, Uu)
         for t in wl:
             blocks[(s, t)] = np.zeros((0, cur[t]))
@@ -607,11 +652,11 @@ def _low_rank_elimination(s, sym: LevelSymbolic, blocks, cur, eps, symmetric, fi
     rec.kind = "lowrank"
     Z_r = Z[:, : rec.w_tot]
     Z_c = Z_r if symmetric else Z[:, rec.w_tot :]
-    X = _lu_solve(L, Uu, U)  # A_ss^{-1} U
+    X = _lu_solve(L, Uu, U, pa)  # A_ss^{-1} U
     VL = householder_complement(X)  # V_L^T A_ss^{-1} U = 0
-    VR = VL if symmetric else householder_complement(_lu_solve_t(L, Uu, U))
-    Ainv_VR = _lu_solve(L, Uu, VR)
-    Ainv_Asn = _lu_solve(L, Uu, A_sn)
+    VR = VL if symmetric else householder_complement(_lu_solve_t(L, Uu, U, pa))
+    Ainv_VR = _lu_solve(L, Uu, VR, pa)
+    Ainv_Asn = _lu_solve(L, Uu, A_sn, pa)
     F_ff = VL.T @ Ainv_VR  # fine-fine block V^T A_ss^{-1} V
     C = U.T @ X  # coarse-coarse block U^T A_ss^{-1} U
     B_fn = VL.T @ Ainv_Asn  # V^T A_ss^{-1} A_sn
@@ -620,8 +665,12 @@ def _low_rank_elimination(s, sym: LevelSymbolic, blocks, cur, eps, symmetric, fi
     B_nc = A_ns @ X  # A_ns A_ss^{-1} U
 
     # ---- elimination operator G_s (Eq. elim), F_ff = L_f U_f
-    Lf, Uf = lu_nopiv(F_ff)
-    ER = _lsolve(Lf, B_fn)  # L_f^{-1} V^T A_ss^{-1} A_sn
+    if pivoting:
+        Lf, Uf, pf = lu_partial(F_ff)
+    else:
+        (Lf, Uf), pf = lu_nopiv(F_ff), None
+    rec.pf = pf
+    ER = _lsolve(Lf, B_fn, pf)  # L_f^{-1} P_f V^T A_ss^{-1} A_sn
     EL = _right_usolve(B_nf, Uf)  # A_ns A_ss^{-1} V U_f^{-1}
     rec.U, rec.Z, rec.VL, rec.VR, rec.Lf, rec.Uf, rec.EL, rec.ER = U, Z, VL, VR, Lf, Uf, EL, ER
 
@@ -730,11 +779,11 @@ def _forward(rec: Record, s, vec):
         return None
     y = vec[s]
     if rec.kind == "full":
-        yf = _lsolve(rec.L, y)
+        yf = _lsolve(rec.L, y, rec.p)
         vec[s] = np.zeros((0, y.shape[1]))
     else:
-        t = _lu_solve(rec.L, rec.Uu, y)
-        yf = _lsolve(rec.Lf, rec.VL.T @ t)
+        t = _lu_solve(rec.L, rec.Uu, y, rec.p)
+        yf = _lsolve(rec.Lf, rec.VL.T @ t, rec.pf)
         vec[s] = rec.U.T @ t
     off = 0
     for a, sz in zip(rec.nbrs, rec.nbr_sizes):
@@ -751,7 +800,7 @@ def _backward(rec: Record, s, vec, yf):
     if rec.kind == "full":
         vec[s] = xf
     else:
-        vec[s] = _lu_solve(rec.L, rec.Uu, rec.VR @ xf + rec.U @ vec[s])
+        vec[s] = _lu_solve(rec.L, rec.Uu, rec.VR @ xf + rec.U @ vec[s], rec.p)
 
 
 # ================================================================ Krylov

@@ -63,6 +63,7 @@ class hs_opts(ctypes.Structure):
         ("symmetric", ctypes.c_int32),
         ("keep_levels", ctypes.c_int32),
         ("coarse_fp64_dofs", ctypes.c_int32),
+        ("pivoting", ctypes.c_int32),
     ]
 
 
@@ -315,10 +316,10 @@ class Factor:
 
     def __init__(self, row_ptr, col_idx, val, dims, eps: float, leaf: int = 64, symmetric: int = -1,
                  precision: int = HS_FP64, fixed_rank: int = 0, keep_levels: bool = False, stream=None,
-                 coarse_fp64_dofs: int = 0, _systems=None):
+                 coarse_fp64_dofs: int = 0, _systems=None, pivoting: int = 0):
         keep: list = []
         opts = hs_opts(float(eps), int(fixed_rank), int(leaf), int(precision), int(symmetric), 1 if keep_levels else 0,
-                       int(coarse_fp64_dofs))
+                       int(coarse_fp64_dofs), int(pivoting))
         h = _P()
         if _systems is None:
             A = _csr_struct(row_ptr, col_idx, val, keep)
@@ -340,10 +341,10 @@ class Factor:
 
     @classmethod
     def batch(cls, systems, eps: float, leaf: int = 64, symmetric: int = -1, precision: int = HS_FP64,
-              fixed_rank: int = 0, stream=None, coarse_fp64_dofs: int = 0) -> "Factor":
+              fixed_rank: int = 0, stream=None, coarse_fp64_dofs: int = 0, pivoting: int = 0) -> "Factor":
         """hs_factor_batch over systems = [(row_ptr, col_idx, val, dims), ...]."""
         return cls(None, None, None, None, eps, leaf, symmetric, precision, fixed_rank, False, stream,
-                   coarse_fp64_dofs, _systems=list(systems))
+                   coarse_fp64_dofs, _systems=list(systems), pivoting=pivoting)
 
     def _lanes(self, rel, nrhs):
         a = np.array(rel[:])
@@ -461,7 +462,7 @@ class Server:
             B2 = B2.contiguous()
         if X is None:
             X = torch.empty_like(B2)
-        opts = hs_opts(float(eps), 0, int(leaf), int(precision), int(symmetric), 0, int(coarse_fp64_dofs))
+        opts = hs_opts(float(eps), 0, int(leaf), int(precision), int(symmetric), 0, int(coarse_fp64_dofs), 0)
         geom = _geom(dims)
         t = _I64(0)
         _check(lib().hs_submit(self._h, int(op_key), ctypes.byref(A), ctypes.byref(geom), ctypes.byref(opts), nrhs,

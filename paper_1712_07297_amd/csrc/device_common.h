@@ -60,6 +60,7 @@ struct LevelDev {
     int symmetric;
     double eps;
     int fixed_rank;
+    int pivoting;             // 1: LU of A_ss and F_ff with partial pivoting inside the cluster
     int gram_splits;          // Gram partial slots per cluster workspace (largest of the level)
     const int* m;             // [ncl] sizes at the start of the level
     int* k;                   // [ncl] coarse sizes after elimination (rank)

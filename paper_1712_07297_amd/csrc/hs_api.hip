@@ -730,6 +730,7 @@ static void bind_level(LevelData& LD, const std::vector<size_t>& offs, const hs_
     D.symmetric = F->symmetric;
     D.eps = F->opts.eps;
     D.fixed_rank = F->opts.fixed_rank;
+    D.pivoting = F->opts.pivoting;
     D.gram_splits = LD.gram_splits;
     D.kn = F->cfg.kn;
     D.kn.qrcp = F->qrcp;
@@ -1100,7 +1101,8 @@ static int factor_impl(hs_factor_s* F, int nsys, const hs_csr* A, const hs_geome
             const int c0 = coff[j], c1 = coff[j + 1];
             int64_t dofs = 0;
             for (int c = c0; c < c1; ++c) dofs += LD.m[c];
-            const bool dn = F->forest.dense[j] == lvl;
+            // with pivoting a complete level runs through the per-cluster kernels
+            const bool dn = F->forest.dense[j] == lvl && !F->opts.pivoting;
             const int single = (mixed && lvl < F->forest.dense[j] && dofs > fp64_dofs) ? 1 : 0;
             for (int c = c0; c < c1; ++c) {
                 LD.f32[c] = single;
@@ -1908,7 +1910,7 @@ extern "C" {
 
 static int check_opts(const hs_opts* opts) {
     if (!(opts->eps >= 0.0) || opts->leaf_size <= 0 || opts->fixed_rank < 0 || opts->coarse_fp64_dofs < 0 ||
-        (opts->precision != HS_FP64 && opts->precision != HS_MIXED))
+        (opts->precision != HS_FP64 && opts->precision != HS_MIXED) || (opts->pivoting != 0 && opts->pivoting != 1))
         return fail(HS_ERR_ARG, "bad options");
     return HS_OK;
 }

@@ -420,6 +420,81 @@ __device__ void wg_complement(PX X, int M, int K, PV V, int ldv, PT tau_sh, doub
         wg_house_form_q(X, M, K, M, tau_sh, K, M - K, V, ldv);
 }
 
+// LU with partial pivoting of the M x M matrix W (ld ldw), in place, P W = L U
+// with L unit lower: at step j the lowest row at or below j whose |entry| is
+// within 1e-10 of the column's largest (one wave searches), rows exchanged
+// across the whole matrix, the column divided by the pivot and the trailing
+// block updated.  perm[i] = original row of row i.  False (nothing else
+// changed) at a zero or non-finite pivot.
+template <class PW>
+__device__ bool wg_lu_partial(PW W, int M, int ldw, lds_i32* perm, lds_i32* ctl) {
+    const int tid = threadIdx.x, nth = blockDim.x;
+    for (int u = tid; u < M; u += nth) perm[u] = u;
+    for (int j = 0; j < M; ++j) {
+        if (tid < 64) {
+            double mx = 0.0;
+            bool bad = false;
+            for (int i = j + tid; i < M; i += 64) {
+                const double a = fabs(W[i + (int64_t)j * ldw]);
+                bad |= !(a <= 1.7976931348623157e308);  // NaN or infinite
+                mx = fmax(mx, a);
+            }
+            mx = wave_max(mx);
+            const double thr = (1.0 - 1e-10) * mx;
+            int cand = M;
+            for (int i = j + tid; i < M; i += 64)
+                if (fabs(W[i + (int64_t)j * ldw]) >= thr) {
+                    cand = i;
+                    break;
+                }
+            cand = wave_min_int(cand);
+            const int anybad = __builtin_amdgcn_readfirstlane(wave_min_int(bad ? 0 : 1) == 0);
+            if (tid == 0) {
+                ctl[0] = cand;
+                ctl[1] = (mx > 0.0 && !anybad && cand < M) ? 0 : 1;
+            }
+        }
+        __syncthreads();
+        if (ctl[1]) return false;
+        const int piv = ctl[0];
+        if (piv != j) {
+            for (int c = tid; c < M; c += nth) {
+                const double a = W[j + (int64_t)c * ldw];
+                W[j + (int64_t)c * ldw] = W[piv + (int64_t)c * ldw];
+                W[piv + (int64_t)c * ldw] = a;
+            }
+            if (tid == 0) {
+                const int t = perm[j];
+                perm[j] = perm[piv];
+                perm[piv] = t;
+            }
+        }
+        __syncthreads();
+        const double p = W[j + (int64_t)j * ldw];
+        for (int i = j + 1 + tid; i < M; i += nth) W[i + (int64_t)j * ldw] /= p;
+        __syncthreads();
+        const int r = M - j - 1;
+        for (int e = tid; e < r * r; e += nth) {
+            const int i = j + 1 + e % r, c = j + 1 + e / r;
+            W[i + (int64_t)c * ldw] -= W[i + (int64_t)j * ldw] * W[j + (int64_t)c * ldw];
+        }
+        __syncthreads();
+    }
+    return true;
+}
+
+// dst (n x n, ld ldd) = src (ld lds) with its columns permuted: dst[:, perm[i]]
+// = src[:, i]; the inverse of a pivoted L times P, from the inverse of L.
+template <class PD>
+__device__ void wg_permute_columns(int n, const double* src, int lds, const lds_i32* perm, PD dst, int ldd) {
+    __syncthreads();
+    for (int x = threadIdx.x; x < n * n; x += blockDim.x) {
+        const int r = x % n, i = x / n;
+        dst[r + (int64_t)perm[i] * ldd] = src[r + (int64_t)i * lds];
+    }
+    __syncthreads();
+}
+
 // Per-cluster elimination operators.  The working M x M matrix W lives in
 // LDS when the colour's largest cluster fits (lds_m), else in the cluster's
 // L2-resident workspace; every dense step below reuses it in turn.
@@ -572,9 +647,12 @@ __global__ void __launch_bounds__(WG, 1) k_pivot(LevelDev L, const int* __restri
     if (tid == 0) L.k[s] = kk;
     if (kk == M) return;  // nothing eliminated
 
-    // ---- 2. A_ss = L U (no pivoting) and its inverse factors
+    // ---- 2. A_ss = L U (P A_ss = L U with pivoting) and its inverse factors
     wg_copy(M, M, Bss, M, W, M);
-    if (!wg_lu<true>(W, M, M, scr, to_lds(isc + 1))) {
+    lds_i32* lu_perm = to_lds(perm);  // the Cholesky pivots above are no longer needed
+    const bool lu_ok =
+        L.pivoting ? wg_lu_partial(W, M, M, lu_perm, to_lds(isc + 1)) : wg_lu<true>(W, M, M, scr, to_lds(isc + 1));
+    if (!lu_ok) {
         if (tid == 0) {
             L.flag[s] = 1;
             L.k[s] = M;  // leave the cluster untouched
@@ -582,11 +660,21 @@ __global__ void __launch_bounds__(WG, 1) k_pivot(LevelDev L, const int* __restri
         return;
     }
     if (kk == 0) {  // E_s = I: one block LU step
-        inv_lower(W, M, TLp);
+        if (L.pivoting) {  // T_L' = L^{-1} P
+            inv_lower(W, M, Linv);
+            wg_permute_columns(M, Linv, M, lu_perm, TLp, M);
+        } else {
+            inv_lower(W, M, TLp);
+        }
         inv_upper(W, M, TRp);
         return;
     }
-    inv_lower(W, M, Linv);
+    if (L.pivoting) {  // L^{-1} P, formed in the A^{-1} slot first
+        inv_lower(W, M, Ainv);
+        wg_permute_columns(M, Ainv, M, lu_perm, Linv, M);
+    } else {
+        inv_lower(W, M, Linv);
+    }
     inv_upper(W, M, Uinv);
     wg_gemm<false, false>(M, M, M, 1.0, Uinv, M, Linv, M, 0.0, Ainv, M, sm_l);
     const int f = M - kk;
@@ -610,14 +698,21 @@ __global__ void __launch_bounds__(WG, 1) k_pivot(LevelDev L, const int* __restri
 
     // ---- 4. elimination operator G_s (Eq. elim): F_ff = T_L[:f] S_R[:, :f] = L_f U_f
     wg_gemm<false, false>(f, f, M, 1.0, TL, M, SR, M, 0.0, W, M, sm_l);
-    if (!wg_lu<true>(W, f, M, scr, to_lds(isc + 1))) {
+    const bool ff_ok =
+        L.pivoting ? wg_lu_partial(W, f, M, lu_perm, to_lds(isc + 1)) : wg_lu<true>(W, f, M, scr, to_lds(isc + 1));
+    if (!ff_ok) {
         if (tid == 0) {
             L.flag[s] = 2;
             L.k[s] = M;
         }
         return;
     }
-    inv_lower(W, f, Linv);
+    if (L.pivoting) {  // L_f^{-1} P_f, formed in the C U^T slot first (written in step 5)
+        inv_lower(W, f, CU);
+        wg_permute_columns(f, CU, M, lu_perm, Linv, M);
+    } else {
+        inv_lower(W, f, Linv);
+    }
     inv_upper(W, f, Uinv);
     // T_L' = [L_f^{-1} T_L[:f, :]; T_L[f:, :]],  T_R' = [T_R[:, :f] U_f^{-1}, T_R[:, f:]]
     wg_gemm<false, false>(f, M, f, 1.0, Linv, M, TL, M, 0.0, TLp, M, sm_l);

@@ -31,12 +31,20 @@ def tol_eps(eps, route="gram"):
     return max(1e-9, 1e-13 / eps**2) if route == "gram" else max(1e-9, 1e-13 / eps)
 
 
+def _perm_matrix(p, n):
+    """P with (P A)[i, :] = A[p[i], :] (identity when p is None)."""
+    return np.eye(n) if p is None else np.eye(n)[p]
+
+
 def oracle_ops(rec):
-    """T_L', T_R', E_R, E_L of an oracle record, as the library stores them."""
+    """T_L', T_R', E_R, E_L of an oracle record, as the library stores them
+    (with pivoting, P A_ss = L U: T_L' of a block LU step is L^{-1} P)."""
+    P = _perm_matrix(rec.p, rec.m)
     if rec.kind == "full":
-        return np.linalg.inv(rec.L), np.linalg.inv(rec.Uu), rec.ER, rec.EL
-    Ainv = np.linalg.inv(rec.L @ rec.Uu)
-    TL = np.vstack([np.linalg.solve(rec.Lf, rec.VL.T @ Ainv), rec.U.T @ Ainv])
+        return np.linalg.inv(rec.L) @ P, np.linalg.inv(rec.Uu), rec.ER, rec.EL
+    Ainv = np.linalg.inv(P.T @ rec.L @ rec.Uu)
+    Pf = _perm_matrix(rec.pf, rec.Lf.shape[0])
+    TL = np.vstack([np.linalg.solve(rec.Lf, Pf @ (rec.VL.T @ Ainv)), rec.U.T @ Ainv])
     TR = np.hstack([Ainv @ rec.VR @ np.linalg.inv(rec.Uf), Ainv @ rec.U])
     return TL, TR, rec.ER, rec.EL
 
@@ -63,9 +71,9 @@ def complement_pivot_ratio(rec, sym):
     in leaves of a graph bisection) the reflector's sign, and the basis V, are
     decided by rounding."""
     H = O.hs_oracle
-    sides = [H._lu_solve(rec.L, rec.Uu, rec.U)]
+    sides = [H._lu_solve(rec.L, rec.Uu, rec.U, rec.p)]
     if not sym:
-        sides.append(H._lu_solve_t(rec.L, rec.Uu, rec.U))
+        sides.append(H._lu_solve_t(rec.L, rec.Uu, rec.U, rec.p))
     worst = np.inf
     for X in sides:
         R = np.array(X, dtype=np.float64)
@@ -110,7 +118,7 @@ def perturbed(A, rel=1e-15, seed=0):
 
 
 def compare_factor(P, A, dims, leaf, eps, sym, check_records=True, max_level_check=99, fixed_rank=0,
-                   rec_tol=None, route=None, raw_records=None, stable_only=False, **kw):
+                   rec_tol=None, route=None, raw_records=None, stable_only=False, pivoting=0, **kw):
     """Factor with both; assert sizes and ranks bit-exact, level matrices and
     stored operators within the bars above.  route: "gram" or "qrcp" (the
     library's choice for these options when None: pivoted QR under a rank cap
@@ -130,15 +138,16 @@ def compare_factor(P, A, dims, leaf, eps, sym, check_records=True, max_level_che
     accuracy), and only what the input determines is compared.
 
     Returns (oracle factor, GPU factor, statistics of what was compared)."""
-    fo = O.factor(A.row_ptr, A.col_idx, A.val, dims, leaf, eps, sym, fixed_rank=fixed_rank, keep_blocks=True)
+    fo = O.factor(A.row_ptr, A.col_idx, A.val, dims, leaf, eps, sym, fixed_rank=fixed_rank, keep_blocks=True,
+                  pivoting=bool(pivoting))
     fps = []
     if stable_only:
         for seed in range(4):
             Ap = perturbed(A, seed=seed)
             fps.append(O.factor(Ap.row_ptr, Ap.col_idx, Ap.val, dims, leaf, eps, sym, fixed_rank=fixed_rank,
-                                keep_blocks=True))
+                                keep_blocks=True, pivoting=bool(pivoting)))
     F = P.Factor(A.row_ptr, A.col_idx, A.val, dims, eps, leaf, symmetric=1 if sym else 0, keep_levels=True,
-                 fixed_rank=fixed_rank, **kw)
+                 fixed_rank=fixed_rank, pivoting=pivoting, **kw)
     if route is None:
         mode = P.config_get("compression")
         route = "qrcp" if mode == 1 or (mode == 0 and (fixed_rank > 0 or eps < P.config_get("qrcp_below_eps"))) \

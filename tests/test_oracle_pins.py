@@ -545,3 +545,54 @@ def test_colour_count_is_the_critical_path():
                 d2.discard(s)
                 depth[s] = 1 + max([depth[t] for t in d2 if ls.pos[t] < ls.pos[s]], default=0)
             assert max(depth) == max(ls.color) + 1
+
+
+# ------------------------------------------------- R16 partial pivoting
+
+
+def test_pivoted_lu_matches_lapack():
+    """Reading R16's LU with partial pivoting against LAPACK getrf (through
+    scipy.linalg.lu): the same permutation and factors on random matrices
+    (ties within 1e-10 do not occur there), and |L_ij| <= 1."""
+    rng = np.random.default_rng(4)
+    for n in (1, 5, 17, 64):
+        A = rng.standard_normal((n, n))
+        L, U, p = O.hs_oracle.lu_partial(A)
+        Ps, Ls, Us = sla.lu(A)  # A = Ps Ls Us
+        assert np.array_equal(A[p], Ps.T @ A)
+        assert np.allclose(L, Ls, atol=1e-13) and np.allclose(U, Us, atol=1e-12)
+        assert np.abs(L).max() <= 1.0
+        assert np.allclose(L @ U, A[p], atol=1e-12)
+
+
+def test_pivoting_solves_zero_diagonal_exactly():
+    """A symmetric indefinite matrix with a zero diagonal: LU without pivoting
+    breaks down at the first pivot of the first block (reading R9); with
+    partial pivoting (R16) the exact mode reproduces the dense solve."""
+    from workloads import zero_diagonal_grid2d
+
+    for nx, leaf in ((16, 8), (32, 16)):
+        A = zero_diagonal_grid2d(np.random.default_rng(3), nx, nx)
+        b = np.random.default_rng(1).uniform(-1, 1, A.n)
+        with pytest.raises(O.hs_oracle.Breakdown):
+            O.factor(A.row_ptr, A.col_idx, A.val, (nx, nx, 1), leaf, 0.0, True)
+        fo = O.factor(A.row_ptr, A.col_idx, A.val, (nx, nx, 1), leaf, 0.0, True, pivoting=True)
+        xd = np.linalg.solve(A.to_dense(), b)
+        assert np.linalg.norm(O.solve(fo, b) - xd) <= 1e-11 * np.linalg.norm(xd)
+
+
+def test_pivoting_keeps_exact_and_compressed_solves():
+    """On a nonsymmetric diagonally dominant operator partial pivoting gives
+    another exact factorization (the same dense solve at eps = 0) and at
+    eps = 1e-3 a preconditioner that GMRES still needs few iterations with."""
+    from workloads import convdiff2d_upwind
+
+    A = convdiff2d_upwind(40, 30.0, 0.3)
+    b = np.random.default_rng(2).uniform(-1, 1, A.n)
+    xd = np.linalg.solve(A.to_dense(), b)
+    for piv in (False, True):
+        fo = O.factor(A.row_ptr, A.col_idx, A.val, (40, 40, 1), 16, 0.0, False, pivoting=piv)
+        assert np.linalg.norm(O.solve(fo, b) - xd) <= 1e-12 * np.linalg.norm(xd)
+        fo = O.factor(A.row_ptr, A.col_idx, A.val, (40, 40, 1), 16, 1e-3, False, pivoting=piv)
+        _, it, rel = O.gmres(A.row_ptr, A.col_idx, A.val, b, lambda R: O.solve(fo, R), 1e-10, 50)
+        assert rel <= 1e-10 and it <= 6

@@ -18,6 +18,7 @@ from .pde import (  # noqa: F401
     quantized_field3d,
     vc_poisson3d,
     helmholtz3d,
+    zero_diagonal_grid2d,
     rhs_uniform,
     make_config,
     config1,

@@ -219,6 +219,21 @@ def helmholtz3d(side: int, points_per_wavelength: float = 32.0) -> CSR:
     return _stencil_csr(side, side, side, np.full(n, 6.0 - kh2), [(o, -1.0) for o in offs])
 
 
+def zero_diagonal_grid2d(rng: np.random.Generator, nx: int, ny: int) -> CSR:
+    """A symmetric indefinite matrix whose diagonal is zero: the 5-point grid
+    graph with random weights, a_ij = a_ji = -w_ij, w_ij uniform [0.5, 1.5).
+    LU without pivoting fails at the first step of every block; with partial
+    pivoting a block is singular only if its subgraph is (e.g. an odd number
+    of cells of a bipartite grid)."""
+    A = poisson2d(nx, ny)
+    rows = np.repeat(np.arange(A.n), np.diff(A.row_ptr))
+    cols = A.col_idx.astype(np.int64)
+    lo, hi = np.minimum(rows, cols), np.maximum(rows, cols)
+    uniq, inv = np.unique(lo * A.n + hi, return_inverse=True)
+    w = rng.uniform(0.5, 1.5, uniq.size)[inv]
+    return CSR(A.n, A.row_ptr, A.col_idx, np.where(rows == cols, 0.0, -w))
+
+
 def random_geometric_spd(rng: np.random.Generator, n: int, degree: float = 8.0, shift: float = 0.05,
                          nonsym: float = 0.0) -> CSR:
     """An unstructured sparse matrix with no grid: n random points in the unit
