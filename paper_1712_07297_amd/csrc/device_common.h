@@ -483,17 +483,17 @@ __device__ inline void mfma_tile64_visit(const v4d acc[2][2], const Fn& f) {
 
 // ------------------------------------------------- BF16 tile core (mixed form)
 // One 64 x 64 tile of D = Left (64 x K) * Right (K x 64) on the BF16 matrix
-// cores with FP32 accumulation (v_mfma_f32_16x16x32_bf16): 4 waves as 2 x 2
+// cores with FP32 accumulation (v_mfma_f32_16x16x16_bf16): 4 waves as 2 x 2
 // quarters of 32 x 32, each 2 x 2 blocks of 16 x 16.  Instruction layout:
-// operand a of lane l holds A[l%16][8(l/16) + i], operand b holds
-// B[8(l/16) + i][l%16] (i = 0..7), result r of lane l is D[4(l/16) + r][l%16].
+// operand a of lane l holds A[l%16][4(l/16) + i], operand b holds
+// B[4(l/16) + i][l%16] (i = 0..3), result r of lane l is D[4(l/16) + r][l%16].
 // As in the FP64 core the transposed block is computed, so lane l%16 indexes
 // rows of D.  Every float operand is split into three BF16 parts
 // x = hi + mid + lo (8 + 8 + 8 significand bits, nearest-even rounding at each
 // step) and the six products whose parts sum to at most 2 are accumulated, so
 // the tile carries float32 accuracy on the BF16 units.
 typedef float v4f __attribute__((ext_vector_type(4)));
-typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef short v4s __attribute__((ext_vector_type(4)));
 constexpr int NSPLIT = 3;
 struct MfmaSmemB {
     unsigned short a[NSPLIT][MKC][MT + 2];  // a[part][k][row] = Left(row, k)
@@ -553,31 +553,28 @@ __device__ inline void mfma_tile64_bf16(int K, const LoadL& la, const LoadR& lb,
         }
         __syncthreads();
         if (k0 + MKC < K) fetch(k0 + MKC);
-        // The six part products as three K = 32 instructions, each holding two
-        // products of the 16 k of this stage side by side (k slots 0-15 the
-        // first, 16-31 the second; lane group lk holds slots 8 lk .. 8 lk + 7),
-        // smallest terms first: (B lo, A hi) + (B hi, A lo), (B mid, A mid) +
-        // (B mid, A hi), (B hi, A mid) + (B hi, A hi).
-        constexpr int PB[3][2] = {{2, 0}, {1, 1}, {0, 0}};  // B part of the first / second product
-        constexpr int PA[3][2] = {{0, 2}, {1, 0}, {1, 0}};  // A part of the first / second product
-        const int half = lk >> 1, k8 = 8 * (lk & 1);
+        v4s av[NSPLIT][2], bv[NSPLIT][2];
 #pragma unroll
-        for (int t = 0; t < 3; ++t) {
-            v8bf av[2], bv[2];
-            const int qa = PA[t][half], qb = PB[t][half];
+        for (int q = 0; q < NSPLIT; ++q)
 #pragma unroll
             for (int i = 0; i < 2; ++i)
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    av[i][u] = __builtin_bit_cast(__bf16, (unsigned short)sm->a[qa][k8 + u][wm + 16 * i + lr]);
-                    bv[i][u] = __builtin_bit_cast(__bf16, (unsigned short)sm->b[qb][k8 + u][wn + 16 * i + lr]);
+                for (int u = 0; u < 4; ++u) {
+                    av[q][i][u] = (short)sm->a[q][4 * lk + u][wm + 16 * i + lr];
+                    bv[q][i][u] = (short)sm->b[q][4 * lk + u][wn + 16 * i + lr];
                 }
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < 2; ++i)
 #pragma unroll
-                for (int j = 0; j < 2; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bv[j], av[i], acc[i][j], 0, 0, 0);
-        }
+            for (int j = 0; j < 2; ++j) {
+                // smallest terms first: (lo,hi) (hi,lo) (mid,mid) (mid,hi) (hi,mid) (hi,hi)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(bv[2][j], av[0][i], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(bv[0][j], av[2][i], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(bv[1][j], av[1][i], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(bv[1][j], av[0][i], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(bv[0][j], av[1][i], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(bv[0][j], av[0][i], acc[i][j], 0, 0, 0);
+            }
     }
 }
 
