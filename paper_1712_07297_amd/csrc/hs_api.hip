@@ -230,7 +230,43 @@ struct Blob {
         data.resize(off + bytes);
         return off;
     }
+    template <class T>
+    size_t zeros(size_t count) {  // count zero-initialised elements
+        return reserve(count * sizeof(T));
+    }
 };
+
+// The level metadata blob of the calling thread, reused from level to level
+// and call to call: its capacity stays, so the host does not fault in fresh
+// pages for tens of megabytes every level (its contents are on the device
+// before the level's synchronisation, which precedes the next reuse).
+static thread_local std::vector<char> t_blob_store;
+struct BlobLease {
+    Blob& b;
+    explicit BlobLease(Blob& blob) : b(blob) { b.data.swap(t_blob_store); }
+    ~BlobLease() {
+        b.data.clear();
+        b.data.swap(t_blob_store);
+    }
+};
+
+// Run fn(0) .. fn(count - 1) on up to `threads` host threads.
+template <class Fn>
+static void parallel_for(int count, int threads, Fn fn) {
+    threads = std::max(1, std::min(threads, count));
+    if (threads == 1) {
+        for (int i = 0; i < count; ++i) fn(i);
+        return;
+    }
+    std::atomic<int> next(0);
+    std::vector<std::thread> pool;
+    for (int t = 0; t < threads; ++t)
+        pool.emplace_back([&] {
+            for (int i = next++; i < count; i = next++) fn(i);
+        });
+    for (auto& th : pool) th.join();
+}
+static int host_threads() { return (int)std::min(16u, std::max(1u, std::thread::hardware_concurrency())); }
 
 // ---------------------------------------------------------------- tracing
 
@@ -543,12 +579,29 @@ static int plan_level(hs_factor_s* F, int lvl, Blob& blob, std::vector<size_t>& 
         cursor += elems * (int64_t)es;
         return o;
     };
+    // every block starts 16-byte aligned, so a cluster's blocks take the sum of
+    // their sizes rounded up to 16 bytes: per-cluster totals in parallel, a
+    // prefix sum, then each cluster's offsets (the same layout as one cursor)
     LD.blk_off.resize(LD.nblk);
-    int64_t cur = 0;
-    for (int a = 0; a < ncl; ++a)
-        for (int e = S.pat_ptr[a]; e < S.pat_ptr[a + 1]; ++e)
-            LD.blk_off[e] = place(cur, (int64_t)m[a] * m[S.pat[e]], LD.esz(a));
-    LD.block_bytes = cur;
+    const int nth = host_threads();
+    std::vector<int64_t> ctot(ncl + 1, 0);
+    parallel_for(nth, nth, [&](int t) {
+        for (int a = (int)((int64_t)ncl * t / nth); a < (int)((int64_t)ncl * (t + 1) / nth); ++a) {
+            int64_t b = 0;
+            for (int e = S.pat_ptr[a]; e < S.pat_ptr[a + 1]; ++e)
+                b += ((int64_t)m[a] * m[S.pat[e]] * (int64_t)LD.esz(a) + 15) & ~int64_t(15);
+            ctot[a + 1] = b;
+        }
+    });
+    for (int a = 0; a < ncl; ++a) ctot[a + 1] += ctot[a];
+    parallel_for(nth, nth, [&](int t) {
+        for (int a = (int)((int64_t)ncl * t / nth); a < (int)((int64_t)ncl * (t + 1) / nth); ++a) {
+            int64_t c = ctot[a];
+            for (int e = S.pat_ptr[a]; e < S.pat_ptr[a + 1]; ++e)
+                LD.blk_off[e] = place(c, (int64_t)m[a] * m[S.pat[e]], LD.esz(a));
+        }
+    });
+    LD.block_bytes = ctot[ncl];
 
     // per-cluster lists (the block ids of every neighbour / fill entry and of
     // all neighbour pairs are found on the device: launch_level_ids,
@@ -598,7 +651,10 @@ static int plan_level(hs_factor_s* F, int lvl, Blob& blob, std::vector<size_t>& 
     };
     std::vector<std::array<ListPre, 2>> spres(S.ncolors);
     std::vector<std::array<std::vector<ListPre>, 2>> fpres(S.ncolors);
-    for (int c = 0; c < S.ncolors; ++c) {
+    std::vector<int64_t> ws_max_c(S.ncolors, 0);
+    // colours touch disjoint slices of order and disjoint clusters: in parallel
+    parallel_for(S.ncolors, nth, [&](int c) {
+        int64_t& ws_max = ws_max_c[c];
         ColourHost& CH = LD.colours[c];
         CH.first = S.color_ptr[c];
         CH.n = S.color_ptr[c + 1] - S.color_ptr[c];
@@ -672,14 +728,15 @@ static int plan_level(hs_factor_s* F, int lvl, Blob& blob, std::vector<size_t>& 
             }
             base += nt;
         }
-    }
+    });
+    for (int c = 0; c < S.ncolors; ++c) ws_max = std::max(ws_max, ws_max_c[c]);
     LD.ws_elems = ws_max;
 
     // blob layout
     offs.clear();
     offs.push_back(blob.add(m));                 // 0 m
     offs.push_back(blob.add(m));                 // 1 k (initialised to m)
-    offs.push_back(blob.add(std::vector<int>(ncl, 0)));  // 2 flag
+    offs.push_back(blob.zeros<int>(ncl));       // 2 flag
     offs.push_back(blob.add(LD.blk_off));        // 3
     offs.push_back(blob.add(S.pos));             // 4 processing position
     offs.push_back(blob.add(S.adj_ptr));         // 5
@@ -687,8 +744,8 @@ static int plan_level(hs_factor_s* F, int lvl, Blob& blob, std::vector<size_t>& 
     offs.push_back(0);                           // 7-9 (LD.ids)
     offs.push_back(0);
     offs.push_back(0);
-    offs.push_back(blob.add(std::vector<int>(S.adj.size(), 0)));  // 10 nbr_noff
-    offs.push_back(blob.add(std::vector<int>(ncl, 0)));           // 11 ntot
+    offs.push_back(blob.zeros<int>(S.adj.size()));  // 10 nbr_noff
+    offs.push_back(blob.zeros<int>(ncl));           // 11 ntot
     offs.push_back(blob.add(ncap));              // 12
     offs.push_back(blob.add(S.fill_ptr));        // 13
     offs.push_back(blob.add(S.fill));            // 14
@@ -704,7 +761,7 @@ static int plan_level(hs_factor_s* F, int lvl, Blob& blob, std::vector<size_t>& 
     offs.push_back(blob.add(order));             // 24 colour slices by type (the work lists)
     LD.order_host = order;
     offs.push_back(blob.add(LD.f32));            // 25 per-cluster storage type
-    offs.push_back(blob.add(std::vector<int>(ncl, 0)));  // 26 fill columns (written by k_offsets)
+    offs.push_back(blob.zeros<int>(ncl));       // 26 fill columns (written by k_offsets)
     auto add_pre = [&](ListPlan& L, const ListPre& lp) {
         L.start = lp.start;
         L.off_pre[0] = blob.add(lp.pre.np);
@@ -916,21 +973,6 @@ static int factor_dense_ranges(hs_factor_s* F, int lvl, const std::vector<std::a
 }
 
 // Run fn(i) for i < count on up to `threads` host threads.
-template <class Fn>
-static void parallel_for(int count, int threads, Fn fn) {
-    threads = std::max(1, std::min(threads, count));
-    if (threads == 1) {
-        for (int i = 0; i < count; ++i) fn(i);
-        return;
-    }
-    std::atomic<int> next(0);
-    std::vector<std::thread> pool;
-    for (int t = 0; t < threads; ++t)
-        pool.emplace_back([&] {
-            for (int i = next++; i < count; i = next++) fn(i);
-        });
-    for (auto& th : pool) th.join();
-}
 
 // Factor nsys independent systems as one block-diagonal system (Alg. 1 on
 // the forest of their cluster trees): every kernel launch of a level and
@@ -1112,6 +1154,7 @@ static int factor_impl(hs_factor_s* F, int nsys, const hs_csr* A, const hs_geome
             if (dn) dense_ranges.push_back({c0, c1});
         }
         Blob blob;
+        BlobLease lease(blob);
         {
             HostScope hs_(PF_H_PLAN);
             rc = plan_level(F, lvl, blob, offs);
