@@ -1380,15 +1380,27 @@ __device__ void merge_block(int b, int P, int Q, const int* __restrict__ pat_ptr
         const TS* sp = blocks_prev + blk_off_prev[src];
         const int lds = m_prev[a];
         if (ka == 0) continue;
-        wg_stage(
-            ka * kc, [&](int x) { return sp[(x % ka) + (int64_t)(x / ka) * lds]; },
-            [&](int x, TS v) { dst[(roff + x % ka) + (int64_t)(coff + x / ka) * ldn] = (TD)v; });
+        // one wave per parent block: four loads in flight per lane
+        const int tot = ka * kc, lane = threadIdx.x & 63;
+        for (int x0 = lane; x0 < tot; x0 += 4 * 64) {
+            TS v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int x = min(x0 + u * 64, tot - 1);
+                v[u] = sp[(x % ka) + (int64_t)(x / ka) * lds];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int x = x0 + u * 64;
+                if (x < tot) dst[(roff + x % ka) + (int64_t)(coff + x / ka) * ldn] = (TD)v[u];
+            }
+        }
     }
 }
 
-// One workgroup per parent block; its row P by binary search over the
-// pattern's row pointers.  Element types per cluster on either side (a
-// system's children and parent may differ).
+// One wave per parent block (four per workgroup); its row P by binary search
+// over the pattern's row pointers.  Element types per cluster on either side
+// (a system's children and parent may differ).
 __global__ void k_merge(const int* __restrict__ pat_ptr_next, const int* __restrict__ pat_next, int ncl_next,
                         const int* __restrict__ pat_ptr_prev, const int* __restrict__ pat_prev, int ncl_prev,
                         const int* __restrict__ k_prev, const int* __restrict__ m_prev,
@@ -1396,7 +1408,8 @@ __global__ void k_merge(const int* __restrict__ pat_ptr_next, const int* __restr
                         const int* __restrict__ f32_prev, const int* __restrict__ m_next,
                         const int64_t* __restrict__ blk_off_next, void* __restrict__ blocks_next,
                         const int* __restrict__ f32_next) {
-    const int b = blockIdx.x;
+    const int b = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (b >= pat_ptr_next[ncl_next]) return;
     int lo = 0, hi = ncl_next;  // last P with pat_ptr_next[P] <= b
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
@@ -1426,7 +1439,7 @@ void launch_merge(int nblk_next, const int* pat_ptr_next, const int* pat_next, i
                   const int64_t* blk_off_prev, const void* blocks_prev, const int* f32_prev, const int* m_next,
                   const int64_t* blk_off_next, void* blocks_next, const int* f32_next, hipStream_t st) {
     if (nblk_next == 0) return;
-    hipLaunchKernelGGL(k_merge, dim3(nblk_next), dim3(256), 0, st, pat_ptr_next, pat_next, ncl_next, pat_ptr_prev,
+    hipLaunchKernelGGL(k_merge, dim3((nblk_next + 3) / 4), dim3(256), 0, st, pat_ptr_next, pat_next, ncl_next, pat_ptr_prev,
                        pat_prev, ncl_prev, k_prev, m_prev, blk_off_prev, blocks_prev, f32_prev, m_next, blk_off_next,
                        blocks_next, f32_next);
 }
