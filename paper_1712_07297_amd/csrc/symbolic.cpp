@@ -9,6 +9,7 @@
 #include "symbolic.h"
 
 #include <algorithm>
+#include <atomic>
 #include <array>
 #include <cstdint>
 #include <cstring>
@@ -548,20 +549,29 @@ void combine_symbolic(std::vector<Symbolic>& parts, bool keep_empty_levels, Symb
     }
 
     out.levels.resize(out.nlevels);
+    // every level on its own, every system's clusters copied into their slice
+    // of the combined arrays; (level, system) tasks on host threads
+    std::vector<std::array<int, 2>> tasks;
+    std::vector<int> alive_of(out.nlevels);
+    struct Base {
+        int64_t adj, fill, pat;
+    };
+    std::vector<std::vector<Base>> base(out.nlevels);
+    std::vector<std::vector<int>> obase(out.nlevels);  // per (system, colour) start in order
     for (int l = 0; l < out.nlevels; ++l) {
         int alive = 0;
         while (alive < ns && F.last[alive] >= l) ++alive;
+        alive_of[l] = alive;
         std::vector<int>& off = F.cl_off[l];
         off.assign(alive + 1, 0);
         int ncolors = 0;
-        size_t nadj = 0, nfill = 0, npat = 0;
+        base[l].assign(alive + 1, Base{0, 0, 0});
         for (int j = 0; j < alive; ++j) {
             const LevelSymbolic& L = parts[F.sys[j]].levels[l];
             off[j + 1] = off[j] + L.ncl;
             ncolors = std::max(ncolors, L.ncolors);
-            nadj += L.adj.size();
-            nfill += L.fill.size();
-            npat += L.pat.size();
+            base[l][j + 1] = Base{base[l][j].adj + (int64_t)L.adj.size(), base[l][j].fill + (int64_t)L.fill.size(),
+                                  base[l][j].pat + (int64_t)L.pat.size()};
         }
         LevelSymbolic& C = out.levels[l];
         C.ncl = off[alive];
@@ -570,38 +580,62 @@ void combine_symbolic(std::vector<Symbolic>& parts, bool keep_empty_levels, Symb
         C.adj_ptr.assign(C.ncl + 1, 0);
         C.fill_ptr.assign(C.ncl + 1, 0);
         C.pat_ptr.assign(C.ncl + 1, 0);
-        C.adj.reserve(nadj);
-        C.fill.reserve(nfill);
-        C.pat.reserve(npat);
-        for (int j = 0; j < alive; ++j) {
-            const LevelSymbolic& L = parts[F.sys[j]].levels[l];
-            const int c0 = off[j];
-            for (int s = 0; s < L.ncl; ++s) {
-                C.color[c0 + s] = L.color[s];
-                for (int e = L.adj_ptr[s]; e < L.adj_ptr[s + 1]; ++e) C.adj.push_back(c0 + L.adj[e]);
-                for (int e = L.fill_ptr[s]; e < L.fill_ptr[s + 1]; ++e) C.fill.push_back(c0 + L.fill[e]);
-                for (int e = L.pat_ptr[s]; e < L.pat_ptr[s + 1]; ++e) C.pat.push_back(c0 + L.pat[e]);
-                C.adj_ptr[c0 + s + 1] = (int)C.adj.size();
-                C.fill_ptr[c0 + s + 1] = (int)C.fill.size();
-                C.pat_ptr[c0 + s + 1] = (int)C.pat.size();
-            }
-        }
+        C.adj.resize(base[l][alive].adj);
+        C.fill.resize(base[l][alive].fill);
+        C.pat.resize(base[l][alive].pat);
         // processing order: colour by colour, systems in placement order
-        C.order.clear();
-        C.order.reserve(C.ncl);
         C.color_ptr.assign(ncolors + 1, 0);
+        obase[l].assign((size_t)alive * ncolors, 0);
+        int w = 0;
         for (int c = 0; c < ncolors; ++c) {
             for (int j = 0; j < alive; ++j) {
                 const LevelSymbolic& L = parts[F.sys[j]].levels[l];
-                if (c >= L.ncolors) continue;
-                for (int x = L.color_ptr[c]; x < L.color_ptr[c + 1]; ++x) C.order.push_back(off[j] + L.order[x]);
+                obase[l][(size_t)j * ncolors + c] = w;
+                if (c < L.ncolors) w += L.color_ptr[c + 1] - L.color_ptr[c];
             }
-            C.color_ptr[c + 1] = (int)C.order.size();
+            C.color_ptr[c + 1] = w;
         }
-        C.pos.assign(C.ncl, 0);
-        for (int x = 0; x < C.ncl; ++x) C.pos[C.order[x]] = x;
-        for (int j = 0; j < alive; ++j) parts[F.sys[j]].levels[l] = LevelSymbolic();
+        C.order.resize(C.ncl);
+        C.pos.resize(C.ncl);
+        for (int j = 0; j < alive; ++j) tasks.push_back({l, j});
     }
+    auto task = [&](int q) {
+        const int l = tasks[q][0], j = tasks[q][1];
+        LevelSymbolic& C = out.levels[l];
+        const LevelSymbolic& L = parts[F.sys[j]].levels[l];
+        const int c0 = F.cl_off[l][j];
+        const Base& b = base[l][j];
+        for (int s = 0; s < L.ncl; ++s) {
+            C.color[c0 + s] = L.color[s];
+            C.adj_ptr[c0 + s + 1] = (int)(b.adj + L.adj_ptr[s + 1]);
+            C.fill_ptr[c0 + s + 1] = (int)(b.fill + L.fill_ptr[s + 1]);
+            C.pat_ptr[c0 + s + 1] = (int)(b.pat + L.pat_ptr[s + 1]);
+        }
+        for (size_t e = 0; e < L.adj.size(); ++e) C.adj[b.adj + e] = c0 + L.adj[e];
+        for (size_t e = 0; e < L.fill.size(); ++e) C.fill[b.fill + e] = c0 + L.fill[e];
+        for (size_t e = 0; e < L.pat.size(); ++e) C.pat[b.pat + e] = c0 + L.pat[e];
+        for (int c = 0; c < L.ncolors; ++c) {
+            int w = obase[l][(size_t)j * C.ncolors + c];
+            for (int x = L.color_ptr[c]; x < L.color_ptr[c + 1]; ++x, ++w) {
+                C.order[w] = c0 + L.order[x];
+                C.pos[c0 + L.order[x]] = w;
+            }
+        }
+    };
+    const int nth = (int)std::min<size_t>(tasks.size(), std::min(16u, std::max(1u, std::thread::hardware_concurrency())));
+    if (nth <= 1) {
+        for (int q = 0; q < (int)tasks.size(); ++q) task(q);
+    } else {
+        std::atomic<int> next(0);
+        std::vector<std::thread> pool;
+        for (int t = 0; t < nth; ++t)
+            pool.emplace_back([&] {
+                for (int q = next++; q < (int)tasks.size(); q = next++) task(q);
+            });
+        for (auto& th : pool) th.join();
+    }
+    for (int l = 0; l < out.nlevels; ++l)
+        for (int j = 0; j < alive_of[l]; ++j) parts[F.sys[j]].levels[l] = LevelSymbolic();
 }
 
 }  // namespace hs
