@@ -489,7 +489,7 @@ int hs_set_allocator(void* (*alloc_fn)(size_t, void*, void*), void (*free_fn)(vo
  *                                  memory beyond
  *   wy_max           128, 0..128   its Q formed through the compact WY form
  *                                  while the coarse size is at most this
- *   gram_splits_max  256, 1..256   partial sums of the fill's Gram matrix
+ *   gram_splits_max  4, 1..256     partial sums of the fill's Gram matrix
  *                                  (Eq. lra) per cluster at most
  *   schur_ptab_max   256, 0..256   Schur tile (Eq. elim): block pointers of
  *                                  its neighbour pairs staged in LDS while

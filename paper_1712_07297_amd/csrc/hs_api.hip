@@ -431,7 +431,10 @@ struct LevelData {
 // Process-wide kernel-variant thresholds (hs_config_set), copied into a
 // factorization when it starts; the variants compute the same numbers.
 struct Config {
-    Knobs kn{LDS_M, TRI_MFMA_MAX, TRI_MFMA_MAX12, 64, 128, TRI_MFMA_MAX, GRAM_SPLITS_MAX, 256, 1024, 1, 0};
+    // gram_splits_max 4: measured faster than one partner per workgroup on the
+    // batched convection-diffusion workload (fewer partial Gram matrices to
+    // write and sum)
+    Knobs kn{LDS_M, TRI_MFMA_MAX, TRI_MFMA_MAX12, 64, 128, TRI_MFMA_MAX, 4, 256, 1024, 1, 0};
     int dense_panel = 128;
     int apply_fwd = 0;              // forward solve step: 0 by cost, 1 one launch, 2 two launches
     int compression = 0;            // rank revelation: 0 by eps and cap, 1 pivoted QR, 2 Gram

@@ -12,7 +12,7 @@ DEFAULTS = {
     "qr_reg1_max": 64,
     "qr_reg2_max": 128,
     "wy_max": 128,
-    "gram_splits_max": 256,
+    "gram_splits_max": 4,
     "schur_ptab_max": 256,
     "schur_noff_max": 1024,
     "cholqr": 1,

@@ -93,6 +93,7 @@ FORCED = [
     ("complement_two_slots", dict(qr_reg1_max=0), ["p3d", "nonsym"]),
     ("complement_in_memory", dict(qr_reg1_max=0, qr_reg2_max=0), ["p3d", "nonsym"]),
     ("complement_q_without_wy", dict(wy_max=0), ["p3d", "nonsym"]),
+    ("gram_one_partner_each", dict(gram_splits_max=256), ["p3d", "nonsym"]),
     ("gram_partners_shared", dict(gram_splits_max=2), ["p3d", "nonsym"]),
     ("gram_single_partial", dict(gram_splits_max=1), ["p3d"]),
     ("schur_no_pointer_table", dict(schur_ptab_max=0), ["p3d", "nonsym", "p2d_exact"]),
