@@ -218,8 +218,8 @@ struct DevBuf {
 // Host blob of aligned arrays uploaded in one copy.
 struct Blob {
     std::vector<char> data;
-    template <class T>
-    size_t add(const std::vector<T>& v) {
+    template <class T, class A>
+    size_t add(const std::vector<T, A>& v) {
         size_t off = (data.size() + 255) & ~size_t(255);
         data.resize(off + v.size() * sizeof(T));
         if (!v.empty()) std::memcpy(data.data() + off, v.data(), v.size() * sizeof(T));
@@ -542,16 +542,26 @@ static std::vector<ConfigEntry> config_table(Config& c) {
 
 // =============================================================== validation
 
-static int validate_csr_host(int64_t n, int64_t nnz, const int64_t* rp, const int32_t* ci) {
-    if (rp[0] != 0 || rp[n] != nnz) return fail(HS_ERR_PATTERN, "row_ptr[0] must be 0 and row_ptr[n] = nnz");
+// The first defect of a host CSR pattern: 0 = none, 1 = bad ends, 2 = row_ptr
+// decreasing, 3 = column out of range, 4 = columns not sorted / unique.
+static int csr_defect(int64_t n, int64_t nnz, const int64_t* rp, const int32_t* ci) {
+    if (rp[0] != 0 || rp[n] != nnz) return 1;
     for (int64_t i = 0; i < n; ++i) {
-        if (rp[i + 1] < rp[i]) return fail(HS_ERR_PATTERN, "row_ptr not non-decreasing");
+        if (rp[i + 1] < rp[i]) return 2;
         for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
-            if (ci[e] < 0 || ci[e] >= n) return fail(HS_ERR_PATTERN, "column index out of range");
-            if (e > rp[i] && ci[e] <= ci[e - 1]) return fail(HS_ERR_PATTERN, "column indices not sorted / unique");
+            if (ci[e] < 0 || ci[e] >= n) return 3;
+            if (e > rp[i] && ci[e] <= ci[e - 1]) return 4;
         }
     }
-    return HS_OK;
+    return 0;
+}
+static int csr_defect_error(int d) {
+    static const char* msg[] = {"", "row_ptr[0] must be 0 and row_ptr[n] = nnz", "row_ptr not non-decreasing",
+                                "column index out of range", "column indices not sorted / unique"};
+    return d ? fail(HS_ERR_PATTERN, msg[d]) : HS_OK;
+}
+static int validate_csr_host(int64_t n, int64_t nnz, const int64_t* rp, const int32_t* ci) {
+    return csr_defect_error(csr_defect(n, nnz, rp, ci));
 }
 
 // ================================================================ planning
@@ -975,7 +985,117 @@ static int factor_dense_ranges(hs_factor_s* F, int lvl, const std::vector<std::a
     return HS_OK;
 }
 
-// Run fn(i) for i < count on up to `threads` host threads.
+// ---- solve plan of one level (Alg. 2 metadata; needs the level's ranks).
+// The host part runs while the next level's kernels are on the device; the
+// metadata is uploaded once every level is planned.
+struct SolveGroupOffsets {
+    size_t part = 0, pre = 0, e0 = 0, e1 = 0;  // blob offsets: part offsets, group prefix, entry ranges
+};
+struct SolvePlan {
+    Blob blob;
+    size_t seg = 0;
+    std::vector<std::array<SolveGroupOffsets, 2>> grp;  // per colour and type
+    double rec_bytes = 0.0, apply_flops = 0.0;
+};
+
+static void plan_solve_level(hs_factor_s* F, int lvl, SolvePlan& P) {
+    LevelData& LD = F->levels[lvl];
+    const LevelSymbolic& S = F->sym.levels[lvl];
+    Blob& sb = P.blob;
+    P.seg = sb.add(LD.seg);
+    P.grp.assign(LD.colours.size(), {});
+    // neighbour groups of the backward sweep: consecutive entries of a
+    // cluster's list up to SOLVE_GROUP_COLS columns of E_R and
+    // SOLVE_GROUP_ENTRIES entries; one f x nrhs partial per group
+    LD.part_max = 0;
+    for (size_t c = 0; c < LD.colours.size(); ++c) {
+        ColourHost& CH = LD.colours[c];
+        for (int t = 0; t < 2; ++t) {
+            std::vector<int64_t> po;
+            std::vector<int> pre(1, 0), ge0, ge1;
+            int64_t acc = 0;
+            // forward step in one launch: every neighbour-row workgroup
+            // forms z_s[:f] = T_L'[:f] y_s again (f m reads each); in two,
+            // z_s is formed once and read back
+            double own_elems = 0.0, reformed_elems = 0.0;
+            int max_nt = 0;
+            for (int i = 0; i < CH.n_t[t]; ++i) {
+                const int s = LD.order_host[CH.first + (t ? CH.n_t[0] : 0) + i];
+                const int f = LD.m[s] - LD.k[s];
+                own_elems += (double)LD.m[s] * LD.m[s];
+                int nt_s = 0;
+                for (int e = S.adj_ptr[s]; e < S.adj_ptr[s + 1]; ++e) {
+                    const int a = S.adj[e];
+                    nt_s += S.pos[a] < S.pos[s] ? LD.k[a] : LD.m[a];
+                }
+                max_nt = std::max(max_nt, nt_s);
+                int ng = 0;
+                if (LD.m[s] > 0 && f > 0) {
+                    int cols = 0;
+                    for (int e = S.adj_ptr[s]; e < S.adj_ptr[s + 1]; ++e) {
+                        const int a = S.adj[e];
+                        const int ca = S.pos[a] < S.pos[s] ? LD.k[a] : LD.m[a];
+                        reformed_elems += (double)((ca + 63) / 64) * f * LD.m[s];
+                        const bool open = ng > 0 && ge1.back() == e;
+                        if (open && cols + ca <= SOLVE_GROUP_COLS && e - ge0.back() < SOLVE_GROUP_ENTRIES) {
+                            ge1.back() = e + 1;
+                            cols += ca;
+                        } else {
+                            ge0.push_back(e);
+                            ge1.push_back(e + 1);
+                            po.push_back(acc);
+                            acc += f;
+                            cols = ca;
+                            ++ng;
+                        }
+                    }
+                }
+                pre.push_back(pre.back() + ng);
+            }
+            po.push_back(acc);
+            CH.part_total[t] = acc;
+            CH.sol[t].grp_total = pre.back();
+            CH.sol[t].fwd_split = F->cfg.apply_fwd == 2 || (F->cfg.apply_fwd == 0 && reformed_elems > 2.0 * own_elems);
+            CH.sol[t].max_nt = max_nt;
+            LD.part_max = std::max(LD.part_max, acc);
+            P.grp[c][t] = {sb.add(po), sb.add(pre), sb.add(ge0), sb.add(ge1)};
+        }
+    }
+    P.rec_bytes = P.apply_flops = 0.0;
+    for (int c = 0; c < LD.ncl; ++c) {
+        const double m = LD.m[c], k = LD.k[c], f = m - k;
+        if (LD.m[c] == 0 || LD.k[c] == LD.m[c]) continue;
+        int nt = 0;
+        for (int e = S.adj_ptr[c]; e < S.adj_ptr[c + 1]; ++e) {
+            const int a = S.adj[e];
+            nt += S.pos[a] < S.pos[c] ? LD.k[a] : LD.m[a];
+        }
+        P.rec_bytes += (double)LD.esz(c) * (2.0 * m * m + 2.0 * f * nt);
+        P.apply_flops += 4.0 * m * m + 4.0 * f * nt;
+    }
+}
+
+// Upload a level's solve metadata (after its block store is no longer needed:
+// the buffer takes the block store's slot) and point the colours at it.
+static int bind_solve_level(hs_factor_s* F, int lvl, SolvePlan& P, hipStream_t st) {
+    LevelData& LD = F->levels[lvl];
+    const Blob& sb = P.blob;
+    DevBuf buf;
+    if (!buf.alloc(sb.data.size())) return fail(HS_ERR_NOMEM, "solve metadata");
+    HIP_TRY(hipMemcpyAsync(buf.p, sb.data.data(), sb.data.size(), hipMemcpyHostToDevice, st));
+    LD.sdev.seg = (const int64_t*)(buf.as<char>() + P.seg);
+    for (size_t c = 0; c < LD.colours.size(); ++c)
+        for (int t = 0; t < 2; ++t) {
+            ColourHost& CH = LD.colours[c];
+            const char* b = buf.as<char>();
+            CH.part_off[t] = (const int64_t*)(b + P.grp[c][t].part);
+            CH.sol[t].grp_pre = (const int*)(b + P.grp[c][t].pre);
+            CH.sol[t].grp_e0 = (const int*)(b + P.grp[c][t].e0);
+            CH.sol[t].grp_e1 = (const int*)(b + P.grp[c][t].e1);
+        }
+    LD.blocks = std::move(buf);  // the block store slot now owns the solve metadata
+    return HS_OK;
+}
 
 // Factor nsys independent systems as one block-diagonal system (Alg. 1 on
 // the forest of their cluster trees): every kernel launch of a level and
@@ -994,8 +1114,8 @@ static int factor_impl(hs_factor_s* F, int nsys, const hs_csr* A, const hs_geome
     if (n > INT32_MAX) return fail(HS_ERR_ARG, "more than 2^31 - 1 unknowns in total");
     F->n = n;
     // ---- host copies of the patterns (the symbolic analysis needs them)
-    std::vector<std::vector<int64_t>> rp_h(nsys);
-    std::vector<std::vector<int32_t>> ci_h(nsys);
+    std::vector<i64vec> rp_h(nsys);  // filled by the copies below (no zeroing first)
+    std::vector<ivec> ci_h(nsys);
     std::vector<const int64_t*> rp(nsys);
     std::vector<const int32_t*> ci(nsys);
     bool dev_copy = false;
@@ -1017,9 +1137,15 @@ static int factor_impl(hs_factor_s* F, int nsys, const hs_csr* A, const hs_geome
         }
     }
     if (dev_copy) HIP_TRY(hipStreamSynchronize(st));
-    for (int i = 0; i < nsys; ++i) {
-        rc = validate_csr_host(A[i].n, A[i].nnz, rp[i], ci[i]);
-        if (rc) return nsys > 1 ? fail(rc, "system " + std::to_string(i) + ": " + g_err) : rc;
+    {  // the systems' patterns checked on host threads, the first defect reported
+        std::vector<int> defect(nsys, 0);
+        parallel_for(nsys, std::min(host_threads(), 16),
+                     [&](int i) { defect[i] = csr_defect(A[i].n, A[i].nnz, rp[i], ci[i]); });
+        for (int i = 0; i < nsys; ++i)
+            if (defect[i]) {
+                rc = csr_defect_error(defect[i]);
+                return nsys > 1 ? fail(rc, "system " + std::to_string(i) + ": " + g_err) : rc;
+            }
     }
     // ---- device copy of A: block diagonal, systems in the caller's order
     if (!F->A_row.alloc((n + 1) * sizeof(int64_t)) || !F->A_col.alloc(nnz * sizeof(int32_t) + 4) ||
@@ -1085,6 +1211,7 @@ static int factor_impl(hs_factor_s* F, int nsys, const hs_csr* A, const hs_geome
     if (nlev > 64) return fail(HS_ERR_UNSUPPORTED, "more than 64 levels");
     F->levels.clear();
     F->levels.resize(nlev);
+    std::vector<SolvePlan> splans(nlev);
     if (!F->cluster_of.alloc(n * sizeof(int)) || !F->local_of.alloc(n * sizeof(int)))
         return fail(HS_ERR_NOMEM, "dof maps");
     HIP_TRY(hipMemcpyAsync(F->cluster_of.p, F->sym.cluster_of.data(), n * sizeof(int), hipMemcpyHostToDevice, st));
@@ -1198,8 +1325,8 @@ static int factor_impl(hs_factor_s* F, int nsys, const hs_csr* A, const hs_geome
                              prev->dev.k, prev->dev.m, prev->dev.blk_off, prev->blocks.p, prev->dev_f32, LD.dev.m,
                              LD.dev.blk_off, LD.blocks.p, LD.dev_f32, st);
             }
-            HostScope hs_(PF_H_SYNC);
-            HIP_TRY(hipStreamSynchronize(st));  // the children's blocks are freed below
+            // the children's blocks go back to the stream-ordered allocator:
+            // a later allocation on this stream runs after the merge
             prev->blocks.release();
             prev->dev.blocks = nullptr;
         }
@@ -1253,6 +1380,11 @@ static int factor_impl(hs_factor_s* F, int nsys, const hs_csr* A, const hs_geome
                 }
             }
         HIP_TRY(hipGetLastError());
+        // the previous level's solve plan on the host while this level runs
+        if (lvl > 0) {
+            HostScope hs_(PF_H_SOLVE_PLAN);
+            plan_solve_level(F, lvl - 1, splans[lvl - 1]);
+        }
         // ranks decide the next level's sizes: one synchronisation per level
         LD.k.resize(LD.ncl);
         std::vector<int> flag(LD.ncl), ntot(LD.ncl), hdflag(dense_ranges.size(), 0);
@@ -1346,101 +1478,19 @@ static int factor_impl(hs_factor_s* F, int nsys, const hs_csr* A, const hs_geome
     }
     F->ws.release();
 
-    // ---- solve plan (needs every rank): segments, part offsets per colour and type
+    // ---- solve plan: the last level's host part, then every level's metadata uploaded
+    {
+        HostScope hs_solve(PF_H_SOLVE_PLAN);
+        plan_solve_level(F, nlev - 1, splans[nlev - 1]);
+        for (int lvl = 0; lvl < nlev; ++lvl) {
+            rc = bind_solve_level(F, lvl, splans[lvl], st);
+            if (rc) return rc;
+        }
+    }
     double rec_bytes = 0.0, apply_flops = 0.0;
-    HostScope hs_solve(PF_H_SOLVE_PLAN);
-    for (int lvl = 0; lvl < nlev; ++lvl) {
-        LevelData& LD = F->levels[lvl];
-        const LevelSymbolic& S = F->sym.levels[lvl];
-        Blob sb;
-        size_t o_seg = sb.add(LD.seg);
-        // neighbour groups of the backward sweep: consecutive entries of a
-        // cluster's list up to SOLVE_GROUP_COLS columns of E_R and
-        // SOLVE_GROUP_ENTRIES entries; one f x nrhs partial per group
-        struct GroupPlan {
-            size_t part, pre, e0, e1;
-        };
-        std::vector<std::array<GroupPlan, 2>> o_grp(LD.colours.size());
-        LD.part_max = 0;
-        for (size_t c = 0; c < LD.colours.size(); ++c) {
-            ColourHost& CH = LD.colours[c];
-            for (int t = 0; t < 2; ++t) {
-                std::vector<int64_t> po;
-                std::vector<int> pre(1, 0), ge0, ge1;
-                int64_t acc = 0;
-                // forward step in one launch: every neighbour-row workgroup
-                // forms z_s[:f] = T_L'[:f] y_s again (f m reads each); in two,
-                // z_s is formed once and read back
-                double own_elems = 0.0, reformed_elems = 0.0;
-                int max_nt = 0;
-                for (int i = 0; i < CH.n_t[t]; ++i) {
-                    const int s = LD.order_host[CH.first + (t ? CH.n_t[0] : 0) + i];
-                    const int f = LD.m[s] - LD.k[s];
-                    own_elems += (double)LD.m[s] * LD.m[s];
-                    int nt_s = 0;
-                    for (int e = S.adj_ptr[s]; e < S.adj_ptr[s + 1]; ++e) {
-                        const int a = S.adj[e];
-                        nt_s += S.pos[a] < S.pos[s] ? LD.k[a] : LD.m[a];
-                    }
-                    max_nt = std::max(max_nt, nt_s);
-                    int ng = 0;
-                    if (LD.m[s] > 0 && f > 0) {
-                        int cols = 0;
-                        for (int e = S.adj_ptr[s]; e < S.adj_ptr[s + 1]; ++e) {
-                            const int a = S.adj[e];
-                            const int ca = S.pos[a] < S.pos[s] ? LD.k[a] : LD.m[a];
-                            reformed_elems += (double)((ca + 63) / 64) * f * LD.m[s];
-                            const bool open = ng > 0 && ge1.back() == e;
-                            if (open && cols + ca <= SOLVE_GROUP_COLS && e - ge0.back() < SOLVE_GROUP_ENTRIES) {
-                                ge1.back() = e + 1;
-                                cols += ca;
-                            } else {
-                                ge0.push_back(e);
-                                ge1.push_back(e + 1);
-                                po.push_back(acc);
-                                acc += f;
-                                cols = ca;
-                                ++ng;
-                            }
-                        }
-                    }
-                    pre.push_back(pre.back() + ng);
-                }
-                po.push_back(acc);
-                CH.part_total[t] = acc;
-                CH.sol[t].grp_total = pre.back();
-                CH.sol[t].fwd_split = F->cfg.apply_fwd == 2 || (F->cfg.apply_fwd == 0 && reformed_elems > 2.0 * own_elems);
-                CH.sol[t].max_nt = max_nt;
-                LD.part_max = std::max(LD.part_max, acc);
-                o_grp[c][t] = {sb.add(po), sb.add(pre), sb.add(ge0), sb.add(ge1)};
-            }
-        }
-        // keep the solve metadata next to the level metadata
-        DevBuf buf;
-        if (!buf.alloc(sb.data.size())) return fail(HS_ERR_NOMEM, "solve metadata");
-        HIP_TRY(hipMemcpyAsync(buf.p, sb.data.data(), sb.data.size(), hipMemcpyHostToDevice, st));
-        LD.sdev.seg = (const int64_t*)(buf.as<char>() + o_seg);
-        for (size_t c = 0; c < LD.colours.size(); ++c)
-            for (int t = 0; t < 2; ++t) {
-                ColourHost& CH = LD.colours[c];
-                const char* b = buf.as<char>();
-                CH.part_off[t] = (const int64_t*)(b + o_grp[c][t].part);
-                CH.sol[t].grp_pre = (const int*)(b + o_grp[c][t].pre);
-                CH.sol[t].grp_e0 = (const int*)(b + o_grp[c][t].e0);
-                CH.sol[t].grp_e1 = (const int*)(b + o_grp[c][t].e1);
-            }
-        LD.blocks = std::move(buf);  // the block store slot now owns the solve metadata
-        for (int c = 0; c < LD.ncl; ++c) {
-            const double m = LD.m[c], k = LD.k[c], f = m - k;
-            if (LD.m[c] == 0 || LD.k[c] == LD.m[c]) continue;
-            int nt = 0;
-            for (int e = S.adj_ptr[c]; e < S.adj_ptr[c + 1]; ++e) {
-                const int a = S.adj[e];
-                nt += S.pos[a] < S.pos[c] ? LD.k[a] : LD.m[a];
-            }
-            rec_bytes += (double)LD.esz(c) * (2.0 * m * m + 2.0 * f * nt);
-            apply_flops += 4.0 * m * m + 4.0 * f * nt;
-        }
+    for (const SolvePlan& sp : splans) {
+        rec_bytes += sp.rec_bytes;
+        apply_flops += sp.apply_flops;
     }
     // solve vector layout: y, z and out of every level, level after level
     F->vec_off.assign(nlev + 1, 0);
@@ -2195,7 +2245,7 @@ int hs_symbolic_arrays(hs_symbolic_t S, int32_t level, int32_t* colors, int32_t*
                        int32_t* fill_ptr, int32_t* fill, int32_t* pat_ptr, int32_t* pat) {
     if (!S || level < 0 || level >= S->sym.nlevels) return fail(HS_ERR_ARG, "bad level");
     const auto& L = S->sym.levels[level];
-    auto cp = [](const std::vector<int>& v, int32_t* o) {
+    auto cp = [](const ivec& v, int32_t* o) {
         if (o) std::copy(v.begin(), v.end(), o);
     };
     cp(L.color, colors);

@@ -38,8 +38,7 @@ constexpr int DENSE_MAX = 1 << 14;  // levels up to this many clusters use word 
 // Greedy distance-2 colouring by ascending index; returns the colour count.
 // Word-bitset form: the clusters within distance 2 of i are the union of
 // N(j) + {j} over j in N(i); those below i are already coloured.
-int colour_distance2_bits(int ncl, const std::vector<int>& ptr, const std::vector<int>& adj,
-                          std::vector<int>& color) {
+int colour_distance2_bits(int ncl, const ivec& ptr, const ivec& adj, ivec& color) {
     const int w = (ncl + 63) >> 6;
     std::vector<uint64_t> nb((size_t)ncl * w, 0), d(w);
     for (int j = 0; j < ncl; ++j) {
@@ -73,8 +72,7 @@ int colour_distance2_bits(int ncl, const std::vector<int>& ptr, const std::vecto
     return ncolors;
 }
 
-int colour_distance2(int ncl, const std::vector<int>& ptr, const std::vector<int>& adj,
-                     std::vector<int>& color) {
+int colour_distance2(int ncl, const ivec& ptr, const ivec& adj, ivec& color) {
     if (ncl <= DENSE_MAX) return colour_distance2_bits(ncl, ptr, adj, color);
     color.assign(ncl, -1);
     std::vector<int> mark;  // mark[c] == i  <=> colour c used near i
@@ -145,7 +143,7 @@ class Pattern {
     std::vector<std::vector<int>> rows_;
 };
 
-void simulate_level(LevelSymbolic& L, std::vector<int>& next_ptr, std::vector<int>& next_adj) {
+void simulate_level(LevelSymbolic& L, ivec& next_ptr, ivec& next_adj) {
     const int ncl = L.ncl;
     L.ncolors = colour_distance2(ncl, L.adj_ptr, L.adj, L.color);
     L.order.resize(ncl);
@@ -182,20 +180,10 @@ void simulate_level(LevelSymbolic& L, std::vector<int>& next_ptr, std::vector<in
                 for (int f = L.adj_ptr[s]; f < L.adj_ptr[s + 1]; ++f) P.add(L.adj[e], L.adj[f]);
         }
     }
-    // every fill list in processing order; the lists are independent, so
-    // large levels sort them on several threads
-    auto sort_fill = [&](int c0, int c1) {
-        for (int c = c0; c < c1; ++c)
-            std::sort(fill[c].begin(), fill[c].end(), [&](int a, int b) { return L.pos[a] < L.pos[b]; });
-    };
-    const int nth = ncl >= 512 ? (int)std::min(8u, std::max(1u, std::thread::hardware_concurrency())) : 1;
-    if (nth > 1) {
-        std::vector<std::thread> th;
-        for (int i = 0; i < nth; ++i) th.emplace_back(sort_fill, (int)((int64_t)ncl * i / nth), (int)((int64_t)ncl * (i + 1) / nth));
-        for (auto& t : th) t.join();
-    } else {
-        sort_fill(0, ncl);
-    }
+    // every fill list in processing order (the caller runs systems on
+    // several host threads, so a level sorts its short lists on one)
+    for (int c = 0; c < ncl; ++c)
+        std::sort(fill[c].begin(), fill[c].end(), [&](int a, int b) { return L.pos[a] < L.pos[b]; });
     L.fill_ptr.assign(ncl + 1, 0);
     L.fill.clear();
     for (int s = 0; s < ncl; ++s) {
@@ -280,7 +268,7 @@ static int finish_symbolic(int64_t n, const int64_t* row_ptr, const int32_t* col
     S.levels.clear();
     S.levels.push_back(std::move(L0));
     for (int lvl = 0; lvl < S.nlevels; ++lvl) {
-        std::vector<int> nptr, nadj;
+        ivec nptr, nadj;
         simulate_level(S.levels[lvl], nptr, nadj);
         if (lvl + 1 < S.nlevels) {
             LevelSymbolic N;
@@ -520,32 +508,51 @@ void combine_symbolic(std::vector<Symbolic>& parts, bool keep_empty_levels, Symb
     for (auto& P : parts) out.depth = std::max(out.depth, P.depth);
     F.cl_off.assign(out.nlevels, {});
 
-    // leaves: placement order; unknown ids in the caller's system order
+    const int hw = (int)std::min(16u, std::max(1u, std::thread::hardware_concurrency()));
+    // run fn(q) for q < count on up to hw host threads
+    auto run = [&](int count, const auto& fn) {
+        const int nth = std::min(count, hw);
+        if (nth <= 1) {
+            for (int q = 0; q < count; ++q) fn(q);
+            return;
+        }
+        std::atomic<int> next(0);
+        std::vector<std::thread> pool;
+        for (int t = 0; t < nth; ++t)
+            pool.emplace_back([&] {
+                for (int q = next++; q < count; q = next++) fn(q);
+            });
+        for (auto& th : pool) th.join();
+    };
+
+    // leaves in placement order; unknown ids in the caller's system order.
+    // Each system fills its own slices (leaf_ptr after its first leaf, its
+    // rows of cluster_of and local_of), so the systems run on host threads.
     {
         std::vector<int> off(ns + 1, 0);
-        for (int j = 0; j < ns; ++j) off[j + 1] = off[j] + parts[F.sys[j]].levels[0].ncl;
-        const int nleaf = off[ns];
-        out.leaf_ptr.assign(nleaf + 1, 0);
-        out.leaf_dofs.resize(out.n);
-        out.cluster_of.assign(out.n, -1);
-        out.local_of.assign(out.n, -1);
-        int64_t w = 0;
+        std::vector<int64_t> dof0(ns + 1, 0);  // first leaf entry of every placement
         for (int j = 0; j < ns; ++j) {
+            off[j + 1] = off[j] + parts[F.sys[j]].levels[0].ncl;
+            dof0[j + 1] = dof0[j] + parts[F.sys[j]].n;
+        }
+        const int nleaf = off[ns];
+        out.leaf_ptr.resize(nleaf + 1);
+        out.leaf_ptr[0] = 0;
+        out.cluster_of.resize(out.n);
+        out.local_of.resize(out.n);
+        run(ns, [&](int j) {
             Symbolic& P = parts[F.sys[j]];
             const int64_t r0 = F.row_off[F.sys[j]];
             const int c0 = off[j];
-            for (int c = 0; c < P.levels[0].ncl; ++c) {
-                for (int e = P.leaf_ptr[c]; e < P.leaf_ptr[c + 1]; ++e) out.leaf_dofs[w++] = r0 + P.leaf_dofs[e];
-                out.leaf_ptr[c0 + c + 1] = (int)w;
-            }
+            for (int c = 0; c < P.levels[0].ncl; ++c) out.leaf_ptr[c0 + c + 1] = (int)(dof0[j] + P.leaf_ptr[c + 1]);
             for (int64_t i = 0; i < P.n; ++i) {
                 out.cluster_of[r0 + i] = c0 + P.cluster_of[i];
                 out.local_of[r0 + i] = P.local_of[i];
             }
-            std::vector<int>().swap(P.cluster_of);
-            std::vector<int>().swap(P.local_of);
-            std::vector<int64_t>().swap(P.leaf_dofs);
-        }
+            ivec().swap(P.cluster_of);
+            ivec().swap(P.local_of);
+            i64vec().swap(P.leaf_dofs);
+        });
     }
 
     out.levels.resize(out.nlevels);
@@ -576,10 +583,13 @@ void combine_symbolic(std::vector<Symbolic>& parts, bool keep_empty_levels, Symb
         LevelSymbolic& C = out.levels[l];
         C.ncl = off[alive];
         C.ncolors = ncolors;
+        // every entry below is written by the (level, system) tasks, except
+        // the leading zeros of the row pointers
         C.color.resize(C.ncl);
-        C.adj_ptr.assign(C.ncl + 1, 0);
-        C.fill_ptr.assign(C.ncl + 1, 0);
-        C.pat_ptr.assign(C.ncl + 1, 0);
+        C.adj_ptr.resize(C.ncl + 1);
+        C.fill_ptr.resize(C.ncl + 1);
+        C.pat_ptr.resize(C.ncl + 1);
+        C.adj_ptr[0] = C.fill_ptr[0] = C.pat_ptr[0] = 0;
         C.adj.resize(base[l][alive].adj);
         C.fill.resize(base[l][alive].fill);
         C.pat.resize(base[l][alive].pat);
@@ -622,18 +632,7 @@ void combine_symbolic(std::vector<Symbolic>& parts, bool keep_empty_levels, Symb
             }
         }
     };
-    const int nth = (int)std::min<size_t>(tasks.size(), std::min(16u, std::max(1u, std::thread::hardware_concurrency())));
-    if (nth <= 1) {
-        for (int q = 0; q < (int)tasks.size(); ++q) task(q);
-    } else {
-        std::atomic<int> next(0);
-        std::vector<std::thread> pool;
-        for (int t = 0; t < nth; ++t)
-            pool.emplace_back([&] {
-                for (int q = next++; q < (int)tasks.size(); q = next++) task(q);
-            });
-        for (auto& th : pool) th.join();
-    }
+    run((int)tasks.size(), task);
     for (int l = 0; l < out.nlevels; ++l)
         for (int j = 0; j < alive_of[l]; ++j) parts[F.sys[j]].levels[l] = LevelSymbolic();
 }

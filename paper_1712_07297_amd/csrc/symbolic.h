@@ -5,20 +5,47 @@
 #pragma once
 
 #include <cstdint>
+#include <memory>
+#include <new>
+#include <utility>
 #include <vector>
 
 namespace hs {
 
+// Allocator whose value construction leaves scalars uninitialised: resize(n)
+// on a vector of it allocates without zeroing, so arrays that are written in
+// full afterwards (on several host threads) are touched once, by the writers.
+template <class T>
+struct NoInitAlloc : std::allocator<T> {
+    template <class U>
+    struct rebind {
+        using other = NoInitAlloc<U>;
+    };
+    NoInitAlloc() = default;
+    template <class U>
+    NoInitAlloc(const NoInitAlloc<U>&) noexcept {}
+    template <class U>
+    void construct(U* p) noexcept {
+        ::new ((void*)p) U;
+    }
+    template <class U, class... Args>
+    void construct(U* p, Args&&... args) {
+        ::new ((void*)p) U(std::forward<Args>(args)...);
+    }
+};
+using ivec = std::vector<int, NoInitAlloc<int>>;
+using i64vec = std::vector<int64_t, NoInitAlloc<int64_t>>;
+
 struct LevelSymbolic {
     int ncl = 0;
     int ncolors = 0;
-    std::vector<int> color;      // colour of every cluster
-    std::vector<int> order;      // clusters by (colour, index)
-    std::vector<int> pos;        // processing position of every cluster
-    std::vector<int> color_ptr;  // order[color_ptr[c] .. color_ptr[c+1]) = colour c
-    std::vector<int> adj_ptr, adj;    // neighbours n(s) at the level start (sorted)
-    std::vector<int> fill_ptr, fill;  // fill partners w(s) when s is processed (by position)
-    std::vector<int> pat_ptr, pat;    // block pattern after the level (incl. diagonal, sorted)
+    ivec color;      // colour of every cluster
+    ivec order;      // clusters by (colour, index)
+    ivec pos;        // processing position of every cluster
+    ivec color_ptr;  // order[color_ptr[c] .. color_ptr[c+1]) = colour c
+    ivec adj_ptr, adj;    // neighbours n(s) at the level start (sorted)
+    ivec fill_ptr, fill;  // fill partners w(s) when s is processed (by position)
+    ivec pat_ptr, pat;    // block pattern after the level (incl. diagonal, sorted)
 
     // block id of (a, b) in the final pattern, -1 if absent
     int block_id(int a, int b) const;
@@ -28,10 +55,10 @@ struct Symbolic {
     int64_t n = 0;
     int depth = 0;
     int nlevels = 0;
-    std::vector<int> leaf_ptr;      // leaf c holds leaf_dofs[leaf_ptr[c] .. leaf_ptr[c+1])
-    std::vector<int64_t> leaf_dofs; // ascending global ids per leaf
-    std::vector<int> cluster_of;    // leaf of every unknown
-    std::vector<int> local_of;      // position of every unknown in its leaf
+    ivec leaf_ptr;      // leaf c holds leaf_dofs[leaf_ptr[c] .. leaf_ptr[c+1])
+    i64vec leaf_dofs;   // ascending global ids per leaf (one system's analysis only)
+    ivec cluster_of;    // leaf of every unknown
+    ivec local_of;      // position of every unknown in its leaf
     std::vector<LevelSymbolic> levels;
 };
 
@@ -51,7 +78,8 @@ int complete_level(const Symbolic& S);
 // cluster p are 2p and 2p + 1 on every level.  Every per-system array
 // (colours, processing order, neighbours, fill partners, pattern) is the
 // system's own, shifted; the processing order of a colour lists the systems
-// in placement order.
+// in placement order.  The combined analysis keeps leaf_ptr, cluster_of and
+// local_of (leaf_dofs stays empty: nothing downstream reads it).
 struct Forest {
     int nsys = 0;
     std::vector<int> sys;                  // placement -> system (caller's index)
