@@ -215,19 +215,27 @@ struct DevBuf {
     }
 };
 
-// Host blob of aligned arrays uploaded in one copy.
+// Host blob of aligned arrays uploaded in one copy.  Its storage is not
+// zero-filled on growth: every byte is written once (arrays copied in,
+// alignment gaps and reserved or zero runs cleared).
+using cvec = std::vector<char, NoInitAlloc<char>>;
 struct Blob {
-    std::vector<char> data;
+    cvec data;
+    size_t grow(size_t bytes) {  // aligned run of `bytes`, the gap before it cleared
+        const size_t end = data.size(), off = (end + 255) & ~size_t(255);
+        data.resize(off + bytes);
+        if (off > end) std::memset(data.data() + end, 0, off - end);
+        return off;
+    }
     template <class T, class A>
     size_t add(const std::vector<T, A>& v) {
-        size_t off = (data.size() + 255) & ~size_t(255);
-        data.resize(off + v.size() * sizeof(T));
+        const size_t off = grow(v.size() * sizeof(T));
         if (!v.empty()) std::memcpy(data.data() + off, v.data(), v.size() * sizeof(T));
         return off;
     }
-    size_t reserve(size_t bytes) {
-        size_t off = (data.size() + 255) & ~size_t(255);
-        data.resize(off + bytes);
+    size_t reserve(size_t bytes) {  // a zeroed run
+        const size_t off = grow(bytes);
+        if (bytes) std::memset(data.data() + off, 0, bytes);
         return off;
     }
     template <class T>
@@ -240,7 +248,7 @@ struct Blob {
 // and call to call: its capacity stays, so the host does not fault in fresh
 // pages for tens of megabytes every level (its contents are on the device
 // before the level's synchronisation, which precedes the next reuse).
-static thread_local std::vector<char> t_blob_store;
+static thread_local cvec t_blob_store;
 struct BlobLease {
     Blob& b;
     explicit BlobLease(Blob& blob) : b(blob) { b.data.swap(t_blob_store); }
@@ -401,7 +409,7 @@ struct LevelData {
     int64_t npairs = 0;                            // sum over clusters of |n(s)|^2
     DevBuf pairs;                                  // block id of every neighbour pair (a_i, a_j) of s
     std::vector<int> m, k;                         // sizes at the start, ranks after
-    std::vector<int64_t> blk_off;                  // in units of the block's element type
+    i64vec blk_off;                                // in units of the block's element type (set in parallel)
     std::vector<int64_t> rec_off;                  // in units of the record's element type
     int64_t block_bytes = 0;
     int64_t rec_bytes = 0;
@@ -422,6 +430,7 @@ struct LevelData {
     std::vector<ColourHost> colours;
     std::vector<int> order_host;                   // the colour slices by type (host copy of the work lists)
     std::vector<int64_t> seg;                      // [ncl+1] segment offsets
+    std::vector<int> ntot_host;                    // per cluster: neighbour unknowns (from the device)
     int64_t nseg = 0;
     int64_t part_max = 0;                          // largest colour part buffer (units of f)
     std::vector<double> kept;                      // dense starting matrix (keep_levels)
@@ -996,6 +1005,7 @@ struct SolvePlan {
     size_t seg = 0;
     std::vector<std::array<SolveGroupOffsets, 2>> grp;  // per colour and type
     double rec_bytes = 0.0, apply_flops = 0.0;
+    double factor_flops = 0.0;  // the level's share of info.factor_flops
 };
 
 static void plan_solve_level(hs_factor_s* F, int lvl, SolvePlan& P) {
@@ -1075,6 +1085,52 @@ static void plan_solve_level(hs_factor_s* F, int lvl, SolvePlan& P) {
     }
 }
 
+// Per-level work model: the factorization flops (info.factor_flops) and, while
+// the profiler times them, the pivot and Schur families' algorithmic flops and
+// bytes.  Host only; runs while the next level is on the device.
+static void account_level(hs_factor_s* F, int lvl, SolvePlan& P) {
+    LevelData& LD = F->levels[lvl];
+    const LevelSymbolic& S = F->sym.levels[lvl];
+    P.factor_flops = 0.0;
+    if (g_prof_on) {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        for (int c = 0; c < LD.ncl; ++c) {
+            const double m = LD.m[c], kk = LD.k[c], f = m - kk, nt = LD.ntot_host[c];
+            if (LD.m[c] == 0 || LD.dense[c]) continue;
+            const int pid = LD.f32[c] ? PF_PIVOT_F32 : PF_PIVOT;
+            if (prof_timed(pid) && f > 0) {
+                // the pivot kernel's share of the algorithmic work (counted as in the
+                // flop model below): LU of A_ss; with fill X = A^{-1} U, the
+                // complement(s), A^{-1} V, F_ff and its LU, C = U^T A^{-1} U; bytes:
+                // A_ss and the Gram matrix read, T_L', T_R' and C written
+                const double sides = F->symmetric ? 1.0 : 2.0;
+                double fl = 2.0 * m * m * m / 3.0, by = (double)LD.esz(c) * (3.0 * m * m);
+                if (kk > 0)
+                    fl += sides * (2.0 * m * m * kk + 4.0 * m * kk * f) + 2.0 * m * m * f + 2.0 * m * f * f +
+                          2.0 * f * f * f / 3.0 + 2.0 * m * kk * kk;
+                if (S.fill_ptr[c + 1] > S.fill_ptr[c] && F->opts.eps > 0.0)
+                    by += 8.0 * m * m + (double)LD.esz(c) * kk * kk;
+                g_prof[pid].flops += fl;
+                g_prof[pid].bytes += by;
+            }
+            if (f == 0 || nt == 0) continue;
+            const int fid = LD.f32[c] ? PF_SCHUR_F32 : PF_SCHUR;
+            if (!prof_timed(fid)) continue;
+            ProfFamily& fam = g_prof[fid];
+            fam.flops += 2.0 * f * nt * nt;
+            fam.bytes += (double)LD.esz(c) * (2.0 * f * nt + 2.0 * nt * nt);
+        }
+    }
+    for (int c = 0; c < LD.ncl; ++c) {
+        int wt = 0;
+        for (int e = S.fill_ptr[c]; e < S.fill_ptr[c + 1]; ++e) {
+            const int t = S.fill[e];
+            wt += S.pos[t] < S.pos[c] ? LD.k[t] : LD.m[t];
+        }
+        P.factor_flops += cluster_flops(LD.m[c], LD.k[c], LD.ntot_host[c], wt, F->symmetric != 0);
+    }
+}
+
 // Upload a level's solve metadata (after its block store is no longer needed:
 // the buffer takes the block store's slot) and point the colours at it.
 static int bind_solve_level(hs_factor_s* F, int lvl, SolvePlan& P, hipStream_t st) {
@@ -1097,6 +1153,15 @@ static int bind_solve_level(hs_factor_s* F, int lvl, SolvePlan& P, hipStream_t s
     return HS_OK;
 }
 
+// Pinned host staging of device-resident patterns (the symbolic analysis
+// reads them on the host; pageable copies run at a fraction of the link's
+// rate).  One buffer, grown on demand and kept until the process ends; a
+// factorization that finds it in use (another thread) copies through
+// pageable memory instead.
+static std::mutex g_pin_mu;
+static char* g_pin = nullptr;
+static size_t g_pin_bytes = 0;
+
 // Factor nsys independent systems as one block-diagonal system (Alg. 1 on
 // the forest of their cluster trees): every kernel launch of a level and
 // colour covers the clusters of all systems.
@@ -1113,23 +1178,66 @@ static int factor_impl(hs_factor_s* F, int nsys, const hs_csr* A, const hs_geome
     nnz = nnz_off[nsys];
     if (n > INT32_MAX) return fail(HS_ERR_ARG, "more than 2^31 - 1 unknowns in total");
     F->n = n;
-    // ---- host copies of the patterns (the symbolic analysis needs them)
-    std::vector<i64vec> rp_h(nsys);  // filled by the copies below (no zeroing first)
+    // ---- host copies of the patterns (the symbolic analysis needs them):
+    // into the pinned staging buffer when it is free and can hold them all
+    std::vector<i64vec> rp_h(nsys);  // pageable fallback, filled by the copies (no zeroing first)
     std::vector<ivec> ci_h(nsys);
     std::vector<const int64_t*> rp(nsys);
     std::vector<const int32_t*> ci(nsys);
     bool dev_copy = false;
+    auto align256 = [](size_t b) { return (b + 255) & ~size_t(255); };
+    size_t pin_need = 0;
+    for (int i = 0; i < nsys; ++i)
+        if (A[i].on_device) pin_need += align256((A[i].n + 1) * sizeof(int64_t)) + align256(A[i].nnz * sizeof(int32_t));
+    std::unique_lock<std::mutex> pin_lock(g_pin_mu, std::defer_lock);
+    char* pin = nullptr;
+    if (pin_need > 0 && pin_lock.try_lock()) {
+        if (g_pin_bytes < pin_need) {
+            if (g_pin) (void)hipHostFree(g_pin);
+            g_pin = nullptr;
+            g_pin_bytes = 0;
+            const size_t want = pin_need + pin_need / 4;
+            if (hipHostMalloc((void**)&g_pin, want, hipHostMallocDefault) == hipSuccess)
+                g_pin_bytes = want;
+            else
+                g_pin = nullptr;
+            (void)hipGetLastError();
+        }
+        if (g_pin_bytes >= pin_need)
+            pin = g_pin;
+        else
+            pin_lock.unlock();
+    }
+    // an early return drains the copies into the staging buffer before the
+    // lock is released (declared after the lock, so destroyed first)
+    struct PinDrain {
+        hipStream_t st;
+        bool on = false;
+        ~PinDrain() {
+            if (on) (void)hipStreamSynchronize(st);
+        }
+    } pin_drain{st, pin != nullptr};
+    size_t pin_off = 0;
     for (int i = 0; i < nsys; ++i) {
         if (A[i].on_device) {
-            rp_h[i].resize(A[i].n + 1);
-            ci_h[i].resize(A[i].nnz);
-            HIP_TRY(hipMemcpyAsync(rp_h[i].data(), A[i].row_ptr, (A[i].n + 1) * sizeof(int64_t),
-                                   hipMemcpyDeviceToHost, st));
+            int64_t* rdst;
+            int32_t* cdst;
+            if (pin) {
+                rdst = (int64_t*)(pin + pin_off);
+                pin_off += align256((A[i].n + 1) * sizeof(int64_t));
+                cdst = (int32_t*)(pin + pin_off);
+                pin_off += align256(A[i].nnz * sizeof(int32_t));
+            } else {
+                rp_h[i].resize(A[i].n + 1);
+                ci_h[i].resize(A[i].nnz);
+                rdst = rp_h[i].data();
+                cdst = ci_h[i].data();
+            }
+            HIP_TRY(hipMemcpyAsync(rdst, A[i].row_ptr, (A[i].n + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, st));
             if (A[i].nnz)
-                HIP_TRY(hipMemcpyAsync(ci_h[i].data(), A[i].col_idx, A[i].nnz * sizeof(int32_t),
-                                       hipMemcpyDeviceToHost, st));
-            rp[i] = rp_h[i].data();
-            ci[i] = ci_h[i].data();
+                HIP_TRY(hipMemcpyAsync(cdst, A[i].col_idx, A[i].nnz * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+            rp[i] = rdst;
+            ci[i] = cdst;
             dev_copy = true;
         } else {
             rp[i] = A[i].row_ptr;
@@ -1137,6 +1245,7 @@ static int factor_impl(hs_factor_s* F, int nsys, const hs_csr* A, const hs_geome
         }
     }
     if (dev_copy) HIP_TRY(hipStreamSynchronize(st));
+    pin_drain.on = false;
     {  // the systems' patterns checked on host threads, the first defect reported
         std::vector<int> defect(nsys, 0);
         parallel_for(nsys, std::min(host_threads(), 16),
@@ -1205,6 +1314,8 @@ static int factor_impl(hs_factor_s* F, int nsys, const hs_csr* A, const hs_geome
                                         (rcs[i] == HS_ERR_GEOMETRY ? "n != nx*ny*nz" : "bad symbolic arguments"));
         combine_symbolic(parts, nsys == 1, F->sym, F->forest);
     }
+    // the host patterns are no longer read: the staging buffer is free again
+    if (pin_lock.owns_lock()) pin_lock.unlock();
     auto t1 = clock::now();
     F->info.symbolic_seconds = std::chrono::duration<double>(t1 - t0).count();
     const int nlev = F->sym.nlevels;
@@ -1384,6 +1495,7 @@ static int factor_impl(hs_factor_s* F, int nsys, const hs_csr* A, const hs_geome
         if (lvl > 0) {
             HostScope hs_(PF_H_SOLVE_PLAN);
             plan_solve_level(F, lvl - 1, splans[lvl - 1]);
+            account_level(F, lvl - 1, splans[lvl - 1]);
         }
         // ranks decide the next level's sizes: one synchronisation per level
         LD.k.resize(LD.ncl);
@@ -1415,44 +1527,8 @@ static int factor_impl(hs_factor_s* F, int nsys, const hs_csr* A, const hs_geome
                                                   ", cluster " + std::to_string(c) +
                                                   (flag[c] == 2 ? " (fine block)" : " (pivot block)"));
             }
-        if (g_prof_on) {
-            prof_flush();
-            std::lock_guard<std::mutex> lk(g_prof_mu);
-            for (int c = 0; c < LD.ncl; ++c) {
-                const double m = LD.m[c], kk = LD.k[c], f = m - kk, nt = ntot[c];
-                if (LD.m[c] == 0 || LD.dense[c]) continue;
-                const int pid = LD.f32[c] ? PF_PIVOT_F32 : PF_PIVOT;
-                if (prof_timed(pid) && f > 0) {
-                    // the pivot kernel's share of the algorithmic work (counted as in the
-                    // flop model below): LU of A_ss; with fill X = A^{-1} U, the
-                    // complement(s), A^{-1} V, F_ff and its LU, C = U^T A^{-1} U; bytes:
-                    // A_ss and the Gram matrix read, T_L', T_R' and C written
-                    const double sides = F->symmetric ? 1.0 : 2.0;
-                    double fl = 2.0 * m * m * m / 3.0, by = (double)LD.esz(c) * (3.0 * m * m);
-                    if (kk > 0)
-                        fl += sides * (2.0 * m * m * kk + 4.0 * m * kk * f) + 2.0 * m * m * f + 2.0 * m * f * f +
-                              2.0 * f * f * f / 3.0 + 2.0 * m * kk * kk;
-                    if (S.fill_ptr[c + 1] > S.fill_ptr[c] && F->opts.eps > 0.0)
-                        by += 8.0 * m * m + (double)LD.esz(c) * kk * kk;
-                    g_prof[pid].flops += fl;
-                    g_prof[pid].bytes += by;
-                }
-                if (f == 0 || nt == 0) continue;
-                const int fid = LD.f32[c] ? PF_SCHUR_F32 : PF_SCHUR;
-                if (!prof_timed(fid)) continue;
-                ProfFamily& fam = g_prof[fid];
-                fam.flops += 2.0 * f * nt * nt;
-                fam.bytes += (double)LD.esz(c) * (2.0 * f * nt + 2.0 * nt * nt);
-            }
-        }
-        for (int c = 0; c < LD.ncl; ++c) {
-            int wt = 0;
-            for (int e = S.fill_ptr[c]; e < S.fill_ptr[c + 1]; ++e) {
-                const int t = S.fill[e];
-                wt += S.pos[t] < S.pos[c] ? LD.k[t] : LD.m[t];
-            }
-            flops += cluster_flops(LD.m[c], LD.k[c], ntot[c], wt, F->symmetric != 0);
-        }
+        if (g_prof_on) prof_flush();
+        LD.ntot_host = std::move(ntot);  // read by account_level
         // solve plan of the level: segments and part offsets
         LD.seg.assign(LD.ncl + 1, 0);
         for (int c = 0; c < LD.ncl; ++c) LD.seg[c + 1] = LD.seg[c] + LD.m[c];
@@ -1482,6 +1558,7 @@ static int factor_impl(hs_factor_s* F, int nsys, const hs_csr* A, const hs_geome
     {
         HostScope hs_solve(PF_H_SOLVE_PLAN);
         plan_solve_level(F, nlev - 1, splans[nlev - 1]);
+        account_level(F, nlev - 1, splans[nlev - 1]);
         for (int lvl = 0; lvl < nlev; ++lvl) {
             rc = bind_solve_level(F, lvl, splans[lvl], st);
             if (rc) return rc;
@@ -1491,6 +1568,7 @@ static int factor_impl(hs_factor_s* F, int nsys, const hs_csr* A, const hs_geome
     for (const SolvePlan& sp : splans) {
         rec_bytes += sp.rec_bytes;
         apply_flops += sp.apply_flops;
+        flops += sp.factor_flops;
     }
     // solve vector layout: y, z and out of every level, level after level
     F->vec_off.assign(nlev + 1, 0);

@@ -168,7 +168,7 @@ void simulate_level(LevelSymbolic& L, ivec& next_ptr, ivec& next_adj) {
         for (int e = L.adj_ptr[s]; e < L.adj_ptr[s + 1]; ++e) isnbr[L.adj[e]] = 1;
         P.row(s, row);
         for (int t : row)
-            if (t != s && !isnbr[t]) fill[s].push_back(t);
+            if (t != s && !isnbr[t]) fill[s].push_back(L.pos[t]);  // by position, mapped back below
         for (int e = L.adj_ptr[s]; e < L.adj_ptr[s + 1]; ++e) isnbr[L.adj[e]] = 0;
         // eliminating s couples every pair of its neighbours
         if (P.dense()) {
@@ -180,15 +180,23 @@ void simulate_level(LevelSymbolic& L, ivec& next_ptr, ivec& next_adj) {
                 for (int f = L.adj_ptr[s]; f < L.adj_ptr[s + 1]; ++f) P.add(L.adj[e], L.adj[f]);
         }
     }
-    // every fill list in processing order (the caller runs systems on
-    // several host threads, so a level sorts its short lists on one)
-    for (int c = 0; c < ncl; ++c)
-        std::sort(fill[c].begin(), fill[c].end(), [&](int a, int b) { return L.pos[a] < L.pos[b]; });
-    L.fill_ptr.assign(ncl + 1, 0);
-    L.fill.clear();
+    // every fill list in processing order: its positions sorted (short
+    // lists; the caller runs systems on several host threads), then the
+    // clusters at those positions
+    L.fill_ptr.resize(ncl + 1);
+    L.fill_ptr[0] = 0;
+    for (int s = 0; s < ncl; ++s) L.fill_ptr[s + 1] = L.fill_ptr[s] + (int)fill[s].size();
+    L.fill.resize(L.fill_ptr[ncl]);
     for (int s = 0; s < ncl; ++s) {
-        L.fill.insert(L.fill.end(), fill[s].begin(), fill[s].end());
-        L.fill_ptr[s + 1] = (int)L.fill.size();
+        std::vector<int>& f = fill[s];
+        for (size_t i = 1; i < f.size(); ++i) {  // insertion sort
+            const int v = f[i];
+            size_t j = i;
+            for (; j > 0 && f[j - 1] > v; --j) f[j] = f[j - 1];
+            f[j] = v;
+        }
+        int* out = L.fill.data() + L.fill_ptr[s];
+        for (size_t i = 0; i < f.size(); ++i) out[i] = L.order[f[i]];
     }
     L.pat_ptr.assign(ncl + 1, 0);
     L.pat.clear();
@@ -410,9 +418,9 @@ int build_symbolic(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, in
         algebraic_leaves(n, row_ptr, col_idx, depth, nodes);
         const int nleaf = (int)nodes.size();
         S.leaf_ptr.assign(nleaf + 1, 0);
-        S.leaf_dofs.resize(n);
-        S.cluster_of.assign(n, -1);
-        S.local_of.assign(n, -1);
+        S.leaf_dofs.resize(n);  // the leaves partition the unknowns: every entry below is written
+        S.cluster_of.resize(n);
+        S.local_of.resize(n);
         int64_t w = 0;
         for (int c = 0; c < nleaf; ++c) {
             int loc = 0;
@@ -449,9 +457,9 @@ int build_symbolic(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, in
     }
     const int nleaf = (int)boxes.size();
     S.leaf_ptr.assign(nleaf + 1, 0);
-    S.leaf_dofs.resize(n);
-    S.cluster_of.assign(n, -1);
-    S.local_of.assign(n, -1);
+    S.leaf_dofs.resize(n);  // the boxes tile the grid: every entry below is written
+    S.cluster_of.resize(n);
+    S.local_of.resize(n);
     int64_t w = 0;
     for (int c = 0; c < nleaf; ++c) {
         const Box& b = boxes[c];
