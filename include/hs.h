@@ -506,6 +506,11 @@ int hs_set_allocator(void* (*alloc_fn)(size_t, void*, void*), void (*free_fn)(vo
  *                                  launches (z_s once, then the neighbour
  *                                  updates); 0 two launches where the first
  *                                  would re-read more than twice T_L'
+ *   apply_wave       1, 0..1       with one right-hand side, the own
+ *                                  products of a colour whose clusters have at
+ *                                  most 128 unknowns run one wave per cluster
+ *                                  (the same sums in the same order; 0: the
+ *                                  64-row workgroup form)
  *   compression      0, 0..2       rank revelation (Eq. lra): 0 the
  *                                  pivoted QR of F^T under a rank cap or
  *                                  below qrcp_below_eps, else the Gram

@@ -2,7 +2,8 @@
 
 The thresholds pick between kernel variants that compute the same numbers up
 to rounding and differ in where their working data lives and how work is
-split: the forward solve step in one launch or two (apply_fwd), the panel
+split: the forward solve step in one launch or two (apply_fwd), the own
+products of a one-right-hand-side solve one wave per cluster (apply_wave), the panel
 width of the dense levels (dense_panel), how many fill partners share a Gram
 workgroup (gram_splits_max), how large a cluster may keep its working matrix
 in LDS (pivot_lds_max).  ``autotune`` times a representative workload (one
@@ -25,6 +26,7 @@ from . import _lib as L
 # parameter -> candidate values (the defaults are among them)
 CANDIDATES: Dict[str, List[float]] = {
     "apply_fwd": [0, 1, 2],
+    "apply_wave": [0, 1],
     "dense_panel": [64, 128],
     "gram_splits_max": [64, 128, 256],
     "pivot_lds_max": [64, 128],

@@ -446,6 +446,7 @@ struct Config {
     Knobs kn{LDS_M, TRI_MFMA_MAX, TRI_MFMA_MAX12, 64, 128, TRI_MFMA_MAX, 4, 256, 1024, 1, 0};
     int dense_panel = 128;
     int apply_fwd = 0;              // forward solve step: 0 by cost, 1 one launch, 2 two launches
+    int apply_wave = 1;             // one right-hand side: own products one wave per cluster
     int compression = 0;            // rank revelation: 0 by eps and cap, 1 pivoted QR, 2 Gram
     double qrcp_below_eps = 1e-5;   // 0: pivoted QR of F^T below this eps (or under a rank cap)
 };
@@ -544,6 +545,7 @@ static std::vector<ConfigEntry> config_table(Config& c) {
         {"cholqr", 0, 1, &c.kn.cholqr, nullptr},
         {"dense_panel", 16, 128, &c.dense_panel, nullptr},
         {"apply_fwd", 0, 2, &c.apply_fwd, nullptr},
+        {"apply_wave", 0, 1, &c.apply_wave, nullptr},
         {"compression", 0, 2, &c.compression, nullptr},
         {"qrcp_below_eps", 0, 1, nullptr, &c.qrcp_below_eps},
     };
@@ -1067,6 +1069,7 @@ static void plan_solve_level(hs_factor_s* F, int lvl, SolvePlan& P) {
             CH.sol[t].grp_total = pre.back();
             CH.sol[t].fwd_split = F->cfg.apply_fwd == 2 || (F->cfg.apply_fwd == 0 && reformed_elems > 2.0 * own_elems);
             CH.sol[t].max_nt = max_nt;
+            CH.sol[t].apply_wave = F->cfg.apply_wave;
             LD.part_max = std::max(LD.part_max, acc);
             P.grp[c][t] = {sb.add(po), sb.add(pre), sb.add(ge0), sb.add(ge1)};
         }

@@ -71,9 +71,80 @@ __global__ void __launch_bounds__(WG) k_apply_fwd_t(SolveLevelDev S, ColourDev C
 
 static size_t tile_shmem(size_t doubles) { return doubles * sizeof(double) + TILE_BYTES; }
 
+// One right-hand side and clusters of at most WAVE_MAXM unknowns: one wave
+// per cluster (four clusters per workgroup), lane l holding rows l and
+// l + 64.  The operator is read straight from memory, a batch of WAVE_LD
+// columns in flight per lane (consecutive lanes read consecutive rows of a
+// column), and the vector entry of column l is broadcast from the lane that
+// holds it; every row's sum is taken from zero in ascending l with one fma
+// per column, the order of the workgroup form, so both give the same bits.
+constexpr int WAVE_MAXM = 128;
+constexpr int WAVE_LD = 8;
+
+// out(i) = sum_l Op(i, l) v(l) for the rows i = lane, lane + 64 < M; v(l) is
+// v0 of lane l (l < 64) or v1 of lane l - 64.
+template <class T>
+__device__ inline void wave_rows_times(const T* __restrict__ op, int M, double v0, double v1, double& a0,
+                                       double& a1) {
+    const int lane = threadIdx.x & 63;
+    const bool ok0 = lane < M, ok1 = lane + 64 < M;
+    a0 = 0.0;
+    a1 = 0.0;
+    int l = 0;
+    for (; l + WAVE_LD <= M; l += WAVE_LD) {
+        T t0[WAVE_LD], t1[WAVE_LD];
+#pragma unroll
+        for (int u = 0; u < WAVE_LD; ++u) {
+            const T* col = op + (int64_t)(l + u) * M;
+            t0[u] = ok0 ? col[lane] : T(0);
+            t1[u] = ok1 ? col[lane + 64] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < WAVE_LD; ++u) {
+            const int lu = l + u;
+            const double vl = lu < 64 ? readlane_d(v0, lu) : readlane_d(v1, lu - 64);
+            a0 = fma((double)t0[u], vl, a0);
+            a1 = fma((double)t1[u], vl, a1);
+        }
+    }
+    for (; l < M; ++l) {
+        const T* col = op + (int64_t)l * M;
+        const double vl = l < 64 ? readlane_d(v0, l) : readlane_d(v1, l - 64);
+        a0 = fma((double)(ok0 ? col[lane] : T(0)), vl, a0);
+        a1 = fma((double)(ok1 ? col[lane + 64] : T(0)), vl, a1);
+    }
+}
+
+// z_s = T_L' y_s (one right-hand side), one wave per cluster.
+template <class T>
+__global__ void __launch_bounds__(WG) k_apply_fwd_t_wave(SolveLevelDev S, ColourDev C, const double* __restrict__ y,
+                                                         double* __restrict__ z) {
+    const int ci = blockIdx.x * (WG / 64) + (threadIdx.x >> 6);
+    if (ci >= C.n) return;
+    const int lane = threadIdx.x & 63;
+    const int s = C.clist[ci];
+    const int M = S.m[s];
+    const double* ys = y + S.seg[s];
+    double* zs = z + S.seg[s];
+    const double y0 = lane < M ? ys[lane] : 0.0;
+    const double y1 = lane + 64 < M ? ys[lane + 64] : 0.0;
+    double a0 = y0, a1 = y1;
+    if (S.k[s] != M) wave_rows_times<T>(srec<T>(S, s), M, y0, y1, a0, a1);
+    if (lane < M) zs[lane] = a0;
+    if (lane + 64 < M) zs[lane + 64] = a1;
+}
+
 void launch_apply_fwd_t(const SolveLevelDev& S, const ColourDev& C, const double* y, double* z, int nrhs,
                         hipStream_t st) {
     if (C.n == 0) return;
+    if (nrhs == 1 && C.apply_wave && C.max_m <= WAVE_MAXM) {
+        const dim3 wgrid((C.n + WG / 64 - 1) / (WG / 64));
+        if (C.f32)
+            hipLaunchKernelGGL(k_apply_fwd_t_wave<float>, wgrid, dim3(WG), 0, st, S, C, y, z);
+        else
+            hipLaunchKernelGGL(k_apply_fwd_t_wave<double>, wgrid, dim3(WG), 0, st, S, C, y, z);
+        return;
+    }
     const size_t sh = tile_shmem((size_t)C.max_m * nrhs);
     const dim3 grid(std::max(1, (C.max_m + UROWS - 1) / UROWS), C.n);
     if (C.f32)
@@ -407,9 +478,66 @@ __global__ void __launch_bounds__(WG) k_apply_bwd_t(SolveLevelDev S, ColourDev C
         tile_buf<T>(vs + (size_t)C.max_m * nrhs), [&](int i, int r, double v) { os[r0 + i + r * M] = v; });
 }
 
+// out_s = T_R' [z_f - sum of the neighbour-group partials ; z_c] (one
+// right-hand side), one wave per cluster; the partials are subtracted in
+// group order, WAVE_LD loads in flight, as in the workgroup form.
+template <class T>
+__global__ void __launch_bounds__(WG) k_apply_bwd_t_wave(SolveLevelDev S, ColourDev C, const double* __restrict__ z,
+                                                         double* __restrict__ out, const double* __restrict__ part,
+                                                         const int64_t* __restrict__ part_off) {
+    const int ci = blockIdx.x * (WG / 64) + (threadIdx.x >> 6);
+    if (ci >= C.n) return;
+    const int lane = threadIdx.x & 63;
+    const int s = C.clist[ci];
+    const int M = S.m[s];
+    const int f = M - S.k[s];
+    const double* zs = z + S.seg[s];
+    double* os = out + S.seg[s];
+    double v0 = lane < M ? zs[lane] : 0.0;
+    double v1 = lane + 64 < M ? zs[lane + 64] : 0.0;
+    if (f > 0) {
+        const bool p0 = lane < f, p1 = lane + 64 < f;
+        const int q0 = C.grp_pre[ci], q1 = C.grp_pre[ci + 1];
+        int q = q0;
+        for (; q + WAVE_LD <= q1; q += WAVE_LD) {
+            double t0[WAVE_LD], t1[WAVE_LD];
+#pragma unroll
+            for (int u = 0; u < WAVE_LD; ++u) {
+                const double* pp = part + part_off[q + u];
+                t0[u] = p0 ? pp[lane] : 0.0;
+                t1[u] = p1 ? pp[lane + 64] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < WAVE_LD; ++u) {
+                v0 -= t0[u];
+                v1 -= t1[u];
+            }
+        }
+        for (; q < q1; ++q) {
+            const double* pp = part + part_off[q];
+            if (p0) v0 -= pp[lane];
+            if (p1) v1 -= pp[lane + 64];
+        }
+        double a0, a1;
+        wave_rows_times<T>(srec<T>(S, s) + (int64_t)M * M, M, v0, v1, a0, a1);
+        v0 = a0;
+        v1 = a1;
+    }
+    if (lane < M) os[lane] = v0;
+    if (lane + 64 < M) os[lane + 64] = v1;
+}
+
 void launch_apply_bwd_t(const SolveLevelDev& S, const ColourDev& C, const double* z, double* out,
                         const double* part, const int64_t* part_off, int nrhs, hipStream_t st) {
     if (C.n == 0) return;
+    if (nrhs == 1 && C.apply_wave && C.max_m <= WAVE_MAXM) {
+        const dim3 wgrid((C.n + WG / 64 - 1) / (WG / 64));
+        if (C.f32)
+            hipLaunchKernelGGL(k_apply_bwd_t_wave<float>, wgrid, dim3(WG), 0, st, S, C, z, out, part, part_off);
+        else
+            hipLaunchKernelGGL(k_apply_bwd_t_wave<double>, wgrid, dim3(WG), 0, st, S, C, z, out, part, part_off);
+        return;
+    }
     const size_t sh = tile_shmem((size_t)C.max_m * nrhs);
     const dim3 grid(std::max(1, (C.max_m + UROWS - 1) / UROWS), C.n);
     if (C.f32)

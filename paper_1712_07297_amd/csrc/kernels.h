@@ -34,6 +34,7 @@ struct ColourDev {
     int grp_total = 0;
     int fwd_split = 0;                // forward step in two launches (own products, then neighbour updates)
     int max_nt = 0;                   // most neighbour rows (current sizes) of a cluster of the colour
+    int apply_wave = 0;               // one right-hand side: own products one wave per cluster (m <= 128)
 };
 // neighbour groups of the backward sweep: at most this many columns of E_R
 // (unless one neighbour alone is wider) and this many entries

@@ -17,6 +17,8 @@ DEFAULTS = {
     "schur_noff_max": 1024,
     "cholqr": 1,
     "dense_panel": 128,
+    "apply_fwd": 0,
+    "apply_wave": 1,
     "compression": 0,
     "qrcp_below_eps": 1e-5,
 }

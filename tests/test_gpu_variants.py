@@ -155,6 +155,39 @@ def test_noise_floor_decision(P, factor_of_floor):
     _check_solve(P, fo, F, A)
 
 
+@pytest.mark.parametrize("case", ["p3d_big_clusters", "convdiff_mixed", "batch_mixed"])
+def test_apply_wave_form_bitwise(P, case):
+    """One right-hand side: the own products one wave per cluster (clusters
+    up to 128 unknowns) and in 64-row workgroup chunks take the same sums in
+    the same order, so the solves agree bit for bit; float32 and float64
+    levels, colours above 128 unknowns falling back to the chunked form."""
+
+    rng = np.random.default_rng(11)
+    if case == "p3d_big_clusters":
+        A = poisson3d(12, 12, 12)
+        mk = lambda: P.Factor(A.row_ptr, A.col_idx, A.val, (12, 12, 12), 1e-4, 200, symmetric=1)  # noqa: E731
+        n = A.n
+    elif case == "convdiff_mixed":
+        A = convdiff2d_upwind(96, 40.0, 0.7)
+        mk = lambda: P.Factor(A.row_ptr, A.col_idx, A.val, (96, 96, 1), 1e-3, 64, symmetric=0,  # noqa: E731
+                              precision=P.HS_MIXED, coarse_fp64_dofs=1000)
+        n = A.n
+    else:
+        As = [convdiff2d_upwind(s, pe, th) for s, pe, th in ((64, 10.0, 0.3), (80, 60.0, 2.0), (48, 90.0, 4.0))]
+        systems = [(a.row_ptr, a.col_idx, a.val, (int(round(a.n ** 0.5)),) * 2 + (1,)) for a in As]
+        mk = lambda: P.Factor.batch(systems, 1e-3, 64, symmetric=0, precision=P.HS_MIXED)  # noqa: E731
+        n = sum(a.n for a in As)
+    b = torch.tensor(rng.uniform(-1, 1, (1, n)), device="cuda")
+    xs = []
+    for mode in (0, 1):
+        with knobs(P, apply_wave=mode):
+            F = mk()
+        xs.append(F.solve(b).cpu().numpy())
+        F.free()
+    print(f"[variants] apply_wave {case}: n={n}", flush=True)
+    assert np.array_equal(xs[0], xs[1])
+
+
 @pytest.mark.parametrize("nrhs", [1, 5])
 def test_apply_launch_forms_bitwise(P, nrhs):
     """The forward step in one launch (neighbour workgroups form z_s[:f]
