@@ -487,7 +487,7 @@ int hs_set_allocator(void* (*alloc_fn)(size_t, void*, void*), void (*free_fn)(vo
  *                                  row slots per lane up to this cluster size
  *                                  (for at most 64 coarse unknowns), in
  *                                  memory beyond
- *   wy_max           128, 0..128   its Q formed through the compact WY form
+ *   wy_max           0, 0..128     its Q formed through the compact WY form
  *                                  while the coarse size is at most this
  *   gram_splits_max  4, 1..256     partial sums of the fill's Gram matrix
  *                                  (Eq. lra) per cluster at most
@@ -496,7 +496,7 @@ int hs_set_allocator(void* (*alloc_fn)(size_t, void*, void*), void (*free_fn)(vo
  *                                  there are at most this many
  *   schur_noff_max   1024, 0..1024 Schur tile: neighbour offsets staged in
  *                                  LDS while there are at most this many
- *   cholqr           1, 0..1       basis U of the fill by Cholesky QR (0:
+ *   cholqr           0, 0..1       basis U of the fill by Cholesky QR (0:
  *                                  always Householder QR)
  *   dense_panel      128, 16..128  panel width of the dense LU of a complete
  *                                  level (Alg. 1, final dense factorization)

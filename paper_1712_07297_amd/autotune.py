@@ -6,7 +6,8 @@ split: the forward solve step in one launch or two (apply_fwd), the own
 products of a one-right-hand-side solve one wave per cluster (apply_wave), the panel
 width of the dense levels (dense_panel), how many fill partners share a Gram
 workgroup (gram_splits_max), how large a cluster may keep its working matrix
-in LDS (pivot_lds_max).  ``autotune`` times a representative workload (one
+in LDS (pivot_lds_max), whether the complement's columns go through the
+compact WY form (wy_max) and the basis U through Cholesky QR (cholqr).  ``autotune`` times a representative workload (one
 factorization and one Krylov solve, on the caller's matrices) under each
 candidate setting, one parameter at a time from the current values, keeps a
 change only when it is faster by more than ``min_gain`` and the solution
@@ -30,6 +31,8 @@ CANDIDATES: Dict[str, List[float]] = {
     "dense_panel": [64, 128],
     "gram_splits_max": [64, 128, 256],
     "pivot_lds_max": [64, 128],
+    "wy_max": [0, 128],
+    "cholqr": [0, 1],
 }
 
 

@@ -440,10 +440,14 @@ struct LevelData {
 // Process-wide kernel-variant thresholds (hs_config_set), copied into a
 // factorization when it starts; the variants compute the same numbers.
 struct Config {
-    // gram_splits_max 4: measured faster than one partner per workgroup on the
-    // batched convection-diffusion workload (fewer partial Gram matrices to
-    // write and sum)
-    Knobs kn{LDS_M, TRI_MFMA_MAX, TRI_MFMA_MAX12, 64, 128, TRI_MFMA_MAX, 4, 256, 1024, 1, 0};
+    // Measured on the batched convection-diffusion workload: four Gram
+    // partials per cluster (fewer partial matrices to write and sum than one
+    // partner per workgroup); the complement's columns formed wave by wave from
+    // the reflectors rather than through the compact WY form (wy_max 0), and
+    // the basis U by Householder QR rather than Cholesky QR (cholqr 0): fewer
+    // GEMM and triangular-inverse calls in the pivot kernel's chain, 4 % off
+    // the mixed step
+    Knobs kn{LDS_M, TRI_MFMA_MAX, TRI_MFMA_MAX12, 64, 128, 0, 4, 256, 1024, 0, 0};
     int dense_panel = 128;
     int apply_fwd = 0;              // forward solve step: 0 by cost, 1 one launch, 2 two launches
     int apply_wave = 1;             // one right-hand side: own products one wave per cluster

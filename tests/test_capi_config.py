@@ -11,11 +11,11 @@ DEFAULTS = {
     "trinv12_max": 192,
     "qr_reg1_max": 64,
     "qr_reg2_max": 128,
-    "wy_max": 128,
+    "wy_max": 0,
     "gram_splits_max": 4,
     "schur_ptab_max": 256,
     "schur_noff_max": 1024,
-    "cholqr": 1,
+    "cholqr": 0,
     "dense_panel": 128,
     "apply_fwd": 0,
     "apply_wave": 1,
