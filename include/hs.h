@@ -198,9 +198,12 @@ int hs_factor(const hs_csr* A, const hs_geometry* geom, const hs_opts* opts, voi
  * recurrence and one stopping test per system and column.  Every system's
  * factor and Krylov numbers are those of hs_factor on that system alone
  * (the same kernels on the same data in the same order; the work of other
- * systems only shares the launches), except that a batch containing a
- * nonsymmetric system factors every system in the general form when
- * opts->symmetric is -1.  A[i] and geom[i] as for hs_factor (host and device
+ * systems only shares the launches) whenever both take the same kernel
+ * variants: a level that the batch's systems together crowd (at least
+ * crowded_min clusters per colour, hs_config_set) takes the crowded variants,
+ * which a lone system's sparser level may not, and the two then agree up to
+ * rounding.  A batch containing a nonsymmetric system factors every system
+ * in the general form when opts->symmetric is -1.  A[i] and geom[i] as for hs_factor (host and device
  * CSR may be mixed); nsys >= 1.  Errors as hs_factor, with the failing
  * system named in hs_last_error(). */
 int hs_factor_batch(int32_t nsys, const hs_csr* A, const hs_geometry* geom, const hs_opts* opts,
@@ -383,7 +386,8 @@ void hs_free(hs_factor_t F);
  * Every result equals that of hs_factor (+ hs_pcg for symmetric operators,
  * hs_gmres(restart 30) otherwise) on the request alone: batched systems get
  * the same kernels in the same order and one Krylov recurrence per system
- * and column.  The memory of a new factorization is estimated as its
+ * and column (up to rounding where the batch crowds a level that the lone
+ * system does not, as for hs_factor_batch).  The memory of a new factorization is estimated as its
  * unknowns times the largest peak bytes per unknown seen so far for the same
  * grid dimension and precision (before the first: 16 KB / unknown), plus the
  * Krylov work vectors. */
@@ -487,17 +491,26 @@ int hs_set_allocator(void* (*alloc_fn)(size_t, void*, void*), void (*free_fn)(vo
  *                                  row slots per lane up to this cluster size
  *                                  (for at most 64 coarse unknowns), in
  *                                  memory beyond
- *   wy_max           0, 0..128     its Q formed through the compact WY form
+ *   wy_max           128, 0..128   its Q formed through the compact WY form
  *                                  while the coarse size is at most this
- *   gram_splits_max  4, 1..256     partial sums of the fill's Gram matrix
+ *   gram_splits_max  256, 1..256   partial sums of the fill's Gram matrix
  *                                  (Eq. lra) per cluster at most
  *   schur_ptab_max   256, 0..256   Schur tile (Eq. elim): block pointers of
  *                                  its neighbour pairs staged in LDS while
  *                                  there are at most this many
  *   schur_noff_max   1024, 0..1024 Schur tile: neighbour offsets staged in
  *                                  LDS while there are at most this many
- *   cholqr           0, 0..1       basis U of the fill by Cholesky QR (0:
+ *   cholqr           1, 0..1       basis U of the fill by Cholesky QR (0:
  *                                  always Householder QR)
+ *   crowded_min      512, 0..2^30  a level whose colours hold at least this
+ *                                  many clusters on average is crowded: its
+ *                                  pivot kernel takes the three settings below
+ *                                  in place of gram_splits_max, wy_max and
+ *                                  cholqr (bound by throughput, not by the
+ *                                  latency of one cluster's chain)
+ *   gram_splits_crowded  4, 1..256 Gram partials per cluster on a crowded level
+ *   wy_max_crowded   0, 0..128     wy_max on a crowded level
+ *   cholqr_crowded   0, 0..1       cholqr on a crowded level
  *   dense_panel      128, 16..128  panel width of the dense LU of a complete
  *                                  level (Alg. 1, final dense factorization)
  *   apply_fwd        0, 0..2       forward step of the solve (Alg. 2) per
@@ -505,7 +518,10 @@ int hs_set_allocator(void* (*alloc_fn)(size_t, void*, void*), void (*free_fn)(vo
  *                                  workgroups each form z_s[:f] again; 2 two
  *                                  launches (z_s once, then the neighbour
  *                                  updates); 0 two launches where the first
- *                                  would re-read more than twice T_L'
+ *                                  would re-read more than twice T_L' and
+ *                                  the solve has at most apply_split_nrhs_max
+ *                                  right-hand sides
+ *   apply_split_nrhs_max  1, 0..2^20  see apply_fwd
  *   apply_wave       1, 0..1       with one right-hand side, the own
  *                                  products of a colour whose clusters have at
  *                                  most 128 unknowns run one wave per cluster

@@ -7,7 +7,9 @@ products of a one-right-hand-side solve one wave per cluster (apply_wave), the p
 width of the dense levels (dense_panel), how many fill partners share a Gram
 workgroup (gram_splits_max), how large a cluster may keep its working matrix
 in LDS (pivot_lds_max), whether the complement's columns go through the
-compact WY form (wy_max) and the basis U through Cholesky QR (cholqr).  ``autotune`` times a representative workload (one
+compact WY form (wy_max) and the basis U through Cholesky QR (cholqr), and
+the same three on crowded levels (gram_splits_crowded, wy_max_crowded,
+cholqr_crowded, with crowded_min clusters per colour).  ``autotune`` times a representative workload (one
 factorization and one Krylov solve, on the caller's matrices) under each
 candidate setting, one parameter at a time from the current values, keeps a
 change only when it is faster by more than ``min_gain`` and the solution
@@ -28,11 +30,16 @@ from . import _lib as L
 CANDIDATES: Dict[str, List[float]] = {
     "apply_fwd": [0, 1, 2],
     "apply_wave": [0, 1],
+    "apply_split_nrhs_max": [1, 64],
     "dense_panel": [64, 128],
     "gram_splits_max": [64, 128, 256],
+    "gram_splits_crowded": [2, 4, 8, 256],
+    "crowded_min": [128, 512, 2048],
     "pivot_lds_max": [64, 128],
     "wy_max": [0, 128],
     "cholqr": [0, 1],
+    "wy_max_crowded": [0, 128],
+    "cholqr_crowded": [0, 1],
 }
 
 

@@ -431,6 +431,7 @@ struct LevelData {
     std::vector<int> order_host;                   // the colour slices by type (host copy of the work lists)
     std::vector<int64_t> seg;                      // [ncl+1] segment offsets
     std::vector<int> ntot_host;                    // per cluster: neighbour unknowns (from the device)
+    Knobs kn{};                                    // the level's kernel-variant thresholds
     int64_t nseg = 0;
     int64_t part_max = 0;                          // largest colour part buffer (units of f)
     std::vector<double> kept;                      // dense starting matrix (keep_levels)
@@ -440,17 +441,29 @@ struct LevelData {
 // Process-wide kernel-variant thresholds (hs_config_set), copied into a
 // factorization when it starts; the variants compute the same numbers.
 struct Config {
-    // Measured on the batched convection-diffusion workload: four Gram
-    // partials per cluster (fewer partial matrices to write and sum than one
-    // partner per workgroup); the complement's columns formed wave by wave from
-    // the reflectors rather than through the compact WY form (wy_max 0), and
-    // the basis U by Householder QR rather than Cholesky QR (cholqr 0): fewer
-    // GEMM and triangular-inverse calls in the pivot kernel's chain, 4 % off
-    // the mixed step
-    Knobs kn{LDS_M, TRI_MFMA_MAX, TRI_MFMA_MAX12, 64, 128, 0, 4, 256, 1024, 0, 0};
+    Knobs kn{LDS_M, TRI_MFMA_MAX, TRI_MFMA_MAX12, 64, 128, TRI_MFMA_MAX, GRAM_SPLITS_MAX, 256, 1024, 1, 0};
+    // Crowded levels (at least crowded_min clusters per colour on average) are
+    // bound by throughput, sparse ones by the latency of each cluster's chain.
+    // On a crowded level the pivot kernel takes gram_splits_crowded Gram
+    // partials per cluster, forms the complement's columns wave by wave from
+    // the reflectors (wy_max_crowded 0) and U by Householder QR
+    // (cholqr_crowded 0): fewer, shorter device-function chains, measured 4 %
+    // and 13 % faster on the batched convection-diffusion workload.  A sparse
+    // level keeps one fill partner per Gram workgroup, the compact WY form and
+    // Cholesky QR: on the 3D Poisson factorization (few clusters per colour,
+    // larger ranks) the crowded settings took 1624 instead of 675 ms.
+    int crowded_min = 512;
+    int gram_splits_crowded = 4;
+    int wy_max_crowded = 0;
+    int cholqr_crowded = 0;
     int dense_panel = 128;
     int apply_fwd = 0;              // forward solve step: 0 by cost, 1 one launch, 2 two launches
     int apply_wave = 1;             // one right-hand side: own products one wave per cluster
+    // apply_fwd 0 splits a colour's forward step (where the one-launch form
+    // would re-read T_L' more than twice) only for at most this many
+    // right-hand sides: with 8 the one-launch form took the 64^3 Poisson PCG
+    // from 346 to 262 ms, with one the split form is the faster
+    int apply_split_nrhs_max = 1;
     int compression = 0;            // rank revelation: 0 by eps and cap, 1 pivoted QR, 2 Gram
     double qrcp_below_eps = 1e-5;   // 0: pivoted QR of F^T below this eps (or under a rank cap)
 };
@@ -547,9 +560,14 @@ static std::vector<ConfigEntry> config_table(Config& c) {
         {"schur_ptab_max", 0, 256, &c.kn.schur_ptab_max, nullptr},
         {"schur_noff_max", 0, 1024, &c.kn.schur_noff_max, nullptr},
         {"cholqr", 0, 1, &c.kn.cholqr, nullptr},
+        {"crowded_min", 0, 1 << 30, &c.crowded_min, nullptr},
+        {"gram_splits_crowded", 1, GRAM_SPLITS_MAX, &c.gram_splits_crowded, nullptr},
+        {"wy_max_crowded", 0, TRI_MFMA_MAX, &c.wy_max_crowded, nullptr},
+        {"cholqr_crowded", 0, 1, &c.cholqr_crowded, nullptr},
         {"dense_panel", 16, 128, &c.dense_panel, nullptr},
         {"apply_fwd", 0, 2, &c.apply_fwd, nullptr},
         {"apply_wave", 0, 1, &c.apply_wave, nullptr},
+        {"apply_split_nrhs_max", 0, 1 << 20, &c.apply_split_nrhs_max, nullptr},
         {"compression", 0, 2, &c.compression, nullptr},
         {"qrcp_below_eps", 0, 1, nullptr, &c.qrcp_below_eps},
     };
@@ -653,7 +671,15 @@ static int plan_level(hs_factor_s* F, int lvl, Blob& blob, std::vector<size_t>& 
     LD.npairs = pp;
     // workspace slots; each cluster uses gram_splits_of(its nf); the pivoted-QR
     // route keeps F (m x its fill columns) behind the slots instead
-    LD.gram_splits = F->qrcp ? 1 : gram_splits_of(max_nf, F->cfg.kn.gram_splits_max);
+    // the level's kernel-variant thresholds: the crowded settings when its
+    // colours hold at least crowded_min clusters on average
+    LD.kn = F->cfg.kn;
+    if ((int64_t)ncl >= (int64_t)F->cfg.crowded_min * std::max(1, S.ncolors)) {
+        LD.kn.gram_splits_max = F->cfg.gram_splits_crowded;
+        LD.kn.wy_max = F->cfg.wy_max_crowded;
+        LD.kn.cholqr = F->cfg.cholqr_crowded;
+    }
+    LD.gram_splits = F->qrcp ? 1 : gram_splits_of(max_nf, LD.kn.gram_splits_max);
     const int64_t slots = ws_slots(LD.gram_splits);
     std::vector<int64_t> fcap(ncl, 0);
     if (F->qrcp)
@@ -817,7 +843,7 @@ static void bind_level(LevelData& LD, const std::vector<size_t>& offs, const hs_
     D.fixed_rank = F->opts.fixed_rank;
     D.pivoting = F->opts.pivoting;
     D.gram_splits = LD.gram_splits;
-    D.kn = F->cfg.kn;
+    D.kn = LD.kn;
     D.kn.qrcp = F->qrcp;
     D.m = (const int*)P(0);
     D.k = (int*)P(1);
@@ -1071,7 +1097,9 @@ static void plan_solve_level(hs_factor_s* F, int lvl, SolvePlan& P) {
             po.push_back(acc);
             CH.part_total[t] = acc;
             CH.sol[t].grp_total = pre.back();
-            CH.sol[t].fwd_split = F->cfg.apply_fwd == 2 || (F->cfg.apply_fwd == 0 && reformed_elems > 2.0 * own_elems);
+            CH.sol[t].fwd_split =
+                F->cfg.apply_fwd == 2 ? 1 : (F->cfg.apply_fwd == 0 && reformed_elems > 2.0 * own_elems ? 2 : 0);
+            CH.sol[t].split_nrhs_max = F->cfg.apply_split_nrhs_max;
             CH.sol[t].max_nt = max_nt;
             CH.sol[t].apply_wave = F->cfg.apply_wave;
             LD.part_max = std::max(LD.part_max, acc);

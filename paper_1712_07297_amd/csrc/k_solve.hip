@@ -299,7 +299,11 @@ constexpr size_t FWD_FUSED_MAX_LDS = 150 * 1024;
 void launch_apply_fwd(const SolveLevelDev& S, const ColourDev& C, double* y, double* z, int nrhs, hipStream_t st) {
     if (C.n == 0) return;
     const size_t sh = tile_shmem(2 * (size_t)C.max_m * nrhs);
-    if (C.fwd_split || sh > FWD_FUSED_MAX_LDS) {
+    // fwd_split: 1 always two launches, 2 two launches for at most
+    // split_nrhs_max right-hand sides (the one-launch form's re-formed z_s
+    // costs less than the second launch once the right-hand sides share it)
+    const bool split = C.fwd_split == 1 || (C.fwd_split == 2 && nrhs <= C.split_nrhs_max);
+    if (split || sh > FWD_FUSED_MAX_LDS) {
         launch_apply_fwd_t(S, C, y, z, nrhs, st);
         launch_apply_fwd_u(S, C, y, z, nrhs, C.max_nbr_m, st);
         return;

@@ -32,7 +32,9 @@ struct ColourDev {
     const int* grp_e0 = nullptr;      // [grp_total] first neighbour entry of the group
     const int* grp_e1 = nullptr;      // [grp_total] one past its last entry
     int grp_total = 0;
-    int fwd_split = 0;                // forward step in two launches (own products, then neighbour updates)
+    int fwd_split = 0;                // forward step in two launches (own products, then neighbour updates):
+                                      // 1 always, 2 for at most split_nrhs_max right-hand sides
+    int split_nrhs_max = 1;
     int max_nt = 0;                   // most neighbour rows (current sizes) of a cluster of the colour
     int apply_wave = 0;               // one right-hand side: own products one wave per cluster (m <= 128)
 };

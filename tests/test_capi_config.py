@@ -11,14 +11,19 @@ DEFAULTS = {
     "trinv12_max": 192,
     "qr_reg1_max": 64,
     "qr_reg2_max": 128,
-    "wy_max": 0,
-    "gram_splits_max": 4,
+    "wy_max": 128,
+    "gram_splits_max": 256,
     "schur_ptab_max": 256,
     "schur_noff_max": 1024,
-    "cholqr": 0,
+    "cholqr": 1,
+    "crowded_min": 512,
+    "gram_splits_crowded": 4,
+    "wy_max_crowded": 0,
+    "cholqr_crowded": 0,
     "dense_panel": 128,
     "apply_fwd": 0,
     "apply_wave": 1,
+    "apply_split_nrhs_max": 1,
     "compression": 0,
     "qrcp_below_eps": 1e-5,
 }

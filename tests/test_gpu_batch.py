@@ -5,8 +5,10 @@ recurrence per system and right-hand side.
 
 The bar: every system's factor and Krylov numbers are those of the same
 system factored alone (bit for bit, since the same kernels run on the same
-data in the same order), the batch solve agrees with the float64 oracle's
-solve of each system, and every system reaches the float64 tolerance.
+data in the same order; these batches hold a few dozen clusters per colour,
+far below crowded_min, so batch and lone take the same kernel variants), the
+batch solve agrees with the float64 oracle's solve of each system, and every
+system reaches the float64 tolerance.
 """
 
 import numpy as np

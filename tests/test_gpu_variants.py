@@ -92,13 +92,16 @@ FORCED = [
     ("trinv_per_wave", dict(pivot_lds_max=0, trinv8_max=0, trinv12_max=0), ["p3d", "nonsym", "p2d_exact"]),
     ("complement_two_slots", dict(qr_reg1_max=0), ["p3d", "nonsym"]),
     ("complement_in_memory", dict(qr_reg1_max=0, qr_reg2_max=0), ["p3d", "nonsym"]),
-    ("complement_q_by_wy", dict(wy_max=128), ["p3d", "nonsym"]),
-    ("gram_one_partner_each", dict(gram_splits_max=256), ["p3d", "nonsym"]),
+    ("complement_q_without_wy", dict(wy_max=0), ["p3d", "nonsym"]),
     ("gram_partners_shared", dict(gram_splits_max=2), ["p3d", "nonsym"]),
     ("gram_single_partial", dict(gram_splits_max=1), ["p3d"]),
     ("schur_no_pointer_table", dict(schur_ptab_max=0), ["p3d", "nonsym", "p2d_exact"]),
     ("schur_offsets_in_memory", dict(schur_noff_max=0, schur_ptab_max=3), ["p3d", "nonsym"]),
-    ("basis_by_cholesky_qr", dict(cholqr=1), ["p3d", "nonsym"]),
+    ("basis_by_householder", dict(cholqr=0), ["p3d", "nonsym"]),
+    # every level crowded: four Gram partials per cluster, the complement's
+    # columns wave by wave, U by Householder QR (the settings of the batched
+    # workload's large levels)
+    ("crowded_settings", dict(crowded_min=0), ["p3d", "nonsym", "p2d_exact"]),
     ("dense_panels_16", dict(dense_panel=16), ["p3d", "p2d_exact"]),
     # forward solve step in one launch / in two
     ("apply_one_launch", dict(apply_fwd=1), ["p3d", "nonsym", "p2d_exact"]),
