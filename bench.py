@@ -389,6 +389,7 @@ def run_single(args):
     for prec in forms:
         name = "mixed" if prec == P.HS_MIXED else "fp64"
         split = {"factor": 0.0, "solve": 0.0}
+        torch.cuda.empty_cache()  # the previous form's cached blocks back to the device
 
         def step():
             t0 = time.perf_counter()
@@ -403,9 +404,14 @@ def run_single(args):
             F.free()
             return it, rel, ok, info
 
-        for w in range(args.warmup):
-            step()
-            print(f"{name}: warmup step {w + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+        try:
+            for w in range(args.warmup):
+                step()
+                print(f"{name}: warmup step {w + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+        except P.HsError as e:  # a form that does not fit is reported, not timed
+            print(f"{name}: {e}", file=sys.stderr, flush=True)
+            recs[name] = {"error": str(e)}
+            continue
         fam = "schur_f32" if prec == P.HS_MIXED else "schur"
         P.profile_reset()
         P.profile_select("" if args.profile else fam)
@@ -453,7 +459,10 @@ def run_single(args):
             "peak_device_gb": info.peak_device_bytes / 1e9,
             "roofline": roof,
         }
-    head_name = "mixed" if "mixed" in recs else "fp64"
+    ok_forms = [k for k in ("mixed", "fp64") if k in recs and "error" not in recs[k]]
+    if not ok_forms:
+        raise SystemExit("no form of the workload fits: " + json.dumps(recs))
+    head_name = ok_forms[0]
     head = recs[head_name]
     out = {
         "metric": METRIC,
@@ -475,7 +484,8 @@ def run_single(args):
         out["roofline"] = head["roofline"]
     if "fp64" in recs and head_name != "fp64":
         out["fp64"] = recs["fp64"]
-        out["mixed_over_fp64"] = head["value"] / recs["fp64"]["value"]
+        if "error" not in recs["fp64"]:
+            out["mixed_over_fp64"] = head["value"] / recs["fp64"]["value"]
     if not args.no_cpu_baseline and args.workload == "poisson64":
         print("timing the CPU oracle sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline_poisson(args.cpu_side)
@@ -645,6 +655,26 @@ def run_serve(args):
         wall = time.perf_counter() - start
         st = srv.stats()
         srv.close()
+        # a request that did not succeed: what it was, how the server ran it,
+        # and the same request factored and solved alone
+        failed = []
+        for i, res in enumerate(results):
+            if res["status"] == 0:
+                continue
+            r = reqs[i]
+            rp, ci, va, dims, sym, n = ops[r.op_key]
+            rec = {"request": i, "kind": r.kind, "side": r.side, "nrhs": r.nrhs, "status": int(res["status"]),
+                   "iterations": int(res["iterations"]), "relres": float(res["relres"]),
+                   "reused": int(res["reused"]), "batch_size": int(res["batch_size"])}
+            try:
+                F = P.Factor(rp, ci, va, dims, 1e-3, 64, symmetric=sym, precision=P.HS_MIXED)
+                Xa, it_a, rel_a, ok_a = (F.pcg if sym else (lambda B_, t_, m_: F.gmres(B_, t_, m_, 30)))(rhs[i], 1e-10, 300)
+                F.free()
+                rec["alone"] = {"iterations": int(it_a), "relres": float(np.max(rel_a)), "converged": bool(ok_a)}
+            except P.HsError as e:
+                rec["alone"] = {"error": str(e)}
+            failed.append(rec)
+            print(f"serve: rho {rho}: request {i} did not succeed: {json.dumps(rec)}", file=sys.stderr, flush=True)
         runs.append({
             "rho": rho,
             "arrival_rate_per_s": lam,
@@ -663,6 +693,7 @@ def run_serve(args):
             "max_relres": max(r["relres"] for r in results if r["status"] == 0),
             "failed": sum(1 for r in results if r["status"] != 0),
             "failed_status": sorted({int(r["status"]) for r in results if r["status"] != 0}),
+            "failed_requests": failed,
             "converged": all(r["status"] == 0 for r in results) and max(r["relres"] for r in results) <= 1e-10,
         })
         print(f"serve: rho {rho}: {json.dumps(runs[-1])}", file=sys.stderr, flush=True)

@@ -522,11 +522,12 @@ int hs_set_allocator(void* (*alloc_fn)(size_t, void*, void*), void (*free_fn)(vo
  *                                  the solve has at most apply_split_nrhs_max
  *                                  right-hand sides
  *   apply_split_nrhs_max  1, 0..2^20  see apply_fwd
- *   apply_wave       1, 0..1       with one right-hand side, the own
- *                                  products of a colour whose clusters have at
- *                                  most 128 unknowns run one wave per cluster
- *                                  (the same sums in the same order; 0: the
- *                                  64-row workgroup form)
+ *   apply_wave       1024, 0..2^30 with one right-hand side, the own
+ *                                  products of a colour of at least this many
+ *                                  clusters, each of at most 128 unknowns, run
+ *                                  one wave per cluster (the same sums in the
+ *                                  same order; 0: always the 64-row workgroup
+ *                                  form)
  *   compression      0, 0..2       rank revelation (Eq. lra): 0 the
  *                                  pivoted QR of F^T under a rank cap or
  *                                  below qrcp_below_eps, else the Gram

@@ -29,7 +29,7 @@ from . import _lib as L
 # parameter -> candidate values (the defaults are among them)
 CANDIDATES: Dict[str, List[float]] = {
     "apply_fwd": [0, 1, 2],
-    "apply_wave": [0, 1],
+    "apply_wave": [0, 256, 1024, 4096],
     "apply_split_nrhs_max": [1, 64],
     "dense_panel": [64, 128],
     "gram_splits_max": [64, 128, 256],

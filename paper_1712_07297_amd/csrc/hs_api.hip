@@ -458,7 +458,11 @@ struct Config {
     int cholqr_crowded = 0;
     int dense_panel = 128;
     int apply_fwd = 0;              // forward solve step: 0 by cost, 1 one launch, 2 two launches
-    int apply_wave = 1;             // one right-hand side: own products one wave per cluster
+    // one right-hand side: own products one wave per cluster in colours of at
+    // least this many clusters (0: never); 1024 keeps the sparse levels of a
+    // single 3D system on the workgroup form (its PCG took 5.6 s with every
+    // colour by waves, 2.7 s so)
+    int apply_wave = 1024;
     // apply_fwd 0 splits a colour's forward step (where the one-launch form
     // would re-read T_L' more than twice) only for at most this many
     // right-hand sides: with 8 the one-launch form took the 64^3 Poisson PCG
@@ -566,7 +570,7 @@ static std::vector<ConfigEntry> config_table(Config& c) {
         {"cholqr_crowded", 0, 1, &c.cholqr_crowded, nullptr},
         {"dense_panel", 16, 128, &c.dense_panel, nullptr},
         {"apply_fwd", 0, 2, &c.apply_fwd, nullptr},
-        {"apply_wave", 0, 1, &c.apply_wave, nullptr},
+        {"apply_wave", 0, 1 << 30, &c.apply_wave, nullptr},
         {"apply_split_nrhs_max", 0, 1 << 20, &c.apply_split_nrhs_max, nullptr},
         {"compression", 0, 2, &c.compression, nullptr},
         {"qrcp_below_eps", 0, 1, nullptr, &c.qrcp_below_eps},

@@ -71,9 +71,11 @@ __global__ void __launch_bounds__(WG) k_apply_fwd_t(SolveLevelDev S, ColourDev C
 
 static size_t tile_shmem(size_t doubles) { return doubles * sizeof(double) + TILE_BYTES; }
 
-// One right-hand side and clusters of at most WAVE_MAXM unknowns: one wave
-// per cluster (four clusters per workgroup), lane l holding rows l and
-// l + 64.  The operator is read straight from memory, a batch of WAVE_LD
+// One right-hand side, clusters of at most WAVE_MAXM unknowns and a colour
+// of at least apply_wave clusters: one wave per cluster (four clusters per
+// workgroup), lane l holding rows l and l + 64.  A wave waits for one memory
+// round trip per WAVE_LD columns, so the form pays where a launch holds
+// thousands of clusters (throughput), not on sparse levels (latency).  The operator is read straight from memory, a batch of WAVE_LD
 // columns in flight per lane (consecutive lanes read consecutive rows of a
 // column), and the vector entry of column l is broadcast from the lane that
 // holds it; every row's sum is taken from zero in ascending l with one fma
@@ -137,7 +139,7 @@ __global__ void __launch_bounds__(WG) k_apply_fwd_t_wave(SolveLevelDev S, Colour
 void launch_apply_fwd_t(const SolveLevelDev& S, const ColourDev& C, const double* y, double* z, int nrhs,
                         hipStream_t st) {
     if (C.n == 0) return;
-    if (nrhs == 1 && C.apply_wave && C.max_m <= WAVE_MAXM) {
+    if (nrhs == 1 && C.apply_wave > 0 && C.n >= C.apply_wave && C.max_m <= WAVE_MAXM) {
         const dim3 wgrid((C.n + WG / 64 - 1) / (WG / 64));
         if (C.f32)
             hipLaunchKernelGGL(k_apply_fwd_t_wave<float>, wgrid, dim3(WG), 0, st, S, C, y, z);
@@ -534,7 +536,7 @@ __global__ void __launch_bounds__(WG) k_apply_bwd_t_wave(SolveLevelDev S, Colour
 void launch_apply_bwd_t(const SolveLevelDev& S, const ColourDev& C, const double* z, double* out,
                         const double* part, const int64_t* part_off, int nrhs, hipStream_t st) {
     if (C.n == 0) return;
-    if (nrhs == 1 && C.apply_wave && C.max_m <= WAVE_MAXM) {
+    if (nrhs == 1 && C.apply_wave > 0 && C.n >= C.apply_wave && C.max_m <= WAVE_MAXM) {
         const dim3 wgrid((C.n + WG / 64 - 1) / (WG / 64));
         if (C.f32)
             hipLaunchKernelGGL(k_apply_bwd_t_wave<float>, wgrid, dim3(WG), 0, st, S, C, z, out, part, part_off);

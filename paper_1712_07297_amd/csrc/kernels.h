@@ -37,6 +37,7 @@ struct ColourDev {
     int split_nrhs_max = 1;
     int max_nt = 0;                   // most neighbour rows (current sizes) of a cluster of the colour
     int apply_wave = 0;               // one right-hand side: own products one wave per cluster (m <= 128)
+                                      // in colours of at least this many clusters (0: never)
 };
 // neighbour groups of the backward sweep: at most this many columns of E_R
 // (unless one neighbour alone is wider) and this many entries

@@ -22,7 +22,7 @@ DEFAULTS = {
     "cholqr_crowded": 0,
     "dense_panel": 128,
     "apply_fwd": 0,
-    "apply_wave": 1,
+    "apply_wave": 1024,
     "apply_split_nrhs_max": 1,
     "compression": 0,
     "qrcp_below_eps": 1e-5,
