@@ -179,7 +179,11 @@ typedef struct hs_info {
  * A: host or device CSR (see hs_csr); geom: grid of the unknowns; opts: see
  * hs_opts.  On success *F_out receives a new factorization that keeps its own
  * device copy of A (for the Krylov solvers).  Synchronises the stream once per
- * level to size the next level (ranks decide the sizes).
+ * level to size the next level (ranks decide the sizes).  The symbolic
+ * analysis runs on the host: a device-resident pattern is copied through a
+ * pinned host staging buffer that the library grows on demand (to 1.25 times
+ * the largest pattern seen) and keeps until the process ends; a call that
+ * finds it in use on another thread copies through pageable memory.
  * Errors: HS_ERR_ARG, HS_ERR_PATTERN, HS_ERR_GEOMETRY, HS_ERR_BREAKDOWN (the
  * failing level and cluster are in hs_factor_info of the partial factor,
  * which is then freed; *F_out is set to NULL), HS_ERR_NOMEM, HS_ERR_HIP,
