@@ -1475,8 +1475,14 @@ static int factor_impl(hs_factor_s* F, int nsys, const hs_csr* A, const hs_geome
                              prev->dev.k, prev->dev.m, prev->dev.blk_off, prev->blocks.p, prev->dev_f32, LD.dev.m,
                              LD.dev.blk_off, LD.blocks.p, LD.dev_f32, st);
             }
-            // the children's blocks go back to the stream-ordered allocator:
-            // a later allocation on this stream runs after the merge
+            // the children's blocks are freed once the merge has read them, as
+            // observed by the host: a pool trim on another thread (the serving
+            // loop's, after an eviction) may return memory whose asynchronous
+            // free is still pending, and the merge would then read freed memory
+            {
+                HostScope hs_(PF_H_SYNC);
+                HIP_TRY(hipStreamSynchronize(st));
+            }
             prev->blocks.release();
             prev->dev.blocks = nullptr;
         }

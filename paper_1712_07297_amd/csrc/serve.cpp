@@ -143,6 +143,9 @@ struct hs_server_s {
     static void trim_pool() {
         int dev = 0;
         hipMemPool_t pool;
+        // every free queued so far completes before the trim (an asynchronous
+        // free whose completion the host has not observed may still be read)
+        (void)hipDeviceSynchronize();
         if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess)
             (void)hipMemPoolTrimTo(pool, 0);
         (void)hipGetLastError();
@@ -249,8 +252,11 @@ struct hs_server_s {
                                        r->nrhs, hipMemcpyDeviceToDevice, st);
             }
         }
-        hs_factor_trim(g->F, st);  // resident between uses: only the factorization itself
+        // the solve's buffers are freed once the host has seen the stream finish
+        // (a pool trim on another worker may return memory whose asynchronous
+        // free is still pending)
         if (hipStreamSynchronize(st) != hipSuccess && rc >= 0) rc = HS_ERR_HIP;
+        hs_factor_trim(g->F, st);  // resident between uses: only the factorization itself
         for (auto& it : items) {
             Req* r = it.first;
             r->res.iterations = iters;
