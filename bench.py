@@ -383,6 +383,12 @@ def run_single(args):
     va = torch.tensor(p.A.val, device=dev)
     B = torch.tensor(np.ascontiguousarray(p.B.T), device=dev)  # (nrhs, n) = column-major n x nrhs
     X = torch.empty_like(B)
+    if args.copy_probe:  # three plain copies of 64 MiB: the counter calibration
+        src = torch.ones(64 * 1024 * 1024 // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        del src, dst
     torch.cuda.synchronize()
     forms = {"both": [P.HS_MIXED, P.HS_FP64], "mixed": [P.HS_MIXED], "fp64": [P.HS_FP64]}[args.forms]
     recs = {}
