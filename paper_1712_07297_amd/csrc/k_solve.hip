@@ -324,14 +324,14 @@ void launch_apply_fwd(const SolveLevelDev& S, const ColourDev& C, double* y, dou
 // consecutive slices of the columns, each lane one row of E_R (consecutive
 // lanes read consecutive rows of a column), and the four slice sums are added
 // in slice order.  The x values of the group are gathered into LDS first.
-constexpr int BWD_XCOLS = 512;   // columns of x held in LDS per pass (times 4 right-hand sides)
+constexpr int BWD_XCOLS = 512;   // columns of x held in LDS per pass (times RC right-hand sides)
 
-template <class T>
+template <class T, int RC>
 __global__ void __launch_bounds__(WG) k_apply_bwd_acc(SolveLevelDev S, ColourDev C, const double* __restrict__ z,
                                                       const double* __restrict__ out, double* __restrict__ part,
                                                       const int64_t* __restrict__ part_off, int nrhs) {
-    __shared__ double xs[4 * BWD_XCOLS];
-    __shared__ double red[3][64][4];
+    __shared__ double xs[RC * BWD_XCOLS];
+    __shared__ double red[3][64][RC];
     __shared__ int tab_c[SOLVE_GROUP_ENTRIES + 1];
     __shared__ int tab_ld[SOLVE_GROUP_ENTRIES];
     __shared__ const double* tab_src[SOLVE_GROUP_ENTRIES];
@@ -358,11 +358,13 @@ __global__ void __launch_bounds__(WG) k_apply_bwd_acc(SolveLevelDev S, ColourDev
     const int ncols = tab_c[ne];
     const T* ER = srec<T>(S, s) + 2 * (int64_t)M * M + (int64_t)S.nbr_noff[e0] * M;  // ld M
     double* dst = part + part_off[g] * nrhs;                                           // f x nrhs
-    for (int r0 = 0; r0 < nrhs; r0 += 4) {
-        const int rr = min(4, nrhs - r0);
+    for (int r0 = 0; r0 < nrhs; r0 += RC) {
+        const int rr = min(RC, nrhs - r0);
         for (int j0 = 0; j0 < f; j0 += 64) {
             const int j = j0 + lane;
-            double acc[4] = {0.0, 0.0, 0.0, 0.0};
+            double acc[RC];
+#pragma unroll
+            for (int t = 0; t < RC; ++t) acc[t] = 0.0;
             for (int c0 = 0; c0 < ncols; c0 += BWD_XCOLS) {
                 const int cc = min(BWD_XCOLS, ncols - c0);
                 __syncthreads();
@@ -391,7 +393,7 @@ __global__ void __launch_bounds__(WG) k_apply_bwd_acc(SolveLevelDev S, ColourDev
                         for (int q = q0; q < q1; ++q) {
                             const double av = (double)col[(int64_t)q * M];
 #pragma unroll
-                            for (int t = 0; t < 4; ++t)
+                            for (int t = 0; t < RC; ++t)
                                 if (t < rr) acc[t] = fma(av, xs[q + t * cc], acc[t]);
                         }
                     }
@@ -399,11 +401,11 @@ __global__ void __launch_bounds__(WG) k_apply_bwd_acc(SolveLevelDev S, ColourDev
             }
             if (w > 0)
 #pragma unroll
-                for (int t = 0; t < 4; ++t) red[w - 1][lane][t] = acc[t];
+                for (int t = 0; t < RC; ++t) red[w - 1][lane][t] = acc[t];
             __syncthreads();
             if (w == 0 && j < f)
 #pragma unroll
-                for (int t = 0; t < 4; ++t)
+                for (int t = 0; t < RC; ++t)
                     if (t < rr)
                         dst[j + (int64_t)(r0 + t) * f] =
                             ((acc[t] + red[0][lane][t]) + red[1][lane][t]) + red[2][lane][t];
@@ -415,12 +417,20 @@ __global__ void __launch_bounds__(WG) k_apply_bwd_acc(SolveLevelDev S, ColourDev
 void launch_apply_bwd_acc(const SolveLevelDev& S, const ColourDev& C, const double* z, const double* out,
                           double* part, const int64_t* part_off, int nrhs, hipStream_t st) {
     if (C.grp_total == 0) return;
-    if (C.f32)
-        hipLaunchKernelGGL(k_apply_bwd_acc<float>, dim3(C.grp_total), dim3(WG), 0, st, S, C, z, out, part, part_off,
-                           nrhs);
-    else
-        hipLaunchKernelGGL(k_apply_bwd_acc<double>, dim3(C.grp_total), dim3(WG), 0, st, S, C, z, out, part, part_off,
-                           nrhs);
+    // right-hand sides per pass over E_R: eight where there are more than
+    // four (E_R read once for up to eight), else four (half the LDS)
+    const dim3 g(C.grp_total);
+    if (nrhs > 4) {
+        if (C.f32)
+            hipLaunchKernelGGL((k_apply_bwd_acc<float, 8>), g, dim3(WG), 0, st, S, C, z, out, part, part_off, nrhs);
+        else
+            hipLaunchKernelGGL((k_apply_bwd_acc<double, 8>), g, dim3(WG), 0, st, S, C, z, out, part, part_off, nrhs);
+    } else {
+        if (C.f32)
+            hipLaunchKernelGGL((k_apply_bwd_acc<float, 4>), g, dim3(WG), 0, st, S, C, z, out, part, part_off, nrhs);
+        else
+            hipLaunchKernelGGL((k_apply_bwd_acc<double, 4>), g, dim3(WG), 0, st, S, C, z, out, part, part_off, nrhs);
+    }
 }
 
 constexpr int BWD_POFF = 512;

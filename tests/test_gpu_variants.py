@@ -158,6 +158,33 @@ def test_noise_floor_decision(P, factor_of_floor):
     _check_solve(P, fo, F, A)
 
 
+@pytest.mark.parametrize("wave", [None, 1], ids=["default", "waves_everywhere"])
+@pytest.mark.parametrize("case", ["p3d_mixed", "convdiff_fp64"])
+def test_solve_columns_independent_bitwise(P, case, wave):
+    """Each column of a solve with several right-hand sides equals that
+    column solved alone, bit for bit: every sweep takes a column's sums in an
+    order that does not depend on how many columns share the launch (the
+    forward step in one launch or two, the own products one wave per cluster
+    or in 64-row chunks, four or eight columns per backward pass)."""
+    if case == "p3d_mixed":
+        A, dims, eps, sym, prec = poisson3d(14, 14, 14), (14, 14, 14), 1e-4, 1, P.HS_MIXED
+    else:
+        A, dims, eps, sym, prec = convdiff2d_upwind(96, 40.0, 0.7), (96, 96, 1), 1e-3, 0, P.HS_FP64
+    settings = {} if wave is None else {"apply_wave": wave}
+    with knobs(P, **settings):
+        F = P.Factor(A.row_ptr, A.col_idx, A.val, dims, eps, 64, symmetric=sym, precision=prec)
+        B = torch.tensor(np.random.default_rng(21).uniform(-1, 1, (8, A.n)), device="cuda")
+        X8 = F.solve(B).cpu().numpy()
+        X5 = F.solve(B[:5].contiguous()).cpu().numpy()
+        for j in range(8):
+            xj = F.solve(B[j:j + 1].contiguous()).cpu().numpy()
+            assert np.array_equal(xj[0], X8[j]), j
+            if j < 5:
+                assert np.array_equal(xj[0], X5[j]), j
+        F.free()
+    print(f"[variants] columns independent: {case} {settings}", flush=True)
+
+
 @pytest.mark.parametrize("case", ["p3d_big_clusters", "convdiff_mixed", "batch_mixed"])
 def test_apply_wave_form_bitwise(P, case):
     """One right-hand side: the own products one wave per cluster (clusters
